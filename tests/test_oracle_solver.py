@@ -1,0 +1,222 @@
+"""Pins of the oracle's generators, coarsest LU, V-cycle (Algorithm 1), PCG
+(Algorithm 4) and BiCGStab (Algorithm 5) against closed forms, library
+routines, dense brute force and invariants."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+import oracle
+from paper_2007_00056_amd import problems as P
+
+
+# ---------------------------------------------------------------- generators
+
+@pytest.mark.parametrize("shape", [(5, 7), (3, 4, 5), (6, 6, 6)])
+def test_poisson_eigenvalues_closed_form(shape):
+    a = P.poisson2d(*shape) if len(shape) == 2 else P.poisson3d(*shape)
+    ev = np.sort(np.linalg.eigvalsh(a.to_scipy().toarray()))
+    grids = np.meshgrid(*[np.arange(1, s + 1) for s in shape], indexing="ij")
+    want = sum(2 - 2 * np.cos(p * np.pi / (s + 1)) for p, s in zip(grids, shape))
+    np.testing.assert_allclose(ev, np.sort(want.ravel()), atol=1e-12)
+
+
+def test_generator_sizes_match_stencil_counts():
+    a = P.poisson2d(64)
+    assert a.n == 4096 and a.nnz == 5 * 4096 - 4 * 64
+    a = P.poisson3d(20)
+    assert a.n == 8000 and a.nnz == 7 * 8000 - 6 * 400
+    assert np.all(np.diff(a.col[a.row_ptr[5]:a.row_ptr[6]]) > 0)
+
+
+def test_convdiff_rows_and_upwinding():
+    a = P.convdiff3d(6)
+    D = a.to_scipy().toarray()
+    i = 2 + 6 * (2 + 6 * 2)  # interior cell
+    assert D[i, i] == 23.5 and D[i, i - 1] == -11 and D[i, i - 6] == -6 and D[i, i - 36] == -3.5
+    assert D[i, i + 1] == -1 and D[i, i + 6] == -1 and D[i, i + 36] == -1
+    assert abs(D[i].sum()) == 0.0
+    assert not np.allclose(D, D.T)
+
+
+def test_vardiff_is_spd_and_row_sums_are_boundary_faces():
+    n = 8
+    a = P.vardiff3d(n, seed=1, corr_len=2.0)
+    D = a.to_scipy().toarray()
+    np.testing.assert_allclose(D, D.T, rtol=0, atol=0)
+    assert np.linalg.eigvalsh(D).min() > 0
+    g = P.gaussian_field(n, 1, corr_len=2.0)
+    assert abs(g.std() - 1.5) < 1e-12 and abs(g.mean()) < 1e-12
+    # interior cells have zero row sum, boundary cells keep their wall faces
+    rs = D.sum(axis=1).reshape(n, n, n)
+    assert np.abs(rs[1:-1, 1:-1, 1:-1]).max() < 1e-9
+    e = np.exp(g)
+    np.testing.assert_allclose(rs[1:-1, 1:-1, 0], 2 * e[1:-1, 1:-1, 0], rtol=1e-12)
+
+
+# ---------------------------------------------------------------- dense LU
+
+def test_lu_matches_lapack_including_pivot_ties():
+    rng = np.random.default_rng(0)
+    for n in (1, 5, 17, 64):
+        A = rng.integers(-3, 4, size=(n, n)).astype(float) + np.eye(n) * 0.5
+        lu, piv, st = oracle.lu_factor(A)
+        assert st == oracle.OK
+        lu_ref, piv_ref = sla.lu_factor(A)
+        np.testing.assert_array_equal(piv, piv_ref)  # getrf takes the first max: lowest row on ties
+        np.testing.assert_allclose(lu, lu_ref, rtol=1e-12, atol=1e-12)
+        b = rng.standard_normal(n)
+        np.testing.assert_allclose(oracle.lu_solve(lu, piv, b), sla.lu_solve((lu_ref, piv_ref), b), rtol=1e-10,
+                                   atol=1e-12)
+
+
+def test_lu_singular_detected():
+    _, _, st = oracle.lu_factor(np.array([[1.0, 2.0], [2.0, 4.0]]))
+    assert st == oracle.ESINGULAR
+
+
+# ---------------------------------------------------------------- V-cycle
+
+def assembled_preconditioner(h, n):
+    return np.stack([h.vcycle(e) for e in np.eye(n)], axis=1)
+
+
+def test_single_level_vcycle_is_exact_solve():
+    a = P.poisson2d(7, 9)  # 63 rows <= 64: the level is solved directly
+    h = oracle.Hierarchy(a)
+    assert h.nlevels == 1
+    b = P.rhs_uniform(a.n, 0)
+    np.testing.assert_allclose(h.vcycle(b), np.linalg.solve(a.to_scipy().toarray(), b), rtol=1e-12)
+    x, info = h.solve(b, rtol=1e-12)
+    assert info["iters"] == 1 and info["status"] == oracle.OK
+
+
+@pytest.mark.parametrize("make", [lambda: P.poisson2d(12, 10), lambda: P.poisson3d(6, 5, 7),
+                                  lambda: P.lognormal_diffusion3d(7, seed=2)])
+def test_vcycle_operator_is_symmetric_positive_definite_and_convergent(make):
+    a = make()
+    h = oracle.Hierarchy(a, max_coarse_rows=8)
+    assert h.nlevels >= 3
+    M = assembled_preconditioner(h, a.n)
+    scale = np.abs(M).max()
+    assert np.abs(M - M.T).max() <= 1e-12 * scale
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
+    E = np.eye(a.n) - M @ a.to_scipy().toarray()
+    assert np.abs(np.linalg.eigvals(E)).max() < 1.0
+
+
+def test_two_level_cycle_matches_dense_formulation():
+    # Figure 1 / Algorithm 1 with L = 1, written with dense operators
+    a = P.lognormal_diffusion3d(5, seed=4)
+    h = oracle.Hierarchy(a, max_coarse_rows=40, max_levels=2)
+    assert h.nlevels == 2
+    L0 = h.level(0)
+    A = a.to_scipy().toarray()
+    nc = h.level(1).n
+    Pm = np.zeros((a.n, nc))
+    Pm[np.arange(a.n), L0.agg] = 1.0
+    Ac = Pm.T @ A @ Pm
+    w = 2.0 / 3.0
+    Dinv = np.diag(1.0 / np.diag(A))
+    f = P.rhs_uniform(a.n, 5)
+    x = w * Dinv @ f
+    x = x + Pm @ np.linalg.solve(Ac, Pm.T @ (f - A @ x))
+    x = x + w * Dinv @ (f - A @ x)
+    np.testing.assert_allclose(h.vcycle(f), x, rtol=1e-11, atol=1e-13)
+
+
+# ---------------------------------------------------------------- PCG / BiCGStab
+
+def test_pcg_manufactured_solution_and_dense_solve():
+    a = P.lognormal_diffusion3d(8, seed=0)
+    A = a.to_scipy()
+    xs = np.random.default_rng(1).standard_normal(a.n)
+    b = A @ xs
+    h = oracle.Hierarchy(a)
+    x, info = h.solve(b, rtol=1e-12)
+    assert info["status"] == oracle.OK
+    kappa = np.linalg.cond(A.toarray())
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= kappa * 1e-12
+    np.testing.assert_allclose(x, np.linalg.solve(A.toarray(), b), rtol=1e-6)
+    assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1e-12
+
+
+def test_pcg_a_norm_error_decreases():
+    a = P.poisson3d(10)
+    A = a.to_scipy()
+    b = P.rhs_uniform(a.n, 3)
+    h = oracle.Hierarchy(a)
+    xs = np.linalg.solve(A.toarray(), b)
+    errs = []
+    for k in range(1, 12):
+        x, _ = h.solve(b, rtol=0.0, maxit=k)
+        e = x - xs
+        errs.append(np.sqrt(e @ (A @ e)))
+    assert all(e2 < e1 for e1, e2 in zip(errs, errs[1:]))
+
+
+class _Count:
+    def __init__(self):
+        self.n = 0
+
+    def __call__(self, *_):
+        self.n += 1
+
+
+@pytest.mark.parametrize("precond", [True, False])
+def test_pcg_iteration_count_matches_scipy_cg(precond):
+    a = P.poisson2d(40)
+    A = a.to_scipy()
+    b = P.rhs_uniform(a.n, 0)
+    h = oracle.Hierarchy(a)
+    x, info = h.solve(b, rtol=1e-8, precond=precond, maxit=2000)
+    M = spla.LinearOperator(A.shape, matvec=h.vcycle) if precond else None
+    cnt = _Count()
+    xr, st = spla.cg(A, b, rtol=1e-8, M=M, maxiter=2000, callback=cnt)
+    assert st == 0 and info["status"] == oracle.OK
+    assert abs(info["iters"] - cnt.n) <= 1
+    np.testing.assert_allclose(x, xr, rtol=1e-5, atol=1e-7)
+
+
+def test_bicgstab_matches_scipy_and_manufactured_solution():
+    a = P.convdiff3d(10)
+    A = a.to_scipy()
+    xs = np.random.default_rng(2).uniform(-1, 1, a.n)
+    b = A @ xs
+    h = oracle.Hierarchy(a)
+    x, info = h.solve(b, method="bicgstab", rtol=1e-10)
+    assert info["status"] == oracle.OK
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-7
+    cnt = _Count()
+    xr, st = spla.bicgstab(A, b, rtol=1e-10, M=spla.LinearOperator(A.shape, matvec=h.vcycle), callback=cnt)
+    assert st == 0
+    assert abs(info["iters"] - cnt.n) <= 1
+
+
+def test_zero_rhs_and_status_codes():
+    a = P.poisson2d(10)
+    h = oracle.Hierarchy(a)
+    x, info = h.solve(np.zeros(a.n), x0=np.ones(a.n))
+    assert info["iters"] == 0 and np.all(x == 0)
+    _, info = h.solve(P.rhs_uniform(a.n, 0), rtol=1e-14, maxit=2)
+    assert info["status"] == oracle.ENOTCONV and info["iters"] == 2
+    b = P.rhs_uniform(a.n, 0)
+    b[3] = np.nan
+    _, info = h.solve(b)
+    assert info["status"] == oracle.ENOTFINITE
+    bad = P.poisson2d(3)
+    bad.val = bad.val.copy()
+    bad.val[0] = 0.0  # zero diagonal
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Hierarchy(bad)
+    assert e.value.status == oracle.EINVAL
+
+
+def test_stall_falls_back_to_dense_or_reports():
+    # a diagonal matrix has no edges: no coarsening progress
+    a = P.from_dense(np.diag(np.arange(1.0, 101.0)))
+    h = oracle.Hierarchy(a)
+    assert h.nlevels == 1
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Hierarchy(a, max_dense_rows=50)
+    assert e.value.status == oracle.ESTALL
