@@ -1,0 +1,213 @@
+"""Benchmark: AMG-preconditioned Krylov solve on one MI355X.
+
+One step = the whole hot path on one synthetic system already resident in GPU
+memory: amg_setup (matching, Galerkin products, coarsest LU) + krylov_solve
+to the workload's relative tolerance + amg_destroy.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "AMG-PCG time to 1e-8 residual + HBM GB/s; served solves/s, p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def level_sizes(h, hemamg):
+    L = hemamg.amg_num_levels(h)
+    return [hemamg.amg_level_size(h, k) for k in range(L)]
+
+
+def kernel_bytes(sizes):
+    """Algorithmic bytes per launch of the level-0 kernels (FP64 values,
+    int32 indices; each array counted once)."""
+    (n, nnz), nc = sizes[0], (sizes[1][0] if len(sizes) > 1 else 0)
+    return {
+        # 12 nnz (val+col) + 4(n+1) row_ptr + dinv, f, agg, z (8+8+4+8) n + e 8 nc
+        0: 12 * nnz + 4 * (n + 1) + 28 * n + 8 * nc,
+        # 12 nnz + 4(n+1) + dinv, f 16 n + members 16 nc + f_c 8 nc
+        1: 12 * nnz + 4 * (n + 1) + 16 * n + 24 * nc,
+        # 12 nnz + 4(n+1) + p read, q write 16 n
+        2: 12 * nnz + 4 * (n + 1) + 16 * n,
+    }
+
+
+def iteration_bytes(sizes, method):
+    """Algorithmic bytes of one Krylov iteration (V-cycle + outer kernels)."""
+    vc = 0
+    for k in range(len(sizes) - 1):
+        n, nnz = sizes[k]
+        nc = sizes[k + 1][0]
+        vc += (12 * nnz + 4 * (n + 1) + 16 * n + 24 * nc) + (12 * nnz + 4 * (n + 1) + 28 * n + 8 * nc)
+    m = sizes[-1][0]
+    vc += 8 * m * m + 16 * m
+    n, nnz = sizes[0]
+    spmv = 12 * nnz + 4 * (n + 1) + 16 * n
+    if method == "pcg":
+        # spmv+dot, update (x,r,p,q read; x,r write), dot(r,z), direction (z,p read; p write)
+        return vc + spmv + 48 * n + 16 * n + 24 * n
+    # BiCGStab: 2 V-cycles, 2 SpMVs, s, update, direction
+    return 2 * vc + 2 * spmv + 24 * n + 72 * n + 32 * n
+
+
+def cpu_baseline(a, b, spec, gpu_iters, budget_s=25.0):
+    """The oracle (single-threaded C) on the same input: setup + solve, with
+    the solve cut to fit `budget_s` and scaled to the GPU's iteration count."""
+    import oracle
+
+    t0 = time.perf_counter()
+    h = oracle.Hierarchy(a)
+    t_setup = time.perf_counter() - t0
+    # time a few iterations first to size the sample
+    t0 = time.perf_counter()
+    _, info = h.solve(b, method=spec["kind"], rtol=spec["rtol"], maxit=2)
+    per_it = (time.perf_counter() - t0) / max(info["iters"], 1)
+    cap = max(1, int((budget_s - t_setup) / per_it)) if per_it > 0 else gpu_iters
+    t0 = time.perf_counter()
+    _, info = h.solve(b, method=spec["kind"], rtol=spec["rtol"], maxit=min(cap, 10 * gpu_iters + 10))
+    t_solve = time.perf_counter() - t0
+    done = max(info["iters"], 1)
+    full = info["status"] == oracle.OK
+    est_solve = t_solve if full else t_solve * gpu_iters / done
+    total = t_setup + est_solve
+    h.close()
+    return {
+        "value": 1.0 / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+        "sample": (f"one setup ({t_setup:.2f} s) + {'full solve' if full else 'partial solve'} of {done} "
+                   f"iterations ({t_solve:.2f} s)" + ("" if full else f", scaled to {gpu_iters} iterations")),
+        "setup_s": t_setup, "solve_s": est_solve, "oracle_iters": info["iters"],
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="poisson3d_128")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is single-GPU and "
+              "a multi-GPU run is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2007_00056_amd import hemamg, problems as P
+
+    if not torch.cuda.is_available():
+        log("bench.py needs a ROCm GPU")
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    log(f"generating {args.workload} (seed {args.seed})")
+    a, b_host, spec = P.make_workload(args.workload, args.seed)
+    method = spec["kind"]
+    A = hemamg.DeviceCSR.from_host(a)
+    b = torch.from_numpy(b_host).cuda()
+    x = torch.zeros_like(b)
+    params = hemamg.amg_params_default()
+    mcode = hemamg.PCG if method == "pcg" else hemamg.BICGSTAB
+    torch.cuda.synchronize()
+
+    kern_tot = {0: [0, 0.0], 1: [0, 0.0], 2: [0, 0.0]}
+
+    def step(timed):
+        t0 = time.perf_counter()
+        h = hemamg.amg_setup(A, params)
+        t1 = time.perf_counter()
+        if timed:
+            for k in kern_tot:
+                hemamg.amg_timing_enable(h, k, True)
+        x.zero_()
+        info = hemamg.krylov_solve(h, mcode, b, x, spec["rtol"], 1000)
+        t2 = time.perf_counter()
+        if timed:
+            for k in kern_tot:
+                c, ms = hemamg.amg_timing_read(h, k)
+                kern_tot[k][0] += c
+                kern_tot[k][1] += ms
+        sizes = level_sizes(h, hemamg)
+        stats = hemamg.amg_setup_stats(h)
+        hemamg.amg_destroy(h)
+        return dict(setup_ms=(t1 - t0) * 1e3, solve_ms=(t2 - t1) * 1e3, iters=info["iters"],
+                    true_rel_res=info["true_rel_res"], sizes=sizes, stats=stats)
+
+    for i in range(args.warmup):
+        r = step(False)
+        log(f"warmup {i}: setup {r['setup_ms']:.2f} ms, solve {r['solve_ms']:.2f} ms, iters {r['iters']}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = []
+    for i in range(args.steps):
+        r = step(True)
+        recs.append(r)
+        log(f"step {i}: setup {r['setup_ms']:.2f} ms, solve {r['solve_ms']:.2f} ms, iters {r['iters']}, "
+            f"true rel res {r['true_rel_res']:.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    sizes = recs[-1]["sizes"]
+    iters = recs[-1]["iters"]
+    setup_ms = float(np.median([r["setup_ms"] for r in recs]))
+    solve_ms = float(np.median([r["solve_ms"] for r in recs]))
+    it_bytes = iteration_bytes(sizes, method)
+    kb = kernel_bytes(sizes)
+    names = {0: "k_prolong_post (level 0)", 1: "k_resid_restrict (level 0)", 2: "k_spmv_dot (outer SpMV)"}
+    kernels = {}
+    for k, (c, ms) in kern_tot.items():
+        if c:
+            avg = ms / c
+            kernels[names[k]] = {"launches": c, "avg_us": avg * 1e3, "bytes": kb[k],
+                                 "gbs": kb[k] / (avg * 1e-3) / 1e9}
+    dom = max(kern_tot, key=lambda k: kern_tot[k][1])
+    c, ms = kern_tot[dom]
+    achieved = kb[dom] / (ms / c * 1e-3) / 1e9 if c else 0.0
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "desc": spec["desc"], "n": a.n, "nnz": a.nnz, "rtol": spec["rtol"],
+                   "method": method, "levels": len(sizes), "seed": args.seed},
+        "setup_ms": setup_ms,
+        "solve_ms": solve_ms,
+        "iters": iters,
+        "ms_per_iter": solve_ms / max(iters, 1),
+        "solve_gbs": it_bytes * iters / (solve_ms * 1e-3) / 1e9,
+        "matching_rounds": recs[-1]["stats"]["rounds"],
+        "kernels": kernels,
+        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on the same input")
+        out["cpu_baseline"] = cpu_baseline(a, b_host, spec, iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

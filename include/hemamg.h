@@ -1,0 +1,145 @@
+/*
+ * hemamg.h -- C ABI of the MI355X (gfx950) aggregation-AMG solver library.
+ *
+ * The library solves A u = f (Section 2 of Ganesan & Shah, "SParSH-AMG: A
+ * library for hybrid CPU-GPU algebraic multigrid and preconditioned iterative
+ * methods") for a square CSR matrix A held in GPU memory, with algebraic
+ * multigrid built by node-based heavy edge matching (Section 2.1.1,
+ * Algorithm 2) used as a preconditioner of CG (Algorithm 4) or BiCGStab
+ * (Algorithm 5).  Every step runs as HIP kernels on one GPU.
+ *
+ * Conventions for every entry point:
+ *  - Indices are int32 and 0-based.  CSR rows store their diagonal, columns
+ *    are strictly ascending, and the pattern is structurally symmetric
+ *    ((i,j) stored iff (j,i) stored; values may differ).
+ *  - Pointers marked [device] are GPU memory; [host] pointers are CPU memory.
+ *  - All GPU work is enqueued on the given stream (hipStream_t passed as a
+ *    void*; NULL is the default stream).  Calls that return data to the host
+ *    synchronise that stream before returning.
+ *  - Every function returns an amg_status and never aborts; on failure
+ *    amg_last_error() holds a message for the calling thread.
+ *  - A handle may be used by one thread at a time.
+ */
+#ifndef HEMAMG_H
+#define HEMAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AMG_OK = 0,
+    AMG_EINVAL = 1,        /* invalid argument or matrix                        */
+    AMG_ENOMEM = 2,        /* GPU allocation failed                             */
+    AMG_ENOTCONV = 3,      /* iteration limit reached (info and x still valid)  */
+    AMG_EBREAKDOWN = 4,    /* Krylov breakdown: zero or non-finite denominator  */
+    AMG_ENOTFINITE = 5,    /* NaN or Inf in the input                           */
+    AMG_ESTALL = 6,        /* coarsening stalled above max_dense_rows           */
+    AMG_ESINGULAR = 7,     /* coarsest matrix is singular                       */
+    AMG_EHIP = 8           /* HIP runtime error                                 */
+} amg_status;
+
+typedef struct amg_hier amg_hier; /* opaque hierarchy handle, owned by the library */
+
+/* CSR matrix.  [device] arrays; borrowed: they must stay valid and unchanged
+ * for the lifetime of any handle built from them. */
+typedef struct {
+    int32_t n;              /* rows = columns, > 0                  */
+    int64_t nnz;            /* row_ptr[n], < 2^31                    */
+    const int32_t* row_ptr; /* [device] int32[n+1], row_ptr[0] = 0   */
+    const int32_t* col_idx; /* [device] int32[nnz]                   */
+    const double* val;      /* [device] float64[nnz]                 */
+} amg_csr;
+
+/* Hierarchy and cycle parameters (Section 3 setup phase; Algorithm 1). */
+typedef struct {
+    int32_t passes_per_level; /* matching passes composed per level: 1 or 2 (2)   */
+    int32_t max_coarse_rows;  /* coarsen until n <= this, 1..1024 (64)            */
+    int32_t max_levels;       /* levels including the coarsest, 1..64 (32)        */
+    int32_t max_dense_rows;   /* largest coarsest level accepted when coarsening  *
+                               * stalls or hits max_levels, <= 1024 (1024)        */
+    double omega;             /* damped-Jacobi weight (2/3)                       */
+    int32_t pre, post;        /* smoothing sweeps before/after the coarse
+                               * correction, 0..8 (1, 1)                          */
+    int32_t true_res_period;  /* recompute b - A x every this many iterations,   *
+                               * 0 = only when the recursive residual converges   *
+                               * (50)                                             */
+} amg_params;
+
+/* Result of a Krylov solve.  [host] */
+typedef struct {
+    int32_t iters;       /* number of solution updates performed               */
+    double rel_res;      /* recursive ||r|| / ||b|| at the stop                */
+    double true_rel_res; /* ||b - A x|| / ||b|| at the stop (last recomputed) */
+    double solve_ms;     /* host wall time of the call                         */
+    int32_t status;      /* same as the return value                           */
+} amg_info;
+
+/* Fills *p with the defaults shown above.  [host] */
+amg_status amg_params_default(amg_params* p);
+
+/* Setup phase (Section 3; Algorithm 2 per pass; coarse operator P^T A P of
+ * Section 2.1.1; LU of the coarsest matrix, Section 2).  Validates A (sorted
+ * in-range columns, non-zero finite diagonal, finite values, structural
+ * symmetry), builds every level on the GPU and returns a handle in *out
+ * (*out = NULL on error).  Blocks the host until the stream has finished.
+ * Coarse levels, D^{-1}, aggregate maps and the coarsest inverse are owned by
+ * the handle; level 0 is borrowed from A.
+ * Errors: AMG_EINVAL, AMG_ENOTFINITE, AMG_ESTALL, AMG_ESINGULAR, AMG_ENOMEM,
+ * AMG_EHIP. */
+amg_status amg_setup(const amg_csr* A, const amg_params* params, void* stream, amg_hier** out);
+
+/* Releases every buffer owned by the handle (after synchronising its last
+ * stream).  NULL is accepted. */
+amg_status amg_destroy(amg_hier* h);
+
+/* Algorithm 1: one V-cycle from a zero initial guess, z = M^{-1} r.
+ * r, z: [device] float64[n], must not alias.  Asynchronous on `stream`.
+ * Errors: AMG_EINVAL for a NULL argument. */
+amg_status amg_vcycle(amg_hier* h, const double* r, double* z, void* stream);
+
+/* Algorithm 4 (method 0: preconditioned CG, A symmetric positive definite)
+ * or Algorithm 5 (method 1: preconditioned BiCGStab, right preconditioned)
+ * with one V-cycle as the preconditioner.  Stops when the recursive residual
+ * reaches ||r|| <= rtol ||b|| and the recomputed residual b - A x confirms it.
+ * b: [device] float64[n]; x: [device] float64[n], initial guess on entry,
+ * the last iterate on return (also on AMG_ENOTCONV and AMG_EBREAKDOWN).
+ * info: [host], may be NULL.  Blocks the host until done.
+ * Errors: AMG_EINVAL, AMG_ENOTFINITE (b or x0 not finite), AMG_ENOTCONV,
+ * AMG_EBREAKDOWN, AMG_EHIP. */
+amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x, double rtol, int32_t maxit,
+                        void* stream, amg_info* info);
+
+/* Number of levels (coarsest included) and the size of level k.  [host] */
+amg_status amg_num_levels(const amg_hier* h, int32_t* levels);
+amg_status amg_level_size(const amg_hier* h, int32_t k, int32_t* n, int64_t* nnz);
+
+/* Copies level k to [host] buffers (any may be NULL): row_ptr int32[n+1],
+ * col_idx int32[nnz], val float64[nnz], agg int32[n] (aggregate of each row
+ * on level k+1; untouched on the coarsest level).  Synchronises the stream. */
+amg_status amg_export_level(const amg_hier* h, int32_t k, int32_t* row_ptr, int32_t* col_idx, double* val,
+                            int32_t* agg, void* stream);
+
+/* Setup statistics: matching rounds of each pass (up to `cap` entries) and
+ * the bytes of GPU memory the handle owns.  [host] */
+amg_status amg_setup_stats(const amg_hier* h, int32_t* rounds, int32_t cap, int32_t* npasses, size_t* owned_bytes);
+
+/* Kernel timing for measurement: when enabled, the launches of the selected
+ * kernel class are bracketed by HIP events on their stream and their
+ * durations accumulated.  kernel: 0 = level-0 fused prolongation + smoothing,
+ * 1 = level-0 fused smoothing + residual + restriction, 2 = Krylov SpMV.
+ * amg_timing_read returns the launch count and total milliseconds
+ * (synchronises the events).  [host] */
+amg_status amg_timing_enable(amg_hier* h, int32_t kernel, int32_t on);
+amg_status amg_timing_read(amg_hier* h, int32_t kernel, int64_t* launches, double* total_ms);
+
+/* Message for the last failing call on this thread (never NULL). */
+const char* amg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEMAMG_H */

@@ -235,7 +235,7 @@ void oracle_params_default(oracle_params* p) {
     p->passes_per_level = 2;
     p->max_coarse_rows = 64;
     p->max_levels = 32;
-    p->max_dense_rows = 4096;
+    p->max_dense_rows = 1024;
     p->omega = 2.0 / 3.0;
     p->pre = 1;
     p->post = 1;

@@ -1,0 +1,819 @@
+// Host orchestration and C ABI (include/hemamg.h): the setup phase (Section 3)
+// building the hierarchy level by level on the GPU, the V-cycle driver
+// (Algorithm 1) and the Krylov drivers (Algorithms 4 and 5).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "amg_internal.hpp"
+#include "hemamg.h"
+
+namespace {
+
+using namespace amg;
+
+thread_local std::string g_err = "no error";
+
+struct Failure {
+    amg_status st;
+    std::string msg;
+};
+
+[[noreturn]] void raise(amg_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    throw Failure{st, buf};
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            if (e_ == hipErrorOutOfMemory) raise(AMG_ENOMEM, "%s: out of GPU memory", #call); \
+            raise(AMG_EHIP, "%s: %s", #call, hipGetErrorString(e_));                          \
+        }                                                                                     \
+    } while (0)
+
+// Stream-ordered device allocations; every byte is counted.
+struct DevPool {
+    hipStream_t s = nullptr;
+    std::vector<void*> ptrs;
+    size_t bytes = 0;
+
+    template <class T>
+    T* get(size_t count) {
+        void* p = nullptr;
+        const size_t b = (count > 0 ? count : 1) * sizeof(T);
+        HIPCHK(hipMallocAsync(&p, b, s));
+        ptrs.push_back(p);
+        bytes += b;
+        return static_cast<T*>(p);
+    }
+    void release() {
+        for (void* p : ptrs) (void)hipFreeAsync(p, s);
+        ptrs.clear();
+        bytes = 0;
+    }
+};
+
+struct Level {
+    int n = 0;
+    int64_t nnz = 0;
+    const int* rp = nullptr;
+    const int* ci = nullptr;
+    const double* v = nullptr;
+    double* dinv = nullptr;
+    int* agg = nullptr;    // to level k+1
+    int4* mem = nullptr;   // members of level k+1 rows
+    double* f = nullptr;   // restricted right-hand side (k >= 1)
+    double* x = nullptr;   // correction (k >= 1)
+    double* t = nullptr;   // scratch of the general smoothing path
+    int lpr = 4;
+
+    LevelView view() const {
+        LevelView w;
+        w.n = n;
+        w.nnz = (int)nnz;
+        w.rp = rp;
+        w.ci = ci;
+        w.v = v;
+        w.dinv = dinv;
+        w.agg = agg;
+        w.mem = mem;
+        w.lpr = lpr;
+        return w;
+    }
+};
+
+// Scalar slots of the Krylov recurrences.
+enum Slot { S_BB = 0, S_RR, S_TRR, S_PQ, S_RHO0, S_RHO1, S_RV, S_TT, S_TS, S_COUNT = 16 };
+
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // start/stop pairs
+    size_t used = 0;
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+
+}  // namespace
+
+struct amg_hier {
+    amg_params p{};
+    std::vector<Level> lev;
+    int n_coarse = 0;
+    double* ainv_t = nullptr;
+    DevPool pool;
+    hipStream_t stream = nullptr;
+    std::vector<int> rounds;
+    // Krylov workspace (allocated on first solve)
+    double *r = nullptr, *z = nullptr, *pv[2] = {nullptr, nullptr}, *q = nullptr, *rb = nullptr, *pt = nullptr,
+           *sv = nullptr, *st = nullptr, *t = nullptr;
+    double* S = nullptr;
+    double* part = nullptr;
+    unsigned* ticket = nullptr;
+    int* err = nullptr;
+    double* S_host = nullptr;
+    Timer tim[3];
+
+    Reducer reducer() const { return Reducer{part, ticket, S}; }
+
+    ~amg_hier() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        pool.release();
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (S_host) (void)hipHostFree(S_host);
+        for (auto& T : tim)
+            for (hipEvent_t e : T.ev) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+template <class F>
+amg_status guarded(F&& f) {
+    try {
+        f();
+        return AMG_OK;
+    } catch (const Failure& e) {
+        g_err = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return AMG_ENOMEM;
+    } catch (...) {
+        g_err = "unexpected internal error";
+        return AMG_EHIP;
+    }
+}
+
+inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+int read_int(const int* d, hipStream_t s) {
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return h;
+}
+
+void check_err_word(const int* err, hipStream_t s, const char* where) {
+    const int e = read_int(err, s);
+    if (e & ERR_NONFINITE) raise(AMG_ENOTFINITE, "%s: matrix has a NaN or Inf value", where);
+    if (e & ERR_STRUCT) raise(AMG_EINVAL, "%s: invalid CSR structure (row_ptr, column range or order)", where);
+    if (e & ERR_DIAG) raise(AMG_EINVAL, "%s: a diagonal entry is missing or zero", where);
+    if (e & ERR_NONSYM) raise(AMG_EINVAL, "%s: sparsity pattern is not structurally symmetric", where);
+    if (e & ERR_SINGULAR) raise(AMG_ESINGULAR, "%s: coarsest matrix is singular", where);
+}
+
+struct Csr {
+    int n = 0;
+    int64_t nnz = 0;
+    int* rp = nullptr;
+    int* ci = nullptr;
+    double* v = nullptr;
+};
+
+// One matching pass on B: mate, aggregate map and leaders.  Buffers come from
+// `tmp` (freed with the level) except those the caller keeps.
+struct Pass {
+    int* mate = nullptr;
+    int* agg = nullptr;
+    int* lead = nullptr;
+    int nc = 0;
+    int rounds = 0;
+};
+
+Pass hem_pass(const Csr& B, DevPool& tmp, hipStream_t s, int* err) {
+    const int n = B.n;
+    HemWork w;
+    w.lowok = tmp.get<uint8_t>((size_t)B.nnz);
+    w.lcnt = tmp.get<int>(n);
+    w.dec = tmp.get<int>(n);
+    w.mate = tmp.get<int>(n);
+    w.wl[0] = tmp.get<int>(n);
+    w.wl[1] = tmp.get<int>(n);
+    w.newly = tmp.get<int>(n);
+    w.cnt = tmp.get<int>(8);
+    w.err = err;
+    HIPCHK(hipMemsetAsync(w.cnt, 0, 8 * sizeof(int), s));
+    launch_hem_init(n, B.rp, B.ci, B.v, w, s);
+    HIPCHK(hipGetLastError());
+    {
+        int head[8];
+        HIPCHK(hipMemcpyAsync(head, w.cnt, sizeof(head), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        check_err_word(err, s, "matching");
+        if (head[5] != 0) raise(AMG_EINVAL, "matching: sparsity pattern is not structurally symmetric");
+    }
+    // Rounds are launched in batches; the size of the next worklist is copied
+    // back after each batch and checked one batch later, so the host check
+    // overlaps the GPU work.  Rounds with an empty worklist do nothing.
+    int* hc = nullptr;
+    HIPCHK(hipHostMalloc((void**)&hc, 2 * sizeof(int), hipHostMallocDefault));
+    std::unique_ptr<int, void (*)(int*)> hc_guard(hc, [](int* p) { (void)hipHostFree(p); });
+    hipEvent_t ev[2];
+    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    struct EvGuard {
+        hipEvent_t* e;
+        ~EvGuard() {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } eg{ev};
+    const int batch = 8;
+    int r = 0;
+    for (int j = 0;; ++j) {
+        for (int b = 0; b < batch; ++b, ++r) launch_hem_round(r, n, B.rp, B.ci, B.v, w, s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&hc[j & 1], w.cnt + hem_next_count_slot(r), sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(ev[j & 1], s));
+        if (j >= 1) {
+            HIPCHK(hipEventSynchronize(ev[(j - 1) & 1]));
+            if (hc[(j - 1) & 1] == 0) break;
+        }
+        if (r > n + 4 * batch) raise(AMG_EHIP, "matching did not terminate (internal error)");
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    int tail[8];
+    HIPCHK(hipMemcpyAsync(tail, w.cnt, sizeof(tail), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    Pass P;
+    P.rounds = tail[6];
+    P.mate = w.mate;
+    // coarse ids: rank of each aggregate's smaller vertex
+    int* flag = tmp.get<int>(n);
+    int* ids = tmp.get<int>((size_t)n + 1);
+    int* stmp = tmp.get<int>(scan_tmp_ints(n));
+    launch_leader_flags(n, w.mate, flag, s);
+    launch_scan(flag, n, ids, stmp, s);
+    P.nc = read_int(ids + n, s);
+    P.agg = tmp.get<int>(n);
+    P.lead = tmp.get<int>(P.nc);
+    launch_assign_ids(n, w.mate, ids, P.agg, P.lead, s);
+    HIPCHK(hipGetLastError());
+    return P;
+}
+
+// Galerkin product of one pass; output buffers from `out`.
+Csr galerkin(const Csr& B, const Pass& P, DevPool& tmp, DevPool& out, hipStream_t s) {
+    Csr C;
+    C.n = P.nc;
+    int* rowcnt = tmp.get<int>(P.nc);
+    int* ovf = tmp.get<int>(P.nc);
+    int* novf = tmp.get<int>(1);
+    int* stmp = tmp.get<int>(scan_tmp_ints(P.nc));
+    HIPCHK(hipMemsetAsync(novf, 0, sizeof(int), s));
+    launch_rap_count(P.nc, P.lead, P.mate, B.rp, B.ci, P.agg, rowcnt, ovf, novf, s);
+    launch_rap_count_slow(P.nc, ovf, novf, P.lead, P.mate, B.rp, B.ci, P.agg, rowcnt, s);
+    C.rp = out.get<int>((size_t)P.nc + 1);
+    launch_scan(rowcnt, P.nc, C.rp, stmp, s);
+    C.nnz = read_int(C.rp + P.nc, s);
+    C.ci = out.get<int>((size_t)C.nnz);
+    C.v = out.get<double>((size_t)C.nnz);
+    launch_rap_fill(P.nc, P.lead, P.mate, B.rp, B.ci, B.v, P.agg, C.rp, C.ci, C.v, s);
+    launch_rap_fill_slow(P.nc, ovf, novf, P.lead, P.mate, B.rp, B.ci, B.v, P.agg, C.rp, C.ci, C.v, s);
+    HIPCHK(hipGetLastError());
+    return C;
+}
+
+void alloc_workspace(amg_hier* h) {
+    if (h->r) return;
+    const int n = h->lev[0].n;
+    DevPool& P = h->pool;
+    h->r = P.get<double>(n);
+    h->z = P.get<double>(n);
+    h->pv[0] = P.get<double>(n);
+    h->pv[1] = P.get<double>(n);
+    h->q = P.get<double>(n);
+    h->rb = P.get<double>(n);
+    h->pt = P.get<double>(n);
+    h->sv = P.get<double>(n);
+    h->st = P.get<double>(n);
+    h->t = P.get<double>(n);
+}
+
+void timed_begin(amg_hier* h, int cls, hipStream_t s) {
+    Timer& T = h->tim[cls];
+    if (!T.on) return;
+    if (T.used + 2 > T.ev.size()) {
+        for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            T.ev.push_back(e);
+        }
+    }
+    HIPCHK(hipEventRecord(T.ev[T.used], s));
+}
+
+void timed_end(amg_hier* h, int cls, hipStream_t s) {
+    Timer& T = h->tim[cls];
+    if (!T.on) return;
+    HIPCHK(hipEventRecord(T.ev[T.used + 1], s));
+    T.used += 2;
+    if (T.used >= 4096) {  // fold completed pairs to bound the pool
+        HIPCHK(hipEventSynchronize(T.ev[T.used - 1]));
+        for (size_t k = 0; k < T.used; k += 2) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, T.ev[k], T.ev[k + 1]));
+            T.total_ms += ms;
+            T.launches += 1;
+        }
+        T.used = 0;
+    }
+}
+
+// Algorithm 1, z = V(r) from a zero initial guess, on every level.
+void run_vcycle(amg_hier* h, const double* r, double* z, hipStream_t s) {
+    const int L = (int)h->lev.size() - 1;
+    const double w = h->p.omega;
+    if (L == 0) {
+        launch_dense_apply(h->n_coarse, h->ainv_t, r, z, s);
+        return;
+    }
+    std::vector<const double*> f(L + 1);
+    std::vector<double*> x(L + 1);
+    f[0] = r;
+    x[0] = z;
+    for (int k = 1; k <= L; ++k) {
+        f[k] = h->lev[k].f;
+        x[k] = h->lev[k].x;
+    }
+    const bool fused = h->p.pre == 1 && h->p.post == 1;
+    for (int k = 0; k < L; ++k) {
+        const Level& Lk = h->lev[k];
+        const LevelView V = Lk.view();
+        const int nc = h->lev[k + 1].n;
+        if (fused) {
+            if (k == 0) timed_begin(h, 1, s);
+            launch_resid_restrict(V, nc, f[k], w, const_cast<double*>(f[k + 1]), s);
+            if (k == 0) timed_end(h, 1, s);
+            continue;
+        }
+        const double* xs = nullptr;
+        if (h->p.pre > 0) {
+            double* a = x[k];
+            double* b = Lk.t;
+            launch_jacobi_zero(Lk.n, Lk.dinv, f[k], w, a, s);
+            for (int it = 1; it < h->p.pre; ++it) {
+                launch_jacobi(V, f[k], a, w, b, s);
+                std::swap(a, b);
+            }
+            if (a != x[k]) HIPCHK(hipMemcpyAsync(x[k], a, sizeof(double) * Lk.n, hipMemcpyDeviceToDevice, s));
+            xs = x[k];
+        } else {
+            launch_scale_zero(Lk.n, x[k], s);
+        }
+        launch_resid_restrict_x(V, nc, f[k], xs, const_cast<double*>(f[k + 1]), s);
+    }
+    launch_dense_apply(h->n_coarse, h->ainv_t, f[L], x[L], s);
+    for (int k = L - 1; k >= 0; --k) {
+        const Level& Lk = h->lev[k];
+        const LevelView V = Lk.view();
+        if (fused) {
+            if (k == 0) timed_begin(h, 0, s);
+            launch_prolong_post(V, f[k], x[k + 1], w, x[k], s);
+            if (k == 0) timed_end(h, 0, s);
+            continue;
+        }
+        launch_prolong_add(Lk.n, Lk.agg, x[k + 1], x[k], s);
+        double* a = x[k];
+        double* b = Lk.t;
+        for (int it = 0; it < h->p.post; ++it) {
+            launch_jacobi(V, f[k], a, w, b, s);
+            std::swap(a, b);
+        }
+        if (a != x[k]) HIPCHK(hipMemcpyAsync(x[k], a, sizeof(double) * Lk.n, hipMemcpyDeviceToDevice, s));
+    }
+}
+
+void read_slots(amg_hier* h, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(h->S_host, h->S, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+inline bool usable(double d) { return std::isfinite(d) && d != 0.0; }
+
+void spmv_dot_timed(amg_hier* h, const LevelView& A, const double* p, double* q, const double* d, int slot,
+                    hipStream_t s) {
+    timed_begin(h, 2, s);
+    launch_spmv_dot(A, p, q, d, h->reducer(), slot, s);
+    timed_end(h, 2, s);
+}
+
+// Algorithm 4 with the readings documented in the header.
+amg_status pcg(amg_hier* h, const double* b, double* x, double rtol, int maxit, hipStream_t s, amg_info& info) {
+    const Level& A0 = h->lev[0];
+    const LevelView A = A0.view();
+    const int n = A0.n;
+    const Reducer R = h->reducer();
+    const int period = h->p.true_res_period;
+    double* S = h->S_host;
+    launch_dot(n, b, b, R, S_BB, s);
+    launch_residual(A, b, x, h->r, R, S_RR, s);
+    read_slots(h, s);
+    const double nb = std::sqrt(S[S_BB]);
+    info.iters = 0;
+    if (nb == 0.0) {
+        launch_scale_zero(n, x, s);
+        HIPCHK(hipStreamSynchronize(s));
+        info.rel_res = info.true_rel_res = 0.0;
+        return AMG_OK;
+    }
+    double rel = std::sqrt(S[S_RR]) / nb;
+    info.rel_res = info.true_rel_res = rel;
+    if (rel <= rtol) return AMG_OK;
+    int cur = S_RHO0, nxt = S_RHO1, pc = 0;
+    run_vcycle(h, h->r, h->z, s);
+    launch_dot(n, h->r, h->z, R, cur, s);
+    HIPCHK(hipMemcpyAsync(h->pv[0], h->z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    for (int it = 1; it <= maxit; ++it) {
+        double* p = h->pv[pc];
+        double* pn = h->pv[1 - pc];
+        spmv_dot_timed(h, A, p, h->q, p, S_PQ, s);
+        launch_cg_update(n, x, h->r, p, h->q, R, cur, S_PQ, S_RR, s);
+        // speculative: preconditioning and the next direction, unused on exit
+        run_vcycle(h, h->r, h->z, s);
+        launch_dot(n, h->r, h->z, R, nxt, s);
+        launch_cg_dir(n, h->z, p, pn, h->S, nxt, cur, s);
+        HIPCHK(hipGetLastError());
+        read_slots(h, s);
+        if (!usable(S[S_PQ]) || !std::isfinite(S[cur])) return AMG_EBREAKDOWN;
+        info.iters = it;
+        rel = std::sqrt(S[S_RR]) / nb;
+        info.rel_res = rel;
+        if (!std::isfinite(rel)) return AMG_EBREAKDOWN;
+        if (rel <= rtol || (period > 0 && it % period == 0)) {
+            launch_residual(A, b, x, h->r, R, S_TRR, s);  // residual replacement
+            read_slots(h, s);
+            const double tr = std::sqrt(S[S_TRR]) / nb;
+            info.true_rel_res = tr;
+            if (tr <= rtol) return AMG_OK;
+            run_vcycle(h, h->r, h->z, s);
+            launch_dot(n, h->r, h->z, R, nxt, s);
+            launch_cg_dir(n, h->z, p, pn, h->S, nxt, cur, s);
+            read_slots(h, s);
+        }
+        if (!usable(S[nxt])) return AMG_EBREAKDOWN;
+        std::swap(cur, nxt);
+        pc = 1 - pc;
+    }
+    return AMG_ENOTCONV;
+}
+
+// Algorithm 5 (right-preconditioned BiCGStab) with p_0 = r_0 = shadow residual.
+amg_status bicgstab(amg_hier* h, const double* b, double* x, double rtol, int maxit, hipStream_t s, amg_info& info) {
+    const Level& A0 = h->lev[0];
+    const LevelView A = A0.view();
+    const int n = A0.n;
+    const Reducer R = h->reducer();
+    const int period = h->p.true_res_period;
+    double* S = h->S_host;
+    launch_dot(n, b, b, R, S_BB, s);
+    launch_residual(A, b, x, h->r, R, S_RR, s);
+    read_slots(h, s);
+    const double nb = std::sqrt(S[S_BB]);
+    info.iters = 0;
+    if (nb == 0.0) {
+        launch_scale_zero(n, x, s);
+        HIPCHK(hipStreamSynchronize(s));
+        info.rel_res = info.true_rel_res = 0.0;
+        return AMG_OK;
+    }
+    double rel = std::sqrt(S[S_RR]) / nb;
+    info.rel_res = info.true_rel_res = rel;
+    if (rel <= rtol) return AMG_OK;
+    HIPCHK(hipMemcpyAsync(h->rb, h->r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->pv[0], h->r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    int cur = S_RHO0, nxt = S_RHO1, pc = 0;
+    launch_dot(n, h->r, h->rb, R, cur, s);
+    double* v = h->q;
+    for (int it = 1; it <= maxit; ++it) {
+        double* p = h->pv[pc];
+        double* pn = h->pv[1 - pc];
+        run_vcycle(h, p, h->pt, s);
+        spmv_dot_timed(h, A, h->pt, v, h->rb, S_RV, s);
+        launch_bicg_s(n, h->r, v, h->sv, h->S, cur, S_RV, s);
+        run_vcycle(h, h->sv, h->st, s);
+        launch_spmv_dot2(A, h->st, h->t, h->sv, R, S_TT, S_TS, s);
+        launch_bicg_update(n, x, h->r, h->pt, h->st, h->sv, h->t, h->rb, R, cur, S_RV, S_TT, S_TS, S_RR, nxt, s);
+        launch_bicg_dir(n, h->r, p, v, pn, h->S, cur, S_RV, S_TT, S_TS, nxt, s);
+        HIPCHK(hipGetLastError());
+        read_slots(h, s);
+        if (!usable(S[S_RV]) || !usable(S[cur])) return AMG_EBREAKDOWN;
+        if (!std::isfinite(S[S_TT]) || !std::isfinite(S[S_TS]) || S[S_TT] == 0.0) return AMG_EBREAKDOWN;
+        const double omega = S[S_TS] / S[S_TT];
+        info.iters = it;
+        rel = std::sqrt(S[S_RR]) / nb;
+        info.rel_res = rel;
+        if (!std::isfinite(rel)) return AMG_EBREAKDOWN;
+        if (rel <= rtol || (period > 0 && it % period == 0)) {
+            launch_residual(A, b, x, h->r, R, S_TRR, s);
+            read_slots(h, s);
+            const double tr = std::sqrt(S[S_TRR]) / nb;
+            info.true_rel_res = tr;
+            if (tr <= rtol) return AMG_OK;
+            launch_dot(n, h->r, h->rb, R, nxt, s);
+            launch_bicg_dir(n, h->r, p, v, pn, h->S, cur, S_RV, S_TT, S_TS, nxt, s);
+            read_slots(h, s);
+        }
+        if (omega == 0.0 || !usable(S[nxt])) return AMG_EBREAKDOWN;
+        std::swap(cur, nxt);
+        pc = 1 - pc;
+    }
+    return AMG_ENOTCONV;
+}
+
+void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hier** out) {
+    if (!Ain || !out) raise(AMG_EINVAL, "amg_setup: NULL argument");
+    *out = nullptr;
+    amg_params p;
+    amg_params_default(&p);
+    if (pin) p = *pin;
+    if (p.passes_per_level < 1 || p.passes_per_level > 2) raise(AMG_EINVAL, "passes_per_level must be 1 or 2");
+    if (p.max_coarse_rows < 1 || p.max_coarse_rows > 1024) raise(AMG_EINVAL, "max_coarse_rows must be in 1..1024");
+    if (p.max_dense_rows < 1 || p.max_dense_rows > 1024) raise(AMG_EINVAL, "max_dense_rows must be in 1..1024");
+    if (p.max_levels < 1 || p.max_levels > 64) raise(AMG_EINVAL, "max_levels must be in 1..64");
+    if (p.pre < 0 || p.pre > 8 || p.post < 0 || p.post > 8) raise(AMG_EINVAL, "pre/post sweeps must be in 0..8");
+    if (!std::isfinite(p.omega)) raise(AMG_EINVAL, "omega must be finite");
+    if (p.true_res_period < 0) raise(AMG_EINVAL, "true_res_period must be >= 0");
+    const amg_csr& A = *Ain;
+    if (A.n <= 0) raise(AMG_EINVAL, "n must be positive");
+    if (A.nnz < A.n || A.nnz >= (int64_t(1) << 31)) raise(AMG_EINVAL, "nnz must be in [n, 2^31)");
+    if (!A.row_ptr || !A.col_idx || !A.val) raise(AMG_EINVAL, "NULL CSR array");
+
+    std::unique_ptr<amg_hier> h(new amg_hier());
+    h->p = p;
+    h->stream = s;
+    h->pool.s = s;
+    DevPool& P = h->pool;
+    h->err = P.get<int>(1);
+    HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), s));
+
+    Level L0;
+    L0.n = A.n;
+    L0.nnz = A.nnz;
+    L0.rp = A.row_ptr;
+    L0.ci = A.col_idx;
+    L0.v = A.val;
+    L0.dinv = P.get<double>(A.n);
+    L0.lpr = pick_lanes_per_row((double)A.nnz / A.n);
+    launch_validate(A.n, A.nnz, A.row_ptr, A.col_idx, A.val, L0.dinv, h->err, s);
+    HIPCHK(hipGetLastError());
+    check_err_word(h->err, s, "amg_setup");
+    h->lev.push_back(L0);
+
+    for (int k = 0;; ++k) {
+        Level& F = h->lev[k];
+        if (F.n <= p.max_coarse_rows) break;
+        if (k + 1 >= p.max_levels) {
+            if (F.n > p.max_dense_rows)
+                raise(AMG_ESTALL, "max_levels reached with %d rows on the coarsest level", F.n);
+            break;
+        }
+        DevPool tmp;
+        tmp.s = s;
+        struct TmpGuard {
+            DevPool& t;
+            ~TmpGuard() { t.release(); }
+        } tg{tmp};
+        Csr B{F.n, F.nnz, const_cast<int*>(F.rp), const_cast<int*>(F.ci), const_cast<double*>(F.v)};
+        Pass p1 = hem_pass(B, tmp, s, h->err);
+        h->rounds.push_back(p1.rounds);
+        DevPool& out1 = (p.passes_per_level == 1) ? P : tmp;
+        Csr C1 = galerkin(B, p1, tmp, out1, s);
+        Csr Cf = C1;
+        int* agg = nullptr;
+        int4* mem = nullptr;
+        if (p.passes_per_level == 2) {
+            Pass p2 = hem_pass(C1, tmp, s, h->err);
+            h->rounds.push_back(p2.rounds);
+            Cf = galerkin(C1, p2, tmp, P, s);
+            agg = P.get<int>(F.n);
+            launch_compose(F.n, p1.agg, p2.agg, agg, s);
+            mem = P.get<int4>(Cf.n);
+            launch_members(Cf.n, p2.lead, p2.mate, p1.lead, p1.mate, mem, s);
+        } else {
+            agg = P.get<int>(F.n);
+            HIPCHK(hipMemcpyAsync(agg, p1.agg, sizeof(int) * F.n, hipMemcpyDeviceToDevice, s));
+            mem = P.get<int4>(Cf.n);
+            launch_members(Cf.n, nullptr, nullptr, p1.lead, p1.mate, mem, s);
+        }
+        HIPCHK(hipGetLastError());
+        if (Cf.n == F.n) {  // no progress: this level becomes the coarsest
+            if (F.n > p.max_dense_rows)
+                raise(AMG_ESTALL, "coarsening stalled at %d rows (above max_dense_rows)", F.n);
+            HIPCHK(hipStreamSynchronize(s));
+            break;
+        }
+        F.agg = agg;
+        F.mem = mem;
+        Level C;
+        C.n = Cf.n;
+        C.nnz = Cf.nnz;
+        C.rp = Cf.rp;
+        C.ci = Cf.ci;
+        C.v = Cf.v;
+        C.dinv = P.get<double>(C.n);
+        C.lpr = pick_lanes_per_row((double)C.nnz / C.n);
+        launch_dinv(C.n, C.rp, C.ci, C.v, C.dinv, h->err, s);
+        HIPCHK(hipGetLastError());
+        check_err_word(h->err, s, "coarse level");
+        h->lev.push_back(C);
+    }
+    // coarsest level: dense LU and inverse
+    Level& Lc = h->lev.back();
+    const int m = Lc.n;
+    h->n_coarse = m;
+    {
+        DevPool tmp;
+        tmp.s = s;
+        double* a = tmp.get<double>((size_t)m * m);
+        int* piv = tmp.get<int>(m);
+        h->ainv_t = P.get<double>((size_t)m * m);
+        HIPCHK(hipMemsetAsync(a, 0, sizeof(double) * (size_t)m * m, s));
+        launch_dense_assemble(m, Lc.rp, Lc.ci, Lc.v, a, s);
+        launch_dense_lu_inverse(m, a, piv, h->ainv_t, h->err, s);
+        HIPCHK(hipGetLastError());
+        try {
+            check_err_word(h->err, s, "coarsest level");
+        } catch (...) {
+            tmp.release();
+            throw;
+        }
+        tmp.release();
+    }
+    // per-level work vectors
+    const bool fused = p.pre == 1 && p.post == 1;
+    for (size_t k = 0; k < h->lev.size(); ++k) {
+        Level& L = h->lev[k];
+        if (k > 0) {
+            L.f = P.get<double>(L.n);
+            L.x = P.get<double>(L.n);
+        }
+        if (!fused) L.t = P.get<double>(L.n);
+    }
+    h->S = P.get<double>(S_COUNT);
+    h->part = P.get<double>(4 * (size_t)kRedBlocks);
+    h->ticket = P.get<unsigned>(1);
+    HIPCHK(hipMemsetAsync(h->ticket, 0, sizeof(unsigned), s));
+    HIPCHK(hipMemsetAsync(h->S, 0, S_COUNT * sizeof(double), s));
+    HIPCHK(hipHostMalloc((void**)&h->S_host, S_COUNT * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipStreamSynchronize(s));
+    *out = h.release();
+}
+
+}  // namespace
+
+extern "C" {
+
+amg_status amg_params_default(amg_params* p) {
+    if (!p) {
+        g_err = "amg_params_default: NULL argument";
+        return AMG_EINVAL;
+    }
+    p->passes_per_level = 2;
+    p->max_coarse_rows = 64;
+    p->max_levels = 32;
+    p->max_dense_rows = 1024;
+    p->omega = 2.0 / 3.0;
+    p->pre = 1;
+    p->post = 1;
+    p->true_res_period = 50;
+    return AMG_OK;
+}
+
+amg_status amg_setup(const amg_csr* A, const amg_params* params, void* stream, amg_hier** out) {
+    if (out) *out = nullptr;
+    return guarded([&] { setup_impl(A, params, as_stream(stream), out); });
+}
+
+amg_status amg_destroy(amg_hier* h) {
+    return guarded([&] { delete h; });
+}
+
+amg_status amg_vcycle(amg_hier* h, const double* r, double* z, void* stream) {
+    return guarded([&] {
+        if (!h || !r || !z) raise(AMG_EINVAL, "amg_vcycle: NULL argument");
+        hipStream_t s = as_stream(stream);
+        h->stream = s;
+        h->pool.s = s;
+        run_vcycle(h, r, z, s);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x, double rtol, int32_t maxit,
+                        void* stream, amg_info* info) {
+    amg_info local{};
+    amg_info& I = info ? *info : local;
+    I = amg_info{};
+    const auto t0 = std::chrono::steady_clock::now();
+    amg_status st = AMG_OK;
+    amg_status g = guarded([&] {
+        if (!h || !b || !x) raise(AMG_EINVAL, "krylov_solve: NULL argument");
+        if (method != 0 && method != 1) raise(AMG_EINVAL, "krylov_solve: method must be 0 (PCG) or 1 (BiCGStab)");
+        if (!(rtol >= 0.0) || maxit < 0) raise(AMG_EINVAL, "krylov_solve: rtol must be >= 0 and maxit >= 0");
+        hipStream_t s = as_stream(stream);
+        h->stream = s;
+        h->pool.s = s;
+        alloc_workspace(h);
+        HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), s));
+        launch_check_finite(h->lev[0].n, b, x, h->err, s);
+        HIPCHK(hipGetLastError());
+        if (read_int(h->err, s) & ERR_NONFINITE) raise(AMG_ENOTFINITE, "krylov_solve: b or x0 has NaN or Inf");
+        st = method == 0 ? pcg(h, b, x, rtol, maxit, s, I) : bicgstab(h, b, x, rtol, maxit, s, I);
+        HIPCHK(hipStreamSynchronize(s));
+        if (st == AMG_ENOTCONV) g_err = "krylov_solve: iteration limit reached";
+        if (st == AMG_EBREAKDOWN) g_err = "krylov_solve: breakdown (zero or non-finite denominator)";
+    });
+    if (g != AMG_OK) st = g;
+    I.status = st;
+    I.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+}
+
+amg_status amg_num_levels(const amg_hier* h, int32_t* levels) {
+    return guarded([&] {
+        if (!h || !levels) raise(AMG_EINVAL, "amg_num_levels: NULL argument");
+        *levels = (int32_t)h->lev.size();
+    });
+}
+
+amg_status amg_level_size(const amg_hier* h, int32_t k, int32_t* n, int64_t* nnz) {
+    return guarded([&] {
+        if (!h || !n || !nnz) raise(AMG_EINVAL, "amg_level_size: NULL argument");
+        if (k < 0 || k >= (int32_t)h->lev.size()) raise(AMG_EINVAL, "amg_level_size: level out of range");
+        *n = h->lev[k].n;
+        *nnz = h->lev[k].nnz;
+    });
+}
+
+amg_status amg_export_level(const amg_hier* h, int32_t k, int32_t* row_ptr, int32_t* col_idx, double* val,
+                            int32_t* agg, void* stream) {
+    return guarded([&] {
+        if (!h) raise(AMG_EINVAL, "amg_export_level: NULL handle");
+        if (k < 0 || k >= (int32_t)h->lev.size()) raise(AMG_EINVAL, "amg_export_level: level out of range");
+        const Level& L = h->lev[k];
+        hipStream_t s = as_stream(stream);
+        if (row_ptr)
+            HIPCHK(hipMemcpyAsync(row_ptr, L.rp, sizeof(int) * ((size_t)L.n + 1), hipMemcpyDeviceToHost, s));
+        if (col_idx) HIPCHK(hipMemcpyAsync(col_idx, L.ci, sizeof(int) * L.nnz, hipMemcpyDeviceToHost, s));
+        if (val) HIPCHK(hipMemcpyAsync(val, L.v, sizeof(double) * L.nnz, hipMemcpyDeviceToHost, s));
+        if (agg && L.agg) HIPCHK(hipMemcpyAsync(agg, L.agg, sizeof(int) * L.n, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    });
+}
+
+amg_status amg_setup_stats(const amg_hier* h, int32_t* rounds, int32_t cap, int32_t* npasses, size_t* owned_bytes) {
+    return guarded([&] {
+        if (!h) raise(AMG_EINVAL, "amg_setup_stats: NULL handle");
+        if (npasses) *npasses = (int32_t)h->rounds.size();
+        if (rounds)
+            for (int32_t i = 0; i < cap && i < (int32_t)h->rounds.size(); ++i) rounds[i] = h->rounds[i];
+        if (owned_bytes) *owned_bytes = h->pool.bytes;
+    });
+}
+
+amg_status amg_timing_enable(amg_hier* h, int32_t kernel, int32_t on) {
+    return guarded([&] {
+        if (!h || kernel < 0 || kernel > 2) raise(AMG_EINVAL, "amg_timing_enable: bad argument");
+        h->tim[kernel].on = on != 0;
+    });
+}
+
+amg_status amg_timing_read(amg_hier* h, int32_t kernel, int64_t* launches, double* total_ms) {
+    return guarded([&] {
+        if (!h || kernel < 0 || kernel > 2) raise(AMG_EINVAL, "amg_timing_read: bad argument");
+        Timer& T = h->tim[kernel];
+        if (T.used > 0) {
+            HIPCHK(hipEventSynchronize(T.ev[T.used - 1]));
+            for (size_t k = 0; k < T.used; k += 2) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, T.ev[k], T.ev[k + 1]));
+                T.total_ms += ms;
+                T.launches += 1;
+            }
+            T.used = 0;
+        }
+        if (launches) *launches = T.launches;
+        if (total_ms) *total_ms = T.total_ms;
+        T.launches = 0;
+        T.total_ms = 0.0;
+    });
+}
+
+const char* amg_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

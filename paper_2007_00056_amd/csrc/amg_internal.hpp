@@ -1,0 +1,131 @@
+// Internal interfaces between the host orchestration (amg_api.hip) and the
+// kernel launchers (k_setup.hip, k_solve.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amg {
+
+// Device error bits raised by validation and setup kernels.
+enum : int {
+    ERR_STRUCT = 1,      // bad row_ptr / column index / column order
+    ERR_NONFINITE = 2,   // NaN or Inf value
+    ERR_DIAG = 4,        // missing or zero diagonal
+    ERR_NONSYM = 8,      // pattern not structurally symmetric
+    ERR_SINGULAR = 16,   // dense coarsest LU met a zero pivot
+};
+
+constexpr int kUndecided = 0x3fffffff;  // round stamp of an undecided vertex
+
+// Lanes per CSR row used by the level kernels (a power of two, 1..16).
+int pick_lanes_per_row(double avg_row_len);
+
+// ---- setup kernels (k_setup.hip) ------------------------------------------
+void launch_validate(int n, int64_t nnz, const int* rp, const int* ci, const double* v, double* dinv, int* err,
+                     hipStream_t s);
+void launch_dinv(int n, const int* rp, const int* ci, const double* v, double* dinv, int* err, hipStream_t s);
+
+// Matching pass state (Algorithm 2 as rounds of locally dominant edges).
+struct HemWork {
+    uint8_t* lowok;   // [nnz] entry (v,u), u < v, is an edge (row u stores a non-zero a_uv)
+    int* lcnt;        // [n] undecided lower neighbours
+    int* dec;         // [n] round in which the vertex was decided
+    int* mate;        // [n] partner or -1
+    int* wl[2];       // [n] ready worklists (ping-pong)
+    int* newly;       // [n] vertices decided this round
+    int* cnt;         // [8] ring of worklist / decided counters, diff accumulator
+    int* err;
+};
+// w.cnt must be zeroed before the call.
+void launch_hem_init(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
+void launch_hem_round(int round, int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
+int hem_next_count_slot(int round);  // counter slot that holds |worklist| before `round`
+
+// Exclusive prefix sum: out[i] = sum in[0..i), out[n] = total.  tmp: scan_tmp_ints(n).
+size_t scan_tmp_ints(int n);
+void launch_scan(const int* in, int n, int* out, int* tmp, hipStream_t s);
+void launch_leader_flags(int n, const int* mate, int* flag, hipStream_t s);
+// agg[v] = id of v's aggregate; lead[id] = smaller vertex of the aggregate.
+void launch_assign_ids(int n, const int* mate, const int* ids, int* agg, int* lead, hipStream_t s);
+
+// Galerkin product of one matching pass (aggregates of size <= 2).
+void launch_rap_count(int nc, const int* lead, const int* mate, const int* rp, const int* ci, const int* agg,
+                      int* rowcnt, int* ovf, int* novf, hipStream_t s);
+void launch_rap_count_slow(int nc, const int* ovf, const int* novf, const int* lead, const int* mate, const int* rp,
+                           const int* ci, const int* agg, int* rowcnt, hipStream_t s);
+void launch_rap_fill(int nc, const int* lead, const int* mate, const int* rp, const int* ci, const double* v,
+                     const int* agg, const int* crp, int* cci, double* cv, hipStream_t s);
+void launch_rap_fill_slow(int nc, const int* ovf, const int* novf, const int* lead, const int* mate, const int* rp,
+                          const int* ci, const double* v, const int* agg, const int* crp, int* cci, double* cv,
+                          hipStream_t s);
+
+void launch_compose(int n, const int* agg1, const int* agg2, int* out, hipStream_t s);
+// Member lists (ascending fine rows, -1 padded) of the level's coarse rows.
+void launch_members(int nc, const int* lead2, const int* mate2, const int* lead1, const int* mate1, int4* mem,
+                    hipStream_t s);
+
+// a must be zeroed before the call.
+void launch_dense_assemble(int n, const int* rp, const int* ci, const double* v, double* a, hipStream_t s);
+void launch_dense_lu_inverse(int n, double* a, int* piv, double* ainv_t, int* err, hipStream_t s);
+
+// ---- solve kernels (k_solve.hip) --------------------------------------------
+struct LevelView {
+    int n;
+    int nnz;
+    const int* rp;
+    const int* ci;
+    const double* v;
+    const double* dinv;
+    const int* agg;   // [n] aggregate on level k+1
+    const int4* mem;  // [n_{k+1}] members of coarse rows (for k < L)
+    int lpr;          // lanes per row
+};
+
+struct Reducer {
+    double* part;     // [4 * kRedBlocks]
+    unsigned* ticket;
+    double* S;        // scalar slots
+};
+
+void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t s);
+// fc = P^T (f - A (w D^{-1} f)) : zero-guess presmoothing, residual, restriction.
+void launch_resid_restrict(const LevelView& L, int nc, const double* f, double w, double* fc, hipStream_t s);
+// z = x + w D^{-1} (f - A x) with x = w D^{-1} f + P e : prolongation + postsmoothing.
+void launch_prolong_post(const LevelView& L, const double* f, const double* e, double w, double* z, hipStream_t s);
+// General smoothing path.
+void launch_jacobi_zero(int n, const double* dinv, const double* f, double w, double* x, hipStream_t s);
+void launch_jacobi(const LevelView& L, const double* f, const double* x, double w, double* xo, hipStream_t s);
+void launch_resid_restrict_x(const LevelView& L, int nc, const double* f, const double* x, double* fc,
+                             hipStream_t s);
+void launch_prolong_add(int n, const int* agg, const double* e, double* x, hipStream_t s);
+void launch_dense_apply(int n, const double* ainv_t, const double* f, double* x, hipStream_t s);
+
+// Krylov vector kernels.  Slots index Reducer::S.
+void launch_residual(const LevelView& A, const double* b, const double* x, double* r, const Reducer& R, int slot_rr,
+                     hipStream_t s);
+void launch_dot(int n, const double* a, const double* b, const Reducer& R, int slot, hipStream_t s);
+void launch_spmv_dot(const LevelView& A, const double* p, double* q, const double* d, const Reducer& R, int slot,
+                     hipStream_t s);
+void launch_spmv_dot2(const LevelView& A, const double* p, double* t, const double* sv, const Reducer& R, int slot_tt,
+                      int slot_ts, hipStream_t s);
+void launch_cg_update(int n, double* x, double* r, const double* p, const double* q, const Reducer& R, int slot_rho,
+                      int slot_pq, int slot_rr, hipStream_t s);
+void launch_cg_dir(int n, const double* z, const double* p, double* pn, const double* S, int slot_new, int slot_old,
+                   hipStream_t s);
+void launch_bicg_s(int n, const double* r, const double* v, double* sv, const double* S, int slot_rho, int slot_rv,
+                   hipStream_t s);
+void launch_bicg_update(int n, double* x, double* r, const double* pt, const double* st, const double* sv,
+                        const double* t, const double* rb, const Reducer& R, int slot_rho, int slot_rv, int slot_tt,
+                        int slot_ts, int slot_rr, int slot_rhonew, hipStream_t s);
+void launch_bicg_dir(int n, const double* r, const double* p, const double* v, double* pn, const double* S,
+                     int slot_rho, int slot_rv, int slot_tt, int slot_ts, int slot_rhonew, hipStream_t s);
+void launch_scale_zero(int n, double* x, hipStream_t s);
+// err |= ERR_NONFINITE if any entry of a or b is NaN or Inf.
+void launch_check_finite(int n, const double* a, const double* b, int* err, hipStream_t s);
+// Round counter of the matching: cnt[6] = 1 + last round that had work.
+
+constexpr int kRedBlocks = 1024;  // max blocks of a reduction kernel
+constexpr int kRedBS = 256;
+
+}  // namespace amg

@@ -1,0 +1,667 @@
+// Setup-phase kernels: CSR validation and D^{-1}, node-based heavy edge
+// matching (Section 2.1.1, Algorithm 2) as rounds of locally dominant edges,
+// coarse numbering by prefix sum, the 0/1 Galerkin product P^T A P, aggregate
+// member lists, and the dense LU + inverse of the coarsest level.
+#include "amg_device.hpp"
+#include "amg_internal.hpp"
+
+namespace amg {
+
+namespace {
+constexpr int BS = 256;
+inline int blocks_for(int64_t work, int bs = BS, int cap = 1 << 30) {
+    int64_t b = (work + bs - 1) / bs;
+    if (b < 1) b = 1;
+    return (int)(b < cap ? b : cap);
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Validation of level 0 and inverse diagonal (the Jacobi smoother's D^{-1}).
+// Row bounds are checked before any entry of the row is read.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BS) void k_validate(int n, int64_t nnz, const int* __restrict__ rp,
+                                                 const int* __restrict__ ci, const double* __restrict__ v,
+                                                 double* __restrict__ dinv, int* err) {
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    const int b = rp[i], e = rp[i + 1];
+    int bits = 0;
+    if (i == 0 && b != 0) bits |= ERR_STRUCT;
+    if (i == n - 1 && (int64_t)e != nnz) bits |= ERR_STRUCT;
+    if (b < 0 || e < b || (int64_t)e > nnz) {
+        atomicOr(err, bits | ERR_STRUCT);
+        return;
+    }
+    double d = 0.0;
+    bool has_d = false;
+    int prev = -1;
+    for (int k = b; k < e; ++k) {
+        const int c = ci[k];
+        if (c < 0 || c >= n || c <= prev) {
+            bits |= ERR_STRUCT;
+            break;
+        }
+        prev = c;
+        const double x = v[k];
+        if (!isfinite(x)) bits |= ERR_NONFINITE;
+        if (c == i) {
+            has_d = true;
+            d = x;
+        }
+    }
+    if (!has_d || d == 0.0) bits |= ERR_DIAG;
+    dinv[i] = has_d && d != 0.0 ? 1.0 / d : 0.0;
+    if (bits) atomicOr(err, bits);
+}
+
+void launch_validate(int n, int64_t nnz, const int* rp, const int* ci, const double* v, double* dinv, int* err,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_validate, dim3(blocks_for(n)), dim3(BS), 0, s, n, nnz, rp, ci, v, dinv, err);
+}
+
+__global__ __launch_bounds__(BS) void k_dinv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                             const double* __restrict__ v, double* __restrict__ dinv, int* err) {
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+        if (ci[k] == i) d = v[k];
+    if (d == 0.0 || !isfinite(d)) atomicOr(err, ERR_DIAG);
+    dinv[i] = d != 0.0 ? 1.0 / d : 0.0;
+}
+
+void launch_dinv(int n, const int* rp, const int* ci, const double* v, double* dinv, int* err, hipStream_t s) {
+    hipLaunchKernelGGL(k_dinv, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, dinv, err);
+}
+
+// ---------------------------------------------------------------------------
+// Heavy edge matching.
+//
+// Visiting vertices in ascending order (Algorithm 2) is the greedy matching
+// over edges {u < w} (a_uw stored in row u, non-zero) in increasing key
+// (u, -|a_uw|, w).  Greedy matching in a strict edge order equals repeated
+// rounds of locally dominant edges: each undecided vertex points along its
+// smallest-key edge to an undecided neighbour, mutual pointers match, and a
+// vertex with no undecided neighbour is a singleton.  Under this key a vertex
+// points to its smallest undecided lower neighbour if it has one, otherwise
+// to its heaviest undecided higher neighbour (lowest index on ties).  Only a
+// vertex without undecided lower neighbours ("ready") can start a match, so
+// each round scans a worklist of ready vertices, and a per-vertex count of
+// undecided lower neighbours adds vertices to the next list as they become
+// ready.  Decisions carry the round number: a vertex counts as undecided in
+// round r while its stamp is >= r, so all reads in a round see the state at
+// the start of the round whatever the interleaving.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_col(const int* __restrict__ ci, int lo, int hi, int c) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int x = ci[mid];
+        if (x == c) return mid;
+        if (x < c) lo = mid + 1;
+        else hi = mid;
+    }
+    return -1;
+}
+
+// counters: cnt[0..2] worklist sizes (ring of 3), cnt[3..4] decided-list sizes
+// (ring of 2), cnt[5] sum over rows of (#upper - #lower) entries, cnt[6] the
+// number of rounds that had work.
+__global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                 const double* __restrict__ v, uint8_t* __restrict__ lowok,
+                                                 int* __restrict__ lcnt, int* __restrict__ dec,
+                                                 int* __restrict__ mate, int* __restrict__ wl0, int* cnt, int* err) {
+    const int y = blockIdx.x * BS + threadIdx.x;
+    if (y >= n) return;
+    dec[y] = kUndecided;
+    mate[y] = -1;
+    int c = 0, nlow = 0, nup = 0, bad = 0;
+    for (int k = rp[y]; k < rp[y + 1]; ++k) {
+        const int u = ci[k];
+        uint8_t ok = 0;
+        if (u < y) {
+            ++nlow;
+            const int pos = find_col(ci, rp[u], rp[u + 1], y);
+            if (pos < 0) bad = 1;
+            else if (v[pos] != 0.0) ok = 1;
+        } else if (u > y) {
+            ++nup;
+        }
+        lowok[k] = ok;
+        c += ok;
+    }
+    lcnt[y] = c;
+    if (bad) atomicOr(err, ERR_NONSYM);
+    if (nup != nlow) atomicAdd(&cnt[5], nup - nlow);
+    if (c == 0) wl0[atomicAdd(&cnt[0], 1)] = y;
+}
+
+__global__ __launch_bounds__(BS) void k_hem_decide(int r, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   const double* __restrict__ v, const uint8_t* __restrict__ lowok,
+                                                   int* dec, int* __restrict__ mate, const int* __restrict__ win,
+                                                   int* __restrict__ wout, int* __restrict__ newly, int* cnt,
+                                                   int slot_in, int slot_out, int slot_new, int zero_w, int zero_n) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        cnt[zero_w] = 0;
+        cnt[zero_n] = 0;
+    }
+    const int m = cnt[slot_in];
+    if (m > 0 && blockIdx.x == 0 && threadIdx.x == 0) cnt[6] = r + 1;  // rounds with work
+    for (int idx = blockIdx.x * BS + threadIdx.x; idx < m; idx += gridDim.x * BS) {
+        const int u = win[idx];
+        int best = -1;
+        double k = -1.0;
+        for (int e = rp[u]; e < rp[u + 1]; ++e) {
+            const int j = ci[e];
+            if (j <= u) continue;
+            const double a = v[e];
+            if (a != 0.0 && dec[j] >= r) {
+                const double w = fabs(a);
+                if (w > k) {
+                    k = w;
+                    best = j;
+                }
+            }
+        }
+        if (best < 0) {  // no undecided neighbour: unaggregated singleton
+            dec[u] = r;
+            mate[u] = -1;
+            newly[atomicAdd(&cnt[slot_new], 1)] = u;
+            continue;
+        }
+        // best points back to its smallest undecided lower neighbour
+        int back = -1;
+        for (int e = rp[best]; e < rp[best + 1]; ++e) {
+            const int x = ci[e];
+            if (x >= best) break;
+            if (lowok[e] && dec[x] >= r) {
+                back = x;
+                break;
+            }
+        }
+        if (back == u) {
+            dec[u] = r;
+            dec[best] = r;
+            mate[u] = best;
+            mate[best] = u;
+            const int pos = atomicAdd(&cnt[slot_new], 2);
+            newly[pos] = u;
+            newly[pos + 1] = best;
+        } else {
+            wout[atomicAdd(&cnt[slot_out], 1)] = u;  // still ready, retry next round
+        }
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_hem_propagate(int r, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                      const double* __restrict__ v, const int* __restrict__ dec,
+                                                      int* __restrict__ lcnt, const int* __restrict__ newly,
+                                                      int* __restrict__ wout, int* cnt, int slot_new, int slot_out) {
+    const int m = cnt[slot_new];
+    for (int idx = blockIdx.x * BS + threadIdx.x; idx < m; idx += gridDim.x * BS) {
+        const int x = newly[idx];
+        for (int e = rp[x]; e < rp[x + 1]; ++e) {
+            const int y = ci[e];
+            if (y > x && v[e] != 0.0) {
+                const int old = atomicSub(&lcnt[y], 1);
+                if (old == 1 && dec[y] > r) wout[atomicAdd(&cnt[slot_out], 1)] = y;
+            }
+        }
+    }
+}
+
+void launch_hem_init(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
+    hipLaunchKernelGGL(k_hem_init, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, w.lowok, w.lcnt, w.dec, w.mate,
+                       w.wl[0], w.cnt, w.err);
+}
+
+int hem_next_count_slot(int round) { return round % 3; }
+
+void launch_hem_round(int r, int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
+    const int g = blocks_for(n, BS, 512);
+    const int* win = w.wl[r & 1];
+    int* wout = w.wl[(r + 1) & 1];
+    const int slot_in = r % 3, slot_out = (r + 1) % 3, zero_w = (r + 2) % 3;
+    const int slot_new = 3 + (r & 1), zero_n = 3 + ((r + 1) & 1);
+    hipLaunchKernelGGL(k_hem_decide, dim3(g), dim3(BS), 0, s, r, rp, ci, v, w.lowok, w.dec, w.mate, win, wout,
+                       w.newly, w.cnt, slot_in, slot_out, slot_new, zero_w, zero_n);
+    hipLaunchKernelGGL(k_hem_propagate, dim3(g), dim3(BS), 0, s, r, rp, ci, v, w.dec, w.lcnt, w.newly, wout, w.cnt,
+                       slot_new, slot_out);
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive prefix sum (three phases: tile sums, scan of tile sums, apply).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = BS * SCAN_ITEMS;
+
+__device__ __forceinline__ int block_excl_scan(int x, int& total) {
+    __shared__ int sh[BS / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    int inc = x;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int y = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += y;
+    }
+    if (lane == kWave - 1) sh[wid] = inc;
+    __syncthreads();
+    int pre = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < BS / kWave; ++w) {
+        const int t = sh[w];
+        if (w < wid) pre += t;
+        total += t;
+    }
+    __syncthreads();
+    return pre + inc - x;
+}
+}  // namespace
+
+__global__ __launch_bounds__(BS) void k_scan_tiles(const int* __restrict__ in, int n, int* __restrict__ tsum) {
+    const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int s = 0;
+#pragma unroll
+    for (int t = 0; t < SCAN_ITEMS; ++t)
+        if (base + t < n) s += in[base + t];
+    int total;
+    block_excl_scan(s, total);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(BS) void k_scan_top(int* tsum, int nt) {
+    int carry = 0;
+    for (int base = 0; base < nt; base += BS) {
+        const int i = base + threadIdx.x;
+        const int x = i < nt ? tsum[i] : 0;
+        int total;
+        const int ex = block_excl_scan(x, total);
+        if (i < nt) tsum[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) tsum[nt] = carry;
+}
+
+__global__ __launch_bounds__(BS) void k_scan_apply(const int* __restrict__ in, int n, const int* __restrict__ tsum,
+                                                   int nt, int* __restrict__ out) {
+    const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int loc[SCAN_ITEMS];
+    int s = 0;
+#pragma unroll
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+        loc[t] = base + t < n ? in[base + t] : 0;
+        s += loc[t];
+    }
+    int total;
+    int ex = block_excl_scan(s, total) + tsum[blockIdx.x];
+#pragma unroll
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+        if (base + t < n) out[base + t] = ex;
+        ex += loc[t];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tsum[nt];
+}
+
+size_t scan_tmp_ints(int n) { return (size_t)(n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+void launch_scan(const int* in, int n, int* out, int* tmp, hipStream_t s) {
+    const int nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nt > 0) hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(BS), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BS), 0, s, tmp, nt);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt > 0 ? nt : 1), dim3(BS), 0, s, in, n, tmp, nt, out);
+}
+
+// Algorithm 2 hands out coarse ids when the smaller vertex of a pair (or a
+// singleton) is visited: ids are ranks of the aggregates' minimum vertex.
+__global__ __launch_bounds__(BS) void k_leader_flags(int n, const int* __restrict__ mate, int* __restrict__ flag) {
+    const int v = blockIdx.x * BS + threadIdx.x;
+    if (v >= n) return;
+    const int m = mate[v];
+    flag[v] = (m < 0 || v < m) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(BS) void k_assign_ids(int n, const int* __restrict__ mate, const int* __restrict__ ids,
+                                                   int* __restrict__ agg, int* __restrict__ lead) {
+    const int v = blockIdx.x * BS + threadIdx.x;
+    if (v >= n) return;
+    const int m = mate[v];
+    if (m >= 0 && m < v) return;
+    const int id = ids[v];
+    agg[v] = id;
+    if (m >= 0) agg[m] = id;
+    lead[id] = v;
+}
+
+void launch_leader_flags(int n, const int* mate, int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_leader_flags, dim3(blocks_for(n)), dim3(BS), 0, s, n, mate, flag);
+}
+
+void launch_assign_ids(int n, const int* mate, const int* ids, int* agg, int* lead, hipStream_t s) {
+    hipLaunchKernelGGL(k_assign_ids, dim3(blocks_for(n)), dim3(BS), 0, s, n, mate, ids, agg, lead);
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin product of one matching pass, A_c = P^T B P with P_{i,agg(i)} = 1
+// (Section 2.1.1).  Coarse row I has members lead[I] < mate[lead[I]]; entry
+// (I,J) sums b_ij over the members in ascending order and, within a member,
+// over its columns in ascending order, the first term initialising the sum.
+// The fixed order makes the values bit-identical on every run.  A thread owns
+// one coarse row and keeps its sorted (column, sum) list in registers; rows
+// with more than RAP_CAP distinct columns go to a slower in-place path.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int RAP_CAP = 32;
+constexpr int RAP_BS = 128;
+}
+
+__global__ __launch_bounds__(RAP_BS) void k_rap_count(int nc, const int* __restrict__ lead,
+                                                      const int* __restrict__ mate, const int* __restrict__ rp,
+                                                      const int* __restrict__ ci, const int* __restrict__ agg,
+                                                      int* __restrict__ rowcnt, int* __restrict__ ovf, int* novf) {
+    const int I = blockIdx.x * RAP_BS + threadIdx.x;
+    if (I >= nc) return;
+    const int m0 = lead[I];
+    const int mm[2] = {m0, mate[m0]};
+    SortedAcc<RAP_CAP> acc;
+    acc.clear();
+    bool ok = true;
+    for (int t = 0; t < 2 && ok; ++t) {
+        const int m = mm[t];
+        if (m < 0) continue;
+        for (int e = rp[m]; e < rp[m + 1]; ++e)
+            if (!acc.template add<false>(agg[ci[e]], 0.0)) {
+                ok = false;
+                break;
+            }
+    }
+    if (ok) {
+        rowcnt[I] = acc.len;
+    } else {
+        rowcnt[I] = 0;
+        ovf[atomicAdd(novf, 1)] = I;
+    }
+}
+
+__global__ __launch_bounds__(RAP_BS) void k_rap_fill(int nc, const int* __restrict__ lead,
+                                                     const int* __restrict__ mate, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci, const double* __restrict__ v,
+                                                     const int* __restrict__ agg, const int* __restrict__ crp,
+                                                     int* __restrict__ cci, double* __restrict__ cv) {
+    const int I = blockIdx.x * RAP_BS + threadIdx.x;
+    if (I >= nc) return;
+    const int m0 = lead[I];
+    const int mm[2] = {m0, mate[m0]};
+    SortedAcc<RAP_CAP> acc;
+    acc.clear();
+    for (int t = 0; t < 2; ++t) {
+        const int m = mm[t];
+        if (m < 0) continue;
+        for (int e = rp[m]; e < rp[m + 1]; ++e)
+            if (!acc.template add<true>(agg[ci[e]], v[e])) return;  // overflow row: slow path
+    }
+    const int o = crp[I];
+#pragma unroll
+    for (int t = 0; t < RAP_CAP; ++t) {
+        if (t < acc.len) {
+            cci[o + t] = acc.key[t];
+            cv[o + t] = acc.val[t];
+        }
+    }
+}
+
+// Distinct coarse columns of an overflow row: count entries whose column does
+// not occur earlier in the member/column order.
+__global__ __launch_bounds__(64) void k_rap_count_slow(const int* __restrict__ ovf, const int* novf,
+                                                       const int* __restrict__ lead, const int* __restrict__ mate,
+                                                       const int* __restrict__ rp, const int* __restrict__ ci,
+                                                       const int* __restrict__ agg, int* __restrict__ rowcnt) {
+    for (int t = blockIdx.x * 64 + threadIdx.x; t < *novf; t += gridDim.x * 64) {
+    const int I = ovf[t];
+    const int m0 = lead[I];
+    const int mm[2] = {m0, mate[m0]};
+    int count = 0;
+    for (int a = 0; a < 2; ++a) {
+        if (mm[a] < 0) continue;
+        for (int e = rp[mm[a]]; e < rp[mm[a] + 1]; ++e) {
+            const int J = agg[ci[e]];
+            bool seen = false;
+            for (int b = 0; b <= a && !seen; ++b) {
+                if (mm[b] < 0) continue;
+                const int end = (b == a) ? e : rp[mm[b] + 1];
+                for (int f = rp[mm[b]]; f < end; ++f)
+                    if (agg[ci[f]] == J) {
+                        seen = true;
+                        break;
+                    }
+            }
+            count += !seen;
+        }
+    }
+    rowcnt[I] = count;
+    }
+}
+
+// Overflow rows: insertion into the row's own output segment, kept sorted.
+__global__ __launch_bounds__(64) void k_rap_fill_slow(const int* __restrict__ ovf, const int* novf,
+                                                      const int* __restrict__ lead, const int* __restrict__ mate,
+                                                      const int* __restrict__ rp, const int* __restrict__ ci,
+                                                      const double* __restrict__ v, const int* __restrict__ agg,
+                                                      const int* __restrict__ crp, int* __restrict__ cci,
+                                                      double* __restrict__ cv) {
+    for (int t = blockIdx.x * 64 + threadIdx.x; t < *novf; t += gridDim.x * 64) {
+    const int I = ovf[t];
+    const int m0 = lead[I];
+    const int mm[2] = {m0, mate[m0]};
+    const int o = crp[I];
+    int len = 0;
+    for (int a = 0; a < 2; ++a) {
+        if (mm[a] < 0) continue;
+        for (int e = rp[mm[a]]; e < rp[mm[a] + 1]; ++e) {
+            const int J = agg[ci[e]];
+            int lo = 0, hi = len;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (cci[o + mid] < J) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < len && cci[o + lo] == J) {
+                cv[o + lo] += v[e];
+            } else {
+                for (int q = len; q > lo; --q) {
+                    cci[o + q] = cci[o + q - 1];
+                    cv[o + q] = cv[o + q - 1];
+                }
+                cci[o + lo] = J;
+                cv[o + lo] = v[e];
+                ++len;
+            }
+        }
+    }
+    }
+}
+
+void launch_rap_count(int nc, const int* lead, const int* mate, const int* rp, const int* ci, const int* agg,
+                      int* rowcnt, int* ovf, int* novf, hipStream_t s) {
+    hipLaunchKernelGGL(k_rap_count, dim3(blocks_for(nc, RAP_BS)), dim3(RAP_BS), 0, s, nc, lead, mate, rp, ci, agg,
+                       rowcnt, ovf, novf);
+}
+
+void launch_rap_count_slow(int nc, const int* ovf, const int* novf, const int* lead, const int* mate, const int* rp,
+                           const int* ci, const int* agg, int* rowcnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_rap_count_slow, dim3(blocks_for(nc, 64, 64)), dim3(64), 0, s, ovf, novf, lead, mate, rp, ci,
+                       agg, rowcnt);
+}
+
+void launch_rap_fill(int nc, const int* lead, const int* mate, const int* rp, const int* ci, const double* v,
+                     const int* agg, const int* crp, int* cci, double* cv, hipStream_t s) {
+    hipLaunchKernelGGL(k_rap_fill, dim3(blocks_for(nc, RAP_BS)), dim3(RAP_BS), 0, s, nc, lead, mate, rp, ci, v, agg,
+                       crp, cci, cv);
+}
+
+void launch_rap_fill_slow(int nc, const int* ovf, const int* novf, const int* lead, const int* mate, const int* rp,
+                          const int* ci, const double* v, const int* agg, const int* crp, int* cci, double* cv,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_rap_fill_slow, dim3(blocks_for(nc, 64, 64)), dim3(64), 0, s, ovf, novf, lead, mate, rp, ci,
+                       v, agg, crp, cci, cv);
+}
+
+// ---------------------------------------------------------------------------
+// Level maps: composed aggregate map and member lists of the coarse rows.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BS) void k_compose(int n, const int* __restrict__ a1, const int* __restrict__ a2,
+                                                int* __restrict__ out) {
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i < n) out[i] = a2[a1[i]];
+}
+
+void launch_compose(int n, const int* agg1, const int* agg2, int* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_compose, dim3(blocks_for(n)), dim3(BS), 0, s, n, agg1, agg2, out);
+}
+
+__device__ __forceinline__ void cswap(int& a, int& b) {
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    a = lo;
+    b = hi;
+}
+
+// lead2 == nullptr: a level made of a single pass (members of pass-1 pairs).
+__global__ __launch_bounds__(BS) void k_members(int nc, const int* __restrict__ lead2, const int* __restrict__ mate2,
+                                                const int* __restrict__ lead1, const int* __restrict__ mate1,
+                                                int4* __restrict__ mem) {
+    const int J = blockIdx.x * BS + threadIdx.x;
+    if (J >= nc) return;
+    constexpr int BIG = 0x7fffffff;
+    int m[4] = {BIG, BIG, BIG, BIG};
+    if (lead2 == nullptr) {
+        const int a = lead1[J], b = mate1[a];
+        m[0] = a;
+        m[1] = b < 0 ? BIG : b;
+    } else {
+        const int I1 = lead2[J], I2 = mate2[I1];
+        const int a1 = lead1[I1], b1 = mate1[a1];
+        m[0] = a1;
+        m[1] = b1 < 0 ? BIG : b1;
+        if (I2 >= 0) {
+            const int a2 = lead1[I2], b2 = mate1[a2];
+            m[2] = a2;
+            m[3] = b2 < 0 ? BIG : b2;
+        }
+    }
+    cswap(m[0], m[1]);
+    cswap(m[2], m[3]);
+    cswap(m[0], m[2]);
+    cswap(m[1], m[3]);
+    cswap(m[1], m[2]);
+    int4 o;
+    o.x = m[0] == BIG ? -1 : m[0];
+    o.y = m[1] == BIG ? -1 : m[1];
+    o.z = m[2] == BIG ? -1 : m[2];
+    o.w = m[3] == BIG ? -1 : m[3];
+    mem[J] = o;
+}
+
+void launch_members(int nc, const int* lead2, const int* mate2, const int* lead1, const int* mate1, int4* mem,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_members, dim3(blocks_for(nc)), dim3(BS), 0, s, nc, lead2, mate2, lead1, mate1, mem);
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest level (Section 2, coarse level solver): dense partial-pivot LU,
+// largest |pivot| with the lowest row on ties, then the explicit inverse so
+// that each V-cycle applies the exact coarse solve as one dense product.
+// One workgroup; the matrix lives in global memory (n <= 1024).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BS) void k_dense_assemble(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                       const double* __restrict__ v, double* __restrict__ a) {
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) a[(size_t)i * n + ci[k]] = v[k];
+}
+
+void launch_dense_assemble(int n, const int* rp, const int* ci, const double* v, double* a, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_assemble, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, a);
+}
+
+__global__ __launch_bounds__(BS) void k_dense_lu_inverse(int n, double* a, int* piv, double* ainv_t, int* err) {
+    __shared__ double sv[BS];
+    __shared__ int si[BS];
+    const int tid = threadIdx.x;
+    for (int k = 0; k < n; ++k) {
+        double best = -1.0;
+        int bi = n;
+        for (int i = k + tid; i < n; i += BS) {
+            const double t = fabs(a[(size_t)i * n + k]);
+            if (t > best) {
+                best = t;
+                bi = i;
+            }
+        }
+        sv[tid] = best;
+        si[tid] = bi;
+        __syncthreads();
+        for (int w = BS / 2; w > 0; w >>= 1) {
+            if (tid < w) {
+                const double ov = sv[tid + w];
+                const int oi = si[tid + w];
+                if (ov > sv[tid] || (ov == sv[tid] && oi < si[tid])) {
+                    sv[tid] = ov;
+                    si[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        const double pv = sv[0];
+        const int p = si[0];
+        __syncthreads();
+        if (!(pv > 0.0) || !isfinite(pv)) {
+            if (tid == 0) atomicOr(err, ERR_SINGULAR);
+            return;
+        }
+        if (tid == 0) piv[k] = p;
+        if (p != k)
+            for (int j = tid; j < n; j += BS) {
+                const double t = a[(size_t)k * n + j];
+                a[(size_t)k * n + j] = a[(size_t)p * n + j];
+                a[(size_t)p * n + j] = t;
+            }
+        __syncthreads();
+        const double d = a[(size_t)k * n + k];
+        for (int i = k + 1 + tid; i < n; i += BS) a[(size_t)i * n + k] /= d;
+        __syncthreads();
+        const int m = n - k - 1;
+        for (int t = tid; t < m * m; t += BS) {
+            const int i = k + 1 + t / m, j = k + 1 + t % m;
+            a[(size_t)i * n + j] -= a[(size_t)i * n + k] * a[(size_t)k * n + j];
+        }
+        __syncthreads();
+    }
+    // column c of the inverse (contiguous in ainv_t) solves A x = e_c
+    for (int c = tid; c < n; c += BS) {
+        double* x = ainv_t + (size_t)c * n;
+        for (int i = 0; i < n; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+        for (int k = 0; k < n; ++k) {
+            const int p = piv[k];
+            const double t = x[k];
+            x[k] = x[p];
+            x[p] = t;
+        }
+        for (int i = 0; i < n; ++i) {
+            double s = x[i];
+            for (int j = 0; j < i; ++j) s -= a[(size_t)i * n + j] * x[j];
+            x[i] = s;
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = x[i];
+            for (int j = i + 1; j < n; ++j) s -= a[(size_t)i * n + j] * x[j];
+            x[i] = s / a[(size_t)i * n + i];
+        }
+    }
+}
+
+void launch_dense_lu_inverse(int n, double* a, int* piv, double* ainv_t, int* err, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_lu_inverse, dim3(1), dim3(BS), 0, s, n, a, piv, ainv_t, err);
+}
+
+}  // namespace amg

@@ -1,0 +1,252 @@
+"""Thin ctypes binding of libhemamg.so (include/hemamg.h).
+
+Functions carry the C names and only marshal arguments: every step of the
+setup and solve runs in the library's HIP kernels.  PyTorch supplies device
+memory (tensor data pointers) and the stream.  Importing this module does not
+touch the GPU; the first call loads the library and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhemamg.so")
+
+AMG_OK, AMG_EINVAL, AMG_ENOMEM, AMG_ENOTCONV, AMG_EBREAKDOWN, AMG_ENOTFINITE, AMG_ESTALL, AMG_ESINGULAR, AMG_EHIP = \
+    range(9)
+STATUS_NAMES = ["AMG_OK", "AMG_EINVAL", "AMG_ENOMEM", "AMG_ENOTCONV", "AMG_EBREAKDOWN", "AMG_ENOTFINITE",
+                "AMG_ESTALL", "AMG_ESINGULAR", "AMG_EHIP"]
+PCG, BICGSTAB = 0, 1
+KERNEL_PROLONG_POST, KERNEL_RESID_RESTRICT, KERNEL_SPMV = 0, 1, 2
+
+EXPORTED = ["amg_params_default", "amg_setup", "amg_destroy", "amg_vcycle", "krylov_solve", "amg_num_levels",
+            "amg_level_size", "amg_export_level", "amg_setup_stats", "amg_timing_enable", "amg_timing_read",
+            "amg_last_error"]
+
+
+class amg_csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
+                ("val", C.c_void_p)]
+
+
+class amg_params(C.Structure):
+    _fields_ = [("passes_per_level", C.c_int32), ("max_coarse_rows", C.c_int32), ("max_levels", C.c_int32),
+                ("max_dense_rows", C.c_int32), ("omega", C.c_double), ("pre", C.c_int32), ("post", C.c_int32),
+                ("true_res_period", C.c_int32)]
+
+
+class amg_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("rel_res", C.c_double), ("true_rel_res", C.c_double),
+                ("solve_ms", C.c_double), ("status", C.c_int32)]
+
+
+class AmgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libhemamg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2007_00056_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "amg_params_default": [C.POINTER(amg_params)],
+            "amg_setup": [C.POINTER(amg_csr), C.POINTER(amg_params), vp, C.POINTER(vp)],
+            "amg_destroy": [vp],
+            "amg_vcycle": [vp, vp, vp, vp],
+            "krylov_solve": [vp, i32, vp, vp, f64, i32, vp, C.POINTER(amg_info)],
+            "amg_num_levels": [vp, C.POINTER(i32)],
+            "amg_level_size": [vp, i32, C.POINTER(i32), C.POINTER(i64)],
+            "amg_export_level": [vp, i32, vp, vp, vp, vp, vp],
+            "amg_setup_stats": [vp, vp, i32, C.POINTER(i32), C.POINTER(C.c_size_t)],
+            "amg_timing_enable": [vp, i32, i32],
+            "amg_timing_read": [vp, i32, C.POINTER(i64), C.POINTER(f64)],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.amg_last_error.argtypes = []
+        L.amg_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != AMG_OK:
+        raise AmgError(st, lib().amg_last_error().decode())
+
+
+def _stream_ptr(stream) -> int | None:
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream if hasattr(s, "cuda_stream") else int(s)
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+# ---------------------------------------------------------------- C entry points
+
+def amg_params_default(**overrides) -> amg_params:
+    p = amg_params()
+    _check(lib().amg_params_default(C.byref(p)))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+class DeviceCSR:
+    """CSR matrix in GPU memory (torch tensors) plus its amg_csr view."""
+
+    def __init__(self, row_ptr, col_idx, val):
+        self.row_ptr, self.col_idx, self.val = row_ptr, col_idx, val
+        self.n = int(row_ptr.numel() - 1)
+        self.nnz = int(col_idx.numel())
+        self.c = amg_csr(self.n, self.nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(val))
+
+    @classmethod
+    def from_host(cls, a, device="cuda"):
+        import torch
+
+        return cls(torch.from_numpy(np.ascontiguousarray(a.row_ptr, dtype=np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(a.col, dtype=np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(a.val, dtype=np.float64)).to(device))
+
+
+def amg_setup(A: DeviceCSR, params: amg_params | None = None, stream=None) -> int:
+    """Returns the handle (an opaque pointer value)."""
+    h = C.c_void_p()
+    _check(lib().amg_setup(C.byref(A.c), C.byref(params) if params is not None else None, _stream_ptr(stream),
+                           C.byref(h)))
+    return h.value
+
+
+def amg_destroy(h: int) -> None:
+    _check(lib().amg_destroy(h))
+
+
+def amg_vcycle(h: int, r, z, stream=None) -> None:
+    _check(lib().amg_vcycle(h, _ptr(r), _ptr(z), _stream_ptr(stream)))
+
+
+def krylov_solve(h: int, method: int, b, x, rtol: float, maxit: int, stream=None, check: bool = True) -> dict:
+    info = amg_info()
+    st = lib().krylov_solve(h, method, _ptr(b), _ptr(x), rtol, maxit, _stream_ptr(stream), C.byref(info))
+    out = dict(status=st, iters=info.iters, rel_res=info.rel_res, true_rel_res=info.true_rel_res,
+               solve_ms=info.solve_ms)
+    if check and st not in (AMG_OK,):
+        raise AmgError(st, lib().amg_last_error().decode())
+    return out
+
+
+def amg_num_levels(h: int) -> int:
+    n = C.c_int32()
+    _check(lib().amg_num_levels(h, C.byref(n)))
+    return n.value
+
+
+def amg_level_size(h: int, k: int):
+    n, nnz = C.c_int32(), C.c_int64()
+    _check(lib().amg_level_size(h, k, C.byref(n), C.byref(nnz)))
+    return n.value, nnz.value
+
+
+def amg_export_level(h: int, k: int, stream=None):
+    """Level k as host arrays (row_ptr, col_idx, val, agg or None)."""
+    n, nnz = amg_level_size(h, k)
+    rp = np.empty(n + 1, np.int32)
+    ci = np.empty(max(nnz, 1), np.int32)
+    v = np.empty(max(nnz, 1), np.float64)
+    last = k == amg_num_levels(h) - 1
+    agg = None if last else np.empty(n, np.int32)
+    _check(lib().amg_export_level(h, k, rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
+                                  None if agg is None else agg.ctypes.data, _stream_ptr(stream)))
+    return rp, ci[:nnz], v[:nnz], agg
+
+
+def amg_setup_stats(h: int):
+    cap = 256
+    rounds = np.zeros(cap, np.int32)
+    npass = C.c_int32()
+    owned = C.c_size_t()
+    _check(lib().amg_setup_stats(h, rounds.ctypes.data, cap, C.byref(npass), C.byref(owned)))
+    return dict(rounds=rounds[:min(npass.value, cap)].tolist(), owned_bytes=owned.value)
+
+
+def amg_timing_enable(h: int, kernel: int, on: bool = True) -> None:
+    _check(lib().amg_timing_enable(h, kernel, int(on)))
+
+
+def amg_timing_read(h: int, kernel: int):
+    cnt, ms = C.c_int64(), C.c_double()
+    _check(lib().amg_timing_read(h, kernel, C.byref(cnt), C.byref(ms)))
+    return cnt.value, ms.value
+
+
+def amg_last_error() -> str:
+    return lib().amg_last_error().decode()
+
+
+# ---------------------------------------------------------------- convenience
+
+class Hierarchy:
+    """Owns an amg_setup handle and the device matrix it borrows."""
+
+    def __init__(self, A: DeviceCSR, params: amg_params | None = None, stream=None, **overrides):
+        if params is None:
+            params = amg_params_default(**overrides)
+        self.A = A  # level 0 is borrowed: keep it alive
+        self.params = params
+        self.h = amg_setup(A, params, stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            amg_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def nlevels(self) -> int:
+        return amg_num_levels(self.h)
+
+    def level(self, k: int):
+        return amg_export_level(self.h, k)
+
+    def vcycle(self, r, z=None, stream=None):
+        import torch
+
+        z = torch.empty_like(r) if z is None else z
+        amg_vcycle(self.h, r, z, stream)
+        return z
+
+    def solve(self, b, x=None, method: str = "pcg", rtol: float = 1e-8, maxit: int = 1000, stream=None,
+              check: bool = True):
+        import torch
+
+        x = torch.zeros_like(b) if x is None else x
+        info = krylov_solve(self.h, {"pcg": PCG, "bicgstab": BICGSTAB}[method], b, x, rtol, maxit, stream, check)
+        return x, info
+
+    def stats(self):
+        return amg_setup_stats(self.h)

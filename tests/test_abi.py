@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every function include/hemamg.h declares
+(no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+from paper_2007_00056_amd import hemamg
+
+HEADER = os.path.join(ROOT, "include", "hemamg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:amg_status|const char\s*\*)\s+(\w+)\s*\(", text, flags=re.M)
+    return names
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for required in ("amg_setup", "amg_vcycle", "krylov_solve", "amg_destroy", "amg_export_level"):
+        assert required in names
+    assert sorted(names) == sorted(hemamg.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(hemamg.LIB_PATH):
+        pytest.fail("libhemamg.so is not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(hemamg.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(hemamg, "_lib", None)
+    monkeypatch.setattr(hemamg, "LIB_PATH", "/nonexistent/libhemamg.so")
+    with pytest.raises(ImportError):
+        hemamg.lib()
+
+
+def test_struct_layouts_match_header():
+    # amg_params: 4 int32, double, 3 int32 -> 40 bytes with natural alignment
+    assert ctypes.sizeof(hemamg.amg_params) == 40
+    assert ctypes.sizeof(hemamg.amg_csr) == 40
+    assert ctypes.sizeof(hemamg.amg_info) == 40
+
+
+def test_params_default_values():
+    if not os.path.exists(hemamg.LIB_PATH):
+        pytest.fail("libhemamg.so is not built")
+    p = hemamg.amg_params_default()  # host-only call, no GPU work
+    assert (p.passes_per_level, p.max_coarse_rows, p.max_levels, p.max_dense_rows) == (2, 64, 32, 1024)
+    assert abs(p.omega - 2.0 / 3.0) < 1e-16 and (p.pre, p.post, p.true_res_period) == (1, 1, 50)

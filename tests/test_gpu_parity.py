@@ -1,0 +1,274 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (stated by the method's specification of this build):
+  * aggregate maps and every coarse level (row_ptr, col_idx and the bits of
+    every value) are bit-identical: both sides run the same deterministic
+    matching and sum each Galerkin entry in the same fixed order;
+  * FP64 solutions agree to relative 2-norm error <= 1e-9 at equal iteration
+    count, and stopping iterations agree within +-1;
+  * one V-cycle agrees to relative error <= 1e-11: both apply the same linear
+    operator in FP64 and differ only in rounding (fused multiply-adds,
+    reduction order, explicit coarse inverse versus LU substitution).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_00056_amd import hemamg, problems as P
+
+pytestmark = pytest.mark.gpu
+
+SOL_TOL = 1e-9
+VC_TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+
+    assert _t.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return _t
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def both(a, **kw):
+    gp = hemamg.amg_params_default(**kw)
+    okw = {k: v for k, v in kw.items() if k in ("passes_per_level", "max_coarse_rows", "max_levels",
+                                                  "max_dense_rows", "omega", "pre", "post")}
+    A = hemamg.DeviceCSR.from_host(a)
+    g = hemamg.Hierarchy(A, gp)
+    o = oracle.Hierarchy(a, **okw)
+    return g, o
+
+
+def bits(x):
+    return np.ascontiguousarray(x, dtype=np.float64).view(np.int64)
+
+
+def assert_same_hierarchy(g, o):
+    assert g.nlevels == o.nlevels
+    for k in range(o.nlevels):
+        ol = o.level(k)
+        rp, ci, v, agg = g.level(k)
+        np.testing.assert_array_equal(rp, ol.row_ptr, err_msg=f"level {k} row_ptr")
+        np.testing.assert_array_equal(ci, ol.col, err_msg=f"level {k} col_idx")
+        np.testing.assert_array_equal(bits(v), bits(ol.val), err_msg=f"level {k} values")
+        if ol.agg is not None:
+            np.testing.assert_array_equal(agg, ol.agg, err_msg=f"level {k} aggregates")
+
+
+CASES = {
+    "poisson2d_64": lambda: P.poisson2d(64),
+    "poisson3d_17x13x11": lambda: P.poisson3d(17, 13, 11),
+    "convdiff3d_13": lambda: P.convdiff3d(13),
+    "lognormal3d_11": lambda: P.lognormal_diffusion3d(11, 5),
+    "vardiff3d_20": lambda: P.vardiff3d(20, seed=1, corr_len=4.0),
+    "random_ties_300": lambda: P.random_symmetric_pattern(300, 0.02, 3, weights=(1, 2)),
+    "random_nonsym_zeros_400": lambda: P.random_symmetric_pattern(400, 0.015, 4, weights=(1, 2, 3),
+                                                                  nonsym_values=True, explicit_zeros=0.1),
+}
+NONSYM = {"convdiff3d_13", "random_nonsym_zeros_400"}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_bit_identical(torch, name):
+    say("case", name)
+    a = CASES[name]()
+    g, o = both(a)
+    assert_same_hierarchy(g, o)
+    g.close()
+
+
+def test_worked_example_single_pass(torch, golden):
+    gold = golden("hem_worked_example.txt")
+    a = P.from_dense(np.array(gold["A"]))
+    g, o = both(a, passes_per_level=1, max_coarse_rows=3)
+    assert g.nlevels == 2
+    rp, ci, v, agg = g.level(0)
+    Pm = np.zeros((6, 3))
+    Pm[np.arange(6), agg] = 1
+    np.testing.assert_array_equal(Pm, np.array(gold["P"]))
+    rp1, ci1, v1, _ = g.level(1)
+    import scipy.sparse as sp
+
+    np.testing.assert_array_equal(sp.csr_matrix((v1, ci1, rp1), shape=(3, 3)).toarray(), np.array(gold["Ac"]))
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_vcycle_matches_oracle(torch, name):
+    say("case", name)
+    a = CASES[name]()
+    g, o = both(a)
+    f = P.rhs_uniform(a.n, 11)
+    z = g.vcycle(dev(torch, f)).cpu().numpy()
+    assert rel(z, o.vcycle(f)) <= VC_TOL
+    g.close()
+
+
+def solve_parity(torch, a, method, rtol, seed=0, **kw):
+    g, o = both(a, **kw)
+    b = P.rhs_uniform(a.n, seed)
+    xo, io = o.solve(b, method=method, rtol=rtol, maxit=500)
+    assert io["status"] == oracle.OK
+    xg, ig = g.solve(dev(torch, b), method=method, rtol=rtol, maxit=500)
+    assert ig["status"] == hemamg.AMG_OK
+    assert abs(ig["iters"] - io["iters"]) <= 1, (ig, io)
+    assert ig["true_rel_res"] <= rtol
+    # equal iteration count for the solution comparison
+    xg2, ig2 = g.solve(dev(torch, b), method=method, rtol=0.0, maxit=io["iters"], check=False)
+    assert ig2["status"] == hemamg.AMG_ENOTCONV and ig2["iters"] == io["iters"]
+    err = rel(xg2.cpu().numpy(), xo)
+    assert err <= SOL_TOL, err
+    g.close()
+    return ig, io
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_matches_oracle(torch, name):
+    say("case", name)
+    method = "bicgstab" if name in NONSYM else "pcg"
+    solve_parity(torch, CASES[name](), method, 1e-8)
+
+
+@pytest.mark.parametrize("kw", [dict(pre=2, post=2), dict(pre=0, post=1), dict(pre=1, post=0),
+                                dict(passes_per_level=1), dict(max_levels=2, max_coarse_rows=16),
+                                dict(omega=0.5, max_coarse_rows=1)])
+def test_parameter_variants_match_oracle(torch, kw):
+    say("params", kw)
+    a = P.poisson3d(12, 10, 9)
+    g, o = both(a, **kw)
+    assert_same_hierarchy(g, o)
+    g.close()
+    solve_parity(torch, a, "pcg", 1e-8, **kw)
+
+
+def test_deterministic_bitwise(torch):
+    a = P.lognormal_diffusion3d(14, 2)
+    A = hemamg.DeviceCSR.from_host(a)
+    b = dev(torch, P.rhs_uniform(a.n, 0))
+    with hemamg.Hierarchy(A) as g:
+        x1, i1 = g.solve(b, rtol=1e-10)
+        x2, i2 = g.solve(b, rtol=1e-10)
+    with hemamg.Hierarchy(A) as g2:
+        x3, _ = g2.solve(b, rtol=1e-10)
+    assert i1["iters"] == i2["iters"]
+    assert torch.equal(x1, x2) and torch.equal(x1, x3)
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_one_by_one(torch):
+    a = P.CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([4.0]))
+    g, o = both(a)
+    assert g.nlevels == 1
+    x, info = g.solve(dev(torch, np.array([2.0])), rtol=1e-12)
+    assert info["iters"] == 1 and x.item() == 0.5
+
+
+def test_single_level_is_exact(torch):
+    a = P.poisson2d(7, 9)
+    g, o = both(a)
+    assert g.nlevels == 1
+    b = P.rhs_uniform(a.n, 1)
+    x, info = g.solve(dev(torch, b), rtol=1e-12)
+    assert info["iters"] == 1
+    assert rel(x.cpu().numpy(), np.linalg.solve(a.to_scipy().toarray(), b)) < 1e-13
+
+
+def test_zero_rhs_and_iteration_limit(torch):
+    a = P.poisson2d(20)
+    A = hemamg.DeviceCSR.from_host(a)
+    with hemamg.Hierarchy(A) as g:
+        x = torch.ones(a.n, dtype=torch.float64, device="cuda")
+        x, info = g.solve(torch.zeros_like(x), x=x)
+        assert info["iters"] == 0 and not x.any()
+        b = P.rhs_uniform(a.n, 0)
+        x, info = g.solve(dev(torch, b), rtol=1e-14, maxit=3, check=False)
+        assert info["status"] == hemamg.AMG_ENOTCONV and info["iters"] == 3
+        xo, io = oracle.Hierarchy(a).solve(b, rtol=1e-14, maxit=3)
+        assert io["status"] == oracle.ENOTCONV
+        assert rel(x.cpu().numpy(), xo) <= SOL_TOL
+
+
+def test_nonfinite_rhs_rejected(torch):
+    a = P.poisson2d(10)
+    with hemamg.Hierarchy(hemamg.DeviceCSR.from_host(a)) as g:
+        b = P.rhs_uniform(a.n, 0)
+        b[5] = np.nan
+        _, info = g.solve(dev(torch, b), check=False)
+        assert info["status"] == hemamg.AMG_ENOTFINITE
+
+
+def bad_setup(torch, a):
+    with pytest.raises(hemamg.AmgError) as e:
+        hemamg.Hierarchy(hemamg.DeviceCSR.from_host(a))
+    return e.value.status
+
+
+def test_invalid_matrices_rejected(torch):
+    a = P.poisson2d(6)
+    z = P.CSR(a.n, a.row_ptr, a.col, a.val.copy())
+    z.val[0] = 0.0
+    assert bad_setup(torch, z) == hemamg.AMG_EINVAL  # zero diagonal
+    nf = P.CSR(a.n, a.row_ptr, a.col, a.val.copy())
+    nf.val[3] = np.inf
+    assert bad_setup(torch, nf) == hemamg.AMG_ENOTFINITE
+    un = P.CSR(a.n, a.row_ptr, a.col.copy(), a.val)
+    un.col[[1, 2]] = un.col[[2, 1]]  # columns out of order in row 0
+    assert bad_setup(torch, un) == hemamg.AMG_EINVAL
+    oor = P.CSR(a.n, a.row_ptr, a.col.copy(), a.val)
+    oor.col[-1] = a.n  # column out of range
+    assert bad_setup(torch, oor) == hemamg.AMG_EINVAL
+    # structurally unsymmetric (needs more rows than one dense level holds):
+    # drop the (1,0) entry of row 1, then the (0,1) entry of row 0
+    d = P.poisson2d(10).to_scipy().toarray()
+    d[1, 0] = 0.0
+    assert bad_setup(torch, P.from_dense(d)) == hemamg.AMG_EINVAL
+    d = P.poisson2d(10).to_scipy().toarray()
+    d[0, 1] = 0.0
+    assert bad_setup(torch, P.from_dense(d)) == hemamg.AMG_EINVAL
+    # n = 0
+    c = hemamg.amg_csr(0, 0, None, None, None)
+    h = hemamg.C.c_void_p()
+    st = hemamg.lib().amg_setup(hemamg.C.byref(c), None, None, hemamg.C.byref(h))
+    assert st == hemamg.AMG_EINVAL and not h.value
+
+
+def test_stall_dense_fallback_and_error(torch):
+    small = P.from_dense(np.diag(np.arange(1.0, 101.0)))
+    g, o = both(small)
+    assert g.nlevels == o.nlevels == 1
+    b = P.rhs_uniform(100, 0)
+    x, info = g.solve(dev(torch, b), rtol=1e-12)
+    np.testing.assert_allclose(x.cpu().numpy(), b / np.arange(1.0, 101.0), rtol=1e-14)
+    big = P.CSR(2000, np.arange(2001, dtype=np.int32), np.arange(2000, dtype=np.int32), np.arange(1.0, 2001.0))
+    assert bad_setup(torch, big) == hemamg.AMG_ESTALL
+
+
+# ---------------------------------------------------------------- full size
+
+def test_poisson3d_128_full_size(torch):
+    """The 128^3 workload in the configuration the benchmark times."""
+    say("case poisson3d_128")
+    a = P.poisson3d(128)
+    ig, io = solve_parity(torch, a, "pcg", 1e-10)
+    say("gpu", ig, "oracle", io)
+
+
+def test_poisson3d_128_hierarchy(torch):
+    a = P.poisson3d(128)
+    g, o = both(a)
+    assert_same_hierarchy(g, o)
+    say("rounds per pass", g.stats()["rounds"])
+    g.close()
