@@ -32,27 +32,35 @@ def level_sizes(h, hemamg):
     return [hemamg.amg_level_size(h, k) for k in range(L)]
 
 
+STREAM_MIN = 32768  # levels with at least this many rows use the CSR-stream kernels
+
+
 def kernel_bytes(sizes):
-    """Algorithmic bytes per launch of the level-0 kernels (FP64 values,
-    int32 indices; each array counted once)."""
+    """Algorithmic bytes per launch of the timed level-0 kernels (FP64 values,
+    int32 indices; every array counted once)."""
     (n, nnz), nc = sizes[0], (sizes[1][0] if len(sizes) > 1 else 0)
     return {
-        # 12 nnz (val+col) + 4(n+1) row_ptr + dinv, f, agg, z (8+8+4+8) n + e 8 nc
+        # prolongation + postsmoothing: val+col 12 nnz, row_ptr 4(n+1), dinv f agg z 28 n, coarse e 8 nc
         0: 12 * nnz + 4 * (n + 1) + 28 * n + 8 * nc,
-        # 12 nnz + 4(n+1) + dinv, f 16 n + members 16 nc + f_c 8 nc
-        1: 12 * nnz + 4 * (n + 1) + 16 * n + 24 * nc,
-        # 12 nnz + 4(n+1) + p read, q write 16 n
+        # presmoothing + residual: 12 nnz + 4(n+1), dinv f 16 n, r 8 n
+        1: 12 * nnz + 4 * (n + 1) + 24 * n,
+        # outer SpMV + dot: 12 nnz + 4(n+1), p read + q write 16 n
         2: 12 * nnz + 4 * (n + 1) + 16 * n,
     }
+
+
+def level_bytes(n, nnz, nc):
+    """One V-cycle level (down + up sweep)."""
+    if n >= STREAM_MIN:  # residual, restriction (members 16 nc, r 8 n, f_c 8 nc), prolongation + smoothing
+        return (12 * nnz + 4 * (n + 1) + 24 * n) + (24 * nc + 8 * n) + (12 * nnz + 4 * (n + 1) + 28 * n + 8 * nc)
+    return (12 * nnz + 4 * (n + 1) + 16 * n + 24 * nc) + (12 * nnz + 4 * (n + 1) + 28 * n + 8 * nc)
 
 
 def iteration_bytes(sizes, method):
     """Algorithmic bytes of one Krylov iteration (V-cycle + outer kernels)."""
     vc = 0
     for k in range(len(sizes) - 1):
-        n, nnz = sizes[k]
-        nc = sizes[k + 1][0]
-        vc += (12 * nnz + 4 * (n + 1) + 16 * n + 24 * nc) + (12 * nnz + 4 * (n + 1) + 28 * n + 8 * nc)
+        vc += level_bytes(sizes[k][0], sizes[k][1], sizes[k + 1][0])
     m = sizes[-1][0]
     vc += 8 * m * m + 16 * m
     n, nnz = sizes[0]
@@ -168,7 +176,7 @@ def main():
     solve_ms = float(np.median([r["solve_ms"] for r in recs]))
     it_bytes = iteration_bytes(sizes, method)
     kb = kernel_bytes(sizes)
-    names = {0: "k_prolong_post (level 0)", 1: "k_resid_restrict (level 0)", 2: "k_spmv_dot (outer SpMV)"}
+    names = {0: "k_stream_post (level 0)", 1: "k_stream_resid (level 0)", 2: "k_stream_spmv_dot (outer SpMV)"}
     kernels = {}
     for k, (c, ms) in kern_tot.items():
         if c:

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -122,12 +123,12 @@ struct amg_hier {
            *sv = nullptr, *st = nullptr, *t = nullptr;
     double* S = nullptr;
     double* part = nullptr;
-    unsigned* ticket = nullptr;
     int* err = nullptr;
+    int stream_min = 32768;  // levels with at least this many rows use CSR-stream kernels
     double* S_host = nullptr;
     Timer tim[3];
 
-    Reducer reducer() const { return Reducer{part, ticket, S}; }
+    Reducer reducer() const { return Reducer{part, S}; }
 
     ~amg_hier() {
         if (stream) (void)hipStreamSynchronize(stream);
@@ -184,8 +185,57 @@ struct Csr {
     double* v = nullptr;
 };
 
-// One matching pass on B: mate, aggregate map and leaders.  Buffers come from
-// `tmp` (freed with the level) except those the caller keeps.
+// Buffers reused by every matching pass and Galerkin product of a setup,
+// sized for level 0 (every later pass is smaller).
+struct SetupWork {
+    HemWork hw{};
+    int* mate[2]{};
+    int* agg[2]{};
+    int* lead[2]{};
+    int* flag = nullptr;
+    int* ids = nullptr;
+    int* stmp = nullptr;
+    int* rowcnt = nullptr;
+    int* ovf = nullptr;
+    int* novf = nullptr;
+    int* hc = nullptr;  // pinned: worklist sizes read back between batches
+    hipEvent_t ev[2]{};
+    int hem_small = 65536;  // passes on at most this many rows run in one workgroup
+
+    void init(int n, int64_t nnz, DevPool& P, int* err) {
+        hw.lowok = P.get<uint8_t>((size_t)nnz);
+        hw.rec = P.get<HemRec>(n);
+        hw.lcnt = P.get<int>(n);
+        hw.dec = P.get<int>(n);
+        hw.wl[0] = P.get<int>(n);
+        hw.wl[1] = P.get<int>(n);
+        hw.cnt = P.get<int>(8);
+        hw.err = err;
+        for (int t = 0; t < 2; ++t) {
+            mate[t] = P.get<int>(n);
+            agg[t] = P.get<int>(n);
+            lead[t] = P.get<int>(n);
+        }
+        flag = P.get<int>(n);
+        ids = P.get<int>((size_t)n + 1);
+        stmp = P.get<int>(scan_tmp_ints(n));
+        rowcnt = P.get<int>(n);
+        ovf = P.get<int>(n);
+        novf = P.get<int>(1);
+        HIPCHK(hipHostMalloc((void**)&hc, 2 * sizeof(int), hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        if (const char* e = getenv("HEMAMG_HEM_SMALL")) hem_small = atoi(e);  // tuning sweeps
+    }
+    ~SetupWork() {
+        if (hc) (void)hipHostFree(hc);
+        if (ev[0]) (void)hipEventDestroy(ev[0]);
+        if (ev[1]) (void)hipEventDestroy(ev[1]);
+    }
+};
+
+// One matching pass on B (Algorithm 2) into slot t: mate, aggregate map and
+// the smaller vertex (leader) of each aggregate.
 struct Pass {
     int* mate = nullptr;
     int* agg = nullptr;
@@ -194,96 +244,67 @@ struct Pass {
     int rounds = 0;
 };
 
-Pass hem_pass(const Csr& B, DevPool& tmp, hipStream_t s, int* err) {
+Pass hem_pass(const Csr& B, SetupWork& W, int t, hipStream_t s, int* err) {
     const int n = B.n;
-    HemWork w;
-    w.lowok = tmp.get<uint8_t>((size_t)B.nnz);
-    w.lcnt = tmp.get<int>(n);
-    w.dec = tmp.get<int>(n);
-    w.mate = tmp.get<int>(n);
-    w.wl[0] = tmp.get<int>(n);
-    w.wl[1] = tmp.get<int>(n);
-    w.newly = tmp.get<int>(n);
-    w.cnt = tmp.get<int>(8);
-    w.err = err;
+    HemWork w = W.hw;
+    w.mate = W.mate[t];
     HIPCHK(hipMemsetAsync(w.cnt, 0, 8 * sizeof(int), s));
     launch_hem_init(n, B.rp, B.ci, B.v, w, s);
-    HIPCHK(hipGetLastError());
-    {
-        int head[8];
-        HIPCHK(hipMemcpyAsync(head, w.cnt, sizeof(head), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        check_err_word(err, s, "matching");
-        if (head[5] != 0) raise(AMG_EINVAL, "matching: sparsity pattern is not structurally symmetric");
-    }
-    // Rounds are launched in batches; the size of the next worklist is copied
-    // back after each batch and checked one batch later, so the host check
-    // overlaps the GPU work.  Rounds with an empty worklist do nothing.
-    int* hc = nullptr;
-    HIPCHK(hipHostMalloc((void**)&hc, 2 * sizeof(int), hipHostMallocDefault));
-    std::unique_ptr<int, void (*)(int*)> hc_guard(hc, [](int* p) { (void)hipHostFree(p); });
-    hipEvent_t ev[2];
-    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-    struct EvGuard {
-        hipEvent_t* e;
-        ~EvGuard() {
-            (void)hipEventDestroy(e[0]);
-            (void)hipEventDestroy(e[1]);
-        }
-    } eg{ev};
-    const int batch = 8;
-    int r = 0;
-    for (int j = 0;; ++j) {
-        for (int b = 0; b < batch; ++b, ++r) launch_hem_round(r, n, B.rp, B.ci, B.v, w, s);
+    if (n <= W.hem_small) {
+        launch_hem_all(n, B.rp, B.ci, B.v, w, s);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(&hc[j & 1], w.cnt + hem_next_count_slot(r), sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipEventRecord(ev[j & 1], s));
-        if (j >= 1) {
-            HIPCHK(hipEventSynchronize(ev[(j - 1) & 1]));
-            if (hc[(j - 1) & 1] == 0) break;
+    } else {
+        // Rounds are launched in batches; the size of the next worklist is
+        // copied back after each batch and checked one batch later, so the host
+        // check overlaps the GPU work.  Rounds with an empty worklist do nothing.
+        const int batch = 16;
+        int r = 0;
+        for (int j = 0;; ++j) {
+            for (int b = 0; b < batch; ++b, ++r) launch_hem_round(r, n, B.rp, B.ci, B.v, w, s);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(&W.hc[j & 1], w.cnt + hem_next_count_slot(r), sizeof(int),
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(W.ev[j & 1], s));
+            if (j >= 1) {
+                HIPCHK(hipEventSynchronize(W.ev[(j - 1) & 1]));
+                if (W.hc[(j - 1) & 1] == 0) break;
+            }
+            if (r > n + 4 * batch) raise(AMG_EHIP, "matching did not terminate (internal error)");
         }
-        if (r > n + 4 * batch) raise(AMG_EHIP, "matching did not terminate (internal error)");
     }
-    HIPCHK(hipStreamSynchronize(s));
+    Pass P;
+    P.mate = w.mate;
+    P.agg = W.agg[t];
+    P.lead = W.lead[t];
+    // coarse ids: rank of each aggregate's smaller vertex
+    launch_leader_flags(n, w.mate, W.flag, s);
+    launch_scan(W.flag, n, W.ids, W.stmp, s);
+    launch_assign_ids(n, w.mate, W.ids, P.agg, P.lead, s);
+    HIPCHK(hipGetLastError());
     int tail[8];
     HIPCHK(hipMemcpyAsync(tail, w.cnt, sizeof(tail), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    Pass P;
+    HIPCHK(hipMemcpyAsync(&P.nc, W.ids + n, sizeof(int), hipMemcpyDeviceToHost, s));
+    check_err_word(err, s, "matching");  // synchronises the stream
+    if (tail[5] != 0) raise(AMG_EINVAL, "matching: sparsity pattern is not structurally symmetric");
+    if (tail[7] != 0) raise(AMG_EHIP, "matching did not terminate (internal error)");
     P.rounds = tail[6];
-    P.mate = w.mate;
-    // coarse ids: rank of each aggregate's smaller vertex
-    int* flag = tmp.get<int>(n);
-    int* ids = tmp.get<int>((size_t)n + 1);
-    int* stmp = tmp.get<int>(scan_tmp_ints(n));
-    launch_leader_flags(n, w.mate, flag, s);
-    launch_scan(flag, n, ids, stmp, s);
-    P.nc = read_int(ids + n, s);
-    P.agg = tmp.get<int>(n);
-    P.lead = tmp.get<int>(P.nc);
-    launch_assign_ids(n, w.mate, ids, P.agg, P.lead, s);
-    HIPCHK(hipGetLastError());
     return P;
 }
 
 // Galerkin product of one pass; output buffers from `out`.
-Csr galerkin(const Csr& B, const Pass& P, DevPool& tmp, DevPool& out, hipStream_t s) {
+Csr galerkin(const Csr& B, const Pass& P, SetupWork& W, DevPool& out, hipStream_t s) {
     Csr C;
     C.n = P.nc;
-    int* rowcnt = tmp.get<int>(P.nc);
-    int* ovf = tmp.get<int>(P.nc);
-    int* novf = tmp.get<int>(1);
-    int* stmp = tmp.get<int>(scan_tmp_ints(P.nc));
-    HIPCHK(hipMemsetAsync(novf, 0, sizeof(int), s));
-    launch_rap_count(P.nc, P.lead, P.mate, B.rp, B.ci, P.agg, rowcnt, ovf, novf, s);
-    launch_rap_count_slow(P.nc, ovf, novf, P.lead, P.mate, B.rp, B.ci, P.agg, rowcnt, s);
+    HIPCHK(hipMemsetAsync(W.novf, 0, sizeof(int), s));
+    launch_rap_count(P.nc, P.lead, P.mate, B.rp, B.ci, P.agg, W.rowcnt, W.ovf, W.novf, s);
+    launch_rap_count_slow(P.nc, W.ovf, W.novf, P.lead, P.mate, B.rp, B.ci, P.agg, W.rowcnt, s);
     C.rp = out.get<int>((size_t)P.nc + 1);
-    launch_scan(rowcnt, P.nc, C.rp, stmp, s);
+    launch_scan(W.rowcnt, P.nc, C.rp, W.stmp, s);
     C.nnz = read_int(C.rp + P.nc, s);
     C.ci = out.get<int>((size_t)C.nnz);
     C.v = out.get<double>((size_t)C.nnz);
     launch_rap_fill(P.nc, P.lead, P.mate, B.rp, B.ci, B.v, P.agg, C.rp, C.ci, C.v, s);
-    launch_rap_fill_slow(P.nc, ovf, novf, P.lead, P.mate, B.rp, B.ci, B.v, P.agg, C.rp, C.ci, C.v, s);
+    launch_rap_fill_slow(P.nc, W.ovf, W.novf, P.lead, P.mate, B.rp, B.ci, B.v, P.agg, C.rp, C.ci, C.v, s);
     HIPCHK(hipGetLastError());
     return C;
 }
@@ -356,9 +377,16 @@ void run_vcycle(amg_hier* h, const double* r, double* z, hipStream_t s) {
         const LevelView V = Lk.view();
         const int nc = h->lev[k + 1].n;
         if (fused) {
-            if (k == 0) timed_begin(h, 1, s);
-            launch_resid_restrict(V, nc, f[k], w, const_cast<double*>(f[k + 1]), s);
-            if (k == 0) timed_end(h, 1, s);
+            if (Lk.n >= h->stream_min) {
+                if (k == 0) timed_begin(h, 1, s);
+                launch_stream_resid(V, f[k], w, Lk.t, s);
+                if (k == 0) timed_end(h, 1, s);
+                launch_restrict(nc, Lk.mem, Lk.t, const_cast<double*>(f[k + 1]), s);
+            } else {
+                if (k == 0) timed_begin(h, 1, s);
+                launch_resid_restrict(V, nc, f[k], w, const_cast<double*>(f[k + 1]), s);
+                if (k == 0) timed_end(h, 1, s);
+            }
             continue;
         }
         const double* xs = nullptr;
@@ -383,7 +411,8 @@ void run_vcycle(amg_hier* h, const double* r, double* z, hipStream_t s) {
         const LevelView V = Lk.view();
         if (fused) {
             if (k == 0) timed_begin(h, 0, s);
-            launch_prolong_post(V, f[k], x[k + 1], w, x[k], s);
+            if (Lk.n >= h->stream_min) launch_stream_post(V, f[k], x[k + 1], w, x[k], s);
+            else launch_prolong_post(V, f[k], x[k + 1], w, x[k], s);
             if (k == 0) timed_end(h, 0, s);
             continue;
         }
@@ -574,6 +603,14 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     check_err_word(h->err, s, "amg_setup");
     h->lev.push_back(L0);
 
+    DevPool wpool;
+    wpool.s = s;
+    struct WpoolGuard {
+        DevPool& t;
+        ~WpoolGuard() { t.release(); }
+    } wg{wpool};
+    SetupWork SW;
+    if (A.n > p.max_coarse_rows && p.max_levels > 1) SW.init(A.n, A.nnz, wpool, h->err);
     for (int k = 0;; ++k) {
         Level& F = h->lev[k];
         if (F.n <= p.max_coarse_rows) break;
@@ -589,17 +626,17 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
             ~TmpGuard() { t.release(); }
         } tg{tmp};
         Csr B{F.n, F.nnz, const_cast<int*>(F.rp), const_cast<int*>(F.ci), const_cast<double*>(F.v)};
-        Pass p1 = hem_pass(B, tmp, s, h->err);
+        Pass p1 = hem_pass(B, SW, 0, s, h->err);
         h->rounds.push_back(p1.rounds);
         DevPool& out1 = (p.passes_per_level == 1) ? P : tmp;
-        Csr C1 = galerkin(B, p1, tmp, out1, s);
+        Csr C1 = galerkin(B, p1, SW, out1, s);
         Csr Cf = C1;
         int* agg = nullptr;
         int4* mem = nullptr;
         if (p.passes_per_level == 2) {
-            Pass p2 = hem_pass(C1, tmp, s, h->err);
+            Pass p2 = hem_pass(C1, SW, 1, s, h->err);
             h->rounds.push_back(p2.rounds);
-            Cf = galerkin(C1, p2, tmp, P, s);
+            Cf = galerkin(C1, p2, SW, P, s);
             agg = P.get<int>(F.n);
             launch_compose(F.n, p1.agg, p2.agg, agg, s);
             mem = P.get<int4>(Cf.n);
@@ -656,18 +693,17 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     }
     // per-level work vectors
     const bool fused = p.pre == 1 && p.post == 1;
+    if (const char* e = getenv("HEMAMG_STREAM_MIN")) h->stream_min = atoi(e);  // tuning sweeps
     for (size_t k = 0; k < h->lev.size(); ++k) {
         Level& L = h->lev[k];
         if (k > 0) {
             L.f = P.get<double>(L.n);
             L.x = P.get<double>(L.n);
         }
-        if (!fused) L.t = P.get<double>(L.n);
+        if (!fused || L.n >= h->stream_min) L.t = P.get<double>(L.n);
     }
     h->S = P.get<double>(S_COUNT);
-    h->part = P.get<double>(4 * (size_t)kRedBlocks);
-    h->ticket = P.get<unsigned>(1);
-    HIPCHK(hipMemsetAsync(h->ticket, 0, sizeof(unsigned), s));
+    h->part = P.get<double>(2 * (size_t)kRedBlocks);
     HIPCHK(hipMemsetAsync(h->S, 0, S_COUNT * sizeof(double), s));
     HIPCHK(hipHostMalloc((void**)&h->S_host, S_COUNT * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipStreamSynchronize(s));

@@ -36,25 +36,19 @@ __device__ __forceinline__ float group_sum(float s) {
     return s;
 }
 
-__device__ __forceinline__ double load_coherent(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Deterministic block + grid reduction of NV sums.  Every block writes its NV
-// partial sums; the last block to arrive (ticket) adds the partials in a fixed
-// pattern and stores the totals to out[slot[k]], then re-arms the ticket.  The
-// result depends only on the grid shape, never on scheduling.
+// Deterministic block reduction of NV sums: block b writes its totals to
+// part[k * gridDim.x + b].  A separate single-block kernel adds the partials
+// in a fixed order (same-address device-scope atomics serialise across the
+// XCDs, so no "last block" ticket is used).
 template <int NV, int BS>
-__device__ __forceinline__ void reduce_store(double (&v)[NV], double* part, unsigned* ticket, double* out,
-                                             const int (&slot)[NV]) {
+__device__ __forceinline__ void block_partials(double (&v)[NV], double* part) {
     static_assert(BS % kWave == 0, "block size must be whole waves");
     constexpr int NW = BS / kWave;
     __shared__ double sh[NV][NW];
-    __shared__ int is_last;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        double s = group_sum<kWave>(v[k]);
+        const double s = group_sum<kWave>(v[k]);
         if (lane == 0) sh[k][wid] = s;
     }
     __syncthreads();
@@ -65,33 +59,6 @@ __device__ __forceinline__ void reduce_store(double (&v)[NV], double* part, unsi
             for (int w = 1; w < NW; ++w) s += sh[k][w];
             part[k * gridDim.x + blockIdx.x] = s;
         }
-        __threadfence();
-        unsigned t = atomicAdd(ticket, 1u);
-        is_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    double acc[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += BS) s += load_coherent(&part[k * gridDim.x + b]);
-        acc[k] = group_sum<kWave>(s);
-    }
-    __syncthreads();
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) sh[k][wid] = acc[k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = sh[k][0];
-            for (int w = 1; w < NW; ++w) s += sh[k][w];
-            out[slot[k]] = s;
-        }
-        *ticket = 0u;
     }
 }
 

@@ -26,20 +26,35 @@ void launch_validate(int n, int64_t nnz, const int* rp, const int* ci, const dou
                      hipStream_t s);
 void launch_dinv(int n, const int* rp, const int* ci, const double* v, double* dinv, int* err, hipStream_t s);
 
+// Per-vertex adjacency record of a matching pass (64 bytes): up to kRecSide
+// higher neighbours j (a_uj non-zero) by |a_uj| descending, column ascending
+// on ties, and up to kRecSide lower edge-neighbours x (row x stores a
+// non-zero a_xu) ascending.  Vertices with more use the CSR rows instead.
+constexpr int kRecSide = 7;
+constexpr int kRecOverflow = 1 << 16;
+struct alignas(64) HemRec {
+    int hdr;  // #higher | #lower << 8 | kRecOverflow
+    int h[kRecSide];
+    int l[kRecSide];
+    int pad;
+};
+
 // Matching pass state (Algorithm 2 as rounds of locally dominant edges).
 struct HemWork {
     uint8_t* lowok;   // [nnz] entry (v,u), u < v, is an edge (row u stores a non-zero a_uv)
+    HemRec* rec;      // [n] adjacency records
     int* lcnt;        // [n] undecided lower neighbours
     int* dec;         // [n] round in which the vertex was decided
     int* mate;        // [n] partner or -1
     int* wl[2];       // [n] ready worklists (ping-pong)
-    int* newly;       // [n] vertices decided this round
-    int* cnt;         // [8] ring of worklist / decided counters, diff accumulator
+    int* cnt;         // [8] worklist size ring, symmetry check, round count, guard
     int* err;
 };
 // w.cnt must be zeroed before the call.
 void launch_hem_init(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
 void launch_hem_round(int round, int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
+// All rounds in one single-workgroup launch (small n).
+void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
 int hem_next_count_slot(int round);  // counter slot that holds |worklist| before `round`
 
 // Exclusive prefix sum: out[i] = sum in[0..i), out[n] = total.  tmp: scan_tmp_ints(n).
@@ -83,12 +98,17 @@ struct LevelView {
 };
 
 struct Reducer {
-    double* part;     // [4 * kRedBlocks]
-    unsigned* ticket;
+    double* part;     // [2 * kRedBlocks] per-block partial sums
     double* S;        // scalar slots
 };
 
 void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t s);
+// Large levels (CSR-stream): r = f - w A D^{-1} f, then f_c = P^T r, and the
+// prolongation + postsmoothing z = x + w D^{-1}(f - A x), x = w D^{-1} f + P e.
+void launch_stream_resid(const LevelView& L, const double* f, double w, double* r, hipStream_t s);
+void launch_restrict(int nc, const int4* mem, const double* r, double* fc, hipStream_t s);
+void launch_stream_post(const LevelView& L, const double* f, const double* e, double w, double* z, hipStream_t s);
+// Small levels (lane groups per row):
 // fc = P^T (f - A (w D^{-1} f)) : zero-guess presmoothing, residual, restriction.
 void launch_resid_restrict(const LevelView& L, int nc, const double* f, double w, double* fc, hipStream_t s);
 // z = x + w D^{-1} (f - A x) with x = w D^{-1} f + P e : prolongation + postsmoothing.
@@ -123,9 +143,7 @@ void launch_bicg_dir(int n, const double* r, const double* p, const double* v, d
 void launch_scale_zero(int n, double* x, hipStream_t s);
 // err |= ERR_NONFINITE if any entry of a or b is NaN or Inf.
 void launch_check_finite(int n, const double* a, const double* b, int* err, hipStream_t s);
-// Round counter of the matching: cnt[6] = 1 + last round that had work.
 
-constexpr int kRedBlocks = 1024;  // max blocks of a reduction kernel
-constexpr int kRedBS = 256;
+constexpr int kRedBlocks = 65536;  // max blocks (partials) of a reduction kernel
 
 }  // namespace amg

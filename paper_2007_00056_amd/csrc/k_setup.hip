@@ -104,18 +104,28 @@ __device__ __forceinline__ int find_col(const int* __restrict__ ci, int lo, int 
     return -1;
 }
 
-// counters: cnt[0..2] worklist sizes (ring of 3), cnt[3..4] decided-list sizes
-// (ring of 2), cnt[5] sum over rows of (#upper - #lower) entries, cnt[6] the
-// number of rounds that had work.
+// counters: cnt[0..2] worklist sizes (ring of 3), cnt[5] sum over rows of
+// (#upper - #lower) entries, cnt[6] the number of rounds that had work,
+// cnt[7] set when the single-workgroup pass hit its round limit.
 __global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                  const double* __restrict__ v, uint8_t* __restrict__ lowok,
-                                                 int* __restrict__ lcnt, int* __restrict__ dec,
-                                                 int* __restrict__ mate, int* __restrict__ wl0, int* cnt, int* err) {
+                                                 HemRec* __restrict__ rec, int* __restrict__ lcnt,
+                                                 int* __restrict__ dec, int* __restrict__ mate,
+                                                 int* __restrict__ wl0, int* cnt, int* err) {
     const int y = blockIdx.x * BS + threadIdx.x;
     if (y >= n) return;
     dec[y] = kUndecided;
     mate[y] = -1;
-    int c = 0, nlow = 0, nup = 0, bad = 0;
+    int c = 0, nlow = 0, nup = 0, bad = 0, nh = 0, nl = 0;
+    bool ovf = false;
+    int hj[kRecSide], lx[kRecSide];
+    double hw[kRecSide];
+#pragma unroll
+    for (int t = 0; t < kRecSide; ++t) {
+        hj[t] = -1;
+        lx[t] = -1;
+        hw[t] = 0.0;
+    }
     for (int k = rp[y]; k < rp[y + 1]; ++k) {
         const int u = ci[k];
         uint8_t ok = 0;
@@ -124,109 +134,338 @@ __global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ 
             const int pos = find_col(ci, rp[u], rp[u + 1], y);
             if (pos < 0) bad = 1;
             else if (v[pos] != 0.0) ok = 1;
+            if (ok) {  // lower edge-neighbour, columns arrive ascending
+                if (nl < kRecSide) {
+#pragma unroll
+                    for (int t = 0; t < kRecSide; ++t)
+                        if (t == nl) lx[t] = u;
+                    ++nl;
+                } else {
+                    ovf = true;
+                }
+            }
         } else if (u > y) {
             ++nup;
+            const double a = v[k];
+            if (a != 0.0) {  // higher neighbour: keep sorted by |a| descending, column ascending
+                if (nh < kRecSide) {
+                    const double w = fabs(a);
+                    int pos = 0;
+#pragma unroll
+                    for (int t = 0; t < kRecSide; ++t)
+                        if (t < nh && hw[t] >= w) pos = t + 1;
+#pragma unroll
+                    for (int t = kRecSide - 1; t > 0; --t)
+                        if (t > pos && t <= nh) {
+                            hw[t] = hw[t - 1];
+                            hj[t] = hj[t - 1];
+                        }
+#pragma unroll
+                    for (int t = 0; t < kRecSide; ++t)
+                        if (t == pos) {
+                            hw[t] = w;
+                            hj[t] = u;
+                        }
+                    ++nh;
+                } else {
+                    ovf = true;
+                }
+            }
         }
         lowok[k] = ok;
         c += ok;
     }
+    HemRec R;
+    R.hdr = nh | (nl << 8) | (ovf ? kRecOverflow : 0);
+#pragma unroll
+    for (int t = 0; t < kRecSide; ++t) {
+        R.h[t] = hj[t];
+        R.l[t] = lx[t];
+    }
+    R.pad = 0;
+    rec[y] = R;
     lcnt[y] = c;
     if (bad) atomicOr(err, ERR_NONSYM);
     if (nup != nlow) atomicAdd(&cnt[5], nup - nlow);
     if (c == 0) wl0[atomicAdd(&cnt[0], 1)] = y;
 }
 
-__global__ __launch_bounds__(BS) void k_hem_decide(int r, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                   const double* __restrict__ v, const uint8_t* __restrict__ lowok,
-                                                   int* dec, int* __restrict__ mate, const int* __restrict__ win,
-                                                   int* __restrict__ wout, int* __restrict__ newly, int* cnt,
-                                                   int slot_in, int slot_out, int slot_new, int zero_w, int zero_n) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        cnt[zero_w] = 0;
-        cnt[zero_n] = 0;
+namespace {
+struct HemState {
+    const int* __restrict__ rp;
+    const int* __restrict__ ci;
+    const double* __restrict__ v;
+    const uint8_t* __restrict__ lowok;
+    const HemRec* __restrict__ rec;
+    int* dec;
+    int* mate;
+    int* lcnt;
+};
+
+// Appends to the next worklist through a block-local LDS list; entries that
+// do not fit go straight to global memory.
+struct Appender {
+    int* s_list;
+    int* s_cnt;
+    int cap;
+    int* gout;
+    int* gcnt;
+    __device__ __forceinline__ void push(int x) const {
+        const int p = atomicAdd(s_cnt, 1);
+        if (p < cap) s_list[p] = x;
+        else gout[atomicAdd(gcnt, 1)] = x;
     }
-    const int m = cnt[slot_in];
-    if (m > 0 && blockIdx.x == 0 && threadIdx.x == 0) cnt[6] = r + 1;  // rounds with work
-    for (int idx = blockIdx.x * BS + threadIdx.x; idx < m; idx += gridDim.x * BS) {
-        const int u = win[idx];
-        int best = -1;
-        double k = -1.0;
-        for (int e = rp[u]; e < rp[u + 1]; ++e) {
-            const int j = ci[e];
-            if (j <= u) continue;
-            const double a = v[e];
-            if (a != 0.0 && dec[j] >= r) {
-                const double w = fabs(a);
-                if (w > k) {
-                    k = w;
-                    best = j;
-                }
+};
+
+constexpr int HEM_WIN = 8;  // row entries whose loads are issued together
+
+template <int SCOPE>
+__device__ __forceinline__ int dec_counter(int* p) {
+    return __hip_atomic_fetch_add(p, -1, __ATOMIC_RELAXED, SCOPE);
+}
+
+// x has just been decided: its higher neighbours lose one undecided lower
+// neighbour; those that reach zero are ready for the next round.  The
+// counter updates of a window are issued before any result is used.
+template <int SCOPE>
+__device__ __forceinline__ void hem_release(const HemState& S, int x, const Appender& A) {
+    const int e0 = S.rp[x], e1 = S.rp[x + 1];
+    for (int b = e0; b < e1; b += HEM_WIN) {
+        int ys[HEM_WIN], old[HEM_WIN];
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t) {
+            const int e = b + t;
+            ys[t] = -1;
+            if (e < e1) {
+                const int y = S.ci[e];
+                if (y > x && S.v[e] != 0.0) ys[t] = y;
             }
         }
-        if (best < 0) {  // no undecided neighbour: unaggregated singleton
-            dec[u] = r;
-            mate[u] = -1;
-            newly[atomicAdd(&cnt[slot_new], 1)] = u;
-            continue;
-        }
-        // best points back to its smallest undecided lower neighbour
-        int back = -1;
-        for (int e = rp[best]; e < rp[best + 1]; ++e) {
-            const int x = ci[e];
-            if (x >= best) break;
-            if (lowok[e] && dec[x] >= r) {
-                back = x;
-                break;
-            }
-        }
-        if (back == u) {
-            dec[u] = r;
-            dec[best] = r;
-            mate[u] = best;
-            mate[best] = u;
-            const int pos = atomicAdd(&cnt[slot_new], 2);
-            newly[pos] = u;
-            newly[pos + 1] = best;
-        } else {
-            wout[atomicAdd(&cnt[slot_out], 1)] = u;  // still ready, retry next round
-        }
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t) old[t] = ys[t] >= 0 ? dec_counter<SCOPE>(&S.lcnt[ys[t]]) : 0;
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t)
+            if (ys[t] >= 0 && old[t] == 1) A.push(ys[t]);
     }
 }
 
-__global__ __launch_bounds__(BS) void k_hem_propagate(int r, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                      const double* __restrict__ v, const int* __restrict__ dec,
-                                                      int* __restrict__ lcnt, const int* __restrict__ newly,
-                                                      int* __restrict__ wout, int* cnt, int slot_new, int slot_out) {
-    const int m = cnt[slot_new];
-    for (int idx = blockIdx.x * BS + threadIdx.x; idx < m; idx += gridDim.x * BS) {
-        const int x = newly[idx];
-        for (int e = rp[x]; e < rp[x + 1]; ++e) {
-            const int y = ci[e];
-            if (y > x && v[e] != 0.0) {
-                const int old = atomicSub(&lcnt[y], 1);
-                if (old == 1 && dec[y] > r) wout[atomicAdd(&cnt[slot_out], 1)] = y;
+// Heaviest undecided higher neighbour of u (lowest index on ties), or -1.
+__device__ __forceinline__ int hem_best(const HemState& S, int r, int u, int e0, int e1) {
+    int best = -1;
+    double k = -1.0;
+    for (int b = e0; b < e1; b += HEM_WIN) {
+        int js[HEM_WIN];
+        double ws[HEM_WIN];
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t) {
+            const int e = b + t;
+            js[t] = -1;
+            ws[t] = 0.0;
+            if (e < e1) {
+                const int j = S.ci[e];
+                const double a = S.v[e];
+                if (j > u && a != 0.0) {
+                    js[t] = j;
+                    ws[t] = fabs(a);
+                }
             }
         }
+        bool und[HEM_WIN];
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t) und[t] = js[t] >= 0 && S.dec[js[t]] >= r;
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t)
+            if (und[t] && ws[t] > k) {  // ascending column order: strict '>' keeps the lowest index
+                k = ws[t];
+                best = js[t];
+            }
+    }
+    return best;
+}
+
+// Smallest undecided lower neighbour of w (over edges (x, w) stored non-zero
+// in row x), or -1.
+__device__ __forceinline__ int hem_back(const HemState& S, int r, int w) {
+    const int e0 = S.rp[w], e1 = S.rp[w + 1];
+    for (int b = e0; b < e1; b += HEM_WIN) {
+        int xs[HEM_WIN];
+        bool stop = false;
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t) {
+            const int e = b + t;
+            xs[t] = -1;
+            if (e < e1) {
+                const int x = S.ci[e];
+                if (x >= w) stop = true;
+                else if (S.lowok[e]) xs[t] = x;
+            }
+        }
+        bool und[HEM_WIN];
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t) und[t] = xs[t] >= 0 && S.dec[xs[t]] >= r;
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t)
+            if (und[t]) return xs[t];  // columns ascend: the first is the smallest
+        if (stop) break;
+    }
+    return -1;
+}
+
+// Counter updates for the higher neighbours listed in a record, all issued
+// before any result is used.
+template <int SCOPE>
+__device__ __forceinline__ void rec_release(const HemState& S, const HemRec& R, int x, const Appender& A) {
+    if (R.hdr & kRecOverflow) {
+        hem_release<SCOPE>(S, x, A);
+        return;
+    }
+    const int nh = R.hdr & 255;
+    int old[kRecSide];
+#pragma unroll
+    for (int t = 0; t < kRecSide; ++t) old[t] = t < nh ? dec_counter<SCOPE>(&S.lcnt[R.h[t]]) : 0;
+#pragma unroll
+    for (int t = 0; t < kRecSide; ++t)
+        if (t < nh && old[t] == 1) A.push(R.h[t]);
+}
+
+// Round r for a ready vertex u.  A vertex counts as undecided while its stamp
+// is >= r, so every read sees the state at the start of the round.  Records
+// list u's higher neighbours in preference order (heaviest first, lowest
+// index on ties) and the target's lower edge-neighbours in ascending order, so
+// "first undecided entry" is the pointer of either side.
+template <int SCOPE>
+__device__ __forceinline__ void hem_visit(const HemState& S, int r, int u, const Appender& A) {
+    const HemRec R = S.rec[u];
+    const int du = S.dec[u];
+    if (du < r) return;  // decided earlier (as a match target): stale entry
+    int best = -1;
+    if (R.hdr & kRecOverflow) {
+        best = hem_best(S, r, u, S.rp[u], S.rp[u + 1]);
+    } else {
+        const int nh = R.hdr & 255;
+        int d[kRecSide];
+#pragma unroll
+        for (int t = 0; t < kRecSide; ++t) d[t] = t < nh ? S.dec[R.h[t]] : -1;
+#pragma unroll
+        for (int t = kRecSide - 1; t >= 0; --t)
+            if (t < nh && d[t] >= r) best = R.h[t];
+    }
+    if (best < 0) {  // no undecided neighbour: unaggregated singleton
+        S.dec[u] = r;
+        S.mate[u] = -1;
+        rec_release<SCOPE>(S, R, u, A);
+        return;
+    }
+    const HemRec B = S.rec[best];
+    int back = -1;
+    if (B.hdr & kRecOverflow) {
+        back = hem_back(S, r, best);
+    } else {
+        const int nl = (B.hdr >> 8) & 255;
+        int d[kRecSide];
+#pragma unroll
+        for (int t = 0; t < kRecSide; ++t) d[t] = t < nl ? S.dec[B.l[t]] : -1;
+#pragma unroll
+        for (int t = kRecSide - 1; t >= 0; --t)
+            if (t < nl && d[t] >= r) back = B.l[t];
+    }
+    if (back == u) {  // best points back: mutual, matched
+        S.dec[u] = r;
+        S.dec[best] = r;
+        S.mate[u] = best;
+        S.mate[best] = u;
+        rec_release<SCOPE>(S, R, u, A);
+        rec_release<SCOPE>(S, B, best, A);
+    } else {
+        A.push(u);  // still ready, retry next round
+    }
+}
+
+constexpr int HEM_BS = 512;
+constexpr int HEM_LCAP = 4096;
+constexpr int HEM_BS1 = 1024;
+constexpr int HEM_LCAP1 = 8192;
+}  // namespace
+
+// One round over the worklist; the decided vertices' neighbours that become
+// ready, and the ready vertices that failed, form the next list.
+__global__ __launch_bounds__(HEM_BS) void k_hem_round(int r, HemState S, const int* __restrict__ win,
+                                                  int* __restrict__ wout, int* cnt, int slot_in, int slot_out,
+                                                  int zero_w) {
+    __shared__ int s_list[HEM_LCAP];
+    __shared__ int s_cnt, s_base;
+    if (threadIdx.x == 0) {
+        s_cnt = 0;
+        if (blockIdx.x == 0) cnt[zero_w] = 0;
+    }
+    __syncthreads();
+    const int m = cnt[slot_in];
+    if (m > 0 && blockIdx.x == 0 && threadIdx.x == 0) cnt[6] = r + 1;  // rounds with work
+    const Appender A{s_list, &s_cnt, HEM_LCAP, wout, &cnt[slot_out]};
+    for (int idx = blockIdx.x * HEM_BS + threadIdx.x; idx < m; idx += gridDim.x * HEM_BS)
+        hem_visit<__HIP_MEMORY_SCOPE_AGENT>(S, r, win[idx], A);
+    __syncthreads();
+    const int k = min(s_cnt, HEM_LCAP);
+    if (threadIdx.x == 0 && k > 0) s_base = atomicAdd(&cnt[slot_out], k);
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += HEM_BS) wout[s_base + i] = s_list[i];
+}
+
+// Small matrices: one workgroup runs every round, separated by barriers.
+// Each round decides at least the smallest undecided vertex, so n + 1 rounds
+// always suffice; the bound only guards against invalid input.
+__global__ __launch_bounds__(HEM_BS1) void k_hem_all(int n, HemState S, int* wl0, int* wl1, int* cnt) {
+    __shared__ int s_list[HEM_LCAP1];
+    __shared__ int s_cnt, s_next, s_m;
+    if (threadIdx.x == 0) s_m = cnt[0];
+    __syncthreads();
+    int* win = wl0;
+    int* wout = wl1;
+    int r = 0;
+    for (; r <= n + 1; ++r) {
+        const int m = s_m;
+        if (m == 0) break;
+        if (threadIdx.x == 0) {
+            s_cnt = 0;
+            s_next = 0;
+        }
+        __syncthreads();
+        const Appender A{s_list, &s_cnt, HEM_LCAP1, wout, &s_next};
+        for (int idx = threadIdx.x; idx < m; idx += HEM_BS1) hem_visit<__HIP_MEMORY_SCOPE_WORKGROUP>(S, r, win[idx], A);
+        __syncthreads();
+        const int k = min(s_cnt, HEM_LCAP1);
+        const int base = s_next;
+        for (int i = threadIdx.x; i < k; i += HEM_BS1) wout[base + i] = s_list[i];
+        __syncthreads();
+        if (threadIdx.x == 0) s_m = base + k;
+        int* t = win;
+        win = wout;
+        wout = t;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cnt[6] = r;
+        if (s_m != 0) cnt[7] = 1;
     }
 }
 
 void launch_hem_init(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
-    hipLaunchKernelGGL(k_hem_init, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, w.lowok, w.lcnt, w.dec, w.mate,
-                       w.wl[0], w.cnt, w.err);
+    hipLaunchKernelGGL(k_hem_init, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, w.lowok, w.rec, w.lcnt, w.dec,
+                       w.mate, w.wl[0], w.cnt, w.err);
 }
 
 int hem_next_count_slot(int round) { return round % 3; }
 
 void launch_hem_round(int r, int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
-    const int g = blocks_for(n, BS, 512);
-    const int* win = w.wl[r & 1];
-    int* wout = w.wl[(r + 1) & 1];
-    const int slot_in = r % 3, slot_out = (r + 1) % 3, zero_w = (r + 2) % 3;
-    const int slot_new = 3 + (r & 1), zero_n = 3 + ((r + 1) & 1);
-    hipLaunchKernelGGL(k_hem_decide, dim3(g), dim3(BS), 0, s, r, rp, ci, v, w.lowok, w.dec, w.mate, win, wout,
-                       w.newly, w.cnt, slot_in, slot_out, slot_new, zero_w, zero_n);
-    hipLaunchKernelGGL(k_hem_propagate, dim3(g), dim3(BS), 0, s, r, rp, ci, v, w.dec, w.lcnt, w.newly, wout, w.cnt,
-                       slot_new, slot_out);
+    const int g = blocks_for(n, HEM_BS, 96);
+    const HemState S{rp, ci, v, w.lowok, w.rec, w.dec, w.mate, w.lcnt};
+    hipLaunchKernelGGL(k_hem_round, dim3(g), dim3(HEM_BS), 0, s, r, S, w.wl[r & 1], w.wl[(r + 1) & 1], w.cnt, r % 3,
+                       (r + 1) % 3, (r + 2) % 3);
+}
+
+void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
+    const HemState S{rp, ci, v, w.lowok, w.rec, w.dec, w.mate, w.lcnt};
+    hipLaunchKernelGGL(k_hem_all, dim3(1), dim3(HEM_BS1), 0, s, n, S, w.wl[0], w.wl[1], w.cnt);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,12 +1,17 @@
-// Solve-phase kernels: CSR SpMV, the fused V-cycle level kernels of
-// Algorithm 1 (damped Jacobi, residual, piecewise-constant restriction and
-// prolongation), the coarsest dense solve, and the vector kernels of
-// Algorithm 4 (PCG) and Algorithm 5 (BiCGStab).
+// Solve-phase kernels: CSR SpMV, the V-cycle level kernels of Algorithm 1
+// (damped Jacobi, residual, piecewise-constant restriction and prolongation),
+// the coarsest dense solve, and the vector kernels of Algorithm 4 (PCG) and
+// Algorithm 5 (BiCGStab).
 //
-// CSR rows are processed by groups of LPR consecutive lanes (LPR in 1..16):
-// each lane walks the row with stride LPR, so a group reads a contiguous row
-// segment, and a butterfly shuffle combines the lanes.  Level kernels map
-// blocks XCD-contiguously so neighbouring rows share an L2.
+// Large levels use a block-level CSR-stream schedule: a 256-thread block owns
+// 256 consecutive rows, reads their contiguous entry range with coalesced,
+// independent loads (val, col and the gathered vector), stages the products
+// in LDS, and then each thread adds its own row's products.  Small levels,
+// where launch latency dominates, use lane groups per row and the fused
+// coarse-row restriction.  Blocks are mapped XCD-contiguously so rows that
+// share vector cache lines share one XCD's L2.
+#include <cstdlib>
+
 #include "amg_device.hpp"
 #include "amg_internal.hpp"
 
@@ -20,8 +25,8 @@ inline int level_blocks(int64_t rows, int lpr) {
     return (int)(b < 1 ? 1 : b);
 }
 
-inline int red_blocks(int64_t rows, int lpr) {
-    int64_t b = (rows * lpr + BS - 1) / BS;
+inline int vec_blocks(int64_t n) {
+    int64_t b = (n + BS - 1) / BS;
     if (b < 1) b = 1;
     return (int)(b < kRedBlocks ? b : kRedBlocks);
 }
@@ -37,11 +42,14 @@ __device__ __forceinline__ double row_ax(int row, int lane, const int* __restric
 }  // namespace
 
 int pick_lanes_per_row(double avg) {
-    if (avg <= 1.5) return 1;
-    if (avg <= 3.0) return 2;
-    if (avg <= 6.0) return 4;
-    if (avg <= 12.0) return 8;
-    return 16;
+    // HEMAMG_LPR=1|2|4|8|16 fixes the schedule (tuning sweeps)
+    if (const char* e = getenv("HEMAMG_LPR")) {
+        const int v = atoi(e);
+        if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16) return v;
+    }
+    if (avg <= 3.0) return 1;
+    if (avg <= 12.0) return 2;
+    return 4;
 }
 
 #define AMG_DISPATCH_LPR(lpr, CALL) \
@@ -54,30 +62,142 @@ int pick_lanes_per_row(double avg) {
     }
 
 // ---------------------------------------------------------------------------
-// y = A x
+// CSR-stream building block.  Rows [r0, min(r0 + 256, n)); entries are
+// processed in LDS chunks so rows of any length are handled.  The sum of a
+// row's products runs in entry order.
 // ---------------------------------------------------------------------------
-template <int LPR>
-__global__ __launch_bounds__(BS) void k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                             const double* __restrict__ v, const double* __restrict__ x,
-                                             double* __restrict__ y) {
-    const int t = xcd_block(blockIdx.x, gridDim.x) * BS + threadIdx.x;
-    const int row = t / LPR, lane = t % LPR;
-    double s = row < n ? row_ax<LPR>(row, lane, rp, ci, v, x) : 0.0;
-    s = group_sum<LPR>(s);
-    if (row < n && lane == 0) y[row] = s;
+constexpr int kStreamChunk = 2048;  // doubles of LDS (16 KB)
+
+template <class Ent>
+__device__ __forceinline__ double stream_rows(int r0, int n, const int* __restrict__ rp, const Ent& ent,
+                                              double* prod) {
+    const int r1 = min(r0 + BS, n);
+    const int e0 = rp[r0], e1 = rp[r1];
+    const int row = r0 + threadIdx.x;
+    const int rb = row < r1 ? rp[row] : 0, re = row < r1 ? rp[row + 1] : 0;
+    double acc = 0.0;
+    for (int c0 = e0; c0 < e1; c0 += kStreamChunk) {
+        const int c1 = min(c0 + kStreamChunk, e1);
+#pragma unroll 4
+        for (int e = c0 + threadIdx.x; e < c1; e += BS) prod[e - c0] = ent(e);
+        __syncthreads();
+        const int lo = max(rb, c0), hi = min(re, c1);
+        for (int e = lo; e < hi; ++e) acc += prod[e - c0];
+        __syncthreads();
+    }
+    return acc;
+}
+
+struct EntAx {  // a_ij x_j
+    const double* __restrict__ v;
+    const int* __restrict__ ci;
+    const double* __restrict__ x;
+    __device__ __forceinline__ double operator()(int e) const { return v[e] * x[ci[e]]; }
+};
+
+struct EntPre {  // a_ij (D^{-1} f)_j : presmoothed zero-guess iterate without the factor w
+    const double* __restrict__ v;
+    const int* __restrict__ ci;
+    const double* __restrict__ dinv;
+    const double* __restrict__ f;
+    __device__ __forceinline__ double operator()(int e) const {
+        const int j = ci[e];
+        return v[e] * (dinv[j] * f[j]);
+    }
+};
+
+struct EntPost {  // a_ij (w D^{-1} f + P e)_j : prolongated iterate
+    const double* __restrict__ v;
+    const int* __restrict__ ci;
+    const double* __restrict__ dinv;
+    const double* __restrict__ f;
+    const int* __restrict__ agg;
+    const double* __restrict__ ec;
+    double w;
+    __device__ __forceinline__ double operator()(int e) const {
+        const int j = ci[e];
+        return v[e] * (w * (dinv[j] * f[j]) + ec[agg[j]]);
+    }
+};
+
+// y = A x
+__global__ __launch_bounds__(BS) void k_stream_spmv(int n, const int* __restrict__ rp, EntAx ent,
+                                                    double* __restrict__ y) {
+    __shared__ double prod[kStreamChunk];
+    for (int b = xcd_block(blockIdx.x, gridDim.x); b * BS < n; b += gridDim.x) {
+        const double s = stream_rows(b * BS, n, rp, ent, prod);
+        const int row = b * BS + threadIdx.x;
+        if (row < n) y[row] = s;
+    }
+}
+
+// r = f - w A D^{-1} f : residual after the zero-guess presmoothing sweep
+__global__ __launch_bounds__(BS) void k_stream_resid(int n, const int* __restrict__ rp, EntPre ent,
+                                                     const double* __restrict__ f, double w,
+                                                     double* __restrict__ r) {
+    __shared__ double prod[kStreamChunk];
+    for (int b = xcd_block(blockIdx.x, gridDim.x); b * BS < n; b += gridDim.x) {
+        const double s = stream_rows(b * BS, n, rp, ent, prod);
+        const int row = b * BS + threadIdx.x;
+        if (row < n) r[row] = f[row] - w * s;
+    }
+}
+
+// z = x + w D^{-1} (f - A x), x = w D^{-1} f + P e : prolongation + postsmoothing
+__global__ __launch_bounds__(BS) void k_stream_post(int n, const int* __restrict__ rp, EntPost ent,
+                                                    double* __restrict__ z) {
+    __shared__ double prod[kStreamChunk];
+    for (int b = xcd_block(blockIdx.x, gridDim.x); b * BS < n; b += gridDim.x) {
+        const double s = stream_rows(b * BS, n, rp, ent, prod);
+        const int row = b * BS + threadIdx.x;
+        if (row < n) {
+            const double di = ent.dinv[row], fi = ent.f[row];
+            const double xi = ent.w * (di * fi) + ent.ec[ent.agg[row]];
+            z[row] = xi + ent.w * (di * (fi - s));
+        }
+    }
+}
+
+// f_c = P^T r, members of each coarse row added in ascending order
+__global__ __launch_bounds__(BS) void k_restrict(int nc, const int4* __restrict__ mem, const double* __restrict__ r,
+                                                 double* __restrict__ fc) {
+    const int J = blockIdx.x * BS + threadIdx.x;
+    if (J >= nc) return;
+    const int4 m = mem[J];
+    double s = r[m.x];
+    if (m.y >= 0) s += r[m.y];
+    if (m.z >= 0) s += r[m.z];
+    if (m.w >= 0) s += r[m.w];
+    fc[J] = s;
+}
+
+inline int stream_blocks(int n) {
+    const int b = (n + BS - 1) / BS;
+    return b < kRedBlocks ? (b < 1 ? 1 : b) : kRedBlocks;
 }
 
 void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t s) {
-#define CALL(W) hipLaunchKernelGGL(k_spmv<W>, dim3(level_blocks(L.n, W)), dim3(BS), 0, s, L.n, L.rp, L.ci, L.v, x, y)
-    AMG_DISPATCH_LPR(L.lpr, CALL)
-#undef CALL
+    hipLaunchKernelGGL(k_stream_spmv, dim3(stream_blocks(L.n)), dim3(BS), 0, s, L.n, L.rp, EntAx{L.v, L.ci, x}, y);
+}
+
+void launch_stream_resid(const LevelView& L, const double* f, double w, double* r, hipStream_t s) {
+    hipLaunchKernelGGL(k_stream_resid, dim3(stream_blocks(L.n)), dim3(BS), 0, s, L.n, L.rp,
+                       EntPre{L.v, L.ci, L.dinv, f}, f, w, r);
+}
+
+void launch_restrict(int nc, const int4* mem, const double* r, double* fc, hipStream_t s) {
+    hipLaunchKernelGGL(k_restrict, dim3(level_blocks(nc, 1)), dim3(BS), 0, s, nc, mem, r, fc);
+}
+
+void launch_stream_post(const LevelView& L, const double* f, const double* e, double w, double* z, hipStream_t s) {
+    hipLaunchKernelGGL(k_stream_post, dim3(stream_blocks(L.n)), dim3(BS), 0, s, L.n, L.rp,
+                       EntPost{L.v, L.ci, L.dinv, f, L.agg, e, w}, z);
 }
 
 // ---------------------------------------------------------------------------
-// Down-sweep of Algorithm 1 on one level, fused: presmoothing from the zero
-// guess x = w D^{-1} f, residual r = f - A x and restriction f_c = P^T r.
-// A group of 4*LPR lanes owns one coarse row; sub-group q handles member q
-// (members ascending) and the member residuals are added in that order.
+// Small levels: down-sweep fused in one kernel.  A group of 4*LPR lanes owns
+// one coarse row; sub-group q handles member q (members ascending) and the
+// member residuals are added in that order.
 // ---------------------------------------------------------------------------
 template <int LPR>
 __global__ __launch_bounds__(BS) void k_resid_restrict(int nc, const int4* __restrict__ mem,
@@ -87,7 +207,7 @@ __global__ __launch_bounds__(BS) void k_resid_restrict(int nc, const int4* __res
                                                        const double* __restrict__ f, double w,
                                                        double* __restrict__ fc) {
     constexpr int G = 4 * LPR;
-    const int t = xcd_block(blockIdx.x, gridDim.x) * BS + threadIdx.x;
+    const int t = blockIdx.x * BS + threadIdx.x;
     const int J = t / G, sub = (t % G) / LPR, lane = t % LPR;
     int i = -1;
     if (J < nc) {
@@ -120,11 +240,6 @@ void launch_resid_restrict(const LevelView& L, int nc, const double* f, double w
 #undef CALL
 }
 
-// ---------------------------------------------------------------------------
-// Up-sweep of Algorithm 1 on one level, fused: prolongation x = x_pre + P e
-// (x_pre = w D^{-1} f recomputed on the fly) and one damped-Jacobi
-// postsmoothing sweep z = x + w D^{-1} (f - A x).
-// ---------------------------------------------------------------------------
 template <int LPR>
 __global__ __launch_bounds__(BS) void k_prolong_post(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                      const double* __restrict__ v,
@@ -132,7 +247,7 @@ __global__ __launch_bounds__(BS) void k_prolong_post(int n, const int* __restric
                                                      const double* __restrict__ f, const int* __restrict__ agg,
                                                      const double* __restrict__ e, double w,
                                                      double* __restrict__ z) {
-    const int t = xcd_block(blockIdx.x, gridDim.x) * BS + threadIdx.x;
+    const int t = blockIdx.x * BS + threadIdx.x;
     const int row = t / LPR, lane = t % LPR;
     double s = 0.0;
     if (row < n) {
@@ -198,7 +313,7 @@ __global__ __launch_bounds__(BS) void k_resid_restrict_x(int nc, const int4* __r
                                                          const double* __restrict__ v, const double* __restrict__ f,
                                                          const double* __restrict__ x, double* __restrict__ fc) {
     constexpr int G = 4 * LPR;
-    const int t = xcd_block(blockIdx.x, gridDim.x) * BS + threadIdx.x;
+    const int t = blockIdx.x * BS + threadIdx.x;
     const int J = t / G, sub = (t % G) / LPR, lane = t % LPR;
     int i = -1;
     if (J < nc) {
@@ -236,138 +351,159 @@ void launch_prolong_add(int n, const int* agg, const double* e, double* x, hipSt
     hipLaunchKernelGGL(k_prolong_add, dim3(level_blocks(n, 1)), dim3(BS), 0, s, n, agg, e, x);
 }
 
-// Coarsest level: x = A_L^{-1} f with the inverse stored column-major.
-__global__ __launch_bounds__(64) void k_dense_apply(int n, const double* __restrict__ ainv_t,
+// Coarsest level: x = A_L^{-1} f with the inverse stored column-major.  One
+// block stages f in LDS; each thread forms one row with independent loads.
+__global__ __launch_bounds__(BS) void k_dense_apply(int n, const double* __restrict__ ainv_t,
                                                    const double* __restrict__ f, double* __restrict__ x) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int j = 0; j < n; ++j) s += ainv_t[(size_t)j * n + i] * f[j];
-    x[i] = s;
+    __shared__ double fs[1024];
+    for (int j = threadIdx.x; j < n; j += BS) fs[j] = f[j];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += BS) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int j = 0;
+        for (; j + 4 <= n; j += 4) {
+            s0 += ainv_t[(size_t)j * n + i] * fs[j];
+            s1 += ainv_t[(size_t)(j + 1) * n + i] * fs[j + 1];
+            s2 += ainv_t[(size_t)(j + 2) * n + i] * fs[j + 2];
+            s3 += ainv_t[(size_t)(j + 3) * n + i] * fs[j + 3];
+        }
+        for (; j < n; ++j) s0 += ainv_t[(size_t)j * n + i] * fs[j];
+        x[i] = (s0 + s1) + (s2 + s3);
+    }
 }
 
 void launch_dense_apply(int n, const double* ainv_t, const double* f, double* x, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_apply, dim3((n + 63) / 64), dim3(64), 0, s, n, ainv_t, f, x);
+    hipLaunchKernelGGL(k_dense_apply, dim3(1), dim3(BS), 0, s, n, ainv_t, f, x);
 }
 
 // ---------------------------------------------------------------------------
-// Krylov kernels.  Reductions go through reduce_store (deterministic); the
-// scalars of the recurrences are read from device slots, so no host round
-// trip sits between the kernels of one iteration.  Update kernels skip the
-// update when the denominator they depend on is zero or not finite; the host
-// reports the breakdown after reading the slots.
+// Krylov kernels.  A reduction kernel writes one partial per block; k_finish
+// (one block) adds them in a fixed order into the scalar slots, so results are
+// reproducible run to run.  The scalars of the recurrences stay in device
+// slots, so no host round trip sits between the kernels of one iteration.
+// Update kernels skip the update when a denominator they depend on is zero or
+// not finite; the host reports the breakdown after reading the slots.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool usable(double d) { return isfinite(d) && d != 0.0; }
 
-template <int LPR>
-__global__ __launch_bounds__(BS) void k_residual(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                 const double* __restrict__ v, const double* __restrict__ b,
-                                                 const double* __restrict__ x, double* __restrict__ r, double* part,
-                                                 unsigned* ticket, double* S, int slot) {
+constexpr int FIN_BS = 1024;
+
+__global__ __launch_bounds__(FIN_BS) void k_finish(int nparts, int nv, const double* __restrict__ part,
+                                                   double* __restrict__ S, int slot0, int slot1) {
+    __shared__ double sh[2][FIN_BS / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (int k = 0; k < nv; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nparts; b += FIN_BS) s += part[k * nparts + b];
+        s = group_sum<kWave>(s);
+        if (lane == 0) sh[k][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < nv; ++k) {
+            double s = sh[k][0];
+            for (int w = 1; w < FIN_BS / kWave; ++w) s += sh[k][w];
+            S[k == 0 ? slot0 : slot1] = s;
+        }
+    }
+}
+
+inline void finish(int nparts, int nv, const Reducer& R, int slot0, int slot1, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(FIN_BS), 0, s, nparts, nv, R.part, R.S, slot0, slot1);
+}
+
+// r = b - A x, partial (r, r)
+__global__ __launch_bounds__(BS) void k_stream_residual(int n, const int* __restrict__ rp, EntAx ent,
+                                                        const double* __restrict__ b, double* __restrict__ r,
+                                                        double* part) {
+    __shared__ double prod[kStreamChunk];
     double acc[1] = {0.0};
-    const int stride = gridDim.x * BS / LPR;
-    const int t = blockIdx.x * BS + threadIdx.x;
-    const int lane = t % LPR;
-    for (int row = t / LPR; row < n; row += stride) {
-        const double s = group_sum<LPR>(row_ax<LPR>(row, lane, rp, ci, v, x));
-        if (lane == 0) {
+    for (int blk = xcd_block(blockIdx.x, gridDim.x); blk * BS < n; blk += gridDim.x) {
+        const double s = stream_rows(blk * BS, n, rp, ent, prod);
+        const int row = blk * BS + threadIdx.x;
+        if (row < n) {
             const double ri = b[row] - s;
             r[row] = ri;
             acc[0] += ri * ri;
         }
     }
-    const int sl[1] = {slot};
-    reduce_store<1, BS>(acc, part, ticket, S, sl);
+    block_partials<1, BS>(acc, part);
 }
 
 void launch_residual(const LevelView& A, const double* b, const double* x, double* r, const Reducer& R, int slot,
                      hipStream_t s) {
-#define CALL(W)                                                                                             \
-    hipLaunchKernelGGL(k_residual<W>, dim3(red_blocks(A.n, W)), dim3(BS), 0, s, A.n, A.rp, A.ci, A.v, b, x, r, \
-                       R.part, R.ticket, R.S, slot)
-    AMG_DISPATCH_LPR(A.lpr, CALL)
-#undef CALL
+    const int g = stream_blocks(A.n);
+    hipLaunchKernelGGL(k_stream_residual, dim3(g), dim3(BS), 0, s, A.n, A.rp, EntAx{A.v, A.ci, x}, b, r, R.part);
+    finish(g, 1, R, slot, slot, s);
 }
 
-__global__ __launch_bounds__(BS) void k_dot(int n, const double* __restrict__ a, const double* __restrict__ b,
-                                            double* part, unsigned* ticket, double* S, int slot) {
+// q = A p, partial (d, q)
+__global__ __launch_bounds__(BS) void k_stream_spmv_dot(int n, const int* __restrict__ rp, EntAx ent,
+                                                        double* __restrict__ q, const double* __restrict__ d,
+                                                        double* part) {
+    __shared__ double prod[kStreamChunk];
     double acc[1] = {0.0};
-    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) acc[0] += a[i] * b[i];
-    const int sl[1] = {slot};
-    reduce_store<1, BS>(acc, part, ticket, S, sl);
-}
-
-void launch_dot(int n, const double* a, const double* b, const Reducer& R, int slot, hipStream_t s) {
-    hipLaunchKernelGGL(k_dot, dim3(red_blocks(n, 1)), dim3(BS), 0, s, n, a, b, R.part, R.ticket, R.S, slot);
-}
-
-// q = A p and (d, q)
-template <int LPR>
-__global__ __launch_bounds__(BS) void k_spmv_dot(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                 const double* __restrict__ v, const double* __restrict__ p,
-                                                 double* __restrict__ q, const double* __restrict__ d, double* part,
-                                                 unsigned* ticket, double* S, int slot) {
-    double acc[1] = {0.0};
-    const int stride = gridDim.x * BS / LPR;
-    const int t = blockIdx.x * BS + threadIdx.x;
-    const int lane = t % LPR;
-    for (int row = t / LPR; row < n; row += stride) {
-        const double s = group_sum<LPR>(row_ax<LPR>(row, lane, rp, ci, v, p));
-        if (lane == 0) {
+    for (int blk = xcd_block(blockIdx.x, gridDim.x); blk * BS < n; blk += gridDim.x) {
+        const double s = stream_rows(blk * BS, n, rp, ent, prod);
+        const int row = blk * BS + threadIdx.x;
+        if (row < n) {
             q[row] = s;
             acc[0] += d[row] * s;
         }
     }
-    const int sl[1] = {slot};
-    reduce_store<1, BS>(acc, part, ticket, S, sl);
+    block_partials<1, BS>(acc, part);
 }
 
 void launch_spmv_dot(const LevelView& A, const double* p, double* q, const double* d, const Reducer& R, int slot,
                      hipStream_t s) {
-#define CALL(W)                                                                                             \
-    hipLaunchKernelGGL(k_spmv_dot<W>, dim3(red_blocks(A.n, W)), dim3(BS), 0, s, A.n, A.rp, A.ci, A.v, p, q, d, \
-                       R.part, R.ticket, R.S, slot)
-    AMG_DISPATCH_LPR(A.lpr, CALL)
-#undef CALL
+    const int g = stream_blocks(A.n);
+    hipLaunchKernelGGL(k_stream_spmv_dot, dim3(g), dim3(BS), 0, s, A.n, A.rp, EntAx{A.v, A.ci, p}, q, d, R.part);
+    finish(g, 1, R, slot, slot, s);
 }
 
-// t = A p, (t, t) and (t, sv)
-template <int LPR>
-__global__ __launch_bounds__(BS) void k_spmv_dot2(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                  const double* __restrict__ v, const double* __restrict__ p,
-                                                  double* __restrict__ tq, const double* __restrict__ sv,
-                                                  double* part, unsigned* ticket, double* S, int slot_tt,
-                                                  int slot_ts) {
+// t = A p, partials (t, t) and (t, sv)
+__global__ __launch_bounds__(BS) void k_stream_spmv_dot2(int n, const int* __restrict__ rp, EntAx ent,
+                                                         double* __restrict__ t, const double* __restrict__ sv,
+                                                         double* part) {
+    __shared__ double prod[kStreamChunk];
     double acc[2] = {0.0, 0.0};
-    const int stride = gridDim.x * BS / LPR;
-    const int t = blockIdx.x * BS + threadIdx.x;
-    const int lane = t % LPR;
-    for (int row = t / LPR; row < n; row += stride) {
-        const double s = group_sum<LPR>(row_ax<LPR>(row, lane, rp, ci, v, p));
-        if (lane == 0) {
-            tq[row] = s;
+    for (int blk = xcd_block(blockIdx.x, gridDim.x); blk * BS < n; blk += gridDim.x) {
+        const double s = stream_rows(blk * BS, n, rp, ent, prod);
+        const int row = blk * BS + threadIdx.x;
+        if (row < n) {
+            t[row] = s;
             acc[0] += s * s;
             acc[1] += s * sv[row];
         }
     }
-    const int sl[2] = {slot_tt, slot_ts};
-    reduce_store<2, BS>(acc, part, ticket, S, sl);
+    block_partials<2, BS>(acc, part);
 }
 
 void launch_spmv_dot2(const LevelView& A, const double* p, double* t, const double* sv, const Reducer& R, int slot_tt,
                       int slot_ts, hipStream_t s) {
-#define CALL(W)                                                                                               \
-    hipLaunchKernelGGL(k_spmv_dot2<W>, dim3(red_blocks(A.n, W)), dim3(BS), 0, s, A.n, A.rp, A.ci, A.v, p, t, sv, \
-                       R.part, R.ticket, R.S, slot_tt, slot_ts)
-    AMG_DISPATCH_LPR(A.lpr, CALL)
-#undef CALL
+    const int g = stream_blocks(A.n);
+    hipLaunchKernelGGL(k_stream_spmv_dot2, dim3(g), dim3(BS), 0, s, A.n, A.rp, EntAx{A.v, A.ci, p}, t, sv, R.part);
+    finish(g, 2, R, slot_tt, slot_ts, s);
 }
 
-// Algorithm 4: alpha = (r,z)/(Ap,p); x += alpha p; r -= alpha Ap; (r,r).
+__global__ __launch_bounds__(BS) void k_dot(int n, const double* __restrict__ a, const double* __restrict__ b,
+                                            double* part) {
+    double acc[1] = {0.0};
+    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) acc[0] += a[i] * b[i];
+    block_partials<1, BS>(acc, part);
+}
+
+void launch_dot(int n, const double* a, const double* b, const Reducer& R, int slot, hipStream_t s) {
+    const int g = vec_blocks(n);
+    hipLaunchKernelGGL(k_dot, dim3(g), dim3(BS), 0, s, n, a, b, R.part);
+    finish(g, 1, R, slot, slot, s);
+}
+
+// Algorithm 4: alpha = (r,z)/(Ap,p); x += alpha p; r -= alpha Ap; partial (r,r).
 __global__ __launch_bounds__(BS) void k_cg_update(int n, double* __restrict__ x, double* __restrict__ r,
                                                   const double* __restrict__ p, const double* __restrict__ q,
-                                                  double* part, unsigned* ticket, double* S, int slot_rho,
-                                                  int slot_pq, int slot_rr) {
+                                                  double* part, const double* __restrict__ S, int slot_rho,
+                                                  int slot_pq) {
     const double rho = S[slot_rho], pq = S[slot_pq];
     const bool ok = usable(pq) && isfinite(rho);
     const double alpha = ok ? rho / pq : 0.0;
@@ -381,14 +517,14 @@ __global__ __launch_bounds__(BS) void k_cg_update(int n, double* __restrict__ x,
         }
         acc[0] += ri * ri;
     }
-    const int sl[1] = {slot_rr};
-    reduce_store<1, BS>(acc, part, ticket, S, sl);
+    block_partials<1, BS>(acc, part);
 }
 
 void launch_cg_update(int n, double* x, double* r, const double* p, const double* q, const Reducer& R, int slot_rho,
                       int slot_pq, int slot_rr, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update, dim3(red_blocks(n, 1)), dim3(BS), 0, s, n, x, r, p, q, R.part, R.ticket, R.S,
-                       slot_rho, slot_pq, slot_rr);
+    const int g = vec_blocks(n);
+    hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(BS), 0, s, n, x, r, p, q, R.part, R.S, slot_rho, slot_pq);
+    finish(g, 1, R, slot_rr, slot_rr, s);
 }
 
 // p_new = z + beta p, beta = rho_new / rho
@@ -396,13 +532,12 @@ __global__ __launch_bounds__(BS) void k_cg_dir(int n, const double* __restrict__
                                                double* __restrict__ pn, const double* __restrict__ S, int slot_new,
                                                int slot_old) {
     const double beta = S[slot_new] / S[slot_old];
-    const int i = blockIdx.x * BS + threadIdx.x;
-    if (i < n) pn[i] = z[i] + beta * p[i];
+    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) pn[i] = z[i] + beta * p[i];
 }
 
 void launch_cg_dir(int n, const double* z, const double* p, double* pn, const double* S, int slot_new, int slot_old,
                    hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_dir, dim3(level_blocks(n, 1)), dim3(BS), 0, s, n, z, p, pn, S, slot_new, slot_old);
+    hipLaunchKernelGGL(k_cg_dir, dim3(vec_blocks(n)), dim3(BS), 0, s, n, z, p, pn, S, slot_new, slot_old);
 }
 
 // Algorithm 5: s = r - alpha v, alpha = rho / (rbar, v)
@@ -410,22 +545,21 @@ __global__ __launch_bounds__(BS) void k_bicg_s(int n, const double* __restrict__
                                                double* __restrict__ sv, const double* __restrict__ S, int slot_rho,
                                                int slot_rv) {
     const double alpha = S[slot_rho] / S[slot_rv];
-    const int i = blockIdx.x * BS + threadIdx.x;
-    if (i < n) sv[i] = r[i] - alpha * v[i];
+    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) sv[i] = r[i] - alpha * v[i];
 }
 
 void launch_bicg_s(int n, const double* r, const double* v, double* sv, const double* S, int slot_rho, int slot_rv,
                    hipStream_t s) {
-    hipLaunchKernelGGL(k_bicg_s, dim3(level_blocks(n, 1)), dim3(BS), 0, s, n, r, v, sv, S, slot_rho, slot_rv);
+    hipLaunchKernelGGL(k_bicg_s, dim3(vec_blocks(n)), dim3(BS), 0, s, n, r, v, sv, S, slot_rho, slot_rv);
 }
 
-// x += alpha pt + omega st; r = s - omega t; (r,r) and (r, rbar)
+// x += alpha pt + omega st; r = s - omega t; partials (r,r) and (r, rbar)
 __global__ __launch_bounds__(BS) void k_bicg_update(int n, double* __restrict__ x, double* __restrict__ r,
                                                     const double* __restrict__ pt, const double* __restrict__ st,
                                                     const double* __restrict__ sv, const double* __restrict__ t,
-                                                    const double* __restrict__ rb, double* part, unsigned* ticket,
-                                                    double* S, int slot_rho, int slot_rv, int slot_tt, int slot_ts,
-                                                    int slot_rr, int slot_rhonew) {
+                                                    const double* __restrict__ rb, double* part,
+                                                    const double* __restrict__ S, int slot_rho, int slot_rv,
+                                                    int slot_tt, int slot_ts) {
     const double rho = S[slot_rho], rv = S[slot_rv], tt = S[slot_tt], ts = S[slot_ts];
     const bool ok = usable(rho) && usable(rv) && usable(tt) && isfinite(ts);
     const double alpha = ok ? rho / rv : 0.0, omega = ok ? ts / tt : 0.0;
@@ -440,15 +574,16 @@ __global__ __launch_bounds__(BS) void k_bicg_update(int n, double* __restrict__ 
         acc[0] += ri * ri;
         acc[1] += ri * rb[i];
     }
-    const int sl[2] = {slot_rr, slot_rhonew};
-    reduce_store<2, BS>(acc, part, ticket, S, sl);
+    block_partials<2, BS>(acc, part);
 }
 
 void launch_bicg_update(int n, double* x, double* r, const double* pt, const double* st, const double* sv,
                         const double* t, const double* rb, const Reducer& R, int slot_rho, int slot_rv, int slot_tt,
                         int slot_ts, int slot_rr, int slot_rhonew, hipStream_t s) {
-    hipLaunchKernelGGL(k_bicg_update, dim3(red_blocks(n, 1)), dim3(BS), 0, s, n, x, r, pt, st, sv, t, rb, R.part,
-                       R.ticket, R.S, slot_rho, slot_rv, slot_tt, slot_ts, slot_rr, slot_rhonew);
+    const int g = vec_blocks(n);
+    hipLaunchKernelGGL(k_bicg_update, dim3(g), dim3(BS), 0, s, n, x, r, pt, st, sv, t, rb, R.part, R.S, slot_rho,
+                       slot_rv, slot_tt, slot_ts);
+    finish(g, 2, R, slot_rr, slot_rhonew, s);
 }
 
 // p_new = r + beta (p - omega v), beta = (rho_new / rho) (alpha / omega)
@@ -458,23 +593,21 @@ __global__ __launch_bounds__(BS) void k_bicg_dir(int n, const double* __restrict
                                                  int slot_ts, int slot_rhonew) {
     const double alpha = S[slot_rho] / S[slot_rv], omega = S[slot_ts] / S[slot_tt];
     const double beta = (S[slot_rhonew] / S[slot_rho]) * (alpha / omega);
-    const int i = blockIdx.x * BS + threadIdx.x;
-    if (i < n) pn[i] = r[i] + beta * (p[i] - omega * v[i]);
+    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) pn[i] = r[i] + beta * (p[i] - omega * v[i]);
 }
 
 void launch_bicg_dir(int n, const double* r, const double* p, const double* v, double* pn, const double* S,
                      int slot_rho, int slot_rv, int slot_tt, int slot_ts, int slot_rhonew, hipStream_t s) {
-    hipLaunchKernelGGL(k_bicg_dir, dim3(level_blocks(n, 1)), dim3(BS), 0, s, n, r, p, v, pn, S, slot_rho, slot_rv,
+    hipLaunchKernelGGL(k_bicg_dir, dim3(vec_blocks(n)), dim3(BS), 0, s, n, r, p, v, pn, S, slot_rho, slot_rv,
                        slot_tt, slot_ts, slot_rhonew);
 }
 
 __global__ __launch_bounds__(BS) void k_zero(int n, double* __restrict__ x) {
-    const int i = blockIdx.x * BS + threadIdx.x;
-    if (i < n) x[i] = 0.0;
+    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) x[i] = 0.0;
 }
 
 void launch_scale_zero(int n, double* x, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero, dim3(level_blocks(n, 1)), dim3(BS), 0, s, n, x);
+    hipLaunchKernelGGL(k_zero, dim3(vec_blocks(n)), dim3(BS), 0, s, n, x);
 }
 
 __global__ __launch_bounds__(BS) void k_check_finite(int n, const double* __restrict__ a,
@@ -485,7 +618,8 @@ __global__ __launch_bounds__(BS) void k_check_finite(int n, const double* __rest
 }
 
 void launch_check_finite(int n, const double* a, const double* b, int* err, hipStream_t s) {
-    hipLaunchKernelGGL(k_check_finite, dim3(red_blocks(n, 1)), dim3(BS), 0, s, n, a, b, err);
+    const int g = vec_blocks(n) < 2048 ? vec_blocks(n) : 2048;
+    hipLaunchKernelGGL(k_check_finite, dim3(g), dim3(BS), 0, s, n, a, b, err);
 }
 
 }  // namespace amg

@@ -82,6 +82,95 @@ def rounds_model(a):
     return mate, rounds
 
 
+def merged_rounds_model(a, rng=None, delay=0.0):
+    """One pass per round: the thread that decides a vertex also decrements the
+    counters of its higher neighbours and queues newly ready ones for the next
+    round; queued vertices that were decided meanwhile (as a match target) are
+    skipped.  With `rng`, each round's list is processed in random order and a
+    fraction `delay` of ready vertices is deferred to the next round, which
+    models arbitrary scheduling: the result must not depend on it."""
+    n, rp, ci, v = a.n, a.row_ptr, a.col, a.val
+
+    def has_edge(u, w):
+        lo, hi = rp[u], rp[u + 1]
+        k = lo + np.searchsorted(ci[lo:hi], w)
+        return k < hi and ci[k] == w and v[k] != 0.0
+
+    dec = np.full(n, UNDECIDED)
+    mate = np.full(n, -1)
+    lcnt = np.zeros(n, dtype=int)
+    for y in range(n):
+        for e in range(rp[y], rp[y + 1]):
+            if ci[e] < y and has_edge(ci[e], y):
+                lcnt[y] += 1
+    work = [y for y in range(n) if lcnt[y] == 0]
+    r = 0
+
+    def release(x, nxt):
+        for e in range(rp[x], rp[x + 1]):
+            y = ci[e]
+            if y > x and v[e] != 0.0:
+                lcnt[y] -= 1
+                if lcnt[y] == 0:
+                    nxt.append(y)
+
+    while work:
+        nxt = []
+        if rng is not None:
+            work = list(rng.permutation(work))
+        for u in work:
+            if dec[u] < r:  # decided in an earlier round: stale entry
+                continue
+            if rng is not None and rng.random() < delay:
+                nxt.append(u)
+                continue
+            best, k = -1, -1.0
+            for e in range(rp[u], rp[u + 1]):
+                j = ci[e]
+                if j > u and v[e] != 0.0 and dec[j] >= r and abs(v[e]) > k:
+                    best, k = j, abs(v[e])
+            if best < 0:
+                dec[u] = r
+                release(u, nxt)
+                continue
+            s = -1
+            for e in range(rp[best], rp[best + 1]):
+                x = ci[e]
+                if x < best and dec[x] >= r and has_edge(x, best):
+                    s = x
+                    break
+            if s == u:
+                dec[u] = dec[best] = r
+                mate[u], mate[best] = best, u
+                release(u, nxt)
+                release(best, nxt)
+            else:
+                nxt.append(u)
+        work = nxt
+        r += 1
+        assert r <= n + 2
+    assert np.all(dec < UNDECIDED)
+    return mate, r
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_merged_rounds_any_schedule_equal_sequential(seed):
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(1, 70))
+    a = P.random_symmetric_pattern(n, float(rng.uniform(0.02, 0.4)), seed, weights=(1, 2, 3)[: 1 + seed % 3],
+                                   nonsym_values=seed % 2 == 1, explicit_zeros=0.15 * (seed % 4 == 0))
+    want = oracle.hem_pass(a)
+    np.testing.assert_array_equal(merged_rounds_model(a)[0], want)
+    np.testing.assert_array_equal(merged_rounds_model(a, rng, delay=0.3)[0], want)
+
+
+def test_merged_rounds_grids():
+    for a in (P.poisson3d(9, 7, 6), P.convdiff3d(7), P.lognormal_diffusion3d(7, 3)):
+        want = oracle.hem_pass(a)
+        np.testing.assert_array_equal(merged_rounds_model(a)[0], want)
+        np.testing.assert_array_equal(merged_rounds_model(a, np.random.default_rng(1), 0.2)[0], want)
+
+
 @pytest.mark.parametrize("seed", range(40))
 def test_rounds_equal_sequential_random(seed):
     rng = np.random.default_rng(100 + seed)
