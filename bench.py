@@ -21,6 +21,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "AMG-PCG time to 1e-8 residual + HBM GB/s; served solves/s, p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2007_00056_amd", "csrc", "k_solve.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stream_post_poisson3d_128_traffic.txt")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source (otherwise None)."""
+    try:
+        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel") != kernel or kv.get("k_solve.hip sha256[:16]") != kernel_source_hash():
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def log(*a):
@@ -109,6 +130,8 @@ def main():
     ap.add_argument("--workload", default="poisson3d_128")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after timing, copy 256 MiB device-to-device (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is single-GPU and "
@@ -209,8 +232,16 @@ def main():
         "matching_rounds": recs[-1]["stats"]["rounds"],
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(names[dom].split()[0]), "algorithmic_bytes": kb[dom]},
     }
+    if args.copy_calibration:
+        src = torch.empty(1 << 25, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 268435456 bytes device-to-device for counter calibration")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the same input")
         out["cpu_baseline"] = cpu_baseline(a, b_host, spec, iters)
