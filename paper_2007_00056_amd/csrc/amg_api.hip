@@ -78,7 +78,9 @@ struct Level {
     int* agg = nullptr;    // to level k+1
     int4* mem = nullptr;   // members of level k+1 rows
     double* f = nullptr;   // restricted right-hand side (k >= 1)
+    double* g = nullptr;   // D^{-1} f (k >= 1)
     double* x = nullptr;   // correction (k >= 1)
+    double* xp = nullptr;  // prolongated iterate w D^{-1} f + P e (k < coarsest)
     double* t = nullptr;   // scratch of the general smoothing path
     int lpr = 4;
 
@@ -121,22 +123,49 @@ struct amg_hier {
     // Krylov workspace (allocated on first solve)
     double *r = nullptr, *z = nullptr, *pv[2] = {nullptr, nullptr}, *q = nullptr, *rb = nullptr, *pt = nullptr,
            *sv = nullptr, *st = nullptr, *t = nullptr;
+    double* g0 = nullptr;  // D^{-1} times the level-0 right-hand side of the V-cycle
     double* S = nullptr;
     double* part = nullptr;
     int* err = nullptr;
-    int stream_min = 32768;  // levels with at least this many rows use CSR-stream kernels
+    int stream_min = 262144;  // levels with at least this many rows use CSR-stream kernels
     double* S_host = nullptr;
     Timer tim[3];
+    // PCG iteration graphs (one per ping-pong parity), replayed on gstream
+    bool use_graphs = false;  // HEMAMG_GRAPHS=1: replay PCG iterations from HIP graphs
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    hipGraphExec_t g_full[2] = {nullptr, nullptr};  // whole iteration
+    hipGraphExec_t g_a[2] = {nullptr, nullptr};     // up to the level-0 postsmoothing (timed mode)
+    hipGraphExec_t g_b[2] = {nullptr, nullptr};     // after it (timed mode)
+    const double* g_key_b = nullptr;
+    double* g_key_x = nullptr;
 
     Reducer reducer() const { return Reducer{part, S}; }
 
+    void drop_graphs() {
+        for (int t = 0; t < 2; ++t) {
+            for (hipGraphExec_t* e : {&g_full[t], &g_a[t], &g_b[t]})
+                if (*e) {
+                    (void)hipGraphExecDestroy(*e);
+                    *e = nullptr;
+                }
+        }
+        g_key_b = nullptr;
+        g_key_x = nullptr;
+    }
+
     ~amg_hier() {
+        drop_graphs();
+        if (gstream) (void)hipStreamSynchronize(gstream);
         if (stream) (void)hipStreamSynchronize(stream);
         pool.release();
         if (stream) (void)hipStreamSynchronize(stream);
         if (S_host) (void)hipHostFree(S_host);
         for (auto& T : tim)
             for (hipEvent_t e : T.ev) (void)hipEventDestroy(e);
+        for (hipEvent_t e : gev)
+            if (e) (void)hipEventDestroy(e);
+        if (gstream) (void)hipStreamDestroy(gstream);
     }
 };
 
@@ -331,7 +360,7 @@ void timed_begin(amg_hier* h, int cls, hipStream_t s) {
     if (T.used + 2 > T.ev.size()) {
         for (int k = 0; k < 64; ++k) {
             hipEvent_t e;
-            HIPCHK(hipEventCreate(&e));
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
             T.ev.push_back(e);
         }
     }
@@ -355,36 +384,72 @@ void timed_end(amg_hier* h, int cls, hipStream_t s) {
     }
 }
 
-// Algorithm 1, z = V(r) from a zero initial guess, on every level.
-void run_vcycle(amg_hier* h, const double* r, double* z, hipStream_t s) {
+// Whether the level-0 postsmoothing can run as a separate step (part 2).
+bool vcycle_splits(const amg_hier* h) { return h->lev.size() > 1 && h->p.pre == 1 && h->p.post == 1; }
+
+// Algorithm 1, z = V(r) from a zero initial guess, on every level.  g0, if
+// given, already holds D^{-1} r.  dot_slot >= 0 also stores (r, z) there.
+// part 0 runs the whole cycle; when vcycle_splits(), part 1 runs everything
+// but the level-0 postsmoothing (and the dot) and part 2 runs only those.
+void run_vcycle(amg_hier* h, const double* r, double* z, hipStream_t s, const double* g0 = nullptr,
+                int dot_slot = -1, int part = 0) {
+    if (part != 0 && !vcycle_splits(h)) {
+        if (part == 2) return;
+        part = 0;
+    }
     const int L = (int)h->lev.size() - 1;
     const double w = h->p.omega;
+    const Reducer R = h->reducer();
     if (L == 0) {
-        launch_dense_apply(h->n_coarse, h->ainv_t, r, z, s);
+        launch_dense_apply(h->n_coarse, h->ainv_t, r, z, nullptr, s);
+        if (dot_slot >= 0) launch_dot(h->lev[0].n, r, z, R, dot_slot, s);
         return;
     }
-    std::vector<const double*> f(L + 1);
+    std::vector<const double*> f(L + 1), g(L + 1);
     std::vector<double*> x(L + 1);
     f[0] = r;
     x[0] = z;
     for (int k = 1; k <= L; ++k) {
         f[k] = h->lev[k].f;
+        g[k] = h->lev[k].g;
         x[k] = h->lev[k].x;
     }
     const bool fused = h->p.pre == 1 && h->p.post == 1;
+    if (fused) {
+        if (!g0) {
+            if (part != 2) launch_scale_dinv(h->lev[0].n, h->lev[0].dinv, r, h->g0, s);
+            g0 = h->g0;
+        }
+        g[0] = g0;
+    }
+    auto scatter_to = [&](int k) {  // into level k from level k+1
+        return Scatter{h->lev[k].mem, g[k], h->lev[k].xp, w};
+    };
+    if (part == 2) {  // level-0 postsmoothing (+ (r, z)) only
+        const Level& L0 = h->lev[0];
+        timed_begin(h, 0, s);
+        if (L0.n >= h->stream_min) {
+            launch_stream_post(L0.view(), L0.xp, g[0], w, z, r, dot_slot >= 0 ? &R : nullptr, dot_slot, nullptr, s);
+        } else {
+            launch_prolong_post(L0.view(), L0.xp, g[0], w, z, nullptr, s);
+            if (dot_slot >= 0) launch_dot(L0.n, r, z, R, dot_slot, s);
+        }
+        timed_end(h, 0, s);
+        return;
+    }
     for (int k = 0; k < L; ++k) {
         const Level& Lk = h->lev[k];
+        const Level& Lc = h->lev[k + 1];
         const LevelView V = Lk.view();
-        const int nc = h->lev[k + 1].n;
+        const int nc = Lc.n;
         if (fused) {
+            if (k == 0) timed_begin(h, 1, s);
             if (Lk.n >= h->stream_min) {
-                if (k == 0) timed_begin(h, 1, s);
-                launch_stream_resid(V, f[k], w, Lk.t, s);
+                launch_stream_resid(V, f[k], g[k], w, Lk.t, s);
                 if (k == 0) timed_end(h, 1, s);
-                launch_restrict(nc, Lk.mem, Lk.t, const_cast<double*>(f[k + 1]), s);
+                launch_restrict(nc, Lk.mem, Lk.t, Lc.dinv, Lc.f, Lc.g, s);
             } else {
-                if (k == 0) timed_begin(h, 1, s);
-                launch_resid_restrict(V, nc, f[k], w, const_cast<double*>(f[k + 1]), s);
+                launch_resid_restrict(V, nc, f[k], g[k], w, Lc.dinv, Lc.f, Lc.g, s);
                 if (k == 0) timed_end(h, 1, s);
             }
             continue;
@@ -405,26 +470,45 @@ void run_vcycle(amg_hier* h, const double* r, double* z, hipStream_t s) {
         }
         launch_resid_restrict_x(V, nc, f[k], xs, const_cast<double*>(f[k + 1]), s);
     }
-    launch_dense_apply(h->n_coarse, h->ainv_t, f[L], x[L], s);
-    for (int k = L - 1; k >= 0; --k) {
-        const Level& Lk = h->lev[k];
-        const LevelView V = Lk.view();
-        if (fused) {
+    // up-sweep: each level's result is scattered to the finer level's
+    // prolongated iterate, which that level's postsmoothing then reads
+    bool dot_done = false;
+    if (fused) {
+        const Scatter sc = scatter_to(L - 1);
+        launch_dense_apply(h->n_coarse, h->ainv_t, f[L], x[L], &sc, s);
+        for (int k = L - 1; k >= (part == 1 ? 1 : 0); --k) {
+            const Level& Lk = h->lev[k];
+            const LevelView V = Lk.view();
+            Scatter sc_k{};
+            if (k > 0) sc_k = scatter_to(k - 1);
+            const Scatter* psc = k > 0 ? &sc_k : nullptr;
             if (k == 0) timed_begin(h, 0, s);
-            if (Lk.n >= h->stream_min) launch_stream_post(V, f[k], x[k + 1], w, x[k], s);
-            else launch_prolong_post(V, f[k], x[k + 1], w, x[k], s);
+            if (Lk.n >= h->stream_min) {
+                const bool with_dot = k == 0 && dot_slot >= 0;
+                launch_stream_post(V, Lk.xp, g[k], w, x[k], f[k], with_dot ? &R : nullptr, dot_slot, psc, s);
+                dot_done = with_dot;
+            } else {
+                launch_prolong_post(V, Lk.xp, g[k], w, x[k], psc, s);
+            }
             if (k == 0) timed_end(h, 0, s);
-            continue;
         }
-        launch_prolong_add(Lk.n, Lk.agg, x[k + 1], x[k], s);
-        double* a = x[k];
-        double* b = Lk.t;
-        for (int it = 0; it < h->p.post; ++it) {
-            launch_jacobi(V, f[k], a, w, b, s);
-            std::swap(a, b);
+    } else {
+        launch_dense_apply(h->n_coarse, h->ainv_t, f[L], x[L], nullptr, s);
+        for (int k = L - 1; k >= 0; --k) {
+            const Level& Lk = h->lev[k];
+            const LevelView V = Lk.view();
+            launch_prolong_add(Lk.n, Lk.agg, x[k + 1], x[k], s);
+            double* a = x[k];
+            double* b = Lk.t;
+            for (int it = 0; it < h->p.post; ++it) {
+                launch_jacobi(V, f[k], a, w, b, s);
+                std::swap(a, b);
+            }
+            if (a != x[k]) HIPCHK(hipMemcpyAsync(x[k], a, sizeof(double) * Lk.n, hipMemcpyDeviceToDevice, s));
         }
-        if (a != x[k]) HIPCHK(hipMemcpyAsync(x[k], a, sizeof(double) * Lk.n, hipMemcpyDeviceToDevice, s));
     }
+    if (part == 1) return;
+    if (dot_slot >= 0 && !dot_done) launch_dot(h->lev[0].n, r, z, R, dot_slot, s);
 }
 
 void read_slots(amg_hier* h, hipStream_t s) {
@@ -441,6 +525,80 @@ void spmv_dot_timed(amg_hier* h, const LevelView& A, const double* p, double* q,
     timed_end(h, 2, s);
 }
 
+// One PCG iteration of parity pc (ping-pong of the direction vectors and of
+// the (r,z) slots): steps [A] q = A p, (p,q); x, r update, (r,r); V-cycle up
+// to level 1.  [P] level-0 postsmoothing and (r, z).  [B] next direction and
+// the read-back of the scalar slots (pinned host memory).
+void pcg_iter_a(amg_hier* h, double* x, int pc, hipStream_t s) {
+    const Level& A0 = h->lev[0];
+    const Reducer R = h->reducer();
+    const int cur = pc ? S_RHO1 : S_RHO0, nxt = pc ? S_RHO0 : S_RHO1;
+    double* p = h->pv[pc];
+    spmv_dot_timed(h, A0.view(), p, h->q, p, S_PQ, s);
+    launch_cg_update(A0.n, x, h->r, p, h->q, A0.dinv, h->g0, R, cur, S_PQ, S_RR, s);
+    run_vcycle(h, h->r, h->z, s, h->g0, nxt, 1);
+}
+
+void pcg_iter_p(amg_hier* h, int pc, hipStream_t s) {
+    run_vcycle(h, h->r, h->z, s, h->g0, pc ? S_RHO0 : S_RHO1, 2);
+}
+
+void pcg_iter_b(amg_hier* h, int pc, hipStream_t s) {
+    const int cur = pc ? S_RHO1 : S_RHO0, nxt = pc ? S_RHO0 : S_RHO1;
+    launch_cg_dir(h->lev[0].n, h->z, h->pv[pc], h->pv[1 - pc], h->S, nxt, cur, s);
+    HIPCHK(hipMemcpyAsync(h->S_host, h->S, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+}
+
+template <class F>
+hipGraphExec_t capture(hipStream_t s, F&& body) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    body();
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        raise(AMG_EHIP, "graph capture failed: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) raise(AMG_EHIP, "graph instantiation failed: %s", hipGetErrorString(e3));
+    return ex;
+}
+
+// Enqueue PCG iteration `pc` and its slot read-back on s (graph replay when
+// possible); the caller synchronises s and reads the slots.
+void pcg_iteration(amg_hier* h, const double* b, double* x, int pc, bool graphs, hipStream_t s) {
+    const bool timed = h->tim[0].on && vcycle_splits(h);
+    if (!graphs) {
+        pcg_iter_a(h, x, pc, s);
+        pcg_iter_p(h, pc, s);
+        pcg_iter_b(h, pc, s);
+        HIPCHK(hipGetLastError());
+        return;
+    }
+    if (h->g_key_b != b || h->g_key_x != x) h->drop_graphs();
+    h->g_key_b = b;
+    h->g_key_x = x;
+    if (!timed) {
+        if (!h->g_full[pc])
+            h->g_full[pc] = capture(s, [&] {
+                pcg_iter_a(h, x, pc, s);
+                pcg_iter_p(h, pc, s);
+                pcg_iter_b(h, pc, s);
+            });
+        HIPCHK(hipGraphLaunch(h->g_full[pc], s));
+        return;
+    }
+    // timed: the level-0 postsmoothing runs between two graphs, bracketed by events
+    if (!h->g_a[pc]) h->g_a[pc] = capture(s, [&] { pcg_iter_a(h, x, pc, s); });
+    if (!h->g_b[pc]) h->g_b[pc] = capture(s, [&] { pcg_iter_b(h, pc, s); });
+    HIPCHK(hipGraphLaunch(h->g_a[pc], s));
+    pcg_iter_p(h, pc, s);
+    HIPCHK(hipGraphLaunch(h->g_b[pc], s));
+}
+
 // Algorithm 4 with the readings documented in the header.
 amg_status pcg(amg_hier* h, const double* b, double* x, double rtol, int maxit, hipStream_t s, amg_info& info) {
     const Level& A0 = h->lev[0];
@@ -448,9 +606,10 @@ amg_status pcg(amg_hier* h, const double* b, double* x, double rtol, int maxit, 
     const int n = A0.n;
     const Reducer R = h->reducer();
     const int period = h->p.true_res_period;
+    const bool graphs = h->use_graphs && !h->tim[1].on && !h->tim[2].on;
     double* S = h->S_host;
     launch_dot(n, b, b, R, S_BB, s);
-    launch_residual(A, b, x, h->r, R, S_RR, s);
+    launch_residual(A, b, x, h->r, h->g0, R, S_RR, s);
     read_slots(h, s);
     const double nb = std::sqrt(S[S_BB]);
     info.iters = 0;
@@ -463,39 +622,31 @@ amg_status pcg(amg_hier* h, const double* b, double* x, double rtol, int maxit, 
     double rel = std::sqrt(S[S_RR]) / nb;
     info.rel_res = info.true_rel_res = rel;
     if (rel <= rtol) return AMG_OK;
-    int cur = S_RHO0, nxt = S_RHO1, pc = 0;
-    run_vcycle(h, h->r, h->z, s);
-    launch_dot(n, h->r, h->z, R, cur, s);
+    int pc = 0;
+    run_vcycle(h, h->r, h->z, s, h->g0, S_RHO0);
     HIPCHK(hipMemcpyAsync(h->pv[0], h->z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     for (int it = 1; it <= maxit; ++it) {
-        double* p = h->pv[pc];
-        double* pn = h->pv[1 - pc];
-        spmv_dot_timed(h, A, p, h->q, p, S_PQ, s);
-        launch_cg_update(n, x, h->r, p, h->q, R, cur, S_PQ, S_RR, s);
-        // speculative: preconditioning and the next direction, unused on exit
-        run_vcycle(h, h->r, h->z, s);
-        launch_dot(n, h->r, h->z, R, nxt, s);
-        launch_cg_dir(n, h->z, p, pn, h->S, nxt, cur, s);
-        HIPCHK(hipGetLastError());
-        read_slots(h, s);
+        const int cur = pc ? S_RHO1 : S_RHO0, nxt = pc ? S_RHO0 : S_RHO1;
+        // the preconditioning, (r, z) and the next direction are speculative:
+        // unused when this iteration stops
+        pcg_iteration(h, b, x, pc, graphs, s);
+        HIPCHK(hipStreamSynchronize(s));
         if (!usable(S[S_PQ]) || !std::isfinite(S[cur])) return AMG_EBREAKDOWN;
         info.iters = it;
         rel = std::sqrt(S[S_RR]) / nb;
         info.rel_res = rel;
         if (!std::isfinite(rel)) return AMG_EBREAKDOWN;
         if (rel <= rtol || (period > 0 && it % period == 0)) {
-            launch_residual(A, b, x, h->r, R, S_TRR, s);  // residual replacement
+            launch_residual(A, b, x, h->r, h->g0, R, S_TRR, s);  // residual replacement
             read_slots(h, s);
             const double tr = std::sqrt(S[S_TRR]) / nb;
             info.true_rel_res = tr;
             if (tr <= rtol) return AMG_OK;
-            run_vcycle(h, h->r, h->z, s);
-            launch_dot(n, h->r, h->z, R, nxt, s);
-            launch_cg_dir(n, h->z, p, pn, h->S, nxt, cur, s);
+            run_vcycle(h, h->r, h->z, s, h->g0, nxt);
+            launch_cg_dir(n, h->z, h->pv[pc], h->pv[1 - pc], h->S, nxt, cur, s);
             read_slots(h, s);
         }
         if (!usable(S[nxt])) return AMG_EBREAKDOWN;
-        std::swap(cur, nxt);
         pc = 1 - pc;
     }
     return AMG_ENOTCONV;
@@ -510,7 +661,7 @@ amg_status bicgstab(amg_hier* h, const double* b, double* x, double rtol, int ma
     const int period = h->p.true_res_period;
     double* S = h->S_host;
     launch_dot(n, b, b, R, S_BB, s);
-    launch_residual(A, b, x, h->r, R, S_RR, s);
+    launch_residual(A, b, x, h->r, nullptr, R, S_RR, s);
     read_slots(h, s);
     const double nb = std::sqrt(S[S_BB]);
     info.iters = 0;
@@ -548,7 +699,7 @@ amg_status bicgstab(amg_hier* h, const double* b, double* x, double rtol, int ma
         info.rel_res = rel;
         if (!std::isfinite(rel)) return AMG_EBREAKDOWN;
         if (rel <= rtol || (period > 0 && it % period == 0)) {
-            launch_residual(A, b, x, h->r, R, S_TRR, s);
+            launch_residual(A, b, x, h->r, nullptr, R, S_TRR, s);
             read_slots(h, s);
             const double tr = std::sqrt(S[S_TRR]) / nb;
             info.true_rel_res = tr;
@@ -694,14 +845,18 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     // per-level work vectors
     const bool fused = p.pre == 1 && p.post == 1;
     if (const char* e = getenv("HEMAMG_STREAM_MIN")) h->stream_min = atoi(e);  // tuning sweeps
+    if (const char* e = getenv("HEMAMG_GRAPHS")) h->use_graphs = atoi(e) != 0;
     for (size_t k = 0; k < h->lev.size(); ++k) {
         Level& L = h->lev[k];
         if (k > 0) {
             L.f = P.get<double>(L.n);
+            L.g = P.get<double>(L.n);
             L.x = P.get<double>(L.n);
         }
+        if (fused && k + 1 < h->lev.size()) L.xp = P.get<double>(L.n);
         if (!fused || L.n >= h->stream_min) L.t = P.get<double>(L.n);
     }
+    h->g0 = P.get<double>(h->lev[0].n);
     h->S = P.get<double>(S_COUNT);
     h->part = P.get<double>(2 * (size_t)kRedBlocks);
     HIPCHK(hipMemsetAsync(h->S, 0, S_COUNT * sizeof(double), s));
@@ -765,12 +920,26 @@ amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x,
         h->stream = s;
         h->pool.s = s;
         alloc_workspace(h);
-        HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), s));
-        launch_check_finite(h->lev[0].n, b, x, h->err, s);
+        // the solve runs on the handle's own stream (graphs cannot be captured
+        // on the null stream), ordered after the caller's prior work on s
+        if (!h->gstream) {
+            HIPCHK(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&h->gev[0], hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&h->gev[1], hipEventDisableTiming));
+        }
+        HIPCHK(hipEventRecord(h->gev[0], s));
+        HIPCHK(hipStreamWaitEvent(h->gstream, h->gev[0], 0));
+        hipStream_t ws = h->gstream;
+        h->pool.s = ws;
+        HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), ws));
+        launch_check_finite(h->lev[0].n, b, x, h->err, ws);
         HIPCHK(hipGetLastError());
-        if (read_int(h->err, s) & ERR_NONFINITE) raise(AMG_ENOTFINITE, "krylov_solve: b or x0 has NaN or Inf");
-        st = method == 0 ? pcg(h, b, x, rtol, maxit, s, I) : bicgstab(h, b, x, rtol, maxit, s, I);
-        HIPCHK(hipStreamSynchronize(s));
+        if (read_int(h->err, ws) & ERR_NONFINITE) raise(AMG_ENOTFINITE, "krylov_solve: b or x0 has NaN or Inf");
+        st = method == 0 ? pcg(h, b, x, rtol, maxit, ws, I) : bicgstab(h, b, x, rtol, maxit, ws, I);
+        HIPCHK(hipStreamSynchronize(ws));
+        HIPCHK(hipEventRecord(h->gev[1], ws));
+        HIPCHK(hipStreamWaitEvent(s, h->gev[1], 0));
+        h->pool.s = s;
         if (st == AMG_ENOTCONV) g_err = "krylov_solve: iteration limit reached";
         if (st == AMG_EBREAKDOWN) g_err = "krylov_solve: breakdown (zero or non-finite denominator)";
     });

@@ -102,35 +102,63 @@ struct Reducer {
     double* S;        // scalar slots
 };
 
+// A coarse level's finished value zc of row i becomes the finer level's
+// prolongated iterate on i's members m: xpf[m] = w gf[m] + zc.
+struct Scatter {
+    const int4* __restrict__ mem;
+    const double* __restrict__ gf;
+    double* __restrict__ xpf;
+    double w;
+    __device__ __forceinline__ void operator()(int i, double zc) const {
+        const int4 m = mem[i];
+        xpf[m.x] = w * gf[m.x] + zc;
+        if (m.y >= 0) xpf[m.y] = w * gf[m.y] + zc;
+        if (m.z >= 0) xpf[m.z] = w * gf[m.z] + zc;
+        if (m.w >= 0) xpf[m.w] = w * gf[m.w] + zc;
+    }
+};
+
 void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t s);
-// Large levels (CSR-stream): r = f - w A D^{-1} f, then f_c = P^T r, and the
-// prolongation + postsmoothing z = x + w D^{-1}(f - A x), x = w D^{-1} f + P e.
-void launch_stream_resid(const LevelView& L, const double* f, double w, double* r, hipStream_t s);
-void launch_restrict(int nc, const int4* mem, const double* r, double* fc, hipStream_t s);
-void launch_stream_post(const LevelView& L, const double* f, const double* e, double w, double* z, hipStream_t s);
-// Small levels (lane groups per row):
-// fc = P^T (f - A (w D^{-1} f)) : zero-guess presmoothing, residual, restriction.
-void launch_resid_restrict(const LevelView& L, int nc, const double* f, double w, double* fc, hipStream_t s);
-// z = x + w D^{-1} (f - A x) with x = w D^{-1} f + P e : prolongation + postsmoothing.
-void launch_prolong_post(const LevelView& L, const double* f, const double* e, double w, double* z, hipStream_t s);
+// Every level keeps g = D^{-1} f next to its right-hand side f; the kernel
+// that produces f also writes g.
+// Large levels (CSR-stream): r = f - w A g, then f_c = P^T r and g_c; the
+// prolongation + postsmoothing z = x + w (g - D^{-1} A x), x = w g + P e,
+// optionally with block partials of (f, z) reduced into slot `slot`.
+void launch_stream_resid(const LevelView& L, const double* f, const double* g, double w, double* r, hipStream_t s);
+void launch_restrict(int nc, const int4* mem, const double* r, const double* dinv_c, double* fc, double* gc,
+                     hipStream_t s);
+struct Reducer;
+struct Scatter;
+// Postsmoothing from the prolongated iterate xp = w g + P e: z = xp + w (g -
+// D^{-1} A xp).  With R, (f, z) goes to slot; with sc, z (a coarse level's
+// result) is scattered to the finer level's prolongated iterate.
+void launch_stream_post(const LevelView& L, const double* xp, const double* g, double w, double* z, const double* f,
+                        const Reducer* R, int slot, const Scatter* sc, hipStream_t s);
+// Small levels (lane groups per row), same operations with the restriction fused.
+void launch_resid_restrict(const LevelView& L, int nc, const double* f, const double* g, double w,
+                           const double* dinv_c, double* fc, double* gc, hipStream_t s);
+void launch_prolong_post(const LevelView& L, const double* xp, const double* g, double w, double* z,
+                         const Scatter* sc, hipStream_t s);
+void launch_scale_dinv(int n, const double* dinv, const double* f, double* g, hipStream_t s);
 // General smoothing path.
 void launch_jacobi_zero(int n, const double* dinv, const double* f, double w, double* x, hipStream_t s);
 void launch_jacobi(const LevelView& L, const double* f, const double* x, double w, double* xo, hipStream_t s);
 void launch_resid_restrict_x(const LevelView& L, int nc, const double* f, const double* x, double* fc,
                              hipStream_t s);
 void launch_prolong_add(int n, const int* agg, const double* e, double* x, hipStream_t s);
-void launch_dense_apply(int n, const double* ainv_t, const double* f, double* x, hipStream_t s);
+void launch_dense_apply(int n, const double* ainv_t, const double* f, double* x, const Scatter* sc, hipStream_t s);
 
 // Krylov vector kernels.  Slots index Reducer::S.
-void launch_residual(const LevelView& A, const double* b, const double* x, double* r, const Reducer& R, int slot_rr,
-                     hipStream_t s);
+// r = b - A x, (r, r); gout (may be null) receives D^{-1} r.
+void launch_residual(const LevelView& A, const double* b, const double* x, double* r, double* gout, const Reducer& R,
+                     int slot_rr, hipStream_t s);
 void launch_dot(int n, const double* a, const double* b, const Reducer& R, int slot, hipStream_t s);
 void launch_spmv_dot(const LevelView& A, const double* p, double* q, const double* d, const Reducer& R, int slot,
                      hipStream_t s);
 void launch_spmv_dot2(const LevelView& A, const double* p, double* t, const double* sv, const Reducer& R, int slot_tt,
                       int slot_ts, hipStream_t s);
-void launch_cg_update(int n, double* x, double* r, const double* p, const double* q, const Reducer& R, int slot_rho,
-                      int slot_pq, int slot_rr, hipStream_t s);
+void launch_cg_update(int n, double* x, double* r, const double* p, const double* q, const double* dinv, double* gout,
+                      const Reducer& R, int slot_rho, int slot_pq, int slot_rr, hipStream_t s);
 void launch_cg_dir(int n, const double* z, const double* p, double* pn, const double* S, int slot_new, int slot_old,
                    hipStream_t s);
 void launch_bicg_s(int n, const double* r, const double* v, double* sv, const double* S, int slot_rho, int slot_rv,

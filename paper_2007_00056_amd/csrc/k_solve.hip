@@ -47,8 +47,7 @@ int pick_lanes_per_row(double avg) {
         const int v = atoi(e);
         if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16) return v;
     }
-    if (avg <= 3.0) return 1;
-    if (avg <= 12.0) return 2;
+    if (avg <= 2.0) return 2;
     return 4;
 }
 
@@ -95,30 +94,27 @@ struct EntAx {  // a_ij x_j
     __device__ __forceinline__ double operator()(int e) const { return v[e] * x[ci[e]]; }
 };
 
-struct EntPre {  // a_ij (D^{-1} f)_j : presmoothed zero-guess iterate without the factor w
-    const double* __restrict__ v;
-    const int* __restrict__ ci;
-    const double* __restrict__ dinv;
-    const double* __restrict__ f;
-    __device__ __forceinline__ double operator()(int e) const {
-        const int j = ci[e];
-        return v[e] * (dinv[j] * f[j]);
-    }
-};
+constexpr int FIN_BS = 1024;
 
-struct EntPost {  // a_ij (w D^{-1} f + P e)_j : prolongated iterate
-    const double* __restrict__ v;
-    const int* __restrict__ ci;
-    const double* __restrict__ dinv;
-    const double* __restrict__ f;
-    const int* __restrict__ agg;
-    const double* __restrict__ ec;
-    double w;
-    __device__ __forceinline__ double operator()(int e) const {
-        const int j = ci[e];
-        return v[e] * (w * (dinv[j] * f[j]) + ec[agg[j]]);
+__global__ __launch_bounds__(FIN_BS) void k_finish(int nparts, int nv, const double* __restrict__ part,
+                                                   double* __restrict__ S, int slot0, int slot1) {
+    __shared__ double sh[2][FIN_BS / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (int k = 0; k < nv; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nparts; b += FIN_BS) s += part[k * nparts + b];
+        s = group_sum<kWave>(s);
+        if (lane == 0) sh[k][wid] = s;
     }
-};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < nv; ++k) {
+            double s = sh[k][0];
+            for (int w = 1; w < FIN_BS / kWave; ++w) s += sh[k][w];
+            S[k == 0 ? slot0 : slot1] = s;
+        }
+    }
+}
 
 // y = A x
 __global__ __launch_bounds__(BS) void k_stream_spmv(int n, const int* __restrict__ rp, EntAx ent,
@@ -131,8 +127,8 @@ __global__ __launch_bounds__(BS) void k_stream_spmv(int n, const int* __restrict
     }
 }
 
-// r = f - w A D^{-1} f : residual after the zero-guess presmoothing sweep
-__global__ __launch_bounds__(BS) void k_stream_resid(int n, const int* __restrict__ rp, EntPre ent,
+// r = f - w A g, g = D^{-1} f : residual after the zero-guess presmoothing sweep
+__global__ __launch_bounds__(BS) void k_stream_resid(int n, const int* __restrict__ rp, EntAx ent,
                                                      const double* __restrict__ f, double w,
                                                      double* __restrict__ r) {
     __shared__ double prod[kStreamChunk];
@@ -143,24 +139,34 @@ __global__ __launch_bounds__(BS) void k_stream_resid(int n, const int* __restric
     }
 }
 
-// z = x + w D^{-1} (f - A x), x = w D^{-1} f + P e : prolongation + postsmoothing
-__global__ __launch_bounds__(BS) void k_stream_post(int n, const int* __restrict__ rp, EntPost ent,
-                                                    double* __restrict__ z) {
+// Postsmoothing on the prolongated iterate xp = w g + P e (written by the
+// coarser level): z = xp + w D^{-1} (f - A xp) = xp + w (g - D^{-1} A xp).
+// MODE 1 also forms block partials of (f, z); MODE 2 scatters z to the finer
+// level's prolongated iterate.
+template <int MODE>
+__global__ __launch_bounds__(BS) void k_stream_post(int n, const int* __restrict__ rp, EntAx ent,
+                                                    const double* __restrict__ g, const double* __restrict__ dinv,
+                                                    double w, double* __restrict__ z, const double* __restrict__ f,
+                                                    double* part, Scatter sc) {
     __shared__ double prod[kStreamChunk];
+    double acc[1] = {0.0};
     for (int b = xcd_block(blockIdx.x, gridDim.x); b * BS < n; b += gridDim.x) {
         const double s = stream_rows(b * BS, n, rp, ent, prod);
         const int row = b * BS + threadIdx.x;
         if (row < n) {
-            const double di = ent.dinv[row], fi = ent.f[row];
-            const double xi = ent.w * (di * fi) + ent.ec[ent.agg[row]];
-            z[row] = xi + ent.w * (di * (fi - s));
+            const double zi = ent.x[row] + w * (g[row] - dinv[row] * s);
+            z[row] = zi;
+            if (MODE == 1) acc[0] += f[row] * zi;
+            if (MODE == 2) sc(row, zi);
         }
     }
+    if (MODE == 1) block_partials<1, BS>(acc, part);
 }
 
-// f_c = P^T r, members of each coarse row added in ascending order
+// f_c = P^T r (members added in ascending order) and g_c = D_c^{-1} f_c
 __global__ __launch_bounds__(BS) void k_restrict(int nc, const int4* __restrict__ mem, const double* __restrict__ r,
-                                                 double* __restrict__ fc) {
+                                                 const double* __restrict__ dinv_c, double* __restrict__ fc,
+                                                 double* __restrict__ gc) {
     const int J = blockIdx.x * BS + threadIdx.x;
     if (J >= nc) return;
     const int4 m = mem[J];
@@ -169,6 +175,7 @@ __global__ __launch_bounds__(BS) void k_restrict(int nc, const int4* __restrict_
     if (m.z >= 0) s += r[m.z];
     if (m.w >= 0) s += r[m.w];
     fc[J] = s;
+    gc[J] = dinv_c[J] * s;
 }
 
 inline int stream_blocks(int n) {
@@ -180,18 +187,33 @@ void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t s) 
     hipLaunchKernelGGL(k_stream_spmv, dim3(stream_blocks(L.n)), dim3(BS), 0, s, L.n, L.rp, EntAx{L.v, L.ci, x}, y);
 }
 
-void launch_stream_resid(const LevelView& L, const double* f, double w, double* r, hipStream_t s) {
-    hipLaunchKernelGGL(k_stream_resid, dim3(stream_blocks(L.n)), dim3(BS), 0, s, L.n, L.rp,
-                       EntPre{L.v, L.ci, L.dinv, f}, f, w, r);
+void launch_stream_resid(const LevelView& L, const double* f, const double* g, double w, double* r,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_stream_resid, dim3(stream_blocks(L.n)), dim3(BS), 0, s, L.n, L.rp, EntAx{L.v, L.ci, g}, f, w,
+                       r);
 }
 
-void launch_restrict(int nc, const int4* mem, const double* r, double* fc, hipStream_t s) {
-    hipLaunchKernelGGL(k_restrict, dim3(level_blocks(nc, 1)), dim3(BS), 0, s, nc, mem, r, fc);
+void launch_restrict(int nc, const int4* mem, const double* r, const double* dinv_c, double* fc, double* gc,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_restrict, dim3(level_blocks(nc, 1)), dim3(BS), 0, s, nc, mem, r, dinv_c, fc, gc);
 }
 
-void launch_stream_post(const LevelView& L, const double* f, const double* e, double w, double* z, hipStream_t s) {
-    hipLaunchKernelGGL(k_stream_post, dim3(stream_blocks(L.n)), dim3(BS), 0, s, L.n, L.rp,
-                       EntPost{L.v, L.ci, L.dinv, f, L.agg, e, w}, z);
+void launch_stream_post(const LevelView& L, const double* xp, const double* g, double w, double* z, const double* f,
+                        const Reducer* R, int slot, const Scatter* sc, hipStream_t s) {
+    const int gsz = stream_blocks(L.n);
+    const EntAx ent{L.v, L.ci, xp};
+    const Scatter none{nullptr, nullptr, nullptr, 0.0};
+    if (R) {
+        hipLaunchKernelGGL(k_stream_post<1>, dim3(gsz), dim3(BS), 0, s, L.n, L.rp, ent, g, L.dinv, w, z, f, R->part,
+                           none);
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(FIN_BS), 0, s, gsz, 1, R->part, R->S, slot, slot);
+    } else if (sc) {
+        hipLaunchKernelGGL(k_stream_post<2>, dim3(gsz), dim3(BS), 0, s, L.n, L.rp, ent, g, L.dinv, w, z, f, nullptr,
+                           *sc);
+    } else {
+        hipLaunchKernelGGL(k_stream_post<0>, dim3(gsz), dim3(BS), 0, s, L.n, L.rp, ent, g, L.dinv, w, z, f, nullptr,
+                           none);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -202,10 +224,10 @@ void launch_stream_post(const LevelView& L, const double* f, const double* e, do
 template <int LPR>
 __global__ __launch_bounds__(BS) void k_resid_restrict(int nc, const int4* __restrict__ mem,
                                                        const int* __restrict__ rp, const int* __restrict__ ci,
-                                                       const double* __restrict__ v,
-                                                       const double* __restrict__ dinv,
+                                                       const double* __restrict__ v, const double* __restrict__ g,
                                                        const double* __restrict__ f, double w,
-                                                       double* __restrict__ fc) {
+                                                       const double* __restrict__ dinv_c, double* __restrict__ fc,
+                                                       double* __restrict__ gc) {
     constexpr int G = 4 * LPR;
     const int t = blockIdx.x * BS + threadIdx.x;
     const int J = t / G, sub = (t % G) / LPR, lane = t % LPR;
@@ -215,13 +237,7 @@ __global__ __launch_bounds__(BS) void k_resid_restrict(int nc, const int4* __res
         i = sub == 0 ? m.x : sub == 1 ? m.y : sub == 2 ? m.z : m.w;
     }
     double s = 0.0;
-    if (i >= 0) {
-        const int b = rp[i], e = rp[i + 1];
-        for (int k = b + lane; k < e; k += LPR) {
-            const int j = ci[k];
-            s += v[k] * (dinv[j] * f[j]);
-        }
-    }
+    if (i >= 0) s = row_ax<LPR>(i, lane, rp, ci, v, g);
     s = group_sum<LPR>(s);
     const double ri = i >= 0 ? f[i] - w * s : 0.0;
     const int base = (threadIdx.x & (kWave - 1)) & ~(G - 1);
@@ -229,48 +245,61 @@ __global__ __launch_bounds__(BS) void k_resid_restrict(int nc, const int4* __res
     const double r1 = __shfl(ri, base + LPR, kWave);
     const double r2 = __shfl(ri, base + 2 * LPR, kWave);
     const double r3 = __shfl(ri, base + 3 * LPR, kWave);
-    if (J < nc && (t % G) == 0) fc[J] = ((r0 + r1) + r2) + r3;
+    if (J < nc && (t % G) == 0) {
+        const double fj = ((r0 + r1) + r2) + r3;
+        fc[J] = fj;
+        gc[J] = dinv_c[J] * fj;
+    }
 }
 
-void launch_resid_restrict(const LevelView& L, int nc, const double* f, double w, double* fc, hipStream_t s) {
+void launch_resid_restrict(const LevelView& L, int nc, const double* f, const double* g, double w,
+                           const double* dinv_c, double* fc, double* gc, hipStream_t s) {
 #define CALL(W)                                                                                                 \
     hipLaunchKernelGGL(k_resid_restrict<W>, dim3(level_blocks((int64_t)nc * 4, W)), dim3(BS), 0, s, nc, L.mem, \
-                       L.rp, L.ci, L.v, L.dinv, f, w, fc)
+                       L.rp, L.ci, L.v, g, f, w, dinv_c, fc, gc)
     AMG_DISPATCH_LPR(L.lpr, CALL)
 #undef CALL
 }
 
-template <int LPR>
+template <int LPR, bool SCAT>
 __global__ __launch_bounds__(BS) void k_prolong_post(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                      const double* __restrict__ v,
                                                      const double* __restrict__ dinv,
-                                                     const double* __restrict__ f, const int* __restrict__ agg,
-                                                     const double* __restrict__ e, double w,
-                                                     double* __restrict__ z) {
+                                                     const double* __restrict__ g, const double* __restrict__ xp,
+                                                     double w, double* __restrict__ z, Scatter sc) {
     const int t = blockIdx.x * BS + threadIdx.x;
     const int row = t / LPR, lane = t % LPR;
-    double s = 0.0;
-    if (row < n) {
-        const int b = rp[row], end = rp[row + 1];
-        for (int k = b + lane; k < end; k += LPR) {
-            const int j = ci[k];
-            s += v[k] * (w * (dinv[j] * f[j]) + e[agg[j]]);
-        }
-    }
+    double s = row < n ? row_ax<LPR>(row, lane, rp, ci, v, xp) : 0.0;
     s = group_sum<LPR>(s);
     if (row < n && lane == 0) {
-        const double di = dinv[row], fi = f[row];
-        const double xi = w * (di * fi) + e[agg[row]];
-        z[row] = xi + w * (di * (fi - s));
+        const double zi = xp[row] + w * (g[row] - dinv[row] * s);
+        z[row] = zi;
+        if (SCAT) sc(row, zi);
     }
 }
 
-void launch_prolong_post(const LevelView& L, const double* f, const double* e, double w, double* z, hipStream_t s) {
-#define CALL(W)                                                                                                       \
-    hipLaunchKernelGGL(k_prolong_post<W>, dim3(level_blocks(L.n, W)), dim3(BS), 0, s, L.n, L.rp, L.ci, L.v, L.dinv, \
-                       f, L.agg, e, w, z)
+void launch_prolong_post(const LevelView& L, const double* xp, const double* g, double w, double* z,
+                         const Scatter* sc, hipStream_t s) {
+    const Scatter none{nullptr, nullptr, nullptr, 0.0};
+#define CALL(W)                                                                                                     \
+    if (sc)                                                                                                        \
+        hipLaunchKernelGGL((k_prolong_post<W, true>), dim3(level_blocks(L.n, W)), dim3(BS), 0, s, L.n, L.rp, L.ci, \
+                           L.v, L.dinv, g, xp, w, z, *sc);                                                         \
+    else                                                                                                           \
+        hipLaunchKernelGGL((k_prolong_post<W, false>), dim3(level_blocks(L.n, W)), dim3(BS), 0, s, L.n, L.rp,     \
+                           L.ci, L.v, L.dinv, g, xp, w, z, none)
     AMG_DISPATCH_LPR(L.lpr, CALL)
 #undef CALL
+}
+
+// g = D^{-1} f
+__global__ __launch_bounds__(BS) void k_scale_dinv(int n, const double* __restrict__ dinv,
+                                                   const double* __restrict__ f, double* __restrict__ g) {
+    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) g[i] = dinv[i] * f[i];
+}
+
+void launch_scale_dinv(int n, const double* dinv, const double* f, double* g, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_dinv, dim3(vec_blocks(n)), dim3(BS), 0, s, n, dinv, f, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -353,8 +382,9 @@ void launch_prolong_add(int n, const int* agg, const double* e, double* x, hipSt
 
 // Coarsest level: x = A_L^{-1} f with the inverse stored column-major.  One
 // block stages f in LDS; each thread forms one row with independent loads.
+// With a scatter, x also becomes the finer level's prolongated iterate.
 __global__ __launch_bounds__(BS) void k_dense_apply(int n, const double* __restrict__ ainv_t,
-                                                   const double* __restrict__ f, double* __restrict__ x) {
+                                                   const double* __restrict__ f, double* __restrict__ x, Scatter sc) {
     __shared__ double fs[1024];
     for (int j = threadIdx.x; j < n; j += BS) fs[j] = f[j];
     __syncthreads();
@@ -368,12 +398,15 @@ __global__ __launch_bounds__(BS) void k_dense_apply(int n, const double* __restr
             s3 += ainv_t[(size_t)(j + 3) * n + i] * fs[j + 3];
         }
         for (; j < n; ++j) s0 += ainv_t[(size_t)j * n + i] * fs[j];
-        x[i] = (s0 + s1) + (s2 + s3);
+        const double xi = (s0 + s1) + (s2 + s3);
+        x[i] = xi;
+        if (sc.mem) sc(i, xi);
     }
 }
 
-void launch_dense_apply(int n, const double* ainv_t, const double* f, double* x, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_apply, dim3(1), dim3(BS), 0, s, n, ainv_t, f, x);
+void launch_dense_apply(int n, const double* ainv_t, const double* f, double* x, const Scatter* sc, hipStream_t s) {
+    const Scatter none{nullptr, nullptr, nullptr, 0.0};
+    hipLaunchKernelGGL(k_dense_apply, dim3(1), dim3(BS), 0, s, n, ainv_t, f, x, sc ? *sc : none);
 }
 
 // ---------------------------------------------------------------------------
@@ -386,28 +419,6 @@ void launch_dense_apply(int n, const double* ainv_t, const double* f, double* x,
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool usable(double d) { return isfinite(d) && d != 0.0; }
 
-constexpr int FIN_BS = 1024;
-
-__global__ __launch_bounds__(FIN_BS) void k_finish(int nparts, int nv, const double* __restrict__ part,
-                                                   double* __restrict__ S, int slot0, int slot1) {
-    __shared__ double sh[2][FIN_BS / kWave];
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    for (int k = 0; k < nv; ++k) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nparts; b += FIN_BS) s += part[k * nparts + b];
-        s = group_sum<kWave>(s);
-        if (lane == 0) sh[k][wid] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < nv; ++k) {
-            double s = sh[k][0];
-            for (int w = 1; w < FIN_BS / kWave; ++w) s += sh[k][w];
-            S[k == 0 ? slot0 : slot1] = s;
-        }
-    }
-}
-
 inline void finish(int nparts, int nv, const Reducer& R, int slot0, int slot1, hipStream_t s) {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(FIN_BS), 0, s, nparts, nv, R.part, R.S, slot0, slot1);
 }
@@ -415,6 +426,7 @@ inline void finish(int nparts, int nv, const Reducer& R, int slot0, int slot1, h
 // r = b - A x, partial (r, r)
 __global__ __launch_bounds__(BS) void k_stream_residual(int n, const int* __restrict__ rp, EntAx ent,
                                                         const double* __restrict__ b, double* __restrict__ r,
+                                                        const double* __restrict__ dinv, double* __restrict__ g,
                                                         double* part) {
     __shared__ double prod[kStreamChunk];
     double acc[1] = {0.0};
@@ -424,16 +436,18 @@ __global__ __launch_bounds__(BS) void k_stream_residual(int n, const int* __rest
         if (row < n) {
             const double ri = b[row] - s;
             r[row] = ri;
+            if (g) g[row] = dinv[row] * ri;
             acc[0] += ri * ri;
         }
     }
     block_partials<1, BS>(acc, part);
 }
 
-void launch_residual(const LevelView& A, const double* b, const double* x, double* r, const Reducer& R, int slot,
-                     hipStream_t s) {
+void launch_residual(const LevelView& A, const double* b, const double* x, double* r, double* gout, const Reducer& R,
+                     int slot, hipStream_t s) {
     const int g = stream_blocks(A.n);
-    hipLaunchKernelGGL(k_stream_residual, dim3(g), dim3(BS), 0, s, A.n, A.rp, EntAx{A.v, A.ci, x}, b, r, R.part);
+    hipLaunchKernelGGL(k_stream_residual, dim3(g), dim3(BS), 0, s, A.n, A.rp, EntAx{A.v, A.ci, x}, b, r, A.dinv, gout,
+                       R.part);
     finish(g, 1, R, slot, slot, s);
 }
 
@@ -502,6 +516,7 @@ void launch_dot(int n, const double* a, const double* b, const Reducer& R, int s
 // Algorithm 4: alpha = (r,z)/(Ap,p); x += alpha p; r -= alpha Ap; partial (r,r).
 __global__ __launch_bounds__(BS) void k_cg_update(int n, double* __restrict__ x, double* __restrict__ r,
                                                   const double* __restrict__ p, const double* __restrict__ q,
+                                                  const double* __restrict__ dinv, double* __restrict__ g,
                                                   double* part, const double* __restrict__ S, int slot_rho,
                                                   int slot_pq) {
     const double rho = S[slot_rho], pq = S[slot_pq];
@@ -515,15 +530,17 @@ __global__ __launch_bounds__(BS) void k_cg_update(int n, double* __restrict__ x,
             ri -= alpha * q[i];
             r[i] = ri;
         }
+        if (g) g[i] = dinv[i] * ri;
         acc[0] += ri * ri;
     }
     block_partials<1, BS>(acc, part);
 }
 
-void launch_cg_update(int n, double* x, double* r, const double* p, const double* q, const Reducer& R, int slot_rho,
-                      int slot_pq, int slot_rr, hipStream_t s) {
+void launch_cg_update(int n, double* x, double* r, const double* p, const double* q, const double* dinv, double* gout,
+                      const Reducer& R, int slot_rho, int slot_pq, int slot_rr, hipStream_t s) {
     const int g = vec_blocks(n);
-    hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(BS), 0, s, n, x, r, p, q, R.part, R.S, slot_rho, slot_pq);
+    hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(BS), 0, s, n, x, r, p, q, dinv, gout, R.part, R.S, slot_rho,
+                       slot_pq);
     finish(g, 1, R, slot_rr, slot_rr, s);
 }
 

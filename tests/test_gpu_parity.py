@@ -166,6 +166,35 @@ def test_deterministic_bitwise(torch):
     assert torch.equal(x1, x2) and torch.equal(x1, x3)
 
 
+@pytest.mark.parametrize("name", ["poisson3d_17x13x11", "lognormal3d_11"])
+def test_graph_replay_matches_eager(torch, name, monkeypatch):
+    """PCG iterations replayed from HIP graphs (whole, and split around the timed
+    kernel) give bitwise the same iterates as eager launches; residual
+    replacement every 7 iterations puts eager work between replays."""
+    a = CASES[name]()
+    b = dev(torch, P.rhs_uniform(a.n, 4))
+    A = hemamg.DeviceCSR.from_host(a)
+    out = {}
+    for mode in ("eager", "graph", "graph_timed"):
+        monkeypatch.setenv("HEMAMG_GRAPHS", "0" if mode == "eager" else "1")
+        monkeypatch.setenv("HEMAMG_STREAM_MIN", "256")  # stream kernels on every level here
+        with hemamg.Hierarchy(A, true_res_period=7) as g:
+            if mode == "graph_timed":
+                hemamg.amg_timing_enable(g.h, hemamg.KERNEL_PROLONG_POST, True)
+            xs = []
+            for rep in range(2):
+                x, info = g.solve(b, rtol=1e-11)
+                xs.append(x.clone())
+            if mode == "graph_timed":
+                launches, ms = hemamg.amg_timing_read(g.h, hemamg.KERNEL_PROLONG_POST)
+                assert launches >= 2 * info["iters"] and ms > 0
+        assert torch.equal(xs[0], xs[1])
+        out[mode] = (xs[0], info["iters"])
+    assert out["graph"][1] == out["eager"][1] == out["graph_timed"][1]
+    assert torch.equal(out["graph"][0], out["eager"][0])
+    assert torch.equal(out["graph_timed"][0], out["eager"][0])
+
+
 # ---------------------------------------------------------------- edge cases
 
 def test_one_by_one(torch):
