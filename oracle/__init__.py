@@ -23,7 +23,8 @@ _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 
 class Params(C.Structure):
     _fields_ = [("passes_per_level", C.c_int32), ("max_coarse_rows", C.c_int32), ("max_levels", C.c_int32),
-                ("max_dense_rows", C.c_int32), ("omega", C.c_double), ("pre", C.c_int32), ("post", C.c_int32)]
+                ("max_dense_rows", C.c_int32), ("omega", C.c_double), ("pre", C.c_int32), ("post", C.c_int32),
+                ("stall_ratio", C.c_double)]
 
 
 class Info(C.Structure):

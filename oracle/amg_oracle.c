@@ -236,6 +236,7 @@ void oracle_params_default(oracle_params* p) {
     p->max_coarse_rows = 64;
     p->max_levels = 32;
     p->max_dense_rows = 1024;
+    p->stall_ratio = 0.9;
     p->omega = 2.0 / 3.0;
     p->pre = 1;
     p->post = 1;
@@ -348,7 +349,8 @@ oracle_hier* oracle_setup(int32_t n, const int32_t* rp, const int32_t* ci, const
     if (p) h->p = *p;
     else oracle_params_default(&h->p);
     int32_t maxlev = h->p.max_levels < MAXLEV ? h->p.max_levels : MAXLEV;
-    if (h->p.passes_per_level < 1 || maxlev < 1 || h->p.pre < 0 || h->p.post < 0) {
+    if (h->p.passes_per_level < 1 || maxlev < 1 || h->p.pre < 0 || h->p.post < 0 ||
+        !(h->p.stall_ratio > 0.0 && h->p.stall_ratio <= 1.0)) {
         oracle_destroy(h);
         *status = ORACLE_EINVAL;
         return NULL;
@@ -369,6 +371,13 @@ oracle_hier* oracle_setup(int32_t n, const int32_t* rp, const int32_t* ci, const
             free(F->agg);
             F->agg = NULL;
             if (F->n > h->p.max_dense_rows) st = ORACLE_ESTALL;
+            break;
+        }
+        /* poor progress on a level the dense solve can take: it is the coarsest */
+        if ((double)h->lev[k + 1].n >= h->p.stall_ratio * (double)F->n && F->n <= h->p.max_dense_rows) {
+            free_level(&h->lev[k + 1]);
+            free(F->agg);
+            F->agg = NULL;
             break;
         }
         ++k;

@@ -38,6 +38,10 @@ typedef struct {
     int32_t max_dense_rows;   /* largest coarsest level accepted on a stall    */
     double omega;             /* Jacobi damping (2/3)                          */
     int32_t pre, post;        /* smoothing sweeps (1, 1)                       */
+    double stall_ratio;       /* a level of n <= max_dense_rows rows becomes   *
+                               * the coarsest when coarsening it would keep    *
+                               * n_c >= stall_ratio * n rows (0.9); 1 stops    *
+                               * only when no row is merged                    */
 } oracle_params;
 
 typedef struct {

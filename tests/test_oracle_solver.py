@@ -220,3 +220,27 @@ def test_stall_falls_back_to_dense_or_reports():
     with pytest.raises(oracle.OracleError) as e:
         oracle.Hierarchy(a, max_dense_rows=50)
     assert e.value.status == oracle.ESTALL
+
+
+def test_star_graph_stall_ratio_rule():
+    # two pairwise passes on a star merge two leaves into the hub: n -> n - 2
+    a = P.star_graph(100, 0)
+    h = oracle.Hierarchy(a)  # 98 >= 0.9 * 100 and 100 <= max_dense_rows: dense at once
+    assert h.nlevels == 1
+    h = oracle.Hierarchy(a, stall_ratio=1.0)  # only a level with no merge stops
+    sizes = [h.level(k).row_ptr.size - 1 for k in range(h.nlevels)]
+    assert sizes == list(range(100, 63, -2)), sizes
+    # a stalling level above max_dense_rows keeps coarsening
+    h = oracle.Hierarchy(a, max_dense_rows=90)
+    sizes = [h.level(k).row_ptr.size - 1 for k in range(h.nlevels)]
+    assert sizes == [100, 98, 96, 94, 92, 90], sizes
+    # the V-cycle of the one-level hierarchy is the exact solve
+    b = P.rhs_uniform(a.n, 1)
+    dense = np.zeros((a.n, a.n))
+    for i in range(a.n):
+        dense[i, a.col[a.row_ptr[i]:a.row_ptr[i + 1]]] = a.val[a.row_ptr[i]:a.row_ptr[i + 1]]
+    np.testing.assert_allclose(oracle.Hierarchy(a).vcycle(b), np.linalg.solve(dense, b), rtol=1e-12)
+    for bad in (0.0, -0.5, 1.5):
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.Hierarchy(a, stall_ratio=bad)
+        assert e.value.status == oracle.EINVAL
