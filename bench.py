@@ -21,8 +21,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "AMG-PCG time to 1e-8 residual + HBM GB/s; served solves/s, p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2007_00056_amd", "csrc", "k_solve.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stream_post_poisson3d_128_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2007_00056_amd", "csrc", "k_vcycle.hip")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash() -> str:
@@ -31,15 +31,16 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source (otherwise None)."""
+def measured_traffic(kernel: str, workload: str, precond: str):
+    """HBM bytes per launch from the committed counter summary of this kernel
+    and workload, if it was taken on the current kernel source (else None)."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_{precond}_traffic.txt")
     try:
-        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line and not line.startswith("#"))
+        kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("kernel") != kernel or kv.get("k_solve.hip sha256[:16]") != kernel_source_hash():
+    if kv.get("kernel") != kernel or kv.get("k_vcycle.hip sha256[:16]") != kernel_source_hash():
         return None
     return float(kv["hbm_bytes_per_launch"])
 
@@ -56,47 +57,53 @@ def level_sizes(h, hemamg):
 STREAM_MIN = 262144  # levels with at least this many rows use the CSR-stream kernels
 
 
-def kernel_bytes(sizes):
-    """Algorithmic bytes per launch of the timed level-0 kernels (FP64 values,
-    int32 indices; every array counted once)."""
+def kernel_bytes(sizes, e, method):
+    """Algorithmic bytes per launch of the timed level-0 kernels: preconditioner
+    values and vectors of e bytes (8 double, 4 float), int32 indices, the
+    level-0 right-hand side and result in double; every array counted once."""
     (n, nnz) = sizes[0]
+    csr = (e + 4) * nnz + 4 * (n + 1)
     return {
-        # postsmoothing from the prolongated iterate xp (PCG form, with (r, z) fused):
-        # val+col 12 nnz, row_ptr 4(n+1), xp g D^{-1} r read 32 n, z write 8 n
-        0: 12 * nnz + 4 * (n + 1) + 40 * n,
-        # presmoothing + residual: 12 nnz + 4(n+1), g gather + f read 16 n, r write 8 n
-        1: 12 * nnz + 4 * (n + 1) + 24 * n,
-        # outer SpMV + dot: 12 nnz + 4(n+1), p read + q write 16 n
+        # postsmoothing from the prolongated iterate xp: xp gather, g, D^{-1} read
+        # (3e n), z write (8 n); PCG fuses (r, z) and also reads r (8 n)
+        0: csr + 3 * e * n + (16 if method == "pcg" else 8) * n,
+        # presmoothing + residual: g gather, r read (8 n), residual write
+        1: csr + 2 * e * n + 8 * n,
+        # outer SpMV + dot, always double: p read + q write
         2: 12 * nnz + 4 * (n + 1) + 16 * n,
     }
 
 
-def level_bytes(k, sizes):
-    """One V-cycle level k (down + up sweep) in the fused FP64 form."""
+def level_bytes(k, sizes, e):
+    """One V-cycle level k (down + up sweep) in the fused form, values and
+    vectors of e bytes; level 0 reads its right-hand side in double."""
     n, nnz = sizes[k]
     nc = sizes[k + 1][0]
     nf = sizes[k - 1][0] if k > 0 else 0
-    scatter = (16 * n + 16 * nf) if k > 0 else 0  # members + finer g read + finer xp write
+    csr = (e + 4) * nnz + 4 * (n + 1)
+    fin = 8 if k == 0 else e
+    scatter = (16 * n + 2 * e * nf) if k > 0 else 0  # members + finer g read + finer xp write
     if n >= STREAM_MIN:
-        down = (12 * nnz + 4 * (n + 1) + 24 * n) + (8 * n + 40 * nc)  # residual, restriction (+ g_c)
+        down = (csr + (fin + 2 * e) * n) + (e * n + (16 + 3 * e) * nc)  # residual, restriction (+ g_c)
     else:
-        down = 12 * nnz + 4 * (n + 1) + 16 * n + 16 * nc + 24 * nc  # fused residual + restriction
-    up = 12 * nnz + 4 * (n + 1) + 32 * n + scatter
+        down = csr + (fin + e) * n + (16 + 3 * e) * nc  # fused residual + restriction
+    up = csr + 4 * e * n + scatter
     return down + up
 
 
-def iteration_bytes(sizes, method):
+def iteration_bytes(sizes, method, e):
     """Algorithmic bytes of one Krylov iteration (V-cycle + outer kernels)."""
-    vc = sum(level_bytes(k, sizes) for k in range(len(sizes) - 1))
+    vc = sum(level_bytes(k, sizes, e) for k in range(len(sizes) - 1))
     m = sizes[-1][0]
-    vc += 8 * m * m + 16 * m + (16 * m + 16 * sizes[-2][0] if len(sizes) > 1 else 0)
+    vc += 8 * m * m + 2 * e * m + (16 * m + 2 * e * sizes[-2][0] if len(sizes) > 1 else 0)
     n, nnz = sizes[0]
+    vc += (8 - e) * n  # level-0 result in double
     spmv = 12 * nnz + 4 * (n + 1) + 16 * n
     if method == "pcg":
-        # spmv+dot, update (x,r,p,q,dinv read; x,r,g write), (r,z) in the V-cycle, direction (z,p read; p write)
-        return vc + spmv + 8 * n + 64 * n + 24 * n
+        # spmv+dot, update (x,r,p,q,dinv read; x,r write; g write), (r,z) in the V-cycle, direction (z,p read; p write)
+        return vc + spmv + 8 * n + 56 * n + e * n + 24 * n
     # BiCGStab: 2 V-cycles (+ D^{-1} scaling of their inputs), 2 SpMVs, s, update, direction
-    return 2 * vc + 2 * 24 * n + 2 * spmv + 24 * n + 72 * n + 32 * n
+    return 2 * vc + 2 * (16 + e) * n + 2 * spmv + 24 * n + 72 * n + 32 * n
 
 
 def cpu_baseline(a, b, spec, gpu_iters, budget_s=25.0):
@@ -135,6 +142,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="poisson3d_128")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--precond", choices=["fp64", "fp32"], default=None,
+                    help="preconditioner precision (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="no HIP events in the timed region (roofline fields are then null)")
@@ -162,7 +171,9 @@ def main():
     A = hemamg.DeviceCSR.from_host(a)
     b = torch.from_numpy(b_host).cuda()
     x = torch.zeros_like(b)
-    params = hemamg.amg_params_default()
+    precond = args.precond or spec["precond"]
+    params = hemamg.amg_params_default(precond_fp32=int(precond == "fp32"))
+    esz = 4 if precond == "fp32" else 8
     mcode = hemamg.PCG if method == "pcg" else hemamg.BICGSTAB
     torch.cuda.synchronize()
 
@@ -211,9 +222,9 @@ def main():
     iters = recs[-1]["iters"]
     setup_ms = float(np.median([r["setup_ms"] for r in recs]))
     solve_ms = float(np.median([r["solve_ms"] for r in recs]))
-    it_bytes = iteration_bytes(sizes, method)
-    kb = kernel_bytes(sizes)
-    names = {0: "k_stream_post (level 0)", 1: "k_stream_resid (level 0)", 2: "k_stream_spmv_dot (outer SpMV)"}
+    it_bytes = iteration_bytes(sizes, method, esz)
+    kb = kernel_bytes(sizes, esz, method)
+    names = {0: "k_vc_post (level 0)", 1: "k_vc_resid (level 0)", 2: "k_stream_spmv_dot (outer SpMV)"}
     kernels = {}
     for k, (c, ms) in kern_tot.items():
         if c:
@@ -234,10 +245,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if precond == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "desc": spec["desc"], "n": a.n, "nnz": a.nnz, "rtol": spec["rtol"],
-                   "method": method, "levels": len(sizes), "seed": args.seed},
+                   "method": method, "precond": precond, "levels": len(sizes), "seed": args.seed},
         "setup_ms": setup_ms,
         "solve_ms": solve_ms,
         "iters": iters,
@@ -247,7 +258,8 @@ def main():
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": measured_traffic(names[dom].split()[0]), "algorithmic_bytes": kb[dom]},
+                     "traffic": measured_traffic(names[dom].split()[0], args.workload, precond),
+                     "algorithmic_bytes": kb[dom]},
     }
     if args.copy_calibration:
         src = torch.empty(1 << 25, dtype=torch.float64, device="cuda").fill_(1.0)

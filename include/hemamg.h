@@ -67,6 +67,16 @@ typedef struct {
     int32_t true_res_period;  /* recompute b - A x every this many iterations,   *
                                * 0 = only when the recursive residual converges   *
                                * (50)                                             */
+    int32_t precond_fp32;     /* 1: the V-cycle runs in float (level values,
+                               * vectors and sums), the Krylov method and the
+                               * coarsest solve stay in double; needs pre = post
+                               * = 1.  The hierarchy itself is built in double
+                               * either way, so aggregates and coarse operators
+                               * do not change.  0: double throughout (0)         */
+    double stall_ratio;       /* a level of n <= max_dense_rows rows becomes the
+                               * coarsest when coarsening it would keep
+                               * n_c >= stall_ratio * n rows; in (0, 1]; 1 stops
+                               * only when no row is merged (0.9)                 */
 } amg_params;
 
 /* Result of a Krylov solve.  [host] */

@@ -77,11 +77,14 @@ struct Level {
     double* dinv = nullptr;
     int* agg = nullptr;    // to level k+1
     int4* mem = nullptr;   // members of level k+1 rows
-    double* f = nullptr;   // restricted right-hand side (k >= 1)
-    double* g = nullptr;   // D^{-1} f (k >= 1)
-    double* x = nullptr;   // correction (k >= 1)
-    double* xp = nullptr;  // prolongated iterate w D^{-1} f + P e (k < coarsest)
-    double* t = nullptr;   // scratch of the general smoothing path
+    float* v32 = nullptr;     // float copy of the values (single-precision preconditioner)
+    float* dinv32 = nullptr;
+    // V-cycle vectors, of the preconditioner's value type (double or float)
+    void* f = nullptr;    // restricted right-hand side (k >= 1)
+    void* g = nullptr;    // D^{-1} f (k >= 1)
+    void* x = nullptr;    // correction (k >= 1)
+    void* xp = nullptr;   // prolongated iterate w D^{-1} f + P e (k < coarsest)
+    void* t = nullptr;    // residual scratch (CSR-stream levels) / general smoothing path
     int lpr = 4;
 
     LevelView view() const {
@@ -123,7 +126,8 @@ struct amg_hier {
     // Krylov workspace (allocated on first solve)
     double *r = nullptr, *z = nullptr, *pv[2] = {nullptr, nullptr}, *q = nullptr, *rb = nullptr, *pt = nullptr,
            *sv = nullptr, *st = nullptr, *t = nullptr;
-    double* g0 = nullptr;  // D^{-1} times the level-0 right-hand side of the V-cycle
+    void* g0 = nullptr;  // D^{-1} times the level-0 right-hand side of the V-cycle
+    bool prec32 = false;  // V-cycle in float (values, vectors, accumulation)
     double* S = nullptr;
     double* part = nullptr;
     int* err = nullptr;
@@ -233,7 +237,9 @@ struct SetupWork {
 
     void init(int n, int64_t nnz, DevPool& P, int* err) {
         hw.lowok = P.get<uint8_t>((size_t)nnz);
-        hw.rec = P.get<HemRec>(n);
+        hw.rec_bytes = sizeof(HemRecT<7>) * (size_t)n;
+        hw.rec = P.get<char>(hw.rec_bytes);
+        hw.side = 7;
         hw.lcnt = P.get<int>(n);
         hw.dec = P.get<int>(n);
         hw.wl[0] = P.get<int>(n);
@@ -277,6 +283,10 @@ Pass hem_pass(const Csr& B, SetupWork& W, int t, hipStream_t s, int* err) {
     const int n = B.n;
     HemWork w = W.hw;
     w.mate = W.mate[t];
+    // record side from the average row length, within the record buffer
+    const double avg = n > 0 ? (double)B.nnz / n : 0.0;
+    w.side = avg <= 9.0 ? 7 : (avg <= 20.0 ? 15 : 31);
+    while (w.side > 7 && (size_t)(w.side + 1) * 8 * (size_t)n > w.rec_bytes) w.side = (w.side + 1) / 2 - 1;
     HIPCHK(hipMemsetAsync(w.cnt, 0, 8 * sizeof(int), s));
     launch_hem_init(n, B.rp, B.ci, B.v, w, s);
     if (n <= W.hem_small) {
@@ -387,77 +397,136 @@ void timed_end(amg_hier* h, int cls, hipStream_t s) {
 // Whether the level-0 postsmoothing can run as a separate step (part 2).
 bool vcycle_splits(const amg_hier* h) { return h->lev.size() > 1 && h->p.pre == 1 && h->p.post == 1; }
 
-// Algorithm 1, z = V(r) from a zero initial guess, on every level.  g0, if
-// given, already holds D^{-1} r.  dot_slot >= 0 also stores (r, z) there.
-// part 0 runs the whole cycle; when vcycle_splits(), part 1 runs everything
-// but the level-0 postsmoothing (and the dot) and part 2 runs only those.
-void run_vcycle(amg_hier* h, const double* r, double* z, hipStream_t s, const double* g0 = nullptr,
-                int dot_slot = -1, int part = 0) {
-    if (part != 0 && !vcycle_splits(h)) {
-        if (part == 2) return;
-        part = 0;
-    }
+template <class T>
+VLevel<T> vlevel(const Level& L);
+template <>
+VLevel<double> vlevel<double>(const Level& L) {
+    return VLevel<double>{L.n, L.rp, L.ci, L.v, L.dinv, L.mem, L.lpr};
+}
+template <>
+VLevel<float> vlevel<float>(const Level& L) {
+    return VLevel<float>{L.n, L.rp, L.ci, L.v32, L.dinv32, L.mem, L.lpr};
+}
+template <class T>
+const T* dinv_of(const Level& L);
+template <>
+const double* dinv_of<double>(const Level& L) {
+    return L.dinv;
+}
+template <>
+const float* dinv_of<float>(const Level& L) {
+    return L.dinv32;
+}
+
+// Algorithm 1 with one pre- and one post-sweep, in value type T.  r and z are
+// double; g0 (T), if given, already holds D^{-1} r.  dot_slot >= 0 also stores
+// (r, z) there.  part 0 runs the whole cycle; part 1 everything but the
+// level-0 postsmoothing (and the dot); part 2 only those.
+template <class T>
+void run_vcycle_t(amg_hier* h, const double* r, double* z, hipStream_t s, const T* g0, int dot_slot, int part) {
     const int L = (int)h->lev.size() - 1;
-    const double w = h->p.omega;
+    const T w = T(h->p.omega);
     const Reducer R = h->reducer();
-    if (L == 0) {
-        launch_dense_apply(h->n_coarse, h->ainv_t, r, z, nullptr, s);
-        if (dot_slot >= 0) launch_dot(h->lev[0].n, r, z, R, dot_slot, s);
+    const Level& L0 = h->lev[0];
+    if (L == 0) {  // a single level is solved directly
+        if (part == 2) return;
+        vc_dense_apply<double, double, double>(h->n_coarse, h->ainv_t, r, z, nullptr, s);
+        if (dot_slot >= 0) launch_dot(L0.n, r, z, R, dot_slot, s);
         return;
     }
-    std::vector<const double*> f(L + 1), g(L + 1);
-    std::vector<double*> x(L + 1);
-    f[0] = r;
-    x[0] = z;
-    for (int k = 1; k <= L; ++k) {
-        f[k] = h->lev[k].f;
-        g[k] = h->lev[k].g;
-        x[k] = h->lev[k].x;
+    auto vec = [](void* p) { return static_cast<T*>(p); };
+    if (!g0) {
+        if (part != 2) vc_scale_dinv<T>(L0.n, L0.dinv, r, vec(h->g0), s);
+        g0 = vec(h->g0);
     }
-    const bool fused = h->p.pre == 1 && h->p.post == 1;
-    if (fused) {
-        if (!g0) {
-            if (part != 2) launch_scale_dinv(h->lev[0].n, h->lev[0].dinv, r, h->g0, s);
-            g0 = h->g0;
-        }
-        g[0] = g0;
-    }
+    auto gk = [&](int k) { return k == 0 ? g0 : vec(h->lev[k].g); };
     auto scatter_to = [&](int k) {  // into level k from level k+1
-        return Scatter{h->lev[k].mem, g[k], h->lev[k].xp, w};
+        return ScatterT<T>{h->lev[k].mem, gk(k), vec(h->lev[k].xp), w};
     };
     if (part == 2) {  // level-0 postsmoothing (+ (r, z)) only
-        const Level& L0 = h->lev[0];
+        const VLevel<T> V = vlevel<T>(L0);
         timed_begin(h, 0, s);
         if (L0.n >= h->stream_min) {
-            launch_stream_post(L0.view(), L0.xp, g[0], w, z, r, dot_slot >= 0 ? &R : nullptr, dot_slot, nullptr, s);
+            vc_stream_post<T, double>(V, vec(L0.xp), g0, w, z, r, dot_slot >= 0 ? &R : nullptr, dot_slot, nullptr, s);
         } else {
-            launch_prolong_post(L0.view(), L0.xp, g[0], w, z, nullptr, s);
+            vc_prolong_post<T, double>(V, vec(L0.xp), g0, w, z, nullptr, s);
             if (dot_slot >= 0) launch_dot(L0.n, r, z, R, dot_slot, s);
         }
         timed_end(h, 0, s);
         return;
     }
+    // down-sweep
     for (int k = 0; k < L; ++k) {
         const Level& Lk = h->lev[k];
         const Level& Lc = h->lev[k + 1];
-        const LevelView V = Lk.view();
-        const int nc = Lc.n;
-        if (fused) {
-            if (k == 0) timed_begin(h, 1, s);
-            if (Lk.n >= h->stream_min) {
-                launch_stream_resid(V, f[k], g[k], w, Lk.t, s);
-                if (k == 0) timed_end(h, 1, s);
-                launch_restrict(nc, Lk.mem, Lk.t, Lc.dinv, Lc.f, Lc.g, s);
-            } else {
-                launch_resid_restrict(V, nc, f[k], g[k], w, Lc.dinv, Lc.f, Lc.g, s);
-                if (k == 0) timed_end(h, 1, s);
-            }
+        const VLevel<T> V = vlevel<T>(Lk);
+        T* fc = vec(Lc.f);
+        T* gc = vec(Lc.g);
+        if (k == 0) timed_begin(h, 1, s);
+        if (Lk.n >= h->stream_min) {
+            if (k == 0) vc_stream_resid<T, double>(V, r, g0, w, vec(Lk.t), s);
+            else vc_stream_resid<T, T>(V, vec(Lk.f), gk(k), w, vec(Lk.t), s);
+            if (k == 0) timed_end(h, 1, s);
+            vc_restrict<T>(Lc.n, Lk.mem, vec(Lk.t), dinv_of<T>(Lc), fc, gc, s);
+        } else {
+            if (k == 0) vc_resid_restrict<T, double>(V, Lc.n, r, g0, w, dinv_of<T>(Lc), fc, gc, s);
+            else vc_resid_restrict<T, T>(V, Lc.n, vec(Lk.f), gk(k), w, dinv_of<T>(Lc), fc, gc, s);
+            if (k == 0) timed_end(h, 1, s);
+        }
+    }
+    // coarsest, then the up-sweep: each level's result is scattered to the
+    // finer level's prolongated iterate, which that level's postsmoothing reads
+    {
+        const ScatterT<T> sc = scatter_to(L - 1);
+        vc_dense_apply<T, T, T>(h->n_coarse, h->ainv_t, vec(h->lev[L].f), vec(h->lev[L].x), &sc, s);
+    }
+    bool dot_done = false;
+    for (int k = L - 1; k >= (part == 1 ? 1 : 0); --k) {
+        const Level& Lk = h->lev[k];
+        const VLevel<T> V = vlevel<T>(Lk);
+        if (k > 0) {
+            const ScatterT<T> sc = scatter_to(k - 1);
+            if (Lk.n >= h->stream_min)
+                vc_stream_post<T, T>(V, vec(Lk.xp), gk(k), w, vec(Lk.x), nullptr, nullptr, -1, &sc, s);
+            else
+                vc_prolong_post<T, T>(V, vec(Lk.xp), gk(k), w, vec(Lk.x), &sc, s);
             continue;
         }
+        timed_begin(h, 0, s);
+        if (Lk.n >= h->stream_min) {
+            vc_stream_post<T, double>(V, vec(Lk.xp), g0, w, z, r, dot_slot >= 0 ? &R : nullptr, dot_slot, nullptr, s);
+            dot_done = dot_slot >= 0;
+        } else {
+            vc_prolong_post<T, double>(V, vec(Lk.xp), g0, w, z, nullptr, s);
+        }
+        timed_end(h, 0, s);
+    }
+    if (part == 1) return;
+    if (dot_slot >= 0 && !dot_done) launch_dot(L0.n, r, z, R, dot_slot, s);
+}
+
+// General path (any sweep counts, double only): damped Jacobi sweeps with
+// explicit iterates, residual + restriction, prolongation, postsmoothing.
+void run_vcycle_general(amg_hier* h, const double* r, double* z, hipStream_t s, int dot_slot) {
+    const int L = (int)h->lev.size() - 1;
+    const double w = h->p.omega;
+    const Reducer R = h->reducer();
+    auto dv = [](void* p) { return static_cast<double*>(p); };
+    std::vector<const double*> f(L + 1);
+    std::vector<double*> x(L + 1);
+    f[0] = r;
+    x[0] = z;
+    for (int k = 1; k <= L; ++k) {
+        f[k] = dv(h->lev[k].f);
+        x[k] = dv(h->lev[k].x);
+    }
+    for (int k = 0; k < L; ++k) {
+        const Level& Lk = h->lev[k];
+        const LevelView V = Lk.view();
         const double* xs = nullptr;
         if (h->p.pre > 0) {
             double* a = x[k];
-            double* b = Lk.t;
+            double* b = dv(Lk.t);
             launch_jacobi_zero(Lk.n, Lk.dinv, f[k], w, a, s);
             for (int it = 1; it < h->p.pre; ++it) {
                 launch_jacobi(V, f[k], a, w, b, s);
@@ -468,47 +537,45 @@ void run_vcycle(amg_hier* h, const double* r, double* z, hipStream_t s, const do
         } else {
             launch_scale_zero(Lk.n, x[k], s);
         }
-        launch_resid_restrict_x(V, nc, f[k], xs, const_cast<double*>(f[k + 1]), s);
+        launch_resid_restrict_x(V, h->lev[k + 1].n, f[k], xs, const_cast<double*>(f[k + 1]), s);
     }
-    // up-sweep: each level's result is scattered to the finer level's
-    // prolongated iterate, which that level's postsmoothing then reads
-    bool dot_done = false;
-    if (fused) {
-        const Scatter sc = scatter_to(L - 1);
-        launch_dense_apply(h->n_coarse, h->ainv_t, f[L], x[L], &sc, s);
-        for (int k = L - 1; k >= (part == 1 ? 1 : 0); --k) {
-            const Level& Lk = h->lev[k];
-            const LevelView V = Lk.view();
-            Scatter sc_k{};
-            if (k > 0) sc_k = scatter_to(k - 1);
-            const Scatter* psc = k > 0 ? &sc_k : nullptr;
-            if (k == 0) timed_begin(h, 0, s);
-            if (Lk.n >= h->stream_min) {
-                const bool with_dot = k == 0 && dot_slot >= 0;
-                launch_stream_post(V, Lk.xp, g[k], w, x[k], f[k], with_dot ? &R : nullptr, dot_slot, psc, s);
-                dot_done = with_dot;
-            } else {
-                launch_prolong_post(V, Lk.xp, g[k], w, x[k], psc, s);
-            }
-            if (k == 0) timed_end(h, 0, s);
+    vc_dense_apply<double, double, double>(h->n_coarse, h->ainv_t, f[L], x[L], nullptr, s);
+    for (int k = L - 1; k >= 0; --k) {
+        const Level& Lk = h->lev[k];
+        const LevelView V = Lk.view();
+        launch_prolong_add(Lk.n, Lk.agg, x[k + 1], x[k], s);
+        double* a = x[k];
+        double* b = dv(Lk.t);
+        for (int it = 0; it < h->p.post; ++it) {
+            launch_jacobi(V, f[k], a, w, b, s);
+            std::swap(a, b);
         }
-    } else {
-        launch_dense_apply(h->n_coarse, h->ainv_t, f[L], x[L], nullptr, s);
-        for (int k = L - 1; k >= 0; --k) {
-            const Level& Lk = h->lev[k];
-            const LevelView V = Lk.view();
-            launch_prolong_add(Lk.n, Lk.agg, x[k + 1], x[k], s);
-            double* a = x[k];
-            double* b = Lk.t;
-            for (int it = 0; it < h->p.post; ++it) {
-                launch_jacobi(V, f[k], a, w, b, s);
-                std::swap(a, b);
-            }
-            if (a != x[k]) HIPCHK(hipMemcpyAsync(x[k], a, sizeof(double) * Lk.n, hipMemcpyDeviceToDevice, s));
-        }
+        if (a != x[k]) HIPCHK(hipMemcpyAsync(x[k], a, sizeof(double) * Lk.n, hipMemcpyDeviceToDevice, s));
     }
-    if (part == 1) return;
-    if (dot_slot >= 0 && !dot_done) launch_dot(h->lev[0].n, r, z, R, dot_slot, s);
+    if (dot_slot >= 0) launch_dot(h->lev[0].n, r, z, R, dot_slot, s);
+}
+
+// z = V(r) (Algorithm 1).  g0, if given, already holds D^{-1} r in the
+// preconditioner's value type.
+void run_vcycle(amg_hier* h, const double* r, double* z, hipStream_t s, const void* g0 = nullptr, int dot_slot = -1,
+                int part = 0) {
+    if (part != 0 && !vcycle_splits(h)) {
+        if (part == 2) return;
+        part = 0;
+    }
+    if (!(h->p.pre == 1 && h->p.post == 1)) {
+        if (h->lev.size() == 1) {
+            vc_dense_apply<double, double, double>(h->n_coarse, h->ainv_t, r, z, nullptr, s);
+            if (dot_slot >= 0) launch_dot(h->lev[0].n, r, z, h->reducer(), dot_slot, s);
+            return;
+        }
+        run_vcycle_general(h, r, z, s, dot_slot);
+        return;
+    }
+    if (h->prec32)
+        run_vcycle_t<float>(h, r, z, s, static_cast<const float*>(g0), dot_slot, part);
+    else
+        run_vcycle_t<double>(h, r, z, s, static_cast<const double*>(g0), dot_slot, part);
 }
 
 void read_slots(amg_hier* h, hipStream_t s) {
@@ -535,7 +602,7 @@ void pcg_iter_a(amg_hier* h, double* x, int pc, hipStream_t s) {
     const int cur = pc ? S_RHO1 : S_RHO0, nxt = pc ? S_RHO0 : S_RHO1;
     double* p = h->pv[pc];
     spmv_dot_timed(h, A0.view(), p, h->q, p, S_PQ, s);
-    launch_cg_update(A0.n, x, h->r, p, h->q, A0.dinv, h->g0, R, cur, S_PQ, S_RR, s);
+    launch_cg_update(A0.n, x, h->r, p, h->q, A0.dinv, h->g0, h->prec32, R, cur, S_PQ, S_RR, s);
     run_vcycle(h, h->r, h->z, s, h->g0, nxt, 1);
 }
 
@@ -609,7 +676,7 @@ amg_status pcg(amg_hier* h, const double* b, double* x, double rtol, int maxit, 
     const bool graphs = h->use_graphs && !h->tim[1].on && !h->tim[2].on;
     double* S = h->S_host;
     launch_dot(n, b, b, R, S_BB, s);
-    launch_residual(A, b, x, h->r, h->g0, R, S_RR, s);
+    launch_residual(A, b, x, h->r, h->g0, h->prec32, R, S_RR, s);
     read_slots(h, s);
     const double nb = std::sqrt(S[S_BB]);
     info.iters = 0;
@@ -637,7 +704,7 @@ amg_status pcg(amg_hier* h, const double* b, double* x, double rtol, int maxit, 
         info.rel_res = rel;
         if (!std::isfinite(rel)) return AMG_EBREAKDOWN;
         if (rel <= rtol || (period > 0 && it % period == 0)) {
-            launch_residual(A, b, x, h->r, h->g0, R, S_TRR, s);  // residual replacement
+            launch_residual(A, b, x, h->r, h->g0, h->prec32, R, S_TRR, s);  // residual replacement
             read_slots(h, s);
             const double tr = std::sqrt(S[S_TRR]) / nb;
             info.true_rel_res = tr;
@@ -661,7 +728,7 @@ amg_status bicgstab(amg_hier* h, const double* b, double* x, double rtol, int ma
     const int period = h->p.true_res_period;
     double* S = h->S_host;
     launch_dot(n, b, b, R, S_BB, s);
-    launch_residual(A, b, x, h->r, nullptr, R, S_RR, s);
+    launch_residual(A, b, x, h->r, nullptr, false, R, S_RR, s);
     read_slots(h, s);
     const double nb = std::sqrt(S[S_BB]);
     info.iters = 0;
@@ -699,7 +766,7 @@ amg_status bicgstab(amg_hier* h, const double* b, double* x, double rtol, int ma
         info.rel_res = rel;
         if (!std::isfinite(rel)) return AMG_EBREAKDOWN;
         if (rel <= rtol || (period > 0 && it % period == 0)) {
-            launch_residual(A, b, x, h->r, nullptr, R, S_TRR, s);
+            launch_residual(A, b, x, h->r, nullptr, false, R, S_TRR, s);
             read_slots(h, s);
             const double tr = std::sqrt(S[S_TRR]) / nb;
             info.true_rel_res = tr;
@@ -728,6 +795,10 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     if (p.pre < 0 || p.pre > 8 || p.post < 0 || p.post > 8) raise(AMG_EINVAL, "pre/post sweeps must be in 0..8");
     if (!std::isfinite(p.omega)) raise(AMG_EINVAL, "omega must be finite");
     if (p.true_res_period < 0) raise(AMG_EINVAL, "true_res_period must be >= 0");
+    if (p.precond_fp32 != 0 && p.precond_fp32 != 1) raise(AMG_EINVAL, "precond_fp32 must be 0 or 1");
+    if (!(p.stall_ratio > 0.0 && p.stall_ratio <= 1.0)) raise(AMG_EINVAL, "stall_ratio must be in (0, 1]");
+    if (p.precond_fp32 && !(p.pre == 1 && p.post == 1))
+        raise(AMG_EINVAL, "a float preconditioner needs one pre- and one post-sweep");
     const amg_csr& A = *Ain;
     if (A.n <= 0) raise(AMG_EINVAL, "n must be positive");
     if (A.nnz < A.n || A.nnz >= (int64_t(1) << 31)) raise(AMG_EINVAL, "nnz must be in [n, 2^31)");
@@ -805,6 +876,10 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
             HIPCHK(hipStreamSynchronize(s));
             break;
         }
+        if ((double)Cf.n >= p.stall_ratio * (double)F.n && F.n <= p.max_dense_rows) {
+            HIPCHK(hipStreamSynchronize(s));  // poor progress on a level the dense solve takes
+            break;
+        }
         F.agg = agg;
         F.mem = mem;
         Level C;
@@ -842,21 +917,29 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
         }
         tmp.release();
     }
-    // per-level work vectors
+    // per-level work vectors, float copies of the values for a float V-cycle
     const bool fused = p.pre == 1 && p.post == 1;
+    h->prec32 = p.precond_fp32 != 0;
+    const size_t esz = h->prec32 ? sizeof(float) : sizeof(double);
     if (const char* e = getenv("HEMAMG_STREAM_MIN")) h->stream_min = atoi(e);  // tuning sweeps
     if (const char* e = getenv("HEMAMG_GRAPHS")) h->use_graphs = atoi(e) != 0;
     for (size_t k = 0; k < h->lev.size(); ++k) {
         Level& L = h->lev[k];
         if (k > 0) {
-            L.f = P.get<double>(L.n);
-            L.g = P.get<double>(L.n);
-            L.x = P.get<double>(L.n);
+            L.f = P.get<char>(esz * L.n);
+            L.g = P.get<char>(esz * L.n);
+            L.x = P.get<char>(esz * L.n);
         }
-        if (fused && k + 1 < h->lev.size()) L.xp = P.get<double>(L.n);
-        if (!fused || L.n >= h->stream_min) L.t = P.get<double>(L.n);
+        if (fused && k + 1 < h->lev.size()) L.xp = P.get<char>(esz * L.n);
+        if (!fused || L.n >= h->stream_min) L.t = P.get<char>(esz * L.n);
+        if (h->prec32) {
+            L.v32 = P.get<float>((size_t)L.nnz);
+            L.dinv32 = P.get<float>(L.n);
+            launch_cast_f32(L.nnz, L.v, L.v32, s);
+            launch_cast_f32(L.n, L.dinv, L.dinv32, s);
+        }
     }
-    h->g0 = P.get<double>(h->lev[0].n);
+    h->g0 = P.get<char>(esz * h->lev[0].n);
     h->S = P.get<double>(S_COUNT);
     h->part = P.get<double>(2 * (size_t)kRedBlocks);
     HIPCHK(hipMemsetAsync(h->S, 0, S_COUNT * sizeof(double), s));
@@ -882,6 +965,8 @@ amg_status amg_params_default(amg_params* p) {
     p->pre = 1;
     p->post = 1;
     p->true_res_period = 50;
+    p->precond_fp32 = 0;
+    p->stall_ratio = 0.9;
     return AMG_OK;
 }
 

@@ -26,23 +26,26 @@ void launch_validate(int n, int64_t nnz, const int* rp, const int* ci, const dou
                      hipStream_t s);
 void launch_dinv(int n, const int* rp, const int* ci, const double* v, double* dinv, int* err, hipStream_t s);
 
-// Per-vertex adjacency record of a matching pass (64 bytes): up to kRecSide
-// higher neighbours j (a_uj non-zero) by |a_uj| descending, column ascending
-// on ties, and up to kRecSide lower edge-neighbours x (row x stores a
-// non-zero a_xu) ascending.  Vertices with more use the CSR rows instead.
-constexpr int kRecSide = 7;
+// Per-vertex adjacency record of a matching pass (64, 128 or 256 bytes for
+// SIDE = 7, 15, 31): up to SIDE higher neighbours j (a_uj non-zero) by |a_uj|
+// descending, column ascending on ties, and up to SIDE lower edge-neighbours
+// x (row x stores a non-zero a_xu) ascending.  Vertices with more use the CSR
+// rows instead.
 constexpr int kRecOverflow = 1 << 16;
-struct alignas(64) HemRec {
+template <int SIDE>
+struct alignas(4 * (SIDE + 1) * 2) HemRecT {
     int hdr;  // #higher | #lower << 8 | kRecOverflow
-    int h[kRecSide];
-    int l[kRecSide];
+    int h[SIDE];
+    int l[SIDE];
     int pad;
 };
+static_assert(sizeof(HemRecT<7>) == 64 && sizeof(HemRecT<15>) == 128 && sizeof(HemRecT<31>) == 256, "record");
 
-// Matching pass state (Algorithm 2 as rounds of locally dominant edges).
 struct HemWork {
     uint8_t* lowok;   // [nnz] entry (v,u), u < v, is an edge (row u stores a non-zero a_uv)
-    HemRec* rec;      // [n] adjacency records
+    void* rec;        // adjacency records, rec_bytes of room
+    size_t rec_bytes;
+    int side;         // record side of the current pass: 7, 15 or 31
     int* lcnt;        // [n] undecided lower neighbours
     int* dec;         // [n] round in which the vertex was decided
     int* mate;        // [n] partner or -1
@@ -104,12 +107,13 @@ struct Reducer {
 
 // A coarse level's finished value zc of row i becomes the finer level's
 // prolongated iterate on i's members m: xpf[m] = w gf[m] + zc.
-struct Scatter {
+template <class T>
+struct ScatterT {
     const int4* __restrict__ mem;
-    const double* __restrict__ gf;
-    double* __restrict__ xpf;
-    double w;
-    __device__ __forceinline__ void operator()(int i, double zc) const {
+    const T* __restrict__ gf;
+    T* __restrict__ xpf;
+    T w;
+    __device__ __forceinline__ void operator()(int i, T zc) const {
         const int4 m = mem[i];
         xpf[m.x] = w * gf[m.x] + zc;
         if (m.y >= 0) xpf[m.y] = w * gf[m.y] + zc;
@@ -118,47 +122,68 @@ struct Scatter {
     }
 };
 
-void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t s);
+// V-cycle view of a level with values of type T (double, or the float copy).
+template <class T>
+struct VLevel {
+    int n;
+    const int* rp;
+    const int* ci;
+    const T* v;
+    const T* dinv;
+    const int4* mem;  // members of level k+1 rows
+    int lpr;
+};
+
+// ---- V-cycle kernels (k_vcycle.hip), T = double or float -------------------
 // Every level keeps g = D^{-1} f next to its right-hand side f; the kernel
-// that produces f also writes g.
-// Large levels (CSR-stream): r = f - w A g, then f_c = P^T r and g_c; the
-// prolongation + postsmoothing z = x + w (g - D^{-1} A x), x = w g + P e,
-// optionally with block partials of (f, z) reduced into slot `slot`.
-void launch_stream_resid(const LevelView& L, const double* f, const double* g, double w, double* r, hipStream_t s);
-void launch_restrict(int nc, const int4* mem, const double* r, const double* dinv_c, double* fc, double* gc,
+// that produces f also writes g.  Large levels (CSR-stream): r = f - w A g,
+// then f_c = P^T r and g_c; postsmoothing from the prolongated iterate xp:
+// z = xp + w (g - D^{-1} A xp), with (f, z) reduced into `slot` when R is
+// given and z scattered into the finer level's xp when sc is given.
+template <class T, class TIN>
+void vc_stream_resid(const VLevel<T>& L, const TIN* f, const T* g, T w, T* r, hipStream_t s);
+template <class T>
+void vc_restrict(int nc, const int4* mem, const T* r, const T* dinv_c, T* fc, T* gc, hipStream_t s);
+template <class T, class TOUT>
+void vc_stream_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, const double* f, const Reducer* R,
+                    int slot, const ScatterT<T>* sc, hipStream_t s);
+// Small levels: the same operations with the restriction fused.
+template <class T, class TIN>
+void vc_resid_restrict(const VLevel<T>& L, int nc, const TIN* f, const T* g, T w, const T* dinv_c, T* fc, T* gc,
+                       hipStream_t s);
+template <class T, class TOUT>
+void vc_prolong_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, const ScatterT<T>* sc,
                      hipStream_t s);
-struct Reducer;
-struct Scatter;
-// Postsmoothing from the prolongated iterate xp = w g + P e: z = xp + w (g -
-// D^{-1} A xp).  With R, (f, z) goes to slot; with sc, z (a coarse level's
-// result) is scattered to the finer level's prolongated iterate.
-void launch_stream_post(const LevelView& L, const double* xp, const double* g, double w, double* z, const double* f,
-                        const Reducer* R, int slot, const Scatter* sc, hipStream_t s);
-// Small levels (lane groups per row), same operations with the restriction fused.
-void launch_resid_restrict(const LevelView& L, int nc, const double* f, const double* g, double w,
-                           const double* dinv_c, double* fc, double* gc, hipStream_t s);
-void launch_prolong_post(const LevelView& L, const double* xp, const double* g, double w, double* z,
-                         const Scatter* sc, hipStream_t s);
-void launch_scale_dinv(int n, const double* dinv, const double* f, double* g, hipStream_t s);
+// g = D^{-1} f (computed in double, stored as T)
+template <class T>
+void vc_scale_dinv(int n, const double* dinv, const double* f, T* g, hipStream_t s);
+// Coarsest level x = A_L^{-1} f in double (explicit inverse, column-major).
+template <class T, class TIN, class TOUT>
+void vc_dense_apply(int n, const double* ainv_t, const TIN* f, TOUT* x, const ScatterT<T>* sc, hipStream_t s);
+
+// S[slot0] (and S[slot1] when nv = 2) = fixed-order sums of the partials.
+void launch_cast_f32(int64_t n, const double* a, float* b, hipStream_t s);
+void launch_finish(int nparts, int nv, const Reducer& R, int slot0, int slot1, hipStream_t s);
+
+void launch_spmv(const LevelView& L, const double* x, double* y, hipStream_t s);
 // General smoothing path.
 void launch_jacobi_zero(int n, const double* dinv, const double* f, double w, double* x, hipStream_t s);
 void launch_jacobi(const LevelView& L, const double* f, const double* x, double w, double* xo, hipStream_t s);
 void launch_resid_restrict_x(const LevelView& L, int nc, const double* f, const double* x, double* fc,
                              hipStream_t s);
 void launch_prolong_add(int n, const int* agg, const double* e, double* x, hipStream_t s);
-void launch_dense_apply(int n, const double* ainv_t, const double* f, double* x, const Scatter* sc, hipStream_t s);
 
 // Krylov vector kernels.  Slots index Reducer::S.
-// r = b - A x, (r, r); gout (may be null) receives D^{-1} r.
-void launch_residual(const LevelView& A, const double* b, const double* x, double* r, double* gout, const Reducer& R,
-                     int slot_rr, hipStream_t s);
+// r = b - A x, (r, r); gout (may be null) receives D^{-1} r, as float when g32.
+void launch_residual(const LevelView& A, const double* b, const double* x, double* r, void* gout, bool g32,
+                     const Reducer& R, int slot_rr, hipStream_t s);
 void launch_dot(int n, const double* a, const double* b, const Reducer& R, int slot, hipStream_t s);
 void launch_spmv_dot(const LevelView& A, const double* p, double* q, const double* d, const Reducer& R, int slot,
                      hipStream_t s);
 void launch_spmv_dot2(const LevelView& A, const double* p, double* t, const double* sv, const Reducer& R, int slot_tt,
                       int slot_ts, hipStream_t s);
-void launch_cg_update(int n, double* x, double* r, const double* p, const double* q, const double* dinv, double* gout,
-                      const Reducer& R, int slot_rho, int slot_pq, int slot_rr, hipStream_t s);
+void launch_cg_update(int n, double* x, double* r, const double* p, const double* q, const double* dinv, void* gout,
+                      bool g32, const Reducer& R, int slot_rho, int slot_pq, int slot_rr, hipStream_t s);
 void launch_cg_dir(int n, const double* z, const double* p, double* pn, const double* S, int slot_new, int slot_old,
                    hipStream_t s);
 void launch_bicg_s(int n, const double* r, const double* v, double* sv, const double* S, int slot_rho, int slot_rv,

@@ -107,9 +107,10 @@ __device__ __forceinline__ int find_col(const int* __restrict__ ci, int lo, int 
 // counters: cnt[0..2] worklist sizes (ring of 3), cnt[5] sum over rows of
 // (#upper - #lower) entries, cnt[6] the number of rounds that had work,
 // cnt[7] set when the single-workgroup pass hit its round limit.
+template <int SIDE>
 __global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                  const double* __restrict__ v, uint8_t* __restrict__ lowok,
-                                                 HemRec* __restrict__ rec, int* __restrict__ lcnt,
+                                                 HemRecT<SIDE>* __restrict__ rec, int* __restrict__ lcnt,
                                                  int* __restrict__ dec, int* __restrict__ mate,
                                                  int* __restrict__ wl0, int* cnt, int* err) {
     const int y = blockIdx.x * BS + threadIdx.x;
@@ -118,10 +119,10 @@ __global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ 
     mate[y] = -1;
     int c = 0, nlow = 0, nup = 0, bad = 0, nh = 0, nl = 0;
     bool ovf = false;
-    int hj[kRecSide], lx[kRecSide];
-    double hw[kRecSide];
+    int hj[SIDE], lx[SIDE];
+    double hw[SIDE];
 #pragma unroll
-    for (int t = 0; t < kRecSide; ++t) {
+    for (int t = 0; t < SIDE; ++t) {
         hj[t] = -1;
         lx[t] = -1;
         hw[t] = 0.0;
@@ -135,9 +136,9 @@ __global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ 
             if (pos < 0) bad = 1;
             else if (v[pos] != 0.0) ok = 1;
             if (ok) {  // lower edge-neighbour, columns arrive ascending
-                if (nl < kRecSide) {
+                if (nl < SIDE) {
 #pragma unroll
-                    for (int t = 0; t < kRecSide; ++t)
+                    for (int t = 0; t < SIDE; ++t)
                         if (t == nl) lx[t] = u;
                     ++nl;
                 } else {
@@ -148,20 +149,20 @@ __global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ 
             ++nup;
             const double a = v[k];
             if (a != 0.0) {  // higher neighbour: keep sorted by |a| descending, column ascending
-                if (nh < kRecSide) {
+                if (nh < SIDE) {
                     const double w = fabs(a);
                     int pos = 0;
 #pragma unroll
-                    for (int t = 0; t < kRecSide; ++t)
+                    for (int t = 0; t < SIDE; ++t)
                         if (t < nh && hw[t] >= w) pos = t + 1;
 #pragma unroll
-                    for (int t = kRecSide - 1; t > 0; --t)
+                    for (int t = SIDE - 1; t > 0; --t)
                         if (t > pos && t <= nh) {
                             hw[t] = hw[t - 1];
                             hj[t] = hj[t - 1];
                         }
 #pragma unroll
-                    for (int t = 0; t < kRecSide; ++t)
+                    for (int t = 0; t < SIDE; ++t)
                         if (t == pos) {
                             hw[t] = w;
                             hj[t] = u;
@@ -175,10 +176,10 @@ __global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ 
         lowok[k] = ok;
         c += ok;
     }
-    HemRec R;
+    HemRecT<SIDE> R;
     R.hdr = nh | (nl << 8) | (ovf ? kRecOverflow : 0);
 #pragma unroll
-    for (int t = 0; t < kRecSide; ++t) {
+    for (int t = 0; t < SIDE; ++t) {
         R.h[t] = hj[t];
         R.l[t] = lx[t];
     }
@@ -196,7 +197,7 @@ struct HemState {
     const int* __restrict__ ci;
     const double* __restrict__ v;
     const uint8_t* __restrict__ lowok;
-    const HemRec* __restrict__ rec;
+    const void* __restrict__ rec;  // HemRecT<SIDE>[n]
     int* dec;
     int* mate;
     int* lcnt;
@@ -313,18 +314,18 @@ __device__ __forceinline__ int hem_back(const HemState& S, int r, int w) {
 
 // Counter updates for the higher neighbours listed in a record, all issued
 // before any result is used.
-template <int SCOPE>
-__device__ __forceinline__ void rec_release(const HemState& S, const HemRec& R, int x, const Appender& A) {
+template <int SCOPE, int SIDE>
+__device__ __forceinline__ void rec_release(const HemState& S, const HemRecT<SIDE>& R, int x, const Appender& A) {
     if (R.hdr & kRecOverflow) {
         hem_release<SCOPE>(S, x, A);
         return;
     }
     const int nh = R.hdr & 255;
-    int old[kRecSide];
+    int old[SIDE];
 #pragma unroll
-    for (int t = 0; t < kRecSide; ++t) old[t] = t < nh ? dec_counter<SCOPE>(&S.lcnt[R.h[t]]) : 0;
+    for (int t = 0; t < SIDE; ++t) old[t] = t < nh ? dec_counter<SCOPE>(&S.lcnt[R.h[t]]) : 0;
 #pragma unroll
-    for (int t = 0; t < kRecSide; ++t)
+    for (int t = 0; t < SIDE; ++t)
         if (t < nh && old[t] == 1) A.push(R.h[t]);
 }
 
@@ -333,9 +334,10 @@ __device__ __forceinline__ void rec_release(const HemState& S, const HemRec& R, 
 // list u's higher neighbours in preference order (heaviest first, lowest
 // index on ties) and the target's lower edge-neighbours in ascending order, so
 // "first undecided entry" is the pointer of either side.
-template <int SCOPE>
+template <int SCOPE, int SIDE>
 __device__ __forceinline__ void hem_visit(const HemState& S, int r, int u, const Appender& A) {
-    const HemRec R = S.rec[u];
+    const HemRecT<SIDE>* __restrict__ recs = static_cast<const HemRecT<SIDE>*>(S.rec);
+    const HemRecT<SIDE> R = recs[u];
     const int du = S.dec[u];
     if (du < r) return;  // decided earlier (as a match target): stale entry
     int best = -1;
@@ -343,30 +345,30 @@ __device__ __forceinline__ void hem_visit(const HemState& S, int r, int u, const
         best = hem_best(S, r, u, S.rp[u], S.rp[u + 1]);
     } else {
         const int nh = R.hdr & 255;
-        int d[kRecSide];
+        int d[SIDE];
 #pragma unroll
-        for (int t = 0; t < kRecSide; ++t) d[t] = t < nh ? S.dec[R.h[t]] : -1;
+        for (int t = 0; t < SIDE; ++t) d[t] = t < nh ? S.dec[R.h[t]] : -1;
 #pragma unroll
-        for (int t = kRecSide - 1; t >= 0; --t)
+        for (int t = SIDE - 1; t >= 0; --t)
             if (t < nh && d[t] >= r) best = R.h[t];
     }
     if (best < 0) {  // no undecided neighbour: unaggregated singleton
         S.dec[u] = r;
         S.mate[u] = -1;
-        rec_release<SCOPE>(S, R, u, A);
+        rec_release<SCOPE, SIDE>(S, R, u, A);
         return;
     }
-    const HemRec B = S.rec[best];
+    const HemRecT<SIDE> B = recs[best];
     int back = -1;
     if (B.hdr & kRecOverflow) {
         back = hem_back(S, r, best);
     } else {
         const int nl = (B.hdr >> 8) & 255;
-        int d[kRecSide];
+        int d[SIDE];
 #pragma unroll
-        for (int t = 0; t < kRecSide; ++t) d[t] = t < nl ? S.dec[B.l[t]] : -1;
+        for (int t = 0; t < SIDE; ++t) d[t] = t < nl ? S.dec[B.l[t]] : -1;
 #pragma unroll
-        for (int t = kRecSide - 1; t >= 0; --t)
+        for (int t = SIDE - 1; t >= 0; --t)
             if (t < nl && d[t] >= r) back = B.l[t];
     }
     if (back == u) {  // best points back: mutual, matched
@@ -374,8 +376,8 @@ __device__ __forceinline__ void hem_visit(const HemState& S, int r, int u, const
         S.dec[best] = r;
         S.mate[u] = best;
         S.mate[best] = u;
-        rec_release<SCOPE>(S, R, u, A);
-        rec_release<SCOPE>(S, B, best, A);
+        rec_release<SCOPE, SIDE>(S, R, u, A);
+        rec_release<SCOPE, SIDE>(S, B, best, A);
     } else {
         A.push(u);  // still ready, retry next round
     }
@@ -389,6 +391,7 @@ constexpr int HEM_LCAP1 = 8192;
 
 // One round over the worklist; the decided vertices' neighbours that become
 // ready, and the ready vertices that failed, form the next list.
+template <int SIDE>
 __global__ __launch_bounds__(HEM_BS) void k_hem_round(int r, HemState S, const int* __restrict__ win,
                                                   int* __restrict__ wout, int* cnt, int slot_in, int slot_out,
                                                   int zero_w) {
@@ -403,7 +406,7 @@ __global__ __launch_bounds__(HEM_BS) void k_hem_round(int r, HemState S, const i
     if (m > 0 && blockIdx.x == 0 && threadIdx.x == 0) cnt[6] = r + 1;  // rounds with work
     const Appender A{s_list, &s_cnt, HEM_LCAP, wout, &cnt[slot_out]};
     for (int idx = blockIdx.x * HEM_BS + threadIdx.x; idx < m; idx += gridDim.x * HEM_BS)
-        hem_visit<__HIP_MEMORY_SCOPE_AGENT>(S, r, win[idx], A);
+        hem_visit<__HIP_MEMORY_SCOPE_AGENT, SIDE>(S, r, win[idx], A);
     __syncthreads();
     const int k = min(s_cnt, HEM_LCAP);
     if (threadIdx.x == 0 && k > 0) s_base = atomicAdd(&cnt[slot_out], k);
@@ -414,6 +417,7 @@ __global__ __launch_bounds__(HEM_BS) void k_hem_round(int r, HemState S, const i
 // Small matrices: one workgroup runs every round, separated by barriers.
 // Each round decides at least the smallest undecided vertex, so n + 1 rounds
 // always suffice; the bound only guards against invalid input.
+template <int SIDE>
 __global__ __launch_bounds__(HEM_BS1) void k_hem_all(int n, HemState S, int* wl0, int* wl1, int* cnt) {
     __shared__ int s_list[HEM_LCAP1];
     __shared__ int s_cnt, s_next, s_m;
@@ -431,7 +435,7 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_all(int n, HemState S, int* wl0
         }
         __syncthreads();
         const Appender A{s_list, &s_cnt, HEM_LCAP1, wout, &s_next};
-        for (int idx = threadIdx.x; idx < m; idx += HEM_BS1) hem_visit<__HIP_MEMORY_SCOPE_WORKGROUP>(S, r, win[idx], A);
+        for (int idx = threadIdx.x; idx < m; idx += HEM_BS1) hem_visit<__HIP_MEMORY_SCOPE_WORKGROUP, SIDE>(S, r, win[idx], A);
         __syncthreads();
         const int k = min(s_cnt, HEM_LCAP1);
         const int base = s_next;
@@ -449,9 +453,19 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_all(int n, HemState S, int* wl0
     }
 }
 
+#define AMG_HEM_SIDE(side, CALL) \
+    switch (side) {                \
+        case 7: CALL(7); break;    \
+        case 15: CALL(15); break;  \
+        default: CALL(31); break;  \
+    }
+
 void launch_hem_init(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
-    hipLaunchKernelGGL(k_hem_init, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, w.lowok, w.rec, w.lcnt, w.dec,
-                       w.mate, w.wl[0], w.cnt, w.err);
+#define CALL(SD)                                                                                               \
+    hipLaunchKernelGGL(k_hem_init<SD>, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, w.lowok,              \
+                       static_cast<HemRecT<SD>*>(w.rec), w.lcnt, w.dec, w.mate, w.wl[0], w.cnt, w.err)
+    AMG_HEM_SIDE(w.side, CALL)
+#undef CALL
 }
 
 int hem_next_count_slot(int round) { return round % 3; }
@@ -459,14 +473,21 @@ int hem_next_count_slot(int round) { return round % 3; }
 void launch_hem_round(int r, int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
     const int g = blocks_for(n, HEM_BS, 96);
     const HemState S{rp, ci, v, w.lowok, w.rec, w.dec, w.mate, w.lcnt};
-    hipLaunchKernelGGL(k_hem_round, dim3(g), dim3(HEM_BS), 0, s, r, S, w.wl[r & 1], w.wl[(r + 1) & 1], w.cnt, r % 3,
-                       (r + 1) % 3, (r + 2) % 3);
+#define CALL(SD)                                                                                          \
+    hipLaunchKernelGGL(k_hem_round<SD>, dim3(g), dim3(HEM_BS), 0, s, r, S, w.wl[r & 1], w.wl[(r + 1) & 1], \
+                       w.cnt, r % 3, (r + 1) % 3, (r + 2) % 3)
+    AMG_HEM_SIDE(w.side, CALL)
+#undef CALL
 }
 
 void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
     const HemState S{rp, ci, v, w.lowok, w.rec, w.dec, w.mate, w.lcnt};
-    hipLaunchKernelGGL(k_hem_all, dim3(1), dim3(HEM_BS1), 0, s, n, S, w.wl[0], w.wl[1], w.cnt);
+#define CALL(SD) \
+    hipLaunchKernelGGL(k_hem_all<SD>, dim3(1), dim3(HEM_BS1), 0, s, n, S, w.wl[0], w.wl[1], w.cnt)
+    AMG_HEM_SIDE(w.side, CALL)
+#undef CALL
 }
+#undef AMG_HEM_SIDE
 
 // ---------------------------------------------------------------------------
 // Exclusive prefix sum (three phases: tile sums, scan of tile sums, apply).
@@ -809,8 +830,8 @@ void launch_members(int nc, const int* lead2, const int* mate2, const int* lead1
 // ---------------------------------------------------------------------------
 // Coarsest level (Section 2, coarse level solver): dense partial-pivot LU,
 // largest |pivot| with the lowest row on ties, then the explicit inverse so
-// that each V-cycle applies the exact coarse solve as one dense product.
-// One workgroup; the matrix lives in global memory (n <= 1024).
+// that each V-cycle applies the exact coarse solve as one dense product
+// (n <= 1024).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(BS) void k_dense_assemble(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                        const double* __restrict__ v, double* __restrict__ a) {
@@ -823,84 +844,137 @@ void launch_dense_assemble(int n, const int* rp, const int* ci, const double* v,
     hipLaunchKernelGGL(k_dense_assemble, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, a);
 }
 
-__global__ __launch_bounds__(BS) void k_dense_lu_inverse(int n, double* a, int* piv, double* ainv_t, int* err) {
-    __shared__ double sv[BS];
-    __shared__ int si[BS];
+namespace {
+constexpr int LU_BS = 1024;
+constexpr int INV_BS = 256;
+
+// Block-wide argmax of (|value|, lowest index on ties) over LU_BS threads.
+__device__ __forceinline__ void lu_argmax(double& v, int& i, double* sv, int* si) {
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off);
+        const int oi = __shfl_xor(i, off);
+        if (ov > v || (ov == v && oi < i)) {
+            v = ov;
+            i = oi;
+        }
+    }
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) {
+        sv[wid] = v;
+        si[wid] = i;
+    }
+    __syncthreads();
+    v = sv[0];
+    i = si[0];
+    for (int w = 1; w < LU_BS / kWave; ++w)
+        if (sv[w] > v || (sv[w] == v && si[w] < i)) {
+            v = sv[w];
+            i = si[w];
+        }
+}
+}  // namespace
+
+// Right-looking LU with partial pivoting in place (row-major a, unit lower L
+// below the diagonal).  perm[i] = original row of position i (P A = L U).
+// One workgroup; the pivot row and the multipliers of each step sit in LDS.
+__global__ __launch_bounds__(LU_BS) void k_dense_lu(int n, double* __restrict__ a, int* __restrict__ perm, int* err) {
+    __shared__ double rowk[1024], colk[1024];
+    __shared__ int sperm[1024];
+    __shared__ double sv[LU_BS / kWave];
+    __shared__ int si[LU_BS / kWave];
     const int tid = threadIdx.x;
+    for (int i = tid; i < n; i += LU_BS) sperm[i] = i;
     for (int k = 0; k < n; ++k) {
         double best = -1.0;
         int bi = n;
-        for (int i = k + tid; i < n; i += BS) {
+        for (int i = k + tid; i < n; i += LU_BS) {
             const double t = fabs(a[(size_t)i * n + k]);
-            if (t > best) {
+            if (t > best) {  // rows ascend per thread: strict '>' keeps the lowest
                 best = t;
                 bi = i;
             }
         }
-        sv[tid] = best;
-        si[tid] = bi;
-        __syncthreads();
-        for (int w = BS / 2; w > 0; w >>= 1) {
-            if (tid < w) {
-                const double ov = sv[tid + w];
-                const int oi = si[tid + w];
-                if (ov > sv[tid] || (ov == sv[tid] && oi < si[tid])) {
-                    sv[tid] = ov;
-                    si[tid] = oi;
-                }
-            }
-            __syncthreads();
-        }
-        const double pv = sv[0];
-        const int p = si[0];
-        __syncthreads();
-        if (!(pv > 0.0) || !isfinite(pv)) {
+        lu_argmax(best, bi, sv, si);
+        if (!(best > 0.0) || !isfinite(best)) {  // uniform across the block
             if (tid == 0) atomicOr(err, ERR_SINGULAR);
             return;
         }
-        if (tid == 0) piv[k] = p;
+        const int p = bi;
+        // row swap (all columns), recorded in the permutation
         if (p != k)
-            for (int j = tid; j < n; j += BS) {
+            for (int j = tid; j < n; j += LU_BS) {
                 const double t = a[(size_t)k * n + j];
                 a[(size_t)k * n + j] = a[(size_t)p * n + j];
                 a[(size_t)p * n + j] = t;
             }
+        if (tid == 0 && p != k) {
+            const int t = sperm[k];
+            sperm[k] = sperm[p];
+            sperm[p] = t;
+        }
         __syncthreads();
         const double d = a[(size_t)k * n + k];
-        for (int i = k + 1 + tid; i < n; i += BS) a[(size_t)i * n + k] /= d;
+        for (int j = k + 1 + tid; j < n; j += LU_BS) rowk[j] = a[(size_t)k * n + j];
+        for (int i = k + 1 + tid; i < n; i += LU_BS) {
+            const double l = a[(size_t)i * n + k] / d;
+            colk[i] = l;
+            a[(size_t)i * n + k] = l;
+        }
         __syncthreads();
         const int m = n - k - 1;
-        for (int t = tid; t < m * m; t += BS) {
+        for (int t = tid; t < m * m; t += LU_BS) {
             const int i = k + 1 + t / m, j = k + 1 + t % m;
-            a[(size_t)i * n + j] -= a[(size_t)i * n + k] * a[(size_t)k * n + j];
+            a[(size_t)i * n + j] -= colk[i] * rowk[j];
         }
         __syncthreads();
     }
-    // column c of the inverse (contiguous in ainv_t) solves A x = e_c
-    for (int c = tid; c < n; c += BS) {
-        double* x = ainv_t + (size_t)c * n;
-        for (int i = 0; i < n; ++i) x[i] = (i == c) ? 1.0 : 0.0;
-        for (int k = 0; k < n; ++k) {
-            const int p = piv[k];
-            const double t = x[k];
-            x[k] = x[p];
-            x[p] = t;
-        }
-        for (int i = 0; i < n; ++i) {
-            double s = x[i];
-            for (int j = 0; j < i; ++j) s -= a[(size_t)i * n + j] * x[j];
-            x[i] = s;
-        }
-        for (int i = n - 1; i >= 0; --i) {
-            double s = x[i];
-            for (int j = i + 1; j < n; ++j) s -= a[(size_t)i * n + j] * x[j];
-            x[i] = s / a[(size_t)i * n + i];
-        }
+    for (int i = tid; i < n; i += LU_BS) perm[i] = sperm[i];
+}
+
+// Columns of A^{-1} = U^{-1} L^{-1} P, INV_COLS per block, held in LDS as
+// x[i * INV_COLS + c] (at most 64 KiB).  Each row of a substitution is a dot
+// product split over INV_SLICES lanes (fixed order) and reduced with
+// shuffles.  Writes the inverse column-major: ainv_t[c * n + i] = (A^{-1})_{ic}.
+template <int INV_COLS>
+__global__ __launch_bounds__(INV_BS) void k_dense_inverse(int n, const double* __restrict__ lu,
+                                                          const int* __restrict__ perm, double* __restrict__ ainv_t) {
+    constexpr int INV_SLICES = INV_BS / INV_COLS;
+    extern __shared__ double x[];
+    const int c0 = blockIdx.x * INV_COLS;
+    const int c = threadIdx.x / INV_SLICES, sl = threadIdx.x % INV_SLICES;
+    for (int t = threadIdx.x; t < n * INV_COLS; t += INV_BS) {
+        const int i = t / INV_COLS, cc = t % INV_COLS;
+        x[t] = perm[i] == c0 + cc ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int i = 1; i < n; ++i) {  // unit lower
+        double s = 0.0;
+        for (int k = sl; k < i; k += INV_SLICES) s += lu[(size_t)i * n + k] * x[k * INV_COLS + c];
+        for (int off = INV_SLICES / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (sl == 0) x[i * INV_COLS + c] -= s;
+        __syncthreads();
+    }
+    for (int i = n - 1; i >= 0; --i) {  // upper
+        double s = 0.0;
+        for (int k = i + 1 + sl; k < n; k += INV_SLICES) s += lu[(size_t)i * n + k] * x[k * INV_COLS + c];
+        for (int off = INV_SLICES / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (sl == 0) x[i * INV_COLS + c] = (x[i * INV_COLS + c] - s) / lu[(size_t)i * n + i];
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < n * INV_COLS; t += INV_BS) {
+        const int cc = t / n, i = t % n;
+        if (c0 + cc < n) ainv_t[(size_t)(c0 + cc) * n + i] = x[i * INV_COLS + cc];
     }
 }
 
-void launch_dense_lu_inverse(int n, double* a, int* piv, double* ainv_t, int* err, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_lu_inverse, dim3(1), dim3(BS), 0, s, n, a, piv, ainv_t, err);
+void launch_dense_lu_inverse(int n, double* a, int* perm, double* ainv_t, int* err, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_lu, dim3(1), dim3(LU_BS), 0, s, n, a, perm, err);
+    if (n <= 512)
+        hipLaunchKernelGGL(k_dense_inverse<16>, dim3((n + 15) / 16), dim3(INV_BS), sizeof(double) * (size_t)n * 16, s,
+                           n, a, perm, ainv_t);
+    else
+        hipLaunchKernelGGL(k_dense_inverse<8>, dim3((n + 7) / 8), dim3(INV_BS), sizeof(double) * (size_t)n * 8, s, n,
+                           a, perm, ainv_t);
 }
 
 }  // namespace amg

@@ -234,6 +234,21 @@ def random_symmetric_pattern(n: int, density: float, seed: int, weights=(1, 2, 3
     return CSR(n, row_ptr, cols.astype(np.int32), vals[rows, cols].astype(np.float64))
 
 
+def star_graph(n: int, seed: int) -> CSR:
+    """Symmetric matrix whose graph is a star: row 0 is coupled to every other
+    row, which are coupled to nothing else.  Off-diagonal weights -1, -2 or -3
+    at random, diagonal sum of |off-diagonal| + 1.  Pairwise matching merges
+    only one leaf with the hub per pass, so coarsening makes almost no progress
+    (the shape high-contrast coefficients give coarse levels)."""
+    rng = np.random.default_rng(seed)
+    w = -rng.choice(np.array([1.0, 2.0, 3.0]), size=n - 1)
+    a = np.zeros((n, n))
+    a[0, 1:] = w
+    a[1:, 0] = w
+    np.fill_diagonal(a, np.abs(a).sum(axis=1) + 1.0)
+    return from_dense(a)
+
+
 def from_dense(a: np.ndarray) -> CSR:
     """CSR of the nonzero pattern of a dense square matrix plus its diagonal."""
     a = np.asarray(a, dtype=np.float64)
@@ -250,10 +265,11 @@ def from_dense(a: np.ndarray) -> CSR:
 # ---------------------------------------------------------------------------
 
 WORKLOADS = {
-    "poisson2d_64": dict(kind="pcg", rtol=1e-8, desc="2D 5-point Poisson, 64x64 interior (N=4096)"),
-    "poisson3d_128": dict(kind="pcg", rtol=1e-10, desc="3D 7-point Poisson, 128^3 (N=2,097,152)"),
-    "vardiff3d_160": dict(kind="pcg", rtol=1e-8, desc="3D variable-coefficient FV diffusion, 160^3"),
-    "convdiff3d_96": dict(kind="bicgstab", rtol=1e-8, desc="3D upwind convection-diffusion, 96^3, Pe=10"),
+    "poisson2d_64": dict(kind="pcg", rtol=1e-8, precond="fp64", desc="2D 5-point Poisson, 64x64 interior (N=4096)"),
+    "poisson3d_128": dict(kind="pcg", rtol=1e-10, precond="fp64", desc="3D 7-point Poisson, 128^3 (N=2,097,152)"),
+    "vardiff3d_160": dict(kind="pcg", rtol=1e-8, precond="fp32", desc="3D variable-coefficient FV diffusion, 160^3"),
+    "convdiff3d_96": dict(kind="bicgstab", rtol=1e-8, precond="fp32",
+                          desc="3D upwind convection-diffusion, 96^3, Pe=10"),
 }
 
 

@@ -42,8 +42,8 @@ def test_binding_fails_loudly_without_library(monkeypatch):
 
 
 def test_struct_layouts_match_header():
-    # amg_params: 4 int32, double, 3 int32 -> 40 bytes with natural alignment
-    assert ctypes.sizeof(hemamg.amg_params) == 40
+    # amg_params: 4 int32, double, 4 int32, double -> 48 bytes with natural alignment
+    assert ctypes.sizeof(hemamg.amg_params) == 48
     assert ctypes.sizeof(hemamg.amg_csr) == 40
     assert ctypes.sizeof(hemamg.amg_info) == 40
 
@@ -54,3 +54,4 @@ def test_params_default_values():
     p = hemamg.amg_params_default()  # host-only call, no GPU work
     assert (p.passes_per_level, p.max_coarse_rows, p.max_levels, p.max_dense_rows) == (2, 64, 32, 1024)
     assert abs(p.omega - 2.0 / 3.0) < 1e-16 and (p.pre, p.post, p.true_res_period) == (1, 1, 50)
+    assert p.precond_fp32 == 0 and p.stall_ratio == 0.9

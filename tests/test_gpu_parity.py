@@ -41,7 +41,7 @@ def dev(torch, x):
 def both(a, **kw):
     gp = hemamg.amg_params_default(**kw)
     okw = {k: v for k, v in kw.items() if k in ("passes_per_level", "max_coarse_rows", "max_levels",
-                                                  "max_dense_rows", "omega", "pre", "post")}
+                                                  "max_dense_rows", "omega", "pre", "post", "stall_ratio")}
     A = hemamg.DeviceCSR.from_host(a)
     g = hemamg.Hierarchy(A, gp)
     o = oracle.Hierarchy(a, **okw)
@@ -283,6 +283,61 @@ def test_stall_dense_fallback_and_error(torch):
     np.testing.assert_allclose(x.cpu().numpy(), b / np.arange(1.0, 101.0), rtol=1e-14)
     big = P.CSR(2000, np.arange(2001, dtype=np.int32), np.arange(2000, dtype=np.int32), np.arange(1.0, 2001.0))
     assert bad_setup(torch, big) == hemamg.AMG_ESTALL
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 65, 300, 513, 1024])
+def test_dense_coarsest_sizes_with_pivoting(torch, n):
+    """The coarsest solve alone (one level) at sizes around its tile edges, on
+    a matrix whose small diagonal forces row exchanges."""
+    say("dense n", n)
+    rng = np.random.default_rng(n)
+    d = np.zeros((n, n))
+    mask = np.triu(rng.random((n, n)) < min(1.0, 8.0 / n), 1)
+    mask = mask | mask.T
+    d[mask] = rng.uniform(-3, 3, size=mask.sum())
+    np.fill_diagonal(d, 0.01 + rng.random(n) * 0.01)
+    if n == 1:
+        d[0, 0] = 2.0
+    a = P.from_dense(d)
+    g, o = both(a, max_coarse_rows=1024)
+    assert g.nlevels == o.nlevels == 1
+    b = P.rhs_uniform(n, 3)
+    z = g.vcycle(dev(torch, b)).cpu().numpy()
+    x = np.linalg.solve(d, b)
+    tol = max(1e-13, 64 * np.finfo(float).eps * np.linalg.cond(d))
+    assert rel(z, x) <= tol, (rel(z, x), tol)
+    assert rel(z, o.vcycle(b)) <= tol
+    g.close()
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(stall_ratio=1.0), dict(max_dense_rows=140), dict(stall_ratio=0.5)])
+def test_star_graph_stall_rule(torch, kw):
+    """Coarsening that merges two rows per level: the stall-ratio rule decides
+    where the hierarchy ends, identically on both sides."""
+    say("star", kw)
+    a = P.star_graph(150, 1)
+    g, o = both(a, **kw)
+    assert_same_hierarchy(g, o)
+    f = P.rhs_uniform(a.n, 5)
+    z = g.vcycle(dev(torch, f)).cpu().numpy()
+    assert rel(z, o.vcycle(f)) <= VC_TOL
+    g.close()
+    A = hemamg.DeviceCSR.from_host(a)
+    for bad in (0.0, 1.5):
+        with pytest.raises(hemamg.AmgError) as e:
+            hemamg.Hierarchy(A, hemamg.amg_params_default(stall_ratio=bad))
+        assert e.value.status == hemamg.AMG_EINVAL
+
+
+def test_vardiff3d_80_high_contrast_hierarchy(torch):
+    """High-contrast coefficients (the 160^3 field's statistics on 80^3), whose
+    coarse levels degenerate into stars."""
+    a = P.vardiff3d(80, seed=0)
+    g, o = both(a)
+    assert_same_hierarchy(g, o)
+    say("levels", g.nlevels, [g.level(k)[0].size - 1 for k in range(g.nlevels)])
+    g.close()
+    solve_parity(torch, a, "pcg", 1e-8)
 
 
 # ---------------------------------------------------------------- full size
