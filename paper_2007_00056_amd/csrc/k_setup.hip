@@ -614,6 +614,29 @@ void launch_assign_ids(int n, const int* mate, const int* ids, int* agg, int* le
 namespace {
 constexpr int RAP_CAP = 32;
 constexpr int RAP_BS = 128;
+constexpr int RAP_WIN = 8;
+}
+
+// Entries of a member row are taken in windows of RAP_WIN whose column and
+// aggregate loads are issued together, then added in entry order.
+template <bool WITH_VAL>
+__device__ __forceinline__ bool rap_row(SortedAcc<RAP_CAP>& acc, int e0, int e1, const int* __restrict__ ci,
+                                        const double* __restrict__ v, const int* __restrict__ agg) {
+    for (int b = e0; b < e1; b += RAP_WIN) {
+        int c[RAP_WIN], J[RAP_WIN];
+        double x[RAP_WIN];
+#pragma unroll
+        for (int t = 0; t < RAP_WIN; ++t) c[t] = b + t < e1 ? ci[b + t] : -1;
+#pragma unroll
+        for (int t = 0; t < RAP_WIN; ++t) {
+            J[t] = c[t] >= 0 ? agg[c[t]] : -1;
+            x[t] = (WITH_VAL && c[t] >= 0) ? v[b + t] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < RAP_WIN; ++t)
+            if (J[t] >= 0 && !acc.template add<WITH_VAL>(J[t], x[t])) return false;
+    }
+    return true;
 }
 
 __global__ __launch_bounds__(RAP_BS) void k_rap_count(int nc, const int* __restrict__ lead,
@@ -623,19 +646,11 @@ __global__ __launch_bounds__(RAP_BS) void k_rap_count(int nc, const int* __restr
     const int I = blockIdx.x * RAP_BS + threadIdx.x;
     if (I >= nc) return;
     const int m0 = lead[I];
-    const int mm[2] = {m0, mate[m0]};
+    const int m1 = mate[m0];
     SortedAcc<RAP_CAP> acc;
     acc.clear();
-    bool ok = true;
-    for (int t = 0; t < 2 && ok; ++t) {
-        const int m = mm[t];
-        if (m < 0) continue;
-        for (int e = rp[m]; e < rp[m + 1]; ++e)
-            if (!acc.template add<false>(agg[ci[e]], 0.0)) {
-                ok = false;
-                break;
-            }
-    }
+    bool ok = rap_row<false>(acc, rp[m0], rp[m0 + 1], ci, nullptr, agg);
+    if (ok && m1 >= 0) ok = rap_row<false>(acc, rp[m1], rp[m1 + 1], ci, nullptr, agg);
     if (ok) {
         rowcnt[I] = acc.len;
     } else {
@@ -652,15 +667,11 @@ __global__ __launch_bounds__(RAP_BS) void k_rap_fill(int nc, const int* __restri
     const int I = blockIdx.x * RAP_BS + threadIdx.x;
     if (I >= nc) return;
     const int m0 = lead[I];
-    const int mm[2] = {m0, mate[m0]};
+    const int m1 = mate[m0];
     SortedAcc<RAP_CAP> acc;
     acc.clear();
-    for (int t = 0; t < 2; ++t) {
-        const int m = mm[t];
-        if (m < 0) continue;
-        for (int e = rp[m]; e < rp[m + 1]; ++e)
-            if (!acc.template add<true>(agg[ci[e]], v[e])) return;  // overflow row: slow path
-    }
+    if (!rap_row<true>(acc, rp[m0], rp[m0 + 1], ci, v, agg)) return;  // overflow row: slow path
+    if (m1 >= 0 && !rap_row<true>(acc, rp[m1], rp[m1 + 1], ci, v, agg)) return;
     const int o = crp[I];
 #pragma unroll
     for (int t = 0; t < RAP_CAP; ++t) {
@@ -671,16 +682,20 @@ __global__ __launch_bounds__(RAP_BS) void k_rap_fill(int nc, const int* __restri
     }
 }
 
-// Distinct coarse columns of an overflow row: count entries whose column does
-// not occur earlier in the member/column order.
-__global__ __launch_bounds__(64) void k_rap_count_slow(const int* __restrict__ ovf, const int* novf,
-                                                       const int* __restrict__ lead, const int* __restrict__ mate,
-                                                       const int* __restrict__ rp, const int* __restrict__ ci,
-                                                       const int* __restrict__ agg, int* __restrict__ rowcnt) {
-    for (int t = blockIdx.x * 64 + threadIdx.x; t < *novf; t += gridDim.x * 64) {
-    const int I = ovf[t];
-    const int m0 = lead[I];
-    const int mm[2] = {m0, mate[m0]};
+// Overflow rows (more than RAP_CAP distinct coarse columns): one wave per
+// row.  The row's entries, in member-then-column order, are staged in LDS
+// with their coarse columns; a stable rank (by column, then entry order)
+// sorts them, and the first lane of each run of equal columns adds the run
+// in entry order, so the sums are the same as on the fast path.  Rows longer
+// than RAP_SLOW_CAP entries fall back to one lane working in place.
+namespace {
+constexpr int RAP_SLOW_CAP = 1024;
+
+__device__ __forceinline__ int rap_entry(int k, int l0, int b0, int b1) { return k < l0 ? b0 + k : b1 + (k - l0); }
+
+// serial fallback: distinct columns of a long row
+__device__ int rap_count_serial(const int mm[2], const int* __restrict__ rp, const int* __restrict__ ci,
+                                const int* __restrict__ agg) {
     int count = 0;
     for (int a = 0; a < 2; ++a) {
         if (mm[a] < 0) continue;
@@ -699,22 +714,13 @@ __global__ __launch_bounds__(64) void k_rap_count_slow(const int* __restrict__ o
             count += !seen;
         }
     }
-    rowcnt[I] = count;
-    }
+    return count;
 }
 
-// Overflow rows: insertion into the row's own output segment, kept sorted.
-__global__ __launch_bounds__(64) void k_rap_fill_slow(const int* __restrict__ ovf, const int* novf,
-                                                      const int* __restrict__ lead, const int* __restrict__ mate,
-                                                      const int* __restrict__ rp, const int* __restrict__ ci,
-                                                      const double* __restrict__ v, const int* __restrict__ agg,
-                                                      const int* __restrict__ crp, int* __restrict__ cci,
-                                                      double* __restrict__ cv) {
-    for (int t = blockIdx.x * 64 + threadIdx.x; t < *novf; t += gridDim.x * 64) {
-    const int I = ovf[t];
-    const int m0 = lead[I];
-    const int mm[2] = {m0, mate[m0]};
-    const int o = crp[I];
+// serial fallback: sorted insertion into the row's own output segment
+__device__ void rap_fill_serial(const int mm[2], const int* __restrict__ rp, const int* __restrict__ ci,
+                                const double* __restrict__ v, const int* __restrict__ agg, int o,
+                                int* __restrict__ cci, double* __restrict__ cv) {
     int len = 0;
     for (int a = 0; a < 2; ++a) {
         if (mm[a] < 0) continue;
@@ -739,6 +745,77 @@ __global__ __launch_bounds__(64) void k_rap_fill_slow(const int* __restrict__ ov
             }
         }
     }
+}
+}  // namespace
+
+template <bool FILL>
+__global__ __launch_bounds__(kWave) void k_rap_slow(const int* __restrict__ ovf, const int* novf,
+                                                    const int* __restrict__ lead, const int* __restrict__ mate,
+                                                    const int* __restrict__ rp, const int* __restrict__ ci,
+                                                    const double* __restrict__ v, const int* __restrict__ agg,
+                                                    int* __restrict__ rowcnt, const int* __restrict__ crp,
+                                                    int* __restrict__ cci, double* __restrict__ cv) {
+    __shared__ int key[RAP_SLOW_CAP], skey[RAP_SLOW_CAP];
+    __shared__ double val[RAP_SLOW_CAP], sval[RAP_SLOW_CAP];
+    __shared__ int s_cnt;
+    const int lane = threadIdx.x;
+    const int nrows = *novf;
+    for (int t = blockIdx.x; t < nrows; t += gridDim.x) {
+        const int I = ovf[t];
+        const int m0 = lead[I];
+        const int mm[2] = {m0, mate[m0]};
+        const int b0 = rp[m0], l0 = rp[m0 + 1] - b0;
+        const int b1 = mm[1] >= 0 ? rp[mm[1]] : 0, l1 = mm[1] >= 0 ? rp[mm[1] + 1] - b1 : 0;
+        const int L = l0 + l1;
+        if (L > RAP_SLOW_CAP) {
+            if (lane == 0) {
+                if (FILL) rap_fill_serial(mm, rp, ci, v, agg, crp[I], cci, cv);
+                else rowcnt[I] = rap_count_serial(mm, rp, ci, agg);
+            }
+            continue;
+        }
+        if (lane == 0) s_cnt = 0;
+        for (int k = lane; k < L; k += kWave) {
+            const int e = rap_entry(k, l0, b0, b1);
+            key[k] = agg[ci[e]];
+            if (FILL) val[k] = v[e];
+        }
+        __syncthreads();
+        int distinct = 0;
+        for (int k = lane; k < L; k += kWave) {
+            const int J = key[k];
+            int less = 0, before = 0;
+            for (int j = 0; j < L; ++j) {
+                const int K = key[j];
+                less += K < J;
+                before += (K == J) & (j < k);
+            }
+            distinct += before == 0;
+            if (FILL) {
+                skey[less + before] = J;
+                sval[less + before] = val[k];
+            }
+        }
+        if (!FILL) {
+            if (distinct) atomicAdd(&s_cnt, distinct);
+            __syncthreads();
+            if (lane == 0) rowcnt[I] = s_cnt;
+            __syncthreads();
+            continue;
+        }
+        __syncthreads();
+        const int o = crp[I];
+        for (int p = lane; p < L; p += kWave) {
+            const int J = skey[p];
+            if (p > 0 && skey[p - 1] == J) continue;  // not the start of a run
+            int d = 0;  // runs before this one = distinct columns below J
+            for (int q = 0; q < p; ++q) d += (q == 0 || skey[q - 1] != skey[q]);
+            double sum = sval[p];
+            for (int q = p + 1; q < L && skey[q] == J; ++q) sum += sval[q];
+            cci[o + d] = J;
+            cv[o + d] = sum;
+        }
+        __syncthreads();
     }
 }
 
@@ -750,8 +827,8 @@ void launch_rap_count(int nc, const int* lead, const int* mate, const int* rp, c
 
 void launch_rap_count_slow(int nc, const int* ovf, const int* novf, const int* lead, const int* mate, const int* rp,
                            const int* ci, const int* agg, int* rowcnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_rap_count_slow, dim3(blocks_for(nc, 64, 64)), dim3(64), 0, s, ovf, novf, lead, mate, rp, ci,
-                       agg, rowcnt);
+    hipLaunchKernelGGL(k_rap_slow<false>, dim3(blocks_for(nc, 1, 512)), dim3(kWave), 0, s, ovf, novf, lead, mate, rp,
+                       ci, nullptr, agg, rowcnt, nullptr, nullptr, nullptr);
 }
 
 void launch_rap_fill(int nc, const int* lead, const int* mate, const int* rp, const int* ci, const double* v,
@@ -763,8 +840,8 @@ void launch_rap_fill(int nc, const int* lead, const int* mate, const int* rp, co
 void launch_rap_fill_slow(int nc, const int* ovf, const int* novf, const int* lead, const int* mate, const int* rp,
                           const int* ci, const double* v, const int* agg, const int* crp, int* cci, double* cv,
                           hipStream_t s) {
-    hipLaunchKernelGGL(k_rap_fill_slow, dim3(blocks_for(nc, 64, 64)), dim3(64), 0, s, ovf, novf, lead, mate, rp, ci,
-                       v, agg, crp, cci, cv);
+    hipLaunchKernelGGL(k_rap_slow<true>, dim3(blocks_for(nc, 1, 512)), dim3(kWave), 0, s, ovf, novf, lead, mate, rp,
+                       ci, v, agg, nullptr, crp, cci, cv);
 }
 
 // ---------------------------------------------------------------------------
