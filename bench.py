@@ -135,6 +135,88 @@ def cpu_baseline(a, b, spec, gpu_iters, budget_s=25.0):
     }
 
 
+def gen_request(item):
+    """Matrix and right-hand side of one served request (side, seed)."""
+    from paper_2007_00056_amd import problems as P
+
+    side, seed = item
+    a = P.lognormal_diffusion3d(side, seed, 1.0)
+    return a, P.rhs_uniform(a.n, seed)
+
+
+def serve_main(args):
+    """Served stream: requests of side log-uniform in [16, 96] with lognormal
+    coefficients arrive as a Poisson process.  The plain form solves them one
+    at a time in double; the served form runs `--workers` requests at once
+    with the float preconditioner.  Both see the same arrival trace, at rates
+    that are fractions of the plain form's measured capacity."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    import torch
+
+    from paper_2007_00056_amd import hemamg, problems as P
+
+    torch.cuda.set_device(0)
+    stream = P.served_stream(args.requests, seed=0)
+    log(f"generating {len(stream)} requests")
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        reqs = list(ex.map(gen_request, stream, chunksize=4))
+    dev = []
+    for a, b in reqs:
+        A = hemamg.DeviceCSR.from_host(a)
+        dev.append((A, torch.from_numpy(b).cuda(), torch.zeros(a.n, dtype=torch.float64, device="cuda")))
+    torch.cuda.synchronize()
+    rows = sum(a.n for a, _ in reqs)
+    log(f"{len(reqs)} requests, {rows} rows in total")
+
+    def run(workers, fp32, arrivals):
+        cfg = hemamg.amg_server_config_default(workers=workers)
+        cfg.params.precond_fp32 = fp32
+        srv = hemamg.amg_server_create(cfg)
+        for _, _, x in dev:
+            x.zero_()
+        torch.cuda.synchronize()
+        tickets = []
+        t0 = time.perf_counter()
+        for i, (A, b, x) in enumerate(dev):
+            if arrivals is not None:
+                dt = t0 + arrivals[i] - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            tickets.append((time.perf_counter() - t0, hemamg.amg_server_submit(srv, A, b, x, hemamg.PCG, 1e-8, 1000)))
+        res = [hemamg.amg_server_wait(srv, t) for _, t in tickets]
+        hemamg.amg_server_destroy(srv)
+        bad = [r for r in res if r["status"] != hemamg.AMG_OK]
+        if bad:
+            raise RuntimeError(f"{len(bad)} requests failed, e.g. {bad[0]}")
+        lat = np.array([r["latency_ms"] for r in res])
+        done = max(ts + l / 1e3 for (ts, _), l in zip(tickets, lat))
+        return dict(solves_per_s=len(res) / done, p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99)), mean_iters=float(np.mean([r["iters"] for r in res])))
+
+    run(1, 0, None)  # warm-up
+    cap = run(1, 0, None)
+    log(f"plain capacity {cap['solves_per_s']:.1f} solves/s")
+    rng = np.random.default_rng(0)
+    gaps = rng.exponential(1.0, len(dev))
+    out_rates = {}
+    for f in args.rates:
+        lam = f * cap["solves_per_s"]
+        arr = np.cumsum(gaps) / lam
+        plain = run(1, 0, arr)
+        served = run(args.workers, 1, arr)
+        out_rates[str(f)] = {"plain": plain, "served": served}
+        log(f"rate {f}: plain {plain}, served {served}")
+    closed = run(args.workers, 1, None)
+    print(json.dumps({
+        "metric": "served solves/s, p50/p99 latency", "value": closed["solves_per_s"], "unit": "solves/s",
+        "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f32+f64",
+        "config": {"workload": "served lognormal diffusion stream", "requests": len(dev), "rows": rows,
+                   "side": [16, 96], "sigma": 1.0, "rtol": 1e-8, "method": "pcg", "workers": args.workers},
+        "plain_capacity": cap, "served_closed_loop": closed, "rates": out_rates,
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +233,10 @@ def main():
                     help="also time the level-0 residual and the outer SpMV (more events in the timed region)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy 256 MiB device-to-device (counter calibration for profiles)")
+    ap.add_argument("--serve", action="store_true", help="served stream of solve requests instead of one system")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--rates", type=lambda t: [float(v) for v in t.split(",")], default=[0.5, 0.8, 1.0])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is single-GPU and "
@@ -164,6 +250,9 @@ def main():
     if not torch.cuda.is_available():
         log("bench.py needs a ROCm GPU")
         sys.exit(1)
+    if args.serve:
+        serve_main(args)
+        return
     torch.cuda.set_device(0)
     log(f"generating {args.workload} (seed {args.seed})")
     a, b_host, spec = P.make_workload(args.workload, args.seed)

@@ -149,6 +149,56 @@ amg_status amg_timing_read(amg_hier* h, int32_t kernel, int64_t* launches, doubl
 /* Message for the last failing call on this thread (never NULL). */
 const char* amg_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Serving: independent solve requests of different sizes on one GPU.
+ * A server owns `workers` host threads, each with its own HIP stream; a
+ * request runs setup, the Krylov solve and teardown on one worker while other
+ * requests proceed on the others, so their kernels overlap on the device.
+ * Requests are admitted in arrival order while the sum of the footprints of
+ * the requests in flight stays within `hbm_budget_bytes` (the device-memory
+ * concern of Section 3.1, here as admission control).
+ * ------------------------------------------------------------------------ */
+typedef struct amg_server amg_server;
+
+typedef struct {
+    int32_t workers;          /* concurrent requests, 1..64 (4)                 */
+    int32_t pad;
+    uint64_t hbm_budget_bytes; /* admission budget (64 GiB)                     */
+    amg_params params;        /* hierarchy and cycle parameters of every request */
+} amg_server_config;
+
+/* Upper estimate of the device memory one request of n rows and nnz entries
+ * needs at its peak (hierarchy, Krylov workspace and setup scratch; level 0
+ * is the caller's).  It assumes the coarse levels together hold at most n
+ * rows and nnz entries (operator complexity <= 2).  [host] */
+amg_status amg_footprint_bytes(int32_t n, int64_t nnz, const amg_params* params, uint64_t* bytes);
+
+/* Fills *c with the defaults shown above (params from amg_params_default). */
+amg_status amg_server_config_default(amg_server_config* c);
+
+/* Starts the worker threads on the current device.  Errors: AMG_EINVAL,
+ * AMG_EHIP. */
+amg_status amg_server_create(const amg_server_config* c, amg_server** out);
+
+/* Queues one request: A (borrowed, [device] arrays as in amg_setup), b and x
+ * ([device] float64[n]; x holds the initial guess) must stay valid until
+ * amg_server_wait returns for it.  method/rtol/maxit as in krylov_solve.
+ * Returns at once with a ticket.  Errors: AMG_EINVAL (NULL argument, or a
+ * footprint above the whole budget). */
+amg_status amg_server_submit(amg_server* s, const amg_csr* A, const double* b, double* x, int32_t method,
+                             double rtol, int32_t maxit, int64_t* ticket);
+
+/* Blocks until request `ticket` has finished and releases it (one wait per
+ * ticket; a second wait returns AMG_EINVAL).  info [host]
+ * (may be NULL) receives the solve summary; latency_ms (may be NULL) the
+ * time from submission to completion, queueing included.  Returns the
+ * request's own status (setup or solve error). */
+amg_status amg_server_wait(amg_server* s, int64_t ticket, amg_info* info, double* latency_ms);
+
+/* Finishes every queued request, stops the workers and frees the server.
+ * Results of requests nobody waited for are discarded.  NULL is accepted. */
+amg_status amg_server_destroy(amg_server* s);
+
 #ifdef __cplusplus
 }
 #endif

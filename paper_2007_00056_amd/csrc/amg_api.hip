@@ -9,7 +9,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <cstdint>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -47,16 +50,41 @@ struct Failure {
     } while (0)
 
 // Stream-ordered device allocations; every byte is counted.
+// Device memory comes from a stream-ordered pool owned by the library (one
+// per device) that keeps freed blocks for reuse instead of returning them to
+// the driver, so building a hierarchy does not remap memory level by level.
+hipMemPool_t lib_pool() {
+    static std::mutex mu;
+    static std::map<int, hipMemPool_t> pools;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(mu);
+    auto it = pools.find(dev);
+    if (it != pools.end()) return it->second;
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    HIPCHK(hipMemPoolCreate(&pool, &props));
+    uint64_t keep = UINT64_MAX;
+    HIPCHK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+    pools[dev] = pool;
+    return pool;
+}
+
 struct DevPool {
     hipStream_t s = nullptr;
+    hipMemPool_t mp = nullptr;
     std::vector<void*> ptrs;
     size_t bytes = 0;
 
     template <class T>
     T* get(size_t count) {
+        if (!mp) mp = lib_pool();
         void* p = nullptr;
         const size_t b = (count > 0 ? count : 1) * sizeof(T);
-        HIPCHK(hipMallocAsync(&p, b, s));
+        HIPCHK(hipMallocFromPoolAsync(&p, b, mp, s));
         ptrs.push_back(p);
         bytes += b;
         return static_cast<T*>(p);
@@ -194,21 +222,29 @@ amg_status guarded(F&& f) {
 
 inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
-int read_int(const int* d, hipStream_t s) {
-    int h = 0;
-    HIPCHK(hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return h;
+// Pinned host words for small read-backs (per thread, kept for the process).
+int* pinned_words() {
+    thread_local int* p = nullptr;
+    if (!p) HIPCHK(hipHostMalloc((void**)&p, 64 * sizeof(int), hipHostMallocDefault));
+    return p;
 }
 
-void check_err_word(const int* err, hipStream_t s, const char* where) {
-    const int e = read_int(err, s);
+int read_int(const int* d, hipStream_t s) {
+    int* h = pinned_words();
+    HIPCHK(hipMemcpyAsync(h, d, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return h[0];
+}
+
+void raise_err_word(int e, const char* where) {
     if (e & ERR_NONFINITE) raise(AMG_ENOTFINITE, "%s: matrix has a NaN or Inf value", where);
     if (e & ERR_STRUCT) raise(AMG_EINVAL, "%s: invalid CSR structure (row_ptr, column range or order)", where);
     if (e & ERR_DIAG) raise(AMG_EINVAL, "%s: a diagonal entry is missing or zero", where);
     if (e & ERR_NONSYM) raise(AMG_EINVAL, "%s: sparsity pattern is not structurally symmetric", where);
     if (e & ERR_SINGULAR) raise(AMG_ESINGULAR, "%s: coarsest matrix is singular", where);
 }
+
+void check_err_word(const int* err, hipStream_t s, const char* where) { raise_err_word(read_int(err, s), where); }
 
 struct Csr {
     int n = 0;
@@ -261,6 +297,7 @@ struct SetupWork {
         HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
         if (const char* e = getenv("HEMAMG_HEM_SMALL")) hem_small = atoi(e);  // tuning sweeps
+        if (const char* e = getenv("HEMAMG_HEM_GRID")) hw.round_grid = atoi(e) > 0 ? atoi(e) : 96;
     }
     ~SetupWork() {
         if (hc) (void)hipHostFree(hc);
@@ -275,7 +312,9 @@ struct Pass {
     int* mate = nullptr;
     int* agg = nullptr;
     int* lead = nullptr;
-    int nc = 0;
+    int* cnt = nullptr;  // matching counters (device)
+    int n = 0;           // fine rows
+    int nc = 0;          // coarse rows, known after the Galerkin count
     int rounds = 0;
 };
 
@@ -285,7 +324,7 @@ Pass hem_pass(const Csr& B, SetupWork& W, int t, hipStream_t s, int* err) {
     w.mate = W.mate[t];
     // record side from the average row length, within the record buffer
     const double avg = n > 0 ? (double)B.nnz / n : 0.0;
-    w.side = avg <= 9.0 ? 7 : (avg <= 20.0 ? 15 : 31);
+    w.side = avg <= 9.0 ? 7 : (avg <= 20.0 || n <= W.hem_small ? 15 : 31);  // one-workgroup passes: at most 15
     while (w.side > 7 && (size_t)(w.side + 1) * 8 * (size_t)n > w.rec_bytes) w.side = (w.side + 1) / 2 - 1;
     HIPCHK(hipMemsetAsync(w.cnt, 0, 8 * sizeof(int), s));
     launch_hem_init(n, B.rp, B.ci, B.v, w, s);
@@ -315,31 +354,44 @@ Pass hem_pass(const Csr& B, SetupWork& W, int t, hipStream_t s, int* err) {
     P.mate = w.mate;
     P.agg = W.agg[t];
     P.lead = W.lead[t];
-    // coarse ids: rank of each aggregate's smaller vertex
+    P.n = n;
+    P.cnt = w.cnt;
+    // coarse ids: rank of each aggregate's smaller vertex; the count stays on
+    // the device until the Galerkin product reads it back with its own sizes
     launch_leader_flags(n, w.mate, W.flag, s);
     launch_scan(W.flag, n, W.ids, W.stmp, s);
     launch_assign_ids(n, w.mate, W.ids, P.agg, P.lead, s);
     HIPCHK(hipGetLastError());
-    int tail[8];
-    HIPCHK(hipMemcpyAsync(tail, w.cnt, sizeof(tail), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&P.nc, W.ids + n, sizeof(int), hipMemcpyDeviceToHost, s));
-    check_err_word(err, s, "matching");  // synchronises the stream
-    if (tail[5] != 0) raise(AMG_EINVAL, "matching: sparsity pattern is not structurally symmetric");
-    if (tail[7] != 0) raise(AMG_EHIP, "matching did not terminate (internal error)");
-    P.rounds = tail[6];
     return P;
 }
 
-// Galerkin product of one pass; output buffers from `out`.
-Csr galerkin(const Csr& B, const Pass& P, SetupWork& W, DevPool& out, hipStream_t s) {
-    Csr C;
-    C.n = P.nc;
+// Galerkin product of one pass; output buffers from `out`.  The row counts
+// are formed over an upper bound of the coarse size (rows past it count 0),
+// so one read-back returns the coarse size, its nonzero count, the matching
+// counters and the error word together.
+Csr galerkin(const Csr& B, Pass& P, SetupWork& W, DevPool& out, hipStream_t s, const int* err) {
+    const int nmax = P.n;  // coarse rows <= fine rows
+    const int* ncp = W.ids + P.n;
     HIPCHK(hipMemsetAsync(W.novf, 0, sizeof(int), s));
-    launch_rap_count(P.nc, P.lead, P.mate, B.rp, B.ci, P.agg, W.rowcnt, W.ovf, W.novf, s);
-    launch_rap_count_slow(P.nc, W.ovf, W.novf, P.lead, P.mate, B.rp, B.ci, P.agg, W.rowcnt, s);
-    C.rp = out.get<int>((size_t)P.nc + 1);
-    launch_scan(W.rowcnt, P.nc, C.rp, W.stmp, s);
-    C.nnz = read_int(C.rp + P.nc, s);
+    launch_rap_count(nmax, ncp, P.lead, P.mate, B.rp, B.ci, P.agg, W.rowcnt, W.ovf, W.novf, s);
+    launch_rap_count_slow(nmax, W.ovf, W.novf, P.lead, P.mate, B.rp, B.ci, P.agg, W.rowcnt, s);
+    Csr C;
+    C.rp = out.get<int>((size_t)nmax + 1);
+    launch_scan(W.rowcnt, nmax, C.rp, W.stmp, s);
+    HIPCHK(hipGetLastError());
+    int* hw = pinned_words();
+    HIPCHK(hipMemcpyAsync(hw, P.cnt, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hw + 8, ncp, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hw + 9, C.rp + nmax, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hw + 10, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    raise_err_word(hw[10], "amg_setup");
+    if (hw[5] != 0) raise(AMG_EINVAL, "matching: sparsity pattern is not structurally symmetric");
+    if (hw[7] != 0) raise(AMG_EHIP, "matching did not terminate (internal error)");
+    P.rounds = hw[6];
+    P.nc = hw[8];
+    C.n = P.nc;
+    C.nnz = hw[9];
     C.ci = out.get<int>((size_t)C.nnz);
     C.v = out.get<double>((size_t)C.nnz);
     launch_rap_fill(P.nc, P.lead, P.mate, B.rp, B.ci, B.v, P.agg, C.rp, C.ci, C.v, s);
@@ -849,16 +901,16 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
         } tg{tmp};
         Csr B{F.n, F.nnz, const_cast<int*>(F.rp), const_cast<int*>(F.ci), const_cast<double*>(F.v)};
         Pass p1 = hem_pass(B, SW, 0, s, h->err);
-        h->rounds.push_back(p1.rounds);
         DevPool& out1 = (p.passes_per_level == 1) ? P : tmp;
-        Csr C1 = galerkin(B, p1, SW, out1, s);
+        Csr C1 = galerkin(B, p1, SW, out1, s, h->err);
+        h->rounds.push_back(p1.rounds);
         Csr Cf = C1;
         int* agg = nullptr;
         int4* mem = nullptr;
         if (p.passes_per_level == 2) {
             Pass p2 = hem_pass(C1, SW, 1, s, h->err);
+            Cf = galerkin(C1, p2, SW, P, s, h->err);
             h->rounds.push_back(p2.rounds);
-            Cf = galerkin(C1, p2, SW, P, s);
             agg = P.get<int>(F.n);
             launch_compose(F.n, p1.agg, p2.agg, agg, s);
             mem = P.get<int4>(Cf.n);
@@ -891,8 +943,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
         C.dinv = P.get<double>(C.n);
         C.lpr = pick_lanes_per_row((double)C.nnz / C.n);
         launch_dinv(C.n, C.rp, C.ci, C.v, C.dinv, h->err, s);
-        HIPCHK(hipGetLastError());
-        check_err_word(h->err, s, "coarse level");
+        HIPCHK(hipGetLastError());  // its error bit is read back with the next level's sizes
         h->lev.push_back(C);
     }
     // coarsest level: dense LU and inverse
@@ -1005,16 +1056,20 @@ amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x,
         h->stream = s;
         h->pool.s = s;
         alloc_workspace(h);
-        // the solve runs on the handle's own stream (graphs cannot be captured
-        // on the null stream), ordered after the caller's prior work on s
-        if (!h->gstream) {
+        // the solve runs on the caller's stream, or on the handle's own stream
+        // (ordered after the caller's prior work) when that is the null
+        // stream or graphs are replayed (they cannot be captured on it)
+        const bool own = s == nullptr || h->use_graphs;
+        if (own && !h->gstream) {
             HIPCHK(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&h->gev[0], hipEventDisableTiming));
             HIPCHK(hipEventCreateWithFlags(&h->gev[1], hipEventDisableTiming));
         }
-        HIPCHK(hipEventRecord(h->gev[0], s));
-        HIPCHK(hipStreamWaitEvent(h->gstream, h->gev[0], 0));
-        hipStream_t ws = h->gstream;
+        if (own) {
+            HIPCHK(hipEventRecord(h->gev[0], s));
+            HIPCHK(hipStreamWaitEvent(h->gstream, h->gev[0], 0));
+        }
+        hipStream_t ws = own ? h->gstream : s;
         h->pool.s = ws;
         HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), ws));
         launch_check_finite(h->lev[0].n, b, x, h->err, ws);
@@ -1022,8 +1077,10 @@ amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x,
         if (read_int(h->err, ws) & ERR_NONFINITE) raise(AMG_ENOTFINITE, "krylov_solve: b or x0 has NaN or Inf");
         st = method == 0 ? pcg(h, b, x, rtol, maxit, ws, I) : bicgstab(h, b, x, rtol, maxit, ws, I);
         HIPCHK(hipStreamSynchronize(ws));
-        HIPCHK(hipEventRecord(h->gev[1], ws));
-        HIPCHK(hipStreamWaitEvent(s, h->gev[1], 0));
+        if (own) {
+            HIPCHK(hipEventRecord(h->gev[1], ws));
+            HIPCHK(hipStreamWaitEvent(s, h->gev[1], 0));
+        }
         h->pool.s = s;
         if (st == AMG_ENOTCONV) g_err = "krylov_solve: iteration limit reached";
         if (st == AMG_EBREAKDOWN) g_err = "krylov_solve: breakdown (zero or non-finite denominator)";

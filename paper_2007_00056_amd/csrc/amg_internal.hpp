@@ -32,6 +32,7 @@ void launch_dinv(int n, const int* rp, const int* ci, const double* v, double* d
 // x (row x stores a non-zero a_xu) ascending.  Vertices with more use the CSR
 // rows instead.
 constexpr int kRecOverflow = 1 << 16;
+constexpr int kHemLdsRows = 32768;  // passes up to this size keep their matching state in LDS
 template <int SIDE>
 struct alignas(4 * (SIDE + 1) * 2) HemRecT {
     int hdr;  // #higher | #lower << 8 | kRecOverflow
@@ -52,6 +53,7 @@ struct HemWork {
     int* wl[2];       // [n] ready worklists (ping-pong)
     int* cnt;         // [8] worklist size ring, symmetry check, round count, guard
     int* err;
+    int round_grid = 96;  // blocks of a one-launch-per-round pass
 };
 // w.cnt must be zeroed before the call.
 void launch_hem_init(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
@@ -68,8 +70,8 @@ void launch_leader_flags(int n, const int* mate, int* flag, hipStream_t s);
 void launch_assign_ids(int n, const int* mate, const int* ids, int* agg, int* lead, hipStream_t s);
 
 // Galerkin product of one matching pass (aggregates of size <= 2).
-void launch_rap_count(int nc, const int* lead, const int* mate, const int* rp, const int* ci, const int* agg,
-                      int* rowcnt, int* ovf, int* novf, hipStream_t s);
+void launch_rap_count(int nmax, const int* ncp, const int* lead, const int* mate, const int* rp, const int* ci,
+                      const int* agg, int* rowcnt, int* ovf, int* novf, hipStream_t s);
 void launch_rap_count_slow(int nc, const int* ovf, const int* novf, const int* lead, const int* mate, const int* rp,
                            const int* ci, const int* agg, int* rowcnt, hipStream_t s);
 void launch_rap_fill(int nc, const int* lead, const int* mate, const int* rp, const int* ci, const double* v,

@@ -1,0 +1,234 @@
+// Serving loop: independent solve requests run concurrently on one GPU.
+//
+// Each worker thread owns a HIP stream and runs whole requests (setup,
+// Krylov solve, teardown) through the public entry points; kernels of
+// different requests overlap on the device.  Requests are admitted in arrival
+// order while the footprints of the requests in flight fit the budget; a
+// request waits at the head of the queue until enough finish.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "hemamg.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    amg_csr A{};
+    const double* b = nullptr;
+    double* x = nullptr;
+    int32_t method = 0;
+    double rtol = 0.0;
+    int32_t maxit = 0;
+    uint64_t foot = 0;
+    Clock::time_point t_submit;
+    Clock::time_point t_done;
+    bool done = false;
+    amg_status st = AMG_OK;
+    amg_info info{};
+};
+
+uint64_t footprint(int32_t n, int64_t nnz, const amg_params& p) {
+    const uint64_t N = (uint64_t)(n > 0 ? n : 0), Z = (uint64_t)(nnz > 0 ? nnz : 0);
+    const uint64_t e = p.precond_fp32 ? 4 : 8;
+    const uint64_t dense = 8ull * 1024 * 1024;  // coarsest inverse (<= 1024 rows)
+    // persistent: level-0 D^{-1}; coarse CSR (row pointers sized by the finer
+    // level), D^{-1}, maps and member lists over <= N rows and <= Z entries;
+    // V-cycle vectors; float copies; Krylov vectors; reduction partials
+    uint64_t b = 8 * N + (8 * N + 12 * Z + 8 * N + 8 * N + 16 * N) + dense;
+    b += 5 * e * 2 * N + e * N;
+    if (p.precond_fp32) b += 4 * 2 * Z + 4 * 2 * N;
+    b += 10 * 8 * N + (1u << 20);
+    // setup scratch at its peak: matching records and state, numbering,
+    // Galerkin counts, the intermediate operator of a two-pass level, the
+    // dense factorisation
+    b += 256 * N + Z + 60 * N + (4 * N + 12 * Z) + dense;
+    return b;
+}
+
+}  // namespace
+
+struct amg_server {
+    amg_server_config cfg{};
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<int64_t> pending;
+    std::unordered_map<int64_t, Request*> reqs;
+    int64_t next_id = 1;
+    uint64_t in_use = 0;
+    int active = 0;
+    bool stopping = false;
+    std::vector<std::thread> threads;
+
+    void worker() {
+        if (hipSetDevice(device) != hipSuccess) return;
+        hipStream_t s = nullptr;
+        const bool have_stream = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+        for (;;) {
+            Request* r = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] {
+                    if (pending.empty()) return stopping;
+                    const Request* f = reqs[pending.front()];
+                    return active == 0 || in_use + f->foot <= cfg.hbm_budget_bytes;
+                });
+                if (pending.empty()) break;  // stopping and drained
+                r = reqs[pending.front()];
+                pending.pop_front();
+                in_use += r->foot;
+                ++active;
+            }
+            run(r, have_stream ? s : nullptr, have_stream);
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                in_use -= r->foot;
+                --active;
+                r->done = true;
+                r->t_done = Clock::now();
+            }
+            cv_done.notify_all();
+            cv_work.notify_all();
+        }
+        if (have_stream) (void)hipStreamDestroy(s);
+    }
+
+    void run(Request* r, hipStream_t s, bool have_stream) {
+        if (!have_stream) {
+            r->st = AMG_EHIP;
+            r->info.status = AMG_EHIP;
+            return;
+        }
+        amg_hier* h = nullptr;
+        amg_status st = amg_setup(&r->A, &cfg.params, s, &h);
+        if (st == AMG_OK) st = krylov_solve(h, r->method, r->b, r->x, r->rtol, r->maxit, s, &r->info);
+        else r->info.status = st;
+        if (h) (void)amg_destroy(h);
+        r->st = st;
+    }
+};
+
+extern "C" {
+
+amg_status amg_footprint_bytes(int32_t n, int64_t nnz, const amg_params* params, uint64_t* bytes) {
+    if (!bytes || n < 0 || nnz < 0) return AMG_EINVAL;
+    amg_params p;
+    if (params) p = *params;
+    else amg_params_default(&p);
+    *bytes = footprint(n, nnz, p);
+    return AMG_OK;
+}
+
+amg_status amg_server_config_default(amg_server_config* c) {
+    if (!c) return AMG_EINVAL;
+    c->workers = 4;
+    c->pad = 0;
+    c->hbm_budget_bytes = 64ull << 30;
+    return amg_params_default(&c->params);
+}
+
+amg_status amg_server_create(const amg_server_config* c, amg_server** out) {
+    if (out) *out = nullptr;
+    if (!out) return AMG_EINVAL;
+    amg_server_config cfg;
+    if (c) cfg = *c;
+    else amg_server_config_default(&cfg);
+    if (cfg.workers < 1 || cfg.workers > 64 || cfg.hbm_budget_bytes == 0) return AMG_EINVAL;
+    amg_server* s = new (std::nothrow) amg_server();
+    if (!s) return AMG_ENOMEM;
+    s->cfg = cfg;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return AMG_EHIP;
+    }
+    try {
+        for (int i = 0; i < cfg.workers; ++i) s->threads.emplace_back([s] { s->worker(); });
+    } catch (...) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stopping = true;
+        }
+        s->cv_work.notify_all();
+        for (auto& t : s->threads) t.join();
+        delete s;
+        return AMG_ENOMEM;
+    }
+    *out = s;
+    return AMG_OK;
+}
+
+amg_status amg_server_submit(amg_server* s, const amg_csr* A, const double* b, double* x, int32_t method,
+                             double rtol, int32_t maxit, int64_t* ticket) {
+    if (!s || !A || !b || !x || !ticket) return AMG_EINVAL;
+    Request* r = new (std::nothrow) Request();
+    if (!r) return AMG_ENOMEM;
+    r->A = *A;
+    r->b = b;
+    r->x = x;
+    r->method = method;
+    r->rtol = rtol;
+    r->maxit = maxit;
+    r->foot = footprint(A->n, A->nnz, s->cfg.params);
+    if (r->foot > s->cfg.hbm_budget_bytes) {
+        delete r;
+        return AMG_EINVAL;
+    }
+    r->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stopping) {
+            delete r;
+            return AMG_EINVAL;
+        }
+        const int64_t id = s->next_id++;
+        s->reqs[id] = r;
+        s->pending.push_back(id);
+        *ticket = id;
+    }
+    s->cv_work.notify_one();
+    return AMG_OK;
+}
+
+amg_status amg_server_wait(amg_server* s, int64_t ticket, amg_info* info, double* latency_ms) {
+    if (!s) return AMG_EINVAL;
+    Request* r = nullptr;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return AMG_EINVAL;
+        r = it->second;
+        s->cv_done.wait(lk, [&] { return r->done; });
+        s->reqs.erase(ticket);  // the map may have changed while waiting
+    }
+    if (info) *info = r->info;
+    if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+    const amg_status st = r->st;
+    delete r;
+    return st;
+}
+
+amg_status amg_server_destroy(amg_server* s) {
+    if (!s) return AMG_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->cv_work.notify_all();
+    for (auto& t : s->threads) t.join();
+    for (auto& kv : s->reqs) delete kv.second;
+    delete s;
+    return AMG_OK;
+}
+
+}  // extern "C"

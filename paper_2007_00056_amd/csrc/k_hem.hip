@@ -1,0 +1,663 @@
+// Node-based heavy edge matching (Section 2.1.1, Algorithm 2) on the GPU.
+//
+// Visiting vertices in ascending order (Algorithm 2) is the greedy matching
+// over edges {u < w} (a_uw stored in row u, non-zero) in increasing key
+// (u, -|a_uw|, w).  Greedy matching in a strict edge order equals repeated
+// rounds of locally dominant edges: each undecided vertex points along its
+// smallest-key edge to an undecided neighbour, mutual pointers match, and a
+// vertex with no undecided neighbour is a singleton.  Under this key a vertex
+// points to its smallest undecided lower neighbour if it has one, otherwise
+// to its heaviest undecided higher neighbour (lowest index on ties).  Only a
+// vertex without undecided lower neighbours ("ready") can start a match, so
+// each round scans a worklist of ready vertices, and a per-vertex count of
+// undecided lower neighbours adds vertices to the next list as they become
+// ready.  Decisions carry the round number: a vertex counts as undecided in
+// round r while its stamp is >= r, so all reads in a round see the state at
+// the start of the round whatever the interleaving.
+//
+// Three drivers run the rounds: one kernel launch per round over the whole
+// GPU (large passes), one workgroup running every round with the state in
+// global memory (mid-size passes), and one workgroup with the round stamps,
+// ready counters and worklists in LDS (small passes), where a round costs
+// two global loads (the two adjacency records) instead of eight.
+#include <cstdint>
+
+#include "amg_device.hpp"
+#include "amg_internal.hpp"
+
+namespace amg {
+
+namespace {
+constexpr int BS = 256;
+inline int blocks_for(int64_t work, int bs = BS, int cap = 1 << 30) {
+    int64_t b = (work + bs - 1) / bs;
+    if (b < 1) b = 1;
+    return (int)(b < cap ? b : cap);
+}
+
+__device__ __forceinline__ int find_col(const int* __restrict__ ci, int lo, int hi, int c) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int x = ci[mid];
+        if (x == c) return mid;
+        if (x < c) lo = mid + 1;
+        else hi = mid;
+    }
+    return -1;
+}
+}  // namespace
+
+// counters: cnt[0..2] worklist sizes (ring of 3), cnt[5] sum over rows of
+// (#upper - #lower) entries, cnt[6] the number of rounds that had work,
+// cnt[7] set when a single-workgroup pass hit its round limit.
+template <int SIDE>
+__global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                 const double* __restrict__ v, uint8_t* __restrict__ lowok,
+                                                 HemRecT<SIDE>* __restrict__ rec, int* __restrict__ lcnt,
+                                                 int* __restrict__ dec, int* __restrict__ mate,
+                                                 int* __restrict__ wl0, int* cnt, int* err) {
+    const int y = blockIdx.x * BS + threadIdx.x;
+    if (y >= n) return;
+    dec[y] = kUndecided;
+    mate[y] = -1;
+    int c = 0, nlow = 0, nup = 0, bad = 0, nh = 0, nl = 0;
+    bool ovf = false;
+    int hj[SIDE], lx[SIDE];
+    double hw[SIDE];
+#pragma unroll
+    for (int t = 0; t < SIDE; ++t) {
+        hj[t] = -1;
+        lx[t] = -1;
+        hw[t] = 0.0;
+    }
+    for (int k = rp[y]; k < rp[y + 1]; ++k) {
+        const int u = ci[k];
+        uint8_t ok = 0;
+        if (u < y) {
+            ++nlow;
+            const int pos = find_col(ci, rp[u], rp[u + 1], y);
+            if (pos < 0) bad = 1;
+            else if (v[pos] != 0.0) ok = 1;
+            if (ok) {  // lower edge-neighbour, columns arrive ascending
+                if (nl < SIDE) {
+#pragma unroll
+                    for (int t = 0; t < SIDE; ++t)
+                        if (t == nl) lx[t] = u;
+                    ++nl;
+                } else {
+                    ovf = true;
+                }
+            }
+        } else if (u > y) {
+            ++nup;
+            const double a = v[k];
+            if (a != 0.0) {  // higher neighbour: keep sorted by |a| descending, column ascending
+                if (nh < SIDE) {
+                    const double w = fabs(a);
+                    int pos = 0;
+#pragma unroll
+                    for (int t = 0; t < SIDE; ++t)
+                        if (t < nh && hw[t] >= w) pos = t + 1;
+#pragma unroll
+                    for (int t = SIDE - 1; t > 0; --t)
+                        if (t > pos && t <= nh) {
+                            hw[t] = hw[t - 1];
+                            hj[t] = hj[t - 1];
+                        }
+#pragma unroll
+                    for (int t = 0; t < SIDE; ++t)
+                        if (t == pos) {
+                            hw[t] = w;
+                            hj[t] = u;
+                        }
+                    ++nh;
+                } else {
+                    ovf = true;
+                }
+            }
+        }
+        lowok[k] = ok;
+        c += ok;
+    }
+    HemRecT<SIDE> R;
+    R.hdr = nh | (nl << 8) | (ovf ? kRecOverflow : 0);
+#pragma unroll
+    for (int t = 0; t < SIDE; ++t) {
+        R.h[t] = hj[t];
+        R.l[t] = lx[t];
+    }
+    R.pad = 0;
+    rec[y] = R;
+    lcnt[y] = c;
+    if (bad) atomicOr(err, ERR_NONSYM);
+    if (nup != nlow) atomicAdd(&cnt[5], nup - nlow);
+    if (c == 0) wl0[atomicAdd(&cnt[0], 1)] = y;
+}
+
+namespace {
+// Read-only inputs of a pass and the partner output.
+struct HemState {
+    const int* __restrict__ rp;
+    const int* __restrict__ ci;
+    const double* __restrict__ v;
+    const uint8_t* __restrict__ lowok;
+    const void* __restrict__ rec;  // HemRecT<SIDE>[n]
+    int* mate;
+};
+
+// Round stamps and ready counters in global memory (atomics at SCOPE).
+template <int SCOPE>
+struct GlobalSt {
+    int* dec;
+    int* lcnt;
+    __device__ __forceinline__ int get(int i) const { return dec[i]; }
+    __device__ __forceinline__ void set(int i, int r) const { dec[i] = r; }
+    // returns the count before the decrement
+    __device__ __forceinline__ int drop(int y) const {
+        return __hip_atomic_fetch_add(&lcnt[y], -1, __ATOMIC_RELAXED, SCOPE);
+    }
+};
+
+// The same in LDS: 16-bit stamps (0xffff = undecided) and 16-bit counters
+// packed two to a word.  A counter is only decremented while positive, so
+// the subtraction never borrows from its neighbour.
+struct LdsSt {
+    uint16_t* dec;
+    unsigned* lcnt2;
+    __device__ __forceinline__ int get(int i) const { return dec[i]; }
+    __device__ __forceinline__ void set(int i, int r) const { dec[i] = (uint16_t)r; }
+    __device__ __forceinline__ int drop(int y) const {
+        const unsigned sh = 16u * (unsigned)(y & 1);
+        const unsigned old = atomicSub(&lcnt2[y >> 1], 1u << sh);
+        return (int)((old >> sh) & 0xffffu);
+    }
+};
+
+// Appends to the next worklist through a block-local LDS list of element
+// type E; entries that do not fit go to a global list.
+template <class E>
+struct Appender {
+    E* s_list;
+    int* s_cnt;
+    int cap;
+    int* gout;
+    int* gcnt;
+    __device__ __forceinline__ void push(int x) const {
+        const int p = atomicAdd(s_cnt, 1);
+        if (p < cap) s_list[p] = (E)x;
+        else gout[atomicAdd(gcnt, 1)] = x;
+    }
+};
+
+constexpr int HEM_WIN = 8;  // row entries whose loads are issued together
+
+// x has just been decided: its higher neighbours lose one undecided lower
+// neighbour; those that reach zero are ready for the next round.  The
+// counter updates of a window are issued before any result is used.
+template <class St, class Ap>
+__device__ __forceinline__ void hem_release(const HemState& S, const St& st, int x, const Ap& A) {
+    const int e0 = S.rp[x], e1 = S.rp[x + 1];
+    for (int b = e0; b < e1; b += HEM_WIN) {
+        int ys[HEM_WIN], old[HEM_WIN];
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t) {
+            const int e = b + t;
+            ys[t] = -1;
+            if (e < e1) {
+                const int y = S.ci[e];
+                if (y > x && S.v[e] != 0.0) ys[t] = y;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t) old[t] = ys[t] >= 0 ? st.drop(ys[t]) : 0;
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t)
+            if (ys[t] >= 0 && old[t] == 1) A.push(ys[t]);
+    }
+}
+
+// Heaviest undecided higher neighbour of u (lowest index on ties), or -1.
+template <class St>
+__device__ __forceinline__ int hem_best(const HemState& S, const St& st, int r, int u, int e0, int e1) {
+    int best = -1;
+    double k = -1.0;
+    for (int b = e0; b < e1; b += HEM_WIN) {
+        int js[HEM_WIN];
+        double ws[HEM_WIN];
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t) {
+            const int e = b + t;
+            js[t] = -1;
+            ws[t] = 0.0;
+            if (e < e1) {
+                const int j = S.ci[e];
+                const double a = S.v[e];
+                if (j > u && a != 0.0) {
+                    js[t] = j;
+                    ws[t] = fabs(a);
+                }
+            }
+        }
+        bool und[HEM_WIN];
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t) und[t] = js[t] >= 0 && st.get(js[t]) >= r;
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t)
+            if (und[t] && ws[t] > k) {  // ascending column order: strict '>' keeps the lowest index
+                k = ws[t];
+                best = js[t];
+            }
+    }
+    return best;
+}
+
+// Smallest undecided lower neighbour of w (over edges (x, w) stored non-zero
+// in row x), or -1.
+template <class St>
+__device__ __forceinline__ int hem_back(const HemState& S, const St& st, int r, int w) {
+    const int e0 = S.rp[w], e1 = S.rp[w + 1];
+    for (int b = e0; b < e1; b += HEM_WIN) {
+        int xs[HEM_WIN];
+        bool stop = false;
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t) {
+            const int e = b + t;
+            xs[t] = -1;
+            if (e < e1) {
+                const int x = S.ci[e];
+                if (x >= w) stop = true;
+                else if (S.lowok[e]) xs[t] = x;
+            }
+        }
+        bool und[HEM_WIN];
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t) und[t] = xs[t] >= 0 && st.get(xs[t]) >= r;
+#pragma unroll
+        for (int t = 0; t < HEM_WIN; ++t)
+            if (und[t]) return xs[t];  // columns ascend: the first is the smallest
+        if (stop) break;
+    }
+    return -1;
+}
+
+// Counter updates for the higher neighbours listed in a record, all issued
+// before any result is used.
+template <class St, int SIDE, class Ap>
+__device__ __forceinline__ void rec_release(const HemState& S, const St& st, const HemRecT<SIDE>& R, int x,
+                                            const Ap& A) {
+    if (R.hdr & kRecOverflow) {
+        hem_release(S, st, x, A);
+        return;
+    }
+    const int nh = R.hdr & 255;
+    int old[SIDE];
+#pragma unroll
+    for (int t = 0; t < SIDE; ++t) old[t] = t < nh ? st.drop(R.h[t]) : 0;
+#pragma unroll
+    for (int t = 0; t < SIDE; ++t)
+        if (t < nh && old[t] == 1) A.push(R.h[t]);
+}
+
+// Round r for a ready vertex u.  Records list u's higher neighbours in
+// preference order (heaviest first, lowest index on ties) and the target's
+// lower edge-neighbours in ascending order, so "first undecided entry" is the
+// pointer of either side.  With WAVE_OK, a vertex whose record (or its
+// target's) overflowed is not handled here: the function returns true and
+// the caller hands it to a whole wave (hem_visit_wave) later in the round.
+template <class St, int SIDE, bool WAVE_OK, class Ap>
+__device__ __forceinline__ bool hem_visit(const HemState& S, const St& st, int r, int u, const Ap& A) {
+    const HemRecT<SIDE>* __restrict__ recs = static_cast<const HemRecT<SIDE>*>(S.rec);
+    const HemRecT<SIDE> R = recs[u];
+    if (st.get(u) < r) return false;  // decided earlier (as a match target): stale entry
+    if (WAVE_OK && (R.hdr & kRecOverflow)) return true;
+    int best = -1;
+    if (R.hdr & kRecOverflow) {
+        best = hem_best(S, st, r, u, S.rp[u], S.rp[u + 1]);
+    } else {
+        const int nh = R.hdr & 255;
+        int d[SIDE];
+#pragma unroll
+        for (int t = 0; t < SIDE; ++t) d[t] = t < nh ? st.get(R.h[t]) : -1;
+#pragma unroll
+        for (int t = SIDE - 1; t >= 0; --t)
+            if (t < nh && d[t] >= r) best = R.h[t];
+    }
+    if (best < 0) {  // no undecided neighbour: unaggregated singleton
+        st.set(u, r);
+        S.mate[u] = -1;
+        rec_release(S, st, R, u, A);
+        return false;
+    }
+    const HemRecT<SIDE> B = recs[best];
+    if (WAVE_OK && (B.hdr & kRecOverflow)) return true;
+    int back = -1;
+    if (B.hdr & kRecOverflow) {
+        back = hem_back(S, st, r, best);
+    } else {
+        const int nl = (B.hdr >> 8) & 255;
+        int d[SIDE];
+#pragma unroll
+        for (int t = 0; t < SIDE; ++t) d[t] = t < nl ? st.get(B.l[t]) : -1;
+#pragma unroll
+        for (int t = SIDE - 1; t >= 0; --t)
+            if (t < nl && d[t] >= r) back = B.l[t];
+    }
+    if (back == u) {  // best points back: mutual, matched
+        st.set(u, r);
+        st.set(best, r);
+        S.mate[u] = best;
+        S.mate[best] = u;
+        rec_release(S, st, R, u, A);
+        rec_release(S, st, B, best, A);
+    } else {
+        A.push(u);  // still ready, retry next round
+    }
+    return false;
+}
+
+// Wave reductions of the cooperative visit.
+__device__ __forceinline__ void wave_best(double& w, int& j) {  // |a| descending, column ascending
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double ow = __shfl_xor(w, off);
+        const int oj = __shfl_xor(j, off);
+        if (ow > w || (ow == w && oj < j)) {
+            w = ow;
+            j = oj;
+        }
+    }
+}
+__device__ __forceinline__ int wave_min(int x) {
+    for (int off = kWave / 2; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off));
+    return x;
+}
+// first lane (in list order) whose entry is undecided, or -1
+__device__ __forceinline__ int wave_first(bool und, int val) {
+    const unsigned long long m = __ballot(und);
+    return m ? __shfl(val, __ffsll((long long)m) - 1) : -1;
+}
+
+// Release of x by a whole wave: its record's higher-neighbour list, or its
+// CSR row when the record overflowed, spread over the lanes.
+template <class St, class Ap>
+__device__ __forceinline__ void wave_release(const HemState& S, const St& st, int x, int hdr, int myh,
+                                             const Ap& A) {
+    const int lane = threadIdx.x % kWave;
+    if (hdr & kRecOverflow) {
+        for (int e = S.rp[x] + lane; e < S.rp[x + 1]; e += kWave) {
+            const int y = S.ci[e];
+            if (y > x && S.v[e] != 0.0 && st.drop(y) == 1) A.push(y);
+        }
+    } else if (lane < (hdr & 255)) {
+        if (st.drop(myh) == 1) A.push(myh);
+    }
+}
+
+// The visit of hem_visit with all 64 lanes of a wave on one vertex u (u is
+// wave-uniform): row scans take one load step per 64 entries and the
+// choices are wave reductions, so long rows cost a few dependent loads.
+template <class St, int SIDE, class Ap>
+__device__ __forceinline__ void hem_visit_wave(const HemState& S, const St& st, int r, int u, const Ap& A) {
+    const int lane = threadIdx.x % kWave;
+    const int* __restrict__ ru = reinterpret_cast<const int*>(static_cast<const HemRecT<SIDE>*>(S.rec) + u);
+    const int hdr = ru[0];
+    const int myh = lane < SIDE ? ru[1 + lane] : -1;
+    if (st.get(u) < r) return;
+    int best;
+    if (hdr & kRecOverflow) {
+        double bw = -1.0;
+        int bj = INT_MAX;
+        for (int e = S.rp[u] + lane; e < S.rp[u + 1]; e += kWave) {
+            const int j = S.ci[e];
+            const double a = S.v[e];
+            if (j > u && a != 0.0 && st.get(j) >= r) {
+                const double w = fabs(a);
+                if (w > bw || (w == bw && j < bj)) {
+                    bw = w;
+                    bj = j;
+                }
+            }
+        }
+        wave_best(bw, bj);
+        best = bw < 0.0 ? -1 : bj;
+    } else {
+        best = wave_first(lane < (hdr & 255) && st.get(myh) >= r, myh);
+    }
+    if (best < 0) {
+        if (lane == 0) {
+            st.set(u, r);
+            S.mate[u] = -1;
+        }
+        wave_release(S, st, u, hdr, myh, A);
+        return;
+    }
+    const int* __restrict__ rb = reinterpret_cast<const int*>(static_cast<const HemRecT<SIDE>*>(S.rec) + best);
+    const int bhdr = rb[0];
+    const int bh = lane < SIDE ? rb[1 + lane] : -1;
+    int back;
+    if (bhdr & kRecOverflow) {
+        int mx = INT_MAX;
+        for (int e = S.rp[best] + lane; e < S.rp[best + 1]; e += kWave) {
+            const int x = S.ci[e];
+            if (x < best && S.lowok[e] && st.get(x) >= r) mx = min(mx, x);
+        }
+        mx = wave_min(mx);
+        back = mx == INT_MAX ? -1 : mx;
+    } else {
+        const int bl = lane < SIDE ? rb[1 + SIDE + lane] : -1;
+        back = wave_first(lane < ((bhdr >> 8) & 255) && st.get(bl) >= r, bl);
+    }
+    if (back == u) {
+        if (lane == 0) {
+            st.set(u, r);
+            st.set(best, r);
+            S.mate[u] = best;
+            S.mate[best] = u;
+        }
+        wave_release(S, st, u, hdr, myh, A);
+        wave_release(S, st, best, bhdr, bh, A);
+    } else if (lane == 0) {
+        A.push(u);
+    }
+}
+
+// One round over a list of ready vertices (items idx < m, fetched by `item`):
+// single-lane visits first, then the deferred long rows one wave each.
+template <class St, int SIDE, int NT, class Ap, class Item>
+__device__ __forceinline__ void hem_round_body(const HemState& S, const St& st, int r, int m, int first, int stride,
+                                               const Item& item, const Ap& A, int* s_wave, int* s_nw, int wcap) {
+    for (int idx = first; idx < m; idx += stride) {
+        const int u = item(idx);
+        if (hem_visit<St, SIDE, true>(S, st, r, u, A)) {
+            const int p = atomicAdd(s_nw, 1);
+            if (p < wcap) s_wave[p] = u;
+            else hem_visit<St, SIDE, false>(S, st, r, u, A);
+        }
+    }
+    __syncthreads();
+    const int nw = min(*s_nw, wcap);
+    for (int k = threadIdx.x / kWave; k < nw; k += NT / kWave) hem_visit_wave<St, SIDE>(S, st, r, s_wave[k], A);
+    __syncthreads();
+}
+
+constexpr int HEM_BS = 512;
+constexpr int HEM_LCAP = 4096;
+constexpr int HEM_BS1 = 1024;
+constexpr int HEM_LCAP1 = 8192;
+constexpr int HEM_WCAP = 1024;  // vertices deferred to the wave path per block and round
+constexpr int HL_LCAP = 4096;   // LDS worklist entries of the LDS-state driver
+constexpr int HL_WCAP = 512;
+}  // namespace
+
+// One round over the worklist; the decided vertices' neighbours that become
+// ready, and the ready vertices that failed, form the next list.
+template <int SIDE>
+__global__ __launch_bounds__(HEM_BS) void k_hem_round(int r, HemState S, int* dec, int* lcnt,
+                                                  const int* __restrict__ win, int* __restrict__ wout, int* cnt,
+                                                  int slot_in, int slot_out, int zero_w) {
+    __shared__ int s_list[HEM_LCAP];
+    __shared__ int s_wave[HEM_WCAP];
+    __shared__ int s_cnt, s_base, s_nw;
+    if (threadIdx.x == 0) {
+        s_cnt = 0;
+        s_nw = 0;
+        if (blockIdx.x == 0) cnt[zero_w] = 0;
+    }
+    __syncthreads();
+    const int m = cnt[slot_in];
+    if (m > 0 && blockIdx.x == 0 && threadIdx.x == 0) cnt[6] = r + 1;  // rounds with work
+    const Appender<int> A{s_list, &s_cnt, HEM_LCAP, wout, &cnt[slot_out]};
+    const GlobalSt<__HIP_MEMORY_SCOPE_AGENT> st{dec, lcnt};
+    hem_round_body<GlobalSt<__HIP_MEMORY_SCOPE_AGENT>, SIDE, HEM_BS>(
+        S, st, r, m, blockIdx.x * HEM_BS + threadIdx.x, gridDim.x * HEM_BS, [&](int i) { return win[i]; }, A, s_wave,
+        &s_nw, HEM_WCAP);
+    const int k = min(s_cnt, HEM_LCAP);
+    if (threadIdx.x == 0 && k > 0) s_base = atomicAdd(&cnt[slot_out], k);
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += HEM_BS) wout[s_base + i] = s_list[i];
+}
+
+// Mid-size passes: one workgroup runs every round, separated by barriers,
+// with the state in global memory.  Each round decides at least the smallest
+// undecided vertex, so n + 1 rounds always suffice; the bound only guards
+// against invalid input.
+template <int SIDE>
+__global__ __launch_bounds__(HEM_BS1) void k_hem_all(int n, HemState S, int* dec, int* lcnt, int* wl0, int* wl1,
+                                                     int* cnt) {
+    __shared__ int s_list[HEM_LCAP1];
+    __shared__ int s_wave[HEM_WCAP];
+    __shared__ int s_cnt, s_next, s_m, s_nw;
+    if (threadIdx.x == 0) s_m = cnt[0];
+    __syncthreads();
+    const GlobalSt<__HIP_MEMORY_SCOPE_WORKGROUP> st{dec, lcnt};
+    int* win = wl0;
+    int* wout = wl1;
+    int r = 0;
+    for (; r <= n + 1; ++r) {
+        const int m = s_m;
+        if (m == 0) break;
+        if (threadIdx.x == 0) {
+            s_cnt = 0;
+            s_next = 0;
+            s_nw = 0;
+        }
+        __syncthreads();
+        const Appender<int> A{s_list, &s_cnt, HEM_LCAP1, wout, &s_next};
+        hem_round_body<GlobalSt<__HIP_MEMORY_SCOPE_WORKGROUP>, SIDE, HEM_BS1>(
+            S, st, r, m, threadIdx.x, HEM_BS1, [&](int i) { return win[i]; }, A, s_wave, &s_nw, HEM_WCAP);
+        const int k = min(s_cnt, HEM_LCAP1);
+        const int base = s_next;
+        for (int i = threadIdx.x; i < k; i += HEM_BS1) wout[base + i] = s_list[i];
+        __syncthreads();
+        if (threadIdx.x == 0) s_m = base + k;
+        int* t = win;
+        win = wout;
+        wout = t;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cnt[6] = r;
+        if (s_m != 0) cnt[7] = 1;
+    }
+}
+
+// Small passes (n <= kHemLdsRows): one workgroup with the round stamps, the
+// ready counters and the worklists in LDS.  A list is its LDS part followed
+// by a global part for entries beyond the LDS capacity.
+template <int SIDE>
+__global__ __launch_bounds__(HEM_BS1) void k_hem_lds(int n, HemState S, const int* __restrict__ lcnt_g, int* wl0,
+                                                     int* wl1, int* cnt) {
+    __shared__ uint16_t s_dec[kHemLdsRows];
+    __shared__ unsigned s_lcnt2[kHemLdsRows / 2];
+    __shared__ uint16_t s_la[HL_LCAP], s_lb[HL_LCAP];
+    __shared__ int s_wave[HL_WCAP];
+    __shared__ int s_cnt, s_gnext, s_nw;
+    for (int i = threadIdx.x; i < n; i += HEM_BS1) s_dec[i] = 0xffff;
+    for (int i = threadIdx.x; 2 * i < n; i += HEM_BS1) {
+        const unsigned lo = (unsigned)lcnt_g[2 * i];
+        const unsigned hi = 2 * i + 1 < n ? (unsigned)lcnt_g[2 * i + 1] : 0u;
+        s_lcnt2[i] = lo | (hi << 16);
+    }
+    __syncthreads();
+    const LdsSt st{s_dec, s_lcnt2};
+    uint16_t* cur = s_la;
+    uint16_t* nxt = s_lb;
+    int* gin = wl0;
+    int* gout = wl1;
+    int kl = 0, kg = cnt[0];  // the initial list is all in global memory
+    int r = 0;
+    for (; r <= n + 1; ++r) {
+        const int m = kl + kg;
+        if (m == 0) break;
+        if (threadIdx.x == 0) {
+            s_cnt = 0;
+            s_gnext = 0;
+            s_nw = 0;
+        }
+        __syncthreads();
+        const Appender<uint16_t> A{nxt, &s_cnt, HL_LCAP, gout, &s_gnext};
+        const uint16_t* c = cur;
+        const int* g = gin;
+        const int klc = kl;
+        hem_round_body<LdsSt, SIDE, HEM_BS1>(
+            S, st, r, m, threadIdx.x, HEM_BS1, [&](int i) { return i < klc ? (int)c[i] : g[i - klc]; }, A, s_wave,
+            &s_nw, HL_WCAP);
+        kl = min(s_cnt, HL_LCAP);
+        kg = s_gnext;
+        __syncthreads();  // every thread has read the counts before the next reset
+        uint16_t* t = cur;
+        cur = nxt;
+        nxt = t;
+        int* tg = gin;
+        gin = gout;
+        gout = tg;
+    }
+    if (threadIdx.x == 0) {
+        cnt[6] = r;
+        if (kl + kg != 0) cnt[7] = 1;
+    }
+}
+
+#define AMG_HEM_SIDE(side, CALL) \
+    switch (side) {                \
+        case 7: CALL(7); break;    \
+        case 15: CALL(15); break;  \
+        default: CALL(31); break;  \
+    }
+
+void launch_hem_init(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
+#define CALL(SD)                                                                                  \
+    hipLaunchKernelGGL(k_hem_init<SD>, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, w.lowok, \
+                       static_cast<HemRecT<SD>*>(w.rec), w.lcnt, w.dec, w.mate, w.wl[0], w.cnt, w.err)
+    AMG_HEM_SIDE(w.side, CALL)
+#undef CALL
+}
+
+int hem_next_count_slot(int round) { return round % 3; }
+
+void launch_hem_round(int r, int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
+    const int g = blocks_for(n, HEM_BS, w.round_grid);
+    const HemState S{rp, ci, v, w.lowok, w.rec, w.mate};
+#define CALL(SD)                                                                                            \
+    hipLaunchKernelGGL(k_hem_round<SD>, dim3(g), dim3(HEM_BS), 0, s, r, S, w.dec, w.lcnt, w.wl[r & 1],       \
+                       w.wl[(r + 1) & 1], w.cnt, r % 3, (r + 1) % 3, (r + 2) % 3)
+    AMG_HEM_SIDE(w.side, CALL)
+#undef CALL
+}
+
+void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
+    const HemState S{rp, ci, v, w.lowok, w.rec, w.mate};
+    if (n <= kHemLdsRows) {
+#define CALL(SD) \
+    hipLaunchKernelGGL(k_hem_lds<SD>, dim3(1), dim3(HEM_BS1), 0, s, n, S, w.lcnt, w.wl[0], w.wl[1], w.cnt)
+        AMG_HEM_SIDE(w.side, CALL)
+#undef CALL
+    } else {
+#define CALL(SD) \
+    hipLaunchKernelGGL(k_hem_all<SD>, dim3(1), dim3(HEM_BS1), 0, s, n, S, w.dec, w.lcnt, w.wl[0], w.wl[1], w.cnt)
+        AMG_HEM_SIDE(w.side, CALL)
+#undef CALL
+    }
+}
+#undef AMG_HEM_SIDE
+
+}  // namespace amg

@@ -1,7 +1,7 @@
-// Setup-phase kernels: CSR validation and D^{-1}, node-based heavy edge
-// matching (Section 2.1.1, Algorithm 2) as rounds of locally dominant edges,
-// coarse numbering by prefix sum, the 0/1 Galerkin product P^T A P, aggregate
-// member lists, and the dense LU + inverse of the coarsest level.
+// Setup-phase kernels: CSR validation and D^{-1}, coarse numbering of a
+// matching (Algorithm 2) by prefix sum, the 0/1 Galerkin product P^T A P,
+// aggregate member lists, and the dense LU + inverse of the coarsest level.
+// The matching itself is in k_hem.hip.
 #include "amg_device.hpp"
 #include "amg_internal.hpp"
 
@@ -74,420 +74,6 @@ __global__ __launch_bounds__(BS) void k_dinv(int n, const int* __restrict__ rp, 
 void launch_dinv(int n, const int* rp, const int* ci, const double* v, double* dinv, int* err, hipStream_t s) {
     hipLaunchKernelGGL(k_dinv, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, dinv, err);
 }
-
-// ---------------------------------------------------------------------------
-// Heavy edge matching.
-//
-// Visiting vertices in ascending order (Algorithm 2) is the greedy matching
-// over edges {u < w} (a_uw stored in row u, non-zero) in increasing key
-// (u, -|a_uw|, w).  Greedy matching in a strict edge order equals repeated
-// rounds of locally dominant edges: each undecided vertex points along its
-// smallest-key edge to an undecided neighbour, mutual pointers match, and a
-// vertex with no undecided neighbour is a singleton.  Under this key a vertex
-// points to its smallest undecided lower neighbour if it has one, otherwise
-// to its heaviest undecided higher neighbour (lowest index on ties).  Only a
-// vertex without undecided lower neighbours ("ready") can start a match, so
-// each round scans a worklist of ready vertices, and a per-vertex count of
-// undecided lower neighbours adds vertices to the next list as they become
-// ready.  Decisions carry the round number: a vertex counts as undecided in
-// round r while its stamp is >= r, so all reads in a round see the state at
-// the start of the round whatever the interleaving.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int find_col(const int* __restrict__ ci, int lo, int hi, int c) {
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        const int x = ci[mid];
-        if (x == c) return mid;
-        if (x < c) lo = mid + 1;
-        else hi = mid;
-    }
-    return -1;
-}
-
-// counters: cnt[0..2] worklist sizes (ring of 3), cnt[5] sum over rows of
-// (#upper - #lower) entries, cnt[6] the number of rounds that had work,
-// cnt[7] set when the single-workgroup pass hit its round limit.
-template <int SIDE>
-__global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                 const double* __restrict__ v, uint8_t* __restrict__ lowok,
-                                                 HemRecT<SIDE>* __restrict__ rec, int* __restrict__ lcnt,
-                                                 int* __restrict__ dec, int* __restrict__ mate,
-                                                 int* __restrict__ wl0, int* cnt, int* err) {
-    const int y = blockIdx.x * BS + threadIdx.x;
-    if (y >= n) return;
-    dec[y] = kUndecided;
-    mate[y] = -1;
-    int c = 0, nlow = 0, nup = 0, bad = 0, nh = 0, nl = 0;
-    bool ovf = false;
-    int hj[SIDE], lx[SIDE];
-    double hw[SIDE];
-#pragma unroll
-    for (int t = 0; t < SIDE; ++t) {
-        hj[t] = -1;
-        lx[t] = -1;
-        hw[t] = 0.0;
-    }
-    for (int k = rp[y]; k < rp[y + 1]; ++k) {
-        const int u = ci[k];
-        uint8_t ok = 0;
-        if (u < y) {
-            ++nlow;
-            const int pos = find_col(ci, rp[u], rp[u + 1], y);
-            if (pos < 0) bad = 1;
-            else if (v[pos] != 0.0) ok = 1;
-            if (ok) {  // lower edge-neighbour, columns arrive ascending
-                if (nl < SIDE) {
-#pragma unroll
-                    for (int t = 0; t < SIDE; ++t)
-                        if (t == nl) lx[t] = u;
-                    ++nl;
-                } else {
-                    ovf = true;
-                }
-            }
-        } else if (u > y) {
-            ++nup;
-            const double a = v[k];
-            if (a != 0.0) {  // higher neighbour: keep sorted by |a| descending, column ascending
-                if (nh < SIDE) {
-                    const double w = fabs(a);
-                    int pos = 0;
-#pragma unroll
-                    for (int t = 0; t < SIDE; ++t)
-                        if (t < nh && hw[t] >= w) pos = t + 1;
-#pragma unroll
-                    for (int t = SIDE - 1; t > 0; --t)
-                        if (t > pos && t <= nh) {
-                            hw[t] = hw[t - 1];
-                            hj[t] = hj[t - 1];
-                        }
-#pragma unroll
-                    for (int t = 0; t < SIDE; ++t)
-                        if (t == pos) {
-                            hw[t] = w;
-                            hj[t] = u;
-                        }
-                    ++nh;
-                } else {
-                    ovf = true;
-                }
-            }
-        }
-        lowok[k] = ok;
-        c += ok;
-    }
-    HemRecT<SIDE> R;
-    R.hdr = nh | (nl << 8) | (ovf ? kRecOverflow : 0);
-#pragma unroll
-    for (int t = 0; t < SIDE; ++t) {
-        R.h[t] = hj[t];
-        R.l[t] = lx[t];
-    }
-    R.pad = 0;
-    rec[y] = R;
-    lcnt[y] = c;
-    if (bad) atomicOr(err, ERR_NONSYM);
-    if (nup != nlow) atomicAdd(&cnt[5], nup - nlow);
-    if (c == 0) wl0[atomicAdd(&cnt[0], 1)] = y;
-}
-
-namespace {
-struct HemState {
-    const int* __restrict__ rp;
-    const int* __restrict__ ci;
-    const double* __restrict__ v;
-    const uint8_t* __restrict__ lowok;
-    const void* __restrict__ rec;  // HemRecT<SIDE>[n]
-    int* dec;
-    int* mate;
-    int* lcnt;
-};
-
-// Appends to the next worklist through a block-local LDS list; entries that
-// do not fit go straight to global memory.
-struct Appender {
-    int* s_list;
-    int* s_cnt;
-    int cap;
-    int* gout;
-    int* gcnt;
-    __device__ __forceinline__ void push(int x) const {
-        const int p = atomicAdd(s_cnt, 1);
-        if (p < cap) s_list[p] = x;
-        else gout[atomicAdd(gcnt, 1)] = x;
-    }
-};
-
-constexpr int HEM_WIN = 8;  // row entries whose loads are issued together
-
-template <int SCOPE>
-__device__ __forceinline__ int dec_counter(int* p) {
-    return __hip_atomic_fetch_add(p, -1, __ATOMIC_RELAXED, SCOPE);
-}
-
-// x has just been decided: its higher neighbours lose one undecided lower
-// neighbour; those that reach zero are ready for the next round.  The
-// counter updates of a window are issued before any result is used.
-template <int SCOPE>
-__device__ __forceinline__ void hem_release(const HemState& S, int x, const Appender& A) {
-    const int e0 = S.rp[x], e1 = S.rp[x + 1];
-    for (int b = e0; b < e1; b += HEM_WIN) {
-        int ys[HEM_WIN], old[HEM_WIN];
-#pragma unroll
-        for (int t = 0; t < HEM_WIN; ++t) {
-            const int e = b + t;
-            ys[t] = -1;
-            if (e < e1) {
-                const int y = S.ci[e];
-                if (y > x && S.v[e] != 0.0) ys[t] = y;
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < HEM_WIN; ++t) old[t] = ys[t] >= 0 ? dec_counter<SCOPE>(&S.lcnt[ys[t]]) : 0;
-#pragma unroll
-        for (int t = 0; t < HEM_WIN; ++t)
-            if (ys[t] >= 0 && old[t] == 1) A.push(ys[t]);
-    }
-}
-
-// Heaviest undecided higher neighbour of u (lowest index on ties), or -1.
-__device__ __forceinline__ int hem_best(const HemState& S, int r, int u, int e0, int e1) {
-    int best = -1;
-    double k = -1.0;
-    for (int b = e0; b < e1; b += HEM_WIN) {
-        int js[HEM_WIN];
-        double ws[HEM_WIN];
-#pragma unroll
-        for (int t = 0; t < HEM_WIN; ++t) {
-            const int e = b + t;
-            js[t] = -1;
-            ws[t] = 0.0;
-            if (e < e1) {
-                const int j = S.ci[e];
-                const double a = S.v[e];
-                if (j > u && a != 0.0) {
-                    js[t] = j;
-                    ws[t] = fabs(a);
-                }
-            }
-        }
-        bool und[HEM_WIN];
-#pragma unroll
-        for (int t = 0; t < HEM_WIN; ++t) und[t] = js[t] >= 0 && S.dec[js[t]] >= r;
-#pragma unroll
-        for (int t = 0; t < HEM_WIN; ++t)
-            if (und[t] && ws[t] > k) {  // ascending column order: strict '>' keeps the lowest index
-                k = ws[t];
-                best = js[t];
-            }
-    }
-    return best;
-}
-
-// Smallest undecided lower neighbour of w (over edges (x, w) stored non-zero
-// in row x), or -1.
-__device__ __forceinline__ int hem_back(const HemState& S, int r, int w) {
-    const int e0 = S.rp[w], e1 = S.rp[w + 1];
-    for (int b = e0; b < e1; b += HEM_WIN) {
-        int xs[HEM_WIN];
-        bool stop = false;
-#pragma unroll
-        for (int t = 0; t < HEM_WIN; ++t) {
-            const int e = b + t;
-            xs[t] = -1;
-            if (e < e1) {
-                const int x = S.ci[e];
-                if (x >= w) stop = true;
-                else if (S.lowok[e]) xs[t] = x;
-            }
-        }
-        bool und[HEM_WIN];
-#pragma unroll
-        for (int t = 0; t < HEM_WIN; ++t) und[t] = xs[t] >= 0 && S.dec[xs[t]] >= r;
-#pragma unroll
-        for (int t = 0; t < HEM_WIN; ++t)
-            if (und[t]) return xs[t];  // columns ascend: the first is the smallest
-        if (stop) break;
-    }
-    return -1;
-}
-
-// Counter updates for the higher neighbours listed in a record, all issued
-// before any result is used.
-template <int SCOPE, int SIDE>
-__device__ __forceinline__ void rec_release(const HemState& S, const HemRecT<SIDE>& R, int x, const Appender& A) {
-    if (R.hdr & kRecOverflow) {
-        hem_release<SCOPE>(S, x, A);
-        return;
-    }
-    const int nh = R.hdr & 255;
-    int old[SIDE];
-#pragma unroll
-    for (int t = 0; t < SIDE; ++t) old[t] = t < nh ? dec_counter<SCOPE>(&S.lcnt[R.h[t]]) : 0;
-#pragma unroll
-    for (int t = 0; t < SIDE; ++t)
-        if (t < nh && old[t] == 1) A.push(R.h[t]);
-}
-
-// Round r for a ready vertex u.  A vertex counts as undecided while its stamp
-// is >= r, so every read sees the state at the start of the round.  Records
-// list u's higher neighbours in preference order (heaviest first, lowest
-// index on ties) and the target's lower edge-neighbours in ascending order, so
-// "first undecided entry" is the pointer of either side.
-template <int SCOPE, int SIDE>
-__device__ __forceinline__ void hem_visit(const HemState& S, int r, int u, const Appender& A) {
-    const HemRecT<SIDE>* __restrict__ recs = static_cast<const HemRecT<SIDE>*>(S.rec);
-    const HemRecT<SIDE> R = recs[u];
-    const int du = S.dec[u];
-    if (du < r) return;  // decided earlier (as a match target): stale entry
-    int best = -1;
-    if (R.hdr & kRecOverflow) {
-        best = hem_best(S, r, u, S.rp[u], S.rp[u + 1]);
-    } else {
-        const int nh = R.hdr & 255;
-        int d[SIDE];
-#pragma unroll
-        for (int t = 0; t < SIDE; ++t) d[t] = t < nh ? S.dec[R.h[t]] : -1;
-#pragma unroll
-        for (int t = SIDE - 1; t >= 0; --t)
-            if (t < nh && d[t] >= r) best = R.h[t];
-    }
-    if (best < 0) {  // no undecided neighbour: unaggregated singleton
-        S.dec[u] = r;
-        S.mate[u] = -1;
-        rec_release<SCOPE, SIDE>(S, R, u, A);
-        return;
-    }
-    const HemRecT<SIDE> B = recs[best];
-    int back = -1;
-    if (B.hdr & kRecOverflow) {
-        back = hem_back(S, r, best);
-    } else {
-        const int nl = (B.hdr >> 8) & 255;
-        int d[SIDE];
-#pragma unroll
-        for (int t = 0; t < SIDE; ++t) d[t] = t < nl ? S.dec[B.l[t]] : -1;
-#pragma unroll
-        for (int t = SIDE - 1; t >= 0; --t)
-            if (t < nl && d[t] >= r) back = B.l[t];
-    }
-    if (back == u) {  // best points back: mutual, matched
-        S.dec[u] = r;
-        S.dec[best] = r;
-        S.mate[u] = best;
-        S.mate[best] = u;
-        rec_release<SCOPE, SIDE>(S, R, u, A);
-        rec_release<SCOPE, SIDE>(S, B, best, A);
-    } else {
-        A.push(u);  // still ready, retry next round
-    }
-}
-
-constexpr int HEM_BS = 512;
-constexpr int HEM_LCAP = 4096;
-constexpr int HEM_BS1 = 1024;
-constexpr int HEM_LCAP1 = 8192;
-}  // namespace
-
-// One round over the worklist; the decided vertices' neighbours that become
-// ready, and the ready vertices that failed, form the next list.
-template <int SIDE>
-__global__ __launch_bounds__(HEM_BS) void k_hem_round(int r, HemState S, const int* __restrict__ win,
-                                                  int* __restrict__ wout, int* cnt, int slot_in, int slot_out,
-                                                  int zero_w) {
-    __shared__ int s_list[HEM_LCAP];
-    __shared__ int s_cnt, s_base;
-    if (threadIdx.x == 0) {
-        s_cnt = 0;
-        if (blockIdx.x == 0) cnt[zero_w] = 0;
-    }
-    __syncthreads();
-    const int m = cnt[slot_in];
-    if (m > 0 && blockIdx.x == 0 && threadIdx.x == 0) cnt[6] = r + 1;  // rounds with work
-    const Appender A{s_list, &s_cnt, HEM_LCAP, wout, &cnt[slot_out]};
-    for (int idx = blockIdx.x * HEM_BS + threadIdx.x; idx < m; idx += gridDim.x * HEM_BS)
-        hem_visit<__HIP_MEMORY_SCOPE_AGENT, SIDE>(S, r, win[idx], A);
-    __syncthreads();
-    const int k = min(s_cnt, HEM_LCAP);
-    if (threadIdx.x == 0 && k > 0) s_base = atomicAdd(&cnt[slot_out], k);
-    __syncthreads();
-    for (int i = threadIdx.x; i < k; i += HEM_BS) wout[s_base + i] = s_list[i];
-}
-
-// Small matrices: one workgroup runs every round, separated by barriers.
-// Each round decides at least the smallest undecided vertex, so n + 1 rounds
-// always suffice; the bound only guards against invalid input.
-template <int SIDE>
-__global__ __launch_bounds__(HEM_BS1) void k_hem_all(int n, HemState S, int* wl0, int* wl1, int* cnt) {
-    __shared__ int s_list[HEM_LCAP1];
-    __shared__ int s_cnt, s_next, s_m;
-    if (threadIdx.x == 0) s_m = cnt[0];
-    __syncthreads();
-    int* win = wl0;
-    int* wout = wl1;
-    int r = 0;
-    for (; r <= n + 1; ++r) {
-        const int m = s_m;
-        if (m == 0) break;
-        if (threadIdx.x == 0) {
-            s_cnt = 0;
-            s_next = 0;
-        }
-        __syncthreads();
-        const Appender A{s_list, &s_cnt, HEM_LCAP1, wout, &s_next};
-        for (int idx = threadIdx.x; idx < m; idx += HEM_BS1) hem_visit<__HIP_MEMORY_SCOPE_WORKGROUP, SIDE>(S, r, win[idx], A);
-        __syncthreads();
-        const int k = min(s_cnt, HEM_LCAP1);
-        const int base = s_next;
-        for (int i = threadIdx.x; i < k; i += HEM_BS1) wout[base + i] = s_list[i];
-        __syncthreads();
-        if (threadIdx.x == 0) s_m = base + k;
-        int* t = win;
-        win = wout;
-        wout = t;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        cnt[6] = r;
-        if (s_m != 0) cnt[7] = 1;
-    }
-}
-
-#define AMG_HEM_SIDE(side, CALL) \
-    switch (side) {                \
-        case 7: CALL(7); break;    \
-        case 15: CALL(15); break;  \
-        default: CALL(31); break;  \
-    }
-
-void launch_hem_init(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
-#define CALL(SD)                                                                                               \
-    hipLaunchKernelGGL(k_hem_init<SD>, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, w.lowok,              \
-                       static_cast<HemRecT<SD>*>(w.rec), w.lcnt, w.dec, w.mate, w.wl[0], w.cnt, w.err)
-    AMG_HEM_SIDE(w.side, CALL)
-#undef CALL
-}
-
-int hem_next_count_slot(int round) { return round % 3; }
-
-void launch_hem_round(int r, int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
-    const int g = blocks_for(n, HEM_BS, 96);
-    const HemState S{rp, ci, v, w.lowok, w.rec, w.dec, w.mate, w.lcnt};
-#define CALL(SD)                                                                                          \
-    hipLaunchKernelGGL(k_hem_round<SD>, dim3(g), dim3(HEM_BS), 0, s, r, S, w.wl[r & 1], w.wl[(r + 1) & 1], \
-                       w.cnt, r % 3, (r + 1) % 3, (r + 2) % 3)
-    AMG_HEM_SIDE(w.side, CALL)
-#undef CALL
-}
-
-void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
-    const HemState S{rp, ci, v, w.lowok, w.rec, w.dec, w.mate, w.lcnt};
-#define CALL(SD) \
-    hipLaunchKernelGGL(k_hem_all<SD>, dim3(1), dim3(HEM_BS1), 0, s, n, S, w.wl[0], w.wl[1], w.cnt)
-    AMG_HEM_SIDE(w.side, CALL)
-#undef CALL
-}
-#undef AMG_HEM_SIDE
 
 // ---------------------------------------------------------------------------
 // Exclusive prefix sum (three phases: tile sums, scan of tile sums, apply).
@@ -639,12 +225,19 @@ __device__ __forceinline__ bool rap_row(SortedAcc<RAP_CAP>& acc, int e0, int e1,
     return true;
 }
 
-__global__ __launch_bounds__(RAP_BS) void k_rap_count(int nc, const int* __restrict__ lead,
-                                                      const int* __restrict__ mate, const int* __restrict__ rp,
-                                                      const int* __restrict__ ci, const int* __restrict__ agg,
-                                                      int* __restrict__ rowcnt, int* __restrict__ ovf, int* novf) {
+// Rows are counted up to nmax (an upper bound of the coarse size *ncp); rows
+// past the coarse size count zero, so a scan over nmax rows gives the offsets.
+__global__ __launch_bounds__(RAP_BS) void k_rap_count(int nmax, const int* __restrict__ ncp,
+                                                      const int* __restrict__ lead, const int* __restrict__ mate,
+                                                      const int* __restrict__ rp, const int* __restrict__ ci,
+                                                      const int* __restrict__ agg, int* __restrict__ rowcnt,
+                                                      int* __restrict__ ovf, int* novf) {
     const int I = blockIdx.x * RAP_BS + threadIdx.x;
-    if (I >= nc) return;
+    if (I >= nmax) return;
+    if (I >= *ncp) {
+        rowcnt[I] = 0;
+        return;
+    }
     const int m0 = lead[I];
     const int m1 = mate[m0];
     SortedAcc<RAP_CAP> acc;
@@ -819,10 +412,10 @@ __global__ __launch_bounds__(kWave) void k_rap_slow(const int* __restrict__ ovf,
     }
 }
 
-void launch_rap_count(int nc, const int* lead, const int* mate, const int* rp, const int* ci, const int* agg,
-                      int* rowcnt, int* ovf, int* novf, hipStream_t s) {
-    hipLaunchKernelGGL(k_rap_count, dim3(blocks_for(nc, RAP_BS)), dim3(RAP_BS), 0, s, nc, lead, mate, rp, ci, agg,
-                       rowcnt, ovf, novf);
+void launch_rap_count(int nmax, const int* ncp, const int* lead, const int* mate, const int* rp, const int* ci,
+                      const int* agg, int* rowcnt, int* ovf, int* novf, hipStream_t s) {
+    hipLaunchKernelGGL(k_rap_count, dim3(blocks_for(nmax, RAP_BS)), dim3(RAP_BS), 0, s, nmax, ncp, lead, mate, rp, ci,
+                       agg, rowcnt, ovf, novf);
 }
 
 void launch_rap_count_slow(int nc, const int* ovf, const int* novf, const int* lead, const int* mate, const int* rp,

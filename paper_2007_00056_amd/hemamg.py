@@ -24,7 +24,8 @@ KERNEL_PROLONG_POST, KERNEL_RESID_RESTRICT, KERNEL_SPMV = 0, 1, 2
 
 EXPORTED = ["amg_params_default", "amg_setup", "amg_destroy", "amg_vcycle", "krylov_solve", "amg_num_levels",
             "amg_level_size", "amg_export_level", "amg_setup_stats", "amg_timing_enable", "amg_timing_read",
-            "amg_last_error"]
+            "amg_last_error", "amg_footprint_bytes", "amg_server_config_default", "amg_server_create",
+            "amg_server_submit", "amg_server_wait", "amg_server_destroy"]
 
 
 class amg_csr(C.Structure):
@@ -42,6 +43,11 @@ class amg_params(C.Structure):
 class amg_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("rel_res", C.c_double), ("true_rel_res", C.c_double),
                 ("solve_ms", C.c_double), ("status", C.c_int32)]
+
+
+class amg_server_config(C.Structure):
+    _fields_ = [("workers", C.c_int32), ("pad", C.c_int32), ("hbm_budget_bytes", C.c_uint64),
+                ("params", amg_params)]
 
 
 class AmgError(RuntimeError):
@@ -73,6 +79,12 @@ def lib():
             "amg_setup_stats": [vp, vp, i32, C.POINTER(i32), C.POINTER(C.c_size_t)],
             "amg_timing_enable": [vp, i32, i32],
             "amg_timing_read": [vp, i32, C.POINTER(i64), C.POINTER(f64)],
+            "amg_footprint_bytes": [i32, i64, C.POINTER(amg_params), C.POINTER(C.c_uint64)],
+            "amg_server_config_default": [C.POINTER(amg_server_config)],
+            "amg_server_create": [C.POINTER(amg_server_config), C.POINTER(vp)],
+            "amg_server_submit": [vp, C.POINTER(amg_csr), vp, vp, i32, f64, i32, C.POINTER(i64)],
+            "amg_server_wait": [vp, i64, C.POINTER(amg_info), C.POINTER(f64)],
+            "amg_server_destroy": [vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -200,6 +212,45 @@ def amg_timing_read(h: int, kernel: int):
 
 def amg_last_error() -> str:
     return lib().amg_last_error().decode()
+
+
+def amg_footprint_bytes(n: int, nnz: int, params: amg_params | None = None) -> int:
+    b = C.c_uint64()
+    _check(lib().amg_footprint_bytes(n, nnz, C.byref(params) if params is not None else None, C.byref(b)))
+    return b.value
+
+
+def amg_server_config_default(**overrides) -> amg_server_config:
+    c = amg_server_config()
+    _check(lib().amg_server_config_default(C.byref(c)))
+    for k, v in overrides.items():
+        setattr(c, k, v)
+    return c
+
+
+def amg_server_create(config: amg_server_config | None = None) -> int:
+    h = C.c_void_p()
+    _check(lib().amg_server_create(C.byref(config) if config is not None else None, C.byref(h)))
+    return h.value
+
+
+def amg_server_submit(s: int, A: DeviceCSR, b, x, method: int, rtol: float, maxit: int) -> int:
+    t = C.c_int64()
+    _check(lib().amg_server_submit(s, C.byref(A.c), _ptr(b), _ptr(x), method, rtol, maxit, C.byref(t)))
+    return t.value
+
+
+def amg_server_wait(s: int, ticket: int) -> dict:
+    """Waits for one request; returns its summary with the status (not raised)."""
+    info = amg_info()
+    lat = C.c_double()
+    st = lib().amg_server_wait(s, ticket, C.byref(info), C.byref(lat))
+    return dict(status=st, iters=info.iters, rel_res=info.rel_res, true_rel_res=info.true_rel_res,
+                solve_ms=info.solve_ms, latency_ms=lat.value)
+
+
+def amg_server_destroy(s: int) -> None:
+    _check(lib().amg_server_destroy(s))
 
 
 # ---------------------------------------------------------------- convenience

@@ -46,6 +46,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(hemamg.amg_params) == 48
     assert ctypes.sizeof(hemamg.amg_csr) == 40
     assert ctypes.sizeof(hemamg.amg_info) == 40
+    # amg_server_config: int32, int32, uint64, amg_params -> 64 bytes
+    assert ctypes.sizeof(hemamg.amg_server_config) == 64
 
 
 def test_params_default_values():
@@ -55,3 +57,18 @@ def test_params_default_values():
     assert (p.passes_per_level, p.max_coarse_rows, p.max_levels, p.max_dense_rows) == (2, 64, 32, 1024)
     assert abs(p.omega - 2.0 / 3.0) < 1e-16 and (p.pre, p.post, p.true_res_period) == (1, 1, 50)
     assert p.precond_fp32 == 0 and p.stall_ratio == 0.9
+
+
+def test_footprint_and_server_defaults():
+    if not os.path.exists(hemamg.LIB_PATH):
+        pytest.fail("libhemamg.so is not built")
+    # host-only calls
+    c = hemamg.amg_server_config_default()
+    assert c.workers == 4 and c.hbm_budget_bytes == 64 << 30 and c.params.passes_per_level == 2
+    small = hemamg.amg_footprint_bytes(4096, 28000)
+    big = hemamg.amg_footprint_bytes(884736, 6137856)
+    assert 0 < small < big
+    # the float preconditioner adds the float copies
+    assert hemamg.amg_footprint_bytes(884736, 6137856, hemamg.amg_params_default(precond_fp32=1)) > big - 20 * 884736
+    with pytest.raises(hemamg.AmgError):
+        hemamg.amg_footprint_bytes(-1, 10)

@@ -1,0 +1,156 @@
+"""GPU tests of the serving loop (amg_server_*): requests of different sizes
+run concurrently on worker streams.  Every kernel is deterministic and a
+request's work touches only its own buffers, so each result must be
+bit-identical to the same request solved alone; admission by footprint and
+error isolation are checked too."""
+import numpy as np
+import pytest
+
+from paper_2007_00056_amd import hemamg, problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+
+    assert _t.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return _t
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def bits(x):
+    return np.ascontiguousarray(x, dtype=np.float64).view(np.int64)
+
+
+def mix():
+    """(matrix, rhs seed, method): lognormal diffusion of several sizes, a
+    Poisson grid and a convection-diffusion system."""
+    out = [(P.lognormal_diffusion3d(m, 1000 + m, 1.0), m, "pcg") for m in (5, 9, 16, 23, 31, 12, 40)]
+    out.append((P.poisson3d(21, 17, 13), 7, "pcg"))
+    out.append((P.convdiff3d(19), 8, "bicgstab"))
+    return out
+
+
+def alone(torch, a, seed, method, params, rtol):
+    A = hemamg.DeviceCSR.from_host(a)
+    b = torch.from_numpy(P.rhs_uniform(a.n, seed)).cuda()
+    with hemamg.Hierarchy(A, params) as g:
+        x, info = g.solve(b, method=method, rtol=rtol, maxit=500)
+    return x.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("workers", [1, 4])
+def test_results_same_alone_and_in_the_mix(torch, fp32, workers):
+    say("workers", workers, "fp32", fp32)
+    rtol = 1e-8
+    cfg = hemamg.amg_server_config_default(workers=workers)
+    cfg.params.precond_fp32 = fp32
+    params = hemamg.amg_params_default(precond_fp32=fp32)
+    items = mix()
+    srv = hemamg.amg_server_create(cfg)
+    try:
+        live = []
+        for a, seed, method in items:
+            A = hemamg.DeviceCSR.from_host(a)
+            b = torch.from_numpy(P.rhs_uniform(a.n, seed)).cuda()
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t = hemamg.amg_server_submit(srv, A, b, x, hemamg.PCG if method == "pcg" else hemamg.BICGSTAB, rtol, 500)
+            live.append((t, A, b, x))
+        res = [hemamg.amg_server_wait(srv, t) for t, *_ in live]
+    finally:
+        hemamg.amg_server_destroy(srv)
+    for (a, seed, method), (t, A, b, x), r in zip(items, live, res):
+        assert r["status"] == hemamg.AMG_OK, r
+        assert r["latency_ms"] > 0
+        xa, ia = alone(torch, a, seed, method, params, rtol)
+        assert r["iters"] == ia["iters"], (r, ia)
+        np.testing.assert_array_equal(bits(x.cpu().numpy()), bits(xa), err_msg=f"n={a.n}")
+
+
+def test_admission_budget_serialises_but_completes(torch):
+    items = mix()[:5]
+    feet = [hemamg.amg_footprint_bytes(a.n, a.nnz) for a, _, _ in items]
+    cfg = hemamg.amg_server_config_default(workers=4, hbm_budget_bytes=max(feet))
+    srv = hemamg.amg_server_create(cfg)
+    try:
+        live = []
+        for a, seed, method in items:
+            A = hemamg.DeviceCSR.from_host(a)
+            b = torch.from_numpy(P.rhs_uniform(a.n, seed)).cuda()
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            live.append((hemamg.amg_server_submit(srv, A, b, x, hemamg.PCG, 1e-8, 500), A, b, x, a, seed))
+        # a request larger than the whole budget is refused at submission
+        big = P.poisson3d(40)
+        Ab = hemamg.DeviceCSR.from_host(big)
+        bb = torch.ones(big.n, dtype=torch.float64, device="cuda")
+        xb = torch.zeros_like(bb)
+        with pytest.raises(hemamg.AmgError) as e:
+            hemamg.amg_server_submit(srv, Ab, bb, xb, hemamg.PCG, 1e-8, 500)
+        assert e.value.status == hemamg.AMG_EINVAL
+        for t, A, b, x, a, seed in live:
+            r = hemamg.amg_server_wait(srv, t)
+            assert r["status"] == hemamg.AMG_OK
+            xa, _ = alone(torch, a, seed, "pcg", hemamg.amg_params_default(), 1e-8)
+            np.testing.assert_array_equal(bits(x.cpu().numpy()), bits(xa))
+    finally:
+        hemamg.amg_server_destroy(srv)
+
+
+def test_failing_request_does_not_disturb_others(torch):
+    good = P.lognormal_diffusion3d(14, 3, 1.0)
+    bad = P.poisson3d(6)
+    bad.val = bad.val.copy()
+    bad.val[bad.row_ptr[5]:bad.row_ptr[6]][bad.col[bad.row_ptr[5]:bad.row_ptr[6]] == 5] = 0.0  # zero diagonal
+    srv = hemamg.amg_server_create(hemamg.amg_server_config_default(workers=2))
+    try:
+        live = []
+        for a in (good, bad, good):
+            A = hemamg.DeviceCSR.from_host(a)
+            b = torch.from_numpy(P.rhs_uniform(a.n, 1)).cuda()
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            live.append((hemamg.amg_server_submit(srv, A, b, x, hemamg.PCG, 1e-8, 500), A, b, x))
+        r = [hemamg.amg_server_wait(srv, t) for t, *_ in live]
+        assert [q["status"] for q in r] == [hemamg.AMG_OK, hemamg.AMG_EINVAL, hemamg.AMG_OK]
+        np.testing.assert_array_equal(bits(live[0][3].cpu().numpy()), bits(live[2][3].cpu().numpy()))
+        assert hemamg.amg_server_wait(srv, live[0][0])["status"] == hemamg.AMG_EINVAL  # already released
+    finally:
+        hemamg.amg_server_destroy(srv)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_footprint_bounds_owned_memory(torch, fp32):
+    for a in (P.lognormal_diffusion3d(30, 4, 1.0), P.poisson3d(48), P.convdiff3d(25)):
+        params = hemamg.amg_params_default(precond_fp32=fp32)
+        A = hemamg.DeviceCSR.from_host(a)
+        b = torch.from_numpy(P.rhs_uniform(a.n, 0)).cuda()
+        with hemamg.Hierarchy(A, params) as g:
+            g.solve(b, rtol=1e-6, check=False)
+            owned = g.stats()["owned_bytes"]
+        foot = hemamg.amg_footprint_bytes(a.n, a.nnz, params)
+        say("n", a.n, "owned", owned, "footprint", foot)
+        assert owned <= foot
+
+
+def test_destroy_drains_queued_requests(torch):
+    a = P.lognormal_diffusion3d(20, 9, 1.0)
+    A = hemamg.DeviceCSR.from_host(a)
+    b = torch.from_numpy(P.rhs_uniform(a.n, 2)).cuda()
+    xs = [torch.zeros_like(b) for _ in range(6)]
+    torch.cuda.synchronize()
+    srv = hemamg.amg_server_create(hemamg.amg_server_config_default(workers=2))
+    for x in xs:
+        hemamg.amg_server_submit(srv, A, b, x, hemamg.PCG, 1e-8, 500)
+    hemamg.amg_server_destroy(srv)  # returns after every queued request ran
+    ref = xs[0].cpu().numpy()
+    assert np.linalg.norm(ref) > 0
+    for x in xs[1:]:
+        np.testing.assert_array_equal(bits(x.cpu().numpy()), bits(ref))
