@@ -289,9 +289,12 @@ def main():
                 kern_tot[k][1] += ms
         sizes = level_sizes(h, hemamg)
         stats = hemamg.amg_setup_stats(h)
+        t3 = time.perf_counter()
         hemamg.amg_destroy(h)
-        return dict(setup_ms=(t1 - t0) * 1e3, solve_ms=(t2 - t1) * 1e3, iters=info["iters"],
-                    true_rel_res=info["true_rel_res"], sizes=sizes, stats=stats)
+        t4 = time.perf_counter()
+        return dict(setup_ms=(t1 - t0) * 1e3, solve_ms=(t2 - t1) * 1e3, destroy_ms=(t4 - t3) * 1e3,
+                    other_ms=(t3 - t2) * 1e3, iters=info["iters"], true_rel_res=info["true_rel_res"], sizes=sizes,
+                    stats=stats)
 
     for i in range(args.warmup):
         r = step(False)
@@ -302,8 +305,8 @@ def main():
     for i in range(args.steps):
         r = step(True)
         recs.append(r)
-        log(f"step {i}: setup {r['setup_ms']:.2f} ms, solve {r['solve_ms']:.2f} ms, iters {r['iters']}, "
-            f"true rel res {r['true_rel_res']:.2e}")
+        log(f"step {i}: setup {r['setup_ms']:.2f} ms, solve {r['solve_ms']:.2f} ms, destroy {r['destroy_ms']:.2f} ms, "
+            f"stats {r['other_ms']:.2f} ms, iters {r['iters']}, true rel res {r['true_rel_res']:.2e}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -340,6 +343,8 @@ def main():
                    "method": method, "precond": precond, "levels": len(sizes), "seed": args.seed},
         "setup_ms": setup_ms,
         "solve_ms": solve_ms,
+        "destroy_ms": float(np.median([r["destroy_ms"] for r in recs])),
+        "between_ms": float(np.median([r["other_ms"] for r in recs])),
         "iters": iters,
         "ms_per_iter": solve_ms / max(iters, 1),
         "solve_gbs": it_bytes * iters / (solve_ms * 1e-3) / 1e9,

@@ -50,6 +50,30 @@ struct Failure {
     } while (0)
 
 // Stream-ordered device allocations; every byte is counted.
+void pinned_put(void* p);
+
+// Streams and events are kept in process-wide free lists per device:
+// creating and destroying them costs milliseconds per handle.  Streams are
+// non-blocking at the default priority; timing events record times, the
+// others do not.
+struct DeviceRes {
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events[2];  // [0] without timing, [1] timing
+};
+std::mutex g_res_mu;
+std::map<int, DeviceRes> g_res;
+
+int current_device() {
+    int d = 0;
+    (void)hipGetDevice(&d);
+    return d;
+}
+
+hipStream_t stream_get();
+void stream_put(hipStream_t s);
+hipEvent_t event_get(bool timing);
+void event_put(hipEvent_t e, bool timing);
+
 // Device memory comes from a stream-ordered pool owned by the library (one
 // per device) that keeps freed blocks for reuse instead of returning them to
 // the driver, so building a hierarchy does not remap memory level by level.
@@ -73,26 +97,48 @@ hipMemPool_t lib_pool() {
     return pool;
 }
 
+// An arena over the pool: pieces (256-byte aligned) are carved from a few
+// chunks (sized from a hint, or by a larger request), so a handle makes a
+// handful of pool calls instead of one per array.
 struct DevPool {
     hipStream_t s = nullptr;
     hipMemPool_t mp = nullptr;
-    std::vector<void*> ptrs;
-    size_t bytes = 0;
+    std::vector<void*> chunks;
+    char* cur = nullptr;
+    size_t left = 0;
+    size_t bytes = 0;                 // device memory held (sum of chunks)
+    size_t next_chunk = size_t(1) << 20;
+
+    void hint(size_t b) {
+        if (b > next_chunk) next_chunk = b;
+    }
 
     template <class T>
     T* get(size_t count) {
-        if (!mp) mp = lib_pool();
-        void* p = nullptr;
-        const size_t b = (count > 0 ? count : 1) * sizeof(T);
-        HIPCHK(hipMallocFromPoolAsync(&p, b, mp, s));
-        ptrs.push_back(p);
-        bytes += b;
-        return static_cast<T*>(p);
+        const size_t b = (((count > 0 ? count : 1) * sizeof(T)) + 255) & ~size_t(255);
+        if (b > left) {
+            if (!mp) mp = lib_pool();
+            const size_t c = b > next_chunk ? b : next_chunk;
+            void* p = nullptr;
+            HIPCHK(hipMallocFromPoolAsync(&p, c, mp, s));
+            chunks.push_back(p);
+            cur = static_cast<char*>(p);
+            left = c;
+            bytes += c;
+            next_chunk = c;
+        }
+        T* r = reinterpret_cast<T*>(cur);
+        cur += b;
+        left -= b;
+        return r;
     }
     void release() {
-        for (void* p : ptrs) (void)hipFreeAsync(p, s);
-        ptrs.clear();
+        for (void* p : chunks) (void)hipFreeAsync(p, s);
+        chunks.clear();
+        cur = nullptr;
+        left = 0;
         bytes = 0;
+        next_chunk = size_t(1) << 20;
     }
 };
 
@@ -192,12 +238,12 @@ struct amg_hier {
         if (stream) (void)hipStreamSynchronize(stream);
         pool.release();
         if (stream) (void)hipStreamSynchronize(stream);
-        if (S_host) (void)hipHostFree(S_host);
+        pinned_put(S_host);
         for (auto& T : tim)
-            for (hipEvent_t e : T.ev) (void)hipEventDestroy(e);
+            for (hipEvent_t e : T.ev) event_put(e, true);
         for (hipEvent_t e : gev)
-            if (e) (void)hipEventDestroy(e);
-        if (gstream) (void)hipStreamDestroy(gstream);
+            if (e) event_put(e, false);
+        if (gstream) stream_put(gstream);
     }
 };
 
@@ -221,6 +267,74 @@ amg_status guarded(F&& f) {
 }
 
 inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+// Pinned host blocks of 4 KiB for the Krylov scalar slots of a handle, kept
+// in a free list for the process (pinned allocation and release are slow).
+constexpr size_t kPinnedBlock = 4096;
+std::mutex g_pinned_mu;
+std::vector<void*> g_pinned_free;
+
+void* pinned_get() {
+    {
+        std::lock_guard<std::mutex> g(g_pinned_mu);
+        if (!g_pinned_free.empty()) {
+            void* p = g_pinned_free.back();
+            g_pinned_free.pop_back();
+            return p;
+        }
+    }
+    void* p = nullptr;
+    HIPCHK(hipHostMalloc(&p, kPinnedBlock, hipHostMallocDefault));
+    return p;
+}
+
+void pinned_put(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(g_pinned_mu);
+    g_pinned_free.push_back(p);
+}
+
+hipStream_t stream_get() {
+    {
+        std::lock_guard<std::mutex> g(g_res_mu);
+        auto& v = g_res[current_device()].streams;
+        if (!v.empty()) {
+            hipStream_t s = v.back();
+            v.pop_back();
+            return s;
+        }
+    }
+    hipStream_t s = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    return s;
+}
+
+void stream_put(hipStream_t s) {
+    if (!s) return;
+    std::lock_guard<std::mutex> g(g_res_mu);
+    g_res[current_device()].streams.push_back(s);
+}
+
+hipEvent_t event_get(bool timing) {
+    {
+        std::lock_guard<std::mutex> g(g_res_mu);
+        auto& v = g_res[current_device()].events[timing ? 1 : 0];
+        if (!v.empty()) {
+            hipEvent_t e = v.back();
+            v.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&e, timing ? hipEventDisableSystemFence : hipEventDisableTiming));
+    return e;
+}
+
+void event_put(hipEvent_t e, bool timing) {
+    if (!e) return;
+    std::lock_guard<std::mutex> g(g_res_mu);
+    g_res[current_device()].events[timing ? 1 : 0].push_back(e);
+}
 
 // Pinned host words for small read-backs (per thread, kept for the process).
 int* pinned_words() {
@@ -293,16 +407,15 @@ struct SetupWork {
         rowcnt = P.get<int>(n);
         ovf = P.get<int>(n);
         novf = P.get<int>(1);
-        HIPCHK(hipHostMalloc((void**)&hc, 2 * sizeof(int), hipHostMallocDefault));
-        HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        hc = pinned_words() + 32;  // this thread's pinned words, past the read-back area
+        ev[0] = event_get(false);
+        ev[1] = event_get(false);
         if (const char* e = getenv("HEMAMG_HEM_SMALL")) hem_small = atoi(e);  // tuning sweeps
         if (const char* e = getenv("HEMAMG_HEM_GRID")) hw.round_grid = atoi(e) > 0 ? atoi(e) : 96;
     }
     ~SetupWork() {
-        if (hc) (void)hipHostFree(hc);
-        if (ev[0]) (void)hipEventDestroy(ev[0]);
-        if (ev[1]) (void)hipEventDestroy(ev[1]);
+        event_put(ev[0], false);
+        event_put(ev[1], false);
     }
 };
 
@@ -422,7 +535,7 @@ void timed_begin(amg_hier* h, int cls, hipStream_t s) {
     if (T.used + 2 > T.ev.size()) {
         for (int k = 0; k < 64; ++k) {
             hipEvent_t e;
-            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+            e = event_get(true);
             T.ev.push_back(e);
         }
     }
@@ -861,6 +974,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     h->stream = s;
     h->pool.s = s;
     DevPool& P = h->pool;
+    P.hint(6 * (size_t)A.nnz + 96 * (size_t)A.n + (size_t(1) << 20));  // most of the hierarchy in one chunk
     h->err = P.get<int>(1);
     HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), s));
 
@@ -879,6 +993,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
 
     DevPool wpool;
     wpool.s = s;
+    wpool.hint((size_t)A.nnz + 160 * (size_t)A.n + 4096);
     struct WpoolGuard {
         DevPool& t;
         ~WpoolGuard() { t.release(); }
@@ -895,6 +1010,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
         }
         DevPool tmp;
         tmp.s = s;
+        tmp.hint(4 * (size_t)F.n + 12 * (size_t)F.nnz + 4096);  // the intermediate operator of pass 1
         struct TmpGuard {
             DevPool& t;
             ~TmpGuard() { t.release(); }
@@ -953,6 +1069,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     {
         DevPool tmp;
         tmp.s = s;
+        tmp.hint(8 * (size_t)m * m + 4 * (size_t)m + 4096);
         double* a = tmp.get<double>((size_t)m * m);
         int* piv = tmp.get<int>(m);
         h->ainv_t = P.get<double>((size_t)m * m);
@@ -994,7 +1111,8 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     h->S = P.get<double>(S_COUNT);
     h->part = P.get<double>(2 * (size_t)kRedBlocks);
     HIPCHK(hipMemsetAsync(h->S, 0, S_COUNT * sizeof(double), s));
-    HIPCHK(hipHostMalloc((void**)&h->S_host, S_COUNT * sizeof(double), hipHostMallocDefault));
+    static_assert(S_COUNT * sizeof(double) <= kPinnedBlock, "slots");
+    h->S_host = static_cast<double*>(pinned_get());
     HIPCHK(hipStreamSynchronize(s));
     *out = h.release();
 }
@@ -1061,9 +1179,9 @@ amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x,
         // stream or graphs are replayed (they cannot be captured on it)
         const bool own = s == nullptr || h->use_graphs;
         if (own && !h->gstream) {
-            HIPCHK(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&h->gev[0], hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&h->gev[1], hipEventDisableTiming));
+            h->gstream = stream_get();
+            h->gev[0] = event_get(false);
+            h->gev[1] = event_get(false);
         }
         if (own) {
             HIPCHK(hipEventRecord(h->gev[0], s));
