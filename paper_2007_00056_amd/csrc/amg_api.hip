@@ -412,6 +412,7 @@ struct SetupWork {
         ev[1] = event_get(false);
         if (const char* e = getenv("HEMAMG_HEM_SMALL")) hem_small = atoi(e);  // tuning sweeps
         if (const char* e = getenv("HEMAMG_HEM_GRID")) hw.round_grid = atoi(e) > 0 ? atoi(e) : 96;
+        if (const char* e = getenv("HEMAMG_HEM_LDS")) hw.lds_rows = atoi(e) < kHemLdsRows ? atoi(e) : kHemLdsRows;
     }
     ~SetupWork() {
         event_put(ev[0], false);
@@ -529,23 +530,34 @@ void alloc_workspace(amg_hier* h) {
     h->t = P.get<double>(n);
 }
 
+void timer_reserve(Timer& T) {
+    if (T.used + 2 > T.ev.size())
+        for (int k = 0; k < 64; ++k) T.ev.push_back(event_get(true));
+}
+
 void timed_begin(amg_hier* h, int cls, hipStream_t s) {
     Timer& T = h->tim[cls];
     if (!T.on) return;
-    if (T.used + 2 > T.ev.size()) {
-        for (int k = 0; k < 64; ++k) {
-            hipEvent_t e;
-            e = event_get(true);
-            T.ev.push_back(e);
-        }
-    }
+    timer_reserve(T);
     HIPCHK(hipEventRecord(T.ev[T.used], s));
 }
 
-void timed_end(amg_hier* h, int cls, hipStream_t s) {
+// The next start/stop pair of class cls for a launch that records them
+// itself (nullptr when timing is off); timed_end then commits the pair
+// without recording.
+void timed_pair(amg_hier* h, int cls, hipEvent_t& a, hipEvent_t& b) {
+    Timer& T = h->tim[cls];
+    a = b = nullptr;
+    if (!T.on) return;
+    timer_reserve(T);
+    a = T.ev[T.used];
+    b = T.ev[T.used + 1];
+}
+
+void timed_end(amg_hier* h, int cls, hipStream_t s, bool recorded = false) {
     Timer& T = h->tim[cls];
     if (!T.on) return;
-    HIPCHK(hipEventRecord(T.ev[T.used + 1], s));
+    if (!recorded) HIPCHK(hipEventRecord(T.ev[T.used + 1], s));
     T.used += 2;
     if (T.used >= 4096) {  // fold completed pairs to bound the pool
         HIPCHK(hipEventSynchronize(T.ev[T.used - 1]));
@@ -610,14 +622,18 @@ void run_vcycle_t(amg_hier* h, const double* r, double* z, hipStream_t s, const 
     };
     if (part == 2) {  // level-0 postsmoothing (+ (r, z)) only
         const VLevel<T> V = vlevel<T>(L0);
-        timed_begin(h, 0, s);
         if (L0.n >= h->stream_min) {
-            vc_stream_post<T, double>(V, vec(L0.xp), g0, w, z, r, dot_slot >= 0 ? &R : nullptr, dot_slot, nullptr, s);
+            hipEvent_t t0, t1;
+            timed_pair(h, 0, t0, t1);
+            vc_stream_post<T, double>(V, vec(L0.xp), g0, w, z, r, dot_slot >= 0 ? &R : nullptr, dot_slot, nullptr, s,
+                                      t0, t1);
+            timed_end(h, 0, s, true);
         } else {
+            timed_begin(h, 0, s);
             vc_prolong_post<T, double>(V, vec(L0.xp), g0, w, z, nullptr, s);
+            timed_end(h, 0, s);
             if (dot_slot >= 0) launch_dot(L0.n, r, z, R, dot_slot, s);
         }
-        timed_end(h, 0, s);
         return;
     }
     // down-sweep
@@ -657,14 +673,18 @@ void run_vcycle_t(amg_hier* h, const double* r, double* z, hipStream_t s, const 
                 vc_prolong_post<T, T>(V, vec(Lk.xp), gk(k), w, vec(Lk.x), &sc, s);
             continue;
         }
-        timed_begin(h, 0, s);
         if (Lk.n >= h->stream_min) {
-            vc_stream_post<T, double>(V, vec(Lk.xp), g0, w, z, r, dot_slot >= 0 ? &R : nullptr, dot_slot, nullptr, s);
+            hipEvent_t t0, t1;
+            timed_pair(h, 0, t0, t1);
+            vc_stream_post<T, double>(V, vec(Lk.xp), g0, w, z, r, dot_slot >= 0 ? &R : nullptr, dot_slot, nullptr, s,
+                                      t0, t1);
+            timed_end(h, 0, s, true);
             dot_done = dot_slot >= 0;
         } else {
+            timed_begin(h, 0, s);
             vc_prolong_post<T, double>(V, vec(Lk.xp), g0, w, z, nullptr, s);
+            timed_end(h, 0, s);
         }
-        timed_end(h, 0, s);
     }
     if (part == 1) return;
     if (dot_slot >= 0 && !dot_done) launch_dot(L0.n, r, z, R, dot_slot, s);

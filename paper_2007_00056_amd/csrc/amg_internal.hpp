@@ -54,6 +54,7 @@ struct HemWork {
     int* cnt;         // [8] worklist size ring, symmetry check, round count, guard
     int* err;
     int round_grid = 96;  // blocks of a one-launch-per-round pass
+    int lds_rows = kHemLdsRows;  // one-workgroup passes up to this size keep their state in LDS
 };
 // w.cnt must be zeroed before the call.
 void launch_hem_init(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
@@ -148,7 +149,8 @@ template <class T>
 void vc_restrict(int nc, const int4* mem, const T* r, const T* dinv_c, T* fc, T* gc, hipStream_t s);
 template <class T, class TOUT>
 void vc_stream_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, const double* f, const Reducer* R,
-                    int slot, const ScatterT<T>* sc, hipStream_t s);
+                    int slot, const ScatterT<T>* sc, hipStream_t s, hipEvent_t t0 = nullptr,
+                    hipEvent_t t1 = nullptr);  // t0/t1: recorded at the start/end of the main kernel
 // Small levels: the same operations with the restriction fused.
 template <class T, class TIN>
 void vc_resid_restrict(const VLevel<T>& L, int nc, const TIN* f, const T* g, T w, const T* dinv_c, T* fc, T* gc,

@@ -491,7 +491,7 @@ constexpr int HL_WCAP = 512;
 // One round over the worklist; the decided vertices' neighbours that become
 // ready, and the ready vertices that failed, form the next list.
 template <int SIDE>
-__global__ __launch_bounds__(HEM_BS) void k_hem_round(int r, HemState S, int* dec, int* lcnt,
+__global__ __launch_bounds__(HEM_BS) void k_hem_round(int r, int n, HemState S, int* dec, int* lcnt,
                                                   const int* __restrict__ win, int* __restrict__ wout, int* cnt,
                                                   int slot_in, int slot_out, int zero_w) {
     __shared__ int s_list[HEM_LCAP];
@@ -503,13 +503,17 @@ __global__ __launch_bounds__(HEM_BS) void k_hem_round(int r, HemState S, int* de
         if (blockIdx.x == 0) cnt[zero_w] = 0;
     }
     __syncthreads();
+    // the list size and this thread's first entry are loaded together
+    // (entries past the size are ignored)
+    const int first = blockIdx.x * HEM_BS + threadIdx.x;
     const int m = cnt[slot_in];
+    const int u0 = first < n ? win[first] : -1;
     if (m > 0 && blockIdx.x == 0 && threadIdx.x == 0) cnt[6] = r + 1;  // rounds with work
     const Appender<int> A{s_list, &s_cnt, HEM_LCAP, wout, &cnt[slot_out]};
     const GlobalSt<__HIP_MEMORY_SCOPE_AGENT> st{dec, lcnt};
     hem_round_body<GlobalSt<__HIP_MEMORY_SCOPE_AGENT>, SIDE, HEM_BS>(
-        S, st, r, m, blockIdx.x * HEM_BS + threadIdx.x, gridDim.x * HEM_BS, [&](int i) { return win[i]; }, A, s_wave,
-        &s_nw, HEM_WCAP);
+        S, st, r, m, first, gridDim.x * HEM_BS, [&](int i) { return i == first ? u0 : win[i]; }, A, s_wave, &s_nw,
+        HEM_WCAP);
     const int k = min(s_cnt, HEM_LCAP);
     if (threadIdx.x == 0 && k > 0) s_base = atomicAdd(&cnt[slot_out], k);
     __syncthreads();
@@ -638,7 +642,7 @@ void launch_hem_round(int r, int n, const int* rp, const int* ci, const double* 
     const int g = blocks_for(n, HEM_BS, w.round_grid);
     const HemState S{rp, ci, v, w.lowok, w.rec, w.mate};
 #define CALL(SD)                                                                                            \
-    hipLaunchKernelGGL(k_hem_round<SD>, dim3(g), dim3(HEM_BS), 0, s, r, S, w.dec, w.lcnt, w.wl[r & 1],       \
+    hipLaunchKernelGGL(k_hem_round<SD>, dim3(g), dim3(HEM_BS), 0, s, r, n, S, w.dec, w.lcnt, w.wl[r & 1],    \
                        w.wl[(r + 1) & 1], w.cnt, r % 3, (r + 1) % 3, (r + 2) % 3)
     AMG_HEM_SIDE(w.side, CALL)
 #undef CALL
@@ -646,7 +650,7 @@ void launch_hem_round(int r, int n, const int* rp, const int* ci, const double* 
 
 void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
     const HemState S{rp, ci, v, w.lowok, w.rec, w.mate};
-    if (n <= kHemLdsRows) {
+    if (n <= w.lds_rows) {
 #define CALL(SD) \
     hipLaunchKernelGGL(k_hem_lds<SD>, dim3(1), dim3(HEM_BS1), 0, s, n, S, w.lcnt, w.wl[0], w.wl[1], w.cnt)
         AMG_HEM_SIDE(w.side, CALL)

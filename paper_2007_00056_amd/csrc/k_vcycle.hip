@@ -11,6 +11,8 @@
 // reads the prolongated iterate xp = w g + P e, which the coarser level wrote
 // by scattering each of its results to its aggregate's fine rows, and smooths
 // z = xp + w (g - D^{-1} A xp).
+#include <hip/hip_ext.h>
+
 #include "amg_internal.hpp"
 #include "amg_stream.hpp"
 
@@ -109,21 +111,25 @@ void vc_restrict(int nc, const int4* mem, const T* r, const T* dinv_c, T* fc, T*
 
 template <class T, class TOUT>
 void vc_stream_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, const double* f, const Reducer* R,
-                    int slot, const ScatterT<T>* sc, hipStream_t s) {
+                    int slot, const ScatterT<T>* sc, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     const int gsz = stream_blocks(L.n, kRedBlocks);
     const EntAx<T> ent{L.v, L.ci, xp};
     const ScatterT<T> none{nullptr, nullptr, nullptr, T(0)};
+    // with t0/t1 the dispatch itself records the kernel's start and end
+#define POST_LAUNCH(MODE, ...)                                                                                     \
+    if (t0)                                                                                                        \
+        hipExtLaunchKernelGGL((k_vc_post<T, TOUT, MODE>), dim3(gsz), dim3(BS), 0, s, t0, t1, 0, __VA_ARGS__);      \
+    else                                                                                                           \
+        hipLaunchKernelGGL((k_vc_post<T, TOUT, MODE>), dim3(gsz), dim3(BS), 0, s, __VA_ARGS__)
     if (R) {
-        hipLaunchKernelGGL((k_vc_post<T, TOUT, 1>), dim3(gsz), dim3(BS), 0, s, L.n, L.rp, ent, g, L.dinv, w, z, f,
-                           R->part, none);
+        POST_LAUNCH(1, L.n, L.rp, ent, g, L.dinv, w, z, f, R->part, none);
         launch_finish(gsz, 1, *R, slot, slot, s);
     } else if (sc) {
-        hipLaunchKernelGGL((k_vc_post<T, TOUT, 2>), dim3(gsz), dim3(BS), 0, s, L.n, L.rp, ent, g, L.dinv, w, z,
-                           nullptr, nullptr, *sc);
+        POST_LAUNCH(2, L.n, L.rp, ent, g, L.dinv, w, z, (const double*)nullptr, (double*)nullptr, *sc);
     } else {
-        hipLaunchKernelGGL((k_vc_post<T, TOUT, 0>), dim3(gsz), dim3(BS), 0, s, L.n, L.rp, ent, g, L.dinv, w, z,
-                           nullptr, nullptr, none);
+        POST_LAUNCH(0, L.n, L.rp, ent, g, L.dinv, w, z, (const double*)nullptr, (double*)nullptr, none);
     }
+#undef POST_LAUNCH
 }
 
 // ---------------------------------------------------------------------------
@@ -285,7 +291,7 @@ void launch_cast_f32(int64_t n, const double* a, float* b, hipStream_t s) {
     template void vc_stream_resid<T, T>(const VLevel<T>&, const T*, const T*, T, T*, hipStream_t);                   \
     template void vc_restrict<T>(int, const int4*, const T*, const T*, T*, T*, hipStream_t);                         \
     template void vc_stream_post<T, T>(const VLevel<T>&, const T*, const T*, T, T*, const double*, const Reducer*,  \
-                                       int, const ScatterT<T>*, hipStream_t);                                        \
+                                       int, const ScatterT<T>*, hipStream_t, hipEvent_t, hipEvent_t);                \
     template void vc_resid_restrict<T, T>(const VLevel<T>&, int, const T*, const T*, T, const T*, T*, T*,            \
                                           hipStream_t);                                                               \
     template void vc_prolong_post<T, T>(const VLevel<T>&, const T*, const T*, T, T*, const ScatterT<T>*,            \
@@ -298,7 +304,8 @@ AMG_INST(float)
 template void vc_stream_resid<float, double>(const VLevel<float>&, const double*, const float*, float, float*,
                                              hipStream_t);
 template void vc_stream_post<float, double>(const VLevel<float>&, const float*, const float*, float, double*,
-                                            const double*, const Reducer*, int, const ScatterT<float>*, hipStream_t);
+                                            const double*, const Reducer*, int, const ScatterT<float>*, hipStream_t,
+                                            hipEvent_t, hipEvent_t);
 template void vc_resid_restrict<float, double>(const VLevel<float>&, int, const double*, const float*, float,
                                                const float*, float*, float*, hipStream_t);
 template void vc_prolong_post<float, double>(const VLevel<float>&, const float*, const float*, float, double*,

@@ -86,6 +86,28 @@ def test_hierarchy_bit_identical(torch, name):
     g.close()
 
 
+DRIVERS = {
+    "launch_per_round": {"HEMAMG_HEM_SMALL": "0"},
+    "one_workgroup_global_state": {"HEMAMG_HEM_LDS": "0"},
+    "launch_per_round_small_grid": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_GRID": "3"},
+}
+
+
+@pytest.mark.parametrize("driver", list(DRIVERS))
+@pytest.mark.parametrize("name", list(CASES))
+def test_matching_drivers_bit_identical(torch, name, driver, monkeypatch):
+    """Every pass through one matching driver whatever its size (the default
+    sends small passes to the LDS-state workgroup): each driver must give the
+    oracle's hierarchy."""
+    say("case", name, "driver", driver)
+    for k, v in DRIVERS[driver].items():
+        monkeypatch.setenv(k, v)
+    a = CASES[name]()
+    g, o = both(a)
+    assert_same_hierarchy(g, o)
+    g.close()
+
+
 def test_worked_example_single_pass(torch, golden):
     gold = golden("hem_worked_example.txt")
     a = P.from_dense(np.array(gold["A"]))
