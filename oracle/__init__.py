@@ -192,7 +192,7 @@ class Hierarchy:
         """Returns (x, info dict)."""
         x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
         info = Info()
-        m = {"pcg": 0, "bicgstab": 1}[method]
+        m = {"pcg": 0, "bicgstab": 1, "stationary": 2}[method]
         st = lib().oracle_krylov(self._h, m, np.ascontiguousarray(b, dtype=np.float64), x, rtol, maxit,
                                  true_res_period, int(precond), C.byref(info))
         return x, dict(status=int(st), iters=info.iters, rel_res=info.rel_res, true_rel_res=info.true_rel_res)

@@ -643,6 +643,44 @@ done:
     return st;
 }
 
+/* AMG as a stationary solver (Algorithm 1 repeated, the "AMG as a solver"
+ * use of Section 4): x <- x + V(b - A x) until ||b - A x|| <= rtol ||b||.
+ * The residual is recomputed every iteration, so it is the true one. */
+static int stationary(const oracle_hier* h, const double* b, double* x, double rtol, int32_t maxit,
+                      oracle_info* info) {
+    const olevel* A = &h->lev[0];
+    int32_t n = A->n;
+    size_t sz = sizeof(double) * (size_t)n;
+    double *r = malloc(sz), *z = malloc(sz);
+    int st = ORACLE_ENOTCONV;
+    double nb = sqrt(dot(n, b, b));
+    info->iters = 0;
+    if (nb == 0.0) {
+        for (int32_t i = 0; i < n; ++i) x[i] = 0.0;
+        info->rel_res = info->true_rel_res = 0.0;
+        st = ORACLE_OK;
+        goto done;
+    }
+    double rel = true_residual(A, b, x, r) / nb;
+    info->rel_res = info->true_rel_res = rel;
+    for (int32_t it = 1; rel > rtol; ++it) {
+        if (it > maxit) goto done;
+        oracle_vcycle(h, r, z);
+        for (int32_t i = 0; i < n; ++i) x[i] += z[i];
+        info->iters = it;
+        rel = true_residual(A, b, x, r) / nb;
+        info->rel_res = info->true_rel_res = rel;
+        if (!isfinite(rel)) {
+            st = ORACLE_EBREAKDOWN;
+            goto done;
+        }
+    }
+    st = ORACLE_OK;
+done:
+    free(r), free(z);
+    return st;
+}
+
 int oracle_krylov(const oracle_hier* h, int32_t method, const double* b, double* x, double rtol, int32_t maxit,
                   int32_t true_res_period, int32_t precond, oracle_info* info) {
     oracle_info local;
@@ -656,6 +694,7 @@ int oracle_krylov(const oracle_hier* h, int32_t method, const double* b, double*
     int st;
     if (method == 0) st = pcg(h, b, x, rtol, maxit, true_res_period, precond, info);
     else if (method == 1) st = bicgstab(h, b, x, rtol, maxit, true_res_period, precond, info);
+    else if (method == 2) st = stationary(h, b, x, rtol, maxit, info);
     else st = ORACLE_EINVAL;
     info->status = st;
     return st;

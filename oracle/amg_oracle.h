@@ -85,7 +85,9 @@ void oracle_destroy(oracle_hier* h);
 /* Algorithm 1: one V-cycle from a zero initial guess, z = M^{-1} f. */
 int oracle_vcycle(const oracle_hier* h, const double* f, double* z);
 
-/* Algorithm 4 (method 0, PCG) and Algorithm 5 (method 1, BiCGStab).
+/* Algorithm 4 (method 0, PCG), Algorithm 5 (method 1, BiCGStab), or
+ * Algorithm 1 iterated as a stationary solver (method 2: x += V(b - A x),
+ * stopping on the recomputed residual; precond and true_res_period unused).
  * precond = 1 applies one V-cycle per preconditioner call, 0 uses M = I.
  * x holds the initial guess on entry and the iterate on return. */
 int oracle_krylov(const oracle_hier* h, int32_t method, const double* b, double* x, double rtol, int32_t maxit,

@@ -244,3 +244,50 @@ def test_star_graph_stall_ratio_rule():
         with pytest.raises(oracle.OracleError) as e:
             oracle.Hierarchy(a, stall_ratio=bad)
         assert e.value.status == oracle.EINVAL
+
+
+# ---------------------------------------------------------------- AMG as a solver
+
+def test_stationary_iterates_follow_the_dense_recurrence():
+    # x_{k+1} = x_k + M (b - A x_k) with M the assembled V-cycle operator
+    a = P.poisson3d(7, 6, 5)
+    h = oracle.Hierarchy(a)
+    A = a.to_scipy().toarray()
+    M = assembled_preconditioner(h, a.n)
+    b = P.rhs_uniform(a.n, 4)
+    x0 = P.rhs_uniform(a.n, 5)
+    x = x0.copy()
+    for k in range(1, 7):
+        x = x + M @ (b - A @ x)
+        xo, info = h.solve(b, x0=x0, method="stationary", rtol=0.0, maxit=k)
+        assert info["status"] == oracle.ENOTCONV and info["iters"] == k
+        assert np.linalg.norm(xo - x) <= 1e-12 * np.linalg.norm(x)
+        r = b - A @ xo
+        assert abs(info["true_rel_res"] - np.linalg.norm(r) / np.linalg.norm(b)) <= 1e-12
+
+
+def test_stationary_converges_at_the_spectral_rate():
+    a = P.poisson3d(9, 8, 7)
+    h = oracle.Hierarchy(a)
+    A = a.to_scipy().toarray()
+    M = assembled_preconditioner(h, a.n)
+    rho = max(abs(np.linalg.eigvals(np.eye(a.n) - M @ A)))
+    assert 0 < rho < 1
+    b = P.rhs_uniform(a.n, 6)
+    x, info = h.solve(b, method="stationary", rtol=1e-10, maxit=500)
+    assert info["status"] == oracle.OK
+    assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-9)
+    assert np.linalg.norm(x - np.linalg.solve(A, b)) <= 1e-7 * np.linalg.norm(x)
+    # asymptotically the error contracts by rho per sweep
+    predicted = np.log(1e-10) / np.log(rho)
+    assert 0.5 * predicted <= info["iters"] <= 1.5 * predicted + 5, (info, predicted)
+
+
+def test_stationary_single_level_is_one_exact_step():
+    a = P.poisson2d(6)
+    h = oracle.Hierarchy(a)
+    assert h.nlevels == 1
+    b = P.rhs_uniform(a.n, 1)
+    x, info = h.solve(b, method="stationary", rtol=1e-12)
+    assert info["status"] == oracle.OK and info["iters"] == 1
+    assert np.linalg.norm(x - np.linalg.solve(a.to_scipy().toarray(), b)) <= 1e-13 * np.linalg.norm(x)
