@@ -63,6 +63,55 @@ int oracle_hem_pass(int32_t n, const int32_t* rp, const int32_t* ci, const doubl
     return ORACLE_OK;
 }
 
+typedef struct {
+    double w;
+    int32_t lo, hi;
+} oedge;
+
+static int edge_order(const void* a, const void* b) {
+    const oedge* x = (const oedge*)a;
+    const oedge* y = (const oedge*)b;
+    if (x->w != y->w) return x->w > y->w ? -1 : 1; /* heaviest first */
+    if (x->lo != y->lo) return x->lo < y->lo ? -1 : 1;
+    if (x->hi != y->hi) return x->hi < y->hi ? -1 : 1;
+    return 0;
+}
+
+int oracle_ehem_pass(int32_t n, const int32_t* rp, const int32_t* ci, const double* v, int32_t* mate) {
+    int64_t m = 0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
+            if (ci[e] != i && v[e] != 0.0) ++m;
+    oedge* T = (oedge*)malloc(sizeof(oedge) * (size_t)(m > 0 ? m : 1));
+    char* assigned = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!T || !assigned) {
+        free(T), free(assigned);
+        return ORACLE_ENOMEM;
+    }
+    m = 0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const int32_t j = ci[e];
+            if (j == i || v[e] == 0.0) continue;
+            T[m].w = fabs(v[e]);
+            T[m].lo = i < j ? i : j;
+            T[m].hi = i < j ? j : i;
+            ++m;
+        }
+    qsort(T, (size_t)m, sizeof(oedge), edge_order);
+    for (int32_t i = 0; i < n; ++i) mate[i] = -1;
+    for (int64_t k = 0; k < m; ++k) {
+        const int32_t i = T[k].lo, j = T[k].hi;
+        if (!assigned[i] && !assigned[j]) {
+            mate[i] = j;
+            mate[j] = i;
+            assigned[i] = assigned[j] = 1;
+        }
+    }
+    free(T), free(assigned);
+    return ORACLE_OK;
+}
+
 /* Algorithm 2, coarse counter C: the coarse id is handed out when the lower */
 /* vertex of a pair (or a singleton) is visited, so ids follow the minimum   */
 /* fine index of each aggregate.                                             */
@@ -237,6 +286,7 @@ void oracle_params_default(oracle_params* p) {
     p->max_levels = 32;
     p->max_dense_rows = 1024;
     p->stall_ratio = 0.9;
+    p->hem = 0;
     p->omega = 2.0 / 3.0;
     p->pre = 1;
     p->post = 1;
@@ -287,7 +337,7 @@ static int make_dinv(olevel* L) {
 
 /* One coarsening step: passes_per_level rounds of (Alg. 2 + Galerkin product), */
 /* composing the aggregate maps.  On success fills *C and fine->agg.           */
-static int coarsen(olevel* F, int32_t passes, olevel* C) {
+static int coarsen(olevel* F, int32_t passes, int32_t hem, olevel* C) {
     int32_t n = F->n;
     int32_t* rp = F->rp;
     int32_t* ci = F->ci;
@@ -299,8 +349,12 @@ static int coarsen(olevel* F, int32_t passes, olevel* C) {
     if (!comp || !mate || !agg) return ORACLE_ENOMEM;
     for (int32_t i = 0; i < F->n; ++i) comp[i] = i;
     for (int32_t p = 0; p < passes; ++p) {
-        oracle_hem_pass(n, rp, ci, v, mate);
-        int32_t nc = oracle_number(n, mate, agg);
+        if (hem == 1) {
+            if (oracle_ehem_pass(n, rp, ci, v, mate) != ORACLE_OK) return ORACLE_ENOMEM;
+        } else {
+            oracle_hem_pass(n, rp, ci, v, mate);
+        }
+        int32_t nc = oracle_number(n, mate, agg); /* ids by each aggregate's minimum fine index */
         int64_t nnzc = oracle_rap_nnz(n, rp, ci, agg, nc);
         int32_t* crp = (int32_t*)malloc(sizeof(int32_t) * ((size_t)nc + 1));
         int32_t* cci = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnzc > 0 ? nnzc : 1));
@@ -350,7 +404,7 @@ oracle_hier* oracle_setup(int32_t n, const int32_t* rp, const int32_t* ci, const
     else oracle_params_default(&h->p);
     int32_t maxlev = h->p.max_levels < MAXLEV ? h->p.max_levels : MAXLEV;
     if (h->p.passes_per_level < 1 || maxlev < 1 || h->p.pre < 0 || h->p.post < 0 ||
-        !(h->p.stall_ratio > 0.0 && h->p.stall_ratio <= 1.0)) {
+        !(h->p.stall_ratio > 0.0 && h->p.stall_ratio <= 1.0) || h->p.hem < 0 || h->p.hem > 1) {
         oracle_destroy(h);
         *status = ORACLE_EINVAL;
         return NULL;
@@ -364,7 +418,7 @@ oracle_hier* oracle_setup(int32_t n, const int32_t* rp, const int32_t* ci, const
             if (F->n > h->p.max_dense_rows) st = ORACLE_ESTALL;
             break;
         }
-        st = coarsen(F, h->p.passes_per_level, &h->lev[k + 1]);
+        st = coarsen(F, h->p.passes_per_level, h->p.hem, &h->lev[k + 1]);
         if (st != ORACLE_OK) break;
         if (h->lev[k + 1].n == F->n) { /* no progress */
             free_level(&h->lev[k + 1]);

@@ -42,6 +42,8 @@ typedef struct {
                                * the coarsest when coarsening it would keep    *
                                * n_c >= stall_ratio * n rows (0.9); 1 stops    *
                                * only when no row is merged                    */
+    int32_t hem;              /* 0: node-based matching (Algorithm 2), 1: edge- *
+                               * based (Algorithm 3) (0)                       */
 } oracle_params;
 
 typedef struct {
@@ -54,6 +56,13 @@ typedef struct {
 /* Section 2.1.1, Algorithm 2: one node-based heavy-edge-matching pass.
  * mate[i] = partner of i, or -1 if i stays an unaggregated singleton. */
 int oracle_hem_pass(int32_t n, const int32_t* rp, const int32_t* ci, const double* v, int32_t* mate);
+
+/* Section 2.1.1, Algorithm 3: edge-based heavy-edge matching.  Every stored
+ * non-zero off-diagonal entry (i, j) is an edge of weight |a_ij|; the list is
+ * sorted by weight descending, ties by the smaller endpoint ascending, then
+ * the larger ascending, and scanned once, matching both endpoints of an edge
+ * whose endpoints are both unmatched.  mate as in oracle_hem_pass. */
+int oracle_ehem_pass(int32_t n, const int32_t* rp, const int32_t* ci, const double* v, int32_t* mate);
 
 /* Algorithm 2, counter C: aggregate ids in visiting order; returns n_c. */
 int32_t oracle_number(int32_t n, const int32_t* mate, int32_t* agg);

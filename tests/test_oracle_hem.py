@@ -248,3 +248,88 @@ def test_brute_force_tiny_graphs_all_weight_assignments():
             A[i, j] = A[j, i] = -w
         a = P.from_dense(A)
         np.testing.assert_array_equal(oracle.hem_pass(a), greedy_sorted_edges(a))
+
+
+# ---------------------------------------------------------------- edge-based HEM (Algorithm 3)
+
+def edges_of(a):
+    """Undirected edges {i, j} with the heavier of |a_ij|, |a_ji| (stored, non-zero)."""
+    w = {}
+    for i in range(a.n):
+        for e in range(a.row_ptr[i], a.row_ptr[i + 1]):
+            j = int(a.col[e])
+            if j != i and a.val[e] != 0.0:
+                k = (min(i, j), max(i, j))
+                w[k] = max(w.get(k, 0.0), abs(a.val[e]))
+    return w
+
+
+def random_graph(n, seed, distinct=True, nonsym=False):
+    rng = np.random.default_rng(seed)
+    mask = np.triu(rng.random((n, n)) < 0.12, 1)
+    vals = np.zeros((n, n))
+    k = int(mask.sum())
+    wts = rng.permutation(np.arange(1, 2 * k + 1))[:k] if distinct else rng.integers(1, 3, k)
+    vals[mask] = -wts.astype(float)
+    vals = vals + vals.T
+    if nonsym:
+        m2 = mask.T & (rng.random((n, n)) < 0.5)
+        vals[m2] *= 0.5
+    np.fill_diagonal(vals, np.abs(vals).sum(axis=1) + 1.0)
+    return P.from_dense(vals)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ehem_is_maximal_and_each_unmatched_edge_is_blocked_by_a_heavier_match(seed):
+    # under a strict edge order this characterises the greedy matching uniquely
+    a = random_graph(40, seed, distinct=seed % 2 == 0, nonsym=seed >= 4)
+    mate = oracle.ehem_pass(a)
+    W = edges_of(a)
+
+    def key(i, j):
+        lo, hi = min(i, j), max(i, j)
+        return (-W[(lo, hi)], lo, hi)
+
+    for i in range(a.n):
+        if mate[i] >= 0:
+            assert mate[mate[i]] == i and (min(i, mate[i]), max(i, mate[i])) in W
+    for (i, j) in W:
+        if mate[i] == j:
+            continue
+        assert mate[i] >= 0 or mate[j] >= 0, (i, j)  # maximal
+        blockers = [key(x, mate[x]) for x in (i, j) if mate[x] >= 0]
+        assert min(blockers) < key(i, j), (i, j)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_ehem_is_invariant_to_the_numbering(seed):
+    # Section 2.1.1: with distinct weights the aggregates do not depend on the
+    # order of the unknowns
+    a = random_graph(50, 100 + seed, distinct=True)
+    dense = a.to_scipy().toarray()
+    perm = np.random.default_rng(seed).permutation(a.n)
+    b = P.from_dense(dense[np.ix_(perm, perm)])
+    ma, mb = oracle.ehem_pass(a), oracle.ehem_pass(b)
+    pairs_a = {frozenset((i, int(ma[i]))) for i in range(a.n) if ma[i] >= 0}
+    pairs_b = {frozenset((int(perm[i]), int(perm[mb[i]]))) for i in range(a.n) if mb[i] >= 0}
+    assert pairs_a == pairs_b
+
+
+@pytest.mark.parametrize("make", [lambda: P.poisson2d(9, 7), lambda: P.poisson3d(6, 5, 4)])
+def test_ehem_equals_node_based_on_equal_weights(make):
+    # equal weights leave the index order (smaller endpoint, then larger), which
+    # is the node-based visiting order
+    a = make()
+    np.testing.assert_array_equal(oracle.ehem_pass(a), oracle.hem_pass(a))
+
+
+def test_ehem_hierarchy_and_solve():
+    a = P.lognormal_diffusion3d(9, 3)
+    h = oracle.Hierarchy(a, hem=1)
+    assert h.nlevels >= 2
+    b = P.rhs_uniform(a.n, 2)
+    x, info = h.solve(b, rtol=1e-10)
+    assert info["status"] == oracle.OK
+    assert np.linalg.norm(a.to_scipy() @ x - b) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-9)
+    with pytest.raises(oracle.OracleError):
+        oracle.Hierarchy(a, hem=2)
