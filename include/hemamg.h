@@ -77,6 +77,9 @@ typedef struct {
                                * coarsest when coarsening it would keep
                                * n_c >= stall_ratio * n rows; in (0, 1]; 1 stops
                                * only when no row is merged (0.9)                 */
+    int32_t hem;              /* matching: 0 node-based (Algorithm 2), 1 edge-
+                               * based (Algorithm 3: edges by weight descending,
+                               * ties by smaller then larger endpoint) (0)         */
 } amg_params;
 
 /* Result of a Krylov solve.  [host] */
@@ -113,8 +116,11 @@ amg_status amg_vcycle(amg_hier* h, const double* r, double* z, void* stream);
 
 /* Algorithm 4 (method 0: preconditioned CG, A symmetric positive definite)
  * or Algorithm 5 (method 1: preconditioned BiCGStab, right preconditioned)
- * with one V-cycle as the preconditioner.  Stops when the recursive residual
- * reaches ||r|| <= rtol ||b|| and the recomputed residual b - A x confirms it.
+ * with one V-cycle as the preconditioner, or AMG as a stationary solver
+ * (method 2: Algorithm 1 repeated, x <- x + V(b - A x), the "AMG as a
+ * solver" use of Section 4).  Stops when the recursive residual reaches
+ * ||r|| <= rtol ||b|| and the recomputed residual b - A x confirms it (the
+ * stationary solver recomputes the residual every iteration).
  * b: [device] float64[n]; x: [device] float64[n], initial guess on entry,
  * the last iterate on return (also on AMG_ENOTCONV and AMG_EBREAKDOWN).
  * info: [host], may be NULL.  Blocks the host until done.

@@ -385,7 +385,14 @@ struct SetupWork {
     hipEvent_t ev[2]{};
     int hem_small = 65536;  // passes on at most this many rows run in one workgroup
 
-    void init(int n, int64_t nnz, DevPool& P, int* err) {
+    bool edge = false;  // edge-based matching (Algorithm 3)
+
+    void init(int n, int64_t nnz, DevPool& P, int* err, bool edge_based) {
+        edge = edge_based;
+        if (edge) {
+            hw.wsym = P.get<double>((size_t)nnz);
+            hw.ptr = P.get<int>(n);
+        }
         hw.lowok = P.get<uint8_t>((size_t)nnz);
         hw.rec_bytes = sizeof(HemRecT<7>) * (size_t)n;
         hw.rec = P.get<char>(hw.rec_bytes);
@@ -432,6 +439,26 @@ struct Pass {
     int rounds = 0;
 };
 
+// Matching rounds launched in batches; the size of the next worklist is
+// copied back after each batch and checked one batch later, so the host
+// check overlaps the GPU work.  Rounds with an empty worklist do nothing.
+template <class Launch>
+void run_rounds(SetupWork& W, HemWork& w, int n, hipStream_t s, Launch&& launch_round) {
+    const int batch = 16;
+    int r = 0;
+    for (int j = 0;; ++j) {
+        for (int b = 0; b < batch; ++b, ++r) launch_round(r);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&W.hc[j & 1], w.cnt + hem_next_count_slot(r), sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(W.ev[j & 1], s));
+        if (j >= 1) {
+            HIPCHK(hipEventSynchronize(W.ev[(j - 1) & 1]));
+            if (W.hc[(j - 1) & 1] == 0) break;
+        }
+        if (r > n + 4 * batch) raise(AMG_EHIP, "matching did not terminate (internal error)");
+    }
+}
+
 Pass hem_pass(const Csr& B, SetupWork& W, int t, hipStream_t s, int* err) {
     const int n = B.n;
     HemWork w = W.hw;
@@ -441,27 +468,16 @@ Pass hem_pass(const Csr& B, SetupWork& W, int t, hipStream_t s, int* err) {
     w.side = avg <= 9.0 ? 7 : (avg <= 20.0 || n <= W.hem_small ? 15 : 31);  // one-workgroup passes: at most 15
     while (w.side > 7 && (size_t)(w.side + 1) * 8 * (size_t)n > w.rec_bytes) w.side = (w.side + 1) / 2 - 1;
     HIPCHK(hipMemsetAsync(w.cnt, 0, 8 * sizeof(int), s));
-    launch_hem_init(n, B.rp, B.ci, B.v, w, s);
-    if (n <= W.hem_small) {
-        launch_hem_all(n, B.rp, B.ci, B.v, w, s);
-        HIPCHK(hipGetLastError());
+    if (W.edge) {
+        launch_ehem_init(n, B.rp, B.ci, B.v, w, s);
+        run_rounds(W, w, n, s, [&](int r) { launch_ehem_round(r, n, B.rp, B.ci, w, s); });
     } else {
-        // Rounds are launched in batches; the size of the next worklist is
-        // copied back after each batch and checked one batch later, so the host
-        // check overlaps the GPU work.  Rounds with an empty worklist do nothing.
-        const int batch = 16;
-        int r = 0;
-        for (int j = 0;; ++j) {
-            for (int b = 0; b < batch; ++b, ++r) launch_hem_round(r, n, B.rp, B.ci, B.v, w, s);
+        launch_hem_init(n, B.rp, B.ci, B.v, w, s);
+        if (n <= W.hem_small) {
+            launch_hem_all(n, B.rp, B.ci, B.v, w, s);
             HIPCHK(hipGetLastError());
-            HIPCHK(hipMemcpyAsync(&W.hc[j & 1], w.cnt + hem_next_count_slot(r), sizeof(int),
-                                  hipMemcpyDeviceToHost, s));
-            HIPCHK(hipEventRecord(W.ev[j & 1], s));
-            if (j >= 1) {
-                HIPCHK(hipEventSynchronize(W.ev[(j - 1) & 1]));
-                if (W.hc[(j - 1) & 1] == 0) break;
-            }
-            if (r > n + 4 * batch) raise(AMG_EHIP, "matching did not terminate (internal error)");
+        } else {
+            run_rounds(W, w, n, s, [&](int r) { launch_hem_round(r, n, B.rp, B.ci, B.v, w, s); });
         }
     }
     Pass P;
@@ -904,6 +920,42 @@ amg_status pcg(amg_hier* h, const double* b, double* x, double rtol, int maxit, 
     return AMG_ENOTCONV;
 }
 
+// AMG as a stationary solver: Algorithm 1 repeated, x <- x + V(b - A x),
+// until the recomputed relative residual reaches rtol.
+amg_status stationary(amg_hier* h, const double* b, double* x, double rtol, int maxit, hipStream_t s,
+                      amg_info& info) {
+    const Level& A0 = h->lev[0];
+    const LevelView A = A0.view();
+    const int n = A0.n;
+    const Reducer R = h->reducer();
+    double* S = h->S_host;
+    launch_dot(n, b, b, R, S_BB, s);
+    launch_residual(A, b, x, h->r, h->g0, h->prec32, R, S_RR, s);
+    read_slots(h, s);
+    const double nb = std::sqrt(S[S_BB]);
+    info.iters = 0;
+    if (nb == 0.0) {
+        launch_scale_zero(n, x, s);
+        HIPCHK(hipStreamSynchronize(s));
+        info.rel_res = info.true_rel_res = 0.0;
+        return AMG_OK;
+    }
+    double rel = std::sqrt(S[S_RR]) / nb;
+    info.rel_res = info.true_rel_res = rel;
+    for (int it = 1; rel > rtol; ++it) {
+        if (it > maxit) return AMG_ENOTCONV;
+        run_vcycle(h, h->r, h->z, s, h->g0);  // D^{-1} r came with the residual
+        launch_add(n, x, h->z, s);
+        launch_residual(A, b, x, h->r, h->g0, h->prec32, R, S_RR, s);
+        read_slots(h, s);
+        info.iters = it;
+        rel = std::sqrt(S[S_RR]) / nb;
+        info.rel_res = info.true_rel_res = rel;
+        if (!std::isfinite(rel)) return AMG_EBREAKDOWN;
+    }
+    return AMG_OK;
+}
+
 // Algorithm 5 (right-preconditioned BiCGStab) with p_0 = r_0 = shadow residual.
 amg_status bicgstab(amg_hier* h, const double* b, double* x, double rtol, int maxit, hipStream_t s, amg_info& info) {
     const Level& A0 = h->lev[0];
@@ -982,6 +1034,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     if (p.true_res_period < 0) raise(AMG_EINVAL, "true_res_period must be >= 0");
     if (p.precond_fp32 != 0 && p.precond_fp32 != 1) raise(AMG_EINVAL, "precond_fp32 must be 0 or 1");
     if (!(p.stall_ratio > 0.0 && p.stall_ratio <= 1.0)) raise(AMG_EINVAL, "stall_ratio must be in (0, 1]");
+    if (p.hem != 0 && p.hem != 1) raise(AMG_EINVAL, "hem must be 0 (node-based) or 1 (edge-based)");
     if (p.precond_fp32 && !(p.pre == 1 && p.post == 1))
         raise(AMG_EINVAL, "a float preconditioner needs one pre- and one post-sweep");
     const amg_csr& A = *Ain;
@@ -1013,13 +1066,13 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
 
     DevPool wpool;
     wpool.s = s;
-    wpool.hint((size_t)A.nnz + 160 * (size_t)A.n + 4096);
+    wpool.hint((size_t)A.nnz * (p.hem == 1 ? 9 : 1) + 168 * (size_t)A.n + 4096);
     struct WpoolGuard {
         DevPool& t;
         ~WpoolGuard() { t.release(); }
     } wg{wpool};
     SetupWork SW;
-    if (A.n > p.max_coarse_rows && p.max_levels > 1) SW.init(A.n, A.nnz, wpool, h->err);
+    if (A.n > p.max_coarse_rows && p.max_levels > 1) SW.init(A.n, A.nnz, wpool, h->err, p.hem == 1);
     for (int k = 0;; ++k) {
         Level& F = h->lev[k];
         if (F.n <= p.max_coarse_rows) break;
@@ -1156,6 +1209,7 @@ amg_status amg_params_default(amg_params* p) {
     p->true_res_period = 50;
     p->precond_fp32 = 0;
     p->stall_ratio = 0.9;
+    p->hem = 0;
     return AMG_OK;
 }
 
@@ -1188,7 +1242,8 @@ amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x,
     amg_status st = AMG_OK;
     amg_status g = guarded([&] {
         if (!h || !b || !x) raise(AMG_EINVAL, "krylov_solve: NULL argument");
-        if (method != 0 && method != 1) raise(AMG_EINVAL, "krylov_solve: method must be 0 (PCG) or 1 (BiCGStab)");
+        if (method < 0 || method > 2)
+            raise(AMG_EINVAL, "krylov_solve: method must be 0 (PCG), 1 (BiCGStab) or 2 (stationary)");
         if (!(rtol >= 0.0) || maxit < 0) raise(AMG_EINVAL, "krylov_solve: rtol must be >= 0 and maxit >= 0");
         hipStream_t s = as_stream(stream);
         h->stream = s;
@@ -1213,7 +1268,9 @@ amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x,
         launch_check_finite(h->lev[0].n, b, x, h->err, ws);
         HIPCHK(hipGetLastError());
         if (read_int(h->err, ws) & ERR_NONFINITE) raise(AMG_ENOTFINITE, "krylov_solve: b or x0 has NaN or Inf");
-        st = method == 0 ? pcg(h, b, x, rtol, maxit, ws, I) : bicgstab(h, b, x, rtol, maxit, ws, I);
+        st = method == 0   ? pcg(h, b, x, rtol, maxit, ws, I)
+             : method == 1 ? bicgstab(h, b, x, rtol, maxit, ws, I)
+                           : stationary(h, b, x, rtol, maxit, ws, I);
         HIPCHK(hipStreamSynchronize(ws));
         if (own) {
             HIPCHK(hipEventRecord(h->gev[1], ws));

@@ -55,12 +55,19 @@ struct HemWork {
     int* err;
     int round_grid = 96;  // blocks of a one-launch-per-round pass
     int lds_rows = kHemLdsRows;  // one-workgroup passes up to this size keep their state in LDS
+    double* wsym = nullptr;  // edge-based matching: [nnz] heavier of |a_uv|, |a_vu| (0 on the diagonal)
+    int* ptr = nullptr;      // edge-based matching: [n] best undecided neighbour
 };
 // w.cnt must be zeroed before the call.
 void launch_hem_init(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
 void launch_hem_round(int round, int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
 // All rounds in one single-workgroup launch (small n).
 void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
+// Edge-based matching (Algorithm 3): initialisation (every vertex dirty, the
+// count in cnt[0]; w.lcnt serves as the per-round marks) and one round (two
+// launches).  w.cnt must be zeroed before the initialisation.
+void launch_ehem_init(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
+void launch_ehem_round(int r, int n, const int* rp, const int* ci, HemWork& w, hipStream_t s);
 int hem_next_count_slot(int round);  // counter slot that holds |worklist| before `round`
 
 // Exclusive prefix sum: out[i] = sum in[0..i), out[n] = total.  tmp: scan_tmp_ints(n).
@@ -198,6 +205,7 @@ void launch_bicg_update(int n, double* x, double* r, const double* pt, const dou
 void launch_bicg_dir(int n, const double* r, const double* p, const double* v, double* pn, const double* S,
                      int slot_rho, int slot_rv, int slot_tt, int slot_ts, int slot_rhonew, hipStream_t s);
 void launch_scale_zero(int n, double* x, hipStream_t s);
+void launch_add(int n, double* x, const double* z, hipStream_t s);
 // err |= ERR_NONFINITE if any entry of a or b is NaN or Inf.
 void launch_check_finite(int n, const double* a, const double* b, int* err, hipStream_t s);
 

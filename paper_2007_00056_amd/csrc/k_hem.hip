@@ -621,6 +621,132 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_lds(int n, HemState S, const in
     }
 }
 
+// ---------------------------------------------------------------------------
+// Edge-based matching (Algorithm 3): the greedy matching over undirected
+// edges {u, v} in increasing key (-W_uv, min(u,v), max(u,v)), where W_uv is
+// the heavier of |a_uv| and |a_vu| (the first occurrence of the pair in the
+// sorted edge list).  Same rounds of locally dominant edges, for this key:
+// every undecided vertex points to its best edge to an undecided neighbour;
+// mutual pointers match; a vertex with no undecided neighbour is a
+// singleton.  A pointer changes only when a neighbour is decided, so each
+// round recomputes the pointers of the vertices next to the previous round's
+// decisions ("dirty"), then (after a launch boundary) matches mutual pairs.
+// ---------------------------------------------------------------------------
+namespace {
+struct EdgeKey {
+    double w;
+    int lo, hi;
+    __device__ __forceinline__ bool better(const EdgeKey& o) const {  // smaller key
+        if (w != o.w) return w > o.w;
+        if (lo != o.lo) return lo < o.lo;
+        return hi < o.hi;
+    }
+};
+}  // namespace
+
+__global__ __launch_bounds__(BS) void k_ehem_init(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                  const double* __restrict__ v, double* __restrict__ wsym,
+                                                  int* __restrict__ dec, int* __restrict__ mate,
+                                                  int* __restrict__ ptr, int* __restrict__ stamp,
+                                                  int* __restrict__ wl0, int* cnt, int* err) {
+    const int u = blockIdx.x * BS + threadIdx.x;
+    if (u >= n) return;
+    dec[u] = kUndecided;
+    mate[u] = -1;
+    ptr[u] = -1;
+    stamp[u] = -1;
+    wl0[u] = u;  // every vertex starts dirty
+    if (u == 0) cnt[0] = n;
+    bool bad = false;
+    for (int e = rp[u]; e < rp[u + 1]; ++e) {
+        const int x = ci[e];
+        double w = 0.0;
+        if (x != u) {
+            const int pos = find_col(ci, rp[x], rp[x + 1], u);
+            if (pos < 0) bad = true;
+            const double back = pos >= 0 ? fabs(v[pos]) : 0.0;
+            const double fwd = fabs(v[e]);
+            w = fwd > back ? fwd : back;
+        }
+        wsym[e] = w;
+    }
+    if (bad) atomicOr(err, ERR_NONSYM);
+}
+
+// pointer of each dirty undecided vertex (state at the start of the round)
+__global__ __launch_bounds__(BS) void k_ehem_point(int r, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   const double* __restrict__ wsym, const int* __restrict__ dec,
+                                                   int* __restrict__ ptr, const int* __restrict__ win, int* cnt,
+                                                   int slot_in, int zero_w) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) cnt[zero_w] = 0;
+    const int m = cnt[slot_in];
+    if (m > 0 && blockIdx.x == 0 && threadIdx.x == 0) cnt[6] = r + 1;  // rounds with work
+    for (int idx = blockIdx.x * BS + threadIdx.x; idx < m; idx += gridDim.x * BS) {
+        const int u = win[idx];
+        if (dec[u] != kUndecided) continue;
+        EdgeKey best{-1.0, 0, 0};
+        int bv = -1;
+        for (int e = rp[u]; e < rp[u + 1]; ++e) {
+            const int x = ci[e];
+            const double w = wsym[e];
+            if (x == u || w == 0.0 || dec[x] != kUndecided) continue;
+            const EdgeKey k{w, min(u, x), max(u, x)};
+            if (bv < 0 || k.better(best)) {
+                best = k;
+                bv = x;
+            }
+        }
+        ptr[u] = bv;
+    }
+}
+
+// mutual pointers match; the undecided neighbours of each decision are the
+// next round's dirty vertices (marked once per round through the stamps)
+__global__ __launch_bounds__(BS) void k_ehem_match(int r, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   const double* __restrict__ wsym, int* __restrict__ dec,
+                                                   int* __restrict__ mate, const int* __restrict__ ptr,
+                                                   int* __restrict__ stamp, const int* __restrict__ win,
+                                                   int* __restrict__ wout, int* cnt, int slot_in, int slot_out) {
+    const int m = cnt[slot_in];
+    for (int idx = blockIdx.x * BS + threadIdx.x; idx < m; idx += gridDim.x * BS) {
+        const int u = win[idx];
+        if (dec[u] != kUndecided) continue;
+        const int v = ptr[u];
+        if (v < 0) {  // no undecided neighbour: unaggregated singleton
+            dec[u] = r;
+            mate[u] = -1;
+            continue;
+        }
+        if (ptr[v] != u) continue;
+        // matched (found by u, and by v too if v is dirty: identical writes)
+        dec[u] = r;
+        dec[v] = r;
+        mate[u] = v;
+        mate[v] = u;
+        for (int q = 0; q < 2; ++q) {
+            const int x = q == 0 ? u : v;
+            for (int e = rp[x]; e < rp[x + 1]; ++e) {
+                const int y = ci[e];
+                if (y == x || wsym[e] == 0.0) continue;
+                if (atomicExch(&stamp[y], r) != r) wout[atomicAdd(&cnt[slot_out], 1)] = y;
+            }
+        }
+    }
+}
+
+void launch_ehem_init(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
+    hipLaunchKernelGGL(k_ehem_init, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, w.wsym, w.dec, w.mate,
+                       w.ptr, w.lcnt, w.wl[0], w.cnt, w.err);
+}
+
+void launch_ehem_round(int r, int n, const int* rp, const int* ci, HemWork& w, hipStream_t s) {
+    const int g = blocks_for(n, BS, 4 * w.round_grid);
+    hipLaunchKernelGGL(k_ehem_point, dim3(g), dim3(BS), 0, s, r, rp, ci, w.wsym, w.dec, w.ptr, w.wl[r & 1], w.cnt,
+                       r % 3, (r + 2) % 3);
+    hipLaunchKernelGGL(k_ehem_match, dim3(g), dim3(BS), 0, s, r, rp, ci, w.wsym, w.dec, w.mate, w.ptr, w.lcnt,
+                       w.wl[r & 1], w.wl[(r + 1) & 1], w.cnt, r % 3, (r + 1) % 3);
+}
+
 #define AMG_HEM_SIDE(side, CALL) \
     switch (side) {                \
         case 7: CALL(7); break;    \

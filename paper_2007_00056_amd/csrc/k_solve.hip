@@ -395,6 +395,15 @@ void launch_bicg_dir(int n, const double* r, const double* p, const double* v, d
                        slot_tt, slot_ts, slot_rhonew);
 }
 
+// x += z (one step of the stationary iteration)
+__global__ __launch_bounds__(BS) void k_add(int n, double* __restrict__ x, const double* __restrict__ z) {
+    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) x[i] += z[i];
+}
+
+void launch_add(int n, double* x, const double* z, hipStream_t s) {
+    hipLaunchKernelGGL(k_add, dim3(vec_blocks(n)), dim3(BS), 0, s, n, x, z);
+}
+
 __global__ __launch_bounds__(BS) void k_zero(int n, double* __restrict__ x) {
     for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) x[i] = 0.0;
 }

@@ -19,7 +19,7 @@ AMG_OK, AMG_EINVAL, AMG_ENOMEM, AMG_ENOTCONV, AMG_EBREAKDOWN, AMG_ENOTFINITE, AM
     range(9)
 STATUS_NAMES = ["AMG_OK", "AMG_EINVAL", "AMG_ENOMEM", "AMG_ENOTCONV", "AMG_EBREAKDOWN", "AMG_ENOTFINITE",
                 "AMG_ESTALL", "AMG_ESINGULAR", "AMG_EHIP"]
-PCG, BICGSTAB = 0, 1
+PCG, BICGSTAB, STATIONARY = 0, 1, 2
 KERNEL_PROLONG_POST, KERNEL_RESID_RESTRICT, KERNEL_SPMV = 0, 1, 2
 
 EXPORTED = ["amg_params_default", "amg_setup", "amg_destroy", "amg_vcycle", "krylov_solve", "amg_num_levels",
@@ -37,7 +37,7 @@ class amg_params(C.Structure):
     _fields_ = [("passes_per_level", C.c_int32), ("max_coarse_rows", C.c_int32), ("max_levels", C.c_int32),
                 ("max_dense_rows", C.c_int32), ("omega", C.c_double), ("pre", C.c_int32), ("post", C.c_int32),
                 ("true_res_period", C.c_int32), ("precond_fp32", C.c_int32),
-                ("stall_ratio", C.c_double)]
+                ("stall_ratio", C.c_double), ("hem", C.c_int32)]
 
 
 class amg_info(C.Structure):
@@ -297,7 +297,8 @@ class Hierarchy:
         import torch
 
         x = torch.zeros_like(b) if x is None else x
-        info = krylov_solve(self.h, {"pcg": PCG, "bicgstab": BICGSTAB}[method], b, x, rtol, maxit, stream, check)
+        info = krylov_solve(self.h, {"pcg": PCG, "bicgstab": BICGSTAB, "stationary": STATIONARY}[method], b, x, rtol,
+                            maxit, stream, check)
         return x, info
 
     def stats(self):

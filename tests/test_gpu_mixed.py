@@ -160,6 +160,15 @@ def test_fp32_rtol_near_double_limit(torch):
     mixed_solve_check(torch, a, "pcg", 1e-12, inv_norm=inv_norm2(a))
 
 
+@pytest.mark.parametrize("name", ["poisson3d_17x13x11", "lognormal3d_11"])
+def test_fp32_stationary_solver(torch, name):
+    # iterative refinement with a float V-cycle: the update and the residual
+    # are double, so the double tolerance is reached
+    say("case", name)
+    a = CASES[name]()
+    mixed_solve_check(torch, a, "stationary", 1e-10, inv_norm=inv_norm2(a))
+
+
 def test_fp32_parameter_rules(torch):
     a = P.poisson3d(10, 9, 8)
     A = hemamg.DeviceCSR.from_host(a)

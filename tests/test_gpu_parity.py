@@ -41,7 +41,7 @@ def dev(torch, x):
 def both(a, **kw):
     gp = hemamg.amg_params_default(**kw)
     okw = {k: v for k, v in kw.items() if k in ("passes_per_level", "max_coarse_rows", "max_levels",
-                                                  "max_dense_rows", "omega", "pre", "post", "stall_ratio")}
+                                                  "max_dense_rows", "omega", "pre", "post", "stall_ratio", "hem")}
     A = hemamg.DeviceCSR.from_host(a)
     g = hemamg.Hierarchy(A, gp)
     o = oracle.Hierarchy(a, **okw)
@@ -161,6 +161,52 @@ def test_solve_matches_oracle(torch, name):
     say("case", name)
     method = "bicgstab" if name in NONSYM else "pcg"
     solve_parity(torch, CASES[name](), method, 1e-8)
+
+
+@pytest.mark.parametrize("name", ["poisson2d_64", "poisson3d_17x13x11", "lognormal3d_11", "vardiff3d_20",
+                                  "convdiff3d_13"])
+def test_stationary_solver_matches_oracle(torch, name):
+    """AMG as a solver (Algorithm 1 repeated): x += V(b - A x)."""
+    say("case", name)
+    solve_parity(torch, CASES[name](), "stationary", 1e-8)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_edge_based_matching_matches_oracle(torch, name):
+    """Algorithm 3 (edges by weight, ties by endpoints): hierarchy bit-identical
+    to the oracle's literal sort-and-scan, and the solve in parity."""
+    say("case", name)
+    a = CASES[name]()
+    g, o = both(a, hem=1)
+    assert_same_hierarchy(g, o)
+    g.close()
+    solve_parity(torch, a, "bicgstab" if name in NONSYM else "pcg", 1e-8, hem=1)
+
+
+def test_edge_based_matching_high_contrast_80(torch):
+    a = P.vardiff3d(80, seed=0)
+    g, o = both(a, hem=1)
+    assert_same_hierarchy(g, o)
+    say("levels", g.nlevels, "rounds per pass", g.stats()["rounds"])
+    g.close()
+    A = hemamg.DeviceCSR.from_host(a)
+    with pytest.raises(hemamg.AmgError) as e:
+        hemamg.Hierarchy(A, hemamg.amg_params_default(hem=2))
+    assert e.value.status == hemamg.AMG_EINVAL
+
+
+def test_edge_based_matching_stall_reported_like_oracle(torch):
+    """On a strongly heterogeneous field the edge-ordered matching leaves many
+    vertices whose neighbours are all taken, coarsening stalls above the dense
+    limit, and setup reports the stall on both sides."""
+    a = P.lognormal_diffusion3d(64, 7, 2.0)
+    with pytest.raises(oracle.OracleError) as eo:
+        oracle.Hierarchy(a, hem=1)
+    assert eo.value.status == oracle.ESTALL
+    A = hemamg.DeviceCSR.from_host(a)
+    with pytest.raises(hemamg.AmgError) as e:
+        hemamg.Hierarchy(A, hemamg.amg_params_default(hem=1))
+    assert e.value.status == hemamg.AMG_ESTALL
 
 
 @pytest.mark.parametrize("kw", [dict(pre=2, post=2), dict(pre=0, post=1), dict(pre=1, post=0),
