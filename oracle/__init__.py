@@ -24,7 +24,7 @@ _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 class Params(C.Structure):
     _fields_ = [("passes_per_level", C.c_int32), ("max_coarse_rows", C.c_int32), ("max_levels", C.c_int32),
                 ("max_dense_rows", C.c_int32), ("omega", C.c_double), ("pre", C.c_int32), ("post", C.c_int32),
-                ("stall_ratio", C.c_double), ("hem", C.c_int32)]
+                ("stall_ratio", C.c_double), ("hem", C.c_int32), ("alternate", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -42,6 +42,7 @@ def lib():
             _b.build()
         L = C.CDLL(_LIB_PATH)
         L.oracle_hem_pass.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _i32p]
+        L.oracle_hem_pass_desc.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _i32p]
         L.oracle_ehem_pass.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _i32p]
         L.oracle_number.argtypes = [C.c_int32, _i32p, _i32p]
         L.oracle_number.restype = C.c_int32
@@ -82,6 +83,15 @@ def hem_pass(a) -> np.ndarray:
     n, rp, ci, v = _csr_args(a)
     mate = np.empty(n, dtype=np.int32)
     lib().oracle_hem_pass(n, rp, ci, v, mate)
+    return mate
+
+
+def hem_pass_desc(a) -> np.ndarray:
+    """Algorithm 2 matching from the last index: mate[i] = partner or -1."""
+    n, rp, ci, v = _csr_args(a)
+    mate = np.empty(n, dtype=np.int32)
+    if lib().oracle_hem_pass_desc(n, rp, ci, v, mate) != 0:
+        raise MemoryError("oracle_hem_pass_desc")
     return mate
 
 

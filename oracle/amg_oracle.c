@@ -63,6 +63,38 @@ int oracle_hem_pass(int32_t n, const int32_t* rp, const int32_t* ci, const doubl
     return ORACLE_OK;
 }
 
+/* Section 2.1.1: matching "from the last index".  The same greedy rule as  */
+/* above with the visiting order reversed: vertices from n-1 down to 0, and  */
+/* each row's neighbours from the highest column down, so among equal        */
+/* weights the first met (the highest index) wins.                           */
+int oracle_hem_pass_desc(int32_t n, const int32_t* rp, const int32_t* ci, const double* v, int32_t* mate) {
+    char* assigned = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!assigned) return ORACLE_ENOMEM;
+    for (int32_t i = 0; i < n; ++i) mate[i] = -1;
+    for (int32_t i = n - 1; i >= 0; --i) {
+        if (assigned[i]) continue;
+        double k = -1.0;
+        int32_t match = -1;
+        for (int32_t e = rp[i + 1] - 1; e >= rp[i]; --e) {
+            int32_t j = ci[e];
+            if (j == i || assigned[j] || v[e] == 0.0) continue;
+            double w = fabs(v[e]);
+            if (w > k) {
+                k = w;
+                match = j;
+            }
+        }
+        if (match >= 0) {
+            mate[i] = match;
+            mate[match] = i;
+            assigned[match] = 1;
+        }
+        assigned[i] = 1;
+    }
+    free(assigned);
+    return ORACLE_OK;
+}
+
 typedef struct {
     double w;
     int32_t lo, hi;
@@ -287,6 +319,7 @@ void oracle_params_default(oracle_params* p) {
     p->max_dense_rows = 1024;
     p->stall_ratio = 0.9;
     p->hem = 0;
+    p->alternate = 0;
     p->omega = 2.0 / 3.0;
     p->pre = 1;
     p->post = 1;
@@ -336,8 +369,11 @@ static int make_dinv(olevel* L) {
 }
 
 /* One coarsening step: passes_per_level rounds of (Alg. 2 + Galerkin product), */
-/* composing the aggregate maps.  On success fills *C and fine->agg.           */
-static int coarsen(olevel* F, int32_t passes, int32_t hem, olevel* C) {
+/* composing the aggregate maps.  On success fills *C and fine->agg.  `first`   */
+/* is the setup-wide index of the level's first pass; with `alternate` the odd  */
+/* ones run from the last index.  Coarse ids follow each aggregate's smallest   */
+/* fine index in either direction.                                             */
+static int coarsen(olevel* F, int32_t passes, int32_t hem, int32_t alternate, int32_t first, olevel* C) {
     int32_t n = F->n;
     int32_t* rp = F->rp;
     int32_t* ci = F->ci;
@@ -351,8 +387,10 @@ static int coarsen(olevel* F, int32_t passes, int32_t hem, olevel* C) {
     for (int32_t p = 0; p < passes; ++p) {
         if (hem == 1) {
             if (oracle_ehem_pass(n, rp, ci, v, mate) != ORACLE_OK) return ORACLE_ENOMEM;
+        } else if (alternate && ((first + p) & 1)) {
+            if (oracle_hem_pass_desc(n, rp, ci, v, mate) != ORACLE_OK) return ORACLE_ENOMEM;
         } else {
-            oracle_hem_pass(n, rp, ci, v, mate);
+            if (oracle_hem_pass(n, rp, ci, v, mate) != ORACLE_OK) return ORACLE_ENOMEM;
         }
         int32_t nc = oracle_number(n, mate, agg); /* ids by each aggregate's minimum fine index */
         int64_t nnzc = oracle_rap_nnz(n, rp, ci, agg, nc);
@@ -404,7 +442,8 @@ oracle_hier* oracle_setup(int32_t n, const int32_t* rp, const int32_t* ci, const
     else oracle_params_default(&h->p);
     int32_t maxlev = h->p.max_levels < MAXLEV ? h->p.max_levels : MAXLEV;
     if (h->p.passes_per_level < 1 || maxlev < 1 || h->p.pre < 0 || h->p.post < 0 ||
-        !(h->p.stall_ratio > 0.0 && h->p.stall_ratio <= 1.0) || h->p.hem < 0 || h->p.hem > 1) {
+        !(h->p.stall_ratio > 0.0 && h->p.stall_ratio <= 1.0) || h->p.hem < 0 || h->p.hem > 1 ||
+        h->p.alternate < 0 || h->p.alternate > 1 || (h->p.alternate && h->p.hem)) {
         oracle_destroy(h);
         *status = ORACLE_EINVAL;
         return NULL;
@@ -418,7 +457,7 @@ oracle_hier* oracle_setup(int32_t n, const int32_t* rp, const int32_t* ci, const
             if (F->n > h->p.max_dense_rows) st = ORACLE_ESTALL;
             break;
         }
-        st = coarsen(F, h->p.passes_per_level, h->p.hem, &h->lev[k + 1]);
+        st = coarsen(F, h->p.passes_per_level, h->p.hem, h->p.alternate, k * h->p.passes_per_level, &h->lev[k + 1]);
         if (st != ORACLE_OK) break;
         if (h->lev[k + 1].n == F->n) { /* no progress */
             free_level(&h->lev[k + 1]);

@@ -44,6 +44,10 @@ typedef struct {
                                * only when no row is merged                    */
     int32_t hem;              /* 0: node-based matching (Algorithm 2), 1: edge- *
                                * based (Algorithm 3) (0)                       */
+    int32_t alternate;        /* 1: node-based passes alternate direction, the *
+                               * setup's passes counted from 0 across levels:  *
+                               * even passes from the first index, odd ones    *
+                               * from the last (0)                             */
 } oracle_params;
 
 typedef struct {
@@ -56,6 +60,12 @@ typedef struct {
 /* Section 2.1.1, Algorithm 2: one node-based heavy-edge-matching pass.
  * mate[i] = partner of i, or -1 if i stays an unaggregated singleton. */
 int oracle_hem_pass(int32_t n, const int32_t* rp, const int32_t* ci, const double* v, int32_t* mate);
+
+/* Section 2.1.1, matching from the last index: the pass of Algorithm 2 with
+ * the vertices visited in descending order and each row scanned in descending
+ * column order, so equal weights go to the highest column index.  mate as in
+ * oracle_hem_pass. */
+int oracle_hem_pass_desc(int32_t n, const int32_t* rp, const int32_t* ci, const double* v, int32_t* mate);
 
 /* Section 2.1.1, Algorithm 3: edge-based heavy-edge matching.  Every stored
  * non-zero off-diagonal entry (i, j) is an edge of weight |a_ij|; the list is

@@ -333,3 +333,93 @@ def test_ehem_hierarchy_and_solve():
     assert np.linalg.norm(a.to_scipy() @ x - b) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-9)
     with pytest.raises(oracle.OracleError):
         oracle.Hierarchy(a, hem=2)
+
+
+# ---------------------------------------------------------------- matching from the last index
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 9])
+def test_desc_chain_pairs_from_the_end(n):
+    # visiting from the last vertex pairs (n-1, n-2), (n-3, n-4), ... and an odd
+    # chain leaves vertex 0 alone
+    mate = oracle.hem_pass_desc(chain(n))
+    want = np.full(n, -1)
+    for i in range(n - 1, 0, -2):
+        want[i], want[i - 1] = i - 1, i
+    np.testing.assert_array_equal(mate, want)
+
+
+def test_desc_tie_goes_to_highest_index():
+    # vertex 3 is visited first; its neighbours 0 and 1 weigh the same -> it takes 1,
+    # and 2 then still finds 0 free.  Taking 0 would leave 1 and 2 alone.
+    A = np.array([[3, 0, -1, -1], [0, 3, 0, -1], [-1, 0, 3, 0], [-1, -1, 0, 3]], float)
+    np.testing.assert_array_equal(oracle.hem_pass_desc(P.from_dense(A)), [2, 3, 0, 1])
+
+
+def test_desc_heaviest_and_current_state():
+    # 3 takes 1 (heavier than 2); 2's only free neighbour is then 0
+    A = np.array([[4, 0, 1, 0], [0, 4, 1, 3], [1, 1, 4, 2], [0, 3, 2, 4]], float)
+    np.testing.assert_array_equal(oracle.hem_pass_desc(P.from_dense(A)), [2, 3, 0, 1])
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_desc_is_the_mirror_image_of_the_ascending_pass(seed):
+    # reversing the numbering (i -> n-1-i) turns "from the last index, ties to the
+    # highest" into "from the first index, ties to the lowest"
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 50))
+    a = P.random_symmetric_pattern(n, float(rng.uniform(0.05, 0.4)), seed, weights=(1, 2),
+                                   nonsym_values=bool(seed % 2), explicit_zeros=0.1 * (seed % 3 == 0))
+    dense = a.to_scipy().toarray()
+    r = P.from_dense(dense[::-1, ::-1].copy())
+    # explicit zeros are lost by from_dense; compare on the dense-built pair only
+    a2 = P.from_dense(dense)
+    m_desc = oracle.hem_pass_desc(a2)
+    m_rev = oracle.hem_pass(r)
+    want = np.where(m_rev[::-1] >= 0, n - 1 - m_rev[::-1], -1)
+    np.testing.assert_array_equal(m_desc, want)
+    # and the ascending/descending pair agrees with the sorted-edge greedy under
+    # the mirrored key
+    np.testing.assert_array_equal(m_rev, greedy_sorted_edges(r))
+
+
+def test_alternating_passes_on_a_chain():
+    # one pass per level: level 0 from the first index pairs (0,1),(2,3),...;
+    # level 1 (a 5-chain) from the last pairs (4,3),(2,1) and leaves 0; level 2
+    # (a 3-chain) from the first again pairs (0,1)
+    a = chain(10)
+    h = oracle.Hierarchy(a, passes_per_level=1, max_coarse_rows=1, alternate=1)
+    np.testing.assert_array_equal(h.level(0).agg, np.arange(10) // 2)
+    np.testing.assert_array_equal(h.level(1).agg, [0, 1, 1, 2, 2])
+    np.testing.assert_array_equal(h.level(2).agg, [0, 0, 1])
+    g = oracle.Hierarchy(a, passes_per_level=1, max_coarse_rows=1)
+    np.testing.assert_array_equal(g.level(1).agg, [0, 0, 1, 1, 2])
+
+
+@pytest.mark.parametrize("ppl", [1, 2])
+def test_alternating_hierarchy_composes_the_passes(ppl):
+    # the setup-wide pass index decides the direction: even from the first
+    # index, odd from the last
+    a = P.lognormal_diffusion3d(7, 5, 1.0)
+    h = oracle.Hierarchy(a, passes_per_level=ppl, alternate=1, max_coarse_rows=8)
+    cur, g = a, 0
+    for k in range(h.nlevels - 1):
+        comp = np.arange(cur.n)
+        for _ in range(ppl):
+            mate = oracle.hem_pass_desc(cur) if g % 2 else oracle.hem_pass(cur)
+            agg, nc = oracle.number(mate)
+            crp, cci, cv = oracle.rap(cur, agg, nc)
+            comp = agg[comp]
+            cur, g = P.CSR(nc, crp, cci, cv), g + 1
+        L, C = h.level(k), h.level(k + 1)
+        np.testing.assert_array_equal(L.agg, comp)
+        np.testing.assert_array_equal(C.row_ptr, cur.row_ptr)
+        np.testing.assert_array_equal(C.col, cur.col)
+        np.testing.assert_array_equal(C.val.view(np.int64), cur.val.view(np.int64))
+
+
+def test_alternate_parameter_checks():
+    a = P.poisson2d(6)
+    for kw in (dict(alternate=2), dict(alternate=-1), dict(alternate=1, hem=1)):
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.Hierarchy(a, **kw)
+        assert e.value.status == oracle.EINVAL
