@@ -106,13 +106,13 @@ def iteration_bytes(sizes, method, e):
     return 2 * vc + 2 * (16 + e) * n + 2 * spmv + 24 * n + 72 * n + 32 * n
 
 
-def cpu_baseline(a, b, spec, gpu_iters, hem=0, budget_s=25.0):
+def cpu_baseline(a, b, spec, gpu_iters, hem=0, alternate=0, budget_s=25.0):
     """The oracle (single-threaded C) on the same input: setup + solve, with
     the solve cut to fit `budget_s` and scaled to the GPU's iteration count."""
     import oracle
 
     t0 = time.perf_counter()
-    h = oracle.Hierarchy(a, hem=hem)
+    h = oracle.Hierarchy(a, hem=hem, alternate=alternate)
     t_setup = time.perf_counter() - t0
     # time a few iterations first to size the sample
     t0 = time.perf_counter()
@@ -228,6 +228,8 @@ def main():
                     help="preconditioner precision (default: the workload's)")
     ap.add_argument("--hem", choices=["node", "edge"], default="node",
                     help="matching: node-based (Algorithm 2) or edge-based (Algorithm 3)")
+    ap.add_argument("--alternate", action="store_true",
+                    help="node-based passes alternate between the first and the last index")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="no HIP events in the timed region (roofline fields are then null)")
@@ -263,7 +265,8 @@ def main():
     b = torch.from_numpy(b_host).cuda()
     x = torch.zeros_like(b)
     precond = args.precond or spec["precond"]
-    params = hemamg.amg_params_default(precond_fp32=int(precond == "fp32"), hem=int(args.hem == "edge"))
+    params = hemamg.amg_params_default(precond_fp32=int(precond == "fp32"), hem=int(args.hem == "edge"),
+                                        alternate=int(args.alternate))
     esz = 4 if precond == "fp32" else 8
     mcode = hemamg.PCG if method == "pcg" else hemamg.BICGSTAB
     torch.cuda.synchronize()
@@ -342,7 +345,8 @@ def main():
         "dtype": "f64" if precond == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "desc": spec["desc"], "n": a.n, "nnz": a.nnz, "rtol": spec["rtol"],
-                   "method": method, "precond": precond, "hem": args.hem, "levels": len(sizes), "seed": args.seed},
+                   "method": method, "precond": precond, "hem": args.hem,
+                   "alternate": int(args.alternate), "levels": len(sizes), "seed": args.seed},
         "setup_ms": setup_ms,
         "solve_ms": solve_ms,
         "destroy_ms": float(np.median([r["destroy_ms"] for r in recs])),
@@ -366,7 +370,8 @@ def main():
         log("copied 268435456 bytes device-to-device for counter calibration")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the same input")
-        out["cpu_baseline"] = cpu_baseline(a, b_host, spec, iters, hem=int(args.hem == "edge"))
+        out["cpu_baseline"] = cpu_baseline(a, b_host, spec, iters, hem=int(args.hem == "edge"),
+                                           alternate=int(args.alternate))
     print(json.dumps(out), flush=True)
 
 

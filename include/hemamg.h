@@ -80,6 +80,14 @@ typedef struct {
     int32_t hem;              /* matching: 0 node-based (Algorithm 2), 1 edge-
                                * based (Algorithm 3: edges by weight descending,
                                * ties by smaller then larger endpoint) (0)         */
+    int32_t alternate;        /* 1: node-based passes alternate direction (Section
+                               * 2.1.1): the setup's passes, counted from 0 across
+                               * levels, start from the first index when even and
+                               * from the last when odd (vertices and row entries
+                               * scanned downward, ties to the highest index);
+                               * coarse ids follow each aggregate's smallest fine
+                               * index either way.  Needs hem = 0.  0: every pass
+                               * from the first index (0)                          */
 } amg_params;
 
 /* Result of a Krylov solve.  [host] */

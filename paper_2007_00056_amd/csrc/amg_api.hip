@@ -386,12 +386,20 @@ struct SetupWork {
     int hem_small = 65536;  // passes on at most this many rows run in one workgroup
 
     bool edge = false;  // edge-based matching (Algorithm 3)
+    int* mrp = nullptr;  // mirrored matrix of a pass from the last index
+    int* mci = nullptr;
+    double* mv = nullptr;
 
-    void init(int n, int64_t nnz, DevPool& P, int* err, bool edge_based) {
+    void init(int n, int64_t nnz, DevPool& P, int* err, bool edge_based, bool alternate) {
         edge = edge_based;
         if (edge) {
             hw.wsym = P.get<double>((size_t)nnz);
             hw.ptr = P.get<int>(n);
+        }
+        if (alternate) {  // every later pass has at most n rows and nnz entries
+            mrp = P.get<int>((size_t)n + 1);
+            mci = P.get<int>((size_t)nnz);
+            mv = P.get<double>((size_t)nnz);
         }
         hw.lowok = P.get<uint8_t>((size_t)nnz);
         hw.rec_bytes = sizeof(HemRecT<7>) * (size_t)n;
@@ -459,10 +467,20 @@ void run_rounds(SetupWork& W, HemWork& w, int n, hipStream_t s, Launch&& launch_
     }
 }
 
-Pass hem_pass(const Csr& B, SetupWork& W, int t, hipStream_t s, int* err) {
-    const int n = B.n;
+// from_last: the pass starts from the last index (run on the mirrored matrix,
+// its pairs mapped back before numbering).
+Pass hem_pass(const Csr& Bin, SetupWork& W, int t, hipStream_t s, int* err, bool from_last) {
+    const int n = Bin.n;
+    Csr B = Bin;
     HemWork w = W.hw;
     w.mate = W.mate[t];
+    if (from_last) {
+        launch_mirror_csr(n, Bin.nnz, Bin.rp, Bin.ci, Bin.v, W.mrp, W.mci, W.mv, s);
+        B.rp = W.mrp;
+        B.ci = W.mci;
+        B.v = W.mv;
+        w.mate = W.agg[t];  // free until numbering writes the aggregate map
+    }
     // record side from the average row length, within the record buffer
     const double avg = n > 0 ? (double)B.nnz / n : 0.0;
     w.side = avg <= 9.0 ? 7 : (avg <= 20.0 || n <= W.hem_small ? 15 : 31);  // one-workgroup passes: at most 15
@@ -479,6 +497,10 @@ Pass hem_pass(const Csr& B, SetupWork& W, int t, hipStream_t s, int* err) {
         } else {
             run_rounds(W, w, n, s, [&](int r) { launch_hem_round(r, n, B.rp, B.ci, B.v, w, s); });
         }
+    }
+    if (from_last) {
+        launch_unmirror_mate(n, w.mate, W.mate[t], s);
+        w.mate = W.mate[t];
     }
     Pass P;
     P.mate = w.mate;
@@ -1035,6 +1057,8 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     if (p.precond_fp32 != 0 && p.precond_fp32 != 1) raise(AMG_EINVAL, "precond_fp32 must be 0 or 1");
     if (!(p.stall_ratio > 0.0 && p.stall_ratio <= 1.0)) raise(AMG_EINVAL, "stall_ratio must be in (0, 1]");
     if (p.hem != 0 && p.hem != 1) raise(AMG_EINVAL, "hem must be 0 (node-based) or 1 (edge-based)");
+    if (p.alternate != 0 && p.alternate != 1) raise(AMG_EINVAL, "alternate must be 0 or 1");
+    if (p.alternate && p.hem != 0) raise(AMG_EINVAL, "alternate applies to node-based matching (hem = 0)");
     if (p.precond_fp32 && !(p.pre == 1 && p.post == 1))
         raise(AMG_EINVAL, "a float preconditioner needs one pre- and one post-sweep");
     const amg_csr& A = *Ain;
@@ -1066,13 +1090,15 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
 
     DevPool wpool;
     wpool.s = s;
-    wpool.hint((size_t)A.nnz * (p.hem == 1 ? 9 : 1) + 168 * (size_t)A.n + 4096);
+    wpool.hint((size_t)A.nnz * (p.hem == 1 ? 9 : 1) + 168 * (size_t)A.n + 4096 +
+               (p.alternate ? 12 * (size_t)A.nnz + 4 * (size_t)A.n : 0));
     struct WpoolGuard {
         DevPool& t;
         ~WpoolGuard() { t.release(); }
     } wg{wpool};
     SetupWork SW;
-    if (A.n > p.max_coarse_rows && p.max_levels > 1) SW.init(A.n, A.nnz, wpool, h->err, p.hem == 1);
+    if (A.n > p.max_coarse_rows && p.max_levels > 1)
+        SW.init(A.n, A.nnz, wpool, h->err, p.hem == 1, p.alternate == 1);
     for (int k = 0;; ++k) {
         Level& F = h->lev[k];
         if (F.n <= p.max_coarse_rows) break;
@@ -1089,7 +1115,9 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
             ~TmpGuard() { t.release(); }
         } tg{tmp};
         Csr B{F.n, F.nnz, const_cast<int*>(F.rp), const_cast<int*>(F.ci), const_cast<double*>(F.v)};
-        Pass p1 = hem_pass(B, SW, 0, s, h->err);
+        // setup-wide pass index: with alternate, odd passes start from the last index
+        const int g0 = k * p.passes_per_level;
+        Pass p1 = hem_pass(B, SW, 0, s, h->err, p.alternate && (g0 & 1));
         DevPool& out1 = (p.passes_per_level == 1) ? P : tmp;
         Csr C1 = galerkin(B, p1, SW, out1, s, h->err);
         h->rounds.push_back(p1.rounds);
@@ -1097,7 +1125,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
         int* agg = nullptr;
         int4* mem = nullptr;
         if (p.passes_per_level == 2) {
-            Pass p2 = hem_pass(C1, SW, 1, s, h->err);
+            Pass p2 = hem_pass(C1, SW, 1, s, h->err, p.alternate && ((g0 + 1) & 1));
             Cf = galerkin(C1, p2, SW, P, s, h->err);
             h->rounds.push_back(p2.rounds);
             agg = P.get<int>(F.n);
@@ -1210,6 +1238,7 @@ amg_status amg_params_default(amg_params* p) {
     p->precond_fp32 = 0;
     p->stall_ratio = 0.9;
     p->hem = 0;
+    p->alternate = 0;
     return AMG_OK;
 }
 

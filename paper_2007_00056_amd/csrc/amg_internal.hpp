@@ -88,6 +88,12 @@ void launch_rap_fill_slow(int nc, const int* ovf, const int* novf, const int* le
                           const int* ci, const double* v, const int* agg, const int* crp, int* cci, double* cv,
                           hipStream_t s);
 
+// Matching from the last index: the mirrored matrix (i -> n-1-i) and the map of
+// its pairs back to the original numbering.
+void launch_mirror_csr(int n, int64_t nnz, const int* rp, const int* ci, const double* v, int* mrp, int* mci,
+                       double* mv, hipStream_t s);
+void launch_unmirror_mate(int n, const int* mr, int* mate, hipStream_t s);
+
 void launch_compose(int n, const int* agg1, const int* agg2, int* out, hipStream_t s);
 // Member lists (ascending fine rows, -1 padded) of the level's coarse rows.
 void launch_members(int nc, const int* lead2, const int* mate2, const int* lead1, const int* mate1, int4* mem,

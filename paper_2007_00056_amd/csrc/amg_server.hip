@@ -53,6 +53,8 @@ uint64_t footprint(int32_t n, int64_t nnz, const amg_params& p) {
     // Galerkin counts, the intermediate operator of a two-pass level, the
     // dense factorisation
     b += 256 * N + Z + 60 * N + (4 * N + 12 * Z) + dense;
+    if (p.hem == 1) b += 8 * Z + 4 * N;            // symmetric weights, pointers
+    if (p.alternate) b += 4 * N + 12 * Z + 4096;  // mirrored matrix of a pass from the last index
     return b;
 }
 

@@ -747,6 +747,43 @@ void launch_ehem_round(int r, int n, const int* rp, const int* ci, HemWork& w, h
                        w.wl[r & 1], w.wl[(r + 1) & 1], w.cnt, r % 3, (r + 1) % 3);
 }
 
+// ---------------------------------------------------------------------------
+// Matching from the last index (Section 2.1.1): vertices visited downward and
+// row entries scanned downward, ties to the highest index.  Renumbering
+// i -> n-1-i turns this into the upward pass, so it runs the kernels above on
+// the mirrored matrix and maps the pairs back.  Mirroring reverses the order
+// of the rows and, with it, of the entries inside each row: the column and
+// value arrays are read backwards as a whole and the columns stay ascending.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BS) void k_mirror_csr(int n, int64_t nnz, const int* __restrict__ rp,
+                                                   const int* __restrict__ ci, const double* __restrict__ v,
+                                                   int* __restrict__ mrp, int* __restrict__ mci,
+                                                   double* __restrict__ mv) {
+    const int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (e < nnz) {
+        mci[e] = n - 1 - ci[nnz - 1 - e];
+        mv[e] = v[nnz - 1 - e];
+    }
+    if (e <= n) mrp[e] = (int)(nnz - rp[n - e]);
+}
+
+__global__ __launch_bounds__(BS) void k_unmirror_mate(int n, const int* __restrict__ mr, int* __restrict__ mate) {
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    const int m = mr[n - 1 - i];
+    mate[i] = m < 0 ? -1 : n - 1 - m;
+}
+
+void launch_mirror_csr(int n, int64_t nnz, const int* rp, const int* ci, const double* v, int* mrp, int* mci,
+                       double* mv, hipStream_t s) {
+    const int64_t work = nnz > (int64_t)n + 1 ? nnz : (int64_t)n + 1;
+    hipLaunchKernelGGL(k_mirror_csr, dim3(blocks_for(work)), dim3(BS), 0, s, n, nnz, rp, ci, v, mrp, mci, mv);
+}
+
+void launch_unmirror_mate(int n, const int* mr, int* mate, hipStream_t s) {
+    hipLaunchKernelGGL(k_unmirror_mate, dim3(blocks_for(n)), dim3(BS), 0, s, n, mr, mate);
+}
+
 #define AMG_HEM_SIDE(side, CALL) \
     switch (side) {                \
         case 7: CALL(7); break;    \

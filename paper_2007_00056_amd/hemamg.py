@@ -37,7 +37,8 @@ class amg_params(C.Structure):
     _fields_ = [("passes_per_level", C.c_int32), ("max_coarse_rows", C.c_int32), ("max_levels", C.c_int32),
                 ("max_dense_rows", C.c_int32), ("omega", C.c_double), ("pre", C.c_int32), ("post", C.c_int32),
                 ("true_res_period", C.c_int32), ("precond_fp32", C.c_int32),
-                ("stall_ratio", C.c_double), ("hem", C.c_int32)]
+                ("stall_ratio", C.c_double), ("hem", C.c_int32),
+                ("alternate", C.c_int32)]
 
 
 class amg_info(C.Structure):

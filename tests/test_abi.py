@@ -42,7 +42,7 @@ def test_binding_fails_loudly_without_library(monkeypatch):
 
 
 def test_struct_layouts_match_header():
-    # amg_params: 4 int32, double, 4 int32, double, int32 -> 56 bytes with natural alignment
+    # amg_params: 4 int32, double, 4 int32, double, 2 int32 -> 56 bytes with natural alignment
     assert ctypes.sizeof(hemamg.amg_params) == 56
     assert ctypes.sizeof(hemamg.amg_csr) == 40
     assert ctypes.sizeof(hemamg.amg_info) == 40
@@ -56,7 +56,7 @@ def test_params_default_values():
     p = hemamg.amg_params_default()  # host-only call, no GPU work
     assert (p.passes_per_level, p.max_coarse_rows, p.max_levels, p.max_dense_rows) == (2, 64, 32, 1024)
     assert abs(p.omega - 2.0 / 3.0) < 1e-16 and (p.pre, p.post, p.true_res_period) == (1, 1, 50)
-    assert p.precond_fp32 == 0 and p.stall_ratio == 0.9 and p.hem == 0
+    assert p.precond_fp32 == 0 and p.stall_ratio == 0.9 and p.hem == 0 and p.alternate == 0
 
 
 def test_footprint_and_server_defaults():
@@ -70,5 +70,7 @@ def test_footprint_and_server_defaults():
     assert 0 < small < big
     # the float preconditioner adds the float copies
     assert hemamg.amg_footprint_bytes(884736, 6137856, hemamg.amg_params_default(precond_fp32=1)) > big - 20 * 884736
+    # the mirrored matrix of passes from the last index is counted
+    assert hemamg.amg_footprint_bytes(884736, 6137856, hemamg.amg_params_default(alternate=1)) >= big + 12 * 6137856
     with pytest.raises(hemamg.AmgError):
         hemamg.amg_footprint_bytes(-1, 10)

@@ -41,7 +41,8 @@ def dev(torch, x):
 def both(a, **kw):
     gp = hemamg.amg_params_default(**kw)
     okw = {k: v for k, v in kw.items() if k in ("passes_per_level", "max_coarse_rows", "max_levels",
-                                                  "max_dense_rows", "omega", "pre", "post", "stall_ratio", "hem")}
+                                                  "max_dense_rows", "omega", "pre", "post", "stall_ratio", "hem",
+                                                  "alternate")}
     A = hemamg.DeviceCSR.from_host(a)
     g = hemamg.Hierarchy(A, gp)
     o = oracle.Hierarchy(a, **okw)
@@ -93,17 +94,18 @@ DRIVERS = {
 }
 
 
+@pytest.mark.parametrize("alternate", [0, 1])
 @pytest.mark.parametrize("driver", list(DRIVERS))
 @pytest.mark.parametrize("name", list(CASES))
-def test_matching_drivers_bit_identical(torch, name, driver, monkeypatch):
+def test_matching_drivers_bit_identical(torch, name, driver, alternate, monkeypatch):
     """Every pass through one matching driver whatever its size (the default
     sends small passes to the LDS-state workgroup): each driver must give the
-    oracle's hierarchy."""
-    say("case", name, "driver", driver)
+    oracle's hierarchy, with passes from the first index only or alternating."""
+    say("case", name, "driver", driver, "alternate", alternate)
     for k, v in DRIVERS[driver].items():
         monkeypatch.setenv(k, v)
     a = CASES[name]()
-    g, o = both(a)
+    g, o = both(a, alternate=alternate)
     assert_same_hierarchy(g, o)
     g.close()
 
@@ -193,6 +195,33 @@ def test_edge_based_matching_high_contrast_80(torch):
     with pytest.raises(hemamg.AmgError) as e:
         hemamg.Hierarchy(A, hemamg.amg_params_default(hem=2))
     assert e.value.status == hemamg.AMG_EINVAL
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("ppl", [1, 2])
+def test_alternating_direction_matches_oracle(torch, name, ppl):
+    """Passes alternate between the first and the last index (Section 2.1.1);
+    the GPU runs a pass from the last index on the mirrored matrix."""
+    say("case", name, "passes", ppl)
+    a = CASES[name]()
+    g, o = both(a, alternate=1, passes_per_level=ppl)
+    assert_same_hierarchy(g, o)
+    g.close()
+    if ppl == 2:
+        solve_parity(torch, a, "bicgstab" if name in NONSYM else "pcg", 1e-8, alternate=1)
+
+
+def test_alternating_direction_at_128(torch):
+    a = P.poisson3d(128)
+    g, o = both(a, alternate=1)
+    assert_same_hierarchy(g, o)
+    say("levels", g.nlevels)
+    g.close()
+    A = hemamg.DeviceCSR.from_host(a)
+    for kw in (dict(alternate=2), dict(alternate=1, hem=1)):
+        with pytest.raises(hemamg.AmgError) as e:
+            hemamg.Hierarchy(A, hemamg.amg_params_default(**kw))
+        assert e.value.status == hemamg.AMG_EINVAL
 
 
 def test_edge_based_matching_stall_reported_like_oracle(torch):
