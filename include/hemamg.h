@@ -213,6 +213,43 @@ amg_status amg_server_wait(amg_server* s, int64_t ticket, amg_info* info, double
  * Results of requests nobody waited for are discarded.  NULL is accepted. */
 amg_status amg_server_destroy(amg_server* s);
 
+/* ------------------------------------------------------------------------
+ * Batched solves: many independent systems of different sizes advanced
+ * together, each kernel launch of the V-cycle (Algorithm 1) and of the
+ * preconditioned CG iteration (Algorithm 4) covering every system.
+ * A batch copies the hierarchies it is made from into concatenated levels
+ * (the hierarchies may be destroyed once amg_batch_create returns).  Each
+ * system keeps its own CG scalars, stop test, residual replacement and
+ * breakdown checks, exactly as krylov_solve applies them; a finished system
+ * is masked off while the others continue.  A system's result does not
+ * depend on which other systems share the batch.  One thread at a time per
+ * batch.
+ * ------------------------------------------------------------------------ */
+typedef struct amg_batch amg_batch;
+
+/* Builds a batch from `count` hierarchies (order kept).  Every hierarchy needs
+ * at least two levels and pre = post = 1, and all must share precond_fp32,
+ * omega and true_res_period.  Blocks the host until the copies are done.
+ * Errors: AMG_EINVAL, AMG_ENOMEM, AMG_EHIP. */
+amg_status amg_batch_create(const amg_hier* const* hiers, int32_t count, void* stream, amg_batch** out);
+
+/* offsets: [host] int32[count + 1]; system i occupies rows
+ * offsets[i] .. offsets[i+1]-1 of the batch vectors. */
+amg_status amg_batch_rows(const amg_batch* b, int32_t* offsets);
+
+/* Preconditioned CG (method must be 0) on every system at once.
+ * b, x: [device] float64[offsets[count]], the systems' right-hand sides and
+ * initial guesses one after another; x receives the solutions.  info: [host]
+ * amg_info[count], one per system (status per system; solve_ms is the call's
+ * wall time).  Returns AMG_OK when every system converged, else the first
+ * failing system's status.  Blocks the host until done.
+ * Errors: AMG_EINVAL, AMG_ENOTFINITE, AMG_ENOTCONV, AMG_EBREAKDOWN, AMG_EHIP. */
+amg_status amg_batch_solve(amg_batch* bt, int32_t method, const double* b, double* x, double rtol, int32_t maxit,
+                           void* stream, amg_info* info);
+
+/* Frees the batch.  NULL is accepted. */
+amg_status amg_batch_destroy(amg_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,7 +10,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhemamg.so")
-SOURCES = ["k_setup.hip", "k_hem.hip", "k_solve.hip", "k_vcycle.hip", "amg_api.hip", "amg_server.hip"]
+SOURCES = ["k_setup.hip", "k_hem.hip", "k_solve.hip", "k_vcycle.hip", "k_batch.hip", "amg_api.hip", "amg_server.hip",
+           "amg_batch.hip"]
 ARCH = os.environ.get("HEMAMG_ARCH", "gfx950")
 
 FLAGS = [

@@ -1,0 +1,257 @@
+// Host-side infrastructure shared by the library's host sources: error
+// reporting, device memory arenas, pooled streams, events and pinned memory,
+// and the hierarchy handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "amg_internal.hpp"
+#include "hemamg.h"
+
+namespace amg {
+inline thread_local std::string g_err = "no error";
+
+struct Failure {
+    amg_status st;
+    std::string msg;
+};
+
+[[noreturn]] inline void raise(amg_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    throw Failure{st, buf};
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            if (e_ == hipErrorOutOfMemory) raise(AMG_ENOMEM, "%s: out of GPU memory", #call); \
+            raise(AMG_EHIP, "%s: %s", #call, hipGetErrorString(e_));                          \
+        }                                                                                     \
+    } while (0)
+
+// Streams and events are kept in process-wide free lists per device:
+// creating and destroying them costs milliseconds per handle.  Streams are
+// non-blocking at the default priority; timing events record times, the
+// others do not.
+int current_device();
+hipStream_t stream_get();
+void stream_put(hipStream_t s);
+hipEvent_t event_get(bool timing);
+void event_put(hipEvent_t e, bool timing);
+// Pinned host blocks of 4 KiB (scalar slots of a handle), kept for reuse.
+void* pinned_get();
+void pinned_put(void* p);
+// Pinned host words for small read-backs (per thread, kept for the process).
+int* pinned_words();
+int read_int(const int* d, hipStream_t s);
+void raise_err_word(int e, const char* where);
+void check_err_word(const int* err, hipStream_t s, const char* where);
+
+// Device memory comes from a stream-ordered pool owned by the library (one
+// per device) that keeps freed blocks for reuse instead of returning them to
+// the driver, so building a hierarchy does not remap memory level by level.
+inline hipMemPool_t lib_pool() {
+    static std::mutex mu;
+    static std::map<int, hipMemPool_t> pools;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(mu);
+    auto it = pools.find(dev);
+    if (it != pools.end()) return it->second;
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    HIPCHK(hipMemPoolCreate(&pool, &props));
+    uint64_t keep = UINT64_MAX;
+    HIPCHK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+    pools[dev] = pool;
+    return pool;
+}
+
+// An arena over the pool: pieces (256-byte aligned) are carved from a few
+// chunks (sized from a hint, or by a larger request), so a handle makes a
+// handful of pool calls instead of one per array.
+struct DevPool {
+    hipStream_t s = nullptr;
+    hipMemPool_t mp = nullptr;
+    std::vector<void*> chunks;
+    char* cur = nullptr;
+    size_t left = 0;
+    size_t bytes = 0;                 // device memory held (sum of chunks)
+    size_t next_chunk = size_t(1) << 20;
+
+    void hint(size_t b) {
+        if (b > next_chunk) next_chunk = b;
+    }
+
+    template <class T>
+    T* get(size_t count) {
+        const size_t b = (((count > 0 ? count : 1) * sizeof(T)) + 255) & ~size_t(255);
+        if (b > left) {
+            if (!mp) mp = lib_pool();
+            const size_t c = b > next_chunk ? b : next_chunk;
+            void* p = nullptr;
+            HIPCHK(hipMallocFromPoolAsync(&p, c, mp, s));
+            chunks.push_back(p);
+            cur = static_cast<char*>(p);
+            left = c;
+            bytes += c;
+            next_chunk = c;
+        }
+        T* r = reinterpret_cast<T*>(cur);
+        cur += b;
+        left -= b;
+        return r;
+    }
+    void release() {
+        for (void* p : chunks) (void)hipFreeAsync(p, s);
+        chunks.clear();
+        cur = nullptr;
+        left = 0;
+        bytes = 0;
+        next_chunk = size_t(1) << 20;
+    }
+};
+
+struct Level {
+    int n = 0;
+    int64_t nnz = 0;
+    const int* rp = nullptr;
+    const int* ci = nullptr;
+    const double* v = nullptr;
+    double* dinv = nullptr;
+    int* agg = nullptr;    // to level k+1
+    int4* mem = nullptr;   // members of level k+1 rows
+    float* v32 = nullptr;     // float copy of the values (single-precision preconditioner)
+    float* dinv32 = nullptr;
+    // V-cycle vectors, of the preconditioner's value type (double or float)
+    void* f = nullptr;    // restricted right-hand side (k >= 1)
+    void* g = nullptr;    // D^{-1} f (k >= 1)
+    void* x = nullptr;    // correction (k >= 1)
+    void* xp = nullptr;   // prolongated iterate w D^{-1} f + P e (k < coarsest)
+    void* t = nullptr;    // residual scratch (CSR-stream levels) / general smoothing path
+    int lpr = 4;
+
+    LevelView view() const {
+        LevelView w;
+        w.n = n;
+        w.nnz = (int)nnz;
+        w.rp = rp;
+        w.ci = ci;
+        w.v = v;
+        w.dinv = dinv;
+        w.agg = agg;
+        w.mem = mem;
+        w.lpr = lpr;
+        return w;
+    }
+};
+
+// Scalar slots of the Krylov recurrences.
+enum Slot { S_BB = 0, S_RR, S_TRR, S_PQ, S_RHO0, S_RHO1, S_RV, S_TT, S_TS, S_COUNT = 16 };
+
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // start/stop pairs
+    size_t used = 0;
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+
+template <class F>
+amg_status guarded(F&& f) {
+    try {
+        f();
+        return AMG_OK;
+    } catch (const Failure& e) {
+        g_err = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return AMG_ENOMEM;
+    } catch (...) {
+        g_err = "unexpected internal error";
+        return AMG_EHIP;
+    }
+}
+
+inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace amg
+
+struct amg_hier {
+    using Level = amg::Level;
+    using DevPool = amg::DevPool;
+    using Timer = amg::Timer;
+    using Reducer = amg::Reducer;
+    amg_params p{};
+    std::vector<Level> lev;
+    int n_coarse = 0;
+    double* ainv_t = nullptr;
+    DevPool pool;
+    hipStream_t stream = nullptr;
+    std::vector<int> rounds;
+    // Krylov workspace (allocated on first solve)
+    double *r = nullptr, *z = nullptr, *pv[2] = {nullptr, nullptr}, *q = nullptr, *rb = nullptr, *pt = nullptr,
+           *sv = nullptr, *st = nullptr, *t = nullptr;
+    void* g0 = nullptr;  // D^{-1} times the level-0 right-hand side of the V-cycle
+    bool prec32 = false;  // V-cycle in float (values, vectors, accumulation)
+    double* S = nullptr;
+    double* part = nullptr;
+    int* err = nullptr;
+    int stream_min = 262144;  // levels with at least this many rows use CSR-stream kernels
+    double* S_host = nullptr;
+    Timer tim[3];
+    // PCG iteration graphs (one per ping-pong parity), replayed on gstream
+    bool use_graphs = false;  // HEMAMG_GRAPHS=1: replay PCG iterations from HIP graphs
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    hipGraphExec_t g_full[2] = {nullptr, nullptr};  // whole iteration
+    hipGraphExec_t g_a[2] = {nullptr, nullptr};     // up to the level-0 postsmoothing (timed mode)
+    hipGraphExec_t g_b[2] = {nullptr, nullptr};     // after it (timed mode)
+    const double* g_key_b = nullptr;
+    double* g_key_x = nullptr;
+
+    Reducer reducer() const { return Reducer{part, S}; }
+
+    void drop_graphs() {
+        for (int t = 0; t < 2; ++t) {
+            for (hipGraphExec_t* e : {&g_full[t], &g_a[t], &g_b[t]})
+                if (*e) {
+                    (void)hipGraphExecDestroy(*e);
+                    *e = nullptr;
+                }
+        }
+        g_key_b = nullptr;
+        g_key_x = nullptr;
+    }
+
+    ~amg_hier() {
+        drop_graphs();
+        if (gstream) (void)hipStreamSynchronize(gstream);
+        if (stream) (void)hipStreamSynchronize(stream);
+        pool.release();
+        if (stream) (void)hipStreamSynchronize(stream);
+        amg::pinned_put(S_host);
+        for (auto& T : tim)
+            for (hipEvent_t e : T.ev) amg::event_put(e, true);
+        for (hipEvent_t e : gev)
+            if (e) amg::event_put(e, false);
+        if (gstream) amg::stream_put(gstream);
+    }
+};

@@ -217,4 +217,56 @@ void launch_check_finite(int n, const double* a, const double* b, int* err, hipS
 
 constexpr int kRedBlocks = 65536;  // max blocks (partials) of a reduction kernel
 
+// ---- batched solves (k_batch.hip) -------------------------------------------
+// Systems ("segments") stored one after another.  blk[b] = (segment, first
+// row) of reduction block b (256 rows, never crossing a segment end);
+// seg_end[s] = one past the segment's last row; mask[s] != 0 selects the
+// segments a launch works on.  Scalars: S[s * kBatchSlots + slot].
+constexpr int kBatchSlots = 8;
+struct BatchTab {
+    const int2* blk;
+    const int* seg_end;
+    const int* mask;
+};
+// Coarsest solve of one segment: x = A_L^{-1} f on n rows (f, x already
+// offset to the segment), each result scattered to the finer level's rows
+// through sc at index row0 + i.
+template <class T>
+struct BDense {
+    int n;
+    int row0;
+    const double* ainv_t;
+    const T* f;
+    T* x;
+    ScatterT<T> sc;
+};
+// One copy of a batch assembly: kind 0 int32 (+add), 1 double, 2 float,
+// 3 int4 member lists (+add on the members present).
+struct GatherPiece {
+    const void* src;
+    void* dst;
+    int64_t count;
+    int add;
+    int kind;
+};
+int gather_chunk();  // elements per block of launch_gather
+
+void launch_bspmv_dot(int nblk, const BatchTab& T, const int* rp, const int* ci, const double* v, const double* p,
+                      double* q, const double* d, double* part, hipStream_t s);
+void launch_bresidual(int nblk, const BatchTab& T, const int* rp, const int* ci, const double* v, const double* x,
+                      const double* b, double* r, const double* dinv, void* g, bool g32, double* part,
+                      hipStream_t s);
+void launch_bdot(int nblk, const BatchTab& T, const double* a, const double* c, double* part, hipStream_t s);
+void launch_bfinish(int nseg, const int* seg_blk, const int* mask, const double* part, double* S, int slot_k,
+                    hipStream_t s);
+void launch_bcg_update(int nblk, const BatchTab& T, double* x, double* r, const double* p, const double* q,
+                       const double* dinv, void* g, bool g32, double* part, const double* S, int slot_rho,
+                       int slot_pq, hipStream_t s);
+void launch_bcg_dir(int nblk, const BatchTab& T, const double* z, const double* p, double* pn, const double* S,
+                    int slot_new, int slot_old, hipStream_t s);
+void launch_bzero(int nblk, const BatchTab& T, double* x, hipStream_t s);
+template <class T>
+void launch_bdense(int nblk, const BDense<T>* dd, const int2* tab, hipStream_t s);
+void launch_gather(int nblk, const GatherPiece* pcs, const int2* tab, hipStream_t s);
+
 }  // namespace amg

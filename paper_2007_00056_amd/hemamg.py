@@ -25,7 +25,8 @@ KERNEL_PROLONG_POST, KERNEL_RESID_RESTRICT, KERNEL_SPMV = 0, 1, 2
 EXPORTED = ["amg_params_default", "amg_setup", "amg_destroy", "amg_vcycle", "krylov_solve", "amg_num_levels",
             "amg_level_size", "amg_export_level", "amg_setup_stats", "amg_timing_enable", "amg_timing_read",
             "amg_last_error", "amg_footprint_bytes", "amg_server_config_default", "amg_server_create",
-            "amg_server_submit", "amg_server_wait", "amg_server_destroy"]
+            "amg_server_submit", "amg_server_wait", "amg_server_destroy", "amg_batch_create", "amg_batch_rows",
+            "amg_batch_solve", "amg_batch_destroy"]
 
 
 class amg_csr(C.Structure):
@@ -86,6 +87,10 @@ def lib():
             "amg_server_submit": [vp, C.POINTER(amg_csr), vp, vp, i32, f64, i32, C.POINTER(i64)],
             "amg_server_wait": [vp, i64, C.POINTER(amg_info), C.POINTER(f64)],
             "amg_server_destroy": [vp],
+            "amg_batch_create": [C.POINTER(vp), i32, vp, C.POINTER(vp)],
+            "amg_batch_rows": [vp, vp],
+            "amg_batch_solve": [vp, i32, vp, vp, f64, i32, vp, vp],
+            "amg_batch_destroy": [vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -254,6 +259,32 @@ def amg_server_destroy(s: int) -> None:
     _check(lib().amg_server_destroy(s))
 
 
+def amg_batch_create(handles, stream=None) -> int:
+    arr = (C.c_void_p * len(handles))(*handles)
+    b = C.c_void_p()
+    _check(lib().amg_batch_create(arr, len(handles), _stream_ptr(stream), C.byref(b)))
+    return b.value
+
+
+def amg_batch_rows(b: int, count: int) -> np.ndarray:
+    off = np.empty(count + 1, np.int32)
+    _check(lib().amg_batch_rows(b, off.ctypes.data))
+    return off
+
+
+def amg_batch_solve(b: int, method: int, rhs, x, rtol: float, maxit: int, count: int, stream=None) -> list:
+    """Solves every system of the batch; returns one summary per system (the
+    statuses are reported, not raised)."""
+    infos = (amg_info * count)()
+    lib().amg_batch_solve(b, method, _ptr(rhs), _ptr(x), rtol, maxit, _stream_ptr(stream), infos)
+    return [dict(status=i.status, iters=i.iters, rel_res=i.rel_res, true_rel_res=i.true_rel_res,
+                 solve_ms=i.solve_ms) for i in infos]
+
+
+def amg_batch_destroy(b: int) -> None:
+    _check(lib().amg_batch_destroy(b))
+
+
 # ---------------------------------------------------------------- convenience
 
 class Hierarchy:
@@ -304,3 +335,33 @@ class Hierarchy:
 
     def stats(self):
         return amg_setup_stats(self.h)
+
+
+class Batch:
+    """Owns an amg_batch_create handle built from hierarchies."""
+
+    def __init__(self, hierarchies, stream=None):
+        self.count = len(hierarchies)
+        self.b = amg_batch_create([h.h if isinstance(h, Hierarchy) else h for h in hierarchies], stream)
+        self.offsets = amg_batch_rows(self.b, self.count)
+
+    def close(self):
+        if getattr(self, "b", None):
+            amg_batch_destroy(self.b)
+            self.b = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def solve(self, rhs, x=None, rtol: float = 1e-8, maxit: int = 1000, stream=None):
+        """rhs, x: device float64 vectors of offsets[-1] rows (systems one after
+        another).  Returns (x, list of per-system summaries)."""
+        import torch
+
+        x = torch.zeros_like(rhs) if x is None else x
+        return x, amg_batch_solve(self.b, PCG, rhs, x, rtol, maxit, self.count, stream)

@@ -1,0 +1,190 @@
+"""GPU tests of batched solves (amg_batch_*): systems of different sizes and
+depths advanced together.  Each system must follow the oracle (same stop
+iteration within one, the same iterate at equal iteration count), and its
+result must be bit-identical whether it is solved alone or in a mix, with or
+without graph replay."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_00056_amd import hemamg, problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+
+    assert _t.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return _t
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def bits(x):
+    return np.ascontiguousarray(x, dtype=np.float64).view(np.int64)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def mix():
+    """SPD systems of several sizes and hierarchy depths (a ragged mix)."""
+    out = [P.lognormal_diffusion3d(m, 1000 + m, 1.0) for m in (5, 9, 16, 23, 12, 31)]
+    out.append(P.poisson3d(21, 17, 13))
+    out.append(P.poisson2d(40))
+    out.append(P.vardiff3d(14, seed=2, corr_len=3.0))
+    return out
+
+
+def make_batch(torch, systems, params, seeds):
+    hs = [hemamg.Hierarchy(hemamg.DeviceCSR.from_host(a), params) for a in systems]
+    bt = hemamg.Batch(hs)
+    off = bt.offsets
+    rhs = np.concatenate([P.rhs_uniform(a.n, s) for a, s in zip(systems, seeds)])
+    assert off[-1] == rhs.size
+    return hs, bt, torch.from_numpy(rhs).cuda()
+
+
+def run(torch, systems, params, seeds, rtol=1e-8, maxit=500, x0=None):
+    hs, bt, rhs = make_batch(torch, systems, params, seeds)
+    try:
+        x = torch.zeros_like(rhs) if x0 is None else torch.from_numpy(x0).cuda()
+        x, infos = bt.solve(rhs, x, rtol=rtol, maxit=maxit)
+        off = bt.offsets
+        xs = x.cpu().numpy()
+        return [xs[off[i]:off[i + 1]] for i in range(len(systems))], infos
+    finally:
+        bt.close()
+        for h in hs:
+            h.close()
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_batch_follows_the_oracle(torch, fp32):
+    systems = mix()
+    seeds = list(range(len(systems)))
+    params = hemamg.amg_params_default(precond_fp32=fp32)
+    xs, infos = run(torch, systems, params, seeds)
+    for i, (a, x, inf) in enumerate(zip(systems, xs, infos)):
+        say("system", i, "n", a.n, inf)
+        assert inf["status"] == hemamg.AMG_OK
+        b = P.rhs_uniform(a.n, seeds[i])
+        assert np.linalg.norm(b - a.to_scipy() @ x) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-6)
+        o = oracle.Hierarchy(a)
+        xo, io = o.solve(b, rtol=1e-8, maxit=500)
+        if fp32:
+            assert abs(inf["iters"] - io["iters"]) <= max(2, int(0.05 * io["iters"])), (inf, io)
+        else:
+            assert abs(inf["iters"] - io["iters"]) <= 1, (inf, io)
+
+
+def test_batch_equal_iterations_match_the_oracle(torch):
+    systems = mix()
+    seeds = [7 + i for i in range(len(systems))]
+    K = 12
+    xs, infos = run(torch, systems, hemamg.amg_params_default(), seeds, rtol=0.0, maxit=K)
+    for i, (a, x, inf) in enumerate(zip(systems, xs, infos)):
+        assert inf["status"] == hemamg.AMG_ENOTCONV and inf["iters"] == K, inf
+        xo, io = oracle.Hierarchy(a).solve(P.rhs_uniform(a.n, seeds[i]), rtol=0.0, maxit=K)
+        assert io["iters"] == K
+        err = rel(x, xo)
+        say("system", i, "n", a.n, "rel err", err)
+        assert err <= 1e-9
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_alone_and_in_the_mix_bit_identical(torch, fp32, monkeypatch):
+    systems = mix()
+    seeds = list(range(len(systems)))
+    params = hemamg.amg_params_default(precond_fp32=fp32)
+    xs, infos = run(torch, systems, params, seeds)
+    # reversed order, and without graph replay
+    monkeypatch.setenv("HEMAMG_BATCH_GRAPHS", "0")
+    xr, ir = run(torch, systems[::-1], params, seeds[::-1])
+    monkeypatch.delenv("HEMAMG_BATCH_GRAPHS")
+    for i in (0, 3, 6, 8):
+        xa, ia = run(torch, [systems[i]], params, [seeds[i]])
+        assert ia[0]["iters"] == infos[i]["iters"] == ir[len(systems) - 1 - i]["iters"]
+        np.testing.assert_array_equal(bits(xa[0]), bits(xs[i]), err_msg=f"system {i}")
+        np.testing.assert_array_equal(bits(xr[len(systems) - 1 - i]), bits(xs[i]), err_msg=f"system {i} reversed")
+
+
+def test_batch_iterations_equal_the_single_solver(torch):
+    systems = mix()
+    params = hemamg.amg_params_default()
+    xs, infos = run(torch, systems, params, list(range(len(systems))))
+    for i, a in enumerate(systems):
+        with hemamg.Hierarchy(hemamg.DeviceCSR.from_host(a), params) as g:
+            x1, i1 = g.solve(torch.from_numpy(P.rhs_uniform(a.n, i)).cuda(), rtol=1e-8, maxit=500)
+        assert abs(i1["iters"] - infos[i]["iters"]) <= 1
+        assert rel(xs[i], x1.cpu().numpy()) <= 1e-8
+
+
+def test_initial_guess_zero_rhs_and_limits(torch):
+    systems = [P.lognormal_diffusion3d(10, 3, 1.0), P.poisson3d(9), P.lognormal_diffusion3d(13, 4, 1.0)]
+    params = hemamg.amg_params_default()
+    hs, bt, rhs = make_batch(torch, systems, params, [1, 2, 3])
+    try:
+        off = bt.offsets
+        rhs[off[1]:off[2]] = 0.0  # system 1: b = 0 -> x = 0
+        x0 = torch.ones_like(rhs)
+        x, infos = bt.solve(rhs, x0.clone(), rtol=1e-8, maxit=500)
+        assert [i["status"] for i in infos] == [hemamg.AMG_OK] * 3
+        assert infos[1]["iters"] == 0
+        xs = x.cpu().numpy()
+        assert np.all(xs[off[1]:off[2]] == 0.0)
+        for i in (0, 2):
+            a = systems[i]
+            b = rhs[off[i]:off[i + 1]].cpu().numpy()
+            assert np.linalg.norm(b - a.to_scipy() @ xs[off[i]:off[i + 1]]) <= 1e-8 * np.linalg.norm(b) * 1.000001
+        # iteration limit: every live system reports it, x keeps the last iterate
+        _, lim = bt.solve(rhs, x0.clone(), rtol=1e-14, maxit=3)
+        assert [i["status"] for i in lim] == [hemamg.AMG_ENOTCONV, hemamg.AMG_OK, hemamg.AMG_ENOTCONV]
+        assert lim[0]["iters"] == 3 and lim[2]["iters"] == 3
+        # non-finite input is refused
+        bad = rhs.clone()
+        bad[off[2]] = float("nan")
+        _, nf = bt.solve(bad, x0.clone())
+        assert all(i["status"] == hemamg.AMG_ENOTFINITE for i in nf)
+    finally:
+        bt.close()
+        for h in hs:
+            h.close()
+
+
+def test_batch_argument_checks(torch):
+    a = P.lognormal_diffusion3d(8, 1, 1.0)
+    with hemamg.Hierarchy(hemamg.DeviceCSR.from_host(a)) as g64, \
+            hemamg.Hierarchy(hemamg.DeviceCSR.from_host(a), precond_fp32=1) as g32, \
+            hemamg.Hierarchy(hemamg.DeviceCSR.from_host(P.poisson2d(5))) as tiny:
+        assert tiny.nlevels == 1
+        for hs in ([g64, g32], [g64, tiny], []):
+            with pytest.raises(hemamg.AmgError) as e:
+                hemamg.Batch(hs)
+            assert e.value.status == hemamg.AMG_EINVAL
+        with hemamg.Batch([g64]) as bt:
+            rhs = torch.ones(a.n, dtype=torch.float64, device="cuda")
+            st = hemamg.lib().amg_batch_solve(bt.b, hemamg.BICGSTAB, rhs.data_ptr(), rhs.data_ptr(), 1e-8, 10,
+                                              hemamg._stream_ptr(None), (hemamg.amg_info * 1)())
+            assert st == hemamg.AMG_EINVAL
+
+
+def test_batch_of_many_with_a_large_system(torch):
+    """A 64^3 system with 40 small ones: deep and shallow hierarchies side by
+    side, many reduction blocks, solved alone and in the batch."""
+    systems = [P.poisson3d(64)] + [P.lognormal_diffusion3d(6 + (i % 9), 50 + i, 1.0) for i in range(40)]
+    seeds = list(range(len(systems)))
+    params = hemamg.amg_params_default()
+    xs, infos = run(torch, systems, params, seeds)
+    assert all(i["status"] == hemamg.AMG_OK for i in infos)
+    xa, ia = run(torch, [systems[0]], params, [0])
+    assert ia[0]["iters"] == infos[0]["iters"]
+    np.testing.assert_array_equal(bits(xa[0]), bits(xs[0]))
+    for i in (1, 17, 40):
+        xo, io = oracle.Hierarchy(systems[i]).solve(P.rhs_uniform(systems[i].n, seeds[i]), rtol=1e-8, maxit=500)
+        assert abs(io["iters"] - infos[i]["iters"]) <= 1
