@@ -169,8 +169,8 @@ def serve_main(args):
     rows = sum(a.n for a, _ in reqs)
     log(f"{len(reqs)} requests, {rows} rows in total")
 
-    def run(workers, fp32, arrivals):
-        cfg = hemamg.amg_server_config_default(workers=workers)
+    def run(workers, fp32, arrivals, batch=0):
+        cfg = hemamg.amg_server_config_default(workers=workers, batch=batch)
         cfg.params.precond_fp32 = fp32
         srv = hemamg.amg_server_create(cfg)
         for _, _, x in dev:
@@ -205,15 +205,20 @@ def serve_main(args):
         arr = np.cumsum(gaps) / lam
         plain = run(1, 0, arr)
         served = run(args.workers, 1, arr)
-        out_rates[str(f)] = {"plain": plain, "served": served}
-        log(f"rate {f}: plain {plain}, served {served}")
+        batched = run(args.workers, 1, arr, args.batch)
+        out_rates[str(f)] = {"plain": plain, "served": served, "batched": batched}
+        log(f"rate {f}: plain {plain}, served {served}, batched {batched}")
     closed = run(args.workers, 1, None)
+    closed_b = run(args.workers, 1, None, args.batch)
+    log(f"closed loop: streams {closed}, batched {closed_b}")
+    best, form = (closed_b, "batched") if closed_b["solves_per_s"] >= closed["solves_per_s"] else (closed, "streams")
     print(json.dumps({
-        "metric": "served solves/s, p50/p99 latency", "value": closed["solves_per_s"], "unit": "solves/s",
+        "metric": "served solves/s, p50/p99 latency", "value": best["solves_per_s"], "unit": "solves/s",
         "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f32+f64",
         "config": {"workload": "served lognormal diffusion stream", "requests": len(dev), "rows": rows,
-                   "side": [16, 96], "sigma": 1.0, "rtol": 1e-8, "method": "pcg", "workers": args.workers},
-        "plain_capacity": cap, "served_closed_loop": closed, "rates": out_rates,
+                   "side": [16, 96], "sigma": 1.0, "rtol": 1e-8, "method": "pcg", "workers": args.workers,
+                   "batch": args.batch, "form": form},
+        "plain_capacity": cap, "served_closed_loop": closed, "batched_closed_loop": closed_b, "rates": out_rates,
     }), flush=True)
 
 
@@ -240,6 +245,7 @@ def main():
     ap.add_argument("--serve", action="store_true", help="served stream of solve requests instead of one system")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=32, help="batched serving: most requests per batched solve")
     ap.add_argument("--rates", type=lambda t: [float(v) for v in t.split(",")], default=[0.5, 0.8, 1.0])
     args = ap.parse_args()
     if args.gpus != 1:

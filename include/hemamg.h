@@ -176,7 +176,11 @@ typedef struct amg_server amg_server;
 
 typedef struct {
     int32_t workers;          /* concurrent requests, 1..64 (4)                 */
-    int32_t pad;
+    int32_t batch;            /* >= 2: workers only build hierarchies, and one
+                               * solver thread advances the ready PCG requests
+                               * (same rtol and maxit) together as batches of
+                               * at most this many (amg_batch_*); 0 or 1: each
+                               * worker solves its own requests (0)              */
     uint64_t hbm_budget_bytes; /* admission budget (64 GiB)                     */
     amg_params params;        /* hierarchy and cycle parameters of every request */
 } amg_server_config;

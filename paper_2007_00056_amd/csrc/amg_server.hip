@@ -5,6 +5,11 @@
 // different requests overlap on the device.  Requests are admitted in arrival
 // order while the footprints of the requests in flight fit the budget; a
 // request waits at the head of the queue until enough finish.
+//
+// Batched mode (batch >= 2): workers only build hierarchies and hand PCG
+// requests to a solver thread, which takes every ready request with the same
+// stop settings (up to `batch`) and advances them together with one batched
+// solve; requests set up while a batch runs form the next one.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -36,6 +41,7 @@ struct Request {
     bool done = false;
     amg_status st = AMG_OK;
     amg_info info{};
+    amg_hier* h = nullptr;  // batched mode: the hierarchy waiting for the solver thread
 };
 
 uint64_t footprint(int32_t n, int64_t nnz, const amg_params& p) {
@@ -58,6 +64,14 @@ uint64_t footprint(int32_t n, int64_t nnz, const amg_params& p) {
     return b;
 }
 
+// What a request adds inside a batch: its concatenated levels (level 0
+// included), vectors and Krylov workspace, and its slices of the batch's
+// right-hand side and solution.
+uint64_t batch_extra(int32_t n, int64_t nnz) {
+    const uint64_t N = (uint64_t)(n > 0 ? n : 0), Z = (uint64_t)(nnz > 0 ? nnz : 0);
+    return 24 * Z + 224 * N + 8ull * 1024 * 1024;
+}
+
 }  // namespace
 
 struct amg_server {
@@ -72,11 +86,43 @@ struct amg_server {
     int active = 0;
     bool stopping = false;
     std::vector<std::thread> threads;
+    // batched mode
+    std::deque<Request*> ready;  // hierarchies built, waiting for the solver thread
+    std::condition_variable cv_ready;
+    int building = 0;  // workers inside a setup
+    std::thread solver;
+    std::vector<hipStream_t> wstreams;
 
-    void worker() {
+    void release_streams() {
+        for (hipStream_t& st : wstreams)
+            if (st) {
+                (void)hipStreamSynchronize(st);
+                (void)hipStreamDestroy(st);
+                st = nullptr;
+            }
+    }
+
+    bool batched() const { return cfg.batch >= 2; }
+
+    void finish(Request* r) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            in_use -= r->foot;
+            --active;
+            r->done = true;
+            r->t_done = Clock::now();
+        }
+        cv_done.notify_all();
+        cv_work.notify_all();
+    }
+
+    // Worker i runs on wstreams[i].  The streams live until the server is
+    // destroyed: in batched mode a hierarchy built on a worker's stream is
+    // released by the solver thread, possibly after that worker has stopped.
+    void worker(int i) {
         if (hipSetDevice(device) != hipSuccess) return;
-        hipStream_t s = nullptr;
-        const bool have_stream = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+        hipStream_t s = wstreams[i];
+        const bool have_stream = s != nullptr;
         for (;;) {
             Request* r = nullptr;
             {
@@ -91,33 +137,128 @@ struct amg_server {
                 pending.pop_front();
                 in_use += r->foot;
                 ++active;
+                ++building;
             }
-            run(r, have_stream ? s : nullptr, have_stream);
+            const bool handed = run(r, have_stream ? s : nullptr, have_stream);
             {
                 std::lock_guard<std::mutex> lk(mu);
-                in_use -= r->foot;
-                --active;
-                r->done = true;
-                r->t_done = Clock::now();
+                --building;
+                if (handed) ready.push_back(r);
             }
-            cv_done.notify_all();
-            cv_work.notify_all();
+            cv_ready.notify_all();
+            if (!handed) finish(r);
         }
-        if (have_stream) (void)hipStreamDestroy(s);
     }
 
-    void run(Request* r, hipStream_t s, bool have_stream) {
+    // Setup, then either the whole solve here or (batched mode, PCG on a
+    // multilevel hierarchy) the hand-over to the solver thread (returns true).
+    bool run(Request* r, hipStream_t s, bool have_stream) {
         if (!have_stream) {
             r->st = AMG_EHIP;
             r->info.status = AMG_EHIP;
-            return;
+            return false;
         }
         amg_hier* h = nullptr;
         amg_status st = amg_setup(&r->A, &cfg.params, s, &h);
+        if (st == AMG_OK && batched() && r->method == 0) {
+            int32_t levels = 0;
+            if (amg_num_levels(h, &levels) == AMG_OK && levels >= 2) {
+                r->h = h;
+                return true;
+            }
+        }
         if (st == AMG_OK) st = krylov_solve(h, r->method, r->b, r->x, r->rtol, r->maxit, s, &r->info);
         else r->info.status = st;
         if (h) (void)amg_destroy(h);
         r->st = st;
+        return false;
+    }
+
+    // Batched mode: solves groups of ready requests together.
+    void solver_loop() {
+        if (hipSetDevice(device) != hipSuccess) return;
+        hipStream_t s = nullptr;
+        const bool have_stream = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+        double* buf = nullptr;  // right-hand sides, then solutions, of a batch
+        size_t cap = 0;
+        for (;;) {
+            std::vector<Request*> grp;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_ready.wait(lk, [&] { return !ready.empty() || (stopping && pending.empty() && building == 0); });
+                if (ready.empty()) break;
+                const Request* head = ready.front();
+                for (auto it = ready.begin(); it != ready.end() && (int)grp.size() < cfg.batch;) {
+                    if ((*it)->rtol == head->rtol && (*it)->maxit == head->maxit) {
+                        grp.push_back(*it);
+                        it = ready.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+            }
+            solve_group(grp, have_stream ? s : nullptr, buf, cap);
+            for (Request* r : grp) finish(r);
+        }
+        if (buf) (void)hipFree(buf);
+        if (have_stream) (void)hipStreamDestroy(s);
+    }
+
+    static void fail_group(std::vector<Request*>& grp, amg_status st) {
+        for (Request* r : grp) {
+            r->st = st;
+            r->info.status = st;
+        }
+    }
+
+    static void solve_group(std::vector<Request*>& grp, hipStream_t s, double*& buf, size_t& cap) {
+        const int n = (int)grp.size();
+        std::vector<const amg_hier*> hs(n);
+        for (int i = 0; i < n; ++i) hs[i] = grp[i]->h;
+        amg_batch* bt = nullptr;
+        const amg_status st = s ? amg_batch_create(hs.data(), n, s, &bt) : AMG_EHIP;
+        for (Request* r : grp) {  // the batch holds its own copy of every level
+            (void)amg_destroy(r->h);
+            r->h = nullptr;
+        }
+        if (st != AMG_OK) return fail_group(grp, st);
+        std::vector<int32_t> off(n + 1);
+        (void)amg_batch_rows(bt, off.data());
+        const size_t need = 2 * (size_t)off[n] * sizeof(double);
+        if (need > cap) {
+            if (buf) (void)hipFree(buf);
+            buf = nullptr;
+            cap = 0;
+            if (hipMalloc((void**)&buf, need + need / 2) != hipSuccess) {
+                (void)amg_batch_destroy(bt);
+                return fail_group(grp, AMG_ENOMEM);
+            }
+            cap = need + need / 2;
+        }
+        double* B = buf;
+        double* X = buf + off[n];
+        bool ok = true;
+        for (int i = 0; i < n; ++i) {
+            const size_t bytes = sizeof(double) * (size_t)(off[i + 1] - off[i]);
+            ok &= hipMemcpyAsync(B + off[i], grp[i]->b, bytes, hipMemcpyDeviceToDevice, s) == hipSuccess;
+            ok &= hipMemcpyAsync(X + off[i], grp[i]->x, bytes, hipMemcpyDeviceToDevice, s) == hipSuccess;
+        }
+        if (!ok) {
+            (void)amg_batch_destroy(bt);
+            return fail_group(grp, AMG_EHIP);
+        }
+        std::vector<amg_info> info(n);
+        (void)amg_batch_solve(bt, 0, B, X, grp[0]->rtol, grp[0]->maxit, s, info.data());
+        for (int i = 0; i < n; ++i) {
+            const size_t bytes = sizeof(double) * (size_t)(off[i + 1] - off[i]);
+            ok &= hipMemcpyAsync(grp[i]->x, X + off[i], bytes, hipMemcpyDeviceToDevice, s) == hipSuccess;
+        }
+        ok &= hipStreamSynchronize(s) == hipSuccess;
+        (void)amg_batch_destroy(bt);
+        for (int i = 0; i < n; ++i) {
+            grp[i]->info = info[i];
+            grp[i]->st = ok ? (amg_status)info[i].status : AMG_EHIP;
+        }
     }
 };
 
@@ -135,7 +276,7 @@ amg_status amg_footprint_bytes(int32_t n, int64_t nnz, const amg_params* params,
 amg_status amg_server_config_default(amg_server_config* c) {
     if (!c) return AMG_EINVAL;
     c->workers = 4;
-    c->pad = 0;
+    c->batch = 0;
     c->hbm_budget_bytes = 64ull << 30;
     return amg_params_default(&c->params);
 }
@@ -146,7 +287,8 @@ amg_status amg_server_create(const amg_server_config* c, amg_server** out) {
     amg_server_config cfg;
     if (c) cfg = *c;
     else amg_server_config_default(&cfg);
-    if (cfg.workers < 1 || cfg.workers > 64 || cfg.hbm_budget_bytes == 0) return AMG_EINVAL;
+    if (cfg.workers < 1 || cfg.workers > 64 || cfg.hbm_budget_bytes == 0 || cfg.batch < 0) return AMG_EINVAL;
+    if (cfg.batch >= 2 && (cfg.params.pre != 1 || cfg.params.post != 1)) return AMG_EINVAL;
     amg_server* s = new (std::nothrow) amg_server();
     if (!s) return AMG_ENOMEM;
     s->cfg = cfg;
@@ -155,14 +297,25 @@ amg_status amg_server_create(const amg_server_config* c, amg_server** out) {
         return AMG_EHIP;
     }
     try {
-        for (int i = 0; i < cfg.workers; ++i) s->threads.emplace_back([s] { s->worker(); });
+        s->wstreams.assign(cfg.workers, nullptr);
+        for (int i = 0; i < cfg.workers; ++i)
+            if (hipStreamCreateWithFlags(&s->wstreams[i], hipStreamNonBlocking) != hipSuccess) {
+                s->release_streams();
+                delete s;
+                return AMG_EHIP;
+            }
+        for (int i = 0; i < cfg.workers; ++i) s->threads.emplace_back([s, i] { s->worker(i); });
+        if (s->batched()) s->solver = std::thread([s] { s->solver_loop(); });
     } catch (...) {
         {
             std::lock_guard<std::mutex> lk(s->mu);
             s->stopping = true;
         }
         s->cv_work.notify_all();
+        s->cv_ready.notify_all();
         for (auto& t : s->threads) t.join();
+        if (s->solver.joinable()) s->solver.join();
+        s->release_streams();
         delete s;
         return AMG_ENOMEM;
     }
@@ -181,7 +334,7 @@ amg_status amg_server_submit(amg_server* s, const amg_csr* A, const double* b, d
     r->method = method;
     r->rtol = rtol;
     r->maxit = maxit;
-    r->foot = footprint(A->n, A->nnz, s->cfg.params);
+    r->foot = footprint(A->n, A->nnz, s->cfg.params) + (s->batched() ? batch_extra(A->n, A->nnz) : 0);
     if (r->foot > s->cfg.hbm_budget_bytes) {
         delete r;
         return AMG_EINVAL;
@@ -228,6 +381,9 @@ amg_status amg_server_destroy(amg_server* s) {
     }
     s->cv_work.notify_all();
     for (auto& t : s->threads) t.join();
+    s->cv_ready.notify_all();  // the workers are done: the solver drains the ready requests and stops
+    if (s->solver.joinable()) s->solver.join();
+    s->release_streams();
     for (auto& kv : s->reqs) delete kv.second;
     delete s;
     return AMG_OK;

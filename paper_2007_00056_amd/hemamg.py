@@ -48,7 +48,7 @@ class amg_info(C.Structure):
 
 
 class amg_server_config(C.Structure):
-    _fields_ = [("workers", C.c_int32), ("pad", C.c_int32), ("hbm_budget_bytes", C.c_uint64),
+    _fields_ = [("workers", C.c_int32), ("batch", C.c_int32), ("hbm_budget_bytes", C.c_uint64),
                 ("params", amg_params)]
 
 

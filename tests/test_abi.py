@@ -64,7 +64,7 @@ def test_footprint_and_server_defaults():
         pytest.fail("libhemamg.so is not built")
     # host-only calls
     c = hemamg.amg_server_config_default()
-    assert c.workers == 4 and c.hbm_budget_bytes == 64 << 30 and c.params.passes_per_level == 2
+    assert c.workers == 4 and c.batch == 0 and c.hbm_budget_bytes == 64 << 30 and c.params.passes_per_level == 2
     small = hemamg.amg_footprint_bytes(4096, 28000)
     big = hemamg.amg_footprint_bytes(884736, 6137856)
     assert 0 < small < big

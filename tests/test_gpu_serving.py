@@ -104,12 +104,13 @@ def test_admission_budget_serialises_but_completes(torch):
         hemamg.amg_server_destroy(srv)
 
 
-def test_failing_request_does_not_disturb_others(torch):
+@pytest.mark.parametrize("batch", [0, 4])
+def test_failing_request_does_not_disturb_others(torch, batch):
     good = P.lognormal_diffusion3d(14, 3, 1.0)
     bad = P.poisson3d(6)
     bad.val = bad.val.copy()
     bad.val[bad.row_ptr[5]:bad.row_ptr[6]][bad.col[bad.row_ptr[5]:bad.row_ptr[6]] == 5] = 0.0  # zero diagonal
-    srv = hemamg.amg_server_create(hemamg.amg_server_config_default(workers=2))
+    srv = hemamg.amg_server_create(hemamg.amg_server_config_default(workers=2, batch=batch))
     try:
         live = []
         for a in (good, bad, good):
@@ -140,13 +141,14 @@ def test_footprint_bounds_owned_memory(torch, fp32):
         assert owned <= foot
 
 
-def test_destroy_drains_queued_requests(torch):
+@pytest.mark.parametrize("batch", [0, 3])
+def test_destroy_drains_queued_requests(torch, batch):
     a = P.lognormal_diffusion3d(20, 9, 1.0)
     A = hemamg.DeviceCSR.from_host(a)
     b = torch.from_numpy(P.rhs_uniform(a.n, 2)).cuda()
     xs = [torch.zeros_like(b) for _ in range(6)]
     torch.cuda.synchronize()
-    srv = hemamg.amg_server_create(hemamg.amg_server_config_default(workers=2))
+    srv = hemamg.amg_server_create(hemamg.amg_server_config_default(workers=2, batch=batch))
     for x in xs:
         hemamg.amg_server_submit(srv, A, b, x, hemamg.PCG, 1e-8, 500)
     hemamg.amg_server_destroy(srv)  # returns after every queued request ran
@@ -154,3 +156,55 @@ def test_destroy_drains_queued_requests(torch):
     assert np.linalg.norm(ref) > 0
     for x in xs[1:]:
         np.testing.assert_array_equal(bits(x.cpu().numpy()), bits(ref))
+
+
+def batch_of_one(torch, a, seed, params, rtol):
+    with hemamg.Hierarchy(hemamg.DeviceCSR.from_host(a), params) as g, hemamg.Batch([g]) as bt:
+        b = torch.from_numpy(P.rhs_uniform(a.n, seed)).cuda()
+        x, info = bt.solve(b, rtol=rtol, maxit=500)
+    return x.cpu().numpy(), info[0]
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("workers,batch", [(1, 2), (4, 8), (3, 64)])
+def test_batched_serving_results_same_as_alone(torch, fp32, workers, batch):
+    """Batched mode: PCG requests are solved in batches of whatever is ready;
+    each result is bit-identical to the same system batched alone.  The
+    BiCGStab request is solved by its worker as in the plain mode."""
+    say("workers", workers, "batch", batch, "fp32", fp32)
+    rtol = 1e-8
+    cfg = hemamg.amg_server_config_default(workers=workers, batch=batch)
+    cfg.params.precond_fp32 = fp32
+    params = hemamg.amg_params_default(precond_fp32=fp32)
+    items = mix()
+    srv = hemamg.amg_server_create(cfg)
+    try:
+        live = []
+        for a, seed, method in items:
+            A = hemamg.DeviceCSR.from_host(a)
+            b = torch.from_numpy(P.rhs_uniform(a.n, seed)).cuda()
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t = hemamg.amg_server_submit(srv, A, b, x, hemamg.PCG if method == "pcg" else hemamg.BICGSTAB, rtol, 500)
+            live.append((t, A, b, x))
+        res = [hemamg.amg_server_wait(srv, t) for t, *_ in live]
+    finally:
+        hemamg.amg_server_destroy(srv)
+    for (a, seed, method), (t, A, b, x), r in zip(items, live, res):
+        assert r["status"] == hemamg.AMG_OK, r
+        if method == "pcg":
+            xa, ia = batch_of_one(torch, a, seed, params, rtol)
+        else:
+            xa, ia = alone(torch, a, seed, method, params, rtol)
+        assert r["iters"] == ia["iters"], (r, ia)
+        np.testing.assert_array_equal(bits(x.cpu().numpy()), bits(xa), err_msg=f"n={a.n}")
+
+
+def test_batched_server_config_checks(torch):
+    for kw in (dict(batch=-1), dict(batch=4)):
+        cfg = hemamg.amg_server_config_default(**kw)
+        if kw["batch"] == 4:
+            cfg.params.pre = 2  # batches need one pre- and one post-sweep
+        with pytest.raises(hemamg.AmgError) as e:
+            hemamg.amg_server_create(cfg)
+        assert e.value.status == hemamg.AMG_EINVAL
