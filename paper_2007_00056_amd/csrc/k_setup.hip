@@ -194,19 +194,57 @@ void launch_assign_ids(int n, const int* mate, const int* ids, int* agg, int* le
 // (I,J) sums b_ij over the members in ascending order and, within a member,
 // over its columns in ascending order, the first term initialising the sum.
 // The fixed order makes the values bit-identical on every run.  A thread owns
-// one coarse row and keeps its sorted (column, sum) list in registers; rows
-// with more than RAP_CAP distinct columns go to a slower in-place path.
+// one coarse row and keeps its sorted (column, sum) list in its own LDS
+// columns (a list this long indexed by position does not stay in registers);
+// rows with more than RAP_CAP distinct columns go to a slower in-place path.
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int RAP_CAP = 32;
 constexpr int RAP_BS = 128;
 constexpr int RAP_WIN = 8;
-}
+
+// Sorted (column, sum) list of one thread: entry t at key[t * RAP_BS] (the
+// threads of a block interleave, so a wave's accesses hit distinct banks).
+// The first value added for a column initialises its sum; later values are
+// added in call order.
+template <bool WITH_VAL>
+struct LdsAcc {
+    int* key;
+    double* val;
+    int len;
+
+    __device__ __forceinline__ int& k(int t) const { return key[t * RAP_BS]; }
+    __device__ __forceinline__ double& x(int t) const { return val[t * RAP_BS]; }
+
+    // false (list unchanged) when a new column does not fit
+    __device__ __forceinline__ bool add(int J, double v) {
+        int lo = 0, hi = len;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (k(mid) < J) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < len && k(lo) == J) {
+            if (WITH_VAL) x(lo) += v;
+            return true;
+        }
+        if (len == RAP_CAP) return false;
+        for (int t = len; t > lo; --t) {
+            k(t) = k(t - 1);
+            if (WITH_VAL) x(t) = x(t - 1);
+        }
+        k(lo) = J;
+        if (WITH_VAL) x(lo) = v;
+        ++len;
+        return true;
+    }
+};
+}  // namespace
 
 // Entries of a member row are taken in windows of RAP_WIN whose column and
 // aggregate loads are issued together, then added in entry order.
 template <bool WITH_VAL>
-__device__ __forceinline__ bool rap_row(SortedAcc<RAP_CAP>& acc, int e0, int e1, const int* __restrict__ ci,
+__device__ __forceinline__ bool rap_row(LdsAcc<WITH_VAL>& acc, int e0, int e1, const int* __restrict__ ci,
                                         const double* __restrict__ v, const int* __restrict__ agg) {
     for (int b = e0; b < e1; b += RAP_WIN) {
         int c[RAP_WIN], J[RAP_WIN];
@@ -220,7 +258,7 @@ __device__ __forceinline__ bool rap_row(SortedAcc<RAP_CAP>& acc, int e0, int e1,
         }
 #pragma unroll
         for (int t = 0; t < RAP_WIN; ++t)
-            if (J[t] >= 0 && !acc.template add<WITH_VAL>(J[t], x[t])) return false;
+            if (J[t] >= 0 && !acc.add(J[t], x[t])) return false;
     }
     return true;
 }
@@ -238,10 +276,10 @@ __global__ __launch_bounds__(RAP_BS) void k_rap_count(int nmax, const int* __res
         rowcnt[I] = 0;
         return;
     }
+    __shared__ int skey[RAP_CAP * RAP_BS];
     const int m0 = lead[I];
     const int m1 = mate[m0];
-    SortedAcc<RAP_CAP> acc;
-    acc.clear();
+    LdsAcc<false> acc{skey + threadIdx.x, nullptr, 0};
     bool ok = rap_row<false>(acc, rp[m0], rp[m0 + 1], ci, nullptr, agg);
     if (ok && m1 >= 0) ok = rap_row<false>(acc, rp[m1], rp[m1 + 1], ci, nullptr, agg);
     if (ok) {
@@ -259,19 +297,17 @@ __global__ __launch_bounds__(RAP_BS) void k_rap_fill(int nc, const int* __restri
                                                      int* __restrict__ cci, double* __restrict__ cv) {
     const int I = blockIdx.x * RAP_BS + threadIdx.x;
     if (I >= nc) return;
+    __shared__ int skey[RAP_CAP * RAP_BS];
+    __shared__ double sval[RAP_CAP * RAP_BS];
     const int m0 = lead[I];
     const int m1 = mate[m0];
-    SortedAcc<RAP_CAP> acc;
-    acc.clear();
+    LdsAcc<true> acc{skey + threadIdx.x, sval + threadIdx.x, 0};
     if (!rap_row<true>(acc, rp[m0], rp[m0 + 1], ci, v, agg)) return;  // overflow row: slow path
     if (m1 >= 0 && !rap_row<true>(acc, rp[m1], rp[m1 + 1], ci, v, agg)) return;
     const int o = crp[I];
-#pragma unroll
-    for (int t = 0; t < RAP_CAP; ++t) {
-        if (t < acc.len) {
-            cci[o + t] = acc.key[t];
-            cv[o + t] = acc.val[t];
-        }
+    for (int t = 0; t < acc.len; ++t) {
+        cci[o + t] = acc.k(t);
+        cv[o + t] = acc.x(t);
     }
 }
 
