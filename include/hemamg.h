@@ -160,6 +160,17 @@ amg_status amg_setup_stats(const amg_hier* h, int32_t* rounds, int32_t cap, int3
 amg_status amg_timing_enable(amg_hier* h, int32_t kernel, int32_t on);
 amg_status amg_timing_read(amg_hier* h, int32_t kernel, int64_t* launches, double* total_ms);
 
+/* Autotuner: chooses each level's V-cycle schedule by timing both steps of
+ * the level on this hierarchy (CSR-stream kernels with 128, 256 or 512 rows
+ * per block, or lane-group kernels with 2, 4 or 8 lanes per row) and keeps
+ * the fastest for later V-cycles and solves.  The schedules differ only in
+ * the order of a row's additions.  schedule: [host] int32[levels] or NULL;
+ * receives rows per block for CSR-stream levels, minus the lanes per row for
+ * lane-group levels, 0 for the coarsest (all 0 when pre/post are not 1, whose
+ * path has one schedule).  Overwrites the handle's work vectors; blocks the
+ * host.  Errors: AMG_EINVAL, AMG_EHIP. */
+amg_status amg_autotune(amg_hier* h, void* stream, int32_t* schedule);
+
 /* Message for the last failing call on this thread (never NULL). */
 const char* amg_last_error(void);
 
@@ -250,6 +261,16 @@ amg_status amg_batch_rows(const amg_batch* b, int32_t* offsets);
  * Errors: AMG_EINVAL, AMG_ENOTFINITE, AMG_ENOTCONV, AMG_EBREAKDOWN, AMG_EHIP. */
 amg_status amg_batch_solve(amg_batch* bt, int32_t method, const double* b, double* x, double rtol, int32_t maxit,
                            void* stream, amg_info* info);
+
+/* Number of concatenated levels of a batch (its deepest system's). */
+amg_status amg_batch_levels(const amg_batch* b, int32_t* levels);
+
+/* Autotuner for a batch: rows per block (128, 256 or 512) of each level's
+ * CSR-stream kernels, chosen by timing the level's steps on this batch.
+ * Results do not change (a row's sum is formed in entry order whatever the
+ * block size).  schedule: [host] int32[levels] or NULL (0 for the last
+ * level).  Blocks the host.  Errors: AMG_EINVAL, AMG_EHIP. */
+amg_status amg_batch_autotune(amg_batch* b, void* stream, int32_t* schedule);
 
 /* Frees the batch.  NULL is accepted. */
 amg_status amg_batch_destroy(amg_batch* b);

@@ -386,6 +386,9 @@ void timed_end(amg_hier* h, int cls, hipStream_t s, bool recorded = false) {
     }
 }
 
+// Whether level L runs the CSR-stream kernels (else the lane-group kernels).
+inline bool streamed(const amg_hier* h, const Level& L) { return L.sched < 0 ? L.n >= h->stream_min : L.sched == 0; }
+
 // Whether the level-0 postsmoothing can run as a separate step (part 2).
 bool vcycle_splits(const amg_hier* h) { return h->lev.size() > 1 && h->p.pre == 1 && h->p.post == 1; }
 
@@ -393,11 +396,11 @@ template <class T>
 VLevel<T> vlevel(const Level& L);
 template <>
 VLevel<double> vlevel<double>(const Level& L) {
-    return VLevel<double>{L.n, L.rp, L.ci, L.v, L.dinv, L.mem, L.lpr};
+    return VLevel<double>{L.n, L.rp, L.ci, L.v, L.dinv, L.mem, L.sched > 0 ? L.sched : L.lpr, L.rb};
 }
 template <>
 VLevel<float> vlevel<float>(const Level& L) {
-    return VLevel<float>{L.n, L.rp, L.ci, L.v32, L.dinv32, L.mem, L.lpr};
+    return VLevel<float>{L.n, L.rp, L.ci, L.v32, L.dinv32, L.mem, L.sched > 0 ? L.sched : L.lpr, L.rb};
 }
 template <class T>
 const T* dinv_of(const Level& L);
@@ -437,7 +440,7 @@ void run_vcycle_t(amg_hier* h, const double* r, double* z, hipStream_t s, const 
     };
     if (part == 2) {  // level-0 postsmoothing (+ (r, z)) only
         const VLevel<T> V = vlevel<T>(L0);
-        if (L0.n >= h->stream_min) {
+        if (streamed(h, L0)) {
             hipEvent_t t0, t1;
             timed_pair(h, 0, t0, t1);
             vc_stream_post<T, double>(V, vec(L0.xp), g0, w, z, r, dot_slot >= 0 ? &R : nullptr, dot_slot, nullptr, s,
@@ -459,7 +462,7 @@ void run_vcycle_t(amg_hier* h, const double* r, double* z, hipStream_t s, const 
         T* fc = vec(Lc.f);
         T* gc = vec(Lc.g);
         if (k == 0) timed_begin(h, 1, s);
-        if (Lk.n >= h->stream_min) {
+        if (streamed(h, Lk)) {
             if (k == 0) vc_stream_resid<T, double>(V, r, g0, w, vec(Lk.t), s);
             else vc_stream_resid<T, T>(V, vec(Lk.f), gk(k), w, vec(Lk.t), s);
             if (k == 0) timed_end(h, 1, s);
@@ -482,13 +485,13 @@ void run_vcycle_t(amg_hier* h, const double* r, double* z, hipStream_t s, const 
         const VLevel<T> V = vlevel<T>(Lk);
         if (k > 0) {
             const ScatterT<T> sc = scatter_to(k - 1);
-            if (Lk.n >= h->stream_min)
+            if (streamed(h, Lk))
                 vc_stream_post<T, T>(V, vec(Lk.xp), gk(k), w, vec(Lk.x), nullptr, nullptr, -1, &sc, s);
             else
                 vc_prolong_post<T, T>(V, vec(Lk.xp), gk(k), w, vec(Lk.x), &sc, s);
             continue;
         }
-        if (Lk.n >= h->stream_min) {
+        if (streamed(h, Lk)) {
             hipEvent_t t0, t1;
             timed_pair(h, 0, t0, t1);
             vc_stream_post<T, double>(V, vec(Lk.xp), g0, w, z, r, dot_slot >= 0 ? &R : nullptr, dot_slot, nullptr, s,
@@ -968,6 +971,8 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     h->prec32 = p.precond_fp32 != 0;
     const size_t esz = h->prec32 ? sizeof(float) : sizeof(double);
     if (const char* e = getenv("HEMAMG_STREAM_MIN")) h->stream_min = atoi(e);  // tuning sweeps
+    if (const char* e = getenv("HEMAMG_RB"))
+        for (Level& L : h->lev) L.rb = atoi(e);
     if (const char* e = getenv("HEMAMG_GRAPHS")) h->use_graphs = atoi(e) != 0;
     for (size_t k = 0; k < h->lev.size(); ++k) {
         Level& L = h->lev[k];
@@ -977,7 +982,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
             L.x = P.get<char>(esz * L.n);
         }
         if (fused && k + 1 < h->lev.size()) L.xp = P.get<char>(esz * L.n);
-        if (!fused || L.n >= h->stream_min) L.t = P.get<char>(esz * L.n);
+        if (k + 1 < h->lev.size()) L.t = P.get<char>(esz * L.n);  // any level may be tuned to CSR-stream
         if (h->prec32) {
             L.v32 = P.get<float>((size_t)L.nnz);
             L.dinv32 = P.get<float>(L.n);
@@ -993,6 +998,109 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     h->S_host = static_cast<double*>(pinned_get());
     HIPCHK(hipStreamSynchronize(s));
     *out = h.release();
+}
+
+
+// ---------------------------------------------------------------------------
+// Autotuner: each level's V-cycle schedule is chosen by timing it on this
+// hierarchy (both steps of the level, several repetitions after a warm-up):
+// CSR-stream kernels with 128, 256 or 512 rows per block, or lane-group
+// kernels with 2, 4 or 8 lanes per row.  The schedules differ only in the
+// order of a row's additions.
+// ---------------------------------------------------------------------------
+template <class T>
+void tune_level_steps(amg_hier* h, int k, hipStream_t s) {
+    const T w = T(h->p.omega);
+    auto vec = [](void* p) { return static_cast<T*>(p); };
+    Level& Lk = h->lev[k];
+    const Level& Lc = h->lev[k + 1];
+    const VLevel<T> V = vlevel<T>(Lk);
+    const T* g = k == 0 ? vec(h->g0) : vec(Lk.g);
+    T* fk = k == 0 ? nullptr : vec(Lk.f);
+    if (streamed(h, Lk)) {
+        if (k == 0) vc_stream_resid<T, double>(V, h->r, g, w, vec(Lk.t), s);
+        else vc_stream_resid<T, T>(V, fk, g, w, vec(Lk.t), s);
+        vc_restrict<T>(Lc.n, Lk.mem, vec(Lk.t), dinv_of<T>(Lc), vec(Lc.f), vec(Lc.g), s);
+    } else {
+        if (k == 0) vc_resid_restrict<T, double>(V, Lc.n, h->r, g, w, dinv_of<T>(Lc), vec(Lc.f), vec(Lc.g), s);
+        else vc_resid_restrict<T, T>(V, Lc.n, fk, g, w, dinv_of<T>(Lc), vec(Lc.f), vec(Lc.g), s);
+    }
+    if (k == 0) {
+        if (streamed(h, Lk))
+            vc_stream_post<T, double>(V, vec(Lk.xp), g, w, h->z, nullptr, nullptr, -1, nullptr, s);
+        else
+            vc_prolong_post<T, double>(V, vec(Lk.xp), g, w, h->z, nullptr, s);
+        return;
+    }
+    const Level& Lf = h->lev[k - 1];
+    const ScatterT<T> sc{Lf.mem, k - 1 == 0 ? vec(h->g0) : vec(Lf.g), vec(Lf.xp), w};
+    if (streamed(h, Lk))
+        vc_stream_post<T, T>(V, vec(Lk.xp), g, w, vec(Lk.x), nullptr, nullptr, -1, &sc, s);
+    else
+        vc_prolong_post<T, T>(V, vec(Lk.xp), g, w, vec(Lk.x), &sc, s);
+}
+
+void autotune_impl(amg_hier* h, hipStream_t s, int32_t* out) {
+    const int nl = (int)h->lev.size();
+    if (out)
+        for (int k = 0; k < nl; ++k) out[k] = 0;
+    if (nl < 2 || !(h->p.pre == 1 && h->p.post == 1)) return;  // the general path has one schedule
+    h->stream = s;
+    h->pool.s = s;
+    alloc_workspace(h);
+    const size_t esz = h->prec32 ? 4 : 8;
+    // finite contents for every vector the level steps touch
+    HIPCHK(hipMemsetAsync(h->r, 0, sizeof(double) * h->lev[0].n, s));
+    HIPCHK(hipMemsetAsync(h->z, 0, sizeof(double) * h->lev[0].n, s));
+    HIPCHK(hipMemsetAsync(h->g0, 0, esz * h->lev[0].n, s));
+    for (int k = 0; k < nl; ++k) {
+        Level& L = h->lev[k];
+        for (void* p : {L.f, L.g, L.x, L.xp, L.t})
+            if (p) HIPCHK(hipMemsetAsync(p, 0, esz * L.n, s));
+    }
+    hipEvent_t e0 = event_get(true), e1 = event_get(true);
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            event_put(a, true);
+            event_put(b, true);
+        }
+    } eg{e0, e1};
+    struct Cand {
+        int sched, rb;
+    };
+    const Cand cands[] = {{0, 128}, {0, 256}, {0, 512}, {2, 256}, {4, 256}, {8, 256}};
+    const int reps = 5;
+    for (int k = 0; k + 1 < nl; ++k) {
+        Level& Lk = h->lev[k];
+        float best = 1e30f;
+        Cand pick{-1, 256};
+        for (const Cand& c : cands) {
+            Lk.sched = c.sched;
+            Lk.rb = c.rb;
+            auto step = [&] {
+                if (h->prec32) tune_level_steps<float>(h, k, s);
+                else tune_level_steps<double>(h, k, s);
+            };
+            step();  // warm-up
+            HIPCHK(hipEventRecord(e0, s));
+            for (int r = 0; r < reps; ++r) step();
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                pick = c;
+            }
+        }
+        Lk.sched = pick.sched;
+        Lk.rb = pick.rb;
+        if (out) out[k] = pick.sched == 0 ? pick.rb : -pick.sched;
+    }
+    h->drop_graphs();
+    HIPCHK(hipStreamSynchronize(s));
 }
 
 }  // namespace
@@ -1138,6 +1246,13 @@ amg_status amg_timing_enable(amg_hier* h, int32_t kernel, int32_t on) {
     return guarded([&] {
         if (!h || kernel < 0 || kernel > 2) raise(AMG_EINVAL, "amg_timing_enable: bad argument");
         h->tim[kernel].on = on != 0;
+    });
+}
+
+amg_status amg_autotune(amg_hier* h, void* stream, int32_t* schedule) {
+    return guarded([&] {
+        if (!h) raise(AMG_EINVAL, "amg_autotune: NULL handle");
+        autotune_impl(h, as_stream(stream), schedule);
     });
 }
 

@@ -48,6 +48,7 @@ struct BLev {
     void* x = nullptr;    // [V] (k >= 1)
     void* xp = nullptr;   // [n]
     void* t = nullptr;    // [n]
+    int rb = 256;         // rows per block of the level's CSR-stream kernels
 };
 
 struct BSeg {
@@ -163,7 +164,7 @@ void batch_vcycle(const amg_batch* B, const double* r, double* z, hipStream_t s)
     auto gk = [&](int k) { return k == 0 ? g0 : static_cast<const T*>(B->lev[k].g); };
     auto view = [&](int k) {
         const BLev& L = B->lev[k];
-        return VLevel<T>{L.n, L.rp, L.ci, vals<T>(L), dinvs<T>(L), L.mem, 4};
+        return VLevel<T>{L.n, L.rp, L.ci, vals<T>(L), dinvs<T>(L), L.mem, 4, L.rb};
     };
     for (int k = 0; k + 1 < K; ++k) {
         const BLev& L = B->lev[k];
@@ -179,6 +180,28 @@ void batch_vcycle(const amg_batch* B, const double* r, double* z, hipStream_t s)
         vc_stream_post<T, T>(view(k), vec(L.xp), gk(k), w, vec(L.x), nullptr, nullptr, -1, &sc, s);
     }
     vc_stream_post<T, double>(view(0), vec(B->lev[0].xp), g0, w, z, nullptr, nullptr, -1, nullptr, s);
+}
+
+// Level k's two steps of the batched V-cycle (for the autotuner).
+template <class T>
+void batch_level_steps(const amg_batch* B, int k, hipStream_t s) {
+    const T w = T(B->omega);
+    auto vec = [](void* p) { return static_cast<T*>(p); };
+    const BLev& L = B->lev[k];
+    const BLev& C = B->lev[k + 1];
+    const VLevel<T> V{L.n, L.rp, L.ci, vals<T>(L), dinvs<T>(L), L.mem, 4, L.rb};
+    const T* g = k == 0 ? static_cast<const T*>(B->g0) : static_cast<const T*>(L.g);
+    if (k == 0) vc_stream_resid<T, double>(V, B->r, g, w, vec(L.t), s);
+    else vc_stream_resid<T, T>(V, vec(L.f), g, w, vec(L.t), s);
+    vc_restrict<T>(C.V, L.mem, vec(L.t), dinvs<T>(C), vec(C.f), vec(C.g), s);
+    if (k == 0) {
+        vc_stream_post<T, double>(V, vec(L.xp), g, w, B->z, nullptr, nullptr, -1, nullptr, s);
+        return;
+    }
+    const BLev& F = B->lev[k - 1];
+    const ScatterT<T> sc{F.mem, k - 1 == 0 ? static_cast<const T*>(B->g0) : static_cast<const T*>(F.g),
+                         vec(F.xp), w};
+    vc_stream_post<T, T>(V, vec(L.xp), g, w, vec(L.x), nullptr, nullptr, -1, &sc, s);
 }
 
 void vcycle(const amg_batch* B, const double* r, double* z, hipStream_t s) {
@@ -566,6 +589,67 @@ void create_impl(const amg_hier* const* hs, int count, hipStream_t caller, amg_b
     *out = B.release();
 }
 
+// Rows per block of every level's CSR-stream kernels, chosen by timing the
+// level's steps on this batch.  A row's sum is formed in entry order whatever
+// the block size, so results do not change.
+void batch_autotune(amg_batch* B, hipStream_t caller, int32_t* out) {
+    hipStream_t s = B->stream;
+    HIPCHK(hipEventRecord(B->ev[0], caller));
+    HIPCHK(hipStreamWaitEvent(s, B->ev[0], 0));
+    const size_t esz = B->prec32 ? 4 : 8;
+    const int K = (int)B->lev.size();
+    HIPCHK(hipMemsetAsync(B->r, 0, sizeof(double) * B->n0, s));
+    HIPCHK(hipMemsetAsync(B->z, 0, sizeof(double) * B->n0, s));
+    HIPCHK(hipMemsetAsync(B->g0, 0, esz * B->n0, s));
+    for (BLev& L : B->lev) {
+        for (void* p : {L.f, L.g, L.x}) if (p) HIPCHK(hipMemsetAsync(p, 0, esz * L.V, s));
+        for (void* p : {L.xp, L.t}) if (p) HIPCHK(hipMemsetAsync(p, 0, esz * L.n, s));
+    }
+    hipEvent_t e0 = event_get(true), e1 = event_get(true);
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            event_put(a, true);
+            event_put(b, true);
+        }
+    } eg{e0, e1};
+    const int cand[] = {128, 256, 512};
+    for (int k = 0; k < K; ++k) {
+        if (out) out[k] = 0;
+        if (k + 1 >= K) continue;
+        BLev& L = B->lev[k];
+        float best = 1e30f;
+        int pick = 256;
+        for (int rb : cand) {
+            L.rb = rb;
+            auto step = [&] {
+                if (B->prec32) batch_level_steps<float>(B, k, s);
+                else batch_level_steps<double>(B, k, s);
+            };
+            step();
+            HIPCHK(hipEventRecord(e0, s));
+            for (int r = 0; r < 5; ++r) step();
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                pick = rb;
+            }
+        }
+        L.rb = pick;
+        if (out) out[k] = pick;
+    }
+    for (hipGraphExec_t& g : B->graph)  // re-captured with the new launch shapes
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    HIPCHK(hipStreamSynchronize(s));
+}
+
 }  // namespace
 
 extern "C" {
@@ -621,6 +705,20 @@ amg_status amg_batch_solve(amg_batch* B, int32_t method, const double* b, double
         for (int i = 0; i < B->nseg; ++i) info[i].solve_ms = ms;
     }
     return st;
+}
+
+amg_status amg_batch_autotune(amg_batch* b, void* stream, int32_t* schedule) {
+    return guarded([&] {
+        if (!b) raise(AMG_EINVAL, "amg_batch_autotune: NULL batch");
+        batch_autotune(b, as_stream(stream), schedule);
+    });
+}
+
+amg_status amg_batch_levels(const amg_batch* b, int32_t* levels) {
+    return guarded([&] {
+        if (!b || !levels) raise(AMG_EINVAL, "amg_batch_levels: NULL argument");
+        *levels = (int32_t)b->lev.size();
+    });
 }
 
 amg_status amg_batch_destroy(amg_batch* b) {

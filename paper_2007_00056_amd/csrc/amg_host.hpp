@@ -146,6 +146,12 @@ struct Level {
     void* xp = nullptr;   // prolongated iterate w D^{-1} f + P e (k < coarsest)
     void* t = nullptr;    // residual scratch (CSR-stream levels) / general smoothing path
     int lpr = 4;
+    // V-cycle schedule of this level: sched < 0 follows the size rule
+    // (CSR-stream kernels from amg_hier::stream_min rows up), 0 forces the
+    // CSR-stream kernels, > 0 the lane-group kernels with that many lanes per
+    // row; rb = rows per block of the CSR-stream kernels.
+    int sched = -1;
+    int rb = 256;
 
     LevelView view() const {
         LevelView w;

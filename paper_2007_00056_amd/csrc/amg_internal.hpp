@@ -148,6 +148,7 @@ struct VLevel {
     const T* dinv;
     const int4* mem;  // members of level k+1 rows
     int lpr;
+    int rb = 256;     // rows per block of the CSR-stream kernels: 128, 256 or 512
 };
 
 // ---- V-cycle kernels (k_vcycle.hip), T = double or float -------------------

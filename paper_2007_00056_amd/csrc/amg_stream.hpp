@@ -1,6 +1,6 @@
 // CSR-stream building block shared by the level and Krylov kernels.
 //
-// A 256-thread block owns 256 consecutive rows.  It reads their contiguous
+// A block of RB threads (256 by default) owns RB consecutive rows.  It reads their contiguous
 // entry range with coalesced, independent loads (values, columns and the
 // gathered vector), stages the products in LDS, and then each thread adds
 // its own row's products in entry order.  Entries are processed in LDS chunks,
@@ -22,9 +22,11 @@ struct EntAx {  // a_ij x_j
     __device__ __forceinline__ T operator()(int e) const { return v[e] * x[ci[e]]; }
 };
 
-template <class T, class Ent>
+// RB rows per block (the block has RB threads); a row's sum does not depend
+// on RB.
+template <class T, int RB = kStreamBS, class Ent>
 __device__ __forceinline__ T stream_rows(int r0, int n, const int* __restrict__ rp, const Ent& ent, T* prod) {
-    constexpr int BS = kStreamBS;
+    constexpr int BS = RB;
     const int r1 = min(r0 + BS, n);
     const int e0 = rp[r0], e1 = rp[r1];
     const int row = r0 + threadIdx.x;

@@ -40,7 +40,7 @@ int pick_lanes_per_row(double avg) {
         if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16) return v;
     }
     if (avg <= 2.0) return 2;
-    return 4;
+    return avg <= 10.0 ? 4 : 8;  // coarse levels of variable coefficients carry 15-30 entries per row
 }
 
 #define AMG_DISPATCH_LPR(lpr, CALL) \

@@ -49,13 +49,13 @@ __device__ __forceinline__ T row_ax(int row, int lane, const int* __restrict__ r
 // Large levels (CSR-stream)
 // ---------------------------------------------------------------------------
 // r = f - w A g : residual after the zero-guess presmoothing sweep
-template <class T, class TIN>
-__global__ __launch_bounds__(BS) void k_vc_resid(int n, const int* __restrict__ rp, EntAx<T> ent,
+template <class T, class TIN, int RB>
+__global__ __launch_bounds__(RB) void k_vc_resid(int n, const int* __restrict__ rp, EntAx<T> ent,
                                                  const TIN* __restrict__ f, T w, T* __restrict__ r) {
     __shared__ T prod[kStreamChunk];
-    for (int b = xcd_block(blockIdx.x, gridDim.x); b * BS < n; b += gridDim.x) {
-        const T s = stream_rows<T>(b * BS, n, rp, ent, prod);
-        const int row = b * BS + threadIdx.x;
+    for (int b = xcd_block(blockIdx.x, gridDim.x); b * RB < n; b += gridDim.x) {
+        const T s = stream_rows<T, RB>(b * RB, n, rp, ent, prod);
+        const int row = b * RB + threadIdx.x;
         if (row < n) r[row] = T(f[row]) - w * s;
     }
 }
@@ -78,16 +78,16 @@ __global__ __launch_bounds__(BS) void k_vc_restrict(int nc, const int4* __restri
 
 // z = xp + w (g - D^{-1} A xp).  MODE 1 also forms block partials of (f, z)
 // in double; MODE 2 scatters z to the finer level's prolongated iterate.
-template <class T, class TOUT, int MODE>
-__global__ __launch_bounds__(BS) void k_vc_post(int n, const int* __restrict__ rp, EntAx<T> ent,
+template <class T, class TOUT, int MODE, int RB>
+__global__ __launch_bounds__(RB) void k_vc_post(int n, const int* __restrict__ rp, EntAx<T> ent,
                                                 const T* __restrict__ g, const T* __restrict__ dinv, T w,
                                                 TOUT* __restrict__ z, const double* __restrict__ f, double* part,
                                                 ScatterT<T> sc) {
     __shared__ T prod[kStreamChunk];
     double acc[1] = {0.0};
-    for (int b = xcd_block(blockIdx.x, gridDim.x); b * BS < n; b += gridDim.x) {
-        const T s = stream_rows<T>(b * BS, n, rp, ent, prod);
-        const int row = b * BS + threadIdx.x;
+    for (int b = xcd_block(blockIdx.x, gridDim.x); b * RB < n; b += gridDim.x) {
+        const T s = stream_rows<T, RB>(b * RB, n, rp, ent, prod);
+        const int row = b * RB + threadIdx.x;
         if (row < n) {
             const T zi = ent.x[row] + w * (g[row] - dinv[row] * s);
             z[row] = TOUT(zi);
@@ -95,13 +95,29 @@ __global__ __launch_bounds__(BS) void k_vc_post(int n, const int* __restrict__ r
             if (MODE == 2) sc(row, zi);
         }
     }
-    if (MODE == 1) block_partials<1, BS>(acc, part);
+    if (MODE == 1) block_partials<1, RB>(acc, part);
+}
+
+// The launchers pick the rows-per-block instantiation from the level.
+#define AMG_DISPATCH_RB(rb, CALL) \
+    switch (rb) {                 \
+        case 128: CALL(128); break; \
+        case 512: CALL(512); break; \
+        default: CALL(256); break;  \
+    }
+
+inline int rb_blocks(int n, int rb) {
+    const int b = (n + rb - 1) / rb;
+    return b < kRedBlocks ? (b < 1 ? 1 : b) : kRedBlocks;
 }
 
 template <class T, class TIN>
 void vc_stream_resid(const VLevel<T>& L, const TIN* f, const T* g, T w, T* r, hipStream_t s) {
-    hipLaunchKernelGGL((k_vc_resid<T, TIN>), dim3(stream_blocks(L.n, kRedBlocks)), dim3(BS), 0, s, L.n, L.rp,
-                       EntAx<T>{L.v, L.ci, g}, f, w, r);
+#define CALL(RB)                                                                                                \
+    hipLaunchKernelGGL((k_vc_resid<T, TIN, RB>), dim3(rb_blocks(L.n, RB)), dim3(RB), 0, s, L.n, L.rp,           \
+                       EntAx<T>{L.v, L.ci, g}, f, w, r)
+    AMG_DISPATCH_RB(L.rb, CALL)
+#undef CALL
 }
 
 template <class T>
@@ -112,15 +128,24 @@ void vc_restrict(int nc, const int4* mem, const T* r, const T* dinv_c, T* fc, T*
 template <class T, class TOUT>
 void vc_stream_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, const double* f, const Reducer* R,
                     int slot, const ScatterT<T>* sc, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-    const int gsz = stream_blocks(L.n, kRedBlocks);
+    const int rb = L.rb == 128 || L.rb == 512 ? L.rb : 256;
+    const int gsz = rb_blocks(L.n, rb);
     const EntAx<T> ent{L.v, L.ci, xp};
     const ScatterT<T> none{nullptr, nullptr, nullptr, T(0)};
     // with t0/t1 the dispatch itself records the kernel's start and end
-#define POST_LAUNCH(MODE, ...)                                                                                     \
+#define POST_RB(MODE, RB, ...)                                                                                     \
     if (t0)                                                                                                        \
-        hipExtLaunchKernelGGL((k_vc_post<T, TOUT, MODE>), dim3(gsz), dim3(BS), 0, s, t0, t1, 0, __VA_ARGS__);      \
+        hipExtLaunchKernelGGL((k_vc_post<T, TOUT, MODE, RB>), dim3(gsz), dim3(RB), 0, s, t0, t1, 0, __VA_ARGS__);  \
     else                                                                                                           \
-        hipLaunchKernelGGL((k_vc_post<T, TOUT, MODE>), dim3(gsz), dim3(BS), 0, s, __VA_ARGS__)
+        hipLaunchKernelGGL((k_vc_post<T, TOUT, MODE, RB>), dim3(gsz), dim3(RB), 0, s, __VA_ARGS__)
+#define POST_LAUNCH(MODE, ...)                      \
+    if (rb == 128) {                                \
+        POST_RB(MODE, 128, __VA_ARGS__);            \
+    } else if (rb == 512) {                         \
+        POST_RB(MODE, 512, __VA_ARGS__);            \
+    } else {                                        \
+        POST_RB(MODE, 256, __VA_ARGS__);            \
+    }
     if (R) {
         POST_LAUNCH(1, L.n, L.rp, ent, g, L.dinv, w, z, f, R->part, none);
         launch_finish(gsz, 1, *R, slot, slot, s);
@@ -130,6 +155,7 @@ void vc_stream_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, c
         POST_LAUNCH(0, L.n, L.rp, ent, g, L.dinv, w, z, (const double*)nullptr, (double*)nullptr, none);
     }
 #undef POST_LAUNCH
+#undef POST_RB
 }
 
 // ---------------------------------------------------------------------------

@@ -26,7 +26,7 @@ EXPORTED = ["amg_params_default", "amg_setup", "amg_destroy", "amg_vcycle", "kry
             "amg_level_size", "amg_export_level", "amg_setup_stats", "amg_timing_enable", "amg_timing_read",
             "amg_last_error", "amg_footprint_bytes", "amg_server_config_default", "amg_server_create",
             "amg_server_submit", "amg_server_wait", "amg_server_destroy", "amg_batch_create", "amg_batch_rows",
-            "amg_batch_solve", "amg_batch_destroy"]
+            "amg_batch_solve", "amg_batch_destroy", "amg_batch_levels", "amg_batch_autotune", "amg_autotune"]
 
 
 class amg_csr(C.Structure):
@@ -91,6 +91,9 @@ def lib():
             "amg_batch_rows": [vp, vp],
             "amg_batch_solve": [vp, i32, vp, vp, f64, i32, vp, vp],
             "amg_batch_destroy": [vp],
+            "amg_batch_levels": [vp, C.POINTER(i32)],
+            "amg_batch_autotune": [vp, vp, vp],
+            "amg_autotune": [vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -281,6 +284,25 @@ def amg_batch_solve(b: int, method: int, rhs, x, rtol: float, maxit: int, count:
                  solve_ms=i.solve_ms) for i in infos]
 
 
+def amg_autotune(h: int, stream=None) -> list:
+    """Tunes the hierarchy's V-cycle schedule in place; returns it per level."""
+    out = np.zeros(amg_num_levels(h), np.int32)
+    _check(lib().amg_autotune(h, _stream_ptr(stream), out.ctypes.data))
+    return out.tolist()
+
+
+def amg_batch_levels(b: int) -> int:
+    n = C.c_int32()
+    _check(lib().amg_batch_levels(b, C.byref(n)))
+    return n.value
+
+
+def amg_batch_autotune(b: int, stream=None) -> list:
+    out = np.zeros(amg_batch_levels(b), np.int32)
+    _check(lib().amg_batch_autotune(b, _stream_ptr(stream), out.ctypes.data))
+    return out.tolist()
+
+
 def amg_batch_destroy(b: int) -> None:
     _check(lib().amg_batch_destroy(b))
 
@@ -336,6 +358,9 @@ class Hierarchy:
     def stats(self):
         return amg_setup_stats(self.h)
 
+    def autotune(self, stream=None) -> list:
+        return amg_autotune(self.h, stream)
+
 
 class Batch:
     """Owns an amg_batch_create handle built from hierarchies."""
@@ -365,3 +390,6 @@ class Batch:
 
         x = torch.zeros_like(rhs) if x is None else x
         return x, amg_batch_solve(self.b, PCG, rhs, x, rtol, maxit, self.count, stream)
+
+    def autotune(self, stream=None) -> list:
+        return amg_batch_autotune(self.b, stream)

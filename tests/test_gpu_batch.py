@@ -188,3 +188,26 @@ def test_batch_of_many_with_a_large_system(torch):
     for i in (1, 17, 40):
         xo, io = oracle.Hierarchy(systems[i]).solve(P.rhs_uniform(systems[i].n, seeds[i]), rtol=1e-8, maxit=500)
         assert abs(io["iters"] - infos[i]["iters"]) <= 1
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_batch_autotune_keeps_every_bit(torch, fp32):
+    """Tuning the rows per block of the concatenated levels changes launch
+    shapes only: results before and after are bit-identical."""
+    systems = mix()
+    seeds = list(range(len(systems)))
+    params = hemamg.amg_params_default(precond_fp32=fp32)
+    hs, bt, rhs = make_batch(torch, systems, params, seeds)
+    try:
+        x0, i0 = bt.solve(rhs, rtol=1e-8, maxit=500)
+        sched = bt.autotune()
+        say("batch schedule", sched)
+        assert len(sched) == hemamg.amg_batch_levels(bt.b)
+        assert all(v in (128, 256, 512) for v in sched[:-1]) and sched[-1] == 0
+        x1, i1 = bt.solve(rhs, rtol=1e-8, maxit=500)
+        assert [a["iters"] for a in i0] == [a["iters"] for a in i1]
+        np.testing.assert_array_equal(bits(x0.cpu().numpy()), bits(x1.cpu().numpy()))
+    finally:
+        bt.close()
+        for h in hs:
+            h.close()

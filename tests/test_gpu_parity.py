@@ -165,6 +165,45 @@ def test_solve_matches_oracle(torch, name):
     solve_parity(torch, CASES[name](), method, 1e-8)
 
 
+@pytest.mark.parametrize("name", ["poisson2d_64", "lognormal3d_11", "vardiff3d_20", "convdiff3d_13"])
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_autotuned_schedule_keeps_parity(torch, name, fp32):
+    """The autotuner picks a schedule per level by timing; any pick is the
+    same V-cycle up to the order of a row's additions."""
+    a = CASES[name]()
+    method = "bicgstab" if name in NONSYM else "pcg"
+    A = hemamg.DeviceCSR.from_host(a)
+    g = hemamg.Hierarchy(A, hemamg.amg_params_default(precond_fp32=fp32))
+    sched = g.autotune()
+    say("case", name, "fp32", fp32, "schedule", sched)
+    assert len(sched) == g.nlevels and sched[-1] == 0
+    assert all(v in (128, 256, 512, -2, -4, -8) for v in sched[:-1])
+    o = oracle.Hierarchy(a)
+    b = P.rhs_uniform(a.n, 3)
+    xo, io = o.solve(b, method=method, rtol=1e-8, maxit=500)
+    xg, ig = g.solve(dev(torch, b), method=method, rtol=1e-8, maxit=500)
+    xg2, ig2 = g.solve(dev(torch, b), method=method, rtol=1e-8, maxit=500)
+    np.testing.assert_array_equal(xg.cpu().numpy(), xg2.cpu().numpy())  # deterministic once tuned
+    if fp32:
+        assert abs(ig["iters"] - io["iters"]) <= max(2, int(0.05 * io["iters"]))
+    else:
+        assert abs(ig["iters"] - io["iters"]) <= 1
+        xg3, _ = g.solve(dev(torch, b), method=method, rtol=0.0, maxit=io["iters"], check=False)
+        assert rel(xg3.cpu().numpy(), xo) <= 1e-9
+    g.close()
+
+
+def test_autotune_at_128(torch):
+    a = P.poisson3d(128)
+    A = hemamg.DeviceCSR.from_host(a)
+    with hemamg.Hierarchy(A) as g:
+        sched = g.autotune()
+        say("schedule", sched)
+        b = dev(torch, P.rhs_uniform(a.n, 0))
+        x, info = g.solve(b, rtol=1e-10, maxit=200)
+        assert info["iters"] <= 54 and info["true_rel_res"] <= 1e-10
+
+
 @pytest.mark.parametrize("name", ["poisson2d_64", "poisson3d_17x13x11", "lognormal3d_11", "vardiff3d_20",
                                   "convdiff3d_13"])
 def test_stationary_solver_matches_oracle(torch, name):
