@@ -950,9 +950,10 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     {
         DevPool tmp;
         tmp.s = s;
-        tmp.hint(8 * (size_t)m * m + 4 * (size_t)m + 4096);
+        tmp.hint(8 * (size_t)m * m + 8 * (size_t)m + 4096);
         double* a = tmp.get<double>((size_t)m * m);
-        int* piv = tmp.get<int>(m);
+        int* piv = tmp.get<int>(2 * (size_t)m);  // permutation and pivot rows
+        if (m > 1024) raise(AMG_EHIP, "coarsest level of %d rows exceeds the dense limit (internal error)", m);
         h->ainv_t = P.get<double>((size_t)m * m);
         HIPCHK(hipMemsetAsync(a, 0, sizeof(double) * (size_t)m * m, s));
         launch_dense_assemble(m, Lc.rp, Lc.ci, Lc.v, a, s);

@@ -101,6 +101,7 @@ void launch_members(int nc, const int* lead2, const int* mate2, const int* lead1
 
 // a must be zeroed before the call.
 void launch_dense_assemble(int n, const int* rp, const int* ci, const double* v, double* a, hipStream_t s);
+// piv: int32[2n] scratch.  n <= 1024.
 void launch_dense_lu_inverse(int n, double* a, int* piv, double* ainv_t, int* err, hipStream_t s);
 
 // ---- solve kernels (k_solve.hip) --------------------------------------------

@@ -580,24 +580,41 @@ __device__ __forceinline__ void lu_argmax(double& v, int& i, double* sv, int* si
 }
 }  // namespace
 
-// Right-looking LU with partial pivoting in place (row-major a, unit lower L
-// below the diagonal).  perm[i] = original row of position i (P A = L U).
-// One workgroup; the pivot row and the multipliers of each step sit in LDS.
-__global__ __launch_bounds__(LU_BS) void k_dense_lu(int n, double* __restrict__ a, int* __restrict__ perm, int* err) {
-    __shared__ double rowk[1024], colk[1024];
-    __shared__ int sperm[1024];
+// Blocked right-looking LU with partial pivoting in place (row-major a, unit
+// lower L below the diagonal; P A = L U with perm[i] = original row of
+// position i).  Panels of LU_NB columns: k_lu_panel factors the panel's rows
+// k0.. in LDS (pivot = largest |value|, lowest row on ties), then k_lu_rest
+// applies the panel's interchanges to every other column and, right of the
+// panel, forms U12 = L11^{-1} A12 and A22 -= L21 U12.  Each entry receives its
+// updates in the order of the unblocked algorithm.  n <= 1024.
+constexpr int LU_NB = 16;
+constexpr int LU_LDP = LU_NB + 1;  // padded LDS row of the panel
+constexpr int LU_COLS = 64;        // columns per block of k_lu_rest
+
+__global__ __launch_bounds__(LU_BS) void k_lu_panel(int n, int k0, double* __restrict__ a, int* __restrict__ perm,
+                                                    int* __restrict__ piv, int* err) {
+    __shared__ double P[1024 * LU_LDP];
     __shared__ double sv[LU_BS / kWave];
     __shared__ int si[LU_BS / kWave];
+    if (*err & ERR_SINGULAR) return;  // an earlier panel failed (uniform)
     const int tid = threadIdx.x;
-    for (int i = tid; i < n; i += LU_BS) sperm[i] = i;
-    for (int k = 0; k < n; ++k) {
+    const int kb = min(LU_NB, n - k0), m = n - k0;
+    if (k0 == 0)
+        for (int i = tid; i < n; i += LU_BS) perm[i] = i;
+    if (tid < kb) piv[k0 + tid] = k0 + tid;  // valid even if this panel fails
+    for (int t = tid; t < m * LU_NB; t += LU_BS) {
+        const int r = t / LU_NB, c = t % LU_NB;
+        P[r * LU_LDP + c] = c < kb ? a[(size_t)(k0 + r) * n + k0 + c] : 0.0;
+    }
+    __syncthreads();
+    for (int c = 0; c < kb; ++c) {
         double best = -1.0;
-        int bi = n;
-        for (int i = k + tid; i < n; i += LU_BS) {
-            const double t = fabs(a[(size_t)i * n + k]);
-            if (t > best) {  // rows ascend per thread: strict '>' keeps the lowest
-                best = t;
-                bi = i;
+        int bi = m;
+        for (int r = c + tid; r < m; r += LU_BS) {
+            const double v = fabs(P[r * LU_LDP + c]);
+            if (v > best) {  // rows ascend per thread: strict '>' keeps the lowest
+                best = v;
+                bi = r;
             }
         }
         lu_argmax(best, bi, sv, si);
@@ -605,82 +622,150 @@ __global__ __launch_bounds__(LU_BS) void k_dense_lu(int n, double* __restrict__ 
             if (tid == 0) atomicOr(err, ERR_SINGULAR);
             return;
         }
-        const int p = bi;
-        // row swap (all columns), recorded in the permutation
-        if (p != k)
-            for (int j = tid; j < n; j += LU_BS) {
-                const double t = a[(size_t)k * n + j];
-                a[(size_t)k * n + j] = a[(size_t)p * n + j];
-                a[(size_t)p * n + j] = t;
-            }
-        if (tid == 0 && p != k) {
-            const int t = sperm[k];
-            sperm[k] = sperm[p];
-            sperm[p] = t;
+        if (bi != c && tid < LU_NB) {
+            const double t = P[c * LU_LDP + tid];
+            P[c * LU_LDP + tid] = P[bi * LU_LDP + tid];
+            P[bi * LU_LDP + tid] = t;
         }
+        if (tid == 0) piv[k0 + c] = k0 + bi;
         __syncthreads();
-        const double d = a[(size_t)k * n + k];
-        for (int j = k + 1 + tid; j < n; j += LU_BS) rowk[j] = a[(size_t)k * n + j];
-        for (int i = k + 1 + tid; i < n; i += LU_BS) {
-            const double l = a[(size_t)i * n + k] / d;
-            colk[i] = l;
-            a[(size_t)i * n + k] = l;
-        }
-        __syncthreads();
-        const int m = n - k - 1;
-        for (int t = tid; t < m * m; t += LU_BS) {
-            const int i = k + 1 + t / m, j = k + 1 + t % m;
-            a[(size_t)i * n + j] -= colk[i] * rowk[j];
+        const double d = P[c * LU_LDP + c];
+        for (int r = c + 1 + tid; r < m; r += LU_BS) {
+            const double l = P[r * LU_LDP + c] / d;
+            P[r * LU_LDP + c] = l;
+            for (int j = c + 1; j < kb; ++j) P[r * LU_LDP + j] -= l * P[c * LU_LDP + j];
         }
         __syncthreads();
     }
-    for (int i = tid; i < n; i += LU_BS) perm[i] = sperm[i];
+    for (int t = tid; t < m * LU_NB; t += LU_BS) {
+        const int r = t / LU_NB, c = t % LU_NB;
+        if (c < kb) a[(size_t)(k0 + r) * n + k0 + c] = P[r * LU_LDP + c];
+    }
+    if (tid == 0)
+        for (int c = 0; c < kb; ++c) {
+            const int p = piv[k0 + c];
+            if (p != k0 + c) {
+                const int t = perm[k0 + c];
+                perm[k0 + c] = perm[p];
+                perm[p] = t;
+            }
+        }
+}
+
+// A block owns LU_COLS columns; 4 groups of 64 threads share its rows.
+__global__ __launch_bounds__(256) void k_lu_rest(int n, int k0, double* __restrict__ a, const int* __restrict__ piv,
+                                                 const int* err) {
+    __shared__ double L11[LU_NB][LU_NB];
+    __shared__ double U[LU_NB][LU_COLS];
+    if (*err & ERR_SINGULAR) return;  // uniform
+    const int kb = min(LU_NB, n - k0);
+    const int cl = threadIdx.x % LU_COLS, rg = threadIdx.x / LU_COLS;
+    const int j = blockIdx.x * LU_COLS + cl;
+    const bool mine = j < n && (j < k0 || j >= k0 + kb);
+    const bool right = mine && j >= k0 + kb;
+    for (int t = threadIdx.x; t < kb * kb; t += 256) L11[t / kb][t % kb] = a[(size_t)(k0 + t / kb) * n + k0 + t % kb];
+    if (rg == 0 && mine)
+        for (int c = 0; c < kb; ++c) {
+            const int p = piv[k0 + c];
+            if (p > k0 + c && p < n) {
+                const double t = a[(size_t)(k0 + c) * n + j];
+                a[(size_t)(k0 + c) * n + j] = a[(size_t)p * n + j];
+                a[(size_t)p * n + j] = t;
+            }
+        }
+    __syncthreads();
+    if (rg == 0 && right)
+        for (int i = 0; i < kb; ++i) {
+            double u = a[(size_t)(k0 + i) * n + j];
+            for (int q = 0; q < i; ++q) u -= L11[i][q] * U[q][cl];
+            U[i][cl] = u;
+            a[(size_t)(k0 + i) * n + j] = u;
+        }
+    __syncthreads();
+    if (right)
+        for (int r = k0 + kb + rg; r < n; r += 4) {
+            const double* l = a + (size_t)r * n + k0;
+            double s = a[(size_t)r * n + j];
+            for (int q = 0; q < kb; ++q) s -= l[q] * U[q][cl];
+            a[(size_t)r * n + j] = s;
+        }
 }
 
 // Columns of A^{-1} = U^{-1} L^{-1} P, INV_COLS per block, held in LDS as
-// x[i * INV_COLS + c] (at most 64 KiB).  Each row of a substitution is a dot
-// product split over INV_SLICES lanes (fixed order) and reduced with
-// shuffles.  Writes the inverse column-major: ainv_t[c * n + i] = (A^{-1})_{ic}.
+// x[i * INV_COLS + c].  Both substitutions go by blocks of 16 rows: the
+// block's rows first subtract the contributions of the rows already solved
+// (one dot per row and column, all threads), then lane c of the first wave
+// finishes column c through the 16x16 diagonal block kept in LDS.  Writes
+// the inverse column-major: ainv_t[c * n + i] = (A^{-1})_{ic}.
 template <int INV_COLS>
 __global__ __launch_bounds__(INV_BS) void k_dense_inverse(int n, const double* __restrict__ lu,
                                                           const int* __restrict__ perm, double* __restrict__ ainv_t) {
-    constexpr int INV_SLICES = INV_BS / INV_COLS;
-    extern __shared__ double x[];
+    constexpr int RB = 16;
+    __shared__ double x[8192];  // n * INV_COLS <= 8192
+    __shared__ double D[RB][RB + 1];
     const int c0 = blockIdx.x * INV_COLS;
-    const int c = threadIdx.x / INV_SLICES, sl = threadIdx.x % INV_SLICES;
-    for (int t = threadIdx.x; t < n * INV_COLS; t += INV_BS) {
+    const int tid = threadIdx.x;
+    for (int t = tid; t < n * INV_COLS; t += INV_BS) {
         const int i = t / INV_COLS, cc = t % INV_COLS;
         x[t] = perm[i] == c0 + cc ? 1.0 : 0.0;
     }
     __syncthreads();
-    for (int i = 1; i < n; ++i) {  // unit lower
-        double s = 0.0;
-        for (int k = sl; k < i; k += INV_SLICES) s += lu[(size_t)i * n + k] * x[k * INV_COLS + c];
-        for (int off = INV_SLICES / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (sl == 0) x[i * INV_COLS + c] -= s;
+    const int oi = tid / INV_COLS, oc = tid % INV_COLS;  // (row in block, column) of this thread's output
+    for (int b0 = 0; b0 < n; b0 += RB) {  // unit lower
+        const int bs = min(RB, n - b0);
+        if (oi < bs) {
+            const double* l = lu + (size_t)(b0 + oi) * n;
+            double s = 0.0;
+            for (int k = 0; k < b0; ++k) s += l[k] * x[k * INV_COLS + oc];
+            x[(b0 + oi) * INV_COLS + oc] -= s;
+        }
+        for (int t = tid; t < bs * bs; t += INV_BS) D[t / bs][t % bs] = lu[(size_t)(b0 + t / bs) * n + b0 + t % bs];
+        __syncthreads();
+        if (tid < INV_COLS)
+            for (int i = 1; i < bs; ++i) {
+                double s = 0.0;
+                for (int k = 0; k < i; ++k) s += D[i][k] * x[(b0 + k) * INV_COLS + tid];
+                x[(b0 + i) * INV_COLS + tid] -= s;
+            }
         __syncthreads();
     }
-    for (int i = n - 1; i >= 0; --i) {  // upper
-        double s = 0.0;
-        for (int k = i + 1 + sl; k < n; k += INV_SLICES) s += lu[(size_t)i * n + k] * x[k * INV_COLS + c];
-        for (int off = INV_SLICES / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if (sl == 0) x[i * INV_COLS + c] = (x[i * INV_COLS + c] - s) / lu[(size_t)i * n + i];
+    for (int b0 = ((n - 1) / RB) * RB; b0 >= 0; b0 -= RB) {  // upper
+        const int bs = min(RB, n - b0);
+        if (oi < bs) {
+            const double* u = lu + (size_t)(b0 + oi) * n;
+            double s = 0.0;
+            for (int k = b0 + bs; k < n; ++k) s += u[k] * x[k * INV_COLS + oc];
+            x[(b0 + oi) * INV_COLS + oc] -= s;
+        }
+        for (int t = tid; t < bs * bs; t += INV_BS) D[t / bs][t % bs] = lu[(size_t)(b0 + t / bs) * n + b0 + t % bs];
+        __syncthreads();
+        if (tid < INV_COLS)
+            for (int i = bs - 1; i >= 0; --i) {
+                double s = 0.0;
+                for (int k = i + 1; k < bs; ++k) s += D[i][k] * x[(b0 + k) * INV_COLS + tid];
+                x[(b0 + i) * INV_COLS + tid] = (x[(b0 + i) * INV_COLS + tid] - s) / D[i][i];
+            }
         __syncthreads();
     }
-    for (int t = threadIdx.x; t < n * INV_COLS; t += INV_BS) {
+    for (int t = tid; t < n * INV_COLS; t += INV_BS) {
         const int cc = t / n, i = t % n;
         if (c0 + cc < n) ainv_t[(size_t)(c0 + cc) * n + i] = x[i * INV_COLS + cc];
     }
 }
 
-void launch_dense_lu_inverse(int n, double* a, int* perm, double* ainv_t, int* err, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_lu, dim3(1), dim3(LU_BS), 0, s, n, a, perm, err);
+// piv: int32[2n] scratch (permutation, then the panels' pivot rows).
+void launch_dense_lu_inverse(int n, double* a, int* piv, double* ainv_t, int* err, hipStream_t s) {
+    int* perm = piv;
+    int* steps = piv + n;
+    for (int k0 = 0; k0 < n; k0 += LU_NB) {
+        hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(LU_BS), 0, s, n, k0, a, perm, steps, err);
+        hipLaunchKernelGGL(k_lu_rest, dim3((n + LU_COLS - 1) / LU_COLS), dim3(256), 0, s, n, k0, a, steps,
+                           (const int*)err);
+    }
     if (n <= 512)
-        hipLaunchKernelGGL(k_dense_inverse<16>, dim3((n + 15) / 16), dim3(INV_BS), sizeof(double) * (size_t)n * 16, s,
-                           n, a, perm, ainv_t);
+        hipLaunchKernelGGL(k_dense_inverse<16>, dim3((n + 15) / 16), dim3(INV_BS), 0, s, n, a, perm, ainv_t);
     else
-        hipLaunchKernelGGL(k_dense_inverse<8>, dim3((n + 7) / 8), dim3(INV_BS), sizeof(double) * (size_t)n * 8, s, n,
-                           a, perm, ainv_t);
+        hipLaunchKernelGGL(k_dense_inverse<8>, dim3((n + 7) / 8), dim3(INV_BS), 0, s, n, a, perm, ainv_t);
 }
 
 }  // namespace amg
