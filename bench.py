@@ -244,9 +244,9 @@ def main():
                     help="after timing, copy 256 MiB device-to-device (counter calibration for profiles)")
     ap.add_argument("--serve", action="store_true", help="served stream of solve requests instead of one system")
     ap.add_argument("--requests", type=int, default=256)
-    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--batch", type=int, default=32, help="batched serving: most requests per batched solve")
-    ap.add_argument("--rates", type=lambda t: [float(v) for v in t.split(",")], default=[0.5, 0.8, 1.0])
+    ap.add_argument("--rates", type=lambda t: [float(v) for v in t.split(",")], default=[0.5, 1.0, 2.0])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is single-GPU and "
