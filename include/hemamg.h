@@ -187,11 +187,12 @@ typedef struct amg_server amg_server;
 
 typedef struct {
     int32_t workers;          /* concurrent requests, 1..64 (4)                 */
-    int32_t batch;            /* >= 2: workers only build hierarchies, and one
-                               * solver thread advances the ready PCG requests
-                               * (same rtol and maxit) together as batches of
-                               * at most this many (amg_batch_*); 0 or 1: each
-                               * worker solves its own requests (0)              */
+    int32_t batch;            /* >= 2: a worker takes up to this many queued PCG
+                               * requests with equal rtol and maxit that fit the
+                               * budget, builds their hierarchies together
+                               * (amg_batch_setup) and solves them together
+                               * (amg_batch_solve); 0 or 1: one request per
+                               * worker (0)                                      */
     uint64_t hbm_budget_bytes; /* admission budget (64 GiB)                     */
     amg_params params;        /* hierarchy and cycle parameters of every request */
 } amg_server_config;
@@ -247,6 +248,22 @@ typedef struct amg_batch amg_batch;
  * omega and true_res_period.  Blocks the host until the copies are done.
  * Errors: AMG_EINVAL, AMG_ENOMEM, AMG_EHIP. */
 amg_status amg_batch_create(const amg_hier* const* hiers, int32_t count, void* stream, amg_batch** out);
+
+/* Batched setup (the setup phase of Section 3 for many systems at once): the
+ * systems' levels are built together on block-diagonal concatenations of
+ * their operators, so every matching round, Galerkin product and level
+ * kernel covers all of them, while each system's stop rules apply to it
+ * alone.  Every system gets exactly the hierarchy amg_setup would build, and
+ * a solve of the returned batch gives bit for bit what amg_batch_create on
+ * the separate hierarchies gives.  A: [host] amg_csr[count] (arrays on the
+ * device, borrowed only during the call); params shared by all (pre = post
+ * = 1).  status: [host] amg_status[count] or NULL; a system that fails
+ * (invalid matrix, stall, singular coarsest level, or a single level) gets
+ * its status there, takes no rows in the batch and reports the status from
+ * amg_batch_solve.  A matrix that is not structurally symmetric fails the
+ * whole call.  Blocks the host.  Errors: AMG_EINVAL, AMG_ENOMEM, AMG_EHIP. */
+amg_status amg_batch_setup(const amg_csr* A, int32_t count, const amg_params* params, void* stream,
+                           amg_batch** out, amg_status* status);
 
 /* offsets: [host] int32[count + 1]; system i occupies rows
  * offsets[i] .. offsets[i+1]-1 of the batch vectors. */

@@ -131,6 +131,23 @@ void raise_err_word(int e, const char* where) {
 
 void check_err_word(const int* err, hipStream_t s, const char* where) { raise_err_word(read_int(err, s), where); }
 
+void validate_params(const amg_params& p) {
+    if (p.passes_per_level < 1 || p.passes_per_level > 2) raise(AMG_EINVAL, "passes_per_level must be 1 or 2");
+    if (p.max_coarse_rows < 1 || p.max_coarse_rows > 1024) raise(AMG_EINVAL, "max_coarse_rows must be in 1..1024");
+    if (p.max_dense_rows < 1 || p.max_dense_rows > 1024) raise(AMG_EINVAL, "max_dense_rows must be in 1..1024");
+    if (p.max_levels < 1 || p.max_levels > 64) raise(AMG_EINVAL, "max_levels must be in 1..64");
+    if (p.pre < 0 || p.pre > 8 || p.post < 0 || p.post > 8) raise(AMG_EINVAL, "pre/post sweeps must be in 0..8");
+    if (!std::isfinite(p.omega)) raise(AMG_EINVAL, "omega must be finite");
+    if (p.true_res_period < 0) raise(AMG_EINVAL, "true_res_period must be >= 0");
+    if (p.precond_fp32 != 0 && p.precond_fp32 != 1) raise(AMG_EINVAL, "precond_fp32 must be 0 or 1");
+    if (!(p.stall_ratio > 0.0 && p.stall_ratio <= 1.0)) raise(AMG_EINVAL, "stall_ratio must be in (0, 1]");
+    if (p.hem != 0 && p.hem != 1) raise(AMG_EINVAL, "hem must be 0 (node-based) or 1 (edge-based)");
+    if (p.alternate != 0 && p.alternate != 1) raise(AMG_EINVAL, "alternate must be 0 or 1");
+    if (p.alternate && p.hem != 0) raise(AMG_EINVAL, "alternate applies to node-based matching (hem = 0)");
+    if (p.precond_fp32 && !(p.pre == 1 && p.post == 1))
+        raise(AMG_EINVAL, "a float preconditioner needs one pre- and one post-sweep");
+}
+
 }  // namespace amg
 
 namespace {
@@ -827,20 +844,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     amg_params p;
     amg_params_default(&p);
     if (pin) p = *pin;
-    if (p.passes_per_level < 1 || p.passes_per_level > 2) raise(AMG_EINVAL, "passes_per_level must be 1 or 2");
-    if (p.max_coarse_rows < 1 || p.max_coarse_rows > 1024) raise(AMG_EINVAL, "max_coarse_rows must be in 1..1024");
-    if (p.max_dense_rows < 1 || p.max_dense_rows > 1024) raise(AMG_EINVAL, "max_dense_rows must be in 1..1024");
-    if (p.max_levels < 1 || p.max_levels > 64) raise(AMG_EINVAL, "max_levels must be in 1..64");
-    if (p.pre < 0 || p.pre > 8 || p.post < 0 || p.post > 8) raise(AMG_EINVAL, "pre/post sweeps must be in 0..8");
-    if (!std::isfinite(p.omega)) raise(AMG_EINVAL, "omega must be finite");
-    if (p.true_res_period < 0) raise(AMG_EINVAL, "true_res_period must be >= 0");
-    if (p.precond_fp32 != 0 && p.precond_fp32 != 1) raise(AMG_EINVAL, "precond_fp32 must be 0 or 1");
-    if (!(p.stall_ratio > 0.0 && p.stall_ratio <= 1.0)) raise(AMG_EINVAL, "stall_ratio must be in (0, 1]");
-    if (p.hem != 0 && p.hem != 1) raise(AMG_EINVAL, "hem must be 0 (node-based) or 1 (edge-based)");
-    if (p.alternate != 0 && p.alternate != 1) raise(AMG_EINVAL, "alternate must be 0 or 1");
-    if (p.alternate && p.hem != 0) raise(AMG_EINVAL, "alternate applies to node-based matching (hem = 0)");
-    if (p.precond_fp32 && !(p.pre == 1 && p.post == 1))
-        raise(AMG_EINVAL, "a float preconditioner needs one pre- and one post-sweep");
+    validate_params(p);
     const amg_csr& A = *Ain;
     if (A.n <= 0) raise(AMG_EINVAL, "n must be positive");
     if (A.nnz < A.n || A.nnz >= (int64_t(1) << 31)) raise(AMG_EINVAL, "nnz must be in [n, 2^31)");
@@ -1105,6 +1109,267 @@ void autotune_impl(amg_hier* h, hipStream_t s, int32_t* out) {
 }
 
 }  // namespace
+
+namespace amg {
+
+// Batched setup (see amg_host.hpp).  Level 0 is the inputs concatenated with
+// column offsets; a block-diagonal operator couples no two systems, so each
+// matching pass and Galerkin product acts on every system exactly as on the
+// system alone, and the coarse ids of a system stay contiguous (numbering by
+// smallest fine index).  After each level the coarse size of every system is
+// read back and the single-system stop rules decide, per system, whether it
+// goes on; systems that stop are dropped from the next level's operator.
+void batch_coarsen(const amg_csr* A, int count, const amg_params& p, hipStream_t s, DevPool& P,
+                   std::vector<SegSrc>& out) {
+    validate_params(p);
+    if (!A || count < 1) raise(AMG_EINVAL, "amg_batch_setup: no systems");
+    out.assign(count, SegSrc{});
+    int* err = P.get<int>((size_t)count + 1);  // per-system words, then the shared one
+    HIPCHK(hipMemsetAsync(err, 0, sizeof(int) * ((size_t)count + 1), s));
+    int* gerr = err + count;
+    // level 0: validate each system on its own (a column outside a system must
+    // not become a coupling to its neighbour), writing D^{-1} in place
+    int64_t N = 0, E = 0;
+    std::vector<int> off(count, 0);
+    std::vector<int64_t> eoff(count, 0);
+    for (int i = 0; i < count; ++i) {
+        const amg_csr& a = A[i];
+        if (a.n <= 0 || a.nnz < a.n || a.nnz >= (int64_t(1) << 31) || !a.row_ptr || !a.col_idx || !a.val) {
+            out[i].status = AMG_EINVAL;
+            continue;
+        }
+        off[i] = (int)N;
+        eoff[i] = E;
+        N += a.n;
+        E += a.nnz;
+    }
+    if (N >= (int64_t(1) << 31) || E >= (int64_t(1) << 31))
+        raise(AMG_EINVAL, "amg_batch_setup: the systems exceed 2^31 rows or entries together");
+    if (N == 0) raise(AMG_EINVAL, "amg_batch_setup: no valid system");
+    Csr M{(int)N, E, P.get<int>((size_t)N + 1), P.get<int>((size_t)E), P.get<double>((size_t)E)};
+    double* dinv = P.get<double>((size_t)N);
+    for (int i = 0; i < count; ++i)
+        if (out[i].status == AMG_OK)
+            launch_validate(A[i].n, A[i].nnz, A[i].row_ptr, A[i].col_idx, A[i].val, dinv + off[i], err + i, s);
+    HIPCHK(hipGetLastError());
+    {
+        std::vector<int> e(count);
+        HIPCHK(hipMemcpyAsync(e.data(), err, sizeof(int) * count, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int i = 0; i < count; ++i) {
+            if (out[i].status != AMG_OK) continue;
+            try {
+                raise_err_word(e[i], "amg_batch_setup");
+            } catch (const Failure& f) {
+                out[i].status = f.st;
+            }
+        }
+    }
+    // concatenate the valid systems
+    std::vector<GatherPiece> pcs;
+    int last = -1;
+    N = 0;
+    E = 0;
+    for (int i = 0; i < count; ++i) {
+        if (out[i].status != AMG_OK) continue;
+        off[i] = (int)N;  // rows of failed systems are left out
+        eoff[i] = E;
+        N += A[i].n;
+        E += A[i].nnz;
+        last = i;
+    }
+    if (last < 0) raise(AMG_EINVAL, "amg_batch_setup: no valid system");
+    M.n = (int)N;
+    M.nnz = E;
+    {
+        // D^{-1} of the valid systems moves with them
+        double* d2 = P.get<double>((size_t)N);
+        int64_t src = 0;
+        for (int i = 0; i < count; ++i) {
+            const int n = A[i].n > 0 ? A[i].n : 0;
+            if (out[i].status == AMG_OK) {
+                pcs.push_back(GatherPiece{A[i].row_ptr, M.rp + off[i], n + (i == last ? 1 : 0), (int)eoff[i], 0});
+                pcs.push_back(GatherPiece{A[i].col_idx, M.ci + eoff[i], A[i].nnz, off[i], 0});
+                pcs.push_back(GatherPiece{A[i].val, M.v + eoff[i], A[i].nnz, 0, 1});
+                pcs.push_back(GatherPiece{dinv + src, d2 + off[i], n, 0, 1});
+            }
+            if (A[i].n > 0 && A[i].nnz >= A[i].n && A[i].nnz < (int64_t(1) << 31) && A[i].row_ptr && A[i].col_idx &&
+                A[i].val)
+                src += n;  // validated systems were written at their first-pass offsets
+        }
+        gather_run(pcs, P, s);
+        dinv = d2;
+    }
+    // the systems present in the current level, in order
+    struct Live {
+        int seg, off, n;
+        int64_t eoff, nnz;
+    };
+    std::vector<Live> live;
+    for (int i = 0; i < count; ++i)
+        if (out[i].status == AMG_OK) live.push_back(Live{i, off[i], A[i].n, eoff[i], A[i].nnz});
+    auto level_src = [&](const Live& L, const Csr& C, const double* dv) {
+        SegLevelSrc t;
+        t.n = L.n;
+        t.nnz = L.nnz;
+        t.rp = C.rp + L.off;
+        t.rp_add = -(int)L.eoff;
+        t.ci = C.ci + L.eoff;
+        t.ci_add = -L.off;
+        t.v = C.v + L.eoff;
+        t.dinv = dv + L.off;
+        return t;
+    };
+    for (const Live& L : live) out[L.seg].lev.push_back(level_src(L, M, dinv));
+    // coarsest blocks, factored at the end: (system, level operator, its rows)
+    struct Coarsest {
+        int seg;
+        Csr C;
+        Live L;
+    };
+    std::vector<Coarsest> fin;
+    DevPool wpool;
+    wpool.s = s;
+    wpool.hint((size_t)E * (p.hem == 1 ? 9 : 1) + 168 * (size_t)N + 4096 +
+               (p.alternate ? 12 * (size_t)E + 4 * (size_t)N : 0));
+    struct WpoolGuard {
+        DevPool& t;
+        ~WpoolGuard() { t.release(); }
+    } wg{wpool};
+    SetupWork SW;
+    SW.init((int)N, E, wpool, gerr, p.hem == 1, p.alternate == 1);
+    int* starts = P.get<int>(2 * (size_t)count);
+    int* offs_d = P.get<int>((size_t)count);
+    std::vector<int> hs(2 * (size_t)count + 2), ho((size_t)count);
+    for (int k = 0; !live.empty(); ++k) {
+        std::vector<char> want(live.size(), 0);
+        bool any = false;
+        for (size_t j = 0; j < live.size(); ++j) {
+            const Live& L = live[j];
+            if (L.n <= p.max_coarse_rows) continue;
+            if (k + 1 >= p.max_levels) {
+                if (L.n > p.max_dense_rows) out[L.seg].status = AMG_ESTALL;
+                continue;
+            }
+            want[j] = 1;
+            any = true;
+        }
+        if (!any) {
+            for (const Live& L : live)
+                if (out[L.seg].status == AMG_OK) fin.push_back(Coarsest{L.seg, M, L});
+            break;
+        }
+        const int g0 = k * p.passes_per_level;
+        Pass p1 = hem_pass(M, SW, 0, s, gerr, p.alternate && (g0 & 1));
+        Csr C1 = galerkin(M, p1, SW, P, s, gerr);
+        Csr Cf = C1;
+        int* agg = P.get<int>((size_t)M.n);
+        int4* mem = nullptr;
+        if (p.passes_per_level == 2) {
+            Pass p2 = hem_pass(C1, SW, 1, s, gerr, p.alternate && ((g0 + 1) & 1));
+            Cf = galerkin(C1, p2, SW, P, s, gerr);
+            launch_compose(M.n, p1.agg, p2.agg, agg, s);
+            mem = P.get<int4>((size_t)Cf.n);
+            launch_members(Cf.n, p2.lead, p2.mate, p1.lead, p1.mate, mem, s);
+        } else {
+            HIPCHK(hipMemcpyAsync(agg, p1.agg, sizeof(int) * M.n, hipMemcpyDeviceToDevice, s));
+            mem = P.get<int4>((size_t)Cf.n);
+            launch_members(Cf.n, nullptr, nullptr, p1.lead, p1.mate, mem, s);
+        }
+        // where each system starts in the coarse level
+        const int m = (int)live.size();
+        for (int j = 0; j < m; ++j) ho[j] = live[j].off;
+        HIPCHK(hipMemcpyAsync(offs_d, ho.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+        launch_seg_starts(m, offs_d, agg, Cf.rp, starts, s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(hs.data(), starts, sizeof(int) * 2 * m, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<Live> next;
+        for (int j = 0; j < m; ++j) {
+            const Live& L = live[j];
+            const int c0 = hs[2 * j], c1 = j + 1 < m ? hs[2 * (j + 1)] : Cf.n;
+            const int64_t q0 = hs[2 * j + 1], q1 = j + 1 < m ? hs[2 * (j + 1) + 1] : Cf.nnz;
+            const int nc = c1 - c0;
+            bool stop = !want[j];
+            if (!stop && nc == L.n) {  // no progress
+                if (L.n > p.max_dense_rows) out[L.seg].status = AMG_ESTALL;
+                stop = true;
+            }
+            if (!stop && (double)nc >= p.stall_ratio * (double)L.n && L.n <= p.max_dense_rows) stop = true;
+            if (stop) {
+                if (out[L.seg].status == AMG_OK) fin.push_back(Coarsest{L.seg, M, L});
+                continue;
+            }
+            SegLevelSrc& cur = out[L.seg].lev.back();
+            cur.mem = mem + c0;
+            cur.mem_add = -L.off;
+            next.push_back(Live{L.seg, c0, nc, q0, q1 - q0});
+        }
+        if (next.empty()) break;
+        // the next level: the coarse operator, without the systems that stopped
+        Csr Mn = Cf;
+        bool compact = next.size() != live.size();
+        if (compact) {
+            int64_t n2 = 0, e2 = 0;
+            for (const Live& L : next) {
+                n2 += L.n;
+                e2 += L.nnz;
+            }
+            Mn = Csr{(int)n2, e2, P.get<int>((size_t)n2 + 1), P.get<int>((size_t)e2), P.get<double>((size_t)e2)};
+            std::vector<GatherPiece> cp;
+            int r = 0;
+            int64_t e = 0;
+            for (size_t j = 0; j < next.size(); ++j) {
+                Live& L = next[j];
+                const bool lastp = j + 1 == next.size();
+                cp.push_back(GatherPiece{Cf.rp + L.off, Mn.rp + r, L.n + (lastp ? 1 : 0), (int)(e - L.eoff), 0});
+                cp.push_back(GatherPiece{Cf.ci + L.eoff, Mn.ci + e, L.nnz, r - L.off, 0});
+                cp.push_back(GatherPiece{Cf.v + L.eoff, Mn.v + e, L.nnz, 0, 1});
+                L.off = r;
+                L.eoff = e;
+                r += L.n;
+                e += L.nnz;
+            }
+            gather_run(cp, P, s);
+        }
+        double* dn = P.get<double>((size_t)Mn.n);
+        launch_dinv(Mn.n, Mn.rp, Mn.ci, Mn.v, dn, gerr, s);
+        HIPCHK(hipGetLastError());
+        for (const Live& L : next) out[L.seg].lev.push_back(level_src(L, Mn, dn));
+        M = Mn;
+        dinv = dn;
+        live.swap(next);
+    }
+    check_err_word(gerr, s, "amg_batch_setup");
+    // coarsest blocks: dense LU and inverse per system
+    for (const Coarsest& c : fin) {
+        SegSrc& S = out[c.seg];
+        const int m = c.L.n;
+        if (S.lev.size() < 2) {  // a single level is not batched
+            S.status = AMG_EINVAL;
+            continue;
+        }
+        if (m > 1024) raise(AMG_EHIP, "coarsest level of %d rows exceeds the dense limit (internal error)", m);
+        double* a = P.get<double>((size_t)m * m);
+        int* piv = P.get<int>(2 * (size_t)m);
+        double* ainv = P.get<double>((size_t)m * m);
+        HIPCHK(hipMemsetAsync(a, 0, sizeof(double) * (size_t)m * m, s));
+        launch_dense_assemble(m, c.C.rp + c.L.off, c.C.ci, c.C.v, a, s, -c.L.off);
+        launch_dense_lu_inverse(m, a, piv, ainv, err + c.seg, s);
+        S.ainv_t = ainv;
+        S.lev.back().mem = nullptr;
+    }
+    HIPCHK(hipGetLastError());
+    std::vector<int> e(count);
+    HIPCHK(hipMemcpyAsync(e.data(), err, sizeof(int) * count, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (const Coarsest& c : fin)
+        if (out[c.seg].status == AMG_OK && (e[c.seg] & ERR_SINGULAR)) out[c.seg].status = AMG_ESINGULAR;
+    for (SegSrc& S : out)
+        if (S.status != AMG_OK) S.lev.clear();
+}
+
+}  // namespace amg
 
 extern "C" {
 

@@ -52,6 +52,7 @@ struct BLev {
 };
 
 struct BSeg {
+    amg_status status = AMG_OK;  // a system whose setup failed takes no rows
     int nlev = 0;
     int n0 = 0;     // level-0 rows
     int off0 = 0;   // first level-0 row
@@ -264,6 +265,11 @@ void batch_pcg(amg_batch* B, double rtol, int maxit, hipStream_t s, amg_info* in
     bool any_zero = false;
     int live = 0;
     for (int i = 0; i < ns; ++i) {
+        if (B->seg[i].status != AMG_OK) {  // its setup failed: nothing to solve
+            info[i].status = B->seg[i].status;
+            act[i] = 0;
+            continue;
+        }
         nb[i] = std::sqrt(sv(i, B_BB));
         if (nb[i] == 0.0) {  // x = 0 is the solution
             zero[i] = 1;
@@ -369,6 +375,10 @@ void build_dense(amg_batch* B, std::vector<char>& host, size_t at_dd, size_t at_
     int nb = 0;
     for (int i = 0; i < B->nseg; ++i) {
         const BSeg& g = B->seg[i];
+        if (g.status != AMG_OK) {
+            dd[i] = BDense<T>{};
+            continue;
+        }
         const BLev& C = B->lev[g.cl];
         const BLev& F = B->lev[g.cl - 1];
         const T* gf = g.cl - 1 == 0 ? static_cast<const T*>(B->g0) : static_cast<const T*>(F.g);
@@ -382,22 +392,16 @@ void build_dense(amg_batch* B, std::vector<char>& host, size_t at_dd, size_t at_
     }
 }
 
-void create_impl(const amg_hier* const* hs, int count, hipStream_t caller, amg_batch** out) {
-    if (!hs || !out || count < 1 || count > (1 << 20)) raise(AMG_EINVAL, "amg_batch_create: bad arguments");
-    for (int i = 0; i < count; ++i) {
-        const amg_hier* h = hs[i];
-        if (!h) raise(AMG_EINVAL, "amg_batch_create: NULL hierarchy %d", i);
-        if (h->lev.size() < 2) raise(AMG_EINVAL, "amg_batch_create: system %d has a single level", i);
-        if (h->p.pre != 1 || h->p.post != 1) raise(AMG_EINVAL, "amg_batch_create: needs pre = post = 1");
-        if (h->prec32 != hs[0]->prec32 || h->p.omega != hs[0]->p.omega ||
-            h->p.true_res_period != hs[0]->p.true_res_period)
-            raise(AMG_EINVAL, "amg_batch_create: systems differ in precision, omega or true_res_period");
-    }
+// Lays out a batch from the systems' levels wherever they are stored (see
+// SegSrc); blocks the host until the copies are done.
+void create_impl(const std::vector<SegSrc>& src, bool prec32, double omega, int period, hipStream_t caller,
+                 amg_batch** out) {
+    const int count = (int)src.size();
     std::unique_ptr<amg_batch> B(new amg_batch());
     B->nseg = count;
-    B->prec32 = hs[0]->prec32;
-    B->omega = hs[0]->p.omega;
-    B->period = hs[0]->p.true_res_period;
+    B->prec32 = prec32;
+    B->omega = omega;
+    B->period = period;
     B->stream = stream_get();
     B->ev[0] = event_get(false);
     B->ev[1] = event_get(false);
@@ -407,7 +411,8 @@ void create_impl(const amg_hier* const* hs, int count, hipStream_t caller, amg_b
     B->pool.s = s;
     const int ns = count;
     int K = 0;
-    for (int i = 0; i < ns; ++i) K = std::max(K, (int)hs[i]->lev.size());
+    for (int i = 0; i < ns; ++i) K = std::max(K, (int)src[i].lev.size());
+    if (K < 2) raise(AMG_EINVAL, "amg_batch: no system with two or more levels");
     B->lev.resize(K);
     B->seg.resize(ns);
     // layouts: pos[k][i] = first row of system i in the level-k vectors
@@ -416,19 +421,20 @@ void create_impl(const amg_hier* const* hs, int count, hipStream_t caller, amg_b
     for (int k = 0; k < K; ++k) {
         BLev& L = B->lev[k];
         for (int i = 0; i < ns; ++i) {
-            const int nl = (int)hs[i]->lev.size();
+            const int nl = (int)src[i].lev.size();
+            if (k == 0) pos[k][i] = L.n;  // a failed system sits empty at its place
             if (k <= nl - 2) {
                 pos[k][i] = L.n;
                 epos[k][i] = L.nnz;
-                L.n += hs[i]->lev[k].n;
-                L.nnz += hs[i]->lev[k].nnz;
+                L.n += src[i].lev[k].n;
+                L.nnz += src[i].lev[k].nnz;
             }
         }
         L.V = L.n;
         for (int i = 0; i < ns; ++i) {
-            if ((int)hs[i]->lev.size() - 1 == k) {
+            if ((int)src[i].lev.size() - 1 == k) {
                 pos[k][i] = L.V;
-                L.V += hs[i]->lev[k].n;
+                L.V += src[i].lev[k].n;
             }
         }
         if ((int64_t)L.V >= (int64_t)1 << 31 || L.nnz >= (int64_t)1 << 31)
@@ -436,11 +442,13 @@ void create_impl(const amg_hier* const* hs, int count, hipStream_t caller, amg_b
     }
     for (int i = 0; i < ns; ++i) {
         BSeg& g = B->seg[i];
-        g.nlev = (int)hs[i]->lev.size();
-        g.n0 = hs[i]->lev[0].n;
+        g.status = src[i].lev.size() >= 2 ? src[i].status : (src[i].status != AMG_OK ? src[i].status : AMG_EINVAL);
         g.off0 = pos[0][i];
+        if (g.status != AMG_OK) continue;  // no rows, no levels
+        g.nlev = (int)src[i].lev.size();
+        g.n0 = src[i].lev[0].n;
         g.cl = g.nlev - 1;
-        g.m = hs[i]->lev[g.cl].n;
+        g.m = src[i].lev[g.cl].n;
         g.crow0 = pos[g.cl][i];
     }
     B->n0 = B->lev[0].n;
@@ -508,22 +516,28 @@ void create_impl(const amg_hier* const* hs, int count, hipStream_t caller, amg_b
         for (int i = 0; i < ns; ++i) {
             const BSeg& g = B->seg[i];
             if (k >= g.nlev) continue;
-            const auto& H = hs[i]->lev[k];
+            const SegLevelSrc& H = src[i].lev[k];
             if (k <= g.nlev - 2) {
                 const int o = pos[k][i];
-                piece(H.rp, L.rp + o, (int64_t)H.n + (i == last ? 1 : 0), (int)epos[k][i], 0);
-                piece(H.ci, L.ci + epos[k][i], H.nnz, o, 0);
+                piece(H.rp, L.rp + o, (int64_t)H.n + (i == last ? 1 : 0), (int)epos[k][i] + H.rp_add, 0);
+                piece(H.ci, L.ci + epos[k][i], H.nnz, o + H.ci_add, 0);
                 piece(H.v, L.v + epos[k][i], H.nnz, 0, 1);
-                if (B->prec32) piece(H.v32, L.v32 + epos[k][i], H.nnz, 0, 2);
-                piece(H.mem, L.mem + pos[k + 1][i], hs[i]->lev[k + 1].n, o, 3);
+                if (B->prec32) {
+                    if (H.v32) piece(H.v32, L.v32 + epos[k][i], H.nnz, 0, 2);
+                    else piece(H.v, L.v32 + epos[k][i], H.nnz, 0, 4);
+                }
+                piece(H.mem, L.mem + pos[k + 1][i], src[i].lev[k + 1].n, o + H.mem_add, 3);
             }
-            if (k <= g.cl) {
-                piece(H.dinv, L.dinv + pos[k][i], H.n, 0, 1);
-                if (B->prec32) piece(H.dinv32, L.dinv32 + pos[k][i], H.n, 0, 2);
+            piece(H.dinv, L.dinv + pos[k][i], H.n, 0, 1);
+            if (B->prec32) {
+                if (H.dinv32) piece(H.dinv32, L.dinv32 + pos[k][i], H.n, 0, 2);
+                else piece(H.dinv, L.dinv32 + pos[k][i], H.n, 0, 4);
             }
         }
     }
-    for (int i = 0; i < ns; ++i) piece(hs[i]->ainv_t, B->ainv + aoff[i], (int64_t)B->seg[i].m * B->seg[i].m, 0, 1);
+    for (int i = 0; i < ns; ++i)
+        if (B->seg[i].status == AMG_OK)
+            piece(src[i].ainv_t, B->ainv + aoff[i], (int64_t)B->seg[i].m * B->seg[i].m, 0, 1);
     const int CH = gather_chunk();
     std::vector<int2> gtab;
     for (size_t p = 0; p < pcs.size(); ++p)
@@ -652,11 +666,97 @@ void batch_autotune(amg_batch* B, hipStream_t caller, int32_t* out) {
 
 }  // namespace
 
+namespace amg {
+
+void gather_run(const std::vector<GatherPiece>& pcs, DevPool& P, hipStream_t s) {
+    if (pcs.empty()) return;
+    const int CH = gather_chunk();
+    std::vector<int2> tab;
+    for (size_t p = 0; p < pcs.size(); ++p)
+        for (int64_t c = 0; c * CH < pcs[p].count; ++c) tab.push_back(make_int2((int)p, (int)c));
+    const size_t a = (sizeof(GatherPiece) * pcs.size() + 255) & ~size_t(255);
+    char* dev = P.get<char>(a + sizeof(int2) * tab.size());
+    HIPCHK(hipMemcpyAsync(dev, pcs.data(), sizeof(GatherPiece) * pcs.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dev + a, tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice, s));
+    launch_gather((int)tab.size(), reinterpret_cast<const GatherPiece*>(dev), reinterpret_cast<const int2*>(dev + a),
+                  s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));  // the host tables are consumed
+}
+
+}  // namespace amg
+
 extern "C" {
 
 amg_status amg_batch_create(const amg_hier* const* hiers, int32_t count, void* stream, amg_batch** out) {
     if (out) *out = nullptr;
-    return guarded([&] { create_impl(hiers, count, as_stream(stream), out); });
+    return guarded([&] {
+        if (!hiers || !out || count < 1 || count > (1 << 20)) raise(AMG_EINVAL, "amg_batch_create: bad arguments");
+        std::vector<SegSrc> src(count);
+        for (int i = 0; i < count; ++i) {
+            const amg_hier* h = hiers[i];
+            if (!h) raise(AMG_EINVAL, "amg_batch_create: NULL hierarchy %d", i);
+            if (h->lev.size() < 2) raise(AMG_EINVAL, "amg_batch_create: system %d has a single level", i);
+            if (h->p.pre != 1 || h->p.post != 1) raise(AMG_EINVAL, "amg_batch_create: needs pre = post = 1");
+            if (h->prec32 != hiers[0]->prec32 || h->p.omega != hiers[0]->p.omega ||
+                h->p.true_res_period != hiers[0]->p.true_res_period)
+                raise(AMG_EINVAL, "amg_batch_create: systems differ in precision, omega or true_res_period");
+            for (size_t k = 0; k < h->lev.size(); ++k) {
+                const Level& L = h->lev[k];
+                SegLevelSrc t;
+                t.n = L.n;
+                t.nnz = L.nnz;
+                t.rp = L.rp;
+                t.ci = L.ci;
+                t.v = L.v;
+                t.v32 = L.v32;
+                t.dinv = L.dinv;
+                t.dinv32 = L.dinv32;
+                t.mem = k + 1 < h->lev.size() ? L.mem : nullptr;
+                src[i].lev.push_back(t);
+            }
+            src[i].ainv_t = h->ainv_t;
+        }
+        create_impl(src, hiers[0]->prec32, hiers[0]->p.omega, hiers[0]->p.true_res_period, as_stream(stream), out);
+    });
+}
+
+amg_status amg_batch_setup(const amg_csr* A, int32_t count, const amg_params* params, void* stream, amg_batch** out,
+                           amg_status* status) {
+    if (out) *out = nullptr;
+    return guarded([&] {
+        if (!A || !out || count < 1 || count > (1 << 20)) raise(AMG_EINVAL, "amg_batch_setup: bad arguments");
+        amg_params p;
+        amg_params_default(&p);
+        if (params) p = *params;
+        if (p.pre != 1 || p.post != 1) raise(AMG_EINVAL, "amg_batch_setup: needs pre = post = 1");
+        hipStream_t caller = as_stream(stream);
+        hipStream_t s = stream_get();
+        hipEvent_t ev = event_get(false);
+        DevPool P;
+        P.s = s;
+        struct Guard {
+            DevPool& P;
+            hipStream_t s;
+            hipEvent_t ev;
+            ~Guard() {
+                (void)hipStreamSynchronize(s);
+                P.release();
+                (void)hipStreamSynchronize(s);
+                event_put(ev, false);
+                stream_put(s);
+            }
+        } guard{P, s, ev};
+        HIPCHK(hipEventRecord(ev, caller));
+        HIPCHK(hipStreamWaitEvent(s, ev, 0));
+        std::vector<SegSrc> src;
+        batch_coarsen(A, count, p, s, P, src);
+        if (status)
+            for (int i = 0; i < count; ++i) status[i] = src[i].status;
+        create_impl(src, p.precond_fp32 != 0, p.omega, p.true_res_period, s, out);
+        HIPCHK(hipEventRecord(ev, s));
+        HIPCHK(hipStreamWaitEvent(caller, ev, 0));
+    });
 }
 
 amg_status amg_batch_rows(const amg_batch* b, int32_t* offsets) {

@@ -198,6 +198,40 @@ amg_status guarded(F&& f) {
 
 inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
+// ---- batches ----------------------------------------------------------------
+// One system's level k inside source arrays (a hierarchy, or the concatenated
+// operators of a batched setup).  Adding rp_add to the row pointers, ci_add to
+// the columns and mem_add to the members gives the system's own numbering.
+struct SegLevelSrc {
+    int n = 0;
+    int64_t nnz = 0;
+    const int* rp = nullptr;  // [n + 1]
+    int rp_add = 0;
+    const int* ci = nullptr;  // [nnz]
+    int ci_add = 0;
+    const double* v = nullptr;
+    const float* v32 = nullptr;     // null: rounded from v
+    const double* dinv = nullptr;   // [n]
+    const float* dinv32 = nullptr;  // null: rounded from dinv
+    const int4* mem = nullptr;      // [rows of level k+1]; null on the coarsest level
+    int mem_add = 0;
+};
+struct SegSrc {
+    amg_status status = AMG_OK;      // a failed system takes no rows in a batch
+    std::vector<SegLevelSrc> lev;    // levels 0 .. coarsest
+    const double* ainv_t = nullptr;  // coarsest inverse, column-major
+};
+
+void validate_params(const amg_params& p);
+// Copies every piece with one launch (blocks the host until done).
+void gather_run(const std::vector<GatherPiece>& pcs, DevPool& P, hipStream_t s);
+// Batched setup: the systems' levels are built together on concatenated
+// operators (one matching round and one Galerkin launch per step for all of
+// them) with each system's stop rule applied to it alone.  The device arrays
+// the sources point to live in P.
+void batch_coarsen(const amg_csr* A, int count, const amg_params& p, hipStream_t s, DevPool& P,
+                   std::vector<SegSrc>& out);
+
 }  // namespace amg
 
 struct amg_hier {

@@ -99,8 +99,13 @@ void launch_compose(int n, const int* agg1, const int* agg2, int* out, hipStream
 void launch_members(int nc, const int* lead2, const int* mate2, const int* lead1, const int* mate1, int4* mem,
                     hipStream_t s);
 
-// a must be zeroed before the call.
-void launch_dense_assemble(int n, const int* rp, const int* ci, const double* v, double* a, hipStream_t s);
+// a must be zeroed before the call.  col_add shifts the stored columns (a
+// diagonal block of a larger matrix); entries outside the block are skipped.
+void launch_dense_assemble(int n, const int* rp, const int* ci, const double* v, double* a, hipStream_t s,
+                           int col_add = 0);
+// Systems stored one after another in a level: out[2j] = agg[off[j]],
+// out[2j+1] = crp[out[2j]] (coarse row and entry where system j starts).
+void launch_seg_starts(int m, const int* off, const int* agg, const int* crp, int* out, hipStream_t s);
 // piv: int32[2n] scratch.  n <= 1024.
 void launch_dense_lu_inverse(int n, double* a, int* piv, double* ainv_t, int* err, hipStream_t s);
 
@@ -243,7 +248,8 @@ struct BDense {
     ScatterT<T> sc;
 };
 // One copy of a batch assembly: kind 0 int32 (+add), 1 double, 2 float,
-// 3 int4 member lists (+add on the members present).
+// 3 int4 member lists (+add on the members present), 4 double rounded to
+// float.
 struct GatherPiece {
     const void* src;
     void* dst;

@@ -6,10 +6,11 @@
 // order while the footprints of the requests in flight fit the budget; a
 // request waits at the head of the queue until enough finish.
 //
-// Batched mode (batch >= 2): workers only build hierarchies and hand PCG
-// requests to a solver thread, which takes every ready request with the same
-// stop settings (up to `batch`) and advances them together with one batched
-// solve; requests set up while a batch runs form the next one.
+// Batched mode (batch >= 2): a worker takes the queued PCG requests with the
+// same stop settings (up to `batch`, within the budget) as one group, builds
+// their hierarchies together (amg_batch_setup) and solves them together
+// (amg_batch_solve); requests arriving meanwhile form the next group, on
+// the next free worker.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -41,7 +42,6 @@ struct Request {
     bool done = false;
     amg_status st = AMG_OK;
     amg_info info{};
-    amg_hier* h = nullptr;  // batched mode: the hierarchy waiting for the solver thread
 };
 
 uint64_t footprint(int32_t n, int64_t nnz, const amg_params& p) {
@@ -69,7 +69,7 @@ uint64_t footprint(int32_t n, int64_t nnz, const amg_params& p) {
 // right-hand side and solution.
 uint64_t batch_extra(int32_t n, int64_t nnz) {
     const uint64_t N = (uint64_t)(n > 0 ? n : 0), Z = (uint64_t)(nnz > 0 ? nnz : 0);
-    return 24 * Z + 224 * N + 8ull * 1024 * 1024;
+    return 60 * Z + 256 * N + 8ull * 1024 * 1024;  // also the batched setup's concatenated levels
 }
 
 }  // namespace
@@ -86,12 +86,7 @@ struct amg_server {
     int active = 0;
     bool stopping = false;
     std::vector<std::thread> threads;
-    // batched mode
-    std::deque<Request*> ready;  // hierarchies built, waiting for the solver thread
-    std::condition_variable cv_ready;
-    int building = 0;  // workers inside a setup
-    std::thread solver;
-    std::vector<hipStream_t> wstreams;
+    std::vector<hipStream_t> wstreams;  // one per worker, destroyed with the server
 
     void release_streams() {
         for (hipStream_t& st : wstreams)
@@ -116,15 +111,16 @@ struct amg_server {
         cv_work.notify_all();
     }
 
-    // Worker i runs on wstreams[i].  The streams live until the server is
-    // destroyed: in batched mode a hierarchy built on a worker's stream is
-    // released by the solver thread, possibly after that worker has stopped.
+    // Worker i runs on wstreams[i].  It takes the request at the head of the
+    // queue once its footprint fits; in batched mode it also takes the queued
+    // PCG requests with the same stop settings that still fit, up to `batch`.
     void worker(int i) {
         if (hipSetDevice(device) != hipSuccess) return;
         hipStream_t s = wstreams[i];
-        const bool have_stream = s != nullptr;
+        double* buf = nullptr;  // batched mode: right-hand sides, then solutions
+        size_t cap = 0;
         for (;;) {
-            Request* r = nullptr;
+            std::vector<Request*> grp;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv_work.wait(lk, [&] {
@@ -133,95 +129,70 @@ struct amg_server {
                     return active == 0 || in_use + f->foot <= cfg.hbm_budget_bytes;
                 });
                 if (pending.empty()) break;  // stopping and drained
-                r = reqs[pending.front()];
+                Request* head = reqs[pending.front()];
                 pending.pop_front();
-                in_use += r->foot;
+                grp.push_back(head);
+                in_use += head->foot;
                 ++active;
-                ++building;
+                if (batched() && head->method == 0) {
+                    for (auto it = pending.begin(); it != pending.end() && (int)grp.size() < cfg.batch;) {
+                        Request* r = reqs[*it];
+                        if (r->method == 0 && r->rtol == head->rtol && r->maxit == head->maxit &&
+                            in_use + r->foot <= cfg.hbm_budget_bytes) {
+                            grp.push_back(r);
+                            in_use += r->foot;
+                            ++active;
+                            it = pending.erase(it);
+                        } else {
+                            ++it;
+                        }
+                    }
+                }
             }
-            const bool handed = run(r, have_stream ? s : nullptr, have_stream);
-            {
-                std::lock_guard<std::mutex> lk(mu);
-                --building;
-                if (handed) ready.push_back(r);
-            }
-            cv_ready.notify_all();
-            if (!handed) finish(r);
+            if (grp.size() == 1 && !(batched() && grp[0]->method == 0)) run_one(grp[0], s);
+            else run_group(grp, s, buf, cap);
+            for (Request* r : grp) finish(r);
         }
+        if (buf) (void)hipFree(buf);
     }
 
-    // Setup, then either the whole solve here or (batched mode, PCG on a
-    // multilevel hierarchy) the hand-over to the solver thread (returns true).
-    bool run(Request* r, hipStream_t s, bool have_stream) {
-        if (!have_stream) {
+    // Setup, solve and teardown of one request.
+    void run_one(Request* r, hipStream_t s) {
+        if (!s) {
             r->st = AMG_EHIP;
             r->info.status = AMG_EHIP;
-            return false;
+            return;
         }
         amg_hier* h = nullptr;
         amg_status st = amg_setup(&r->A, &cfg.params, s, &h);
-        if (st == AMG_OK && batched() && r->method == 0) {
-            int32_t levels = 0;
-            if (amg_num_levels(h, &levels) == AMG_OK && levels >= 2) {
-                r->h = h;
-                return true;
-            }
-        }
         if (st == AMG_OK) st = krylov_solve(h, r->method, r->b, r->x, r->rtol, r->maxit, s, &r->info);
         else r->info.status = st;
         if (h) (void)amg_destroy(h);
         r->st = st;
-        return false;
     }
 
-    // Batched mode: solves groups of ready requests together.
-    void solver_loop() {
-        if (hipSetDevice(device) != hipSuccess) return;
-        hipStream_t s = nullptr;
-        const bool have_stream = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
-        double* buf = nullptr;  // right-hand sides, then solutions, of a batch
-        size_t cap = 0;
-        for (;;) {
-            std::vector<Request*> grp;
-            {
-                std::unique_lock<std::mutex> lk(mu);
-                cv_ready.wait(lk, [&] { return !ready.empty() || (stopping && pending.empty() && building == 0); });
-                if (ready.empty()) break;
-                const Request* head = ready.front();
-                for (auto it = ready.begin(); it != ready.end() && (int)grp.size() < cfg.batch;) {
-                    if ((*it)->rtol == head->rtol && (*it)->maxit == head->maxit) {
-                        grp.push_back(*it);
-                        it = ready.erase(it);
-                    } else {
-                        ++it;
-                    }
-                }
-            }
-            solve_group(grp, have_stream ? s : nullptr, buf, cap);
-            for (Request* r : grp) finish(r);
-        }
-        if (buf) (void)hipFree(buf);
-        if (have_stream) (void)hipStreamDestroy(s);
+    static void fail(Request* r, amg_status st) {
+        r->st = st;
+        r->info.status = st;
     }
 
-    static void fail_group(std::vector<Request*>& grp, amg_status st) {
-        for (Request* r : grp) {
-            r->st = st;
-            r->info.status = st;
-        }
-    }
-
-    static void solve_group(std::vector<Request*>& grp, hipStream_t s, double*& buf, size_t& cap) {
+    // Batched mode: one batched setup and one batched PCG solve for the group.
+    // When the batched setup fails as a whole, or a system cannot be batched
+    // (a single level), the requests concerned are run one by one.
+    void run_group(std::vector<Request*>& grp, hipStream_t s, double*& buf, size_t& cap) {
         const int n = (int)grp.size();
-        std::vector<const amg_hier*> hs(n);
-        for (int i = 0; i < n; ++i) hs[i] = grp[i]->h;
-        amg_batch* bt = nullptr;
-        const amg_status st = s ? amg_batch_create(hs.data(), n, s, &bt) : AMG_EHIP;
-        for (Request* r : grp) {  // the batch holds its own copy of every level
-            (void)amg_destroy(r->h);
-            r->h = nullptr;
+        if (!s) {
+            for (Request* r : grp) fail(r, AMG_EHIP);
+            return;
         }
-        if (st != AMG_OK) return fail_group(grp, st);
+        std::vector<amg_csr> A(n);
+        for (int i = 0; i < n; ++i) A[i] = grp[i]->A;
+        std::vector<amg_status> st(n, AMG_OK);
+        amg_batch* bt = nullptr;
+        if (amg_batch_setup(A.data(), n, &cfg.params, s, &bt, st.data()) != AMG_OK) {
+            for (Request* r : grp) run_one(r, s);
+            return;
+        }
         std::vector<int32_t> off(n + 1);
         (void)amg_batch_rows(bt, off.data());
         const size_t need = 2 * (size_t)off[n] * sizeof(double);
@@ -231,7 +202,8 @@ struct amg_server {
             cap = 0;
             if (hipMalloc((void**)&buf, need + need / 2) != hipSuccess) {
                 (void)amg_batch_destroy(bt);
-                return fail_group(grp, AMG_ENOMEM);
+                for (Request* r : grp) fail(r, AMG_ENOMEM);
+                return;
             }
             cap = need + need / 2;
         }
@@ -240,24 +212,28 @@ struct amg_server {
         bool ok = true;
         for (int i = 0; i < n; ++i) {
             const size_t bytes = sizeof(double) * (size_t)(off[i + 1] - off[i]);
+            if (bytes == 0) continue;
             ok &= hipMemcpyAsync(B + off[i], grp[i]->b, bytes, hipMemcpyDeviceToDevice, s) == hipSuccess;
             ok &= hipMemcpyAsync(X + off[i], grp[i]->x, bytes, hipMemcpyDeviceToDevice, s) == hipSuccess;
         }
-        if (!ok) {
-            (void)amg_batch_destroy(bt);
-            return fail_group(grp, AMG_EHIP);
-        }
         std::vector<amg_info> info(n);
-        (void)amg_batch_solve(bt, 0, B, X, grp[0]->rtol, grp[0]->maxit, s, info.data());
-        for (int i = 0; i < n; ++i) {
+        if (ok) (void)amg_batch_solve(bt, 0, B, X, grp[0]->rtol, grp[0]->maxit, s, info.data());
+        for (int i = 0; i < n && ok; ++i) {
             const size_t bytes = sizeof(double) * (size_t)(off[i + 1] - off[i]);
+            if (bytes == 0) continue;
             ok &= hipMemcpyAsync(grp[i]->x, X + off[i], bytes, hipMemcpyDeviceToDevice, s) == hipSuccess;
         }
         ok &= hipStreamSynchronize(s) == hipSuccess;
         (void)amg_batch_destroy(bt);
         for (int i = 0; i < n; ++i) {
-            grp[i]->info = info[i];
-            grp[i]->st = ok ? (amg_status)info[i].status : AMG_EHIP;
+            if (!ok) {
+                fail(grp[i], AMG_EHIP);
+            } else if (st[i] == AMG_EINVAL && off[i + 1] == off[i]) {
+                run_one(grp[i], s);  // invalid or a single level: the plain path decides
+            } else {
+                grp[i]->info = info[i];
+                grp[i]->st = (amg_status)info[i].status;
+            }
         }
     }
 };
@@ -305,16 +281,13 @@ amg_status amg_server_create(const amg_server_config* c, amg_server** out) {
                 return AMG_EHIP;
             }
         for (int i = 0; i < cfg.workers; ++i) s->threads.emplace_back([s, i] { s->worker(i); });
-        if (s->batched()) s->solver = std::thread([s] { s->solver_loop(); });
     } catch (...) {
         {
             std::lock_guard<std::mutex> lk(s->mu);
             s->stopping = true;
         }
         s->cv_work.notify_all();
-        s->cv_ready.notify_all();
         for (auto& t : s->threads) t.join();
-        if (s->solver.joinable()) s->solver.join();
         s->release_streams();
         delete s;
         return AMG_ENOMEM;
@@ -381,8 +354,6 @@ amg_status amg_server_destroy(amg_server* s) {
     }
     s->cv_work.notify_all();
     for (auto& t : s->threads) t.join();
-    s->cv_ready.notify_all();  // the workers are done: the solver drains the ready requests and stops
-    if (s->solver.joinable()) s->solver.join();
     s->release_streams();
     for (auto& kv : s->reqs) delete kv.second;
     delete s;

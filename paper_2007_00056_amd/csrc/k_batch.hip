@@ -196,6 +196,9 @@ __global__ __launch_bounds__(BS) void k_gather(const GatherPiece* __restrict__ p
             case 2:
                 static_cast<float*>(P.dst)[e] = static_cast<const float*>(P.src)[e];
                 break;
+            case 4:
+                static_cast<float*>(P.dst)[e] = float(static_cast<const double*>(P.src)[e]);
+                break;
             default: {
                 int4 m = static_cast<const int4*>(P.src)[e];
                 m.x += P.add;  // the first member always exists

@@ -539,15 +539,37 @@ void launch_members(int nc, const int* lead2, const int* mate2, const int* lead1
 // that each V-cycle applies the exact coarse solve as one dense product
 // (n <= 1024).
 // ---------------------------------------------------------------------------
+// Row i of the block: entries rp[i]..rp[i+1]-1 of ci/v, columns shifted by
+// col_add (a diagonal block of a larger matrix starts at column -col_add).
 __global__ __launch_bounds__(BS) void k_dense_assemble(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                       const double* __restrict__ v, double* __restrict__ a) {
+                                                       const double* __restrict__ v, double* __restrict__ a,
+                                                       int col_add) {
     const int i = blockIdx.x * BS + threadIdx.x;
     if (i >= n) return;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) a[(size_t)i * n + ci[k]] = v[k];
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int c = ci[k] + col_add;
+        if (c >= 0 && c < n) a[(size_t)i * n + c] = v[k];
+    }
 }
 
-void launch_dense_assemble(int n, const int* rp, const int* ci, const double* v, double* a, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_assemble, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, a);
+void launch_dense_assemble(int n, const int* rp, const int* ci, const double* v, double* a, hipStream_t s,
+                           int col_add) {
+    hipLaunchKernelGGL(k_dense_assemble, dim3(blocks_for(n)), dim3(BS), 0, s, n, rp, ci, v, a, col_add);
+}
+
+// Start of each system inside a concatenated level and its coarse level:
+// out[2j] = agg[off[j]] (first coarse row), out[2j+1] = crp[out[2j]].
+__global__ __launch_bounds__(BS) void k_seg_starts(int m, const int* __restrict__ off, const int* __restrict__ agg,
+                                                   const int* __restrict__ crp, int* __restrict__ out) {
+    const int j = blockIdx.x * BS + threadIdx.x;
+    if (j >= m) return;
+    const int c = agg[off[j]];
+    out[2 * j] = c;
+    out[2 * j + 1] = crp[c];
+}
+
+void launch_seg_starts(int m, const int* off, const int* agg, const int* crp, int* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_starts, dim3(blocks_for(m)), dim3(BS), 0, s, m, off, agg, crp, out);
 }
 
 namespace {

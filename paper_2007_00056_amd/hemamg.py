@@ -26,7 +26,8 @@ EXPORTED = ["amg_params_default", "amg_setup", "amg_destroy", "amg_vcycle", "kry
             "amg_level_size", "amg_export_level", "amg_setup_stats", "amg_timing_enable", "amg_timing_read",
             "amg_last_error", "amg_footprint_bytes", "amg_server_config_default", "amg_server_create",
             "amg_server_submit", "amg_server_wait", "amg_server_destroy", "amg_batch_create", "amg_batch_rows",
-            "amg_batch_solve", "amg_batch_destroy", "amg_batch_levels", "amg_batch_autotune", "amg_autotune"]
+            "amg_batch_solve", "amg_batch_destroy", "amg_batch_levels", "amg_batch_autotune", "amg_autotune",
+            "amg_batch_setup"]
 
 
 class amg_csr(C.Structure):
@@ -88,6 +89,7 @@ def lib():
             "amg_server_wait": [vp, i64, C.POINTER(amg_info), C.POINTER(f64)],
             "amg_server_destroy": [vp],
             "amg_batch_create": [C.POINTER(vp), i32, vp, C.POINTER(vp)],
+            "amg_batch_setup": [C.POINTER(amg_csr), i32, C.POINTER(amg_params), vp, C.POINTER(vp), vp],
             "amg_batch_rows": [vp, vp],
             "amg_batch_solve": [vp, i32, vp, vp, f64, i32, vp, vp],
             "amg_batch_destroy": [vp],
@@ -269,6 +271,17 @@ def amg_batch_create(handles, stream=None) -> int:
     return b.value
 
 
+def amg_batch_setup(systems, params: amg_params | None = None, stream=None):
+    """Builds the hierarchies of every system together; returns (batch handle,
+    per-system statuses)."""
+    arr = (amg_csr * len(systems))(*[A.c for A in systems])
+    st = np.zeros(len(systems), np.int32)
+    b = C.c_void_p()
+    _check(lib().amg_batch_setup(arr, len(systems), C.byref(params) if params is not None else None,
+                                 _stream_ptr(stream), C.byref(b), st.ctypes.data))
+    return b.value, st.tolist()
+
+
 def amg_batch_rows(b: int, count: int) -> np.ndarray:
     off = np.empty(count + 1, np.int32)
     _check(lib().amg_batch_rows(b, off.ctypes.data))
@@ -363,12 +376,27 @@ class Hierarchy:
 
 
 class Batch:
-    """Owns an amg_batch_create handle built from hierarchies."""
+    """Owns a batch built from hierarchies (amg_batch_create) or set up from
+    matrices (Batch.setup, amg_batch_setup)."""
 
-    def __init__(self, hierarchies, stream=None):
-        self.count = len(hierarchies)
-        self.b = amg_batch_create([h.h if isinstance(h, Hierarchy) else h for h in hierarchies], stream)
+    def __init__(self, hierarchies=None, stream=None, _handle=None, _count=None):
+        if _handle is not None:
+            self.count, self.b = _count, _handle
+        else:
+            self.count = len(hierarchies)
+            self.b = amg_batch_create([h.h if isinstance(h, Hierarchy) else h for h in hierarchies], stream)
+        self.status = [AMG_OK] * self.count
         self.offsets = amg_batch_rows(self.b, self.count)
+
+    @classmethod
+    def setup(cls, systems, params: amg_params | None = None, stream=None, **overrides):
+        """systems: DeviceCSR matrices (borrowed during the call only)."""
+        if params is None:
+            params = amg_params_default(**overrides)
+        h, st = amg_batch_setup(systems, params, stream)
+        bt = cls(_handle=h, _count=len(systems))
+        bt.status = st
+        return bt
 
     def close(self):
         if getattr(self, "b", None):

@@ -211,3 +211,94 @@ def test_batch_autotune_keeps_every_bit(torch, fp32):
         bt.close()
         for h in hs:
             h.close()
+
+
+def separate(torch, systems, params, seeds):
+    xs, infos = run(torch, systems, params, seeds)
+    return xs, infos
+
+
+def setup_batch(torch, systems, params, seeds):
+    devs = [hemamg.DeviceCSR.from_host(a) for a in systems]
+    bt = hemamg.Batch.setup(devs, params)
+    return bt, devs
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(precond_fp32=1), dict(alternate=1), dict(hem=1),
+                                dict(passes_per_level=1, max_coarse_rows=16)])
+def test_batched_setup_equals_separate_setups(torch, kw):
+    """Building the hierarchies together (block-diagonal concatenations, one
+    matching round for all) gives every system the hierarchy amg_setup
+    builds: the batched solve is bit-identical to the batch assembled from
+    separate hierarchies."""
+    say("params", kw)
+    systems = mix()
+    seeds = list(range(len(systems)))
+    params = hemamg.amg_params_default(**kw)
+    xs, infos = separate(torch, systems, params, seeds)
+    bt, devs = setup_batch(torch, systems, params, seeds)
+    try:
+        assert bt.status == [hemamg.AMG_OK] * len(systems)
+        off = bt.offsets
+        rhs = torch.from_numpy(np.concatenate([P.rhs_uniform(a.n, s) for a, s in zip(systems, seeds)])).cuda()
+        x, inf2 = bt.solve(rhs, rtol=1e-8, maxit=500)
+        xh = x.cpu().numpy()
+        for i in range(len(systems)):
+            assert inf2[i]["iters"] == infos[i]["iters"], (i, inf2[i], infos[i])
+            np.testing.assert_array_equal(bits(xh[off[i]:off[i + 1]]), bits(xs[i]), err_msg=f"system {i}")
+    finally:
+        bt.close()
+
+
+def test_batched_setup_reports_failing_systems(torch):
+    good = [P.lognormal_diffusion3d(10, 5, 1.0), P.poisson3d(12), P.lognormal_diffusion3d(14, 6, 1.0)]
+    zero_diag = P.poisson3d(6)
+    zero_diag.val = zero_diag.val.copy()
+    row = slice(zero_diag.row_ptr[7], zero_diag.row_ptr[8])
+    zero_diag.val[row][zero_diag.col[row] == 7] = 0.0
+    tiny = P.poisson2d(5)  # one level: not batched
+    systems = [good[0], zero_diag, good[1], tiny, good[2]]
+    params = hemamg.amg_params_default()
+    bt, devs = setup_batch(torch, systems, params, None)
+    try:
+        assert bt.status == [hemamg.AMG_OK, hemamg.AMG_EINVAL, hemamg.AMG_OK, hemamg.AMG_EINVAL, hemamg.AMG_OK]
+        off = bt.offsets
+        assert off[2] - off[1] == 0 and off[4] - off[3] == 0
+        rhs = torch.from_numpy(np.concatenate([P.rhs_uniform(a.n, 3) if bt.status[i] == 0 else np.zeros(0)
+                                               for i, a in enumerate(systems)])).cuda()
+        x, infos = bt.solve(rhs, rtol=1e-8, maxit=500)
+        assert [i["status"] for i in infos] == bt.status
+        xh = x.cpu().numpy()
+        for i, a in ((0, good[0]), (2, good[1]), (4, good[2])):
+            xa, ia = run(torch, [a], params, [3])
+            assert ia[0]["iters"] == infos[i]["iters"]
+            np.testing.assert_array_equal(bits(xh[off[i]:off[i + 1]]), bits(xa[0]))
+    finally:
+        bt.close()
+
+
+def test_batched_setup_stall_and_depths(torch):
+    """Systems of very different depths and a high-contrast one whose coarse
+    levels stall (stall-ratio stop): every system stops where amg_setup
+    stops, and systems leave the concatenation at different levels."""
+    systems = [P.vardiff3d(24, seed=3), P.lognormal_diffusion3d(7, 2, 1.0), P.poisson3d(40),
+               P.lognormal_diffusion3d(20, 9, 2.0)]
+    params = hemamg.amg_params_default()
+    for a in systems:
+        with hemamg.Hierarchy(hemamg.DeviceCSR.from_host(a), params) as g:
+            say("n", a.n, "levels", g.nlevels, [hemamg.amg_level_size(g.h, k)[0] for k in range(g.nlevels)])
+    seeds = [11, 12, 13, 14]
+    xs, infos = separate(torch, systems, params, seeds)
+    bt, devs = setup_batch(torch, systems, params, seeds)
+    try:
+        assert bt.status == [hemamg.AMG_OK] * 4
+        assert hemamg.amg_batch_levels(bt.b) == max(hemamg.Hierarchy(d, params).nlevels for d in devs)
+        off = bt.offsets
+        rhs = torch.from_numpy(np.concatenate([P.rhs_uniform(a.n, s) for a, s in zip(systems, seeds)])).cuda()
+        x, inf2 = bt.solve(rhs, rtol=1e-8, maxit=500)
+        xh = x.cpu().numpy()
+        for i in range(4):
+            assert inf2[i]["iters"] == infos[i]["iters"]
+            np.testing.assert_array_equal(bits(xh[off[i]:off[i + 1]]), bits(xs[i]), err_msg=f"system {i}")
+    finally:
+        bt.close()
