@@ -243,7 +243,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy 256 MiB device-to-device (counter calibration for profiles)")
     ap.add_argument("--serve", action="store_true", help="served stream of solve requests instead of one system")
-    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--requests", type=int, default=1024)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--batch", type=int, default=32, help="batched serving: most requests per batched solve")
     ap.add_argument("--rates", type=lambda t: [float(v) for v in t.split(",")], default=[0.5, 1.0, 2.0])
