@@ -187,8 +187,9 @@ typedef struct amg_server amg_server;
 
 typedef struct {
     int32_t workers;          /* concurrent requests, 1..64 (4)                 */
-    int32_t batch;            /* >= 2: a worker takes up to this many queued PCG
-                               * requests with equal rtol and maxit that fit the
+    int32_t batch;            /* >= 2: a worker takes up to this many queued
+                               * requests with equal method (PCG or BiCGStab),
+                               * rtol and maxit that fit the
                                * budget, builds their hierarchies together
                                * (amg_batch_setup) and solves them together
                                * (amg_batch_solve); 0 or 1: one request per
@@ -232,7 +233,8 @@ amg_status amg_server_destroy(amg_server* s);
 /* ------------------------------------------------------------------------
  * Batched solves: many independent systems of different sizes advanced
  * together, each kernel launch of the V-cycle (Algorithm 1) and of the
- * preconditioned CG iteration (Algorithm 4) covering every system.
+ * preconditioned CG or BiCGStab iteration (Algorithms 4, 5) covering every
+ * system.
  * A batch copies the hierarchies it is made from into concatenated levels
  * (the hierarchies may be destroyed once amg_batch_create returns).  Each
  * system keeps its own CG scalars, stop test, residual replacement and
@@ -269,7 +271,8 @@ amg_status amg_batch_setup(const amg_csr* A, int32_t count, const amg_params* pa
  * offsets[i] .. offsets[i+1]-1 of the batch vectors. */
 amg_status amg_batch_rows(const amg_batch* b, int32_t* offsets);
 
-/* Preconditioned CG (method must be 0) on every system at once.
+/* Preconditioned CG (method 0, Algorithm 4) or BiCGStab (method 1,
+ * Algorithm 5) on every system at once.
  * b, x: [device] float64[offsets[count]], the systems' right-hand sides and
  * initial guesses one after another; x receives the solutions.  info: [host]
  * amg_info[count], one per system (status per system; solve_ms is the call's

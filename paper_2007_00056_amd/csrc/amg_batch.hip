@@ -30,7 +30,8 @@ namespace {
 
 using namespace amg;
 
-enum BSlot { B_BB = 0, B_RR, B_TRR, B_PQ, B_RHO0, B_RHO1 };
+enum BSlot { B_BB = 0, B_RR, B_TRR, B_PQ, B_RHO0, B_RHO1, B_TT, B_TS };  // B_PQ is (rbar, v) in BiCGStab
+static_assert(B_TS < kBatchSlots, "slots per system");
 
 struct BLev {
     int n = 0;        // smoothing rows
@@ -106,6 +107,8 @@ struct amg_batch {
     // Krylov vectors over level 0
     double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *pv[2] = {nullptr, nullptr}, *q = nullptr;
     void* g0 = nullptr;
+    double *rb = nullptr, *pt = nullptr, *sv = nullptr, *st = nullptr, *t = nullptr;  // BiCGStab, on first use
+    hipGraphExec_t bgraph[2] = {nullptr, nullptr};                                   // BiCGStab iterations
     int* err = nullptr;
     // host side
     double* S_host = nullptr;  // pinned [nseg * kBatchSlots]
@@ -121,6 +124,8 @@ struct amg_batch {
 
     ~amg_batch() {
         for (hipGraphExec_t& g : graph)
+            if (g) (void)hipGraphExecDestroy(g);
+        for (hipGraphExec_t& g : bgraph)
             if (g) (void)hipGraphExecDestroy(g);
         if (stream) (void)hipStreamSynchronize(stream);
         pool.release();
@@ -367,6 +372,173 @@ void batch_pcg(amg_batch* B, double rtol, int maxit, hipStream_t s, amg_info* in
         if (act[i]) info[i].status = AMG_ENOTCONV;
 }
 
+// D^{-1} v into the level-0 slot the V-cycle reads (a preconditioner input
+// other than the CG residual).
+void scale_dinv(const amg_batch* B, const double* v, hipStream_t s) {
+    const BLev& L0 = B->lev[0];
+    if (B->prec32) vc_scale_dinv<float>(B->n0, L0.dinv, v, static_cast<float*>(B->g0), s);
+    else vc_scale_dinv<double>(B->n0, L0.dinv, v, static_cast<double*>(B->g0), s);
+}
+
+// One BiCGStab iteration for the systems in `act`; pc selects the direction
+// pair and the (r, rbar) slots (they alternate together).
+void bicg_iteration(const amg_batch* B, int pc, hipStream_t s) {
+    const int cur = pc ? B_RHO1 : B_RHO0, nxt = pc ? B_RHO0 : B_RHO1;
+    const BLev& L0 = B->lev[0];
+    const BatchTab T = B->tab(B->act);
+    const double* p = B->pv[pc];
+    double* pn = B->pv[1 - pc];
+    scale_dinv(B, p, s);
+    vcycle(B, p, B->pt, s);
+    launch_bspmv_dot(B->nblk, T, L0.rp, L0.ci, L0.v, B->pt, B->q, B->rb, B->part, s);
+    finish(B, B->act, B_PQ, s);
+    launch_bbicg_s(B->nblk, T, B->r, B->q, B->sv, B->S, cur, B_PQ, s);
+    scale_dinv(B, B->sv, s);
+    vcycle(B, B->sv, B->st, s);
+    launch_bspmv_dot2(B->nblk, T, L0.rp, L0.ci, L0.v, B->st, B->t, B->sv, B->part, s);
+    launch_bfinish(B->nseg, B->seg_blk, B->act, B->part, B->S, B_TT, s);
+    launch_bfinish(B->nseg, B->seg_blk, B->act, B->part + B->nblk, B->S, B_TS, s);
+    launch_bbicg_update(B->nblk, T, B->x, B->r, B->pt, B->st, B->sv, B->t, B->rb, B->part, B->S, cur, B_PQ, B_TT,
+                        B_TS, s);
+    launch_bfinish(B->nseg, B->seg_blk, B->act, B->part, B->S, B_RR, s);
+    launch_bfinish(B->nseg, B->seg_blk, B->act, B->part + B->nblk, B->S, nxt, s);
+    launch_bbicg_dir(B->nblk, T, B->r, p, B->q, pn, B->S, cur, B_PQ, B_TT, B_TS, nxt, s);
+}
+
+// Algorithm 5 (right preconditioned, p_0 = r_0 = shadow residual) for every
+// system, with the stop rule, residual replacement and breakdown checks of
+// the single-system solver applied per system.
+void batch_bicgstab(amg_batch* B, double rtol, int maxit, hipStream_t s, amg_info* info) {
+    const int ns = B->nseg;
+    const BLev& L0 = B->lev[0];
+    if (!B->rb) {
+        const int n0 = B->n0;
+        B->rb = B->pool.get<double>(n0);
+        B->pt = B->pool.get<double>(n0);
+        B->sv = B->pool.get<double>(n0);
+        B->st = B->pool.get<double>(n0);
+        B->t = B->pool.get<double>(n0);
+    }
+    const double* S = B->S_host;
+    auto sv = [&](int i, int k) { return S[(size_t)i * kBatchSlots + k]; };
+    std::vector<double> nb(ns, 0.0);
+    std::vector<char> act(ns, 1), mark(ns, 0), zero(ns, 0);
+    for (int i = 0; i < ns; ++i) info[i] = amg_info{};
+    launch_bdot(B->nblk, B->tab(B->all), B->b, B->b, B->part, s);
+    finish(B, B->all, B_BB, s);
+    launch_bresidual(B->nblk, B->tab(B->all), L0.rp, L0.ci, L0.v, B->x, B->b, B->r, L0.dinv, B->g0, B->prec32,
+                     B->part, s);
+    finish(B, B->all, B_RR, s);
+    read_slots(B, s);
+    bool any_zero = false;
+    int live = 0;
+    for (int i = 0; i < ns; ++i) {
+        if (B->seg[i].status != AMG_OK) {
+            info[i].status = B->seg[i].status;
+            act[i] = 0;
+            continue;
+        }
+        nb[i] = std::sqrt(sv(i, B_BB));
+        if (nb[i] == 0.0) {
+            zero[i] = 1;
+            any_zero = true;
+            act[i] = 0;
+            continue;
+        }
+        const double rel = std::sqrt(sv(i, B_RR)) / nb[i];
+        info[i].rel_res = info[i].true_rel_res = rel;
+        if (rel <= rtol) act[i] = 0;
+        live += act[i];
+    }
+    if (any_zero) {
+        upload_mask(B, zero, B->mark, s);
+        launch_bzero(B->nblk, B->tab(B->mark), B->x, s);
+    }
+    upload_mask(B, act, B->act, s);
+    if (live == 0) return;
+    HIPCHK(hipMemcpyAsync(B->rb, B->r, sizeof(double) * B->n0, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(B->pv[0], B->r, sizeof(double) * B->n0, hipMemcpyDeviceToDevice, s));
+    launch_bdot(B->nblk, B->tab(B->act), B->r, B->rb, B->part, s);
+    finish(B, B->act, B_RHO0, s);
+    if (B->use_graphs && !B->bgraph[0]) {
+        for (int pc = 0; pc < 2; ++pc) B->bgraph[pc] = capture_graph(s, [&] { bicg_iteration(B, pc, s); });
+    }
+    int pc = 0;
+    for (int it = 1; it <= maxit && live > 0; ++it) {
+        const int cur = pc ? B_RHO1 : B_RHO0, nxt = pc ? B_RHO0 : B_RHO1;
+        if (B->use_graphs) HIPCHK(hipGraphLaunch(B->bgraph[pc], s));
+        else bicg_iteration(B, pc, s);
+        read_slots(B, s);
+        bool any_mark = false, changed = false;
+        std::vector<double> omega(ns, 0.0);
+        for (int i = 0; i < ns; ++i) {
+            if (!act[i]) continue;
+            const bool bad = !usable(sv(i, B_PQ)) || !usable(sv(i, cur)) || !std::isfinite(sv(i, B_TT)) ||
+                             !std::isfinite(sv(i, B_TS)) || sv(i, B_TT) == 0.0;
+            if (bad) {
+                info[i].status = AMG_EBREAKDOWN;
+                act[i] = 0;
+                changed = true;
+                continue;
+            }
+            omega[i] = sv(i, B_TS) / sv(i, B_TT);
+            info[i].iters = it;
+            const double rel = std::sqrt(sv(i, B_RR)) / nb[i];
+            info[i].rel_res = rel;
+            if (!std::isfinite(rel)) {
+                info[i].status = AMG_EBREAKDOWN;
+                act[i] = 0;
+                changed = true;
+                continue;
+            }
+            mark[i] = rel <= rtol || (B->period > 0 && it % B->period == 0);
+            any_mark |= mark[i] != 0;
+        }
+        if (any_mark) {  // recompute b - A x (residual replacement) for the marked systems
+            upload_mask(B, mark, B->mark, s);
+            launch_bresidual(B->nblk, B->tab(B->mark), L0.rp, L0.ci, L0.v, B->x, B->b, B->r, L0.dinv, B->g0,
+                             B->prec32, B->part, s);
+            finish(B, B->mark, B_TRR, s);
+            read_slots(B, s);
+            bool again = false;
+            for (int i = 0; i < ns; ++i) {
+                if (!mark[i]) continue;
+                const double tr = std::sqrt(sv(i, B_TRR)) / nb[i];
+                info[i].true_rel_res = tr;
+                if (tr <= rtol) {
+                    act[i] = 0;
+                    mark[i] = 0;
+                    changed = true;
+                } else {
+                    again = true;
+                }
+            }
+            if (again) {  // the next direction from the recomputed residual
+                upload_mask(B, mark, B->mark, s);
+                launch_bdot(B->nblk, B->tab(B->mark), B->r, B->rb, B->part, s);
+                finish(B, B->mark, nxt, s);
+                launch_bbicg_dir(B->nblk, B->tab(B->mark), B->r, B->pv[pc], B->q, B->pv[1 - pc], B->S, cur, B_PQ,
+                                 B_TT, B_TS, nxt, s);
+                read_slots(B, s);
+            }
+            std::fill(mark.begin(), mark.end(), 0);
+        }
+        for (int i = 0; i < ns; ++i) {
+            if (act[i] && (omega[i] == 0.0 || !usable(sv(i, nxt)))) {
+                info[i].status = AMG_EBREAKDOWN;
+                act[i] = 0;
+                changed = true;
+            }
+        }
+        live = 0;
+        for (int i = 0; i < ns; ++i) live += act[i];
+        if (changed && live > 0) upload_mask(B, act, B->act, s);
+        pc = 1 - pc;
+    }
+    for (int i = 0; i < ns; ++i)
+        if (act[i]) info[i].status = AMG_ENOTCONV;
+}
+
 template <class T>
 void build_dense(amg_batch* B, std::vector<char>& host, size_t at_dd, size_t at_dtab, const std::vector<size_t>& aoff) {
     BDense<T>* dd = reinterpret_cast<BDense<T>*>(host.data() + at_dd);
@@ -501,7 +673,7 @@ void create_impl(const std::vector<SegSrc>& src, bool prec32, double omega, int 
     int ndb = 0;
     for (int i = 0; i < ns; ++i) ndb += (B->seg[i].m + 63) / 64;
     B->ndblk = ndb;
-    B->part = P.get<double>(B->nblk);
+    B->part = P.get<double>(2 * (size_t)B->nblk);
     B->S = P.get<double>((size_t)ns * kBatchSlots);
     // copies that assemble the levels
     std::vector<GatherPiece> pcs;
@@ -656,11 +828,12 @@ void batch_autotune(amg_batch* B, hipStream_t caller, int32_t* out) {
         L.rb = pick;
         if (out) out[k] = pick;
     }
-    for (hipGraphExec_t& g : B->graph)  // re-captured with the new launch shapes
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
+    for (hipGraphExec_t* gs : {B->graph, B->bgraph})  // re-captured with the new launch shapes
+        for (int k = 0; k < 2; ++k)
+            if (gs[k]) {
+                (void)hipGraphExecDestroy(gs[k]);
+                gs[k] = nullptr;
+            }
     HIPCHK(hipStreamSynchronize(s));
 }
 
@@ -773,7 +946,8 @@ amg_status amg_batch_solve(amg_batch* B, int32_t method, const double* b, double
     amg_status st = AMG_OK;
     amg_status g = guarded([&] {
         if (!B || !b || !x || !info) raise(AMG_EINVAL, "amg_batch_solve: NULL argument");
-        if (method != 0) raise(AMG_EINVAL, "amg_batch_solve: only method 0 (PCG) is batched");
+        if (method != 0 && method != 1)
+            raise(AMG_EINVAL, "amg_batch_solve: method must be 0 (PCG) or 1 (BiCGStab)");
         if (!(rtol >= 0.0) || maxit < 0) raise(AMG_EINVAL, "amg_batch_solve: rtol must be >= 0 and maxit >= 0");
         hipStream_t caller = as_stream(stream);
         hipStream_t s = B->stream;
@@ -785,7 +959,8 @@ amg_status amg_batch_solve(amg_batch* B, int32_t method, const double* b, double
         launch_check_finite(B->n0, B->b, B->x, B->err, s);
         HIPCHK(hipGetLastError());
         if (read_int(B->err, s) & ERR_NONFINITE) raise(AMG_ENOTFINITE, "amg_batch_solve: b or x0 has NaN or Inf");
-        batch_pcg(B, rtol, maxit, s, info);
+        if (method == 0) batch_pcg(B, rtol, maxit, s, info);
+        else batch_bicgstab(B, rtol, maxit, s, info);
         HIPCHK(hipMemcpyAsync(x, B->x, sizeof(double) * B->n0, hipMemcpyDeviceToDevice, s));
         HIPCHK(hipStreamSynchronize(s));
         HIPCHK(hipEventRecord(B->ev[1], s));

@@ -273,6 +273,17 @@ void launch_bcg_update(int nblk, const BatchTab& T, double* x, double* r, const 
 void launch_bcg_dir(int nblk, const BatchTab& T, const double* z, const double* p, double* pn, const double* S,
                     int slot_new, int slot_old, hipStream_t s);
 void launch_bzero(int nblk, const BatchTab& T, double* x, hipStream_t s);
+// Algorithm 5 over a batch (two-sum kernels write their second partials at part + nblk).
+void launch_bbicg_s(int nblk, const BatchTab& T, const double* r, const double* v, double* sv, const double* S,
+                    int slot_rho, int slot_rv, hipStream_t s);
+void launch_bspmv_dot2(int nblk, const BatchTab& T, const int* rp, const int* ci, const double* v, const double* st,
+                       double* t, const double* sv, double* part, hipStream_t s);
+void launch_bbicg_update(int nblk, const BatchTab& T, double* x, double* r, const double* pt, const double* st,
+                         const double* sv, const double* t, const double* rb, double* part, const double* S,
+                         int slot_rho, int slot_rv, int slot_tt, int slot_ts, hipStream_t s);
+void launch_bbicg_dir(int nblk, const BatchTab& T, const double* r, const double* p, const double* v, double* pn,
+                      const double* S, int slot_rho, int slot_rv, int slot_tt, int slot_ts, int slot_rhonew,
+                      hipStream_t s);
 template <class T>
 void launch_bdense(int nblk, const BDense<T>* dd, const int2* tab, hipStream_t s);
 void launch_gather(int nblk, const GatherPiece* pcs, const int2* tab, hipStream_t s);

@@ -6,8 +6,9 @@
 // order while the footprints of the requests in flight fit the budget; a
 // request waits at the head of the queue until enough finish.
 //
-// Batched mode (batch >= 2): a worker takes the queued PCG requests with the
-// same stop settings (up to `batch`, within the budget) as one group, builds
+// Batched mode (batch >= 2): a worker takes the queued PCG (or BiCGStab)
+// requests with the same method and stop settings (up to `batch`, within the
+// budget) as one group, builds
 // their hierarchies together (amg_batch_setup) and solves them together
 // (amg_batch_solve); requests arriving meanwhile form the next group, on
 // the next free worker.
@@ -113,7 +114,8 @@ struct amg_server {
 
     // Worker i runs on wstreams[i].  It takes the request at the head of the
     // queue once its footprint fits; in batched mode it also takes the queued
-    // PCG requests with the same stop settings that still fit, up to `batch`.
+    // requests with the same Krylov method (PCG or BiCGStab) and stop settings
+    // that still fit, up to `batch`.
     void worker(int i) {
         if (hipSetDevice(device) != hipSuccess) return;
         hipStream_t s = wstreams[i];
@@ -134,10 +136,10 @@ struct amg_server {
                 grp.push_back(head);
                 in_use += head->foot;
                 ++active;
-                if (batched() && head->method == 0) {
+                if (batched() && head->method <= 1) {
                     for (auto it = pending.begin(); it != pending.end() && (int)grp.size() < cfg.batch;) {
                         Request* r = reqs[*it];
-                        if (r->method == 0 && r->rtol == head->rtol && r->maxit == head->maxit &&
+                        if (r->method == head->method && r->rtol == head->rtol && r->maxit == head->maxit &&
                             in_use + r->foot <= cfg.hbm_budget_bytes) {
                             grp.push_back(r);
                             in_use += r->foot;
@@ -149,7 +151,7 @@ struct amg_server {
                     }
                 }
             }
-            if (grp.size() == 1 && !(batched() && grp[0]->method == 0)) run_one(grp[0], s);
+            if (!(batched() && grp[0]->method <= 1)) run_one(grp[0], s);
             else run_group(grp, s, buf, cap);
             for (Request* r : grp) finish(r);
         }
@@ -217,7 +219,7 @@ struct amg_server {
             ok &= hipMemcpyAsync(X + off[i], grp[i]->x, bytes, hipMemcpyDeviceToDevice, s) == hipSuccess;
         }
         std::vector<amg_info> info(n);
-        if (ok) (void)amg_batch_solve(bt, 0, B, X, grp[0]->rtol, grp[0]->maxit, s, info.data());
+        if (ok) (void)amg_batch_solve(bt, grp[0]->method, B, X, grp[0]->rtol, grp[0]->maxit, s, info.data());
         for (int i = 0; i < n && ok; ++i) {
             const size_t bytes = sizeof(double) * (size_t)(off[i + 1] - off[i]);
             if (bytes == 0) continue;

@@ -135,6 +135,82 @@ __global__ __launch_bounds__(BS) void k_bcg_dir(BatchTab T, const double* __rest
     if (i < T.seg_end[bk.x]) pn[i] = z[i] + beta * p[i];
 }
 
+// Algorithm 5 over a batch.  s = r - alpha v, alpha = rho / (rbar, v)
+__global__ __launch_bounds__(BS) void k_bbicg_s(BatchTab T, const double* __restrict__ r,
+                                                const double* __restrict__ v, double* __restrict__ sv,
+                                                const double* __restrict__ S, int slot_rho, int slot_rv) {
+    const int2 bk = T.blk[blockIdx.x];
+    if (!T.mask[bk.x]) return;
+    const double alpha = slotv(S, bk.x, slot_rho) / slotv(S, bk.x, slot_rv);
+    const int i = bk.y + threadIdx.x;
+    if (i < T.seg_end[bk.x]) sv[i] = r[i] - alpha * v[i];
+}
+
+// t = A s; partials (t, t) at part[b] and (t, s) at part[nblk + b]
+__global__ __launch_bounds__(BS) void k_bspmv_dot2(BatchTab T, const int* __restrict__ rp, EntAx<double> ent,
+                                                   double* __restrict__ t, const double* __restrict__ sv,
+                                                   double* part) {
+    __shared__ double prod[kStreamChunk];
+    const int2 bk = T.blk[blockIdx.x];
+    double acc[2] = {0.0, 0.0};
+    if (T.mask[bk.x]) {  // uniform per block
+        const int end = T.seg_end[bk.x];
+        const double s = stream_rows<double>(bk.y, end, rp, ent, prod);
+        const int row = bk.y + threadIdx.x;
+        if (row < end) {
+            t[row] = s;
+            acc[0] = s * s;
+            acc[1] = s * sv[row];
+        }
+    }
+    block_partials<2, BS>(acc, part);
+}
+
+// x += alpha pt + omega st; r = s - omega t; partials (r, r) and (r, rbar).
+// A segment whose scalars are unusable keeps x and r.
+__global__ __launch_bounds__(BS) void k_bbicg_update(BatchTab T, double* __restrict__ x, double* __restrict__ r,
+                                                     const double* __restrict__ pt, const double* __restrict__ st,
+                                                     const double* __restrict__ sv, const double* __restrict__ t,
+                                                     const double* __restrict__ rb, double* part,
+                                                     const double* __restrict__ S, int slot_rho, int slot_rv,
+                                                     int slot_tt, int slot_ts) {
+    const int2 bk = T.blk[blockIdx.x];
+    double acc[2] = {0.0, 0.0};
+    if (T.mask[bk.x]) {
+        const double rho = slotv(S, bk.x, slot_rho), rv = slotv(S, bk.x, slot_rv);
+        const double tt = slotv(S, bk.x, slot_tt), ts = slotv(S, bk.x, slot_ts);
+        const bool ok = usable(rho) && usable(rv) && usable(tt) && isfinite(ts);
+        const double alpha = ok ? rho / rv : 0.0, omega = ok ? ts / tt : 0.0;
+        const int i = bk.y + threadIdx.x;
+        if (i < T.seg_end[bk.x]) {
+            double ri = r[i];
+            if (ok) {
+                x[i] = x[i] + alpha * pt[i] + omega * st[i];
+                ri = sv[i] - omega * t[i];
+                r[i] = ri;
+            }
+            acc[0] = ri * ri;
+            acc[1] = ri * rb[i];
+        }
+    }
+    block_partials<2, BS>(acc, part);
+}
+
+// p_new = r + beta (p - omega v), beta = (rho_new / rho) (alpha / omega)
+__global__ __launch_bounds__(BS) void k_bbicg_dir(BatchTab T, const double* __restrict__ r,
+                                                  const double* __restrict__ p, const double* __restrict__ v,
+                                                  double* __restrict__ pn, const double* __restrict__ S, int slot_rho,
+                                                  int slot_rv, int slot_tt, int slot_ts, int slot_rhonew) {
+    const int2 bk = T.blk[blockIdx.x];
+    if (!T.mask[bk.x]) return;
+    const int g = bk.x;
+    const double alpha = slotv(S, g, slot_rho) / slotv(S, g, slot_rv);
+    const double omega = slotv(S, g, slot_ts) / slotv(S, g, slot_tt);
+    const double beta = (slotv(S, g, slot_rhonew) / slotv(S, g, slot_rho)) * (alpha / omega);
+    const int i = bk.y + threadIdx.x;
+    if (i < T.seg_end[g]) pn[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
 __global__ __launch_bounds__(BS) void k_bzero(BatchTab T, double* __restrict__ x) {
     const int2 bk = T.blk[blockIdx.x];
     if (!T.mask[bk.x]) return;
@@ -252,6 +328,30 @@ void launch_bcg_update(int nblk, const BatchTab& T, double* x, double* r, const 
 void launch_bcg_dir(int nblk, const BatchTab& T, const double* z, const double* p, double* pn, const double* S,
                     int slot_new, int slot_old, hipStream_t s) {
     hipLaunchKernelGGL(k_bcg_dir, dim3(nblk), dim3(BS), 0, s, T, z, p, pn, S, slot_new, slot_old);
+}
+
+void launch_bbicg_s(int nblk, const BatchTab& T, const double* r, const double* v, double* sv, const double* S,
+                    int slot_rho, int slot_rv, hipStream_t s) {
+    hipLaunchKernelGGL(k_bbicg_s, dim3(nblk), dim3(BS), 0, s, T, r, v, sv, S, slot_rho, slot_rv);
+}
+
+void launch_bspmv_dot2(int nblk, const BatchTab& T, const int* rp, const int* ci, const double* v, const double* st,
+                       double* t, const double* sv, double* part, hipStream_t s) {
+    hipLaunchKernelGGL(k_bspmv_dot2, dim3(nblk), dim3(BS), 0, s, T, rp, EntAx<double>{v, ci, st}, t, sv, part);
+}
+
+void launch_bbicg_update(int nblk, const BatchTab& T, double* x, double* r, const double* pt, const double* st,
+                         const double* sv, const double* t, const double* rb, double* part, const double* S,
+                         int slot_rho, int slot_rv, int slot_tt, int slot_ts, hipStream_t s) {
+    hipLaunchKernelGGL(k_bbicg_update, dim3(nblk), dim3(BS), 0, s, T, x, r, pt, st, sv, t, rb, part, S, slot_rho,
+                       slot_rv, slot_tt, slot_ts);
+}
+
+void launch_bbicg_dir(int nblk, const BatchTab& T, const double* r, const double* p, const double* v, double* pn,
+                      const double* S, int slot_rho, int slot_rv, int slot_tt, int slot_ts, int slot_rhonew,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_bbicg_dir, dim3(nblk), dim3(BS), 0, s, T, r, p, v, pn, S, slot_rho, slot_rv, slot_tt,
+                       slot_ts, slot_rhonew);
 }
 
 void launch_bzero(int nblk, const BatchTab& T, double* x, hipStream_t s) {

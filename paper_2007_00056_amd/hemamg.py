@@ -411,13 +411,14 @@ class Batch:
     def __exit__(self, *exc):
         self.close()
 
-    def solve(self, rhs, x=None, rtol: float = 1e-8, maxit: int = 1000, stream=None):
+    def solve(self, rhs, x=None, rtol: float = 1e-8, maxit: int = 1000, stream=None, method: str = "pcg"):
         """rhs, x: device float64 vectors of offsets[-1] rows (systems one after
         another).  Returns (x, list of per-system summaries)."""
         import torch
 
         x = torch.zeros_like(rhs) if x is None else x
-        return x, amg_batch_solve(self.b, PCG, rhs, x, rtol, maxit, self.count, stream)
+        m = {"pcg": PCG, "bicgstab": BICGSTAB}[method]
+        return x, amg_batch_solve(self.b, m, rhs, x, rtol, maxit, self.count, stream)
 
     def autotune(self, stream=None) -> list:
         return amg_batch_autotune(self.b, stream)

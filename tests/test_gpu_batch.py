@@ -169,7 +169,7 @@ def test_batch_argument_checks(torch):
             assert e.value.status == hemamg.AMG_EINVAL
         with hemamg.Batch([g64]) as bt:
             rhs = torch.ones(a.n, dtype=torch.float64, device="cuda")
-            st = hemamg.lib().amg_batch_solve(bt.b, hemamg.BICGSTAB, rhs.data_ptr(), rhs.data_ptr(), 1e-8, 10,
+            st = hemamg.lib().amg_batch_solve(bt.b, hemamg.STATIONARY, rhs.data_ptr(), rhs.data_ptr(), 1e-8, 10,
                                               hemamg._stream_ptr(None), (hemamg.amg_info * 1)())
             assert st == hemamg.AMG_EINVAL
 
@@ -302,3 +302,72 @@ def test_batched_setup_stall_and_depths(torch):
             np.testing.assert_array_equal(bits(xh[off[i]:off[i + 1]]), bits(xs[i]), err_msg=f"system {i}")
     finally:
         bt.close()
+
+
+def nonsym_mix():
+    """Nonsymmetric systems of several sizes: upwind convection-diffusion and
+    random patterns with unsymmetric values."""
+    out = [P.convdiff3d(m) for m in (7, 11, 16, 24)]
+    out.append(P.random_symmetric_pattern(400, 0.015, 4, weights=(1, 2, 3), nonsym_values=True))
+    for a in out[-1:]:  # diagonally dominant so that the method converges
+        d = a.to_scipy()
+        import scipy.sparse as sp
+        rows = np.abs(d).sum(axis=1).A.ravel()
+        a2 = (d + sp.diags(rows + 1.0)).tocsr()
+        a2.sort_indices()
+        out[-1] = P.CSR(a2.shape[0], a2.indptr.astype(np.int32), a2.indices.astype(np.int32), a2.data)
+    return out
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_batched_bicgstab_follows_the_oracle_and_is_composition_independent(torch, fp32):
+    systems = nonsym_mix()
+    seeds = [20 + i for i in range(len(systems))]
+    params = hemamg.amg_params_default(precond_fp32=fp32)
+    hs, bt, rhs = make_batch(torch, systems, params, seeds)
+    try:
+        x, infos = bt.solve(rhs, rtol=1e-8, maxit=500, method="bicgstab")
+        off = bt.offsets
+        xh = x.cpu().numpy()
+    finally:
+        bt.close()
+        for h in hs:
+            h.close()
+    for i, (a, inf) in enumerate(zip(systems, infos)):
+        say("system", i, "n", a.n, inf)
+        assert inf["status"] == hemamg.AMG_OK
+        b = P.rhs_uniform(a.n, seeds[i])
+        xi = xh[off[i]:off[i + 1]]
+        assert np.linalg.norm(b - a.to_scipy() @ xi) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-6)
+        xo, io = oracle.Hierarchy(a).solve(b, method="bicgstab", rtol=1e-8, maxit=500)
+        tol = max(2, int(0.05 * io["iters"])) if fp32 else 1
+        assert abs(inf["iters"] - io["iters"]) <= tol, (inf, io)
+        # alone (a batch of one, from the batched setup) gives the same bits
+        bt1 = hemamg.Batch.setup([hemamg.DeviceCSR.from_host(a)], params)
+        try:
+            x1, i1 = bt1.solve(torch.from_numpy(b).cuda(), rtol=1e-8, maxit=500, method="bicgstab")
+        finally:
+            bt1.close()
+        assert i1[0]["iters"] == inf["iters"]
+        np.testing.assert_array_equal(bits(x1.cpu().numpy()), bits(xi))
+
+
+def test_batched_bicgstab_equal_iterations_match_the_oracle(torch):
+    systems = nonsym_mix()
+    seeds = [30 + i for i in range(len(systems))]
+    K = 6
+    hs, bt, rhs = make_batch(torch, systems, hemamg.amg_params_default(), seeds)
+    try:
+        x, infos = bt.solve(rhs, rtol=0.0, maxit=K, method="bicgstab")
+        off = bt.offsets
+        xh = x.cpu().numpy()
+    finally:
+        bt.close()
+        for h in hs:
+            h.close()
+    for i, a in enumerate(systems):
+        assert infos[i]["iters"] == K and infos[i]["status"] == hemamg.AMG_ENOTCONV
+        xo, io = oracle.Hierarchy(a).solve(P.rhs_uniform(a.n, seeds[i]), method="bicgstab", rtol=0.0, maxit=K)
+        err = rel(xh[off[i]:off[i + 1]], xo)
+        say("system", i, "rel err", err)
+        assert err <= 1e-9

@@ -158,19 +158,19 @@ def test_destroy_drains_queued_requests(torch, batch):
         np.testing.assert_array_equal(bits(x.cpu().numpy()), bits(ref))
 
 
-def batch_of_one(torch, a, seed, params, rtol):
+def batch_of_one(torch, a, seed, params, rtol, method="pcg"):
     with hemamg.Hierarchy(hemamg.DeviceCSR.from_host(a), params) as g, hemamg.Batch([g]) as bt:
         b = torch.from_numpy(P.rhs_uniform(a.n, seed)).cuda()
-        x, info = bt.solve(b, rtol=rtol, maxit=500)
+        x, info = bt.solve(b, rtol=rtol, maxit=500, method=method)
     return x.cpu().numpy(), info[0]
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
 @pytest.mark.parametrize("workers,batch", [(1, 2), (4, 8), (3, 64)])
 def test_batched_serving_results_same_as_alone(torch, fp32, workers, batch):
-    """Batched mode: PCG requests are solved in batches of whatever is ready;
-    each result is bit-identical to the same system batched alone.  The
-    BiCGStab request is solved by its worker as in the plain mode."""
+    """Batched mode: requests are set up and solved in groups of whatever is
+    queued (PCG and BiCGStab requests in separate groups); each result is
+    bit-identical to the same system batched alone."""
     say("workers", workers, "batch", batch, "fp32", fp32)
     rtol = 1e-8
     cfg = hemamg.amg_server_config_default(workers=workers, batch=batch)
@@ -192,10 +192,7 @@ def test_batched_serving_results_same_as_alone(torch, fp32, workers, batch):
         hemamg.amg_server_destroy(srv)
     for (a, seed, method), (t, A, b, x), r in zip(items, live, res):
         assert r["status"] == hemamg.AMG_OK, r
-        if method == "pcg":
-            xa, ia = batch_of_one(torch, a, seed, params, rtol)
-        else:
-            xa, ia = alone(torch, a, seed, method, params, rtol)
+        xa, ia = batch_of_one(torch, a, seed, params, rtol, method)
         assert r["iters"] == ia["iters"], (r, ia)
         np.testing.assert_array_equal(bits(x.cpu().numpy()), bits(xa), err_msg=f"n={a.n}")
 
