@@ -36,7 +36,8 @@ def measured_traffic(kernel: str, workload: str, precond: str):
     and workload, if it was taken on the current kernel source (else None)."""
     path = os.path.join(PROFILES, f"{kernel}_{workload}_{precond}_traffic.txt")
     try:
-        kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
+        # "key: value" lines; keys may hold a colon themselves, values do not
+        kv = dict(line.rsplit(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}

@@ -282,6 +282,13 @@ amg_status amg_batch_rows(const amg_batch* b, int32_t* offsets);
 amg_status amg_batch_solve(amg_batch* bt, int32_t method, const double* b, double* x, double rtol, int32_t maxit,
                            void* stream, amg_info* info);
 
+/* Iterations are replayed from HIP graphs captured at the first solve of each
+ * method (on by default).  While a capture lasts, device-wide calls from other
+ * threads of the process (hipDeviceSynchronize, allocations) fail with
+ * hipErrorStreamCaptureUnsupported, so multi-threaded callers turn graphs off
+ * (on = 0); results are the same either way. */
+amg_status amg_batch_set_graphs(amg_batch* b, int32_t on);
+
 /* Number of concatenated levels of a batch (its deepest system's). */
 amg_status amg_batch_levels(const amg_batch* b, int32_t* levels);
 

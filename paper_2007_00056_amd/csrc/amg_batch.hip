@@ -989,6 +989,13 @@ amg_status amg_batch_autotune(amg_batch* b, void* stream, int32_t* schedule) {
     });
 }
 
+amg_status amg_batch_set_graphs(amg_batch* b, int32_t on) {
+    return guarded([&] {
+        if (!b) raise(AMG_EINVAL, "amg_batch_set_graphs: NULL batch");
+        b->use_graphs = on != 0;
+    });
+}
+
 amg_status amg_batch_levels(const amg_batch* b, int32_t* levels) {
     return guarded([&] {
         if (!b || !levels) raise(AMG_EINVAL, "amg_batch_levels: NULL argument");

@@ -195,6 +195,9 @@ struct amg_server {
             for (Request* r : grp) run_one(r, s);
             return;
         }
+        // no graph capture on a worker: it would make device-wide calls of the
+        // other workers and of the caller's threads fail while it lasts
+        (void)amg_batch_set_graphs(bt, 0);
         std::vector<int32_t> off(n + 1);
         (void)amg_batch_rows(bt, off.data());
         const size_t need = 2 * (size_t)off[n] * sizeof(double);

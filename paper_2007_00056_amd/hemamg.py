@@ -27,7 +27,7 @@ EXPORTED = ["amg_params_default", "amg_setup", "amg_destroy", "amg_vcycle", "kry
             "amg_last_error", "amg_footprint_bytes", "amg_server_config_default", "amg_server_create",
             "amg_server_submit", "amg_server_wait", "amg_server_destroy", "amg_batch_create", "amg_batch_rows",
             "amg_batch_solve", "amg_batch_destroy", "amg_batch_levels", "amg_batch_autotune", "amg_autotune",
-            "amg_batch_setup"]
+            "amg_batch_setup", "amg_batch_set_graphs"]
 
 
 class amg_csr(C.Structure):
@@ -90,6 +90,7 @@ def lib():
             "amg_server_destroy": [vp],
             "amg_batch_create": [C.POINTER(vp), i32, vp, C.POINTER(vp)],
             "amg_batch_setup": [C.POINTER(amg_csr), i32, C.POINTER(amg_params), vp, C.POINTER(vp), vp],
+            "amg_batch_set_graphs": [vp, i32],
             "amg_batch_rows": [vp, vp],
             "amg_batch_solve": [vp, i32, vp, vp, f64, i32, vp, vp],
             "amg_batch_destroy": [vp],
@@ -422,3 +423,6 @@ class Batch:
 
     def autotune(self, stream=None) -> list:
         return amg_batch_autotune(self.b, stream)
+
+    def set_graphs(self, on: bool) -> None:
+        _check(lib().amg_batch_set_graphs(self.b, int(on)))
