@@ -261,9 +261,20 @@ void run_rounds(SetupWork& W, HemWork& w, int n, hipStream_t s, Launch&& launch_
     }
 }
 
+// Systems of a batched setup inside the operator of a pass: seg = device table
+// of (first row, rows) in the pass's numbering.  Systems up to the LDS limit
+// are matched one workgroup each; the round kernels run only for larger ones.
+struct SegPass {
+    const int2* seg = nullptr;
+    int nseg = 0;
+    bool all_small = false;
+    int* sl[2] = {nullptr, nullptr};  // list space, a row per vertex each
+};
+
 // from_last: the pass starts from the last index (run on the mirrored matrix,
 // its pairs mapped back before numbering).
-Pass hem_pass(const Csr& Bin, SetupWork& W, int t, hipStream_t s, int* err, bool from_last) {
+Pass hem_pass(const Csr& Bin, SetupWork& W, int t, hipStream_t s, int* err, bool from_last,
+              const SegPass* sp = nullptr) {
     const int n = Bin.n;
     Csr B = Bin;
     HemWork w = W.hw;
@@ -285,7 +296,12 @@ Pass hem_pass(const Csr& Bin, SetupWork& W, int t, hipStream_t s, int* err, bool
         run_rounds(W, w, n, s, [&](int r) { launch_ehem_round(r, n, B.rp, B.ci, w, s); });
     } else {
         launch_hem_init(n, B.rp, B.ci, B.v, w, s);
-        if (n <= W.hem_small) {
+        if (sp) {
+            launch_hem_lds_seg(sp->nseg, sp->seg, B.rp, B.ci, B.v, w, sp->sl[0], sp->sl[1], s);
+            HIPCHK(hipGetLastError());
+            if (!sp->all_small)
+                run_rounds(W, w, n, s, [&](int r) { launch_hem_round(r, n, B.rp, B.ci, B.v, w, s); });
+        } else if (n <= W.hem_small) {
             launch_hem_all(n, B.rp, B.ci, B.v, w, s);
             HIPCHK(hipGetLastError());
         } else {
@@ -1241,6 +1257,13 @@ void batch_coarsen(const amg_csr* A, int count, const amg_params& p, hipStream_t
     int* starts = P.get<int>(2 * (size_t)count);
     int* offs_d = P.get<int>((size_t)count);
     std::vector<int> hs(2 * (size_t)count + 2), ho((size_t)count);
+    // node-based passes match each system of at most the LDS limit in a
+    // workgroup of its own (its rounds run concurrently with the others')
+    const bool seg_ok = p.hem == 0;
+    int2* seg_d[2] = {P.get<int2>((size_t)count), P.get<int2>((size_t)count)};
+    int* sl0 = seg_ok ? wpool.get<int>((size_t)N) : nullptr;
+    int* sl1 = seg_ok ? wpool.get<int>((size_t)N) : nullptr;
+    std::vector<int2> hseg((size_t)count);
     for (int k = 0; !live.empty(); ++k) {
         std::vector<char> want(live.size(), 0);
         bool any = false;
@@ -1260,13 +1283,35 @@ void batch_coarsen(const amg_csr* A, int count, const amg_params& p, hipStream_t
             break;
         }
         const int g0 = k * p.passes_per_level;
-        Pass p1 = hem_pass(M, SW, 0, s, gerr, p.alternate && (g0 & 1));
+        const int m = (int)live.size();
+        for (int j = 0; j < m; ++j) ho[j] = live[j].off;
+        HIPCHK(hipMemcpyAsync(offs_d, ho.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+        const bool fl1 = p.alternate && (g0 & 1), fl2 = p.alternate && ((g0 + 1) & 1);
+        SegPass sp1, sp2;
+        if (seg_ok) {
+            int big = 0;
+            for (int j = 0; j < m; ++j) {
+                const Live& L = live[j];
+                hseg[j] = fl1 ? make_int2(M.n - L.off - L.n, L.n) : make_int2(L.off, L.n);
+                big = std::max(big, L.n);
+            }
+            HIPCHK(hipMemcpyAsync(seg_d[0], hseg.data(), sizeof(int2) * m, hipMemcpyHostToDevice, s));
+            sp1.seg = seg_d[0];
+            sp1.nseg = m;
+            sp1.all_small = big <= SW.hw.lds_rows;  // a system's later passes are smaller
+            sp1.sl[0] = sl0;
+            sp1.sl[1] = sl1;
+            sp2 = sp1;
+            sp2.seg = seg_d[1];
+        }
+        Pass p1 = hem_pass(M, SW, 0, s, gerr, fl1, seg_ok ? &sp1 : nullptr);
         Csr C1 = galerkin(M, p1, SW, P, s, gerr);
         Csr Cf = C1;
         int* agg = P.get<int>((size_t)M.n);
         int4* mem = nullptr;
         if (p.passes_per_level == 2) {
-            Pass p2 = hem_pass(C1, SW, 1, s, gerr, p.alternate && ((g0 + 1) & 1));
+            if (seg_ok) launch_seg_table(m, offs_d, p1.agg, C1.n, fl2, seg_d[1], s);
+            Pass p2 = hem_pass(C1, SW, 1, s, gerr, fl2, seg_ok ? &sp2 : nullptr);
             Cf = galerkin(C1, p2, SW, P, s, gerr);
             launch_compose(M.n, p1.agg, p2.agg, agg, s);
             mem = P.get<int4>((size_t)Cf.n);
@@ -1277,9 +1322,6 @@ void batch_coarsen(const amg_csr* A, int count, const amg_params& p, hipStream_t
             launch_members(Cf.n, nullptr, nullptr, p1.lead, p1.mate, mem, s);
         }
         // where each system starts in the coarse level
-        const int m = (int)live.size();
-        for (int j = 0; j < m; ++j) ho[j] = live[j].off;
-        HIPCHK(hipMemcpyAsync(offs_d, ho.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
         launch_seg_starts(m, offs_d, agg, Cf.rp, starts, s);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(hs.data(), starts, sizeof(int) * 2 * m, hipMemcpyDeviceToHost, s));

@@ -63,6 +63,14 @@ void launch_hem_init(int n, const int* rp, const int* ci, const double* v, HemWo
 void launch_hem_round(int round, int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
 // All rounds in one single-workgroup launch (small n).
 void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
+// Block-diagonal operators: seg[j] = (first row, rows) of system j; systems of
+// at most kHemLdsRows rows are matched one workgroup each and marked decided
+// (stamp -1) for the round kernels.  sl0/sl1: global list space, n rows each.
+void launch_hem_lds_seg(int nseg, const int2* seg, const int* rp, const int* ci, const double* v, HemWork& w,
+                        int* sl0, int* sl1, hipStream_t s);
+// seg[j] for the operator of the next pass: system j starts at agg[off[j]]
+// (n rows in all; mirror numbers the operator backwards).
+void launch_seg_table(int m, const int* off, const int* agg, int n, bool mirror, int2* seg, hipStream_t s);
 // Edge-based matching (Algorithm 3): initialisation (every vertex dirty, the
 // count in cnt[0]; w.lcnt serves as the per-round marks) and one round (two
 // launches).  w.cnt must be zeroed before the initialisation.

@@ -45,6 +45,8 @@ struct Request {
     amg_info info{};
 };
 
+constexpr int32_t kSmallRows = 32768;  // systems matched in one workgroup by a batched setup
+
 uint64_t footprint(int32_t n, int64_t nnz, const amg_params& p) {
     const uint64_t N = (uint64_t)(n > 0 ? n : 0), Z = (uint64_t)(nnz > 0 ? nnz : 0);
     const uint64_t e = p.precond_fp32 ? 4 : 8;
@@ -137,9 +139,14 @@ struct amg_server {
                 in_use += head->foot;
                 ++active;
                 if (batched() && head->method <= 1) {
+                    // systems that fit one workgroup's matching state are grouped
+                    // apart from larger ones: a group of small systems then needs
+                    // no round kernels at all
+                    const bool small = head->A.n <= kSmallRows;
                     for (auto it = pending.begin(); it != pending.end() && (int)grp.size() < cfg.batch;) {
                         Request* r = reqs[*it];
-                        if (r->method == head->method && r->rtol == head->rtol && r->maxit == head->maxit &&
+                        if ((r->A.n <= kSmallRows) == small && r->method == head->method && r->rtol == head->rtol &&
+                            r->maxit == head->maxit &&
                             in_use + r->foot <= cfg.hbm_budget_bytes) {
                             grp.push_back(r);
                             in_use += r->foot;

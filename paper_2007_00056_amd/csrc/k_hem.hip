@@ -161,12 +161,15 @@ struct GlobalSt {
 // The same in LDS: 16-bit stamps (0xffff = undecided) and 16-bit counters
 // packed two to a word.  A counter is only decremented while positive, so
 // the subtraction never borrows from its neighbour.
+// Vertices off .. off+n-1 are held at LDS index (vertex - off).
 struct LdsSt {
     uint16_t* dec;
     unsigned* lcnt2;
-    __device__ __forceinline__ int get(int i) const { return dec[i]; }
-    __device__ __forceinline__ void set(int i, int r) const { dec[i] = (uint16_t)r; }
+    int off;
+    __device__ __forceinline__ int get(int i) const { return dec[i - off]; }
+    __device__ __forceinline__ void set(int i, int r) const { dec[i - off] = (uint16_t)r; }
     __device__ __forceinline__ int drop(int y) const {
+        y -= off;
         const unsigned sh = 16u * (unsigned)(y & 1);
         const unsigned old = atomicSub(&lcnt2[y >> 1], 1u << sh);
         return (int)((old >> sh) & 0xffffu);
@@ -174,7 +177,7 @@ struct LdsSt {
 };
 
 // Appends to the next worklist through a block-local LDS list of element
-// type E; entries that do not fit go to a global list.
+// type E (holding vertex - off); entries that do not fit go to a global list.
 template <class E>
 struct Appender {
     E* s_list;
@@ -182,9 +185,10 @@ struct Appender {
     int cap;
     int* gout;
     int* gcnt;
+    int off = 0;
     __device__ __forceinline__ void push(int x) const {
         const int p = atomicAdd(s_cnt, 1);
-        if (p < cap) s_list[p] = (E)x;
+        if (p < cap) s_list[p] = (E)(x - off);
         else gout[atomicAdd(gcnt, 1)] = x;
     }
 };
@@ -565,11 +569,14 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_all(int n, HemState S, int* dec
 }
 
 // Small passes (n <= kHemLdsRows): one workgroup with the round stamps, the
-// ready counters and the worklists in LDS.  A list is its LDS part followed
-// by a global part for entries beyond the LDS capacity.
+// ready counters and the worklists in LDS, for the vertices off .. off+n-1
+// (no edge leaves the range).  A list is its LDS part followed by a global
+// part for entries beyond the LDS capacity.  The first list is the kg0
+// entries of gin, or with scan the vertices whose counter is zero.  Returns
+// the rounds run; *left is nonzero when the round bound was hit.
 template <int SIDE>
-__global__ __launch_bounds__(HEM_BS1) void k_hem_lds(int n, HemState S, const int* __restrict__ lcnt_g, int* wl0,
-                                                     int* wl1, int* cnt) {
+__device__ int hem_lds_body(int off, int n, const HemState& S, const int* __restrict__ lcnt_g, int* gin,
+                            int* gout, int kg0, bool scan, int* left) {
     __shared__ uint16_t s_dec[kHemLdsRows];
     __shared__ unsigned s_lcnt2[kHemLdsRows / 2];
     __shared__ uint16_t s_la[HL_LCAP], s_lb[HL_LCAP];
@@ -577,17 +584,28 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_lds(int n, HemState S, const in
     __shared__ int s_cnt, s_gnext, s_nw;
     for (int i = threadIdx.x; i < n; i += HEM_BS1) s_dec[i] = 0xffff;
     for (int i = threadIdx.x; 2 * i < n; i += HEM_BS1) {
-        const unsigned lo = (unsigned)lcnt_g[2 * i];
-        const unsigned hi = 2 * i + 1 < n ? (unsigned)lcnt_g[2 * i + 1] : 0u;
+        const unsigned lo = (unsigned)lcnt_g[off + 2 * i];
+        const unsigned hi = 2 * i + 1 < n ? (unsigned)lcnt_g[off + 2 * i + 1] : 0u;
         s_lcnt2[i] = lo | (hi << 16);
     }
+    if (threadIdx.x == 0) {
+        s_cnt = 0;
+        s_gnext = 0;
+    }
     __syncthreads();
-    const LdsSt st{s_dec, s_lcnt2};
+    const LdsSt st{s_dec, s_lcnt2, off};
     uint16_t* cur = s_la;
     uint16_t* nxt = s_lb;
-    int* gin = wl0;
-    int* gout = wl1;
-    int kl = 0, kg = cnt[0];  // the initial list is all in global memory
+    int kl = 0, kg = kg0;
+    if (scan) {  // the first list: vertices with no lower edge-neighbour
+        const Appender<uint16_t> A{cur, &s_cnt, HL_LCAP, gin, &s_gnext, off};
+        for (int i = threadIdx.x; i < n; i += HEM_BS1)
+            if (lcnt_g[off + i] == 0) A.push(off + i);
+        __syncthreads();
+        kl = min(s_cnt, HL_LCAP);
+        kg = s_gnext;
+        __syncthreads();
+    }
     int r = 0;
     for (; r <= n + 1; ++r) {
         const int m = kl + kg;
@@ -598,13 +616,13 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_lds(int n, HemState S, const in
             s_nw = 0;
         }
         __syncthreads();
-        const Appender<uint16_t> A{nxt, &s_cnt, HL_LCAP, gout, &s_gnext};
+        const Appender<uint16_t> A{nxt, &s_cnt, HL_LCAP, gout, &s_gnext, off};
         const uint16_t* c = cur;
         const int* g = gin;
         const int klc = kl;
         hem_round_body<LdsSt, SIDE, HEM_BS1>(
-            S, st, r, m, threadIdx.x, HEM_BS1, [&](int i) { return i < klc ? (int)c[i] : g[i - klc]; }, A, s_wave,
-            &s_nw, HL_WCAP);
+            S, st, r, m, threadIdx.x, HEM_BS1, [&](int i) { return i < klc ? (int)c[i] + off : g[i - klc]; }, A,
+            s_wave, &s_nw, HL_WCAP);
         kl = min(s_cnt, HL_LCAP);
         kg = s_gnext;
         __syncthreads();  // every thread has read the counts before the next reset
@@ -615,9 +633,41 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_lds(int n, HemState S, const in
         gin = gout;
         gout = tg;
     }
+    *left = kl + kg;
+    return r;
+}
+
+template <int SIDE>
+__global__ __launch_bounds__(HEM_BS1) void k_hem_lds(int n, HemState S, const int* __restrict__ lcnt_g, int* wl0,
+                                                     int* wl1, int* cnt) {
+    int left = 0;
+    const int r = hem_lds_body<SIDE>(0, n, S, lcnt_g, wl0, wl1, cnt[0], false, &left);
     if (threadIdx.x == 0) {
         cnt[6] = r;
-        if (kl + kg != 0) cnt[7] = 1;
+        if (left != 0) cnt[7] = 1;
+    }
+}
+
+// Systems stored one after another (a block-diagonal operator): block b
+// matches system seg[b] = (first vertex, rows) with the LDS-state rounds when
+// it has at most kHemLdsRows rows (larger ones are left to the other
+// drivers), then marks its vertices as decided before round 0 in the global
+// stamps so that those drivers skip them.  Global list space: the system's
+// own rows of sl0 and sl1.
+template <int SIDE>
+__global__ __launch_bounds__(HEM_BS1) void k_hem_lds_seg(const int2* __restrict__ seg, HemState S,
+                                                         const int* __restrict__ lcnt_g, int* __restrict__ dec_g,
+                                                         int* sl0, int* sl1, int* cnt) {
+    const int2 sg = seg[blockIdx.x];
+    const int off = sg.x, n = sg.y;
+    if (n <= 0 || n > kHemLdsRows) return;  // uniform
+    int left = 0;
+    const int r = hem_lds_body<SIDE>(off, n, S, lcnt_g, sl0 + off, sl1 + off, 0, true, &left);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += HEM_BS1) dec_g[off + i] = -1;
+    if (threadIdx.x == 0) {
+        atomicMax(&cnt[6], r);
+        if (left != 0) atomicOr(&cnt[7], 1);
     }
 }
 
@@ -809,6 +859,32 @@ void launch_hem_round(int r, int n, const int* rp, const int* ci, const double* 
                        w.wl[(r + 1) & 1], w.cnt, r % 3, (r + 1) % 3, (r + 2) % 3)
     AMG_HEM_SIDE(w.side, CALL)
 #undef CALL
+}
+
+void launch_hem_lds_seg(int nseg, const int2* seg, const int* rp, const int* ci, const double* v, HemWork& w,
+                        int* sl0, int* sl1, hipStream_t s) {
+    if (nseg <= 0) return;
+    const HemState S{rp, ci, v, w.lowok, w.rec, w.mate};
+#define CALL(SD)                                                                                                 \
+    hipLaunchKernelGGL(k_hem_lds_seg<SD>, dim3(nseg), dim3(HEM_BS1), 0, s, seg, S, w.lcnt, w.dec, sl0, sl1, w.cnt)
+    AMG_HEM_SIDE(w.side, CALL)
+#undef CALL
+}
+
+// Rows of system j of a pass from the previous pass's aggregate map: the
+// systems start at rows off[j] of the previous operator, so in this one at
+// agg[off[j]]; with mirror the operator is numbered backwards (n rows).
+__global__ __launch_bounds__(BS) void k_seg_table(int m, const int* __restrict__ off, const int* __restrict__ agg,
+                                                  int n, int mirror, int2* __restrict__ seg) {
+    const int j = blockIdx.x * BS + threadIdx.x;
+    if (j >= m) return;
+    const int a = off[j] >= 0 ? agg[off[j]] : 0;
+    const int b = j + 1 < m ? agg[off[j + 1]] : n;
+    seg[j] = mirror ? make_int2(n - b, b - a) : make_int2(a, b - a);
+}
+
+void launch_seg_table(int m, const int* off, const int* agg, int n, bool mirror, int2* seg, hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_table, dim3(blocks_for(m)), dim3(BS), 0, s, m, off, agg, n, mirror ? 1 : 0, seg);
 }
 
 void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {
