@@ -371,3 +371,30 @@ def test_batched_bicgstab_equal_iterations_match_the_oracle(torch):
         err = rel(xh[off[i]:off[i + 1]], xo)
         say("system", i, "rel err", err)
         assert err <= 1e-9
+
+
+def test_batched_setup_at_served_sizes(torch):
+    """A group as the server forms it from the served stream: 96^3 (the
+    largest side) with smaller lognormal systems, float preconditioner; the
+    batched setup and solve equal the separate hierarchies' batch bit for
+    bit, and every system meets the tolerance."""
+    sides = [96, 16, 41, 23, 64, 18, 30, 55]
+    systems = [P.lognormal_diffusion3d(m, 2000 + m, 1.0) for m in sides]
+    seeds = [2000 + m for m in sides]
+    params = hemamg.amg_params_default(precond_fp32=1)
+    xs, infos = separate(torch, systems, params, seeds)
+    bt, devs = setup_batch(torch, systems, params, seeds)
+    try:
+        assert bt.status == [hemamg.AMG_OK] * len(systems)
+        off = bt.offsets
+        rhs = torch.from_numpy(np.concatenate([P.rhs_uniform(a.n, s) for a, s in zip(systems, seeds)])).cuda()
+        x, inf2 = bt.solve(rhs, rtol=1e-8, maxit=1000)
+        xh = x.cpu().numpy()
+        for i, a in enumerate(systems):
+            say("side", sides[i], inf2[i])
+            assert inf2[i]["status"] == hemamg.AMG_OK and inf2[i]["iters"] == infos[i]["iters"]
+            np.testing.assert_array_equal(bits(xh[off[i]:off[i + 1]]), bits(xs[i]), err_msg=f"side {sides[i]}")
+            b = P.rhs_uniform(a.n, seeds[i])
+            assert np.linalg.norm(b - a.to_scipy() @ xh[off[i]:off[i + 1]]) <= 1e-8 * np.linalg.norm(b) * 1.000001
+    finally:
+        bt.close()
