@@ -33,11 +33,13 @@ def rel(a, b):
 
 
 def mix():
-    """SPD systems of several sizes and hierarchy depths (a ragged mix)."""
+    """SPD systems of several sizes and hierarchy depths (a ragged mix), one with
+    many tied weights and explicit zeros."""
     out = [P.lognormal_diffusion3d(m, 1000 + m, 1.0) for m in (5, 9, 16, 23, 12, 31)]
     out.append(P.poisson3d(21, 17, 13))
     out.append(P.poisson2d(40))
     out.append(P.vardiff3d(14, seed=2, corr_len=3.0))
+    out.append(P.random_symmetric_pattern(300, 0.02, 3, weights=(1, 2), explicit_zeros=0.1))
     return out
 
 
@@ -225,7 +227,8 @@ def setup_batch(torch, systems, params, seeds):
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(precond_fp32=1), dict(alternate=1), dict(hem=1),
-                                dict(passes_per_level=1, max_coarse_rows=16)])
+                                dict(passes_per_level=1, max_coarse_rows=16),
+                                dict(passes_per_level=1, alternate=1, max_coarse_rows=16)])
 def test_batched_setup_equals_separate_setups(torch, kw):
     """Building the hierarchies together (block-diagonal concatenations, one
     matching round for all) gives every system the hierarchy amg_setup
