@@ -40,7 +40,6 @@ int current_device() {
 // Pinned host blocks of 4 KiB for the Krylov scalar slots of a handle, kept
 // in a free list for the process (pinned allocation and release are slow).
 namespace {
-constexpr size_t kPinnedBlock = 4096;
 std::mutex g_pinned_mu;
 std::vector<void*> g_pinned_free;
 }  // namespace

@@ -114,6 +114,7 @@ struct amg_batch {
     double* S_host = nullptr;  // pinned [nseg * kBatchSlots]
     int* mask_host = nullptr;  // pinned [nseg]
     void* pinned = nullptr;
+    bool pinned_pooled = false;  // a block of the process-wide pinned pool
     bool use_graphs = true;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipStream_t stream = nullptr;
@@ -130,7 +131,10 @@ struct amg_batch {
         if (stream) (void)hipStreamSynchronize(stream);
         pool.release();
         if (stream) (void)hipStreamSynchronize(stream);
-        if (pinned) (void)hipHostFree(pinned);
+        if (pinned) {
+            if (pinned_pooled) amg::pinned_put(pinned);
+            else (void)hipHostFree(pinned);
+        }
         for (hipEvent_t e : ev)
             if (e) amg::event_put(e, false);
         if (stream) amg::stream_put(stream);
@@ -765,9 +769,15 @@ void create_impl(const std::vector<SegSrc>& src, bool prec32, double omega, int 
     launch_gather((int)gtab.size(), reinterpret_cast<const GatherPiece*>(dev + at_pcs),
                   reinterpret_cast<const int2*>(dev + at_gtab), s);
     HIPCHK(hipGetLastError());
-    // pinned host memory for the scalars and masks
+    // pinned host memory for the scalars and masks: a block of the pinned
+    // pool when it fits (pinned allocation costs about a millisecond)
     const size_t pin = sizeof(double) * kBatchSlots * ns + sizeof(int) * ns;
-    HIPCHK(hipHostMalloc(&B->pinned, pin, hipHostMallocDefault));
+    if (pin <= kPinnedBlock) {
+        B->pinned = pinned_get();
+        B->pinned_pooled = true;
+    } else {
+        HIPCHK(hipHostMalloc(&B->pinned, pin, hipHostMallocDefault));
+    }
     B->S_host = static_cast<double*>(B->pinned);
     B->mask_host = reinterpret_cast<int*>(B->S_host + (size_t)kBatchSlots * ns);
     if (const char* e = getenv("HEMAMG_BATCH_GRAPHS")) B->use_graphs = atoi(e) != 0;

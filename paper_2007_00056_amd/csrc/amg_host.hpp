@@ -51,7 +51,9 @@ hipStream_t stream_get();
 void stream_put(hipStream_t s);
 hipEvent_t event_get(bool timing);
 void event_put(hipEvent_t e, bool timing);
-// Pinned host blocks of 4 KiB (scalar slots of a handle), kept for reuse.
+// Pinned host blocks of kPinnedBlock bytes (scalar slots of a handle or a
+// batch), kept for reuse.
+constexpr size_t kPinnedBlock = 4096;
 void* pinned_get();
 void pinned_put(void* p);
 // Pinned host words for small read-backs (per thread, kept for the process).
