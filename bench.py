@@ -250,8 +250,8 @@ def main():
     ap.add_argument("--rates", type=lambda t: [float(v) for v in t.split(",")], default=[0.5, 1.0, 2.0])
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is single-GPU and "
-              "a multi-GPU run is not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver runs on one "
+              "GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch

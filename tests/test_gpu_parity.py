@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Bars (stated by the method's specification of this build):
+Bars for the HIP path against the oracle:
   * aggregate maps and every coarse level (row_ptr, col_idx and the bits of
     every value) are bit-identical: both sides run the same deterministic
     matching and sum each Galerkin entry in the same fixed order;
