@@ -177,6 +177,7 @@ struct SetupWork {
     int* hc = nullptr;  // pinned: worklist sizes read back between batches
     hipEvent_t ev[2]{};
     int hem_small = 65536;  // passes on at most this many rows run in one workgroup
+    bool tile_strict = false;  // a tiled pass past its time limit is an error (tests), not repeated
 
     bool edge = false;  // edge-based matching (Algorithm 3)
     int* mrp = nullptr;  // mirrored matrix of a pass from the last index
@@ -221,6 +222,9 @@ struct SetupWork {
         if (const char* e = getenv("HEMAMG_HEM_SMALL")) hem_small = atoi(e);  // tuning sweeps
         if (const char* e = getenv("HEMAMG_HEM_GRID")) hw.round_grid = atoi(e) > 0 ? atoi(e) : 96;
         if (const char* e = getenv("HEMAMG_HEM_LDS")) hw.lds_rows = atoi(e) < kHemLdsRows ? atoi(e) : kHemLdsRows;
+        if (const char* e = getenv("HEMAMG_TILE_STRICT")) tile_strict = atoi(e) != 0;
+        if (const char* e = getenv("HEMAMG_HEM_TILE"))  // rows per tile; 0: no tiled passes
+            hw.tile_rows = atoi(e) <= 0 ? 0 : (atoi(e) < kHemTileRows ? atoi(e) : kHemTileRows);
     }
     ~SetupWork() {
         event_put(ev[0], false);
@@ -260,6 +264,35 @@ void run_rounds(SetupWork& W, HemWork& w, int n, hipStream_t s, Launch&& launch_
     }
 }
 
+// Time limit of a tiled pass in wall-clock ticks (250 ms; a pass of a few
+// million rows takes a few milliseconds).
+long long tile_timeout_ticks() {
+    thread_local int dev = -1;
+    thread_local long long ticks = 0;
+    int d = 0;
+    HIPCHK(hipGetDevice(&d));
+    if (d != dev) {
+        int khz = 0;
+        HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d));
+        ticks = (long long)(khz > 0 ? khz : 100000) * 250;
+        dev = d;
+    }
+    return ticks;
+}
+
+bool tiled(const HemWork& w, int n) {
+    return w.tile_rows > 0 && ((int64_t)n + w.tile_rows - 1) / w.tile_rows <= kHemMaxTiles;
+}
+
+// A tiled pass; false when it did not finish (the caller repeats the pass).
+bool run_tiles(SetupWork& W, HemWork& w, const Csr& B, hipStream_t s) {
+    launch_hem_tile(B.n, B.rp, B.ci, B.v, w, tile_timeout_ticks(), s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&W.hc[2], w.cnt + 7, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return W.hc[2] == 0;
+}
+
 // Systems of a batched setup inside the operator of a pass: seg = device table
 // of (first row, rows) in the pass's numbering.  Systems up to the LDS limit
 // are matched one workgroup each; the round kernels run only for larger ones.
@@ -287,25 +320,38 @@ Pass hem_pass(const Csr& Bin, SetupWork& W, int t, hipStream_t s, int* err, bool
     }
     // record side from the average row length, within the record buffer
     const double avg = n > 0 ? (double)B.nnz / n : 0.0;
-    w.side = avg <= 9.0 ? 7 : (avg <= 20.0 || n <= W.hem_small ? 15 : 31);  // one-workgroup passes: at most 15
+    // workgroup-wide drivers (one workgroup, tiles) take records of at most 15
+    w.side = avg <= 9.0 ? 7 : (avg <= 20.0 || n <= W.hem_small || tiled(w, n) ? 15 : 31);
     while (w.side > 7 && (size_t)(w.side + 1) * 8 * (size_t)n > w.rec_bytes) w.side = (w.side + 1) / 2 - 1;
     HIPCHK(hipMemsetAsync(w.cnt, 0, 8 * sizeof(int), s));
     if (W.edge) {
         launch_ehem_init(n, B.rp, B.ci, B.v, w, s);
         run_rounds(W, w, n, s, [&](int r) { launch_ehem_round(r, n, B.rp, B.ci, w, s); });
     } else {
-        launch_hem_init(n, B.rp, B.ci, B.v, w, s);
-        if (sp) {
-            launch_hem_lds_seg(sp->nseg, sp->seg, B.rp, B.ci, B.v, w, sp->sl[0], sp->sl[1], s);
+        // small passes: one workgroup with LDS state; larger ones: tiles, else
+        // one workgroup with global state or one launch per round
+        auto start = [&] {
+            launch_hem_init(n, B.rp, B.ci, B.v, w, s);
+            if (sp) launch_hem_lds_seg(sp->nseg, sp->seg, B.rp, B.ci, B.v, w, sp->sl[0], sp->sl[1], s);
             HIPCHK(hipGetLastError());
-            if (!sp->all_small)
-                run_rounds(W, w, n, s, [&](int r) { launch_hem_round(r, n, B.rp, B.ci, B.v, w, s); });
-        } else if (n <= W.hem_small) {
+        };
+        auto rounds = [&] { run_rounds(W, w, n, s, [&](int r) { launch_hem_round(r, n, B.rp, B.ci, B.v, w, s); }); };
+        start();
+        if (sp ? sp->all_small : n <= W.hem_small && n <= w.lds_rows) {
+            if (!sp) launch_hem_all(n, B.rp, B.ci, B.v, w, s);
+        } else if (tiled(w, n)) {
+            if (!run_tiles(W, w, B, s)) {  // past its time limit: repeat with the round kernels
+                if (W.tile_strict) raise(AMG_EHIP, "tiled matching pass did not finish in time");
+                HIPCHK(hipMemsetAsync(w.cnt, 0, 8 * sizeof(int), s));
+                start();
+                rounds();
+            }
+        } else if (!sp && n <= W.hem_small) {
             launch_hem_all(n, B.rp, B.ci, B.v, w, s);
-            HIPCHK(hipGetLastError());
         } else {
-            run_rounds(W, w, n, s, [&](int r) { launch_hem_round(r, n, B.rp, B.ci, B.v, w, s); });
+            rounds();
         }
+        HIPCHK(hipGetLastError());
     }
     if (from_last) {
         launch_unmirror_mate(n, w.mate, W.mate[t], s);

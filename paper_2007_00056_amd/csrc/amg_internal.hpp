@@ -33,6 +33,8 @@ void launch_dinv(int n, const int* rp, const int* ci, const double* v, double* d
 // rows instead.
 constexpr int kRecOverflow = 1 << 16;
 constexpr int kHemLdsRows = 32768;  // passes up to this size keep their matching state in LDS
+constexpr int kHemTileRows = 16384;  // largest tile of a tiled pass (its state in LDS)
+constexpr int kHemMaxTiles = 4096;   // tiled passes up to this many tiles
 template <int SIDE>
 struct alignas(4 * (SIDE + 1) * 2) HemRecT {
     int hdr;  // #higher | #lower << 8 | kRecOverflow
@@ -54,6 +56,7 @@ struct HemWork {
     int* cnt;         // [8] worklist size ring, symmetry check, round count, guard
     int* err;
     int round_grid = 96;  // blocks of a one-launch-per-round pass
+    int tile_rows = kHemTileRows;  // rows per tile of a tiled pass (0: no tiled passes)
     int lds_rows = kHemLdsRows;  // one-workgroup passes up to this size keep their state in LDS
     double* wsym = nullptr;  // edge-based matching: [nnz] heavier of |a_uv|, |a_vu| (0 on the diagonal)
     int* ptr = nullptr;      // edge-based matching: [n] best undecided neighbour
@@ -63,6 +66,13 @@ void launch_hem_init(int n, const int* rp, const int* ci, const double* v, HemWo
 void launch_hem_round(int round, int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
 // All rounds in one single-workgroup launch (small n).
 void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s);
+// Tiled pass: one workgroup per w.tile_rows rows, all rounds in one launch
+// (after launch_hem_init and, for block-diagonal operators, launch_hem_lds_seg;
+// w.side 7 or 15).
+// cnt[7] != 0 afterwards: the pass did not finish within tmo wall-clock ticks
+// (or a counter exceeded 16 bits) and must be repeated with the round kernels.
+void launch_hem_tile(int n, const int* rp, const int* ci, const double* v, HemWork& w, long long tmo,
+                     hipStream_t s);
 // Block-diagonal operators: seg[j] = (first row, rows) of system j; systems of
 // at most kHemLdsRows rows are matched one workgroup each and marked decided
 // (stamp -1) for the round kernels.  sl0/sl1: global list space, n rows each.

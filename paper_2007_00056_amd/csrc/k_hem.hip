@@ -672,6 +672,311 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_lds_seg(const int2* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Tiled passes: the vertices are cut into tiles of T consecutive indices, one
+// workgroup per tile, all in one launch.  A workgroup keeps its tile's round
+// stamps, ready counters and worklists in LDS and runs rounds of its own, as
+// the LDS-state driver does, while the other tiles run theirs.  A decision on
+// a vertex u reads only u's neighbours and the states of its target's lower
+// edge-neighbours below u, so a tile waits only on lower tiles, and the
+// matching is the same greedy matching whatever the timing.
+//
+// Vertices with lower edge-neighbours in lower tiles ("exposed") start
+// "pending": they count as undecided, but their own tile may neither match
+// them nor let them choose until all those neighbours are decided.  A lower
+// tile may take a pending vertex; the taker publishes the target's state in
+// dec_g before its own (release).  Whoever next needs a pending vertex y (y
+// itself once ready, or a vertex that wants y as its target) reads dec_g of
+// y's lower-tile edge-neighbours; when all are decided it reads dec_g[y]
+// after an acquire fence, which tells whether y was taken, and settles y with
+// one compare-and-swap on its LDS stamp.  A vertex that wants a target in a
+// higher tile re-reads the target after the same fence, once the target's
+// lower edge-neighbours below it read decided.  Any other stale read of dec_g
+// only makes a vertex wait for a later round.
+//
+// A workgroup that runs past its time limit sets cnt[7] and stops; the host
+// then repeats the pass with the round kernels.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kTileUnd = 0x7fffffff;   // LDS stamp: undecided
+constexpr int kTilePend = 0x7ffffffe;  // LDS stamp: exposed, not settled yet
+constexpr int kExposed = 1 << 20;      // lcnt flag set by k_hem_tile_prep
+constexpr int kPublished = 1;          // dec_g of a vertex decided in the pass
+constexpr int TL_LCAP = 4096;          // LDS worklist entries per list
+
+struct TileSt {
+    int* sdec;        // LDS stamps of the tile
+    unsigned* lcnt2;  // LDS ready counters, two 16-bit counters a word
+    int off, m;       // the tile: vertices off .. off+m-1
+    int* dec_g;
+    __device__ __forceinline__ bool mine(int i) const { return (unsigned)(i - off) < (unsigned)m; }
+    __device__ __forceinline__ bool gdone(int i) const {
+        return __hip_atomic_load(&dec_g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kUndecided;
+    }
+    __device__ __forceinline__ int get(int i) const { return mine(i) ? sdec[i - off] : (gdone(i) ? -1 : INT_MAX); }
+    __device__ __forceinline__ int drop(int y) const {  // count before the decrement
+        y -= off;
+        const unsigned sh = 16u * (unsigned)(y & 1);
+        const unsigned old = atomicSub(&lcnt2[y >> 1], 1u << sh);
+        return (int)((old >> sh) & 0xffffu);
+    }
+};
+
+__device__ __forceinline__ void publish(int* dec_g, int v, bool release) {
+    if (release)
+        __hip_atomic_store(&dec_g[v], kPublished, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        __hip_atomic_store(&dec_g[v], kPublished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// x is decided: its higher neighbours in the tile lose an undecided lower
+// neighbour (higher tiles read dec_g instead).
+template <int SIDE, class Ap>
+__device__ __forceinline__ void tile_release(const HemState& S, const TileSt& st, const HemRecT<SIDE>& R, int x,
+                                             const Ap& A) {
+    if (R.hdr & kRecOverflow) {
+        for (int e = S.rp[x]; e < S.rp[x + 1]; ++e) {
+            const int y = S.ci[e];
+            if (y > x && st.mine(y) && S.v[e] != 0.0 && st.drop(y) == 1) A.push(y);
+        }
+        return;
+    }
+    const int nh = R.hdr & 255;
+    int old[SIDE];
+#pragma unroll
+    for (int t = 0; t < SIDE; ++t) old[t] = t < nh && st.mine(R.h[t]) ? st.drop(R.h[t]) : 0;
+#pragma unroll
+    for (int t = 0; t < SIDE; ++t)
+        if (t < nh && old[t] == 1) A.push(R.h[t]);
+}
+
+enum { kUnsettled = 0, kFree = 1, kGone = 2 };
+
+// Settles the pending vertex y (record Ry): kFree when y is now an ordinary
+// undecided vertex, kGone when it is decided (taken by a lower tile, or
+// matched in this round), kUnsettled while a lower-tile edge-neighbour is
+// undecided.  A vertex found taken is stamped r - 1 (unavailable at once),
+// counted and released by the thread that settles it.
+template <int SIDE, class Ap>
+__device__ __forceinline__ int tile_settle(const HemState& S, const TileSt& st, const HemRecT<SIDE>& Ry, int y, int r,
+                                           const Ap& A, int* s_ndec) {
+    bool open = false;
+    if (Ry.hdr & kRecOverflow) {
+        for (int e = S.rp[y]; e < S.rp[y + 1] && !open; ++e) {
+            const int x = S.ci[e];
+            if (x >= st.off) break;  // columns ascend
+            if (S.lowok[e] && !st.gdone(x)) open = true;
+        }
+    } else {
+        const int nl = (Ry.hdr >> 8) & 255;
+        bool d[SIDE];
+#pragma unroll
+        for (int t = 0; t < SIDE; ++t) d[t] = t < nl && Ry.l[t] < st.off ? st.gdone(Ry.l[t]) : true;
+#pragma unroll
+        for (int t = 0; t < SIDE; ++t) open |= !d[t];
+    }
+    if (open) return kUnsettled;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const bool taken = st.gdone(y);
+    const int old = atomicCAS(&st.sdec[y - st.off], kTilePend, taken ? r - 1 : kTileUnd);
+    if (old == kTilePend) {
+        if (!taken) return kFree;
+        atomicAdd(s_ndec, 1);
+        tile_release<SIDE>(S, st, Ry, y, A);
+        return kGone;
+    }
+    return old == kTileUnd ? kFree : kGone;
+}
+
+// Round r for a ready vertex u of the tile (the visit of hem_visit, with the
+// cross-tile rules above).
+template <int SIDE, class Ap>
+__device__ __forceinline__ void tile_visit(const HemState& S, const TileSt& st, int r, int u, const Ap& A,
+                                           int* s_ndec) {
+    const HemRecT<SIDE>* __restrict__ recs = static_cast<const HemRecT<SIDE>*>(S.rec);
+    const HemRecT<SIDE> R = recs[u];
+    const int su = st.sdec[u - st.off];
+    if (su < r) return;  // decided earlier (as a match target): stale entry
+    if (su == kTilePend) {
+        const int k = tile_settle<SIDE>(S, st, R, u, r, A, s_ndec);
+        if (k == kUnsettled) A.push(u);
+        if (k != kFree) return;
+    }
+    int best = -1;
+    if (R.hdr & kRecOverflow) {
+        best = hem_best(S, st, r, u, S.rp[u], S.rp[u + 1]);
+    } else {
+        const int nh = R.hdr & 255;
+        int d[SIDE];
+#pragma unroll
+        for (int t = 0; t < SIDE; ++t) d[t] = t < nh ? st.get(R.h[t]) : -1;
+#pragma unroll
+        for (int t = SIDE - 1; t >= 0; --t)
+            if (t < nh && d[t] >= r) best = R.h[t];
+    }
+    if (best < 0) {  // no undecided neighbour: unaggregated singleton
+        st.sdec[u - st.off] = r;
+        S.mate[u] = -1;
+        publish(st.dec_g, u, false);
+        atomicAdd(s_ndec, 1);
+        tile_release<SIDE>(S, st, R, u, A);
+        return;
+    }
+    const HemRecT<SIDE> B = recs[best];
+    int back = -1;
+    if (B.hdr & kRecOverflow) {
+        back = hem_back(S, st, r, best);
+    } else {
+        const int nl = (B.hdr >> 8) & 255;
+        int d[SIDE];
+#pragma unroll
+        for (int t = 0; t < SIDE; ++t) d[t] = t < nl ? st.get(B.l[t]) : -1;
+#pragma unroll
+        for (int t = SIDE - 1; t >= 0; --t)
+            if (t < nl && d[t] >= r) back = B.l[t];
+    }
+    if (back != u) {
+        A.push(u);  // still ready, retry next round
+        return;
+    }
+    if (st.mine(best)) {
+        if (st.sdec[best - st.off] == kTilePend && tile_settle<SIDE>(S, st, B, best, r, A, s_ndec) != kFree) {
+            A.push(u);
+            return;
+        }
+        st.sdec[u - st.off] = r;
+        st.sdec[best - st.off] = r;
+        S.mate[u] = best;
+        S.mate[best] = u;
+        publish(st.dec_g, best, false);
+        publish(st.dec_g, u, false);
+        atomicAdd(s_ndec, 2);
+        tile_release<SIDE>(S, st, R, u, A);
+        tile_release<SIDE>(S, st, B, best, A);
+        return;
+    }
+    // best lies in a higher tile: re-read it after the reads of its lower
+    // edge-neighbours, then publish it before u
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (st.gdone(best)) {
+        A.push(u);
+        return;
+    }
+    st.sdec[u - st.off] = r;
+    S.mate[u] = best;
+    S.mate[best] = u;
+    publish(st.dec_g, best, false);
+    publish(st.dec_g, u, true);
+    atomicAdd(s_ndec, 1);
+    tile_release<SIDE>(S, st, R, u, A);
+}
+}  // namespace
+
+// Per vertex: the LDS ready counter (lcnt: undecided lower edge-neighbours in
+// its own tile) and kExposed when it has lower edge-neighbours in lower
+// tiles.  After k_hem_init.  A counter beyond 16 bits sets cnt[7] (the pass
+// then runs the round kernels).
+__global__ __launch_bounds__(BS) void k_hem_tile_prep(int n, int T, const int* __restrict__ rp,
+                                                      const int* __restrict__ ci, const uint8_t* __restrict__ lowok,
+                                                      int* __restrict__ lcnt, int* cnt) {
+    const int y = blockIdx.x * BS + threadIdx.x;
+    if (y >= n) return;
+    const int t0 = (y / T) * T;
+    int cross = 0;
+    for (int k = rp[y]; k < rp[y + 1]; ++k) {
+        if (ci[k] >= t0) break;  // columns ascend
+        cross += lowok[k];
+    }
+    const int c = lcnt[y] - cross;
+    if (c > 0xffff) atomicOr(&cnt[7], 2);
+    lcnt[y] = c | (cross > 0 ? kExposed : 0);
+}
+
+// One workgroup per tile.  gl0/gl1: global list space (the tile's rows of
+// each); tmo: time limit in wall-clock ticks.
+template <int SIDE>
+__global__ __launch_bounds__(HEM_BS1) void k_hem_tile(int n, int T, HemState S, int* dec_g,
+                                                      const int* __restrict__ lcnt_g, int* gl0, int* gl1, int* cnt,
+                                                      long long tmo) {
+    __shared__ int s_dec[kHemTileRows];
+    __shared__ unsigned s_lcnt2[kHemTileRows / 2];
+    __shared__ uint16_t s_la[TL_LCAP], s_lb[TL_LCAP];
+    __shared__ int s_cnt, s_gnext, s_ndec, s_stop;
+    const long long t_start = wall_clock64();
+    if (cnt[7] & 2) return;  // a counter beyond 16 bits: the host repeats the pass with rounds
+    const int off = blockIdx.x * T;
+    const int m = min(T, n - off);
+    if (threadIdx.x == 0) {
+        s_cnt = 0;
+        s_gnext = 0;
+        s_ndec = 0;
+        s_stop = 0;
+    }
+    __syncthreads();
+    // Vertices decided before the pass (stamp -1: systems of another driver)
+    // count as done; lower tiles may already publish others (kPublished).
+    int pre = 0;
+    for (int i = threadIdx.x; i < m; i += HEM_BS1) {
+        const bool done = dec_g[off + i] == -1;
+        pre += done;
+        s_dec[i] = done ? -1 : ((lcnt_g[off + i] & kExposed) ? kTilePend : kTileUnd);
+    }
+    for (int i = threadIdx.x; 2 * i < m; i += HEM_BS1) {
+        const unsigned lo = (unsigned)lcnt_g[off + 2 * i] & 0xffffu;
+        const unsigned hi = 2 * i + 1 < m ? (unsigned)lcnt_g[off + 2 * i + 1] & 0xffffu : 0u;
+        s_lcnt2[i] = lo | (hi << 16);
+    }
+    if (pre) atomicAdd(&s_ndec, pre);
+    __syncthreads();
+    const TileSt st{s_dec, s_lcnt2, off, m, dec_g};
+    int* gin = gl0 + off;
+    int* gout = gl1 + off;
+    uint16_t* cur = s_la;
+    uint16_t* nxt = s_lb;
+    int kl, kg;
+    {  // the first list: undecided vertices without undecided lower neighbours in the tile
+        const Appender<uint16_t> A{cur, &s_cnt, TL_LCAP, gin, &s_gnext, off};
+        for (int i = threadIdx.x; i < m; i += HEM_BS1)
+            if (s_dec[i] != -1 && (lcnt_g[off + i] & 0xffff) == 0) A.push(off + i);
+        __syncthreads();
+        kl = min(s_cnt, TL_LCAP);
+        kg = s_gnext;
+        __syncthreads();
+    }
+    int r = 1;  // stamps r - 1 >= 0 mark vertices found taken
+    bool stop = s_ndec >= m;
+    while (!stop) {
+        if (threadIdx.x == 0) {
+            s_cnt = 0;
+            s_gnext = 0;
+        }
+        __syncthreads();
+        const Appender<uint16_t> A{nxt, &s_cnt, TL_LCAP, gout, &s_gnext, off};
+        const int klc = kl;
+        for (int idx = threadIdx.x; idx < kl + kg; idx += HEM_BS1) {
+            const int u = idx < klc ? (int)cur[idx] + off : gin[idx - klc];
+            tile_visit<SIDE>(S, st, r, u, A, &s_ndec);
+        }
+        if (threadIdx.x == 0 && wall_clock64() - t_start > tmo) s_stop = 1;
+        __syncthreads();
+        kl = min(s_cnt, TL_LCAP);
+        kg = s_gnext;
+        stop = s_ndec >= m || s_stop != 0;
+        __syncthreads();  // every thread has read the counts before the next reset
+        uint16_t* t = cur;
+        cur = nxt;
+        nxt = t;
+        int* tg = gin;
+        gin = gout;
+        gout = tg;
+        ++r;
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(&cnt[6], r - 1);
+        if (s_ndec < m) atomicOr(&cnt[7], 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Edge-based matching (Algorithm 3): the greedy matching over undirected
 // edges {u, v} in increasing key (-W_uv, min(u,v), max(u,v)), where W_uv is
 // the heavier of |a_uv| and |a_vu| (the first occurrence of the pair in the
@@ -885,6 +1190,20 @@ __global__ __launch_bounds__(BS) void k_seg_table(int m, const int* __restrict__
 
 void launch_seg_table(int m, const int* off, const int* agg, int n, bool mirror, int2* seg, hipStream_t s) {
     hipLaunchKernelGGL(k_seg_table, dim3(blocks_for(m)), dim3(BS), 0, s, m, off, agg, n, mirror ? 1 : 0, seg);
+}
+
+void launch_hem_tile(int n, const int* rp, const int* ci, const double* v, HemWork& w, long long tmo,
+                     hipStream_t s) {
+    const int T = w.tile_rows;
+    const int nt = (n + T - 1) / T;
+    hipLaunchKernelGGL(k_hem_tile_prep, dim3(blocks_for(n)), dim3(BS), 0, s, n, T, rp, ci, w.lowok, w.lcnt, w.cnt);
+    const HemState S{rp, ci, v, w.lowok, w.rec, w.mate};
+#define CALL(SD)                                                                                               \
+    hipLaunchKernelGGL(k_hem_tile<SD>, dim3(nt), dim3(HEM_BS1), 0, s, n, T, S, w.dec, w.lcnt, w.wl[0], w.wl[1], \
+                       w.cnt, tmo)
+    if (w.side == 7) CALL(7);
+    else CALL(15);  // records of tiled passes hold at most 15 entries a side
+#undef CALL
 }
 
 void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWork& w, hipStream_t s) {

@@ -88,9 +88,14 @@ def test_hierarchy_bit_identical(torch, name):
 
 
 DRIVERS = {
-    "launch_per_round": {"HEMAMG_HEM_SMALL": "0"},
-    "one_workgroup_global_state": {"HEMAMG_HEM_LDS": "0"},
-    "launch_per_round_small_grid": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_GRID": "3"},
+    "launch_per_round": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_TILE": "0"},
+    "one_workgroup_global_state": {"HEMAMG_HEM_LDS": "0", "HEMAMG_HEM_TILE": "0"},
+    "launch_per_round_small_grid": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_GRID": "3", "HEMAMG_HEM_TILE": "0"},
+    # tiled passes with tiles far smaller than the systems: many cross-tile
+    # edges, messages and takes; 37 rows leave a ragged last tile
+    "tiles_64": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_TILE": "64", "HEMAMG_TILE_STRICT": "1"},
+    "tiles_37": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_TILE": "37", "HEMAMG_TILE_STRICT": "1"},
+    "tiles_1": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_TILE": "1", "HEMAMG_TILE_STRICT": "1"},
 }
 
 
