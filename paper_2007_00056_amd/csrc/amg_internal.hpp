@@ -33,7 +33,7 @@ void launch_dinv(int n, const int* rp, const int* ci, const double* v, double* d
 // rows instead.
 constexpr int kRecOverflow = 1 << 16;
 constexpr int kHemLdsRows = 32768;  // passes up to this size keep their matching state in LDS
-constexpr int kHemTileRows = 16384;  // largest tile of a tiled pass (its state in LDS)
+constexpr int kHemTileRows = 32768;  // largest tile of a tiled pass (its state in LDS)
 constexpr int kHemMaxTiles = 4096;   // tiled passes up to this many tiles
 template <int SIDE>
 struct alignas(4 * (SIDE + 1) * 2) HemRecT {

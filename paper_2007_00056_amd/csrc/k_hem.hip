@@ -680,53 +680,54 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_lds_seg(const int2* __restrict_
 // edge-neighbours below u, so a tile waits only on lower tiles, and the
 // matching is the same greedy matching whatever the timing.
 //
-// Vertices with lower edge-neighbours in lower tiles ("exposed") start
-// "pending": they count as undecided, but their own tile may neither match
-// them nor let them choose until all those neighbours are decided.  A lower
-// tile may take a pending vertex; the taker publishes the target's state in
-// dec_g before its own (release).  Whoever next needs a pending vertex y (y
-// itself once ready, or a vertex that wants y as its target) reads dec_g of
-// y's lower-tile edge-neighbours; when all are decided it reads dec_g[y]
-// after an acquire fence, which tells whether y was taken, and settles y with
-// one compare-and-swap on its LDS stamp.  A vertex that wants a target in a
-// higher tile re-reads the target after the same fence, once the target's
-// lower edge-neighbours below it read decided.  Any other stale read of dec_g
-// only makes a vertex wait for a later round.
-//
+// dec_g[v] publishes each decision to the other tiles in one word: partner
+// + 2, or 1 for a singleton (kUndecided before).  A vertex can only be taken
+// by one of its lower edge-neighbours, so a reader learns whether y is taken
+// from y's lower edge-neighbours' words alone; no read has to be ordered
+// after another, and a stale word only makes a vertex wait for a later round.
+//  * Vertices with lower edge-neighbours in lower tiles ("exposed") start
+//    "pending": they count as undecided, but their own tile may neither match
+//    them nor let them choose until those neighbours are all decided.  Then
+//    the words tell whether one of them took the vertex, and one
+//    compare-and-swap on its LDS stamp settles it (free, or taken: stamped
+//    decided, counted and released by the thread that settles it).
+//  * A vertex u whose target lies in a higher tile takes it once the target's
+//    lower edge-neighbours below u read decided and none of them names it.
+//    The thread waits for its own stores before the round ends, so later
+//    rounds of the tile read the target's word as taken.
 // A workgroup that runs past its time limit sets cnt[7] and stops; the host
 // then repeats the pass with the round kernels.
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int kTileUnd = 0x7fffffff;   // LDS stamp: undecided
-constexpr int kTilePend = 0x7ffffffe;  // LDS stamp: exposed, not settled yet
+constexpr int kTileUnd = 0xffff;       // LDS stamp: undecided
+constexpr int kTilePend = 0xfffe;      // LDS stamp: exposed, not settled yet
+constexpr int kTileMaxRound = 0xfff0;  // rounds stop below the two stamps above
 constexpr int kExposed = 1 << 20;      // lcnt flag set by k_hem_tile_prep
-constexpr int kPublished = 1;          // dec_g of a vertex decided in the pass
 constexpr int TL_LCAP = 4096;          // LDS worklist entries per list
 
 struct TileSt {
-    int* sdec;        // LDS stamps of the tile
+    uint16_t* sdec;   // LDS stamps of the tile
     unsigned* lcnt2;  // LDS ready counters, two 16-bit counters a word
     int off, m;       // the tile: vertices off .. off+m-1
     int* dec_g;
     __device__ __forceinline__ bool mine(int i) const { return (unsigned)(i - off) < (unsigned)m; }
-    __device__ __forceinline__ bool gdone(int i) const {
-        return __hip_atomic_load(&dec_g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kUndecided;
+    __device__ __forceinline__ int word(int i) const {
+        return __hip_atomic_load(&dec_g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __device__ __forceinline__ int get(int i) const { return mine(i) ? sdec[i - off] : (gdone(i) ? -1 : INT_MAX); }
+    // round-stamp view: undecided in round r while >= r
+    __device__ __forceinline__ int get(int i) const {
+        return mine(i) ? sdec[i - off] : (word(i) != kUndecided ? -1 : INT_MAX);
+    }
     __device__ __forceinline__ int drop(int y) const {  // count before the decrement
         y -= off;
         const unsigned sh = 16u * (unsigned)(y & 1);
         const unsigned old = atomicSub(&lcnt2[y >> 1], 1u << sh);
         return (int)((old >> sh) & 0xffffu);
     }
+    __device__ __forceinline__ void publish(int v, int partner) const {
+        __hip_atomic_store(&dec_g[v], partner + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 };
-
-__device__ __forceinline__ void publish(int* dec_g, int v, bool release) {
-    if (release)
-        __hip_atomic_store(&dec_g[v], kPublished, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    else
-        __hip_atomic_store(&dec_g[v], kPublished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // x is decided: its higher neighbours in the tile lose an undecided lower
 // neighbour (higher tiles read dec_g instead).
@@ -751,33 +752,30 @@ __device__ __forceinline__ void tile_release(const HemState& S, const TileSt& st
 
 enum { kUnsettled = 0, kFree = 1, kGone = 2 };
 
-// Settles the pending vertex y (record Ry): kFree when y is now an ordinary
-// undecided vertex, kGone when it is decided (taken by a lower tile, or
-// matched in this round), kUnsettled while a lower-tile edge-neighbour is
-// undecided.  A vertex found taken is stamped r - 1 (unavailable at once),
-// counted and released by the thread that settles it.
+// Compare-and-swap of the 16-bit LDS stamp i; returns the stamp before.
+__device__ __forceinline__ int cas_stamp(uint16_t* sdec, int i, int expect, int want) {
+    unsigned* w = reinterpret_cast<unsigned*>(sdec) + (i >> 1);
+    const unsigned sh = 16u * (unsigned)(i & 1);
+    unsigned old = *w;
+    for (;;) {
+        const int h = (int)((old >> sh) & 0xffffu);
+        if (h != expect) return h;
+        const unsigned nw = (old & ~(0xffffu << sh)) | ((unsigned)want << sh);
+        const unsigned got = atomicCAS(w, old, nw);
+        if (got == old) return expect;
+        old = got;  // the other half changed meanwhile, or this one
+    }
+}
+
+// Settles the pending vertex y (record Ry) once its lower-tile edge-neighbours
+// are decided (all: open == false; taken: one of them names y).  Returns
+// kFree or kGone (taken, or matched in this round after another thread
+// settled it free).  A vertex found taken is stamped r - 1 (unavailable at
+// once), counted and released by the thread whose swap succeeds.
 template <int SIDE, class Ap>
 __device__ __forceinline__ int tile_settle(const HemState& S, const TileSt& st, const HemRecT<SIDE>& Ry, int y, int r,
-                                           const Ap& A, int* s_ndec) {
-    bool open = false;
-    if (Ry.hdr & kRecOverflow) {
-        for (int e = S.rp[y]; e < S.rp[y + 1] && !open; ++e) {
-            const int x = S.ci[e];
-            if (x >= st.off) break;  // columns ascend
-            if (S.lowok[e] && !st.gdone(x)) open = true;
-        }
-    } else {
-        const int nl = (Ry.hdr >> 8) & 255;
-        bool d[SIDE];
-#pragma unroll
-        for (int t = 0; t < SIDE; ++t) d[t] = t < nl && Ry.l[t] < st.off ? st.gdone(Ry.l[t]) : true;
-#pragma unroll
-        for (int t = 0; t < SIDE; ++t) open |= !d[t];
-    }
-    if (open) return kUnsettled;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const bool taken = st.gdone(y);
-    const int old = atomicCAS(&st.sdec[y - st.off], kTilePend, taken ? r - 1 : kTileUnd);
+                                           bool taken, const Ap& A, int* s_ndec) {
+    const int old = cas_stamp(st.sdec, y - st.off, kTilePend, taken ? r - 1 : kTileUnd);
     if (old == kTilePend) {
         if (!taken) return kFree;
         atomicAdd(s_ndec, 1);
@@ -785,6 +783,84 @@ __device__ __forceinline__ int tile_settle(const HemState& S, const TileSt& st, 
         return kGone;
     }
     return old == kTileUnd ? kFree : kGone;
+}
+
+// Lower-tile edge-neighbours of y: open when one is undecided, taken when
+// one names y as its partner.
+template <int SIDE>
+__device__ __forceinline__ void cross_lower(const HemState& S, const TileSt& st, const HemRecT<SIDE>& Ry, int y,
+                                            bool& open, bool& taken) {
+    open = false;
+    taken = false;
+    if (Ry.hdr & kRecOverflow) {
+        for (int e = S.rp[y]; e < S.rp[y + 1]; ++e) {
+            const int x = S.ci[e];
+            if (x >= st.off) break;  // columns ascend
+            if (!S.lowok[e]) continue;
+            const int wx = st.word(x);
+            open |= wx == kUndecided;
+            taken |= wx == y + 2;
+        }
+        return;
+    }
+    const int nl = (Ry.hdr >> 8) & 255;
+    int wx[SIDE];
+#pragma unroll
+    for (int t = 0; t < SIDE; ++t) wx[t] = t < nl && Ry.l[t] < st.off ? st.word(Ry.l[t]) : 0;
+#pragma unroll
+    for (int t = 0; t < SIDE; ++t) {
+        open |= wx[t] == kUndecided;
+        taken |= wx[t] == y + 2;
+    }
+}
+
+// Smallest undecided lower edge-neighbour of w (stamp view of round r), or -1;
+// named: an out-of-tile lower edge-neighbour below the result names w.
+template <int SIDE>
+__device__ __forceinline__ int tile_back(const HemState& S, const TileSt& st, const HemRecT<SIDE>& B, int w, int r,
+                                         bool& named) {
+    named = false;
+    if (B.hdr & kRecOverflow) {
+        for (int e = S.rp[w]; e < S.rp[w + 1]; ++e) {
+            const int x = S.ci[e];
+            if (x >= w) break;
+            if (!S.lowok[e]) continue;
+            if (st.mine(x)) {
+                if (st.sdec[x - st.off] >= r) return x;
+            } else {
+                const int wx = st.word(x);
+                if (wx == kUndecided) return x;
+                named |= wx == w + 2;
+            }
+        }
+        return -1;
+    }
+    const int nl = (B.hdr >> 8) & 255;
+    int d[SIDE];
+    bool nm[SIDE];
+#pragma unroll
+    for (int t = 0; t < SIDE; ++t) {
+        nm[t] = false;
+        d[t] = -1;
+        if (t < nl) {
+            const int x = B.l[t];
+            if (st.mine(x)) {
+                d[t] = st.sdec[x - st.off];
+            } else {
+                const int wx = st.word(x);
+                d[t] = wx == kUndecided ? INT_MAX : -1;
+                nm[t] = wx == w + 2;
+            }
+        }
+    }
+    int back = -1;
+#pragma unroll
+    for (int t = SIDE - 1; t >= 0; --t)
+        if (t < nl && d[t] >= r) back = B.l[t];
+#pragma unroll
+    for (int t = 0; t < SIDE; ++t)
+        if (t < nl && nm[t] && (back < 0 || B.l[t] < back)) named = true;
+    return back;
 }
 
 // Round r for a ready vertex u of the tile (the visit of hem_visit, with the
@@ -796,10 +872,18 @@ __device__ __forceinline__ void tile_visit(const HemState& S, const TileSt& st, 
     const HemRecT<SIDE> R = recs[u];
     const int su = st.sdec[u - st.off];
     if (su < r) return;  // decided earlier (as a match target): stale entry
+    // the first preference's record, loaded with the states it is chosen by
+    const bool spec = !(R.hdr & kRecOverflow) && (R.hdr & 255) > 0;
+    HemRecT<SIDE> B;
+    if (spec) B = recs[R.h[0]];
     if (su == kTilePend) {
-        const int k = tile_settle<SIDE>(S, st, R, u, r, A, s_ndec);
-        if (k == kUnsettled) A.push(u);
-        if (k != kFree) return;
+        bool open, taken;
+        cross_lower<SIDE>(S, st, R, u, open, taken);
+        if (open) {
+            A.push(u);
+            return;
+        }
+        if (tile_settle<SIDE>(S, st, R, u, r, taken, A, s_ndec) != kFree) return;
     }
     int best = -1;
     if (R.hdr & kRecOverflow) {
@@ -814,58 +898,48 @@ __device__ __forceinline__ void tile_visit(const HemState& S, const TileSt& st, 
             if (t < nh && d[t] >= r) best = R.h[t];
     }
     if (best < 0) {  // no undecided neighbour: unaggregated singleton
-        st.sdec[u - st.off] = r;
+        st.sdec[u - st.off] = (uint16_t)r;
         S.mate[u] = -1;
-        publish(st.dec_g, u, false);
+        st.publish(u, -1);
         atomicAdd(s_ndec, 1);
         tile_release<SIDE>(S, st, R, u, A);
         return;
     }
-    const HemRecT<SIDE> B = recs[best];
-    int back = -1;
-    if (B.hdr & kRecOverflow) {
-        back = hem_back(S, st, r, best);
-    } else {
-        const int nl = (B.hdr >> 8) & 255;
-        int d[SIDE];
-#pragma unroll
-        for (int t = 0; t < SIDE; ++t) d[t] = t < nl ? st.get(B.l[t]) : -1;
-#pragma unroll
-        for (int t = SIDE - 1; t >= 0; --t)
-            if (t < nl && d[t] >= r) back = B.l[t];
-    }
+    if (!spec || best != R.h[0]) B = recs[best];
+    bool named;
+    const int back = tile_back<SIDE>(S, st, B, best, r, named);
     if (back != u) {
         A.push(u);  // still ready, retry next round
         return;
     }
     if (st.mine(best)) {
-        if (st.sdec[best - st.off] == kTilePend && tile_settle<SIDE>(S, st, B, best, r, A, s_ndec) != kFree) {
+        // a pending target: its lower-tile edge-neighbours are all below u,
+        // hence decided; named says whether one of them took it
+        if (st.sdec[best - st.off] == kTilePend && tile_settle<SIDE>(S, st, B, best, r, named, A, s_ndec) != kFree) {
             A.push(u);
             return;
         }
-        st.sdec[u - st.off] = r;
-        st.sdec[best - st.off] = r;
+        st.sdec[u - st.off] = (uint16_t)r;
+        st.sdec[best - st.off] = (uint16_t)r;
         S.mate[u] = best;
         S.mate[best] = u;
-        publish(st.dec_g, best, false);
-        publish(st.dec_g, u, false);
+        st.publish(best, u);
+        st.publish(u, best);
         atomicAdd(s_ndec, 2);
         tile_release<SIDE>(S, st, R, u, A);
         tile_release<SIDE>(S, st, B, best, A);
         return;
     }
-    // best lies in a higher tile: re-read it after the reads of its lower
-    // edge-neighbours, then publish it before u
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (st.gdone(best)) {
+    if (named) {  // taken from a lower tile
         A.push(u);
         return;
     }
-    st.sdec[u - st.off] = r;
+    st.sdec[u - st.off] = (uint16_t)r;
     S.mate[u] = best;
     S.mate[best] = u;
-    publish(st.dec_g, best, false);
-    publish(st.dec_g, u, true);
+    st.publish(best, u);
+    st.publish(u, best);
+    __builtin_amdgcn_s_waitcnt(0);  // stores complete before the round ends
     atomicAdd(s_ndec, 1);
     tile_release<SIDE>(S, st, R, u, A);
 }
@@ -897,7 +971,7 @@ template <int SIDE>
 __global__ __launch_bounds__(HEM_BS1) void k_hem_tile(int n, int T, HemState S, int* dec_g,
                                                       const int* __restrict__ lcnt_g, int* gl0, int* gl1, int* cnt,
                                                       long long tmo) {
-    __shared__ int s_dec[kHemTileRows];
+    __shared__ uint16_t s_dec[kHemTileRows];
     __shared__ unsigned s_lcnt2[kHemTileRows / 2];
     __shared__ uint16_t s_la[TL_LCAP], s_lb[TL_LCAP];
     __shared__ int s_cnt, s_gnext, s_ndec, s_stop;
@@ -912,13 +986,13 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_tile(int n, int T, HemState S, 
         s_stop = 0;
     }
     __syncthreads();
-    // Vertices decided before the pass (stamp -1: systems of another driver)
-    // count as done; lower tiles may already publish others (kPublished).
+    // Vertices decided before the pass (dec_g -1: systems of another driver)
+    // count as done (LDS stamp 0); lower tiles may already publish others.
     int pre = 0;
     for (int i = threadIdx.x; i < m; i += HEM_BS1) {
         const bool done = dec_g[off + i] == -1;
         pre += done;
-        s_dec[i] = done ? -1 : ((lcnt_g[off + i] & kExposed) ? kTilePend : kTileUnd);
+        s_dec[i] = (uint16_t)(done ? 0 : ((lcnt_g[off + i] & kExposed) ? kTilePend : kTileUnd));
     }
     for (int i = threadIdx.x; 2 * i < m; i += HEM_BS1) {
         const unsigned lo = (unsigned)lcnt_g[off + 2 * i] & 0xffffu;
@@ -936,13 +1010,13 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_tile(int n, int T, HemState S, 
     {  // the first list: undecided vertices without undecided lower neighbours in the tile
         const Appender<uint16_t> A{cur, &s_cnt, TL_LCAP, gin, &s_gnext, off};
         for (int i = threadIdx.x; i < m; i += HEM_BS1)
-            if (s_dec[i] != -1 && (lcnt_g[off + i] & 0xffff) == 0) A.push(off + i);
+            if (s_dec[i] != 0 && (lcnt_g[off + i] & 0xffff) == 0) A.push(off + i);
         __syncthreads();
         kl = min(s_cnt, TL_LCAP);
         kg = s_gnext;
         __syncthreads();
     }
-    int r = 1;  // stamps r - 1 >= 0 mark vertices found taken
+    int r = 2;  // stamps r - 1 >= 1 mark vertices found taken
     bool stop = s_ndec >= m;
     while (!stop) {
         if (threadIdx.x == 0) {
@@ -956,7 +1030,7 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_tile(int n, int T, HemState S, 
             const int u = idx < klc ? (int)cur[idx] + off : gin[idx - klc];
             tile_visit<SIDE>(S, st, r, u, A, &s_ndec);
         }
-        if (threadIdx.x == 0 && wall_clock64() - t_start > tmo) s_stop = 1;
+        if (threadIdx.x == 0 && (wall_clock64() - t_start > tmo || r >= kTileMaxRound)) s_stop = 1;
         __syncthreads();
         kl = min(s_cnt, TL_LCAP);
         kg = s_gnext;
@@ -971,7 +1045,7 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_tile(int n, int T, HemState S, 
         ++r;
     }
     if (threadIdx.x == 0) {
-        atomicMax(&cnt[6], r - 1);
+        atomicMax(&cnt[6], r - 2);
         if (s_ndec < m) atomicOr(&cnt[7], 1);
     }
 }
