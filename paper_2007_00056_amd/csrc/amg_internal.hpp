@@ -27,17 +27,21 @@ void launch_validate(int n, int64_t nnz, const int* rp, const int* ci, const dou
 void launch_dinv(int n, const int* rp, const int* ci, const double* v, double* dinv, int* err, hipStream_t s);
 
 // Per-vertex adjacency record of a matching pass (64, 128 or 256 bytes for
-// SIDE = 7, 15, 31): up to SIDE higher neighbours j (a_uj non-zero) by |a_uj|
-// descending, column ascending on ties, and up to SIDE lower edge-neighbours
-// x (row x stores a non-zero a_xu) ascending.  Vertices with more use the CSR
-// rows instead.
+// SIDE = 7, 15, 31): the first SIDE higher neighbours j (a_uj non-zero) by
+// |a_uj| descending, column ascending on ties, and the first SIDE lower
+// edge-neighbours x (row x stores a non-zero a_xu) ascending.  kRecHiTrunc /
+// kRecLoTrunc: the row has more of them (the first undecided entry of a list
+// is still the vertex's choice when the list has one; otherwise the CSR row
+// decides); kRecOverflow: either.
 constexpr int kRecOverflow = 1 << 16;
+constexpr int kRecHiTrunc = 1 << 17;
+constexpr int kRecLoTrunc = 1 << 18;
 constexpr int kHemLdsRows = 32768;  // passes up to this size keep their matching state in LDS
 constexpr int kHemTileRows = 32768;  // largest tile of a tiled pass (its state in LDS)
 constexpr int kHemMaxTiles = 4096;   // tiled passes up to this many tiles
 template <int SIDE>
 struct alignas(4 * (SIDE + 1) * 2) HemRecT {
-    int hdr;  // #higher | #lower << 8 | kRecOverflow
+    int hdr;  // #higher | #lower << 8 | kRecOverflow | kRecHiTrunc | kRecLoTrunc
     int h[SIDE];
     int l[SIDE];
     int pad;

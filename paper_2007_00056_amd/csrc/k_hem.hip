@@ -61,7 +61,7 @@ __global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ 
     dec[y] = kUndecided;
     mate[y] = -1;
     int c = 0, nlow = 0, nup = 0, bad = 0, nh = 0, nl = 0;
-    bool ovf = false;
+    bool hitr = false, lotr = false;
     int hj[SIDE], lx[SIDE];
     double hw[SIDE];
 #pragma unroll
@@ -85,22 +85,22 @@ __global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ 
                         if (t == nl) lx[t] = u;
                     ++nl;
                 } else {
-                    ovf = true;
+                    lotr = true;  // the smallest SIDE are kept
                 }
             }
         } else if (u > y) {
             ++nup;
             const double a = v[k];
-            if (a != 0.0) {  // higher neighbour: keep sorted by |a| descending, column ascending
-                if (nh < SIDE) {
-                    const double w = fabs(a);
-                    int pos = 0;
+            if (a != 0.0) {  // higher neighbour: the first SIDE by |a| descending, column ascending
+                const double w = fabs(a);
+                int pos = 0;
 #pragma unroll
-                    for (int t = 0; t < SIDE; ++t)
-                        if (t < nh && hw[t] >= w) pos = t + 1;
+                for (int t = 0; t < SIDE; ++t)
+                    if (t < nh && hw[t] >= w) pos = t + 1;
+                if (pos < SIDE) {
 #pragma unroll
                     for (int t = SIDE - 1; t > 0; --t)
-                        if (t > pos && t <= nh) {
+                        if (t > pos && t <= nh) {  // a full list drops its last entry
                             hw[t] = hw[t - 1];
                             hj[t] = hj[t - 1];
                         }
@@ -110,17 +110,16 @@ __global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ 
                             hw[t] = w;
                             hj[t] = u;
                         }
-                    ++nh;
-                } else {
-                    ovf = true;
                 }
+                if (nh < SIDE) ++nh;
+                else hitr = true;
             }
         }
         lowok[k] = ok;
         c += ok;
     }
     HemRecT<SIDE> R;
-    R.hdr = nh | (nl << 8) | (ovf ? kRecOverflow : 0);
+    R.hdr = nh | (nl << 8) | (hitr ? kRecHiTrunc : 0) | (lotr ? kRecLoTrunc : 0) | (hitr || lotr ? kRecOverflow : 0);
 #pragma unroll
     for (int t = 0; t < SIDE; ++t) {
         R.h[t] = hj[t];
@@ -289,7 +288,7 @@ __device__ __forceinline__ int hem_back(const HemState& S, const St& st, int r, 
 template <class St, int SIDE, class Ap>
 __device__ __forceinline__ void rec_release(const HemState& S, const St& st, const HemRecT<SIDE>& R, int x,
                                             const Ap& A) {
-    if (R.hdr & kRecOverflow) {
+    if (R.hdr & kRecHiTrunc) {
         hem_release(S, st, x, A);
         return;
     }
@@ -305,19 +304,18 @@ __device__ __forceinline__ void rec_release(const HemState& S, const St& st, con
 // Round r for a ready vertex u.  Records list u's higher neighbours in
 // preference order (heaviest first, lowest index on ties) and the target's
 // lower edge-neighbours in ascending order, so "first undecided entry" is the
-// pointer of either side.  With WAVE_OK, a vertex whose record (or its
-// target's) overflowed is not handled here: the function returns true and
-// the caller hands it to a whole wave (hem_visit_wave) later in the round.
+// pointer of either side; a truncated list decides only when it holds an
+// undecided entry.  With WAVE_OK, a visit that needs a CSR row (a pointer
+// past a truncated list, or the release of a truncated higher list) is not
+// done here: the function returns true before any change and the caller
+// hands u to a whole wave (hem_visit_wave) later in the round.
 template <class St, int SIDE, bool WAVE_OK, class Ap>
 __device__ __forceinline__ bool hem_visit(const HemState& S, const St& st, int r, int u, const Ap& A) {
     const HemRecT<SIDE>* __restrict__ recs = static_cast<const HemRecT<SIDE>*>(S.rec);
     const HemRecT<SIDE> R = recs[u];
     if (st.get(u) < r) return false;  // decided earlier (as a match target): stale entry
-    if (WAVE_OK && (R.hdr & kRecOverflow)) return true;
     int best = -1;
-    if (R.hdr & kRecOverflow) {
-        best = hem_best(S, st, r, u, S.rp[u], S.rp[u + 1]);
-    } else {
+    {
         const int nh = R.hdr & 255;
         int d[SIDE];
 #pragma unroll
@@ -326,6 +324,10 @@ __device__ __forceinline__ bool hem_visit(const HemState& S, const St& st, int r
         for (int t = SIDE - 1; t >= 0; --t)
             if (t < nh && d[t] >= r) best = R.h[t];
     }
+    if (best < 0 && (R.hdr & kRecHiTrunc)) {  // every listed choice decided: the row decides
+        if (WAVE_OK) return true;
+        best = hem_best(S, st, r, u, S.rp[u], S.rp[u + 1]);
+    }
     if (best < 0) {  // no undecided neighbour: unaggregated singleton
         st.set(u, r);
         S.mate[u] = -1;
@@ -333,11 +335,8 @@ __device__ __forceinline__ bool hem_visit(const HemState& S, const St& st, int r
         return false;
     }
     const HemRecT<SIDE> B = recs[best];
-    if (WAVE_OK && (B.hdr & kRecOverflow)) return true;
     int back = -1;
-    if (B.hdr & kRecOverflow) {
-        back = hem_back(S, st, r, best);
-    } else {
+    {
         const int nl = (B.hdr >> 8) & 255;
         int d[SIDE];
 #pragma unroll
@@ -346,7 +345,12 @@ __device__ __forceinline__ bool hem_visit(const HemState& S, const St& st, int r
         for (int t = SIDE - 1; t >= 0; --t)
             if (t < nl && d[t] >= r) back = B.l[t];
     }
+    if (back < 0 && (B.hdr & kRecLoTrunc)) {
+        if (WAVE_OK) return true;
+        back = hem_back(S, st, r, best);
+    }
     if (back == u) {  // best points back: mutual, matched
+        if (WAVE_OK && ((R.hdr | B.hdr) & kRecHiTrunc)) return true;  // releases scan rows
         st.set(u, r);
         st.set(best, r);
         S.mate[u] = best;
@@ -386,7 +390,7 @@ template <class St, class Ap>
 __device__ __forceinline__ void wave_release(const HemState& S, const St& st, int x, int hdr, int myh,
                                              const Ap& A) {
     const int lane = threadIdx.x % kWave;
-    if (hdr & kRecOverflow) {
+    if (hdr & kRecHiTrunc) {
         for (int e = S.rp[x] + lane; e < S.rp[x + 1]; e += kWave) {
             const int y = S.ci[e];
             if (y > x && S.v[e] != 0.0 && st.drop(y) == 1) A.push(y);
@@ -407,7 +411,7 @@ __device__ __forceinline__ void hem_visit_wave(const HemState& S, const St& st, 
     const int myh = lane < SIDE ? ru[1 + lane] : -1;
     if (st.get(u) < r) return;
     int best;
-    if (hdr & kRecOverflow) {
+    if (hdr & kRecHiTrunc) {
         double bw = -1.0;
         int bj = INT_MAX;
         for (int e = S.rp[u] + lane; e < S.rp[u + 1]; e += kWave) {
@@ -438,7 +442,7 @@ __device__ __forceinline__ void hem_visit_wave(const HemState& S, const St& st, 
     const int bhdr = rb[0];
     const int bh = lane < SIDE ? rb[1 + lane] : -1;
     int back;
-    if (bhdr & kRecOverflow) {
+    if (bhdr & kRecLoTrunc) {
         int mx = INT_MAX;
         for (int e = S.rp[best] + lane; e < S.rp[best + 1]; e += kWave) {
             const int x = S.ci[e];
@@ -734,7 +738,7 @@ struct TileSt {
 template <int SIDE, class Ap>
 __device__ __forceinline__ void tile_release(const HemState& S, const TileSt& st, const HemRecT<SIDE>& R, int x,
                                              const Ap& A) {
-    if (R.hdr & kRecOverflow) {
+    if (R.hdr & kRecHiTrunc) {
         for (int e = S.rp[x]; e < S.rp[x + 1]; ++e) {
             const int y = S.ci[e];
             if (y > x && st.mine(y) && S.v[e] != 0.0 && st.drop(y) == 1) A.push(y);
@@ -792,7 +796,8 @@ __device__ __forceinline__ void cross_lower(const HemState& S, const TileSt& st,
                                             bool& open, bool& taken) {
     open = false;
     taken = false;
-    if (Ry.hdr & kRecOverflow) {
+    const int nl = (Ry.hdr >> 8) & 255;
+    if ((Ry.hdr & kRecLoTrunc) && Ry.l[SIDE - 1] < st.off) {  // a full list; more lower-tile ones may follow
         for (int e = S.rp[y]; e < S.rp[y + 1]; ++e) {
             const int x = S.ci[e];
             if (x >= st.off) break;  // columns ascend
@@ -803,7 +808,6 @@ __device__ __forceinline__ void cross_lower(const HemState& S, const TileSt& st,
         }
         return;
     }
-    const int nl = (Ry.hdr >> 8) & 255;
     int wx[SIDE];
 #pragma unroll
     for (int t = 0; t < SIDE; ++t) wx[t] = t < nl && Ry.l[t] < st.off ? st.word(Ry.l[t]) : 0;
@@ -815,26 +819,13 @@ __device__ __forceinline__ void cross_lower(const HemState& S, const TileSt& st,
 }
 
 // Smallest undecided lower edge-neighbour of w (stamp view of round r), or -1;
-// named: an out-of-tile lower edge-neighbour below the result names w.
+// named: an out-of-tile lower edge-neighbour below the result names w.  The
+// listed neighbours decide unless all are decided and the list is truncated;
+// then the CSR row does.
 template <int SIDE>
 __device__ __forceinline__ int tile_back(const HemState& S, const TileSt& st, const HemRecT<SIDE>& B, int w, int r,
                                          bool& named) {
     named = false;
-    if (B.hdr & kRecOverflow) {
-        for (int e = S.rp[w]; e < S.rp[w + 1]; ++e) {
-            const int x = S.ci[e];
-            if (x >= w) break;
-            if (!S.lowok[e]) continue;
-            if (st.mine(x)) {
-                if (st.sdec[x - st.off] >= r) return x;
-            } else {
-                const int wx = st.word(x);
-                if (wx == kUndecided) return x;
-                named |= wx == w + 2;
-            }
-        }
-        return -1;
-    }
     const int nl = (B.hdr >> 8) & 255;
     int d[SIDE];
     bool nm[SIDE];
@@ -857,10 +848,25 @@ __device__ __forceinline__ int tile_back(const HemState& S, const TileSt& st, co
 #pragma unroll
     for (int t = SIDE - 1; t >= 0; --t)
         if (t < nl && d[t] >= r) back = B.l[t];
+    if (back >= 0 || !(B.hdr & kRecLoTrunc)) {
 #pragma unroll
-    for (int t = 0; t < SIDE; ++t)
-        if (t < nl && nm[t] && (back < 0 || B.l[t] < back)) named = true;
-    return back;
+        for (int t = 0; t < SIDE; ++t)
+            if (t < nl && nm[t] && (back < 0 || B.l[t] < back)) named = true;
+        return back;
+    }
+    for (int e = S.rp[w]; e < S.rp[w + 1]; ++e) {  // every listed one decided
+        const int x = S.ci[e];
+        if (x >= w) break;
+        if (!S.lowok[e]) continue;
+        if (st.mine(x)) {
+            if (st.sdec[x - st.off] >= r) return x;
+        } else {
+            const int wx = st.word(x);
+            if (wx == kUndecided) return x;
+            named |= wx == w + 2;
+        }
+    }
+    return -1;
 }
 
 // Round r for a ready vertex u of the tile (the visit of hem_visit, with the
@@ -873,7 +879,7 @@ __device__ __forceinline__ void tile_visit(const HemState& S, const TileSt& st, 
     const int su = st.sdec[u - st.off];
     if (su < r) return;  // decided earlier (as a match target): stale entry
     // the first preference's record, loaded with the states it is chosen by
-    const bool spec = !(R.hdr & kRecOverflow) && (R.hdr & 255) > 0;
+    const bool spec = (R.hdr & 255) > 0;
     HemRecT<SIDE> B;
     if (spec) B = recs[R.h[0]];
     if (su == kTilePend) {
@@ -886,9 +892,7 @@ __device__ __forceinline__ void tile_visit(const HemState& S, const TileSt& st, 
         if (tile_settle<SIDE>(S, st, R, u, r, taken, A, s_ndec) != kFree) return;
     }
     int best = -1;
-    if (R.hdr & kRecOverflow) {
-        best = hem_best(S, st, r, u, S.rp[u], S.rp[u + 1]);
-    } else {
+    {
         const int nh = R.hdr & 255;
         int d[SIDE];
 #pragma unroll
@@ -897,6 +901,8 @@ __device__ __forceinline__ void tile_visit(const HemState& S, const TileSt& st, 
         for (int t = SIDE - 1; t >= 0; --t)
             if (t < nh && d[t] >= r) best = R.h[t];
     }
+    if (best < 0 && (R.hdr & kRecHiTrunc))  // every listed choice decided: the row decides
+        best = hem_best(S, st, r, u, S.rp[u], S.rp[u + 1]);
     if (best < 0) {  // no undecided neighbour: unaggregated singleton
         st.sdec[u - st.off] = (uint16_t)r;
         S.mate[u] = -1;
@@ -1030,7 +1036,8 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_tile(int n, int T, HemState S, 
             const int u = idx < klc ? (int)cur[idx] + off : gin[idx - klc];
             tile_visit<SIDE>(S, st, r, u, A, &s_ndec);
         }
-        if (threadIdx.x == 0 && (wall_clock64() - t_start > tmo || r >= kTileMaxRound)) s_stop = 1;
+        if (threadIdx.x == 0 && (r & 31) == 0 && (wall_clock64() - t_start > tmo || r >= kTileMaxRound))
+            s_stop = 1;
         __syncthreads();
         kl = min(s_cnt, TL_LCAP);
         kg = s_gnext;
