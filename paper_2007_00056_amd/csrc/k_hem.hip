@@ -47,6 +47,22 @@ __device__ __forceinline__ int find_col(const int* __restrict__ ci, int lo, int 
 }
 }  // namespace
 
+constexpr int INIT_GRP = 4;  // row entries whose loads k_hem_init issues together
+
+// Position of column c in ci[lo, hi) (ascending), or -1: rows of up to 8
+// entries in one load step, longer ones by bisection.
+__device__ __forceinline__ int find_col_short(const int* __restrict__ ci, int lo, int hi, int c) {
+    if (hi - lo > 8) return find_col(ci, lo, hi, c);
+    int x[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) x[t] = lo + t < hi ? ci[lo + t] : -1;
+    int p = -1;
+#pragma unroll
+    for (int t = 7; t >= 0; --t)
+        if (x[t] == c) p = lo + t;
+    return p;
+}
+
 // counters: cnt[0..2] worklist sizes (ring of 3), cnt[5] sum over rows of
 // (#upper - #lower) entries, cnt[6] the number of rounds that had work,
 // cnt[7] set when a single-workgroup pass hit its round limit.
@@ -57,80 +73,105 @@ __global__ __launch_bounds__(BS) void k_hem_init(int n, const int* __restrict__ 
                                                  int* __restrict__ dec, int* __restrict__ mate,
                                                  int* __restrict__ wl0, int* cnt, int* err) {
     const int y = blockIdx.x * BS + threadIdx.x;
-    if (y >= n) return;
-    dec[y] = kUndecided;
-    mate[y] = -1;
-    int c = 0, nlow = 0, nup = 0, bad = 0, nh = 0, nl = 0;
-    bool hitr = false, lotr = false;
-    int hj[SIDE], lx[SIDE];
-    double hw[SIDE];
+    int nlow = 0, nup = 0;
+    if (y < n) {
+        dec[y] = kUndecided;
+        mate[y] = -1;
+        int c = 0, bad = 0, nh = 0, nl = 0;
+        bool hitr = false, lotr = false;
+        int hj[SIDE], lx[SIDE];
+        double hw[SIDE];
 #pragma unroll
-    for (int t = 0; t < SIDE; ++t) {
-        hj[t] = -1;
-        lx[t] = -1;
-        hw[t] = 0.0;
-    }
-    for (int k = rp[y]; k < rp[y + 1]; ++k) {
-        const int u = ci[k];
-        uint8_t ok = 0;
-        if (u < y) {
-            ++nlow;
-            const int pos = find_col(ci, rp[u], rp[u + 1], y);
-            if (pos < 0) bad = 1;
-            else if (v[pos] != 0.0) ok = 1;
-            if (ok) {  // lower edge-neighbour, columns arrive ascending
-                if (nl < SIDE) {
+        for (int t = 0; t < SIDE; ++t) {
+            hj[t] = -1;
+            lx[t] = -1;
+            hw[t] = 0.0;
+        }
+        // Entries in groups of INIT_GRP: the loads of a group (columns, the rows
+        // of the lower neighbours, the mirrored entries' values) are issued
+        // together, then the entries are taken in order.
+        const int e0 = rp[y], e1 = rp[y + 1];
+        for (int k0 = e0; k0 < e1; k0 += INIT_GRP) {
+            int us[INIT_GRP], pos[INIT_GRP];
+            double own[INIT_GRP], mir[INIT_GRP];
 #pragma unroll
-                    for (int t = 0; t < SIDE; ++t)
-                        if (t == nl) lx[t] = u;
-                    ++nl;
-                } else {
-                    lotr = true;  // the smallest SIDE are kept
-                }
+            for (int t = 0; t < INIT_GRP; ++t) {
+                us[t] = k0 + t < e1 ? ci[k0 + t] : y;
+                own[t] = k0 + t < e1 ? v[k0 + t] : 0.0;
             }
-        } else if (u > y) {
-            ++nup;
-            const double a = v[k];
-            if (a != 0.0) {  // higher neighbour: the first SIDE by |a| descending, column ascending
-                const double w = fabs(a);
-                int pos = 0;
 #pragma unroll
-                for (int t = 0; t < SIDE; ++t)
-                    if (t < nh && hw[t] >= w) pos = t + 1;
-                if (pos < SIDE) {
+            for (int t = 0; t < INIT_GRP; ++t) pos[t] = us[t] < y ? find_col_short(ci, rp[us[t]], rp[us[t] + 1], y) : -1;
 #pragma unroll
-                    for (int t = SIDE - 1; t > 0; --t)
-                        if (t > pos && t <= nh) {  // a full list drops its last entry
-                            hw[t] = hw[t - 1];
-                            hj[t] = hj[t - 1];
+            for (int t = 0; t < INIT_GRP; ++t) mir[t] = pos[t] >= 0 ? v[pos[t]] : 0.0;
+#pragma unroll
+            for (int q = 0; q < INIT_GRP; ++q) {
+                const int k = k0 + q;
+                if (k >= e1) break;
+                const int u = us[q];
+                uint8_t ok = 0;
+                if (u < y) {
+                    ++nlow;
+                    if (pos[q] < 0) bad = 1;
+                    else if (mir[q] != 0.0) ok = 1;
+                    if (ok) {  // lower edge-neighbour, columns arrive ascending
+                        if (nl < SIDE) {
+#pragma unroll
+                            for (int t = 0; t < SIDE; ++t)
+                                if (t == nl) lx[t] = u;
+                            ++nl;
+                        } else {
+                            lotr = true;  // the smallest SIDE are kept
                         }
+                    }
+                } else if (u > y) {
+                    ++nup;
+                    const double a = own[q];
+                    if (a != 0.0) {  // higher neighbour: the first SIDE by |a| descending, column ascending
+                        const double w = fabs(a);
+                        int at = 0;
 #pragma unroll
-                    for (int t = 0; t < SIDE; ++t)
-                        if (t == pos) {
-                            hw[t] = w;
-                            hj[t] = u;
+                        for (int t = 0; t < SIDE; ++t)
+                            if (t < nh && hw[t] >= w) at = t + 1;
+                        if (at < SIDE) {
+#pragma unroll
+                            for (int t = SIDE - 1; t > 0; --t)
+                                if (t > at && t <= nh) {  // a full list drops its last entry
+                                    hw[t] = hw[t - 1];
+                                    hj[t] = hj[t - 1];
+                                }
+#pragma unroll
+                            for (int t = 0; t < SIDE; ++t)
+                                if (t == at) {
+                                    hw[t] = w;
+                                    hj[t] = u;
+                                }
                         }
+                        if (nh < SIDE) ++nh;
+                        else hitr = true;
+                    }
                 }
-                if (nh < SIDE) ++nh;
-                else hitr = true;
+                lowok[k] = ok;
+                c += ok;
             }
         }
-        lowok[k] = ok;
-        c += ok;
-    }
-    HemRecT<SIDE> R;
-    R.hdr = nh | (nl << 8) | (hitr ? kRecHiTrunc : 0) | (lotr ? kRecLoTrunc : 0) | (hitr || lotr ? kRecOverflow : 0);
+        HemRecT<SIDE> R;
+        R.hdr = nh | (nl << 8) | (hitr ? kRecHiTrunc : 0) | (lotr ? kRecLoTrunc : 0) | (hitr || lotr ? kRecOverflow : 0);
 #pragma unroll
-    for (int t = 0; t < SIDE; ++t) {
-        R.h[t] = hj[t];
-        R.l[t] = lx[t];
+        for (int t = 0; t < SIDE; ++t) {
+            R.h[t] = hj[t];
+            R.l[t] = lx[t];
+        }
+        R.pad = 0;
+        rec[y] = R;
+        lcnt[y] = c;
+        if (bad) atomicOr(err, ERR_NONSYM);
+        if (c == 0) wl0[atomicAdd(&cnt[0], 1)] = y;
     }
-    R.pad = 0;
-    rec[y] = R;
-    lcnt[y] = c;
-    if (bad) atomicOr(err, ERR_NONSYM);
-    if (nup != nlow) atomicAdd(&cnt[5], nup - nlow);
-    if (c == 0) wl0[atomicAdd(&cnt[0], 1)] = y;
+    // the pattern check: one atomic per wave (boundary rows differ one by one)
+    int diff = nup - nlow;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) diff += __shfl_xor(diff, o);
+    if (threadIdx.x % kWave == 0 && diff != 0) atomicAdd(&cnt[5], diff);
 }
 
 namespace {

@@ -36,14 +36,13 @@ __global__ __launch_bounds__(BS) void k_validate(int n, int64_t nnz, const int* 
     double d = 0.0;
     bool has_d = false;
     int prev = -1;
+    // no early exit, so the loads of several entries are in flight together
+#pragma unroll 4
     for (int k = b; k < e; ++k) {
         const int c = ci[k];
-        if (c < 0 || c >= n || c <= prev) {
-            bits |= ERR_STRUCT;
-            break;
-        }
-        prev = c;
         const double x = v[k];
+        if (c < 0 || c >= n || c <= prev) bits |= ERR_STRUCT;
+        prev = c;
         if (!isfinite(x)) bits |= ERR_NONFINITE;
         if (c == i) {
             has_d = true;
