@@ -531,6 +531,12 @@ __device__ __forceinline__ void hem_round_body(const HemState& S, const St& st, 
 constexpr int HEM_BS = 512;
 constexpr int HEM_LCAP = 4096;
 constexpr int HEM_BS1 = 1024;
+// Threads of the workgroup-wide drivers with LDS state (one workgroup, systems
+// of a batch, tiles): records of 31 entries a side need the registers of 512.
+template <int SIDE>
+constexpr int hem_nt() {
+    return SIDE > 15 ? 512 : 1024;
+}
 constexpr int HEM_LCAP1 = 8192;
 constexpr int HEM_WCAP = 1024;  // vertices deferred to the wave path per block and round
 constexpr int HL_LCAP = 4096;   // LDS worklist entries of the LDS-state driver
@@ -620,15 +626,15 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_all(int n, HemState S, int* dec
 // entries of gin, or with scan the vertices whose counter is zero.  Returns
 // the rounds run; *left is nonzero when the round bound was hit.
 template <int SIDE>
-__device__ int hem_lds_body(int off, int n, const HemState& S, const int* __restrict__ lcnt_g, int* gin,
+__device__ __forceinline__ int hem_lds_body(int off, int n, const HemState& S, const int* __restrict__ lcnt_g, int* gin,
                             int* gout, int kg0, bool scan, int* left) {
     __shared__ uint16_t s_dec[kHemLdsRows];
     __shared__ unsigned s_lcnt2[kHemLdsRows / 2];
     __shared__ uint16_t s_la[HL_LCAP], s_lb[HL_LCAP];
     __shared__ int s_wave[HL_WCAP];
     __shared__ int s_cnt, s_gnext, s_nw;
-    for (int i = threadIdx.x; i < n; i += HEM_BS1) s_dec[i] = 0xffff;
-    for (int i = threadIdx.x; 2 * i < n; i += HEM_BS1) {
+    for (int i = threadIdx.x; i < n; i += hem_nt<SIDE>()) s_dec[i] = 0xffff;
+    for (int i = threadIdx.x; 2 * i < n; i += hem_nt<SIDE>()) {
         const unsigned lo = (unsigned)lcnt_g[off + 2 * i];
         const unsigned hi = 2 * i + 1 < n ? (unsigned)lcnt_g[off + 2 * i + 1] : 0u;
         s_lcnt2[i] = lo | (hi << 16);
@@ -644,7 +650,7 @@ __device__ int hem_lds_body(int off, int n, const HemState& S, const int* __rest
     int kl = 0, kg = kg0;
     if (scan) {  // the first list: vertices with no lower edge-neighbour
         const Appender<uint16_t> A{cur, &s_cnt, HL_LCAP, gin, &s_gnext, off};
-        for (int i = threadIdx.x; i < n; i += HEM_BS1)
+        for (int i = threadIdx.x; i < n; i += hem_nt<SIDE>())
             if (lcnt_g[off + i] == 0) A.push(off + i);
         __syncthreads();
         kl = min(s_cnt, HL_LCAP);
@@ -665,8 +671,8 @@ __device__ int hem_lds_body(int off, int n, const HemState& S, const int* __rest
         const uint16_t* c = cur;
         const int* g = gin;
         const int klc = kl;
-        hem_round_body<LdsSt, SIDE, HEM_BS1>(
-            S, st, r, m, threadIdx.x, HEM_BS1, [&](int i) { return i < klc ? (int)c[i] + off : g[i - klc]; }, A,
+        hem_round_body<LdsSt, SIDE, hem_nt<SIDE>()>(
+            S, st, r, m, threadIdx.x, hem_nt<SIDE>(), [&](int i) { return i < klc ? (int)c[i] + off : g[i - klc]; }, A,
             s_wave, &s_nw, HL_WCAP);
         kl = min(s_cnt, HL_LCAP);
         kg = s_gnext;
@@ -683,7 +689,7 @@ __device__ int hem_lds_body(int off, int n, const HemState& S, const int* __rest
 }
 
 template <int SIDE>
-__global__ __launch_bounds__(HEM_BS1) void k_hem_lds(int n, HemState S, const int* __restrict__ lcnt_g, int* wl0,
+__global__ __launch_bounds__(hem_nt<SIDE>()) void k_hem_lds(int n, HemState S, const int* __restrict__ lcnt_g, int* wl0,
                                                      int* wl1, int* cnt) {
     int left = 0;
     const int r = hem_lds_body<SIDE>(0, n, S, lcnt_g, wl0, wl1, cnt[0], false, &left);
@@ -700,7 +706,7 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_lds(int n, HemState S, const in
 // stamps so that those drivers skip them.  Global list space: the system's
 // own rows of sl0 and sl1.
 template <int SIDE>
-__global__ __launch_bounds__(HEM_BS1) void k_hem_lds_seg(const int2* __restrict__ seg, HemState S,
+__global__ __launch_bounds__(hem_nt<SIDE>()) void k_hem_lds_seg(const int2* __restrict__ seg, HemState S,
                                                          const int* __restrict__ lcnt_g, int* __restrict__ dec_g,
                                                          int* sl0, int* sl1, int* cnt) {
     const int2 sg = seg[blockIdx.x];
@@ -709,7 +715,7 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_lds_seg(const int2* __restrict_
     int left = 0;
     const int r = hem_lds_body<SIDE>(off, n, S, lcnt_g, sl0 + off, sl1 + off, 0, true, &left);
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += HEM_BS1) dec_g[off + i] = -1;
+    for (int i = threadIdx.x; i < n; i += hem_nt<SIDE>()) dec_g[off + i] = -1;
     if (threadIdx.x == 0) {
         atomicMax(&cnt[6], r);
         if (left != 0) atomicOr(&cnt[7], 1);
@@ -1015,7 +1021,7 @@ __global__ __launch_bounds__(BS) void k_hem_tile_prep(int n, int T, const int* _
 // One workgroup per tile.  gl0/gl1: global list space (the tile's rows of
 // each); tmo: time limit in wall-clock ticks.
 template <int SIDE>
-__global__ __launch_bounds__(HEM_BS1) void k_hem_tile(int n, int T, HemState S, int* dec_g,
+__global__ __launch_bounds__(hem_nt<SIDE>()) void k_hem_tile(int n, int T, HemState S, int* dec_g,
                                                       const int* __restrict__ lcnt_g, int* gl0, int* gl1, int* cnt,
                                                       long long tmo) {
     __shared__ uint16_t s_dec[kHemTileRows];
@@ -1036,12 +1042,12 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_tile(int n, int T, HemState S, 
     // Vertices decided before the pass (dec_g -1: systems of another driver)
     // count as done (LDS stamp 0); lower tiles may already publish others.
     int pre = 0;
-    for (int i = threadIdx.x; i < m; i += HEM_BS1) {
+    for (int i = threadIdx.x; i < m; i += hem_nt<SIDE>()) {
         const bool done = dec_g[off + i] == -1;
         pre += done;
         s_dec[i] = (uint16_t)(done ? 0 : ((lcnt_g[off + i] & kExposed) ? kTilePend : kTileUnd));
     }
-    for (int i = threadIdx.x; 2 * i < m; i += HEM_BS1) {
+    for (int i = threadIdx.x; 2 * i < m; i += hem_nt<SIDE>()) {
         const unsigned lo = (unsigned)lcnt_g[off + 2 * i] & 0xffffu;
         const unsigned hi = 2 * i + 1 < m ? (unsigned)lcnt_g[off + 2 * i + 1] & 0xffffu : 0u;
         s_lcnt2[i] = lo | (hi << 16);
@@ -1056,7 +1062,7 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_tile(int n, int T, HemState S, 
     int kl, kg;
     {  // the first list: undecided vertices without undecided lower neighbours in the tile
         const Appender<uint16_t> A{cur, &s_cnt, TL_LCAP, gin, &s_gnext, off};
-        for (int i = threadIdx.x; i < m; i += HEM_BS1)
+        for (int i = threadIdx.x; i < m; i += hem_nt<SIDE>())
             if (s_dec[i] != 0 && (lcnt_g[off + i] & 0xffff) == 0) A.push(off + i);
         __syncthreads();
         kl = min(s_cnt, TL_LCAP);
@@ -1073,7 +1079,7 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_tile(int n, int T, HemState S, 
         __syncthreads();
         const Appender<uint16_t> A{nxt, &s_cnt, TL_LCAP, gout, &s_gnext, off};
         const int klc = kl;
-        for (int idx = threadIdx.x; idx < kl + kg; idx += HEM_BS1) {
+        for (int idx = threadIdx.x; idx < kl + kg; idx += hem_nt<SIDE>()) {
             const int u = idx < klc ? (int)cur[idx] + off : gin[idx - klc];
             tile_visit<SIDE>(S, st, r, u, A, &s_ndec);
         }
@@ -1293,7 +1299,7 @@ void launch_hem_lds_seg(int nseg, const int2* seg, const int* rp, const int* ci,
     if (nseg <= 0) return;
     const HemState S{rp, ci, v, w.lowok, w.rec, w.mate};
 #define CALL(SD)                                                                                                 \
-    hipLaunchKernelGGL(k_hem_lds_seg<SD>, dim3(nseg), dim3(HEM_BS1), 0, s, seg, S, w.lcnt, w.dec, sl0, sl1, w.cnt)
+    hipLaunchKernelGGL(k_hem_lds_seg<SD>, dim3(nseg), dim3(hem_nt<SD>()), 0, s, seg, S, w.lcnt, w.dec, sl0, sl1, w.cnt)
     AMG_HEM_SIDE(w.side, CALL)
 #undef CALL
 }
@@ -1321,7 +1327,7 @@ void launch_hem_tile(int n, const int* rp, const int* ci, const double* v, HemWo
     hipLaunchKernelGGL(k_hem_tile_prep, dim3(blocks_for(n)), dim3(BS), 0, s, n, T, rp, ci, w.lowok, w.lcnt, w.cnt);
     const HemState S{rp, ci, v, w.lowok, w.rec, w.mate};
 #define CALL(SD)                                                                                               \
-    hipLaunchKernelGGL(k_hem_tile<SD>, dim3(nt), dim3(HEM_BS1), 0, s, n, T, S, w.dec, w.lcnt, w.wl[0], w.wl[1], \
+    hipLaunchKernelGGL(k_hem_tile<SD>, dim3(nt), dim3(hem_nt<SD>()), 0, s, n, T, S, w.dec, w.lcnt, w.wl[0], w.wl[1], \
                        w.cnt, tmo)
     if (w.side == 7) CALL(7);
     else CALL(15);  // records of tiled passes hold at most 15 entries a side
@@ -1332,7 +1338,7 @@ void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWor
     const HemState S{rp, ci, v, w.lowok, w.rec, w.mate};
     if (n <= w.lds_rows) {
 #define CALL(SD) \
-    hipLaunchKernelGGL(k_hem_lds<SD>, dim3(1), dim3(HEM_BS1), 0, s, n, S, w.lcnt, w.wl[0], w.wl[1], w.cnt)
+    hipLaunchKernelGGL(k_hem_lds<SD>, dim3(1), dim3(hem_nt<SD>()), 0, s, n, S, w.lcnt, w.wl[0], w.wl[1], w.cnt)
         AMG_HEM_SIDE(w.side, CALL)
 #undef CALL
     } else {
