@@ -26,6 +26,19 @@ inline int level_blocks(int64_t rows, int lpr) {
     return (int)(b < 1 ? 1 : b);
 }
 
+// Small levels run all their blocks on one XCD, so each kernel of the
+// V-cycle finds the previous one's vectors in the same L2: a launch of nb
+// working blocks takes nb * kNumXcd blocks (workgroups go to the XCDs in
+// turn) and only every kNumXcd-th block works.
+constexpr int kPinMaxBlocks = 32;
+inline int pin_of(int nb) { return nb <= kPinMaxBlocks ? 1 : 0; }
+inline dim3 pinned_grid(int nb) { return dim3(pin_of(nb) ? nb * kNumXcd : nb); }
+// this block's working index, or -1 for a block that only fills the other XCDs
+__device__ __forceinline__ int pinned_block(int pin) {
+    if (!pin) return blockIdx.x;
+    return blockIdx.x % kNumXcd == 0 ? (int)(blockIdx.x / kNumXcd) : -1;
+}
+
 template <int LPR, class T>
 __device__ __forceinline__ T row_ax(int row, int lane, const int* __restrict__ rp, const int* __restrict__ ci,
                                     const T* __restrict__ v, const T* __restrict__ x) {
@@ -170,9 +183,11 @@ __global__ __launch_bounds__(BS) void k_vc_resid_restrict(int nc, const int4* __
                                                           const T* __restrict__ v, const T* __restrict__ g,
                                                           const TIN* __restrict__ f, T w,
                                                           const T* __restrict__ dinv_c, T* __restrict__ fc,
-                                                          T* __restrict__ gc) {
+                                                          T* __restrict__ gc, int pin) {
     constexpr int G = 4 * LPR;
-    const int t = blockIdx.x * BS + threadIdx.x;
+    const int blk = pinned_block(pin);
+    if (blk < 0) return;
+    const int t = blk * BS + threadIdx.x;
     const int J = t / G, sub = (t % G) / LPR, lane = t % LPR;
     int i = -1;
     if (J < nc) {
@@ -198,9 +213,12 @@ __global__ __launch_bounds__(BS) void k_vc_resid_restrict(int nc, const int4* __
 template <class T, class TIN>
 void vc_resid_restrict(const VLevel<T>& L, int nc, const TIN* f, const T* g, T w, const T* dinv_c, T* fc, T* gc,
                        hipStream_t s) {
-#define CALL(W)                                                                                                    \
-    hipLaunchKernelGGL((k_vc_resid_restrict<W, T, TIN>), dim3(level_blocks((int64_t)nc * 4, W)), dim3(BS), 0, s, \
-                       nc, L.mem, L.rp, L.ci, L.v, g, f, w, dinv_c, fc, gc)
+#define CALL(W)                                                                                          \
+    {                                                                                                    \
+        const int nb = level_blocks((int64_t)nc * 4, W);                                                 \
+        hipLaunchKernelGGL((k_vc_resid_restrict<W, T, TIN>), pinned_grid(nb), dim3(BS), 0, s, nc, L.mem, \
+                           L.rp, L.ci, L.v, g, f, w, dinv_c, fc, gc, pin_of(nb));                        \
+    }
     AMG_DISPATCH_LPR(L.lpr, CALL)
 #undef CALL
 }
@@ -210,8 +228,10 @@ __global__ __launch_bounds__(BS) void k_vc_prolong_post(int n, const int* __rest
                                                         const int* __restrict__ ci, const T* __restrict__ v,
                                                         const T* __restrict__ dinv, const T* __restrict__ g,
                                                         const T* __restrict__ xp, T w, TOUT* __restrict__ z,
-                                                        ScatterT<T> sc) {
-    const int t = blockIdx.x * BS + threadIdx.x;
+                                                        ScatterT<T> sc, int pin) {
+    const int blk = pinned_block(pin);
+    if (blk < 0) return;
+    const int t = blk * BS + threadIdx.x;
     const int row = t / LPR, lane = t % LPR;
     T s = row < n ? row_ax<LPR>(row, lane, rp, ci, v, xp) : T(0);
     s = group_sum<LPR>(s);
@@ -226,13 +246,16 @@ template <class T, class TOUT>
 void vc_prolong_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, const ScatterT<T>* sc,
                      hipStream_t s) {
     const ScatterT<T> none{nullptr, nullptr, nullptr, T(0)};
-#define CALL(W)                                                                                                 \
-    if (sc)                                                                                                    \
-        hipLaunchKernelGGL((k_vc_prolong_post<W, T, TOUT, true>), dim3(level_blocks(L.n, W)), dim3(BS), 0, s, \
-                           L.n, L.rp, L.ci, L.v, L.dinv, g, xp, w, z, *sc);                                    \
-    else                                                                                                       \
-        hipLaunchKernelGGL((k_vc_prolong_post<W, T, TOUT, false>), dim3(level_blocks(L.n, W)), dim3(BS), 0, s, \
-                           L.n, L.rp, L.ci, L.v, L.dinv, g, xp, w, z, none)
+#define CALL(W)                                                                                          \
+    {                                                                                                    \
+        const int nb = level_blocks(L.n, W);                                                             \
+        if (sc)                                                                                          \
+            hipLaunchKernelGGL((k_vc_prolong_post<W, T, TOUT, true>), pinned_grid(nb), dim3(BS), 0, s, L.n, \
+                               L.rp, L.ci, L.v, L.dinv, g, xp, w, z, *sc, pin_of(nb));                   \
+        else                                                                                             \
+            hipLaunchKernelGGL((k_vc_prolong_post<W, T, TOUT, false>), pinned_grid(nb), dim3(BS), 0, s, L.n, \
+                               L.rp, L.ci, L.v, L.dinv, g, xp, w, z, none, pin_of(nb));                  \
+    }
     AMG_DISPATCH_LPR(L.lpr, CALL)
 #undef CALL
 }
@@ -265,13 +288,15 @@ constexpr int DENSE_WAVES = DENSE_BS / kWave;
 template <class T, class TIN, class TOUT>
 __global__ __launch_bounds__(DENSE_BS) void k_vc_dense(int n, const double* __restrict__ ainv_t,
                                                        const TIN* __restrict__ f, TOUT* __restrict__ x,
-                                                       ScatterT<T> sc) {
+                                                       ScatterT<T> sc, int pin) {
     __shared__ double fs[1024];
     __shared__ double part[DENSE_WAVES][DENSE_ROWS];
+    const int blk = pinned_block(pin);
+    if (blk < 0) return;
     for (int j = threadIdx.x; j < n; j += DENSE_BS) fs[j] = double(f[j]);
     __syncthreads();
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-    const int i = blockIdx.x * DENSE_ROWS + lane;
+    const int i = blk * DENSE_ROWS + lane;
     double s0 = 0.0, s1 = 0.0;
     if (i < n) {
         int j = w;
@@ -295,8 +320,9 @@ __global__ __launch_bounds__(DENSE_BS) void k_vc_dense(int n, const double* __re
 template <class T, class TIN, class TOUT>
 void vc_dense_apply(int n, const double* ainv_t, const TIN* f, TOUT* x, const ScatterT<T>* sc, hipStream_t s) {
     const ScatterT<T> none{nullptr, nullptr, nullptr, T(0)};
-    hipLaunchKernelGGL((k_vc_dense<T, TIN, TOUT>), dim3((n + DENSE_ROWS - 1) / DENSE_ROWS), dim3(DENSE_BS), 0, s, n,
-                       ainv_t, f, x, sc ? *sc : none);
+    const int nb = (n + DENSE_ROWS - 1) / DENSE_ROWS;
+    hipLaunchKernelGGL((k_vc_dense<T, TIN, TOUT>), pinned_grid(nb), dim3(DENSE_BS), 0, s, n, ainv_t, f, x,
+                       sc ? *sc : none, pin_of(nb));
 }
 
 // float copies of the level values and inverse diagonals, rounded to nearest
