@@ -15,11 +15,13 @@
 // round r while its stamp is >= r, so all reads in a round see the state at
 // the start of the round whatever the interleaving.
 //
-// Three drivers run the rounds: one kernel launch per round over the whole
-// GPU (large passes), one workgroup running every round with the state in
-// global memory (mid-size passes), and one workgroup with the round stamps,
-// ready counters and worklists in LDS (small passes), where a round costs
-// two global loads (the two adjacency records) instead of eight.
+// Drivers: one workgroup with the round stamps, ready counters and worklists
+// in LDS (passes up to kHemLdsRows rows; a round costs the two adjacency
+// record loads), the same per system of a block-diagonal batch, and tiles of
+// consecutive rows with one such workgroup each, all in one launch (larger
+// passes; the tiles exchange decisions through one published word per
+// vertex).  One kernel launch per round over the whole GPU and one workgroup
+// with the state in global memory remain for passes the tiles do not take.
 #include <cstdint>
 
 #include "amg_device.hpp"
