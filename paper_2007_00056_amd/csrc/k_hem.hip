@@ -703,17 +703,17 @@ __global__ __launch_bounds__(hem_nt<SIDE>()) void k_hem_lds(int n, HemState S, c
 
 // Systems stored one after another (a block-diagonal operator): block b
 // matches system seg[b] = (first vertex, rows) with the LDS-state rounds when
-// it has at most kHemLdsRows rows (larger ones are left to the other
+// it has at most lim (<= kHemLdsRows) rows (larger ones are left to the other
 // drivers), then marks its vertices as decided before round 0 in the global
 // stamps so that those drivers skip them.  Global list space: the system's
 // own rows of sl0 and sl1.
 template <int SIDE>
 __global__ __launch_bounds__(hem_nt<SIDE>()) void k_hem_lds_seg(const int2* __restrict__ seg, HemState S,
                                                          const int* __restrict__ lcnt_g, int* __restrict__ dec_g,
-                                                         int* sl0, int* sl1, int* cnt) {
+                                                         int* sl0, int* sl1, int* cnt, int lim) {
     const int2 sg = seg[blockIdx.x];
     const int off = sg.x, n = sg.y;
-    if (n <= 0 || n > kHemLdsRows) return;  // uniform
+    if (n <= 0 || n > lim) return;  // uniform
     int left = 0;
     const int r = hem_lds_body<SIDE>(off, n, S, lcnt_g, sl0 + off, sl1 + off, 0, true, &left);
     __syncthreads();
@@ -1301,7 +1301,8 @@ void launch_hem_lds_seg(int nseg, const int2* seg, const int* rp, const int* ci,
     if (nseg <= 0) return;
     const HemState S{rp, ci, v, w.lowok, w.rec, w.mate};
 #define CALL(SD)                                                                                                 \
-    hipLaunchKernelGGL(k_hem_lds_seg<SD>, dim3(nseg), dim3(hem_nt<SD>()), 0, s, seg, S, w.lcnt, w.dec, sl0, sl1, w.cnt)
+    hipLaunchKernelGGL(k_hem_lds_seg<SD>, dim3(nseg), dim3(hem_nt<SD>()), 0, s, seg, S, w.lcnt, w.dec, sl0, sl1, \
+                       w.cnt, w.lds_rows < kHemLdsRows ? w.lds_rows : kHemLdsRows)
     AMG_HEM_SIDE(w.side, CALL)
 #undef CALL
 }

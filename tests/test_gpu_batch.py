@@ -401,3 +401,32 @@ def test_batched_setup_at_served_sizes(torch):
             assert np.linalg.norm(b - a.to_scipy() @ xh[off[i]:off[i + 1]]) <= 1e-8 * np.linalg.norm(b) * 1.000001
     finally:
         bt.close()
+
+
+@pytest.mark.parametrize("alternate", [0, 1])
+def test_batched_setup_tiles_across_systems(torch, alternate, monkeypatch):
+    """Tiled matching inside a batched setup: with the per-system LDS limit at
+    200 rows and tiles of 37 rows, the small systems are matched one
+    workgroup each and marked decided, and the others by tiles that straddle
+    system boundaries and those decided rows.  The batch must equal the
+    hierarchies set up one by one (which use the same drivers alone)."""
+    say("alternate", alternate)
+    monkeypatch.setenv("HEMAMG_HEM_LDS", "200")
+    monkeypatch.setenv("HEMAMG_HEM_TILE", "37")
+    monkeypatch.setenv("HEMAMG_TILE_STRICT", "1")
+    systems = mix()
+    seeds = list(range(len(systems)))
+    params = hemamg.amg_params_default(alternate=alternate)
+    xs, infos = separate(torch, systems, params, seeds)
+    bt, devs = setup_batch(torch, systems, params, seeds)
+    try:
+        assert bt.status == [hemamg.AMG_OK] * len(systems)
+        off = bt.offsets
+        rhs = torch.from_numpy(np.concatenate([P.rhs_uniform(a.n, s) for a, s in zip(systems, seeds)])).cuda()
+        x, inf2 = bt.solve(rhs, rtol=1e-8, maxit=500)
+        xh = x.cpu().numpy()
+        for i in range(len(systems)):
+            assert inf2[i]["iters"] == infos[i]["iters"], (i, inf2[i], infos[i])
+            np.testing.assert_array_equal(bits(xh[off[i]:off[i + 1]]), bits(xs[i]), err_msg=f"system {i}")
+    finally:
+        bt.close()
