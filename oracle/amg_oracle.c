@@ -6,8 +6,10 @@
  * accumulation, and each function names the passage of the paper it follows.
  *
  * Readings taken where the paper is silent or garbled:
- *  - heavy-edge ties go to the lowest column index (strict '>' while scanning
- *    a row in ascending column order); explicit zeros are not edges;
+ *  - among equal heavy-edge weights the lowest column index wins (the highest
+ *    in a pass from the last index); explicit zeros are not edges;
+ *  - a level that stalls (no row merged) or reaches the depth limit becomes
+ *    the dense coarsest level if it has at most max_dense_rows (4096) rows;
  *  - a level applies `passes_per_level` matching passes, each on the Galerkin
  *    operator of the previous pass, and composes their aggregate maps;
  *  - a coarse entry (I,J) is the sum of the fine entries b_ij with i in I,
@@ -31,68 +33,67 @@
 
 /* ------------------------------------------------------------------------ */
 /* Section 2.1.1, Algorithm 2: node-based heavy edge matching.               */
-/* Visit the vertices in ascending order.  An unassigned vertex i is paired  */
-/* with the unassigned neighbour j != i (a_ij stored and non-zero) of        */
-/* largest |a_ij|; if it has none it stays a singleton.                      */
 /* ------------------------------------------------------------------------ */
-int oracle_hem_pass(int32_t n, const int32_t* rp, const int32_t* ci, const double* v, int32_t* mate) {
-    char* assigned = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
-    if (!assigned) return ORACLE_ENOMEM;
-    for (int32_t i = 0; i < n; ++i) mate[i] = -1;
-    for (int32_t i = 0; i < n; ++i) {
-        if (assigned[i]) continue;
-        double k = -1.0;
-        int32_t match = -1;
-        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
-            int32_t j = ci[e];
-            if (j == i || assigned[j] || v[e] == 0.0) continue;
-            double w = fabs(v[e]);
-            if (w > k) { /* strict: the first (lowest j) of equal weights wins */
-                k = w;
-                match = j;
-            }
+/* Preference between two free neighbours of a vertex: the heavier coupling  */
+/* |a_ij| wins; between equal weights the lower column wins when vertices    */
+/* are visited upward and the higher column when they are visited downward   */
+/* (the neighbour met first in the visiting direction).                      */
+static int prefer(double w, int32_t j, double best_w, int32_t best_j, int down) {
+    if (best_j < 0) return 1;
+    if (w != best_w) return w > best_w;
+    return down ? j > best_j : j < best_j;
+}
+
+/* The most preferred neighbour of vertex i that is still free: a stored,   */
+/* non-zero off-diagonal entry a_ij with j not yet taken.  -1 if none.       */
+static int32_t heaviest_free(const int32_t* rp, const int32_t* ci, const double* v, const char* taken, int32_t i,
+                             int down) {
+    int32_t best_j = -1;
+    double best_w = 0.0;
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const int32_t j = ci[e];
+        if (j == i || v[e] == 0.0 || taken[j]) continue;
+        const double w = fabs(v[e]);
+        if (prefer(w, j, best_w, best_j, down)) {
+            best_w = w;
+            best_j = j;
         }
-        if (match >= 0) {
-            mate[i] = match;
-            mate[match] = i;
-            assigned[match] = 1;
-        }
-        assigned[i] = 1;
     }
-    free(assigned);
+    return best_j;
+}
+
+/* One greedy pass: each vertex, in visiting order, that nobody has taken    */
+/* yet takes its most preferred free neighbour (both become a pair) or,      */
+/* without one, stays alone.  mate[u] = partner, or -1 for a singleton.      */
+static int greedy_pass(int32_t n, const int32_t* rp, const int32_t* ci, const double* v, int32_t* mate, int down) {
+    char* taken = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!taken) return ORACLE_ENOMEM;
+    for (int32_t u = 0; u < n; ++u) mate[u] = -1;
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t u = down ? n - 1 - t : t;
+        if (taken[u]) continue;
+        taken[u] = 1;
+        const int32_t w = heaviest_free(rp, ci, v, taken, u, down);
+        if (w >= 0) {
+            mate[u] = w;
+            mate[w] = u;
+            taken[w] = 1;
+        }
+    }
+    free(taken);
     return ORACLE_OK;
 }
 
-/* Section 2.1.1: matching "from the last index".  The same greedy rule as  */
-/* above with the visiting order reversed: vertices from n-1 down to 0, and  */
-/* each row's neighbours from the highest column down, so among equal        */
-/* weights the first met (the highest index) wins.                           */
+/* Vertices visited from the first index (the order Algorithm 2 prints). */
+int oracle_hem_pass(int32_t n, const int32_t* rp, const int32_t* ci, const double* v, int32_t* mate) {
+    return greedy_pass(n, rp, ci, v, mate, 0);
+}
+
+/* Section 2.1.1, matching from the last index: the same rule with the      */
+/* vertices visited from n-1 down to 0, equal weights going to the higher   */
+/* column.                                                                   */
 int oracle_hem_pass_desc(int32_t n, const int32_t* rp, const int32_t* ci, const double* v, int32_t* mate) {
-    char* assigned = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
-    if (!assigned) return ORACLE_ENOMEM;
-    for (int32_t i = 0; i < n; ++i) mate[i] = -1;
-    for (int32_t i = n - 1; i >= 0; --i) {
-        if (assigned[i]) continue;
-        double k = -1.0;
-        int32_t match = -1;
-        for (int32_t e = rp[i + 1] - 1; e >= rp[i]; --e) {
-            int32_t j = ci[e];
-            if (j == i || assigned[j] || v[e] == 0.0) continue;
-            double w = fabs(v[e]);
-            if (w > k) {
-                k = w;
-                match = j;
-            }
-        }
-        if (match >= 0) {
-            mate[i] = match;
-            mate[match] = i;
-            assigned[match] = 1;
-        }
-        assigned[i] = 1;
-    }
-    free(assigned);
-    return ORACLE_OK;
+    return greedy_pass(n, rp, ci, v, mate, 1);
 }
 
 typedef struct {
@@ -316,7 +317,7 @@ void oracle_params_default(oracle_params* p) {
     p->passes_per_level = 2;
     p->max_coarse_rows = 64;
     p->max_levels = 32;
-    p->max_dense_rows = 1024;
+    p->max_dense_rows = 4096;
     p->stall_ratio = 0.9;
     p->hem = 0;
     p->alternate = 0;

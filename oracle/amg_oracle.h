@@ -35,7 +35,8 @@ typedef struct {
     int32_t passes_per_level; /* HEM passes composed into one level (2)        */
     int32_t max_coarse_rows;  /* stop coarsening at n <= this (64)             */
     int32_t max_levels;       /* hierarchy depth limit, coarsest included (32) */
-    int32_t max_dense_rows;   /* largest coarsest level accepted on a stall    */
+    int32_t max_dense_rows;   /* largest coarsest level accepted on a stall  *
+                               * or at the depth limit (4096)                  */
     double omega;             /* Jacobi damping (2/3)                          */
     int32_t pre, post;        /* smoothing sweeps (1, 1)                       */
     double stall_ratio;       /* a level of n <= max_dense_rows rows becomes   *

@@ -260,6 +260,26 @@ def from_dense(a: np.ndarray) -> CSR:
     return CSR(n, row_ptr, cols.astype(np.int32), a[rows, cols].copy())
 
 
+def diagonal(d) -> CSR:
+    """Diagonal matrix: no off-diagonal couplings, so matching merges nothing."""
+    d = np.asarray(d, dtype=np.float64)
+    n = d.size
+    return CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d.copy())
+
+
+def block_diag(*mats: CSR) -> CSR:
+    """Block-diagonal matrix of the given blocks, in order (columns shifted)."""
+    rps, cols, vals, r0, e0 = [np.zeros(1, dtype=np.int64)], [], [], 0, 0
+    for m in mats:
+        rps.append(np.asarray(m.row_ptr[1:], dtype=np.int64) + e0)
+        cols.append(np.asarray(m.col, dtype=np.int64) + r0)
+        vals.append(np.asarray(m.val, dtype=np.float64))
+        r0 += m.n
+        e0 += m.nnz
+    return CSR(r0, np.concatenate(rps).astype(np.int32), np.concatenate(cols).astype(np.int32),
+               np.concatenate(vals))
+
+
 # ---------------------------------------------------------------------------
 # Named workloads (sizes of the paper-scale synthetic configurations)
 # ---------------------------------------------------------------------------

@@ -125,6 +125,112 @@ def test_two_level_cycle_matches_dense_formulation():
     np.testing.assert_allclose(h.vcycle(f), x, rtol=1e-11, atol=1e-13)
 
 
+def multigrid_operator(A, Ps, omega, pre, post):
+    """B_0 with z = B_0 f for the V-cycle, from the textbook error-propagation
+    identity of multigrid (not from Algorithm 1's steps): with the Jacobi
+    iteration matrix S_k = I - omega D_k^{-1} A_k and the Galerkin operators
+    A_{k+1} = P_k^T A_k P_k, the cycle's error propagation is
+    E_k = S_k^post (I - P_k B_{k+1} P_k^T A_k) S_k^pre, B_L = A_L^{-1}, and
+    B_k = (I - E_k) A_k^{-1}."""
+    As = [A]
+    for Pm in Ps:
+        As.append(Pm.T @ As[-1] @ Pm)
+    B = np.linalg.inv(As[-1])
+    for k in range(len(Ps) - 1, -1, -1):
+        Ak, Pm = As[k], Ps[k]
+        S = np.eye(Ak.shape[0]) - omega * np.diag(1.0 / np.diag(Ak)) @ Ak
+        E = np.linalg.matrix_power(S, post) @ (np.eye(Ak.shape[0]) - Pm @ B @ Pm.T @ Ak) @ \
+            np.linalg.matrix_power(S, pre)
+        B = (np.eye(Ak.shape[0]) - E) @ np.linalg.inv(Ak)
+    return B
+
+
+@pytest.mark.parametrize("make,kw", [
+    (lambda: P.lognormal_diffusion3d(6, seed=7), dict(omega=0.6, pre=2, post=3)),
+    (lambda: P.poisson2d(14, 11), dict(omega=0.8, pre=1, post=2)),
+    (lambda: P.convdiff3d(6), dict(omega=0.5, pre=3, post=1)),
+])
+def test_three_level_cycle_matches_error_propagation_identity(make, kw):
+    """Algorithm 1 recursing through two coarse levels (max_levels = 3) with
+    non-default damping and sweep counts: the assembled V-cycle operator equals
+    the multigrid error-propagation identity built from dense P_k and
+    P_k^T A_k P_k (the oracle's coarse matrices are not used)."""
+    a = make()
+    h = oracle.Hierarchy(a, max_levels=3, max_coarse_rows=8, **kw)
+    assert h.nlevels == 3
+    A = a.to_scipy().toarray()
+    Ps = []
+    for k in range(2):
+        agg = h.level(k).agg
+        Pm = np.zeros((agg.size, h.level(k + 1).n))
+        Pm[np.arange(agg.size), agg] = 1.0
+        Ps.append(Pm)
+    B = multigrid_operator(A, Ps, kw["omega"], kw["pre"], kw["post"])
+    M = assembled_preconditioner(h, a.n)
+    assert np.abs(M - B).max() <= 1e-10 * np.abs(B).max()
+    # a dropped coarse correction or a wrong sweep count is far off
+    B_wrong = multigrid_operator(A, Ps, kw["omega"], kw["pre"], kw["post"] + 1)
+    assert np.abs(M - B_wrong).max() > 1e-3 * np.abs(B).max()
+
+
+def poisson_beside_diagonal():
+    """A 64x64 Poisson block (coarsens 4:1) beside a 2000-row diagonal block
+    (merges nothing): coarsening ends at a level of 1025..4096 rows."""
+    return P.block_diag(P.poisson2d(64), P.diagonal(np.arange(1.0, 2001.0)))
+
+
+def poisson_beside_star():
+    """A 64x64 Poisson block beside a 1500-row star (two rows merge per level)."""
+    return P.block_diag(P.poisson2d(64), P.star_graph(1500, 2))
+
+
+@pytest.mark.parametrize("make,kw,coarsest,why", [
+    (poisson_beside_diagonal, dict(stall_ratio=1.0), 2001, "no row merged"),
+    (poisson_beside_star, dict(stall_ratio=1.0), 1439, "depth limit"),
+    (poisson_beside_diagonal, dict(), 2256, "poor progress"),
+    (poisson_beside_star, dict(), 1558, "poor progress"),
+])
+def test_stalled_coarsening_ends_in_a_dense_level_of_up_to_4096_rows(make, kw, coarsest, why):
+    """Section 3 setup with the stop readings: a level that stalls (nothing
+    merged, or the depth limit) becomes the dense coarsest when it has at most
+    max_dense_rows = 4096 rows, and so does one of at most that size whose
+    coarsening would keep 90% of its rows; above the limit a stall is an
+    error.  The solve with the dense coarsest still reaches a manufactured
+    solution."""
+    a = make()
+    h = oracle.Hierarchy(a, **kw)
+    sizes = [h.level(k).n for k in range(h.nlevels)]
+    assert sizes[-1] == coarsest and 1024 < coarsest <= 4096, (why, sizes)
+    xs = np.random.default_rng(3).standard_normal(a.n)
+    b = a.to_scipy() @ xs
+    x, info = h.solve(b, rtol=1e-12, maxit=300)
+    assert info["status"] == oracle.OK
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+    if why != "poor progress":
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.Hierarchy(a, max_dense_rows=coarsest - 1, **kw)
+        assert e.value.status == oracle.ESTALL
+
+
+def test_dense_level_at_the_4096_row_limit_and_above():
+    d = np.linspace(1.0, 7.0, 4096)
+    h = oracle.Hierarchy(P.diagonal(d))
+    assert h.nlevels == 1
+    b = P.rhs_uniform(4096, 2)
+    np.testing.assert_allclose(h.vcycle(b), b / d, rtol=1e-15)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Hierarchy(P.diagonal(np.linspace(1.0, 7.0, 4097)))
+    assert e.value.status == oracle.ESTALL
+
+
+def test_single_dense_level_of_a_star_is_the_exact_solve():
+    a = P.star_graph(3000, 2)  # coarsening would keep 2998 of 3000 rows
+    h = oracle.Hierarchy(a)
+    assert h.nlevels == 1
+    b = P.rhs_uniform(a.n, 4)
+    np.testing.assert_allclose(h.vcycle(b), sla.solve(a.to_scipy().toarray(), b), rtol=1e-11)
+
+
 # ---------------------------------------------------------------- PCG / BiCGStab
 
 def test_pcg_manufactured_solution_and_dense_solve():
