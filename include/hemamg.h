@@ -57,10 +57,12 @@ typedef struct {
 /* Hierarchy and cycle parameters (Section 3 setup phase; Algorithm 1). */
 typedef struct {
     int32_t passes_per_level; /* matching passes composed per level: 1 or 2 (2)   */
-    int32_t max_coarse_rows;  /* coarsen until n <= this, 1..1024 (64)            */
+    int32_t max_coarse_rows;  /* coarsen until n <= this, 1..4096 (64)            */
     int32_t max_levels;       /* levels including the coarsest, 1..64 (32)        */
     int32_t max_dense_rows;   /* largest coarsest level accepted when coarsening  *
-                               * stalls or hits max_levels, <= 1024 (1024)        */
+                               * stalls or hits max_levels, 1..4096 (4096); the   *
+                               * coarsest level is factored densely (LU) and      *
+                               * applied as an explicit inverse                   */
     double omega;             /* damped-Jacobi weight (2/3)                       */
     int32_t pre, post;        /* smoothing sweeps before/after the coarse
                                * correction, 0..8 (1, 1)                          */
@@ -95,9 +97,36 @@ typedef struct {
     int32_t iters;       /* number of solution updates performed               */
     double rel_res;      /* recursive ||r|| / ||b|| at the stop                */
     double true_rel_res; /* ||b - A x|| / ||b|| at the stop (last recomputed) */
+    double setup_ms;     /* host wall time of the setup call that built the
+                          * hierarchy (amg_setup, or amg_batch_setup for the
+                          * whole batch; 0 for a batch made by
+                          * amg_batch_create)                                  */
     double solve_ms;     /* host wall time of the call                         */
+    int32_t levels;      /* levels of the hierarchy, the coarsest included     */
     int32_t status;      /* same as the return value                           */
 } amg_info;
+
+/* Device-memory allocator (the setup phase of Section 3 builds every coarse
+ * level in GPU memory; Section 3.1 makes that memory the scarce resource, so
+ * the caller may own it).  Every device buffer a handle or batch owns, and
+ * every temporary of its setup, is drawn through it in a few large chunks:
+ *  - alloc(bytes, ctx, stream) returns `bytes` (a multiple of 256) of device
+ *    memory on the current device, 256-byte aligned, usable by work enqueued
+ *    on `stream` (a hipStream_t, possibly NULL), or NULL on failure (the
+ *    entry point then returns AMG_ENOMEM after freeing what it drew);
+ *  - free(ptr, ctx, stream) returns a block alloc gave.  Work enqueued on
+ *    `stream` may still use the block: the allocator must reuse it only for
+ *    work ordered after that (stream-ordered release, as hipFreeAsync and
+ *    PyTorch's caching allocator do).
+ * Both are called on the thread of the entry point (for a server, on its
+ * worker threads).  The allocator must outlive every handle, batch and
+ * server it was given to.  Passing NULL (or a struct whose alloc is NULL)
+ * uses the library's own stream-ordered pool. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* ctx, void* stream);
+    void (*free)(void* ptr, void* ctx, void* stream);
+    void* ctx;
+} amg_allocator;
 
 /* Fills *p with the defaults shown above.  [host] */
 amg_status amg_params_default(amg_params* p);
@@ -107,11 +136,13 @@ amg_status amg_params_default(amg_params* p);
  * in-range columns, non-zero finite diagonal, finite values, structural
  * symmetry), builds every level on the GPU and returns a handle in *out
  * (*out = NULL on error).  Blocks the host until the stream has finished.
- * Coarse levels, D^{-1}, aggregate maps and the coarsest inverse are owned by
- * the handle; level 0 is borrowed from A.
- * Errors: AMG_EINVAL, AMG_ENOTFINITE, AMG_ESTALL, AMG_ESINGULAR, AMG_ENOMEM,
- * AMG_EHIP. */
-amg_status amg_setup(const amg_csr* A, const amg_params* params, void* stream, amg_hier** out);
+ * Coarse levels, D^{-1}, aggregate maps, the coarsest inverse and (at the
+ * first solve) the Krylov workspace are owned by the handle and drawn through
+ * `alloc` (NULL: the library's pool); level 0 is borrowed from A.
+ * Errors: AMG_EINVAL, AMG_ENOTFINITE, AMG_ESTALL, AMG_ESINGULAR, AMG_ENOMEM
+ * (an allocation failed; nothing drawn stays allocated), AMG_EHIP. */
+amg_status amg_setup(const amg_csr* A, const amg_params* params, const amg_allocator* alloc, void* stream,
+                     amg_hier** out);
 
 /* Releases every buffer owned by the handle (after synchronising its last
  * stream).  NULL is accepted. */
@@ -131,9 +162,10 @@ amg_status amg_vcycle(amg_hier* h, const double* r, double* z, void* stream);
  * stationary solver recomputes the residual every iteration).
  * b: [device] float64[n]; x: [device] float64[n], initial guess on entry,
  * the last iterate on return (also on AMG_ENOTCONV and AMG_EBREAKDOWN).
- * info: [host], may be NULL.  Blocks the host until done.
+ * info: [host], may be NULL.  Blocks the host until done.  The first solve
+ * of a handle draws its Krylov workspace through the handle's allocator.
  * Errors: AMG_EINVAL, AMG_ENOTFINITE (b or x0 not finite), AMG_ENOTCONV,
- * AMG_EBREAKDOWN, AMG_EHIP. */
+ * AMG_EBREAKDOWN, AMG_ENOMEM (workspace), AMG_EHIP. */
 amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x, double rtol, int32_t maxit,
                         void* stream, amg_info* info);
 
@@ -196,6 +228,10 @@ typedef struct {
                                * worker (0)                                      */
     uint64_t hbm_budget_bytes; /* admission budget (64 GiB)                     */
     amg_params params;        /* hierarchy and cycle parameters of every request */
+    amg_allocator alloc;      /* device memory of every request's hierarchy,
+                               * workspace and batch buffers, drawn on the
+                               * worker threads (alloc = NULL: the library's
+                               * pool) (NULL)                                    */
 } amg_server_config;
 
 /* Upper estimate of the device memory one request of n rows and nnz entries
@@ -214,10 +250,14 @@ amg_status amg_server_create(const amg_server_config* c, amg_server** out);
 /* Queues one request: A (borrowed, [device] arrays as in amg_setup), b and x
  * ([device] float64[n]; x holds the initial guess) must stay valid until
  * amg_server_wait returns for it.  method/rtol/maxit as in krylov_solve.
+ * stream: the producer's stream (NULL: the default stream); the worker
+ * reads A, b and x only after the work enqueued on it before this call has
+ * finished, so they may still be written asynchronously there.  The worker
+ * writes x on its own stream; amg_server_wait returns after that write.
  * Returns at once with a ticket.  Errors: AMG_EINVAL (NULL argument, or a
- * footprint above the whole budget). */
+ * footprint above the whole budget), AMG_EHIP. */
 amg_status amg_server_submit(amg_server* s, const amg_csr* A, const double* b, double* x, int32_t method,
-                             double rtol, int32_t maxit, int64_t* ticket);
+                             double rtol, int32_t maxit, void* stream, int64_t* ticket);
 
 /* Blocks until request `ticket` has finished and releases it (one wait per
  * ticket; a second wait returns AMG_EINVAL).  info [host]
@@ -247,9 +287,11 @@ typedef struct amg_batch amg_batch;
 
 /* Builds a batch from `count` hierarchies (order kept).  Every hierarchy needs
  * at least two levels and pre = post = 1, and all must share precond_fp32,
- * omega and true_res_period.  Blocks the host until the copies are done.
- * Errors: AMG_EINVAL, AMG_ENOMEM, AMG_EHIP. */
-amg_status amg_batch_create(const amg_hier* const* hiers, int32_t count, void* stream, amg_batch** out);
+ * omega and true_res_period.  The batch's device memory is drawn through
+ * `alloc` (NULL: the library's pool).  Blocks the host until the copies are
+ * done.  Errors: AMG_EINVAL, AMG_ENOMEM, AMG_EHIP. */
+amg_status amg_batch_create(const amg_hier* const* hiers, int32_t count, const amg_allocator* alloc, void* stream,
+                            amg_batch** out);
 
 /* Batched setup (the setup phase of Section 3 for many systems at once): the
  * systems' levels are built together on block-diagonal concatenations of
@@ -263,9 +305,11 @@ amg_status amg_batch_create(const amg_hier* const* hiers, int32_t count, void* s
  * (invalid matrix, stall, singular coarsest level, or a single level) gets
  * its status there, takes no rows in the batch and reports the status from
  * amg_batch_solve.  A matrix that is not structurally symmetric fails the
- * whole call.  Blocks the host.  Errors: AMG_EINVAL, AMG_ENOMEM, AMG_EHIP. */
-amg_status amg_batch_setup(const amg_csr* A, int32_t count, const amg_params* params, void* stream,
-                           amg_batch** out, amg_status* status);
+ * whole call.  Device memory (the batch and the setup's temporaries) is drawn
+ * through `alloc` (NULL: the library's pool).  Blocks the host.
+ * Errors: AMG_EINVAL, AMG_ENOMEM, AMG_EHIP. */
+amg_status amg_batch_setup(const amg_csr* A, int32_t count, const amg_params* params, const amg_allocator* alloc,
+                           void* stream, amg_batch** out, amg_status* status);
 
 /* offsets: [host] int32[count + 1]; system i occupies rows
  * offsets[i] .. offsets[i+1]-1 of the batch vectors. */

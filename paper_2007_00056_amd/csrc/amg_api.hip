@@ -132,8 +132,10 @@ void check_err_word(const int* err, hipStream_t s, const char* where) { raise_er
 
 void validate_params(const amg_params& p) {
     if (p.passes_per_level < 1 || p.passes_per_level > 2) raise(AMG_EINVAL, "passes_per_level must be 1 or 2");
-    if (p.max_coarse_rows < 1 || p.max_coarse_rows > 1024) raise(AMG_EINVAL, "max_coarse_rows must be in 1..1024");
-    if (p.max_dense_rows < 1 || p.max_dense_rows > 1024) raise(AMG_EINVAL, "max_dense_rows must be in 1..1024");
+    if (p.max_coarse_rows < 1 || p.max_coarse_rows > kDenseMaxRows)
+        raise(AMG_EINVAL, "max_coarse_rows must be in 1..%d", kDenseMaxRows);
+    if (p.max_dense_rows < 1 || p.max_dense_rows > kDenseMaxRows)
+        raise(AMG_EINVAL, "max_dense_rows must be in 1..%d", kDenseMaxRows);
     if (p.max_levels < 1 || p.max_levels > 64) raise(AMG_EINVAL, "max_levels must be in 1..64");
     if (p.pre < 0 || p.pre > 8 || p.post < 0 || p.post > 8) raise(AMG_EINVAL, "pre/post sweeps must be in 0..8");
     if (!std::isfinite(p.omega)) raise(AMG_EINVAL, "omega must be finite");
@@ -411,16 +413,18 @@ void alloc_workspace(amg_hier* h) {
     if (h->r) return;
     const int n = h->lev[0].n;
     DevPool& P = h->pool;
-    h->r = P.get<double>(n);
-    h->z = P.get<double>(n);
-    h->pv[0] = P.get<double>(n);
-    h->pv[1] = P.get<double>(n);
-    h->q = P.get<double>(n);
-    h->rb = P.get<double>(n);
-    h->pt = P.get<double>(n);
-    h->sv = P.get<double>(n);
-    h->st = P.get<double>(n);
-    h->t = P.get<double>(n);
+    double* v[10];
+    for (double*& p : v) p = P.get<double>(n);  // all or none: an allocation failure leaves h->r unset
+    h->z = v[1];
+    h->pv[0] = v[2];
+    h->pv[1] = v[3];
+    h->q = v[4];
+    h->rb = v[5];
+    h->pt = v[6];
+    h->sv = v[7];
+    h->st = v[8];
+    h->t = v[9];
+    h->r = v[0];
 }
 
 void timer_reserve(Timer& T) {
@@ -899,9 +903,12 @@ amg_status bicgstab(amg_hier* h, const double* b, double* x, double rtol, int ma
     return AMG_ENOTCONV;
 }
 
-void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hier** out) {
+void setup_impl(const amg_csr* Ain, const amg_params* pin, const amg_allocator* alloc, hipStream_t s,
+                amg_hier** out) {
+    const auto t0 = std::chrono::steady_clock::now();
     if (!Ain || !out) raise(AMG_EINVAL, "amg_setup: NULL argument");
     *out = nullptr;
+    const amg_allocator al = checked_allocator(alloc);
     amg_params p;
     amg_params_default(&p);
     if (pin) p = *pin;
@@ -915,6 +922,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     h->p = p;
     h->stream = s;
     h->pool.s = s;
+    h->pool.al = al;
     DevPool& P = h->pool;
     P.hint(6 * (size_t)A.nnz + 96 * (size_t)A.n + (size_t(1) << 20));  // most of the hierarchy in one chunk
     h->err = P.get<int>(1);
@@ -935,6 +943,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
 
     DevPool wpool;
     wpool.s = s;
+    wpool.al = al;
     wpool.hint((size_t)A.nnz * (p.hem == 1 ? 9 : 1) + 168 * (size_t)A.n + 4096 +
                (p.alternate ? 12 * (size_t)A.nnz + 4 * (size_t)A.n : 0));
     struct WpoolGuard {
@@ -954,6 +963,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
         }
         DevPool tmp;
         tmp.s = s;
+        tmp.al = al;
         tmp.hint(4 * (size_t)F.n + 12 * (size_t)F.nnz + 4096);  // the intermediate operator of pass 1
         struct TmpGuard {
             DevPool& t;
@@ -1013,24 +1023,23 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     const int m = Lc.n;
     h->n_coarse = m;
     {
+        if (m > kDenseMaxRows) raise(AMG_EHIP, "coarsest level of %d rows exceeds the dense limit (internal error)", m);
         DevPool tmp;
         tmp.s = s;
+        tmp.al = al;
         tmp.hint(8 * (size_t)m * m + 8 * (size_t)m + 4096);
+        struct TmpGuard {
+            DevPool& t;
+            ~TmpGuard() { t.release(); }
+        } tg{tmp};
         double* a = tmp.get<double>((size_t)m * m);
         int* piv = tmp.get<int>(2 * (size_t)m);  // permutation and pivot rows
-        if (m > 1024) raise(AMG_EHIP, "coarsest level of %d rows exceeds the dense limit (internal error)", m);
         h->ainv_t = P.get<double>((size_t)m * m);
         HIPCHK(hipMemsetAsync(a, 0, sizeof(double) * (size_t)m * m, s));
         launch_dense_assemble(m, Lc.rp, Lc.ci, Lc.v, a, s);
         launch_dense_lu_inverse(m, a, piv, h->ainv_t, h->err, s);
         HIPCHK(hipGetLastError());
-        try {
-            check_err_word(h->err, s, "coarsest level");
-        } catch (...) {
-            tmp.release();
-            throw;
-        }
-        tmp.release();
+        check_err_word(h->err, s, "coarsest level");
     }
     // per-level work vectors, float copies of the values for a float V-cycle
     const bool fused = p.pre == 1 && p.post == 1;
@@ -1063,6 +1072,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, hipStream_t s, amg_hi
     static_assert(S_COUNT * sizeof(double) <= kPinnedBlock, "slots");
     h->S_host = static_cast<double*>(pinned_get());
     HIPCHK(hipStreamSynchronize(s));
+    h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = h.release();
 }
 
@@ -1291,6 +1301,7 @@ void batch_coarsen(const amg_csr* A, int count, const amg_params& p, hipStream_t
     std::vector<Coarsest> fin;
     DevPool wpool;
     wpool.s = s;
+    wpool.al = P.al;
     wpool.hint((size_t)E * (p.hem == 1 ? 9 : 1) + 168 * (size_t)N + 4096 +
                (p.alternate ? 12 * (size_t)E + 4 * (size_t)N : 0));
     struct WpoolGuard {
@@ -1436,7 +1447,7 @@ void batch_coarsen(const amg_csr* A, int count, const amg_params& p, hipStream_t
             S.status = AMG_EINVAL;
             continue;
         }
-        if (m > 1024) raise(AMG_EHIP, "coarsest level of %d rows exceeds the dense limit (internal error)", m);
+        if (m > kDenseMaxRows) raise(AMG_EHIP, "coarsest level of %d rows exceeds the dense limit (internal error)", m);
         double* a = P.get<double>((size_t)m * m);
         int* piv = P.get<int>(2 * (size_t)m);
         double* ainv = P.get<double>((size_t)m * m);
@@ -1468,7 +1479,7 @@ amg_status amg_params_default(amg_params* p) {
     p->passes_per_level = 2;
     p->max_coarse_rows = 64;
     p->max_levels = 32;
-    p->max_dense_rows = 1024;
+    p->max_dense_rows = kDenseMaxRows;
     p->omega = 2.0 / 3.0;
     p->pre = 1;
     p->post = 1;
@@ -1480,9 +1491,10 @@ amg_status amg_params_default(amg_params* p) {
     return AMG_OK;
 }
 
-amg_status amg_setup(const amg_csr* A, const amg_params* params, void* stream, amg_hier** out) {
+amg_status amg_setup(const amg_csr* A, const amg_params* params, const amg_allocator* alloc, void* stream,
+                     amg_hier** out) {
     if (out) *out = nullptr;
-    return guarded([&] { setup_impl(A, params, as_stream(stream), out); });
+    return guarded([&] { setup_impl(A, params, alloc, as_stream(stream), out); });
 }
 
 amg_status amg_destroy(amg_hier* h) {
@@ -1550,6 +1562,10 @@ amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x,
     if (g != AMG_OK) st = g;
     I.status = st;
     I.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (h) {
+        I.setup_ms = h->setup_ms;
+        I.levels = (int32_t)h->lev.size();
+    }
     return st;
 }
 

@@ -120,6 +120,7 @@ struct amg_batch {
     hipStream_t stream = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     amg::DevPool pool;
+    double setup_ms = 0.0;  // amg_batch_setup: host wall time of the call
 
     BatchTab tab(const int* mask) const { return BatchTab{btab, seg_end, mask}; }
 
@@ -570,8 +571,8 @@ void build_dense(amg_batch* B, std::vector<char>& host, size_t at_dd, size_t at_
 
 // Lays out a batch from the systems' levels wherever they are stored (see
 // SegSrc); blocks the host until the copies are done.
-void create_impl(const std::vector<SegSrc>& src, bool prec32, double omega, int period, hipStream_t caller,
-                 amg_batch** out) {
+void create_impl(const std::vector<SegSrc>& src, bool prec32, double omega, int period, const amg_allocator& al,
+                 hipStream_t caller, amg_batch** out) {
     const int count = (int)src.size();
     std::unique_ptr<amg_batch> B(new amg_batch());
     B->nseg = count;
@@ -585,6 +586,7 @@ void create_impl(const std::vector<SegSrc>& src, bool prec32, double omega, int 
     HIPCHK(hipEventRecord(B->ev[0], caller));
     HIPCHK(hipStreamWaitEvent(s, B->ev[0], 0));
     B->pool.s = s;
+    B->pool.al = al;
     const int ns = count;
     int K = 0;
     for (int i = 0; i < ns; ++i) K = std::max(K, (int)src[i].lev.size());
@@ -871,10 +873,12 @@ void gather_run(const std::vector<GatherPiece>& pcs, DevPool& P, hipStream_t s) 
 
 extern "C" {
 
-amg_status amg_batch_create(const amg_hier* const* hiers, int32_t count, void* stream, amg_batch** out) {
+amg_status amg_batch_create(const amg_hier* const* hiers, int32_t count, const amg_allocator* alloc, void* stream,
+                            amg_batch** out) {
     if (out) *out = nullptr;
     return guarded([&] {
         if (!hiers || !out || count < 1 || count > (1 << 20)) raise(AMG_EINVAL, "amg_batch_create: bad arguments");
+        const amg_allocator al = checked_allocator(alloc);
         std::vector<SegSrc> src(count);
         for (int i = 0; i < count; ++i) {
             const amg_hier* h = hiers[i];
@@ -900,15 +904,17 @@ amg_status amg_batch_create(const amg_hier* const* hiers, int32_t count, void* s
             }
             src[i].ainv_t = h->ainv_t;
         }
-        create_impl(src, hiers[0]->prec32, hiers[0]->p.omega, hiers[0]->p.true_res_period, as_stream(stream), out);
+        create_impl(src, hiers[0]->prec32, hiers[0]->p.omega, hiers[0]->p.true_res_period, al, as_stream(stream), out);
     });
 }
 
-amg_status amg_batch_setup(const amg_csr* A, int32_t count, const amg_params* params, void* stream, amg_batch** out,
-                           amg_status* status) {
+amg_status amg_batch_setup(const amg_csr* A, int32_t count, const amg_params* params, const amg_allocator* alloc,
+                           void* stream, amg_batch** out, amg_status* status) {
     if (out) *out = nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
     return guarded([&] {
         if (!A || !out || count < 1 || count > (1 << 20)) raise(AMG_EINVAL, "amg_batch_setup: bad arguments");
+        const amg_allocator al = checked_allocator(alloc);
         amg_params p;
         amg_params_default(&p);
         if (params) p = *params;
@@ -918,6 +924,7 @@ amg_status amg_batch_setup(const amg_csr* A, int32_t count, const amg_params* pa
         hipEvent_t ev = event_get(false);
         DevPool P;
         P.s = s;
+        P.al = al;
         struct Guard {
             DevPool& P;
             hipStream_t s;
@@ -936,9 +943,10 @@ amg_status amg_batch_setup(const amg_csr* A, int32_t count, const amg_params* pa
         batch_coarsen(A, count, p, s, P, src);
         if (status)
             for (int i = 0; i < count; ++i) status[i] = src[i].status;
-        create_impl(src, p.precond_fp32 != 0, p.omega, p.true_res_period, s, out);
+        create_impl(src, p.precond_fp32 != 0, p.omega, p.true_res_period, al, s, out);
         HIPCHK(hipEventRecord(ev, s));
         HIPCHK(hipStreamWaitEvent(caller, ev, 0));
+        (*out)->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     });
 }
 
@@ -987,7 +995,11 @@ amg_status amg_batch_solve(amg_batch* B, int32_t method, const double* b, double
     }
     if (B && info) {
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        for (int i = 0; i < B->nseg; ++i) info[i].solve_ms = ms;
+        for (int i = 0; i < B->nseg; ++i) {
+            info[i].solve_ms = ms;
+            info[i].setup_ms = B->setup_ms;
+            info[i].levels = B->seg[i].nlev;
+        }
     }
     return st;
 }

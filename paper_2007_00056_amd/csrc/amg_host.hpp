@@ -11,6 +11,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "amg_internal.hpp"
@@ -85,13 +86,25 @@ inline hipMemPool_t lib_pool() {
     return pool;
 }
 
-// An arena over the pool: pieces (256-byte aligned) are carved from a few
-// chunks (sized from a hint, or by a larger request), so a handle makes a
-// handful of pool calls instead of one per array.
+// The caller's allocator (amg_allocator), checked and copied: both
+// functions set, or neither (then the library pool serves).
+inline amg_allocator checked_allocator(const amg_allocator* a) {
+    amg_allocator r{};
+    if (!a || (!a->alloc && !a->free)) return r;
+    if (!a->alloc || !a->free) raise(AMG_EINVAL, "amg_allocator: alloc and free must both be set");
+    return *a;
+}
+
+// An arena over the pool (or the caller's allocator): pieces (256-byte
+// aligned) are carved from a few chunks (sized from a hint, or by a larger
+// request), so a handle makes a handful of allocation calls instead of one
+// per array.  Chunks are released stream-ordered on the stream they were
+// drawn on.
 struct DevPool {
     hipStream_t s = nullptr;
     hipMemPool_t mp = nullptr;
-    std::vector<void*> chunks;
+    amg_allocator al{};                // al.alloc set: chunks come from the caller
+    std::vector<std::pair<void*, hipStream_t>> chunks;
     char* cur = nullptr;
     size_t left = 0;
     size_t bytes = 0;                 // device memory held (sum of chunks)
@@ -105,11 +118,16 @@ struct DevPool {
     T* get(size_t count) {
         const size_t b = (((count > 0 ? count : 1) * sizeof(T)) + 255) & ~size_t(255);
         if (b > left) {
-            if (!mp) mp = lib_pool();
             const size_t c = b > next_chunk ? b : next_chunk;
             void* p = nullptr;
-            HIPCHK(hipMallocFromPoolAsync(&p, c, mp, s));
-            chunks.push_back(p);
+            if (al.alloc) {
+                p = al.alloc(c, al.ctx, s);
+                if (!p) raise(AMG_ENOMEM, "the caller's allocator returned NULL for %zu bytes", c);
+            } else {
+                if (!mp) mp = lib_pool();
+                HIPCHK(hipMallocFromPoolAsync(&p, c, mp, s));
+            }
+            chunks.emplace_back(p, s);
             cur = static_cast<char*>(p);
             left = c;
             bytes += c;
@@ -121,7 +139,10 @@ struct DevPool {
         return r;
     }
     void release() {
-        for (void* p : chunks) (void)hipFreeAsync(p, s);
+        for (auto& c : chunks) {
+            if (al.alloc) al.free(c.first, al.ctx, c.second);
+            else (void)hipFreeAsync(c.first, c.second);
+        }
         chunks.clear();
         cur = nullptr;
         left = 0;
@@ -246,6 +267,7 @@ struct amg_hier {
     int n_coarse = 0;
     double* ainv_t = nullptr;
     DevPool pool;
+    double setup_ms = 0.0;  // host wall time of the setup call
     hipStream_t stream = nullptr;
     std::vector<int> rounds;
     // Krylov workspace (allocated on first solve)

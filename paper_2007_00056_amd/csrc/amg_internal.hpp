@@ -17,6 +17,7 @@ enum : int {
 };
 
 constexpr int kUndecided = 0x3fffffff;  // round stamp of an undecided vertex
+constexpr int kDenseMaxRows = 4096;     // largest coarsest level (dense LU, explicit inverse)
 
 // Lanes per CSR row used by the level kernels (a power of two, 1..16).
 int pick_lanes_per_row(double avg_row_len);
@@ -128,7 +129,7 @@ void launch_dense_assemble(int n, const int* rp, const int* ci, const double* v,
 // Systems stored one after another in a level: out[2j] = agg[off[j]],
 // out[2j+1] = crp[out[2j]] (coarse row and entry where system j starts).
 void launch_seg_starts(int m, const int* off, const int* agg, const int* crp, int* out, hipStream_t s);
-// piv: int32[2n] scratch.  n <= 1024.
+// piv: int32[2n] scratch.  n <= kDenseMaxRows.
 void launch_dense_lu_inverse(int n, double* a, int* piv, double* ainv_t, int* err, hipStream_t s);
 
 // ---- solve kernels (k_solve.hip) --------------------------------------------

@@ -24,7 +24,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "hemamg.h"
+#include "amg_host.hpp"
 
 namespace {
 
@@ -34,6 +34,7 @@ struct Request {
     amg_csr A{};
     const double* b = nullptr;
     double* x = nullptr;
+    hipEvent_t ready = nullptr;  // recorded on the producer's stream at submission
     int32_t method = 0;
     double rtol = 0.0;
     int32_t maxit = 0;
@@ -50,7 +51,11 @@ constexpr int32_t kSmallRows = 32768;  // systems matched in one workgroup by a 
 uint64_t footprint(int32_t n, int64_t nnz, const amg_params& p) {
     const uint64_t N = (uint64_t)(n > 0 ? n : 0), Z = (uint64_t)(nnz > 0 ? nnz : 0);
     const uint64_t e = p.precond_fp32 ? 4 : 8;
-    const uint64_t dense = 8ull * 1024 * 1024;  // coarsest inverse (<= 1024 rows)
+    // coarsest inverse: at most max(max_coarse_rows, max_dense_rows) rows, and
+    // never more than the system has
+    uint64_t m = (uint64_t)(p.max_coarse_rows > p.max_dense_rows ? p.max_coarse_rows : p.max_dense_rows);
+    if (m > N) m = N;
+    const uint64_t dense = 8 * m * m + 4096;
     // persistent: level-0 D^{-1}; coarse CSR (row pointers sized by the finer
     // level), D^{-1}, maps and member lists over <= N rows and <= Z entries;
     // V-cycle vectors; float copies; Krylov vectors; reduction partials
@@ -70,9 +75,13 @@ uint64_t footprint(int32_t n, int64_t nnz, const amg_params& p) {
 // What a request adds inside a batch: its concatenated levels (level 0
 // included), vectors and Krylov workspace, and its slices of the batch's
 // right-hand side and solution.
-uint64_t batch_extra(int32_t n, int64_t nnz) {
+uint64_t batch_extra(int32_t n, int64_t nnz, const amg_params& p) {
     const uint64_t N = (uint64_t)(n > 0 ? n : 0), Z = (uint64_t)(nnz > 0 ? nnz : 0);
-    return 60 * Z + 256 * N + 8ull * 1024 * 1024;  // also the batched setup's concatenated levels
+    uint64_t m = (uint64_t)(p.max_coarse_rows > p.max_dense_rows ? p.max_coarse_rows : p.max_dense_rows);
+    if (m > N) m = N;
+    // also the batched setup's concatenated levels and its coarsest blocks
+    // (matrix, factors and inverse)
+    return 60 * Z + 256 * N + 16 * m * m + 8 * m + 4096;
 }
 
 }  // namespace
@@ -121,8 +130,6 @@ struct amg_server {
     void worker(int i) {
         if (hipSetDevice(device) != hipSuccess) return;
         hipStream_t s = wstreams[i];
-        double* buf = nullptr;  // batched mode: right-hand sides, then solutions
-        size_t cap = 0;
         for (;;) {
             std::vector<Request*> grp;
             {
@@ -158,12 +165,20 @@ struct amg_server {
                     }
                 }
             }
+            // the worker reads b and x only after the producers' writes
+            for (Request* r : grp)
+                if (r->ready) {
+                    (void)hipStreamWaitEvent(s, r->ready, 0);
+                    amg::event_put(r->ready, false);
+                    r->ready = nullptr;
+                }
             if (!(batched() && grp[0]->method <= 1)) run_one(grp[0], s);
-            else run_group(grp, s, buf, cap);
+            else run_group(grp, s);
             for (Request* r : grp) finish(r);
         }
-        if (buf) (void)hipFree(buf);
     }
+
+    const amg_allocator* alloc() const { return cfg.alloc.alloc ? &cfg.alloc : nullptr; }
 
     // Setup, solve and teardown of one request.
     void run_one(Request* r, hipStream_t s) {
@@ -173,7 +188,10 @@ struct amg_server {
             return;
         }
         amg_hier* h = nullptr;
-        amg_status st = amg_setup(&r->A, &cfg.params, s, &h);
+        amg_status st = amg_setup(&r->A, &cfg.params, alloc(), s, &h);
+        // no graph capture on a worker: it would make device-wide calls of the
+        // other workers and of the caller's threads fail while it lasts
+        if (h) h->use_graphs = false;
         if (st == AMG_OK) st = krylov_solve(h, r->method, r->b, r->x, r->rtol, r->maxit, s, &r->info);
         else r->info.status = st;
         if (h) (void)amg_destroy(h);
@@ -188,7 +206,7 @@ struct amg_server {
     // Batched mode: one batched setup and one batched PCG solve for the group.
     // When the batched setup fails as a whole, or a system cannot be batched
     // (a single level), the requests concerned are run one by one.
-    void run_group(std::vector<Request*>& grp, hipStream_t s, double*& buf, size_t& cap) {
+    void run_group(std::vector<Request*>& grp, hipStream_t s) {
         const int n = (int)grp.size();
         if (!s) {
             for (Request* r : grp) fail(r, AMG_EHIP);
@@ -198,7 +216,7 @@ struct amg_server {
         for (int i = 0; i < n; ++i) A[i] = grp[i]->A;
         std::vector<amg_status> st(n, AMG_OK);
         amg_batch* bt = nullptr;
-        if (amg_batch_setup(A.data(), n, &cfg.params, s, &bt, st.data()) != AMG_OK) {
+        if (amg_batch_setup(A.data(), n, &cfg.params, alloc(), s, &bt, st.data()) != AMG_OK) {
             for (Request* r : grp) run_one(r, s);
             return;
         }
@@ -207,20 +225,29 @@ struct amg_server {
         (void)amg_batch_set_graphs(bt, 0);
         std::vector<int32_t> off(n + 1);
         (void)amg_batch_rows(bt, off.data());
-        const size_t need = 2 * (size_t)off[n] * sizeof(double);
-        if (need > cap) {
-            if (buf) (void)hipFree(buf);
-            buf = nullptr;
-            cap = 0;
-            if (hipMalloc((void**)&buf, need + need / 2) != hipSuccess) {
-                (void)amg_batch_destroy(bt);
-                for (Request* r : grp) fail(r, AMG_ENOMEM);
-                return;
+        // right-hand sides and solutions of the group, drawn like every other
+        // buffer of a request (so the allocator accounts for them) and released
+        // with the group
+        amg::DevPool io;
+        io.s = s;
+        io.al = cfg.alloc.alloc ? cfg.alloc : amg_allocator{};
+        struct IoGuard {
+            amg::DevPool& p;
+            hipStream_t s;
+            ~IoGuard() {
+                (void)hipStreamSynchronize(s);
+                p.release();
             }
-            cap = need + need / 2;
+        } iog{io, s};
+        double* B = nullptr;
+        try {
+            B = io.get<double>(2 * (size_t)(off[n] > 0 ? off[n] : 1));
+        } catch (const amg::Failure&) {
+            (void)amg_batch_destroy(bt);
+            for (Request* r : grp) fail(r, AMG_ENOMEM);
+            return;
         }
-        double* B = buf;
-        double* X = buf + off[n];
+        double* X = B + off[n];
         bool ok = true;
         for (int i = 0; i < n; ++i) {
             const size_t bytes = sizeof(double) * (size_t)(off[i + 1] - off[i]);
@@ -266,6 +293,7 @@ amg_status amg_server_config_default(amg_server_config* c) {
     c->workers = 4;
     c->batch = 0;
     c->hbm_budget_bytes = 64ull << 30;
+    c->alloc = amg_allocator{};
     return amg_params_default(&c->params);
 }
 
@@ -276,6 +304,7 @@ amg_status amg_server_create(const amg_server_config* c, amg_server** out) {
     if (c) cfg = *c;
     else amg_server_config_default(&cfg);
     if (cfg.workers < 1 || cfg.workers > 64 || cfg.hbm_budget_bytes == 0 || cfg.batch < 0) return AMG_EINVAL;
+    if (!cfg.alloc.alloc != !cfg.alloc.free) return AMG_EINVAL;
     if (cfg.batch >= 2 && (cfg.params.pre != 1 || cfg.params.post != 1)) return AMG_EINVAL;
     amg_server* s = new (std::nothrow) amg_server();
     if (!s) return AMG_ENOMEM;
@@ -309,7 +338,7 @@ amg_status amg_server_create(const amg_server_config* c, amg_server** out) {
 }
 
 amg_status amg_server_submit(amg_server* s, const amg_csr* A, const double* b, double* x, int32_t method,
-                             double rtol, int32_t maxit, int64_t* ticket) {
+                             double rtol, int32_t maxit, void* stream, int64_t* ticket) {
     if (!s || !A || !b || !x || !ticket) return AMG_EINVAL;
     Request* r = new (std::nothrow) Request();
     if (!r) return AMG_ENOMEM;
@@ -319,15 +348,28 @@ amg_status amg_server_submit(amg_server* s, const amg_csr* A, const double* b, d
     r->method = method;
     r->rtol = rtol;
     r->maxit = maxit;
-    r->foot = footprint(A->n, A->nnz, s->cfg.params) + (s->batched() ? batch_extra(A->n, A->nnz) : 0);
+    r->foot = footprint(A->n, A->nnz, s->cfg.params) + (s->batched() ? batch_extra(A->n, A->nnz, s->cfg.params) : 0);
     if (r->foot > s->cfg.hbm_budget_bytes) {
         delete r;
         return AMG_EINVAL;
+    }
+    // the request's inputs are ready once the work the producer enqueued on
+    // `stream` so far has finished
+    const amg_status est = amg::guarded([&] {
+        using amg::raise;
+        r->ready = amg::event_get(false);
+        HIPCHK(hipEventRecord(r->ready, static_cast<hipStream_t>(stream)));
+    });
+    if (est != AMG_OK) {
+        if (r->ready) amg::event_put(r->ready, false);
+        delete r;
+        return est;
     }
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stopping) {
+            amg::event_put(r->ready, false);
             delete r;
             return AMG_EINVAL;
         }
@@ -367,7 +409,10 @@ amg_status amg_server_destroy(amg_server* s) {
     s->cv_work.notify_all();
     for (auto& t : s->threads) t.join();
     s->release_streams();
-    for (auto& kv : s->reqs) delete kv.second;
+    for (auto& kv : s->reqs) {
+        if (kv.second->ready) amg::event_put(kv.second->ready, false);
+        delete kv.second;
+    }
     delete s;
     return AMG_OK;
 }

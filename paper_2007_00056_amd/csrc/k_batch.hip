@@ -225,7 +225,7 @@ __global__ __launch_bounds__(BS) void k_bzero(BatchTab T, double* __restrict__ x
 template <class T>
 __global__ __launch_bounds__(512) void k_bdense(const BDense<T>* __restrict__ dd, const int2* __restrict__ tab) {
     constexpr int ROWS = 64, WAVES = 8;
-    __shared__ double fs[1024];
+    __shared__ double fs[kDenseMaxRows];
     __shared__ double psum[WAVES][ROWS];
     const int2 bk = tab[blockIdx.x];
     const BDense<T> d = dd[bk.x];

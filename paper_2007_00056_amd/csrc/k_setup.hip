@@ -603,36 +603,42 @@ __device__ __forceinline__ void lu_argmax(double& v, int& i, double* sv, int* si
 
 // Blocked right-looking LU with partial pivoting in place (row-major a, unit
 // lower L below the diagonal; P A = L U with perm[i] = original row of
-// position i).  Panels of LU_NB columns: k_lu_panel factors the panel's rows
+// position i).  Panels of NB columns: k_lu_panel factors the panel's rows
 // k0.. in LDS (pivot = largest |value|, lowest row on ties), then k_lu_rest
 // applies the panel's interchanges to every other column and, right of the
 // panel, forms U12 = L11^{-1} A12 and A22 -= L21 U12.  Each entry receives its
-// updates in the order of the unblocked algorithm.  n <= 1024.
-constexpr int LU_NB = 16;
-constexpr int LU_LDP = LU_NB + 1;  // padded LDS row of the panel
+// updates in the order of the unblocked algorithm, whatever NB.  The panel of
+// the remaining m = n - k0 rows must fit LDS: NB = 16 up to 1024 rows, 8 up
+// to 2048, 4 up to 4096 (n <= 4096).
 constexpr int LU_COLS = 64;        // columns per block of k_lu_rest
+constexpr int LU_LDS_DOUBLES = 18432;  // 144 KiB of panel
 
+template <int NB>
+constexpr int lu_ldp() { return NB >= 8 ? NB + 1 : NB; }  // padded LDS row of the panel
+
+template <int NB>
 __global__ __launch_bounds__(LU_BS) void k_lu_panel(int n, int k0, double* __restrict__ a, int* __restrict__ perm,
                                                     int* __restrict__ piv, int* err) {
-    __shared__ double P[1024 * LU_LDP];
+    constexpr int LDP = lu_ldp<NB>();
+    __shared__ double P[LU_LDS_DOUBLES];
     __shared__ double sv[LU_BS / kWave];
     __shared__ int si[LU_BS / kWave];
     if (*err & ERR_SINGULAR) return;  // an earlier panel failed (uniform)
     const int tid = threadIdx.x;
-    const int kb = min(LU_NB, n - k0), m = n - k0;
+    const int kb = min(NB, n - k0), m = n - k0;
     if (k0 == 0)
         for (int i = tid; i < n; i += LU_BS) perm[i] = i;
     if (tid < kb) piv[k0 + tid] = k0 + tid;  // valid even if this panel fails
-    for (int t = tid; t < m * LU_NB; t += LU_BS) {
-        const int r = t / LU_NB, c = t % LU_NB;
-        P[r * LU_LDP + c] = c < kb ? a[(size_t)(k0 + r) * n + k0 + c] : 0.0;
+    for (int t = tid; t < m * NB; t += LU_BS) {
+        const int r = t / NB, c = t % NB;
+        P[r * LDP + c] = c < kb ? a[(size_t)(k0 + r) * n + k0 + c] : 0.0;
     }
     __syncthreads();
     for (int c = 0; c < kb; ++c) {
         double best = -1.0;
         int bi = m;
         for (int r = c + tid; r < m; r += LU_BS) {
-            const double v = fabs(P[r * LU_LDP + c]);
+            const double v = fabs(P[r * LDP + c]);
             if (v > best) {  // rows ascend per thread: strict '>' keeps the lowest
                 best = v;
                 bi = r;
@@ -643,24 +649,24 @@ __global__ __launch_bounds__(LU_BS) void k_lu_panel(int n, int k0, double* __res
             if (tid == 0) atomicOr(err, ERR_SINGULAR);
             return;
         }
-        if (bi != c && tid < LU_NB) {
-            const double t = P[c * LU_LDP + tid];
-            P[c * LU_LDP + tid] = P[bi * LU_LDP + tid];
-            P[bi * LU_LDP + tid] = t;
+        if (bi != c && tid < NB) {
+            const double t = P[c * LDP + tid];
+            P[c * LDP + tid] = P[bi * LDP + tid];
+            P[bi * LDP + tid] = t;
         }
         if (tid == 0) piv[k0 + c] = k0 + bi;
         __syncthreads();
-        const double d = P[c * LU_LDP + c];
+        const double d = P[c * LDP + c];
         for (int r = c + 1 + tid; r < m; r += LU_BS) {
-            const double l = P[r * LU_LDP + c] / d;
-            P[r * LU_LDP + c] = l;
-            for (int j = c + 1; j < kb; ++j) P[r * LU_LDP + j] -= l * P[c * LU_LDP + j];
+            const double l = P[r * LDP + c] / d;
+            P[r * LDP + c] = l;
+            for (int j = c + 1; j < kb; ++j) P[r * LDP + j] -= l * P[c * LDP + j];
         }
         __syncthreads();
     }
-    for (int t = tid; t < m * LU_NB; t += LU_BS) {
-        const int r = t / LU_NB, c = t % LU_NB;
-        if (c < kb) a[(size_t)(k0 + r) * n + k0 + c] = P[r * LU_LDP + c];
+    for (int t = tid; t < m * NB; t += LU_BS) {
+        const int r = t / NB, c = t % NB;
+        if (c < kb) a[(size_t)(k0 + r) * n + k0 + c] = P[r * LDP + c];
     }
     if (tid == 0)
         for (int c = 0; c < kb; ++c) {
@@ -674,12 +680,13 @@ __global__ __launch_bounds__(LU_BS) void k_lu_panel(int n, int k0, double* __res
 }
 
 // A block owns LU_COLS columns; 4 groups of 64 threads share its rows.
+template <int NB>
 __global__ __launch_bounds__(256) void k_lu_rest(int n, int k0, double* __restrict__ a, const int* __restrict__ piv,
                                                  const int* err) {
-    __shared__ double L11[LU_NB][LU_NB];
-    __shared__ double U[LU_NB][LU_COLS];
+    __shared__ double L11[NB][NB];
+    __shared__ double U[NB][LU_COLS];
     if (*err & ERR_SINGULAR) return;  // uniform
-    const int kb = min(LU_NB, n - k0);
+    const int kb = min(NB, n - k0);
     const int cl = threadIdx.x % LU_COLS, rg = threadIdx.x / LU_COLS;
     const int j = blockIdx.x * LU_COLS + cl;
     const bool mine = j < n && (j < k0 || j >= k0 + kb);
@@ -718,11 +725,11 @@ __global__ __launch_bounds__(256) void k_lu_rest(int n, int k0, double* __restri
 // (one dot per row and column, all threads), then lane c of the first wave
 // finishes column c through the 16x16 diagonal block kept in LDS.  Writes
 // the inverse column-major: ainv_t[c * n + i] = (A^{-1})_{ic}.
-template <int INV_COLS>
+template <int INV_COLS, int XCAP>
 __global__ __launch_bounds__(INV_BS) void k_dense_inverse(int n, const double* __restrict__ lu,
                                                           const int* __restrict__ perm, double* __restrict__ ainv_t) {
     constexpr int RB = 16;
-    __shared__ double x[8192];  // n * INV_COLS <= 8192
+    __shared__ double x[XCAP];  // n * INV_COLS <= XCAP
     __shared__ double D[RB][RB + 1];
     const int c0 = blockIdx.x * INV_COLS;
     const int tid = threadIdx.x;
@@ -774,19 +781,36 @@ __global__ __launch_bounds__(INV_BS) void k_dense_inverse(int n, const double* _
     }
 }
 
-// piv: int32[2n] scratch (permutation, then the panels' pivot rows).
+// piv: int32[2n] scratch (permutation, then the panels' pivot rows).  n <= 4096.
 void launch_dense_lu_inverse(int n, double* a, int* piv, double* ainv_t, int* err, hipStream_t s) {
     int* perm = piv;
     int* steps = piv + n;
-    for (int k0 = 0; k0 < n; k0 += LU_NB) {
-        hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(LU_BS), 0, s, n, k0, a, perm, steps, err);
-        hipLaunchKernelGGL(k_lu_rest, dim3((n + LU_COLS - 1) / LU_COLS), dim3(256), 0, s, n, k0, a, steps,
-                           (const int*)err);
+    const dim3 rest_grid((n + LU_COLS - 1) / LU_COLS);
+#define LU_STEP(NB)                                                                                           \
+    hipLaunchKernelGGL(k_lu_panel<NB>, dim3(1), dim3(LU_BS), 0, s, n, k0, a, perm, steps, err);             \
+    hipLaunchKernelGGL(k_lu_rest<NB>, rest_grid, dim3(256), 0, s, n, k0, a, steps, (const int*)err);        \
+    k0 += NB
+    static_assert(4096 * lu_ldp<4>() <= LU_LDS_DOUBLES && 2048 * lu_ldp<8>() <= LU_LDS_DOUBLES &&
+                      1024 * lu_ldp<16>() <= LU_LDS_DOUBLES, "panel LDS");
+    for (int k0 = 0; k0 < n;) {
+        const int m = n - k0;
+        if (m > 2048) {
+            LU_STEP(4);
+        } else if (m > 1024) {
+            LU_STEP(8);
+        } else {
+            LU_STEP(16);
+        }
     }
+#undef LU_STEP
     if (n <= 512)
-        hipLaunchKernelGGL(k_dense_inverse<16>, dim3((n + 15) / 16), dim3(INV_BS), 0, s, n, a, perm, ainv_t);
+        hipLaunchKernelGGL((k_dense_inverse<16, 8192>), dim3((n + 15) / 16), dim3(INV_BS), 0, s, n, a, perm, ainv_t);
+    else if (n <= 1024)
+        hipLaunchKernelGGL((k_dense_inverse<8, 8192>), dim3((n + 7) / 8), dim3(INV_BS), 0, s, n, a, perm, ainv_t);
+    else if (n <= 2048)
+        hipLaunchKernelGGL((k_dense_inverse<8, 16384>), dim3((n + 7) / 8), dim3(INV_BS), 0, s, n, a, perm, ainv_t);
     else
-        hipLaunchKernelGGL(k_dense_inverse<8>, dim3((n + 7) / 8), dim3(INV_BS), 0, s, n, a, perm, ainv_t);
+        hipLaunchKernelGGL((k_dense_inverse<4, 16384>), dim3((n + 3) / 4), dim3(INV_BS), 0, s, n, a, perm, ainv_t);
 }
 
 }  // namespace amg

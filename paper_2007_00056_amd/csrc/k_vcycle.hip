@@ -289,7 +289,7 @@ template <class T, class TIN, class TOUT>
 __global__ __launch_bounds__(DENSE_BS) void k_vc_dense(int n, const double* __restrict__ ainv_t,
                                                        const TIN* __restrict__ f, TOUT* __restrict__ x,
                                                        ScatterT<T> sc, int pin) {
-    __shared__ double fs[1024];
+    __shared__ double fs[kDenseMaxRows];
     __shared__ double part[DENSE_WAVES][DENSE_ROWS];
     const int blk = pinned_block(pin);
     if (blk < 0) return;

@@ -45,12 +45,20 @@ class amg_params(C.Structure):
 
 class amg_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("rel_res", C.c_double), ("true_rel_res", C.c_double),
-                ("solve_ms", C.c_double), ("status", C.c_int32)]
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("levels", C.c_int32), ("status", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class amg_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
 
 
 class amg_server_config(C.Structure):
     _fields_ = [("workers", C.c_int32), ("batch", C.c_int32), ("hbm_budget_bytes", C.c_uint64),
-                ("params", amg_params)]
+                ("params", amg_params), ("alloc", amg_allocator)]
 
 
 class AmgError(RuntimeError):
@@ -72,7 +80,7 @@ def lib():
         vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         sig = {
             "amg_params_default": [C.POINTER(amg_params)],
-            "amg_setup": [C.POINTER(amg_csr), C.POINTER(amg_params), vp, C.POINTER(vp)],
+            "amg_setup": [C.POINTER(amg_csr), C.POINTER(amg_params), C.POINTER(amg_allocator), vp, C.POINTER(vp)],
             "amg_destroy": [vp],
             "amg_vcycle": [vp, vp, vp, vp],
             "krylov_solve": [vp, i32, vp, vp, f64, i32, vp, C.POINTER(amg_info)],
@@ -85,11 +93,12 @@ def lib():
             "amg_footprint_bytes": [i32, i64, C.POINTER(amg_params), C.POINTER(C.c_uint64)],
             "amg_server_config_default": [C.POINTER(amg_server_config)],
             "amg_server_create": [C.POINTER(amg_server_config), C.POINTER(vp)],
-            "amg_server_submit": [vp, C.POINTER(amg_csr), vp, vp, i32, f64, i32, C.POINTER(i64)],
+            "amg_server_submit": [vp, C.POINTER(amg_csr), vp, vp, i32, f64, i32, vp, C.POINTER(i64)],
             "amg_server_wait": [vp, i64, C.POINTER(amg_info), C.POINTER(f64)],
             "amg_server_destroy": [vp],
-            "amg_batch_create": [C.POINTER(vp), i32, vp, C.POINTER(vp)],
-            "amg_batch_setup": [C.POINTER(amg_csr), i32, C.POINTER(amg_params), vp, C.POINTER(vp), vp],
+            "amg_batch_create": [C.POINTER(vp), i32, C.POINTER(amg_allocator), vp, C.POINTER(vp)],
+            "amg_batch_setup": [C.POINTER(amg_csr), i32, C.POINTER(amg_params), C.POINTER(amg_allocator), vp,
+                                C.POINTER(vp), vp],
             "amg_batch_set_graphs": [vp, i32],
             "amg_batch_rows": [vp, vp],
             "amg_batch_solve": [vp, i32, vp, vp, f64, i32, vp, vp],
@@ -124,6 +133,47 @@ def _ptr(t) -> int:
     return t.data_ptr()
 
 
+def _info_dict(st: int, info: amg_info) -> dict:
+    return dict(status=st, iters=info.iters, rel_res=info.rel_res, true_rel_res=info.true_rel_res,
+                setup_ms=info.setup_ms, solve_ms=info.solve_ms, levels=info.levels)
+
+
+class Allocator:
+    """An amg_allocator whose alloc/free are Python callables
+    alloc(nbytes, stream) -> device address (0 on failure) and
+    free(address, stream).  Keep the object alive while any handle, batch or
+    server uses it (the C side holds its function pointers)."""
+
+    def __init__(self, alloc, free):
+        def _a(size, ctx, stream):
+            try:
+                return int(alloc(int(size), int(stream or 0))) or None
+            except Exception:  # the library turns NULL into AMG_ENOMEM
+                return None
+
+        def _f(ptr, ctx, stream):
+            free(int(ptr), int(stream or 0))
+
+        self._a, self._f = ALLOC_FN(_a), FREE_FN(_f)
+        self.c = amg_allocator(self._a, self._f, None)
+
+
+class TorchAllocator(Allocator):
+    """Routes device memory through PyTorch's caching allocator, so torch's
+    memory statistics and limits see every byte a handle owns."""
+
+    def __init__(self, device=None):
+        import torch
+
+        dev = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+        super().__init__(lambda n, st: torch.cuda.caching_allocator_alloc(n, dev, st),
+                         lambda p, st: torch.cuda.caching_allocator_delete(p))
+
+
+def _alloc_ref(alloc):
+    return C.byref(alloc.c) if alloc is not None else None
+
+
 # ---------------------------------------------------------------- C entry points
 
 def amg_params_default(**overrides) -> amg_params:
@@ -152,11 +202,11 @@ class DeviceCSR:
                    torch.from_numpy(np.ascontiguousarray(a.val, dtype=np.float64)).to(device))
 
 
-def amg_setup(A: DeviceCSR, params: amg_params | None = None, stream=None) -> int:
+def amg_setup(A: DeviceCSR, params: amg_params | None = None, stream=None, alloc: Allocator | None = None) -> int:
     """Returns the handle (an opaque pointer value)."""
     h = C.c_void_p()
-    _check(lib().amg_setup(C.byref(A.c), C.byref(params) if params is not None else None, _stream_ptr(stream),
-                           C.byref(h)))
+    _check(lib().amg_setup(C.byref(A.c), C.byref(params) if params is not None else None, _alloc_ref(alloc),
+                           _stream_ptr(stream), C.byref(h)))
     return h.value
 
 
@@ -171,8 +221,7 @@ def amg_vcycle(h: int, r, z, stream=None) -> None:
 def krylov_solve(h: int, method: int, b, x, rtol: float, maxit: int, stream=None, check: bool = True) -> dict:
     info = amg_info()
     st = lib().krylov_solve(h, method, _ptr(b), _ptr(x), rtol, maxit, _stream_ptr(stream), C.byref(info))
-    out = dict(status=st, iters=info.iters, rel_res=info.rel_res, true_rel_res=info.true_rel_res,
-               solve_ms=info.solve_ms)
+    out = _info_dict(st, info)
     if check and st not in (AMG_OK,):
         raise AmgError(st, lib().amg_last_error().decode())
     return out
@@ -246,9 +295,11 @@ def amg_server_create(config: amg_server_config | None = None) -> int:
     return h.value
 
 
-def amg_server_submit(s: int, A: DeviceCSR, b, x, method: int, rtol: float, maxit: int) -> int:
+def amg_server_submit(s: int, A: DeviceCSR, b, x, method: int, rtol: float, maxit: int, stream=None) -> int:
+    """stream: where b and x were produced (default: torch's current stream)."""
     t = C.c_int64()
-    _check(lib().amg_server_submit(s, C.byref(A.c), _ptr(b), _ptr(x), method, rtol, maxit, C.byref(t)))
+    _check(lib().amg_server_submit(s, C.byref(A.c), _ptr(b), _ptr(x), method, rtol, maxit, _stream_ptr(stream),
+                                   C.byref(t)))
     return t.value
 
 
@@ -257,29 +308,28 @@ def amg_server_wait(s: int, ticket: int) -> dict:
     info = amg_info()
     lat = C.c_double()
     st = lib().amg_server_wait(s, ticket, C.byref(info), C.byref(lat))
-    return dict(status=st, iters=info.iters, rel_res=info.rel_res, true_rel_res=info.true_rel_res,
-                solve_ms=info.solve_ms, latency_ms=lat.value)
+    return dict(_info_dict(st, info), latency_ms=lat.value)
 
 
 def amg_server_destroy(s: int) -> None:
     _check(lib().amg_server_destroy(s))
 
 
-def amg_batch_create(handles, stream=None) -> int:
+def amg_batch_create(handles, stream=None, alloc: Allocator | None = None) -> int:
     arr = (C.c_void_p * len(handles))(*handles)
     b = C.c_void_p()
-    _check(lib().amg_batch_create(arr, len(handles), _stream_ptr(stream), C.byref(b)))
+    _check(lib().amg_batch_create(arr, len(handles), _alloc_ref(alloc), _stream_ptr(stream), C.byref(b)))
     return b.value
 
 
-def amg_batch_setup(systems, params: amg_params | None = None, stream=None):
+def amg_batch_setup(systems, params: amg_params | None = None, stream=None, alloc: Allocator | None = None):
     """Builds the hierarchies of every system together; returns (batch handle,
     per-system statuses)."""
     arr = (amg_csr * len(systems))(*[A.c for A in systems])
     st = np.zeros(len(systems), np.int32)
     b = C.c_void_p()
     _check(lib().amg_batch_setup(arr, len(systems), C.byref(params) if params is not None else None,
-                                 _stream_ptr(stream), C.byref(b), st.ctypes.data))
+                                 _alloc_ref(alloc), _stream_ptr(stream), C.byref(b), st.ctypes.data))
     return b.value, st.tolist()
 
 
@@ -294,8 +344,7 @@ def amg_batch_solve(b: int, method: int, rhs, x, rtol: float, maxit: int, count:
     statuses are reported, not raised)."""
     infos = (amg_info * count)()
     lib().amg_batch_solve(b, method, _ptr(rhs), _ptr(x), rtol, maxit, _stream_ptr(stream), infos)
-    return [dict(status=i.status, iters=i.iters, rel_res=i.rel_res, true_rel_res=i.true_rel_res,
-                 solve_ms=i.solve_ms) for i in infos]
+    return [_info_dict(i.status, i) for i in infos]
 
 
 def amg_autotune(h: int, stream=None) -> list:
@@ -326,12 +375,14 @@ def amg_batch_destroy(b: int) -> None:
 class Hierarchy:
     """Owns an amg_setup handle and the device matrix it borrows."""
 
-    def __init__(self, A: DeviceCSR, params: amg_params | None = None, stream=None, **overrides):
+    def __init__(self, A: DeviceCSR, params: amg_params | None = None, stream=None, alloc: Allocator | None = None,
+                 **overrides):
         if params is None:
             params = amg_params_default(**overrides)
         self.A = A  # level 0 is borrowed: keep it alive
         self.params = params
-        self.h = amg_setup(A, params, stream)
+        self.alloc = alloc  # its callbacks must outlive the handle
+        self.h = amg_setup(A, params, stream, alloc)
 
     def close(self):
         if getattr(self, "h", None):
@@ -380,22 +431,24 @@ class Batch:
     """Owns a batch built from hierarchies (amg_batch_create) or set up from
     matrices (Batch.setup, amg_batch_setup)."""
 
-    def __init__(self, hierarchies=None, stream=None, _handle=None, _count=None):
+    def __init__(self, hierarchies=None, stream=None, alloc: Allocator | None = None, _handle=None, _count=None):
+        self.alloc = alloc
         if _handle is not None:
             self.count, self.b = _count, _handle
         else:
             self.count = len(hierarchies)
-            self.b = amg_batch_create([h.h if isinstance(h, Hierarchy) else h for h in hierarchies], stream)
+            self.b = amg_batch_create([h.h if isinstance(h, Hierarchy) else h for h in hierarchies], stream, alloc)
         self.status = [AMG_OK] * self.count
         self.offsets = amg_batch_rows(self.b, self.count)
 
     @classmethod
-    def setup(cls, systems, params: amg_params | None = None, stream=None, **overrides):
+    def setup(cls, systems, params: amg_params | None = None, stream=None, alloc: Allocator | None = None,
+              **overrides):
         """systems: DeviceCSR matrices (borrowed during the call only)."""
         if params is None:
             params = amg_params_default(**overrides)
-        h, st = amg_batch_setup(systems, params, stream)
-        bt = cls(_handle=h, _count=len(systems))
+        h, st = amg_batch_setup(systems, params, stream, alloc)
+        bt = cls(alloc=alloc, _handle=h, _count=len(systems))
         bt.status = st
         return bt
 

@@ -1,5 +1,6 @@
 import os
 import sys
+import threading
 
 import pytest
 
@@ -32,3 +33,38 @@ def load_golden(name):
 @pytest.fixture(scope="session")
 def golden():
     return load_golden
+
+
+class CountingAllocator:
+    """An amg_allocator (device memory from torch's caching allocator) that
+    counts live and peak bytes and the calls made, and can fail the k-th
+    allocation (returns NULL) to force the library's out-of-memory path from
+    the host."""
+
+    def __init__(self, torch, fail_at=None):
+        from paper_2007_00056_amd import hemamg
+
+        self.live = self.peak = self.calls = 0
+        self.sizes = {}
+        self.fail_at = fail_at
+        self.lock = threading.Lock()
+
+        def alloc(n, stream):
+            with self.lock:
+                self.calls += 1
+                if self.fail_at is not None and self.calls == self.fail_at:
+                    return 0
+            p = torch.cuda.caching_allocator_alloc(n, torch.cuda.current_device(), stream)
+            with self.lock:
+                self.sizes[p] = n
+                self.live += n
+                self.peak = max(self.peak, self.live)
+            return p
+
+        def free(p, stream):
+            with self.lock:
+                self.live -= self.sizes.pop(p)
+            torch.cuda.caching_allocator_delete(p)
+
+        self.impl = hemamg.Allocator(alloc, free)
+        self.c = self.impl.c

@@ -45,16 +45,39 @@ def test_struct_layouts_match_header():
     # amg_params: 4 int32, double, 4 int32, double, 2 int32 -> 56 bytes with natural alignment
     assert ctypes.sizeof(hemamg.amg_params) == 56
     assert ctypes.sizeof(hemamg.amg_csr) == 40
-    assert ctypes.sizeof(hemamg.amg_info) == 40
-    # amg_server_config: int32, int32, uint64, amg_params -> 72 bytes
-    assert ctypes.sizeof(hemamg.amg_server_config) == 72
+    # amg_info: int32, 4 doubles, 2 int32 -> 48 bytes
+    assert ctypes.sizeof(hemamg.amg_info) == 48
+    assert ctypes.sizeof(hemamg.amg_allocator) == 24
+    # amg_server_config: int32, int32, uint64, amg_params, amg_allocator -> 96 bytes
+    assert ctypes.sizeof(hemamg.amg_server_config) == 96
+
+
+def prototype(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"amg_status\s+" + name + r"\s*\(([^)]*)\)", text)
+    return [" ".join(a.split()) for a in m.group(1).split(",")]
+
+
+def test_setup_entry_points_take_an_allocator():
+    """The setup calls draw every device buffer through the caller's
+    allocator (NULL selects the library pool)."""
+    assert prototype("amg_setup") == ["const amg_csr* A", "const amg_params* params", "const amg_allocator* alloc",
+                                      "void* stream", "amg_hier** out"]
+    assert prototype("amg_batch_setup")[:4] == ["const amg_csr* A", "int32_t count", "const amg_params* params",
+                                                "const amg_allocator* alloc"]
+    assert "const amg_allocator* alloc" in prototype("amg_batch_create")
+    text = open(HEADER).read()
+    assert re.search(r"void\* \(\*alloc\)\(size_t bytes, void\* ctx, void\* stream\);", text)
+    assert re.search(r"void \(\*free\)\(void\* ptr, void\* ctx, void\* stream\);", text)
+    names = [f[0] for f in hemamg.amg_info._fields_]
+    assert "setup_ms" in names and "levels" in names
 
 
 def test_params_default_values():
     if not os.path.exists(hemamg.LIB_PATH):
         pytest.fail("libhemamg.so is not built")
     p = hemamg.amg_params_default()  # host-only call, no GPU work
-    assert (p.passes_per_level, p.max_coarse_rows, p.max_levels, p.max_dense_rows) == (2, 64, 32, 1024)
+    assert (p.passes_per_level, p.max_coarse_rows, p.max_levels, p.max_dense_rows) == (2, 64, 32, 4096)
     assert abs(p.omega - 2.0 / 3.0) < 1e-16 and (p.pre, p.post, p.true_res_period) == (1, 1, 50)
     assert p.precond_fp32 == 0 and p.stall_ratio == 0.9 and p.hem == 0 and p.alternate == 0
 

@@ -5,10 +5,12 @@ Bars for the HIP path against the oracle:
     every value) are bit-identical: both sides run the same deterministic
     matching and sum each Galerkin entry in the same fixed order;
   * FP64 solutions agree to relative 2-norm error <= 1e-9 at equal iteration
-    count, and stopping iterations agree within +-1;
-  * one V-cycle agrees to relative error <= 1e-11: both apply the same linear
-    operator in FP64 and differ only in rounding (fused multiply-adds,
-    reduction order, explicit coarse inverse versus LU substitution).
+    count, and element by element to max|x_g - x_o| <= 1e-9 max|x_o|;
+    stopping iterations agree within +-1;
+  * one V-cycle agrees to relative error <= 1e-11, in the 2-norm and element
+    by element against max|z_o|: both apply the same linear operator in FP64
+    and differ only in rounding (fused multiply-adds, reduction order,
+    explicit coarse inverse versus LU substitution).
 """
 import numpy as np
 import pytest
@@ -134,6 +136,16 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def maxrel(a, b):
+    """Largest element-wise difference relative to the largest element of b."""
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def assert_close(x, xo, tol, what=""):
+    e2, emax = rel(x, xo), maxrel(x, xo)
+    assert e2 <= tol and emax <= tol, (what, e2, emax)
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_vcycle_matches_oracle(torch, name):
     say("case", name)
@@ -141,7 +153,7 @@ def test_vcycle_matches_oracle(torch, name):
     g, o = both(a)
     f = P.rhs_uniform(a.n, 11)
     z = g.vcycle(dev(torch, f)).cpu().numpy()
-    assert rel(z, o.vcycle(f)) <= VC_TOL
+    assert_close(z, o.vcycle(f), VC_TOL, name)
     g.close()
 
 
@@ -157,8 +169,8 @@ def solve_parity(torch, a, method, rtol, seed=0, **kw):
     # equal iteration count for the solution comparison
     xg2, ig2 = g.solve(dev(torch, b), method=method, rtol=0.0, maxit=io["iters"], check=False)
     assert ig2["status"] == hemamg.AMG_ENOTCONV and ig2["iters"] == io["iters"]
-    err = rel(xg2.cpu().numpy(), xo)
-    assert err <= SOL_TOL, err
+    assert_close(xg2.cpu().numpy(), xo, SOL_TOL, "equal iterations")
+    assert ig["levels"] == o.nlevels and ig["setup_ms"] > 0
     g.close()
     return ig, io
 
@@ -194,7 +206,7 @@ def test_autotuned_schedule_keeps_parity(torch, name, fp32):
     else:
         assert abs(ig["iters"] - io["iters"]) <= 1
         xg3, _ = g.solve(dev(torch, b), method=method, rtol=0.0, maxit=io["iters"], check=False)
-        assert rel(xg3.cpu().numpy(), xo) <= 1e-9
+        assert_close(xg3.cpu().numpy(), xo, SOL_TOL)
     g.close()
 
 
@@ -368,7 +380,7 @@ def test_zero_rhs_and_iteration_limit(torch):
         assert info["status"] == hemamg.AMG_ENOTCONV and info["iters"] == 3
         xo, io = oracle.Hierarchy(a).solve(b, rtol=1e-14, maxit=3)
         assert io["status"] == oracle.ENOTCONV
-        assert rel(x.cpu().numpy(), xo) <= SOL_TOL
+        assert_close(x.cpu().numpy(), xo, SOL_TOL)
 
 
 def test_nonfinite_rhs_rejected(torch):
@@ -411,7 +423,7 @@ def test_invalid_matrices_rejected(torch):
     # n = 0
     c = hemamg.amg_csr(0, 0, None, None, None)
     h = hemamg.C.c_void_p()
-    st = hemamg.lib().amg_setup(hemamg.C.byref(c), None, None, hemamg.C.byref(h))
+    st = hemamg.lib().amg_setup(hemamg.C.byref(c), None, None, None, hemamg.C.byref(h))
     assert st == hemamg.AMG_EINVAL and not h.value
 
 
@@ -422,14 +434,16 @@ def test_stall_dense_fallback_and_error(torch):
     b = P.rhs_uniform(100, 0)
     x, info = g.solve(dev(torch, b), rtol=1e-12)
     np.testing.assert_allclose(x.cpu().numpy(), b / np.arange(1.0, 101.0), rtol=1e-14)
-    big = P.CSR(2000, np.arange(2001, dtype=np.int32), np.arange(2000, dtype=np.int32), np.arange(1.0, 2001.0))
+    big = P.diagonal(np.arange(1.0, 4098.0))  # 4097 rows: nothing merges, above the dense limit
     assert bad_setup(torch, big) == hemamg.AMG_ESTALL
 
 
-@pytest.mark.parametrize("n", [1, 2, 63, 65, 300, 513, 1024])
+@pytest.mark.parametrize("n", [1, 2, 63, 65, 300, 513, 1024, 1025, 2049, 4096])
 def test_dense_coarsest_sizes_with_pivoting(torch, n):
-    """The coarsest solve alone (one level) at sizes around its tile edges, on
-    a matrix whose small diagonal forces row exchanges."""
+    """The coarsest solve alone (one level) at sizes around its tile edges and
+    panel-width changes (16 columns up to 1024 remaining rows, 8 up to 2048, 4
+    above), up to the 4096-row limit, on a matrix whose small diagonal forces
+    row exchanges."""
     say("dense n", n)
     rng = np.random.default_rng(n)
     d = np.zeros((n, n))
@@ -440,14 +454,18 @@ def test_dense_coarsest_sizes_with_pivoting(torch, n):
     if n == 1:
         d[0, 0] = 2.0
     a = P.from_dense(d)
-    g, o = both(a, max_coarse_rows=1024)
-    assert g.nlevels == o.nlevels == 1
+    A = hemamg.DeviceCSR.from_host(a)
+    g = hemamg.Hierarchy(A, hemamg.amg_params_default(max_coarse_rows=4096))
+    assert g.nlevels == 1
     b = P.rhs_uniform(n, 3)
     z = g.vcycle(dev(torch, b)).cpu().numpy()
     x = np.linalg.solve(d, b)
     tol = max(1e-13, 64 * np.finfo(float).eps * np.linalg.cond(d))
     assert rel(z, x) <= tol, (rel(z, x), tol)
-    assert rel(z, o.vcycle(b)) <= tol
+    if n <= 2049:  # the oracle's plain LU of 4096 rows takes half a minute
+        o = oracle.Hierarchy(a, max_coarse_rows=4096)
+        assert o.nlevels == 1
+        assert rel(z, o.vcycle(b)) <= tol
     g.close()
 
 
@@ -461,13 +479,47 @@ def test_star_graph_stall_rule(torch, kw):
     assert_same_hierarchy(g, o)
     f = P.rhs_uniform(a.n, 5)
     z = g.vcycle(dev(torch, f)).cpu().numpy()
-    assert rel(z, o.vcycle(f)) <= VC_TOL
+    assert_close(z, o.vcycle(f), VC_TOL)
     g.close()
     A = hemamg.DeviceCSR.from_host(a)
     for bad in (0.0, 1.5):
         with pytest.raises(hemamg.AmgError) as e:
             hemamg.Hierarchy(A, hemamg.amg_params_default(stall_ratio=bad))
         assert e.value.status == hemamg.AMG_EINVAL
+
+
+def poisson_beside_diagonal():
+    return P.block_diag(P.poisson2d(64), P.diagonal(np.arange(1.0, 2001.0)))
+
+
+def poisson_beside_star():
+    return P.block_diag(P.poisson2d(64), P.star_graph(1500, 2))
+
+
+@pytest.mark.parametrize("make,kw,coarsest", [
+    (poisson_beside_diagonal, dict(stall_ratio=1.0), 2001),   # a level merges nothing
+    (poisson_beside_star, dict(stall_ratio=1.0), 1439),       # the depth limit
+    (poisson_beside_diagonal, dict(), 2256),                  # poor progress
+    (poisson_beside_star, dict(), 1558),
+    (lambda: P.star_graph(3000, 2), dict(), 3000),            # a single dense level
+])
+def test_stall_between_1025_and_4096_rows_is_dense_solved_like_the_oracle(torch, make, kw, coarsest):
+    """Coarsening that stalls between 1025 and 4096 rows ends in a dense
+    coarsest level on both sides: identical hierarchies, V-cycle and PCG in
+    parity, and the same ESTALL when the dense limit is set below it."""
+    say("stall case", coarsest, kw)
+    a = make()
+    g, o = both(a, **kw)
+    assert_same_hierarchy(g, o)
+    assert g.level(g.nlevels - 1)[0].size - 1 == coarsest
+    f = P.rhs_uniform(a.n, 6)
+    assert_close(g.vcycle(dev(torch, f)).cpu().numpy(), o.vcycle(f), VC_TOL)
+    g.close()
+    solve_parity(torch, a, "pcg", 1e-8, **kw)
+    if coarsest in (2001, 1439):
+        with pytest.raises(hemamg.AmgError) as e:
+            hemamg.Hierarchy(hemamg.DeviceCSR.from_host(a), max_dense_rows=coarsest - 1, **kw)
+        assert e.value.status == hemamg.AMG_ESTALL
 
 
 def test_vardiff3d_80_high_contrast_hierarchy(torch):

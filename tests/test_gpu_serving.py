@@ -1,11 +1,17 @@
 """GPU tests of the serving loop (amg_server_*): requests of different sizes
 run concurrently on worker streams.  Every kernel is deterministic and a
 request's work touches only its own buffers, so each result must be
-bit-identical to the same request solved alone; admission by footprint and
-error isolation are checked too."""
+bit-identical to the same request solved alone; every served result is also
+checked against the CPU oracle (stopping iterations within +-1 in double,
+max(2, 5%) with the float preconditioner; at equal iteration count a double
+result within 1e-9 of the oracle's, in the 2-norm and element by element).
+Admission by footprint, the caller's allocator and error isolation are
+checked too."""
 import numpy as np
 import pytest
 
+import oracle
+from conftest import CountingAllocator
 from paper_2007_00056_amd import hemamg, problems as P
 
 pytestmark = pytest.mark.gpu
@@ -34,6 +40,52 @@ def mix():
     out.append((P.poisson3d(21, 17, 13), 7, "pcg"))
     out.append((P.convdiff3d(19), 8, "bicgstab"))
     return out
+
+
+def serve(torch, cfg, items, rtol, maxits=None):
+    """Submits every (matrix, seed, method) item to a server, waits for all;
+    returns (results, solutions as host arrays)."""
+    srv = hemamg.amg_server_create(cfg)
+    try:
+        live = []
+        for i, (a, seed, method) in enumerate(items):
+            A = hemamg.DeviceCSR.from_host(a)
+            b = torch.from_numpy(P.rhs_uniform(a.n, seed)).cuda()
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            m = hemamg.PCG if method == "pcg" else hemamg.BICGSTAB
+            t = hemamg.amg_server_submit(srv, A, b, x, m, rtol, 500 if maxits is None else maxits[i])
+            live.append((t, A, b, x))
+        res = [hemamg.amg_server_wait(srv, t) for t, *_ in live]
+    finally:
+        hemamg.amg_server_destroy(srv)
+    return res, [x.cpu().numpy() for *_, x in live]
+
+
+def check_served_against_oracle(torch, cfg, items, res, xs, fp32, rtol):
+    """Every served result against the oracle's solve of the same request."""
+    outs = []
+    for (a, seed, method), r, x in zip(items, res, xs):
+        b = P.rhs_uniform(a.n, seed)
+        xo, io = oracle.Hierarchy(a).solve(b, method=method, rtol=rtol, maxit=500)
+        assert io["status"] == oracle.OK
+        slack = max(2, int(0.05 * io["iters"])) if fp32 else 1
+        assert abs(r["iters"] - io["iters"]) <= slack, (a.n, r, io)
+        A = a.to_scipy()
+        nb = np.linalg.norm(b)
+        assert np.linalg.norm(b - A @ x) <= rtol * nb * (1 + 1e-6)
+        assert np.linalg.norm(A @ (x - xo)) <= 2 * rtol * nb * (1 + 1e-6)
+        outs.append((xo, io["iters"]))
+    if fp32:
+        return
+    # double: the same requests served again with the oracle's iteration count
+    res2, xs2 = serve(torch, cfg, items, 0.0, [it for _, it in outs])
+    for (a, _, _), r, x, (xo, it) in zip(items, res2, xs2, outs):
+        assert r["status"] == hemamg.AMG_ENOTCONV and r["iters"] == it, (r, it)
+        e2 = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+        emax = np.abs(x - xo).max() / np.abs(xo).max()
+        say("n", a.n, "iters", it, "rel err", e2, "max element err", emax)
+        assert e2 <= 1e-9 and emax <= 1e-9, (a.n, e2, emax)
 
 
 def alone(torch, a, seed, method, params, rtol):
@@ -68,10 +120,11 @@ def test_results_same_alone_and_in_the_mix(torch, fp32, workers):
         hemamg.amg_server_destroy(srv)
     for (a, seed, method), (t, A, b, x), r in zip(items, live, res):
         assert r["status"] == hemamg.AMG_OK, r
-        assert r["latency_ms"] > 0
+        assert r["latency_ms"] > 0 and r["setup_ms"] > 0 and r["levels"] >= 2
         xa, ia = alone(torch, a, seed, method, params, rtol)
         assert r["iters"] == ia["iters"], (r, ia)
         np.testing.assert_array_equal(bits(x.cpu().numpy()), bits(xa), err_msg=f"n={a.n}")
+    check_served_against_oracle(torch, cfg, items, res, [x.cpu().numpy() for *_, x in live], fp32, rtol)
 
 
 def test_admission_budget_serialises_but_completes(torch):
@@ -195,6 +248,7 @@ def test_batched_serving_results_same_as_alone(torch, fp32, workers, batch):
         xa, ia = batch_of_one(torch, a, seed, params, rtol, method)
         assert r["iters"] == ia["iters"], (r, ia)
         np.testing.assert_array_equal(bits(x.cpu().numpy()), bits(xa), err_msg=f"n={a.n}")
+    check_served_against_oracle(torch, cfg, items, res, [x.cpu().numpy() for *_, x in live], fp32, rtol)
 
 
 def test_batched_server_config_checks(torch):
@@ -205,3 +259,56 @@ def test_batched_server_config_checks(torch):
         with pytest.raises(hemamg.AmgError) as e:
             hemamg.amg_server_create(cfg)
         assert e.value.status == hemamg.AMG_EINVAL
+
+
+@pytest.mark.parametrize("batch", [0, 4])
+def test_server_memory_goes_through_the_allocator_within_the_budget(torch, batch):
+    """Every byte a request's hierarchy, workspace and batch buffers use is
+    drawn through the configured allocator on the workers; admission keeps the
+    live bytes within the budget, and everything is returned at the end."""
+    items = mix()
+    feet = [hemamg.amg_footprint_bytes(a.n, a.nnz) for a, _, _ in items]
+    ca = CountingAllocator(torch)
+    cfg = hemamg.amg_server_config_default(workers=3, batch=batch, hbm_budget_bytes=2 * max(feet) + max(feet) // 2)
+    cfg.alloc = ca.c
+    res, xs = serve(torch, cfg, items, 1e-8)
+    assert all(r["status"] == hemamg.AMG_OK for r in res), res
+    say("batch", batch, "calls", ca.calls, "peak MB", ca.peak / 1e6, "budget MB", cfg.hbm_budget_bytes / 1e6)
+    assert ca.calls > 0 and ca.live == 0
+    assert 0 < ca.peak <= cfg.hbm_budget_bytes
+    params = hemamg.amg_params_default()
+    for (a, seed, method), r, x in zip(items, res, xs):
+        if batch:
+            xa, _ = batch_of_one(torch, a, seed, params, 1e-8, method)
+        else:
+            xa, _ = alone(torch, a, seed, method, params, 1e-8)
+        np.testing.assert_array_equal(bits(x), bits(xa), err_msg=f"n={a.n}")
+
+
+def test_inputs_written_on_the_producer_stream_are_waited_for(torch):
+    """b is filled asynchronously on a side stream and submitted with that
+    stream, without a host synchronisation: the worker waits for it."""
+    a = P.lognormal_diffusion3d(40, 17, 1.0)
+    A = hemamg.DeviceCSR.from_host(a)
+    src = torch.from_numpy(P.rhs_uniform(a.n, 17)).cuda()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    srv = hemamg.amg_server_create(hemamg.amg_server_config_default(workers=2))
+    try:
+        xs, bs = [], []
+        with torch.cuda.stream(side):
+            for rep in range(3):
+                b = torch.zeros_like(src)
+                torch.cuda._sleep(2_000_000)  # keep the side stream busy before the write
+                b.copy_(src)
+                x = torch.zeros_like(src)
+                t = hemamg.amg_server_submit(srv, A, b, x, hemamg.PCG, 1e-8, 500, stream=side)
+                xs.append((t, x))
+                bs.append(b)
+        res = [hemamg.amg_server_wait(srv, t) for t, _ in xs]
+    finally:
+        hemamg.amg_server_destroy(srv)
+    xa, ia = alone(torch, a, 17, "pcg", hemamg.amg_params_default(), 1e-8)
+    for r, (_, x) in zip(res, xs):
+        assert r["status"] == hemamg.AMG_OK and r["iters"] == ia["iters"]
+        np.testing.assert_array_equal(bits(x.cpu().numpy()), bits(xa))
