@@ -2,9 +2,15 @@
 
 One step = the whole hot path on one synthetic system already resident in GPU
 memory: amg_setup (matching, Galerkin products, coarsest LU) + krylov_solve
-to the workload's relative tolerance + amg_destroy.  Prints one JSON line.
+to the workload's relative tolerance + amg_destroy.  After the timed steps
+the same run measures the served stream (1024 requests of lognormal
+diffusion, plain double form against the batched float-preconditioned form
+at the plain form's capacity, and the batched form in closed loop) and the
+CPU oracle on a bounded sample.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--gpus 1]
+                  [--no-serve] [--no-cpu-baseline]
+  python bench.py --serve-only   (the served stream alone, with more rates)
 """
 from __future__ import annotations
 
@@ -59,20 +65,49 @@ STREAM_MIN = 262144  # levels with at least this many rows use the CSR-stream ke
 
 
 def kernel_bytes(sizes, e, method):
-    """Algorithmic bytes per launch of the timed level-0 kernels: preconditioner
+    """Bytes each timed level-0 kernel moves as implemented: preconditioner
     values and vectors of e bytes (8 double, 4 float), int32 indices, the
     level-0 right-hand side and result in double; every array counted once."""
     (n, nnz) = sizes[0]
     csr = (e + 4) * nnz + 4 * (n + 1)
     return {
-        # postsmoothing from the prolongated iterate xp: xp gather, g, D^{-1} read
-        # (3e n), z write (8 n); PCG fuses (r, z) and also reads r (8 n)
-        0: csr + 3 * e * n + (16 if method == "pcg" else 8) * n,
+        # postsmoothing from the prolongated iterate xp: xp gather and D^{-1}
+        # (2e n), z write (8 n), and g = D^{-1} f: a double level 0 forms it from
+        # f (8 n read), a float one reads it (4 n); PCG's fused (r, z) reads r = f
+        0: csr + 2 * e * n + 8 * n + (8 * n if e == 8 else 4 * n + (8 * n if method == "pcg" else 0)),
         # presmoothing + residual: g gather, r read (8 n), residual write
         1: csr + 2 * e * n + 8 * n,
         # outer SpMV + dot, always double: p read + q write
         2: 12 * nnz + 4 * (n + 1) + 16 * n,
     }
+
+
+def model_bytes(sizes, e):
+    """The per-launch byte model of the fused prolongation + postsmoothing on
+    level 0 (values of e bytes, int32 columns): (e + 4) nnz + 32 N + 8 N_c,
+    i.e. 12 nnz + 32 N + 8 N_c in double."""
+    (n, nnz), nc = sizes[0], sizes[1][0]
+    return (e + 4) * nnz + 32 * n + 8 * nc
+
+
+def host_cpu():
+    """Host description for the CPU baseline: logical CPUs and model name."""
+    import subprocess
+
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        nproc = int(subprocess.run(["nproc"], capture_output=True, text=True, timeout=10).stdout.strip())
+    except (OSError, ValueError, subprocess.SubprocessError):
+        nproc = os.cpu_count()
+    return {"nproc": nproc, "model": model}
 
 
 def level_bytes(k, sizes, e):
@@ -128,12 +163,12 @@ def cpu_baseline(a, b, spec, gpu_iters, hem=0, alternate=0, budget_s=25.0):
     est_solve = t_solve if full else t_solve * gpu_iters / done
     total = t_setup + est_solve
     h.close()
-    return {
+    return dict({
         "value": 1.0 / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
         "sample": (f"one setup ({t_setup:.2f} s) + {'full solve' if full else 'partial solve'} of {done} "
                    f"iterations ({t_solve:.2f} s)" + ("" if full else f", scaled to {gpu_iters} iterations")),
         "setup_s": t_setup, "solve_s": est_solve, "oracle_iters": info["iters"],
-    }
+    }, **host_cpu())
 
 
 def gen_request(item):
@@ -145,19 +180,20 @@ def gen_request(item):
     return a, P.rhs_uniform(a.n, seed)
 
 
-def serve_main(args):
+def served_stream(args, rates, closed_streams=False):
     """Served stream: requests of side log-uniform in [16, 96] with lognormal
     coefficients arrive as a Poisson process.  The plain form solves them one
-    at a time in double; the served form runs `--workers` requests at once
-    with the float preconditioner.  Both see the same arrival trace, at rates
-    that are fractions of the plain form's measured capacity."""
+    at a time in double; the batched form runs `--workers` workers that group
+    queued requests (up to `--batch`) into batched setups and solves with the
+    float preconditioner.  Both see the same arrival trace, at rates that are
+    fractions of the plain form's measured capacity.  Returns a dict."""
     from concurrent.futures import ProcessPoolExecutor
 
     import torch
 
     from paper_2007_00056_amd import hemamg, problems as P
 
-    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
     stream = P.served_stream(args.requests, seed=0)
     log(f"generating {len(stream)} requests")
     with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
@@ -168,18 +204,20 @@ def serve_main(args):
         dev.append((A, torch.from_numpy(b).cuda(), torch.zeros(a.n, dtype=torch.float64, device="cuda")))
     torch.cuda.synchronize()
     rows = sum(a.n for a, _ in reqs)
-    log(f"{len(reqs)} requests, {rows} rows in total")
+    del reqs
+    log(f"{len(dev)} requests, {rows} rows in total, ready in {time.perf_counter() - t_gen:.1f} s")
 
-    def run(workers, fp32, arrivals, batch=0):
+    def run(workers, fp32, arrivals, batch=0, limit=None):
         cfg = hemamg.amg_server_config_default(workers=workers, batch=batch)
         cfg.params.precond_fp32 = fp32
         srv = hemamg.amg_server_create(cfg)
-        for _, _, x in dev:
+        items = dev if limit is None else dev[:limit]
+        for _, _, x in items:
             x.zero_()
         torch.cuda.synchronize()
         tickets = []
         t0 = time.perf_counter()
-        for i, (A, b, x) in enumerate(dev):
+        for i, (A, b, x) in enumerate(items):
             if arrivals is not None:
                 dt = t0 + arrivals[i] - time.perf_counter()
                 if dt > 0:
@@ -195,31 +233,45 @@ def serve_main(args):
         return dict(solves_per_s=len(res) / done, p50_ms=float(np.percentile(lat, 50)),
                     p99_ms=float(np.percentile(lat, 99)), mean_iters=float(np.mean([r["iters"] for r in res])))
 
-    run(1, 0, None)  # warm-up
+    run(1, 0, None, limit=32)  # warm-up
+    run(args.workers, 1, None, args.batch, limit=64)
     cap = run(1, 0, None)
     log(f"plain capacity {cap['solves_per_s']:.1f} solves/s")
     rng = np.random.default_rng(0)
     gaps = rng.exponential(1.0, len(dev))
     out_rates = {}
-    for f in args.rates:
+    for f in rates:
         lam = f * cap["solves_per_s"]
         arr = np.cumsum(gaps) / lam
-        plain = run(1, 0, arr)
-        served = run(args.workers, 1, arr)
-        batched = run(args.workers, 1, arr, args.batch)
-        out_rates[str(f)] = {"plain": plain, "served": served, "batched": batched}
-        log(f"rate {f}: plain {plain}, served {served}, batched {batched}")
-    closed = run(args.workers, 1, None)
+        r = {"plain": run(1, 0, arr), "batched": run(args.workers, 1, arr, args.batch)}
+        if closed_streams:
+            r["served"] = run(args.workers, 1, arr)
+        out_rates[str(f)] = r
+        log(f"rate {f}: {r}")
     closed_b = run(args.workers, 1, None, args.batch)
-    log(f"closed loop: streams {closed}, batched {closed_b}")
-    best, form = (closed_b, "batched") if closed_b["solves_per_s"] >= closed["solves_per_s"] else (closed, "streams")
+    log(f"closed loop, batched: {closed_b}")
+    out = {"workload": "served lognormal diffusion stream", "requests": len(dev), "rows": rows, "side": [16, 96],
+           "sigma": 1.0, "rtol": 1e-8, "method": "pcg", "workers": args.workers, "batch": args.batch,
+           "plain": "one request at a time, double", "batched": "grouped batched setup + solve, float preconditioner",
+           "plain_capacity": cap, "rates": out_rates, "batched_closed_loop": closed_b}
+    if closed_streams:
+        out["served_closed_loop"] = run(args.workers, 1, None)
+    del dev
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def serve_main(args):
+    """The served stream alone (--serve-only): one JSON line."""
+    out = served_stream(args, args.rates, closed_streams=True)
+    best = out["batched_closed_loop"]
     print(json.dumps({
         "metric": "served solves/s, p50/p99 latency", "value": best["solves_per_s"], "unit": "solves/s",
         "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f32+f64",
-        "config": {"workload": "served lognormal diffusion stream", "requests": len(dev), "rows": rows,
-                   "side": [16, 96], "sigma": 1.0, "rtol": 1e-8, "method": "pcg", "workers": args.workers,
-                   "batch": args.batch, "form": form},
-        "plain_capacity": cap, "served_closed_loop": closed, "batched_closed_loop": closed_b, "rates": out_rates,
+        "config": {k: out[k] for k in ("workload", "requests", "rows", "side", "sigma", "rtol", "method", "workers",
+                                       "batch")},
+        "served": out,
     }), flush=True)
 
 
@@ -243,11 +295,13 @@ def main():
                     help="also time the level-0 residual and the outer SpMV (more events in the timed region)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy 256 MiB device-to-device (counter calibration for profiles)")
-    ap.add_argument("--serve", action="store_true", help="served stream of solve requests instead of one system")
+    ap.add_argument("--serve-only", action="store_true", help="the served stream of solve requests alone")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served stream after the timed steps")
     ap.add_argument("--requests", type=int, default=1024)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--batch", type=int, default=32, help="batched serving: most requests per batched solve")
-    ap.add_argument("--rates", type=lambda t: [float(v) for v in t.split(",")], default=[0.5, 1.0, 2.0])
+    ap.add_argument("--rates", type=lambda t: [float(v) for v in t.split(",")], default=[0.5, 1.0, 2.0],
+                    help="arrival rates (fractions of the plain capacity) of --serve-only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver runs on one "
@@ -261,7 +315,7 @@ def main():
     if not torch.cuda.is_available():
         log("bench.py needs a ROCm GPU")
         sys.exit(1)
-    if args.serve:
+    if args.serve_only:
         serve_main(args)
         return
     torch.cuda.set_device(0)
@@ -337,7 +391,26 @@ def main():
                                  "gbs": kb[k] / (avg * 1e-3) / 1e9}
     dom = max(kern_tot, key=lambda k: kern_tot[k][1]) if kern_tot else 0
     c, ms = kern_tot.get(dom, (0, 0.0))
-    achieved = kb[dom] / (ms / c * 1e-3) / 1e9 if c else None
+    # the roofline of the dominant kernel (level-0 prolongation + postsmoothing)
+    # uses the byte model; the implementation's own count is reported beside it
+    mb = model_bytes(sizes, esz)
+    avg_s = ms / c * 1e-3 if c else None
+    achieved = mb / avg_s / 1e9 if c and dom == 0 else (kb[dom] / avg_s / 1e9 if c else None)
+    # setup: matching passes (GPU time of each pass from its own events)
+    st = recs[-1]["stats"]
+    m_ms = [float(np.median([r["stats"]["match_ms"][i] for r in recs])) for i in range(len(st["rounds"]))]
+    passes = []
+    for i, (rd, mm, pn, pz) in enumerate(zip(st["rounds"], m_ms, st["pass_n"], st["pass_nnz"])):
+        rb = 12 * pz + 4 * (pn + 1)  # one read of the matched operator
+        passes.append({"n": pn, "nnz": pz, "rounds": rd, "ms": mm, "us_per_round": mm * 1e3 / max(rd, 1),
+                       "read_bytes": rb, "hbm_frac": rb / (mm * 1e-3) / (HBM_PEAK_GBS * 1e9) if mm > 0 else None})
+    match_total = sum(m_ms)
+    setup_block = {"setup_ms": setup_ms, "matching_ms": match_total, "matching_share_of_setup": match_total / setup_ms,
+                   "rounds_total": int(sum(st["rounds"])),
+                   "us_per_round": match_total * 1e3 / max(sum(st["rounds"]), 1),
+                   "matching_hbm_frac": (sum(p["read_bytes"] for p in passes) / (match_total * 1e-3)
+                                         / (HBM_PEAK_GBS * 1e9)) if match_total > 0 else None,
+                   "passes": passes}
     out = {
         "metric": METRIC,
         "value": args.steps / elapsed,
@@ -361,12 +434,16 @@ def main():
         "iters": iters,
         "ms_per_iter": solve_ms / max(iters, 1),
         "solve_gbs": it_bytes * iters / (solve_ms * 1e-3) / 1e9,
-        "matching_rounds": recs[-1]["stats"]["rounds"],
+        "matching_rounds": st["rounds"],
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": measured_traffic(names[dom].split()[0], args.workload, precond),
-                     "algorithmic_bytes": kb[dom]},
+                     "algorithmic_bytes": mb if dom == 0 else kb[dom],
+                     "bytes_model": f"({esz}+4) nnz + 32 N + 8 N_c" if dom == 0 else "as implemented",
+                     "impl_bytes": kb[dom], "avg_us": avg_s * 1e6 if avg_s else None,
+                     "impl_frac": kb[dom] / avg_s / 1e9 / HBM_PEAK_GBS if avg_s else None},
+        "setup": setup_block,
     }
     if args.copy_calibration:
         src = torch.empty(1 << 25, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -379,6 +456,11 @@ def main():
         log("timing the CPU oracle on the same input")
         out["cpu_baseline"] = cpu_baseline(a, b_host, spec, iters, hem=int(args.hem == "edge"),
                                            alternate=int(args.alternate))
+    if not args.no_serve:
+        del A, b, x
+        torch.cuda.empty_cache()
+        log("served stream")
+        out["served"] = served_stream(args, [1.0])
     print(json.dumps(out), flush=True)
 
 

@@ -179,9 +179,13 @@ amg_status amg_level_size(const amg_hier* h, int32_t k, int32_t* n, int64_t* nnz
 amg_status amg_export_level(const amg_hier* h, int32_t k, int32_t* row_ptr, int32_t* col_idx, double* val,
                             int32_t* agg, void* stream);
 
-/* Setup statistics: matching rounds of each pass (up to `cap` entries) and
- * the bytes of GPU memory the handle owns.  [host] */
-amg_status amg_setup_stats(const amg_hier* h, int32_t* rounds, int32_t cap, int32_t* npasses, size_t* owned_bytes);
+/* Setup statistics of each matching pass, in setup order, up to `cap`
+ * entries per array: rounds run, GPU time in milliseconds (HIP events around
+ * the pass, its coarse numbering included), rows and entries of the matched
+ * operator; the number of passes and the bytes of GPU memory the handle owns.
+ * Any output may be NULL.  [host] */
+amg_status amg_setup_stats(const amg_hier* h, int32_t cap, int32_t* rounds, double* match_ms, int32_t* pass_n,
+                           int64_t* pass_nnz, int32_t* npasses, size_t* owned_bytes);
 
 /* Kernel timing for measurement: when enabled, the launches of the selected
  * kernel class are bracketed by HIP events on their stream and their

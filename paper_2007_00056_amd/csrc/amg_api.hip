@@ -953,6 +953,19 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, const amg_allocator* 
     SetupWork SW;
     if (A.n > p.max_coarse_rows && p.max_levels > 1)
         SW.init(A.n, A.nnz, wpool, h->err, p.hem == 1, p.alternate == 1);
+    // timing events around every matching pass (start/end pairs), read once
+    // the setup has synchronised
+    std::vector<hipEvent_t> pev;
+    struct EvGuard {
+        std::vector<hipEvent_t>& v;
+        ~EvGuard() {
+            for (hipEvent_t e : v) event_put(e, true);
+        }
+    } evg{pev};
+    auto mark_pass = [&](hipStream_t st) {
+        pev.push_back(event_get(true));
+        HIPCHK(hipEventRecord(pev.back(), st));
+    };
     for (int k = 0;; ++k) {
         Level& F = h->lev[k];
         if (F.n <= p.max_coarse_rows) break;
@@ -972,7 +985,11 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, const amg_allocator* 
         Csr B{F.n, F.nnz, const_cast<int*>(F.rp), const_cast<int*>(F.ci), const_cast<double*>(F.v)};
         // setup-wide pass index: with alternate, odd passes start from the last index
         const int g0 = k * p.passes_per_level;
+        mark_pass(s);
         Pass p1 = hem_pass(B, SW, 0, s, h->err, p.alternate && (g0 & 1));
+        mark_pass(s);
+        h->pass_n.push_back(B.n);
+        h->pass_nnz.push_back(B.nnz);
         DevPool& out1 = (p.passes_per_level == 1) ? P : tmp;
         Csr C1 = galerkin(B, p1, SW, out1, s, h->err);
         h->rounds.push_back(p1.rounds);
@@ -980,7 +997,11 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, const amg_allocator* 
         int* agg = nullptr;
         int4* mem = nullptr;
         if (p.passes_per_level == 2) {
+            mark_pass(s);
             Pass p2 = hem_pass(C1, SW, 1, s, h->err, p.alternate && ((g0 + 1) & 1));
+            mark_pass(s);
+            h->pass_n.push_back(C1.n);
+            h->pass_nnz.push_back(C1.nnz);
             Cf = galerkin(C1, p2, SW, P, s, h->err);
             h->rounds.push_back(p2.rounds);
             agg = P.get<int>(F.n);
@@ -1072,6 +1093,11 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, const amg_allocator* 
     static_assert(S_COUNT * sizeof(double) <= kPinnedBlock, "slots");
     h->S_host = static_cast<double*>(pinned_get());
     HIPCHK(hipStreamSynchronize(s));
+    for (size_t k = 0; k + 1 < pev.size(); k += 2) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, pev[k], pev[k + 1]));
+        h->match_ms.push_back(ms);
+    }
     h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = h.release();
 }
@@ -1601,12 +1627,18 @@ amg_status amg_export_level(const amg_hier* h, int32_t k, int32_t* row_ptr, int3
     });
 }
 
-amg_status amg_setup_stats(const amg_hier* h, int32_t* rounds, int32_t cap, int32_t* npasses, size_t* owned_bytes) {
+amg_status amg_setup_stats(const amg_hier* h, int32_t cap, int32_t* rounds, double* match_ms, int32_t* pass_n,
+                           int64_t* pass_nnz, int32_t* npasses, size_t* owned_bytes) {
     return guarded([&] {
         if (!h) raise(AMG_EINVAL, "amg_setup_stats: NULL handle");
-        if (npasses) *npasses = (int32_t)h->rounds.size();
-        if (rounds)
-            for (int32_t i = 0; i < cap && i < (int32_t)h->rounds.size(); ++i) rounds[i] = h->rounds[i];
+        const int32_t np = (int32_t)h->rounds.size();
+        if (npasses) *npasses = np;
+        for (int32_t i = 0; i < cap && i < np; ++i) {
+            if (rounds) rounds[i] = h->rounds[i];
+            if (match_ms) match_ms[i] = i < (int32_t)h->match_ms.size() ? h->match_ms[i] : 0.0;
+            if (pass_n) pass_n[i] = i < (int32_t)h->pass_n.size() ? h->pass_n[i] : 0;
+            if (pass_nnz) pass_nnz[i] = i < (int32_t)h->pass_nnz.size() ? h->pass_nnz[i] : 0;
+        }
         if (owned_bytes) *owned_bytes = h->pool.bytes;
     });
 }

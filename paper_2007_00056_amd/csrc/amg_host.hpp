@@ -270,6 +270,9 @@ struct amg_hier {
     double setup_ms = 0.0;  // host wall time of the setup call
     hipStream_t stream = nullptr;
     std::vector<int> rounds;
+    std::vector<double> match_ms;  // GPU time of each matching pass (with its numbering)
+    std::vector<int> pass_n;       // rows and entries of the operator each pass matched
+    std::vector<int64_t> pass_nnz;
     // Krylov workspace (allocated on first solve)
     double *r = nullptr, *z = nullptr, *pv[2] = {nullptr, nullptr}, *q = nullptr, *rb = nullptr, *pt = nullptr,
            *sv = nullptr, *st = nullptr, *t = nullptr;

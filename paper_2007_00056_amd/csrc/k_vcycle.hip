@@ -13,6 +13,8 @@
 // z = xp + w (g - D^{-1} A xp).
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "amg_internal.hpp"
 #include "amg_stream.hpp"
 
@@ -91,7 +93,9 @@ __global__ __launch_bounds__(BS) void k_vc_restrict(int nc, const int4* __restri
 
 // z = xp + w (g - D^{-1} A xp).  MODE 1 also forms block partials of (f, z)
 // in double; MODE 2 scatters z to the finer level's prolongated iterate.
-template <class T, class TOUT, int MODE, int RB>
+// GF: g = D^{-1} f is formed here from the level's right-hand side f (in
+// double, whoever wrote g formed exactly this product), so g is not read.
+template <class T, class TOUT, int MODE, int RB, bool GF>
 __global__ __launch_bounds__(RB) void k_vc_post(int n, const int* __restrict__ rp, EntAx<T> ent,
                                                 const T* __restrict__ g, const T* __restrict__ dinv, T w,
                                                 TOUT* __restrict__ z, const double* __restrict__ f, double* part,
@@ -102,7 +106,9 @@ __global__ __launch_bounds__(RB) void k_vc_post(int n, const int* __restrict__ r
         const T s = stream_rows<T, RB>(b * RB, n, rp, ent, prod);
         const int row = b * RB + threadIdx.x;
         if (row < n) {
-            const T zi = ent.x[row] + w * (g[row] - dinv[row] * s);
+            const T di = dinv[row];
+            const T gi = GF ? di * T(f[row]) : g[row];
+            const T zi = ent.x[row] + w * (gi - di * s);
             z[row] = TOUT(zi);
             if (MODE == 1) acc[0] += f[row] * double(zi);
             if (MODE == 2) sc(row, zi);
@@ -138,37 +144,47 @@ void vc_restrict(int nc, const int4* mem, const T* r, const T* dinv_c, T* fc, T*
     hipLaunchKernelGGL(k_vc_restrict<T>, dim3(level_blocks(nc, 1)), dim3(BS), 0, s, nc, mem, r, dinv_c, fc, gc);
 }
 
+template <class T, class TOUT, int MODE, int RB, bool GF>
+void post_launch(int gsz, hipStream_t s, hipEvent_t t0, hipEvent_t t1, int n, const int* rp, const EntAx<T>& ent,
+                 const T* g, const T* dinv, T w, TOUT* z, const double* f, double* part, const ScatterT<T>& sc) {
+    // with t0/t1 the dispatch itself records the kernel's start and end
+    if (t0)
+        hipExtLaunchKernelGGL((k_vc_post<T, TOUT, MODE, RB, GF>), dim3(gsz), dim3(RB), 0, s, t0, t1, 0, n, rp, ent, g,
+                              dinv, w, z, f, part, sc);
+    else
+        hipLaunchKernelGGL((k_vc_post<T, TOUT, MODE, RB, GF>), dim3(gsz), dim3(RB), 0, s, n, rp, ent, g, dinv, w, z, f,
+                           part, sc);
+}
+
+template <class T, class TOUT, int MODE, bool GF>
+void post_rb(int rb, int n, hipStream_t s, hipEvent_t t0, hipEvent_t t1, const int* rp, const EntAx<T>& ent,
+             const T* g, const T* dinv, T w, TOUT* z, const double* f, double* part, const ScatterT<T>& sc) {
+    const int gsz = rb_blocks(n, rb);
+    if (rb == 128) post_launch<T, TOUT, MODE, 128, GF>(gsz, s, t0, t1, n, rp, ent, g, dinv, w, z, f, part, sc);
+    else if (rb == 512) post_launch<T, TOUT, MODE, 512, GF>(gsz, s, t0, t1, n, rp, ent, g, dinv, w, z, f, part, sc);
+    else post_launch<T, TOUT, MODE, 256, GF>(gsz, s, t0, t1, n, rp, ent, g, dinv, w, z, f, part, sc);
+}
+
 template <class T, class TOUT>
 void vc_stream_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, const double* f, const Reducer* R,
                     int slot, const ScatterT<T>* sc, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     const int rb = L.rb == 128 || L.rb == 512 ? L.rb : 256;
-    const int gsz = rb_blocks(L.n, rb);
     const EntAx<T> ent{L.v, L.ci, xp};
     const ScatterT<T> none{nullptr, nullptr, nullptr, T(0)};
-    // with t0/t1 the dispatch itself records the kernel's start and end
-#define POST_RB(MODE, RB, ...)                                                                                     \
-    if (t0)                                                                                                        \
-        hipExtLaunchKernelGGL((k_vc_post<T, TOUT, MODE, RB>), dim3(gsz), dim3(RB), 0, s, t0, t1, 0, __VA_ARGS__);  \
-    else                                                                                                           \
-        hipLaunchKernelGGL((k_vc_post<T, TOUT, MODE, RB>), dim3(gsz), dim3(RB), 0, s, __VA_ARGS__)
-#define POST_LAUNCH(MODE, ...)                      \
-    if (rb == 128) {                                \
-        POST_RB(MODE, 128, __VA_ARGS__);            \
-    } else if (rb == 512) {                         \
-        POST_RB(MODE, 512, __VA_ARGS__);            \
-    } else {                                        \
-        POST_RB(MODE, 256, __VA_ARGS__);            \
-    }
+    // a double level 0 forms g = D^{-1} f itself instead of reading it
+    constexpr bool kCanGF = std::is_same<T, double>::value && std::is_same<TOUT, double>::value;
+    const bool gf = kCanGF && f != nullptr;
     if (R) {
-        POST_LAUNCH(1, L.n, L.rp, ent, g, L.dinv, w, z, f, R->part, none);
-        launch_finish(gsz, 1, *R, slot, slot, s);
+        if (gf) post_rb<T, TOUT, 1, kCanGF>(rb, L.n, s, t0, t1, L.rp, ent, g, L.dinv, w, z, f, R->part, none);
+        else post_rb<T, TOUT, 1, false>(rb, L.n, s, t0, t1, L.rp, ent, g, L.dinv, w, z, f, R->part, none);
+        launch_finish(rb_blocks(L.n, rb), 1, *R, slot, slot, s);
     } else if (sc) {
-        POST_LAUNCH(2, L.n, L.rp, ent, g, L.dinv, w, z, (const double*)nullptr, (double*)nullptr, *sc);
+        post_rb<T, TOUT, 2, false>(rb, L.n, s, t0, t1, L.rp, ent, g, L.dinv, w, z, nullptr, nullptr, *sc);
+    } else if (gf) {
+        post_rb<T, TOUT, 0, kCanGF>(rb, L.n, s, t0, t1, L.rp, ent, g, L.dinv, w, z, f, nullptr, none);
     } else {
-        POST_LAUNCH(0, L.n, L.rp, ent, g, L.dinv, w, z, (const double*)nullptr, (double*)nullptr, none);
+        post_rb<T, TOUT, 0, false>(rb, L.n, s, t0, t1, L.rp, ent, g, L.dinv, w, z, nullptr, nullptr, none);
     }
-#undef POST_LAUNCH
-#undef POST_RB
 }
 
 // ---------------------------------------------------------------------------

@@ -87,7 +87,7 @@ def lib():
             "amg_num_levels": [vp, C.POINTER(i32)],
             "amg_level_size": [vp, i32, C.POINTER(i32), C.POINTER(i64)],
             "amg_export_level": [vp, i32, vp, vp, vp, vp, vp],
-            "amg_setup_stats": [vp, vp, i32, C.POINTER(i32), C.POINTER(C.c_size_t)],
+            "amg_setup_stats": [vp, i32, vp, vp, vp, vp, C.POINTER(i32), C.POINTER(C.c_size_t)],
             "amg_timing_enable": [vp, i32, i32],
             "amg_timing_read": [vp, i32, C.POINTER(i64), C.POINTER(f64)],
             "amg_footprint_bytes": [i32, i64, C.POINTER(amg_params), C.POINTER(C.c_uint64)],
@@ -253,12 +253,20 @@ def amg_export_level(h: int, k: int, stream=None):
 
 
 def amg_setup_stats(h: int):
+    """Per matching pass: rounds, GPU ms, rows and entries of the matched
+    operator; and the bytes the handle owns."""
     cap = 256
     rounds = np.zeros(cap, np.int32)
+    ms = np.zeros(cap, np.float64)
+    pn = np.zeros(cap, np.int32)
+    pz = np.zeros(cap, np.int64)
     npass = C.c_int32()
     owned = C.c_size_t()
-    _check(lib().amg_setup_stats(h, rounds.ctypes.data, cap, C.byref(npass), C.byref(owned)))
-    return dict(rounds=rounds[:min(npass.value, cap)].tolist(), owned_bytes=owned.value)
+    _check(lib().amg_setup_stats(h, cap, rounds.ctypes.data, ms.ctypes.data, pn.ctypes.data, pz.ctypes.data,
+                                 C.byref(npass), C.byref(owned)))
+    k = min(npass.value, cap)
+    return dict(rounds=rounds[:k].tolist(), match_ms=ms[:k].tolist(), pass_n=pn[:k].tolist(), pass_nnz=pz[:k].tolist(),
+                owned_bytes=owned.value)
 
 
 def amg_timing_enable(h: int, kernel: int, on: bool = True) -> None:

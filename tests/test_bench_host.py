@@ -41,3 +41,22 @@ def test_committed_summaries_parse():
             kv = {k.strip(): v.strip() for k, v in kv.items()}
             assert kv["kernel"] == "k_vc_post" and len(kv["k_vcycle.hip sha256[:16]"]) == 16
             assert float(kv["hbm_bytes_per_launch"]) > 0
+
+
+def test_byte_counts_of_the_timed_kernel_at_128():
+    """Level-0 prolongation + postsmoothing of the 128^3 Poisson system:
+    the byte model 12 nnz + 32 N + 8 N_c, and the implementation's count
+    (row pointers, values and columns, the prolongated iterate, D^{-1}, the
+    result, and r read once, from which g = D^{-1} r is formed)."""
+    n, nnz, nc = 128 ** 3, 7 * 128 ** 3 - 6 * 128 ** 2, 64 * 64 * 128
+    sizes = [(n, nnz), (nc, 7 * nc)]
+    assert bench.model_bytes(sizes, 8) == 12 * nnz + 32 * n + 8 * nc == 246284288
+    assert bench.kernel_bytes(sizes, 8, "pcg")[0] == 12 * nnz + 4 * (n + 1) + 32 * n
+    # the float preconditioner reads g (float) and, for PCG's (r, z), r
+    assert bench.kernel_bytes(sizes, 4, "pcg")[0] == 8 * nnz + 4 * (n + 1) + 8 * n + 8 * n + 4 * n + 8 * n
+    assert bench.model_bytes(sizes, 4) == 8 * nnz + 32 * n + 8 * nc
+
+
+def test_host_description():
+    h = bench.host_cpu()
+    assert h["nproc"] >= 1 and (h["model"] is None or isinstance(h["model"], str))
