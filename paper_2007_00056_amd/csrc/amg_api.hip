@@ -53,8 +53,10 @@ void* pinned_get() {
             return p;
         }
     }
+    // mapped into the device and coherent: kernels may write slots straight
+    // into it, and the host reads them once the stream has finished
     void* p = nullptr;
-    HIPCHK(hipHostMalloc(&p, kPinnedBlock, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(&p, kPinnedBlock, hipHostMallocMapped | hipHostMallocCoherent));
     return p;
 }
 
@@ -522,11 +524,18 @@ void run_vcycle_t(amg_hier* h, const double* r, double* z, hipStream_t s, const 
     };
     if (part == 2) {  // level-0 postsmoothing (+ (r, z)) only
         const VLevel<T> V = vlevel<T>(L0);
+        h->rz_np = 0;
         if (streamed(h, L0)) {
             hipEvent_t t0, t1;
             timed_pair(h, 0, t0, t1);
-            vc_stream_post<T, double>(V, vec(L0.xp), g0, w, z, r, dot_slot >= 0 ? &R : nullptr, dot_slot, nullptr, s,
-                                      t0, t1);
+            if (dot_slot >= 0 && h->fuse_dots) {  // (r, z) partials for the direction kernel to add
+                const Reducer Rz{R.part + kPartRZ, R.S};
+                h->rz_np = vc_stream_post<T, double>(V, vec(L0.xp), g0, w, z, r, &Rz, kPartialsOnly, nullptr, s, t0,
+                                                     t1);
+            } else {
+                vc_stream_post<T, double>(V, vec(L0.xp), g0, w, z, r, dot_slot >= 0 ? &R : nullptr, dot_slot, nullptr,
+                                          s, t0, t1);
+            }
             timed_end(h, 0, s, true);
         } else {
             timed_begin(h, 0, s);
@@ -680,14 +689,26 @@ void spmv_dot_timed(amg_hier* h, const LevelView& A, const double* p, double* q,
 // One PCG iteration of parity pc (ping-pong of the direction vectors and of
 // the (r,z) slots): steps [A] q = A p, (p,q); x, r update, (r,r); V-cycle up
 // to level 1.  [P] level-0 postsmoothing and (r, z).  [B] next direction and
-// the read-back of the scalar slots (pinned host memory).
+// the hand-over of the scalar slots (mapped host memory).  The reductions of
+// the iteration are added by their consumer kernels from the producers' block
+// partials (the update adds (p, q), the direction kernel (r, z) and (r, r)),
+// so no separate finish kernel runs.
 void pcg_iter_a(amg_hier* h, double* x, int pc, hipStream_t s) {
     const Level& A0 = h->lev[0];
     const Reducer R = h->reducer();
     const int cur = pc ? S_RHO1 : S_RHO0, nxt = pc ? S_RHO0 : S_RHO1;
     double* p = h->pv[pc];
-    spmv_dot_timed(h, A0.view(), p, h->q, p, S_PQ, s);
-    launch_cg_update(A0.n, x, h->r, p, h->q, A0.dinv, h->g0, h->prec32, R, cur, S_PQ, S_RR, s);
+    if (h->fuse_dots) {
+        timed_begin(h, 2, s);
+        const int np = launch_spmv_dot_parts(A0.view(), p, h->q, p, R.part + kPartPQ, s);
+        timed_end(h, 2, s);
+        launch_cg_update(A0.n, x, h->r, p, h->q, A0.dinv, h->g0, h->prec32, R, cur, S_PQ, S_RR, s, R.part + kPartPQ,
+                         np, R.part + kPartRR, &h->rr_np);
+    } else {
+        spmv_dot_timed(h, A0.view(), p, h->q, p, S_PQ, s);
+        launch_cg_update(A0.n, x, h->r, p, h->q, A0.dinv, h->g0, h->prec32, R, cur, S_PQ, S_RR, s);
+        h->rr_np = 0;
+    }
     run_vcycle(h, h->r, h->z, s, h->g0, nxt, 1);
 }
 
@@ -697,8 +718,10 @@ void pcg_iter_p(amg_hier* h, int pc, hipStream_t s) {
 
 void pcg_iter_b(amg_hier* h, int pc, hipStream_t s) {
     const int cur = pc ? S_RHO1 : S_RHO0, nxt = pc ? S_RHO0 : S_RHO1;
-    launch_cg_dir(h->lev[0].n, h->z, h->pv[pc], h->pv[1 - pc], h->S, nxt, cur, s);
-    HIPCHK(hipMemcpyAsync(h->S_host, h->S, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+    double* part = h->part;
+    // the direction kernel also writes the slots into the mapped host block
+    launch_cg_dir(h->lev[0].n, h->z, h->pv[pc], h->pv[1 - pc], h->S, nxt, cur, s, h->S_dev, S_COUNT,
+                  h->rz_np ? part + kPartRZ : nullptr, h->rz_np, h->rr_np ? part + kPartRR : nullptr, h->rr_np, S_RR);
 }
 
 template <class F>
@@ -1070,6 +1093,7 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, const amg_allocator* 
     if (const char* e = getenv("HEMAMG_RB"))
         for (Level& L : h->lev) L.rb = atoi(e);
     if (const char* e = getenv("HEMAMG_GRAPHS")) h->use_graphs = atoi(e) != 0;
+    if (const char* e = getenv("HEMAMG_FUSE_DOTS")) h->fuse_dots = atoi(e) != 0;
     for (size_t k = 0; k < h->lev.size(); ++k) {
         Level& L = h->lev[k];
         if (k > 0) {
@@ -1090,8 +1114,9 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, const amg_allocator* 
     h->S = P.get<double>(S_COUNT);
     h->part = P.get<double>(2 * (size_t)kRedBlocks);
     HIPCHK(hipMemsetAsync(h->S, 0, S_COUNT * sizeof(double), s));
-    static_assert(S_COUNT * sizeof(double) <= kPinnedBlock, "slots");
+    static_assert((S_COUNT + 1) * sizeof(double) <= kPinnedBlock, "slots and a read-back word");
     h->S_host = static_cast<double*>(pinned_get());
+    HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&h->S_dev), h->S_host, 0));
     HIPCHK(hipStreamSynchronize(s));
     for (size_t k = 0; k + 1 < pev.size(); k += 2) {
         float ms = 0.f;
@@ -1493,6 +1518,101 @@ void batch_coarsen(const amg_csr* A, int count, const amg_params& p, hipStream_t
         if (S.status != AMG_OK) S.lev.clear();
 }
 
+// The Krylov solve behind krylov_solve.  ext (non-null): kKrylovVecs work
+// vectors of at least n doubles each that the caller provides; the solve
+// then draws nothing: no workspace from the handle's allocator, no stream of
+// its own, no graph capture, read-backs through the handle's pinned slots.
+amg_status krylov_run(amg_hier* h, int32_t method, const double* b, double* x, double rtol, int32_t maxit,
+                      void* stream, amg_info* info, double* const* ext) {
+    amg_info local{};
+    amg_info& I = info ? *info : local;
+    I = amg_info{};
+    const auto t0 = std::chrono::steady_clock::now();
+    amg_status st = AMG_OK;
+    amg_status g = guarded([&] {
+        if (!h || !b || !x) raise(AMG_EINVAL, "krylov_solve: NULL argument");
+        if (method < 0 || method > 2)
+            raise(AMG_EINVAL, "krylov_solve: method must be 0 (PCG), 1 (BiCGStab) or 2 (stationary)");
+        if (!(rtol >= 0.0) || maxit < 0) raise(AMG_EINVAL, "krylov_solve: rtol must be >= 0 and maxit >= 0");
+        hipStream_t s = as_stream(stream);
+        h->stream = s;
+        h->pool.s = s;
+        // the caller's vectors stand in for the handle's workspace for this
+        // call only (graphs captured on the handle's own vectors stay valid)
+        double* saved[kKrylovVecs];
+        double** slot[kKrylovVecs] = {&h->r, &h->z, &h->pv[0], &h->pv[1], &h->q,
+                                      &h->rb, &h->pt, &h->sv, &h->st, &h->t};
+        const bool graphs_were = h->use_graphs;
+        struct Restore {
+            amg_hier* h;
+            double** const* slot;
+            double* const* saved;
+            bool on, graphs;
+            ~Restore() {
+                if (!on) return;
+                for (int k = 0; k < kKrylovVecs; ++k) *slot[k] = saved[k];
+                h->use_graphs = graphs;
+            }
+        } restore{h, slot, saved, ext != nullptr, graphs_were};
+        if (ext) {
+            for (int k = 0; k < kKrylovVecs; ++k) {
+                saved[k] = *slot[k];
+                *slot[k] = ext[k];
+            }
+            h->use_graphs = false;
+        } else {
+            alloc_workspace(h);
+        }
+        // the solve runs on the caller's stream, or on the handle's own stream
+        // (ordered after the caller's prior work) when that is the null
+        // stream or graphs are replayed (they cannot be captured on it)
+        const bool own = !ext && (s == nullptr || h->use_graphs);
+        if (own && !h->gstream) {
+            h->gstream = stream_get();
+            h->gev[0] = event_get(false);
+            h->gev[1] = event_get(false);
+        }
+        if (own) {
+            HIPCHK(hipEventRecord(h->gev[0], s));
+            HIPCHK(hipStreamWaitEvent(h->gstream, h->gev[0], 0));
+        }
+        hipStream_t ws = own ? h->gstream : s;
+        h->pool.s = ws;
+        HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), ws));
+        launch_check_finite(h->lev[0].n, b, x, h->err, ws);
+        HIPCHK(hipGetLastError());
+        int e = 0;
+        if (ext) {  // the handle's pinned block, past the scalar slots
+            int* hw = reinterpret_cast<int*>(h->S_host + S_COUNT);
+            HIPCHK(hipMemcpyAsync(hw, h->err, sizeof(int), hipMemcpyDeviceToHost, ws));
+            HIPCHK(hipStreamSynchronize(ws));
+            e = *hw;
+        } else {
+            e = read_int(h->err, ws);
+        }
+        if (e & ERR_NONFINITE) raise(AMG_ENOTFINITE, "krylov_solve: b or x0 has NaN or Inf");
+        st = method == 0   ? pcg(h, b, x, rtol, maxit, ws, I)
+             : method == 1 ? bicgstab(h, b, x, rtol, maxit, ws, I)
+                           : stationary(h, b, x, rtol, maxit, ws, I);
+        HIPCHK(hipStreamSynchronize(ws));
+        if (own) {
+            HIPCHK(hipEventRecord(h->gev[1], ws));
+            HIPCHK(hipStreamWaitEvent(s, h->gev[1], 0));
+        }
+        h->pool.s = s;
+        if (st == AMG_ENOTCONV) g_err = "krylov_solve: iteration limit reached";
+        if (st == AMG_EBREAKDOWN) g_err = "krylov_solve: breakdown (zero or non-finite denominator)";
+    });
+    if (g != AMG_OK) st = g;
+    I.status = st;
+    I.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (h) {
+        I.setup_ms = h->setup_ms;
+        I.levels = (int32_t)h->lev.size();
+    }
+    return st;
+}
+
 }  // namespace amg
 
 extern "C" {
@@ -1540,59 +1660,7 @@ amg_status amg_vcycle(amg_hier* h, const double* r, double* z, void* stream) {
 
 amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x, double rtol, int32_t maxit,
                         void* stream, amg_info* info) {
-    amg_info local{};
-    amg_info& I = info ? *info : local;
-    I = amg_info{};
-    const auto t0 = std::chrono::steady_clock::now();
-    amg_status st = AMG_OK;
-    amg_status g = guarded([&] {
-        if (!h || !b || !x) raise(AMG_EINVAL, "krylov_solve: NULL argument");
-        if (method < 0 || method > 2)
-            raise(AMG_EINVAL, "krylov_solve: method must be 0 (PCG), 1 (BiCGStab) or 2 (stationary)");
-        if (!(rtol >= 0.0) || maxit < 0) raise(AMG_EINVAL, "krylov_solve: rtol must be >= 0 and maxit >= 0");
-        hipStream_t s = as_stream(stream);
-        h->stream = s;
-        h->pool.s = s;
-        alloc_workspace(h);
-        // the solve runs on the caller's stream, or on the handle's own stream
-        // (ordered after the caller's prior work) when that is the null
-        // stream or graphs are replayed (they cannot be captured on it)
-        const bool own = s == nullptr || h->use_graphs;
-        if (own && !h->gstream) {
-            h->gstream = stream_get();
-            h->gev[0] = event_get(false);
-            h->gev[1] = event_get(false);
-        }
-        if (own) {
-            HIPCHK(hipEventRecord(h->gev[0], s));
-            HIPCHK(hipStreamWaitEvent(h->gstream, h->gev[0], 0));
-        }
-        hipStream_t ws = own ? h->gstream : s;
-        h->pool.s = ws;
-        HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), ws));
-        launch_check_finite(h->lev[0].n, b, x, h->err, ws);
-        HIPCHK(hipGetLastError());
-        if (read_int(h->err, ws) & ERR_NONFINITE) raise(AMG_ENOTFINITE, "krylov_solve: b or x0 has NaN or Inf");
-        st = method == 0   ? pcg(h, b, x, rtol, maxit, ws, I)
-             : method == 1 ? bicgstab(h, b, x, rtol, maxit, ws, I)
-                           : stationary(h, b, x, rtol, maxit, ws, I);
-        HIPCHK(hipStreamSynchronize(ws));
-        if (own) {
-            HIPCHK(hipEventRecord(h->gev[1], ws));
-            HIPCHK(hipStreamWaitEvent(s, h->gev[1], 0));
-        }
-        h->pool.s = s;
-        if (st == AMG_ENOTCONV) g_err = "krylov_solve: iteration limit reached";
-        if (st == AMG_EBREAKDOWN) g_err = "krylov_solve: breakdown (zero or non-finite denominator)";
-    });
-    if (g != AMG_OK) st = g;
-    I.status = st;
-    I.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    if (h) {
-        I.setup_ms = h->setup_ms;
-        I.levels = (int32_t)h->lev.size();
-    }
-    return st;
+    return amg::krylov_run(h, method, b, x, rtol, maxit, stream, info, nullptr);
 }
 
 amg_status amg_num_levels(const amg_hier* h, int32_t* levels) {

@@ -254,17 +254,44 @@ void upload_mask(amg_batch* B, const std::vector<char>& on, int* dst, hipStream_
 
 inline bool usable(double d) { return std::isfinite(d) && d != 0.0; }
 
-// Algorithm 4 for every system of the batch, with the stop rule, residual
-// replacement and breakdown checks of the single-system solver applied per
-// system.
-void batch_pcg(amg_batch* B, double rtol, int maxit, hipStream_t s, amg_info* info) {
+}  // namespace
+
+namespace amg {
+
+// Algorithm 4 for every system of a batch, advanced one iteration at a time,
+// with the stop rule, residual replacement and breakdown checks of the
+// single-system solver applied per system.  A system leaves the iteration as
+// soon as it is done; its iterate then no longer changes.
+struct PcgRun {
+    amg_batch* B = nullptr;
+    double rtol = 0.0;
+    int maxit = 0;
+    hipStream_t s = nullptr;
+    std::vector<amg_info> info;
+    std::vector<double> nb;
+    std::vector<char> act, mark, zero;
+    int it = 0, pc = 0, live = 0;
+    bool pending = false;  // an iteration was enqueued and not collected
+};
+
+namespace {
+double slot(const PcgRun& R, int i, int k) { return R.B->S_host[(size_t)i * kBatchSlots + k]; }
+}  // namespace
+
+PcgRun* pcg_run_start(amg_batch* B, double rtol, int maxit, std::vector<int>& done) {
+    std::unique_ptr<PcgRun> R(new PcgRun());
+    R->B = B;
+    R->rtol = rtol;
+    R->maxit = maxit;
+    R->s = B->stream;
+    hipStream_t s = R->s;
     const int ns = B->nseg;
     const BLev& L0 = B->lev[0];
-    const double* S = B->S_host;
-    auto sv = [&](int i, int k) { return S[(size_t)i * kBatchSlots + k]; };
-    std::vector<double> nb(ns, 0.0);
-    std::vector<char> act(ns, 1), mark(ns, 0), zero(ns, 0);
-    for (int i = 0; i < ns; ++i) info[i] = amg_info{};
+    R->info.assign(ns, amg_info{});
+    R->nb.assign(ns, 0.0);
+    R->act.assign(ns, 1);
+    R->mark.assign(ns, 0);
+    R->zero.assign(ns, 0);
     // (b, b) and r = b - A x, g0 = D^{-1} r
     launch_bdot(B->nblk, B->tab(B->all), B->b, B->b, B->part, s);
     finish(B, B->all, B_BB, s);
@@ -273,31 +300,47 @@ void batch_pcg(amg_batch* B, double rtol, int maxit, hipStream_t s, amg_info* in
     finish(B, B->all, B_RR, s);
     read_slots(B, s);
     bool any_zero = false;
-    int live = 0;
     for (int i = 0; i < ns; ++i) {
         if (B->seg[i].status != AMG_OK) {  // its setup failed: nothing to solve
-            info[i].status = B->seg[i].status;
-            act[i] = 0;
+            R->info[i].status = B->seg[i].status;
+            R->act[i] = 0;
+            done.push_back(i);
             continue;
         }
-        nb[i] = std::sqrt(sv(i, B_BB));
-        if (nb[i] == 0.0) {  // x = 0 is the solution
-            zero[i] = 1;
+        R->nb[i] = std::sqrt(slot(*R, i, B_BB));
+        if (R->nb[i] == 0.0) {  // x = 0 is the solution
+            R->zero[i] = 1;
             any_zero = true;
-            act[i] = 0;
+            R->act[i] = 0;
+            done.push_back(i);
             continue;
         }
-        const double rel = std::sqrt(sv(i, B_RR)) / nb[i];
-        info[i].rel_res = info[i].true_rel_res = rel;
-        if (rel <= rtol) act[i] = 0;
-        live += act[i];
+        const double rel = std::sqrt(slot(*R, i, B_RR)) / R->nb[i];
+        R->info[i].rel_res = R->info[i].true_rel_res = rel;
+        if (rel <= rtol) {
+            R->act[i] = 0;
+            done.push_back(i);
+        }
+        R->live += R->act[i];
     }
     if (any_zero) {
-        upload_mask(B, zero, B->mark, s);
+        upload_mask(B, R->zero, B->mark, s);
         launch_bzero(B->nblk, B->tab(B->mark), B->x, s);
     }
-    upload_mask(B, act, B->act, s);
-    if (live == 0) return;
+    if (R->live > 0 && maxit <= 0) {  // no iteration allowed
+        for (int i = 0; i < ns; ++i)
+            if (R->act[i]) {
+                R->info[i].status = AMG_ENOTCONV;
+                R->act[i] = 0;
+                done.push_back(i);
+            }
+        R->live = 0;
+    }
+    upload_mask(B, R->act, B->act, s);
+    if (R->live == 0) {
+        HIPCHK(hipStreamSynchronize(s));
+        return R.release();
+    }
     vcycle(B, B->r, B->z, s);
     launch_bdot(B->nblk, B->tab(B->act), B->r, B->z, B->part, s);
     finish(B, B->act, B_RHO0, s);
@@ -305,76 +348,124 @@ void batch_pcg(amg_batch* B, double rtol, int maxit, hipStream_t s, amg_info* in
     if (B->use_graphs && !B->graph[0]) {
         for (int pc = 0; pc < 2; ++pc) B->graph[pc] = capture_graph(s, [&] { iteration(B, pc, s); });
     }
-    int pc = 0;
-    for (int it = 1; it <= maxit && live > 0; ++it) {
-        const int cur = pc ? B_RHO1 : B_RHO0, nxt = pc ? B_RHO0 : B_RHO1;
-        if (B->use_graphs) HIPCHK(hipGraphLaunch(B->graph[pc], s));
-        else iteration(B, pc, s);
-        read_slots(B, s);
-        bool any_mark = false, changed = false;
-        for (int i = 0; i < ns; ++i) {
-            if (!act[i]) continue;
-            if (!usable(sv(i, B_PQ)) || !std::isfinite(sv(i, cur))) {
-                info[i].status = AMG_EBREAKDOWN;
-                act[i] = 0;
-                changed = true;
-                continue;
-            }
-            info[i].iters = it;
-            const double rel = std::sqrt(sv(i, B_RR)) / nb[i];
-            info[i].rel_res = rel;
-            if (!std::isfinite(rel)) {
-                info[i].status = AMG_EBREAKDOWN;
-                act[i] = 0;
-                changed = true;
-                continue;
-            }
-            mark[i] = rel <= rtol || (B->period > 0 && it % B->period == 0);
-            any_mark |= mark[i] != 0;
+    HIPCHK(hipGetLastError());
+    return R.release();
+}
+
+void pcg_run_enqueue(PcgRun* R) {
+    if (R->live == 0 || R->pending) return;
+    amg_batch* B = R->B;
+    if (B->use_graphs) HIPCHK(hipGraphLaunch(B->graph[R->pc], R->s));
+    else iteration(B, R->pc, R->s);
+    HIPCHK(hipMemcpyAsync(B->S_host, B->S, sizeof(double) * kBatchSlots * B->nseg, hipMemcpyDeviceToHost, R->s));
+    HIPCHK(hipGetLastError());
+    R->pending = true;
+}
+
+void pcg_run_collect(PcgRun* R, std::vector<int>& done) {
+    if (!R->pending) return;
+    R->pending = false;
+    amg_batch* B = R->B;
+    hipStream_t s = R->s;
+    const int ns = B->nseg;
+    const BLev& L0 = B->lev[0];
+    HIPCHK(hipStreamSynchronize(s));
+    const int it = ++R->it;
+    const int pc = R->pc;
+    const int cur = pc ? B_RHO1 : B_RHO0, nxt = pc ? B_RHO0 : B_RHO1;
+    std::vector<char>& act = R->act;
+    std::vector<char>& mark = R->mark;
+    bool any_mark = false, changed = false;
+    auto leave = [&](int i) {
+        act[i] = 0;
+        changed = true;
+        done.push_back(i);
+    };
+    for (int i = 0; i < ns; ++i) {
+        if (!act[i]) continue;
+        if (!usable(slot(*R, i, B_PQ)) || !std::isfinite(slot(*R, i, cur))) {
+            R->info[i].status = AMG_EBREAKDOWN;
+            leave(i);
+            continue;
         }
-        if (any_mark) {  // recompute b - A x (residual replacement) for the marked systems
-            upload_mask(B, mark, B->mark, s);
-            launch_bresidual(B->nblk, B->tab(B->mark), L0.rp, L0.ci, L0.v, B->x, B->b, B->r, L0.dinv, B->g0,
-                             B->prec32, B->part, s);
-            finish(B, B->mark, B_TRR, s);
-            read_slots(B, s);
-            bool again = false;
-            for (int i = 0; i < ns; ++i) {
-                if (!mark[i]) continue;
-                const double tr = std::sqrt(sv(i, B_TRR)) / nb[i];
-                info[i].true_rel_res = tr;
-                if (tr <= rtol) {
-                    act[i] = 0;
-                    mark[i] = 0;
-                    changed = true;
-                } else {
-                    again = true;
-                }
-            }
-            if (again) {  // restart the direction from the recomputed residual
-                upload_mask(B, mark, B->mark, s);
-                vcycle(B, B->r, B->z, s);
-                launch_bdot(B->nblk, B->tab(B->mark), B->r, B->z, B->part, s);
-                finish(B, B->mark, nxt, s);
-                launch_bcg_dir(B->nblk, B->tab(B->mark), B->z, B->pv[pc], B->pv[1 - pc], B->S, nxt, cur, s);
-                read_slots(B, s);
-            }
-            std::fill(mark.begin(), mark.end(), 0);
+        R->info[i].iters = it;
+        const double rel = std::sqrt(slot(*R, i, B_RR)) / R->nb[i];
+        R->info[i].rel_res = rel;
+        if (!std::isfinite(rel)) {
+            R->info[i].status = AMG_EBREAKDOWN;
+            leave(i);
+            continue;
         }
-        for (int i = 0; i < ns; ++i) {
-            if (act[i] && !usable(sv(i, nxt))) {
-                info[i].status = AMG_EBREAKDOWN;
-                act[i] = 0;
-                changed = true;
-            }
-        }
-        live = 0;
-        for (int i = 0; i < ns; ++i) live += act[i];
-        if (changed && live > 0) upload_mask(B, act, B->act, s);
-        pc = 1 - pc;
+        mark[i] = rel <= R->rtol || (B->period > 0 && it % B->period == 0);
+        any_mark |= mark[i] != 0;
     }
-    for (int i = 0; i < ns; ++i)
-        if (act[i]) info[i].status = AMG_ENOTCONV;
+    if (any_mark) {  // recompute b - A x (residual replacement) for the marked systems
+        upload_mask(B, mark, B->mark, s);
+        launch_bresidual(B->nblk, B->tab(B->mark), L0.rp, L0.ci, L0.v, B->x, B->b, B->r, L0.dinv, B->g0,
+                         B->prec32, B->part, s);
+        finish(B, B->mark, B_TRR, s);
+        read_slots(B, s);
+        bool again = false;
+        for (int i = 0; i < ns; ++i) {
+            if (!mark[i]) continue;
+            const double tr = std::sqrt(slot(*R, i, B_TRR)) / R->nb[i];
+            R->info[i].true_rel_res = tr;
+            if (tr <= R->rtol) {
+                mark[i] = 0;
+                leave(i);
+            } else {
+                again = true;
+            }
+        }
+        if (again) {  // restart the direction from the recomputed residual
+            upload_mask(B, mark, B->mark, s);
+            vcycle(B, B->r, B->z, s);
+            launch_bdot(B->nblk, B->tab(B->mark), B->r, B->z, B->part, s);
+            finish(B, B->mark, nxt, s);
+            launch_bcg_dir(B->nblk, B->tab(B->mark), B->z, B->pv[pc], B->pv[1 - pc], B->S, nxt, cur, s);
+            read_slots(B, s);
+        }
+        std::fill(mark.begin(), mark.end(), 0);
+    }
+    for (int i = 0; i < ns; ++i) {
+        if (act[i] && !usable(slot(*R, i, nxt))) {
+            R->info[i].status = AMG_EBREAKDOWN;
+            leave(i);
+        }
+    }
+    R->live = 0;
+    for (int i = 0; i < ns; ++i) R->live += act[i];
+    if (R->live > 0 && it >= R->maxit) {  // iteration limit
+        for (int i = 0; i < ns; ++i)
+            if (act[i]) {
+                R->info[i].status = AMG_ENOTCONV;
+                act[i] = 0;
+                done.push_back(i);
+            }
+        R->live = 0;
+    } else if (changed && R->live > 0) {
+        upload_mask(B, act, B->act, s);
+    }
+    R->pc = 1 - pc;
+}
+
+int pcg_run_live(const PcgRun* R) { return R->live; }
+const amg_info& pcg_run_info(const PcgRun* R, int i) { return R->info[i]; }
+void pcg_run_end(PcgRun* R) { delete R; }
+
+}  // namespace amg
+
+namespace {
+
+void batch_pcg(amg_batch* B, double rtol, int maxit, hipStream_t s, amg_info* info) {
+    (void)s;  // the run uses the batch's own stream
+    std::vector<int> done;
+    std::unique_ptr<PcgRun> R(pcg_run_start(B, rtol, maxit, done));
+    while (R->live > 0 && R->it < maxit) {
+        pcg_run_enqueue(R.get());
+        pcg_run_collect(R.get(), done);
+    }
+    for (int i = 0; i < B->nseg; ++i) info[i] = R->info[i];
 }
 
 // D^{-1} v into the level-0 slot the V-cycle reads (a preconditioner input
@@ -867,6 +958,29 @@ void gather_run(const std::vector<GatherPiece>& pcs, DevPool& P, hipStream_t s) 
                   s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));  // the host tables are consumed
+}
+
+void batch_load(amg_batch* B, int i, const double* b, const double* x0, hipStream_t after) {
+    const BSeg& g = B->seg[i];
+    if (after) {
+        HIPCHK(hipEventRecord(B->ev[0], after));
+        HIPCHK(hipStreamWaitEvent(B->stream, B->ev[0], 0));
+    }
+    if (g.n0 == 0) return;
+    HIPCHK(hipMemcpyAsync(B->b + g.off0, b, sizeof(double) * g.n0, hipMemcpyDeviceToDevice, B->stream));
+    HIPCHK(hipMemcpyAsync(B->x + g.off0, x0, sizeof(double) * g.n0, hipMemcpyDeviceToDevice, B->stream));
+}
+
+const double* batch_x(const amg_batch* B, int i, int* n) {
+    *n = B->seg[i].n0;
+    return B->x + B->seg[i].off0;
+}
+
+hipStream_t batch_stream(const amg_batch* B) { return B->stream; }
+
+void batch_fill_info(const amg_batch* B, int i, amg_info& I) {
+    I.setup_ms = B->setup_ms;
+    I.levels = B->seg[i].nlev;
 }
 
 }  // namespace amg

@@ -62,6 +62,31 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double* part) {
     }
 }
 
+// Sum of np block partials in a fixed order, formed by a whole block of BS
+// threads and returned to every thread: lane sums over a stride of BS, the
+// wave butterfly, then the waves in order.  Every block that calls it gets
+// the same value, so a consumer kernel can finish a reduction itself.
+template <int BS>
+__device__ __forceinline__ double block_sum_partials(const double* __restrict__ part, int np) {
+    static_assert(BS % kWave == 0, "block size must be whole waves");
+    constexpr int NW = BS / kWave;
+    __shared__ double sh[NW];
+    __shared__ double tot;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < np; b += BS) s += part[b];
+    s = group_sum<kWave>(s);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) sh[wid] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int w = 1; w < NW; ++w) t += sh[w];
+        tot = t;
+    }
+    __syncthreads();
+    return tot;
+}
+
 // Sorted list of up to CAP (key, sum) pairs kept in registers (all indexing
 // resolves at compile time after unrolling).  The first value added for a key
 // initialises its sum; later values are added in call order.

@@ -53,7 +53,7 @@ void stream_put(hipStream_t s);
 hipEvent_t event_get(bool timing);
 void event_put(hipEvent_t e, bool timing);
 // Pinned host blocks of kPinnedBlock bytes (scalar slots of a handle or a
-// batch), kept for reuse.
+// batch), mapped into the device and coherent, kept for reuse.
 constexpr size_t kPinnedBlock = 4096;
 void* pinned_get();
 void pinned_put(void* p);
@@ -248,6 +248,33 @@ struct SegSrc {
 void validate_params(const amg_params& p);
 // Copies every piece with one launch (blocks the host until done).
 void gather_run(const std::vector<GatherPiece>& pcs, DevPool& P, hipStream_t s);
+// Work vectors of a Krylov solve (PCG, BiCGStab, stationary), n doubles each.
+constexpr int kKrylovVecs = 10;
+amg_status krylov_run(amg_hier* h, int32_t method, const double* b, double* x, double rtol, int32_t maxit,
+                      void* stream, amg_info* info, double* const* ext);
+// Batched PCG advanced one iteration at a time (the solve of amg_batch_solve
+// with method 0, step by step): start runs the prologue on the batch's stream
+// from the right-hand sides and initial guesses already in the batch
+// (batch_load), enqueue queues one iteration, collect waits for it and
+// applies the per-system rules.  `done` receives the systems that left the
+// iteration (their iterate is final from then on).  Blocks the host in start
+// and collect only.
+struct PcgRun;
+PcgRun* pcg_run_start(amg_batch* B, double rtol, int maxit, std::vector<int>& done);
+void pcg_run_enqueue(PcgRun* R);
+void pcg_run_collect(PcgRun* R, std::vector<int>& done);
+int pcg_run_live(const PcgRun* R);
+const amg_info& pcg_run_info(const PcgRun* R, int i);
+void pcg_run_end(PcgRun* R);
+// System i's right-hand side and initial guess into the batch (device to
+// device, on the batch's stream, ordered after `after` when given).
+void batch_load(amg_batch* B, int i, const double* b, const double* x0, hipStream_t after);
+// Device address and rows of system i's iterate inside the batch, and the
+// batch's stream.
+const double* batch_x(const amg_batch* B, int i, int* n);
+hipStream_t batch_stream(const amg_batch* B);
+// setup_ms and levels of system i (what amg_batch_solve reports).
+void batch_fill_info(const amg_batch* B, int i, amg_info& I);
 // Batched setup: the systems' levels are built together on concatenated
 // operators (one matching round and one Galerkin launch per step for all of
 // them) with each system's stop rule applied to it alone.  The device arrays
@@ -282,7 +309,12 @@ struct amg_hier {
     double* part = nullptr;
     int* err = nullptr;
     int stream_min = 262144;  // levels with at least this many rows use CSR-stream kernels
-    double* S_host = nullptr;
+    // the PCG iteration's reductions are added by their consumer kernels
+    // (HEMAMG_FUSE_DOTS=0: separate finish kernels); partial counts pending
+    bool fuse_dots = true;
+    int rz_np = 0, rr_np = 0;
+    double* S_host = nullptr;  // pinned, mapped and coherent host block of the slots
+    double* S_dev = nullptr;   // the same block's device address
     Timer tim[3];
     // PCG iteration graphs (one per ping-pong parity), replayed on gstream
     bool use_graphs = false;  // HEMAMG_GRAPHS=1: replay PCG iterations from HIP graphs

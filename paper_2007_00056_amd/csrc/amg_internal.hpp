@@ -190,10 +190,13 @@ template <class T, class TIN>
 void vc_stream_resid(const VLevel<T>& L, const TIN* f, const T* g, T w, T* r, hipStream_t s);
 template <class T>
 void vc_restrict(int nc, const int4* mem, const T* r, const T* dinv_c, T* fc, T* gc, hipStream_t s);
+// slot == kPartialsOnly: the (f, z) partials stay in R->part (at most
+// kFusedParts blocks) for a consumer kernel to add; returns their number (0
+// when no partials are left).
 template <class T, class TOUT>
-void vc_stream_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, const double* f, const Reducer* R,
-                    int slot, const ScatterT<T>* sc, hipStream_t s, hipEvent_t t0 = nullptr,
-                    hipEvent_t t1 = nullptr);  // t0/t1: recorded at the start/end of the main kernel
+int vc_stream_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, const double* f, const Reducer* R,
+                   int slot, const ScatterT<T>* sc, hipStream_t s, hipEvent_t t0 = nullptr,
+                   hipEvent_t t1 = nullptr);  // t0/t1: recorded at the start/end of the main kernel
 // Small levels: the same operations with the restriction fused.
 template <class T, class TIN>
 void vc_resid_restrict(const VLevel<T>& L, int nc, const TIN* f, const T* g, T w, const T* dinv_c, T* fc, T* gc,
@@ -227,12 +230,27 @@ void launch_residual(const LevelView& A, const double* b, const double* x, doubl
 void launch_dot(int n, const double* a, const double* b, const Reducer& R, int slot, hipStream_t s);
 void launch_spmv_dot(const LevelView& A, const double* p, double* q, const double* d, const Reducer& R, int slot,
                      hipStream_t s);
+// q = A p with the block partials of (d, q) left in part (at most
+// kFusedParts blocks); returns their number.
+int launch_spmv_dot_parts(const LevelView& A, const double* p, double* q, const double* d, double* part,
+                          hipStream_t s);
 void launch_spmv_dot2(const LevelView& A, const double* p, double* t, const double* sv, const Reducer& R, int slot_tt,
                       int slot_ts, hipStream_t s);
+// pq_part (non-null): the update adds the pq_np partials of (p, q) itself
+// (block 0 stores the sum in slot_pq) and leaves the partials of (r, r) in
+// rr_part (at most kFusedParts blocks; *rr_np receives their number) instead
+// of finishing them into slot_rr.
 void launch_cg_update(int n, double* x, double* r, const double* p, const double* q, const double* dinv, void* gout,
-                      bool g32, const Reducer& R, int slot_rho, int slot_pq, int slot_rr, hipStream_t s);
-void launch_cg_dir(int n, const double* z, const double* p, double* pn, const double* S, int slot_new, int slot_old,
-                   hipStream_t s);
+                      bool g32, const Reducer& R, int slot_rho, int slot_pq, int slot_rr, hipStream_t s,
+                      const double* pq_part = nullptr, int pq_np = 0, double* rr_part = nullptr, int* rr_np = nullptr);
+// Sh/nsh: optional host memory mapped into the device that receives the
+// first nsh scalar slots (nsh <= 256).  new_part (non-null): the kernel adds
+// the new_np partials of the new (r, z) itself (block 0 stores the sum in
+// slot_new).  rr_part (non-null): block 0 adds the rr_np partials of (r, r)
+// into slot_rr.
+void launch_cg_dir(int n, const double* z, const double* p, double* pn, double* S, int slot_new, int slot_old,
+                   hipStream_t s, double* Sh = nullptr, int nsh = 0, const double* new_part = nullptr, int new_np = 0,
+                   const double* rr_part = nullptr, int rr_np = 0, int slot_rr = 0);
 void launch_bicg_s(int n, const double* r, const double* v, double* sv, const double* S, int slot_rho, int slot_rv,
                    hipStream_t s);
 void launch_bicg_update(int n, double* x, double* r, const double* pt, const double* st, const double* sv,
@@ -246,6 +264,14 @@ void launch_add(int n, double* x, const double* z, hipStream_t s);
 void launch_check_finite(int n, const double* a, const double* b, int* err, hipStream_t s);
 
 constexpr int kRedBlocks = 65536;  // max blocks (partials) of a reduction kernel
+// Reductions whose consumer kernel adds the partials itself use at most this
+// many blocks (each consumer block reads them all).
+constexpr int kFusedParts = 2048;
+// Partial regions of the PCG iteration inside Reducer::part (each holds up to
+// kFusedParts): (p, q) of the SpMV, (r, r) of the update, (r, z) of the
+// level-0 postsmoothing.
+constexpr int kPartPQ = 0, kPartRR = 4096, kPartRZ = 8192;
+constexpr int kPartialsOnly = -2;  // slot value: leave the block partials, no finish kernel
 
 // ---- batched solves (k_batch.hip) -------------------------------------------
 // Systems ("segments") stored one after another.  blk[b] = (segment, first

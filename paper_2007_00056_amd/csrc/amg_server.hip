@@ -1,23 +1,31 @@
 // Serving loop: independent solve requests run concurrently on one GPU.
 //
-// Each worker thread owns a HIP stream and runs whole requests (setup,
-// Krylov solve, teardown) through the public entry points; kernels of
-// different requests overlap on the device.  Requests are admitted in arrival
-// order while the footprints of the requests in flight fit the budget; a
-// request waits at the head of the queue until enough finish.
+// Requests are admitted in arrival order while the footprints of the
+// requests in flight fit the budget; a request waits at the head of the
+// queue until enough memory is released.
 //
-// Batched mode (batch >= 2): a worker takes the queued PCG (or BiCGStab)
-// requests with the same method and stop settings (up to `batch`, within the
-// budget) as one group, builds
-// their hierarchies together (amg_batch_setup) and solves them together
-// (amg_batch_solve); requests arriving meanwhile form the next group, on
-// the next free worker.
+// Plain mode: each worker thread owns a HIP stream and runs whole requests
+// (setup, Krylov solve, teardown) through the public entry points; kernels
+// of different requests overlap on the device.
+//
+// Batched mode (batch >= 2), continuous: worker threads take the queued
+// requests of one class (method, stop settings, small or large systems; up
+// to `batch`, within the budget) and build their hierarchies together
+// (amg_batch_setup).  A PCG group then joins the solve scheduler, one
+// thread that advances every batch in flight by one iteration per tick
+// (each batch on its own stream, so their kernels overlap), while the
+// workers already set up the next groups from whatever has arrived since.
+// A request is complete as soon as its own system leaves the iteration; the
+// batch's memory, and the budget of its requests, is released when its last
+// system is done.  BiCGStab groups are solved by their worker in one call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstdint>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -90,15 +98,28 @@ struct amg_server {
     amg_server_config cfg{};
     int device = 0;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_solve;
     std::deque<int64_t> pending;
     std::unordered_map<int64_t, Request*> reqs;
     int64_t next_id = 1;
     uint64_t in_use = 0;
     int active = 0;
     bool stopping = false;
+    bool workers_done = false;
     std::vector<std::thread> threads;
+    std::thread scheduler;
     std::vector<hipStream_t> wstreams;  // one per worker, destroyed with the server
+
+    // A set-up PCG group waiting for, or in, the solve scheduler.
+    struct Flight {
+        amg_batch* bt = nullptr;
+        std::vector<Request*> grp;     // nullptr once the request is complete
+        std::vector<uint64_t> feet;    // budget released with the batch
+        std::vector<char> batched;     // system i is solved in the batch
+        amg::PcgRun* run = nullptr;
+        Clock::time_point t0;
+    };
+    std::deque<std::unique_ptr<Flight>> ready;  // set up, not yet started
 
     void release_streams() {
         for (hipStream_t& st : wstreams)
@@ -110,17 +131,50 @@ struct amg_server {
     }
 
     bool batched() const { return cfg.batch >= 2; }
+    const amg_allocator* alloc() const { return cfg.alloc.alloc ? &cfg.alloc : nullptr; }
 
-    void finish(Request* r) {
+    // Workers drain the queue and exit, then the scheduler finishes the
+    // batches in flight and exits.
+    void stop_threads() {
         {
             std::lock_guard<std::mutex> lk(mu);
-            in_use -= r->foot;
-            --active;
+            stopping = true;
+        }
+        cv_work.notify_all();
+        for (auto& t : threads) t.join();
+        threads.clear();
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            workers_done = true;
+        }
+        cv_solve.notify_all();
+        if (scheduler.joinable()) scheduler.join();
+    }
+
+    // The request's result is final: its waiter may proceed (and free it).
+    void complete(Request* r) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
             r->done = true;
             r->t_done = Clock::now();
         }
         cv_done.notify_all();
+    }
+
+    // Its memory is released: admission may take the next requests.
+    void release(uint64_t foot) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            in_use -= foot;
+            --active;
+        }
         cv_work.notify_all();
+    }
+
+    void finish(Request* r) {
+        const uint64_t f = r->foot;
+        complete(r);
+        release(f);
     }
 
     // Worker i runs on wstreams[i].  It takes the request at the head of the
@@ -172,13 +226,17 @@ struct amg_server {
                     amg::event_put(r->ready, false);
                     r->ready = nullptr;
                 }
-            if (!(batched() && grp[0]->method <= 1)) run_one(grp[0], s);
-            else run_group(grp, s);
-            for (Request* r : grp) finish(r);
+            if (!(batched() && grp[0]->method <= 1)) {
+                run_one(grp[0], s);
+                finish(grp[0]);
+            } else if (grp[0]->method == 0) {
+                setup_group(grp, s);  // on to the solve scheduler
+            } else {
+                run_group(grp, s);
+                for (Request* r : grp) finish(r);
+            }
         }
     }
-
-    const amg_allocator* alloc() const { return cfg.alloc.alloc ? &cfg.alloc : nullptr; }
 
     // Setup, solve and teardown of one request.
     void run_one(Request* r, hipStream_t s) {
@@ -203,9 +261,73 @@ struct amg_server {
         r->info.status = st;
     }
 
-    // Batched mode: one batched setup and one batched PCG solve for the group.
-    // When the batched setup fails as a whole, or a system cannot be batched
-    // (a single level), the requests concerned are run one by one.
+    // A PCG group: batched setup on the worker's stream, the systems' right-
+    // hand sides and initial guesses loaded into the batch, then the group
+    // joins the solve scheduler.  When the batched setup fails as a whole, or a
+    // system cannot be batched (a single level), the requests concerned are
+    // run one by one here.
+    void setup_group(std::vector<Request*>& grp, hipStream_t s) {
+        const int n = (int)grp.size();
+        std::vector<amg_csr> A(n);
+        for (int i = 0; i < n; ++i) A[i] = grp[i]->A;
+        std::vector<amg_status> st(n, AMG_OK);
+        amg_batch* bt = nullptr;
+        if (!s || amg_batch_setup(A.data(), n, &cfg.params, alloc(), s, &bt, st.data()) != AMG_OK) {
+            for (Request* r : grp) {
+                run_one(r, s);
+                finish(r);
+            }
+            return;
+        }
+        (void)amg_batch_set_graphs(bt, 0);
+        std::unique_ptr<Flight> F(new Flight());
+        F->bt = bt;
+        F->grp = grp;
+        F->batched.assign(n, 1);
+        for (Request* r : grp) F->feet.push_back(r->foot);
+        std::vector<int32_t> off(n + 1);
+        (void)amg_batch_rows(bt, off.data());
+        std::vector<Request*> alone;
+        const amg_status lst = amg::guarded([&] {
+            for (int i = 0; i < n; ++i) {
+                if (st[i] == AMG_EINVAL && off[i + 1] == off[i]) {  // invalid or a single level: the plain path
+                    F->batched[i] = 0;
+                    continue;
+                }
+                if (off[i + 1] > off[i]) amg::batch_load(bt, i, grp[i]->b, grp[i]->x, i == 0 ? s : nullptr);
+            }
+        });
+        if (lst != AMG_OK) {
+            (void)amg_batch_destroy(bt);
+            for (Request* r : grp) {
+                fail(r, lst);
+                finish(r);
+            }
+            return;
+        }
+        F->feet.clear();
+        for (int i = 0; i < n; ++i) {
+            if (!F->batched[i]) {
+                alone.push_back(grp[i]);
+                F->grp[i] = nullptr;
+            } else {
+                F->feet.push_back(grp[i]->foot);
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            ready.push_back(std::move(F));
+        }
+        cv_solve.notify_one();
+        for (Request* r : alone) {
+            run_one(r, s);
+            finish(r);
+        }
+    }
+
+    // BiCGStab groups: one batched setup and one batched solve.  When the
+    // batched setup fails as a whole, or a system cannot be batched (a single
+    // level), the requests concerned are run one by one.
     void run_group(std::vector<Request*>& grp, hipStream_t s) {
         const int n = (int)grp.size();
         if (!s) {
@@ -275,6 +397,105 @@ struct amg_server {
             }
         }
     }
+
+    // System i of flight F is done: its iterate goes to the request's x (on
+    // the batch's stream, waited for), and the request completes.
+    void deliver(Flight& F, int i, amg_status err = AMG_OK) {
+        Request* r = F.grp[i];
+        if (!r) return;
+        F.grp[i] = nullptr;
+        if (err != AMG_OK) {
+            fail(r, err);
+        } else {
+            r->info = amg::pcg_run_info(F.run, i);
+            amg::batch_fill_info(F.bt, i, r->info);
+            r->st = (amg_status)r->info.status;
+            int n = 0;
+            const double* xs = amg::batch_x(F.bt, i, &n);
+            hipStream_t bs = amg::batch_stream(F.bt);
+            if (n > 0 && (hipMemcpyAsync(r->x, xs, sizeof(double) * n, hipMemcpyDeviceToDevice, bs) != hipSuccess ||
+                          hipStreamSynchronize(bs) != hipSuccess))
+                fail(r, AMG_EHIP);
+        }
+        r->info.solve_ms = std::chrono::duration<double, std::milli>(Clock::now() - F.t0).count();
+        complete(r);
+    }
+
+    // The last system of F is done: the batch and the budget go.
+    void retire(Flight& F) {
+        for (size_t i = 0; i < F.grp.size(); ++i) deliver(F, (int)i, AMG_EHIP);  // none left normally
+        if (F.run) amg::pcg_run_end(F.run);
+        F.run = nullptr;
+        (void)amg_batch_destroy(F.bt);
+        F.bt = nullptr;
+        for (uint64_t f : F.feet) release(f);
+    }
+
+    // The solve scheduler: every tick, each batch in flight gets one PCG
+    // iteration enqueued on its own stream, then each is collected; groups
+    // set up meanwhile join at the next tick.
+    void solve_loop() {
+        if (hipSetDevice(device) != hipSuccess) return;
+        std::vector<std::unique_ptr<Flight>> live;
+        std::vector<int> done;
+        for (;;) {
+            std::vector<std::unique_ptr<Flight>> fresh;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_solve.wait(lk, [&] { return !ready.empty() || !live.empty() || workers_done; });
+                if (ready.empty() && live.empty() && workers_done) break;
+                while (!ready.empty()) {
+                    fresh.push_back(std::move(ready.front()));
+                    ready.pop_front();
+                }
+            }
+            for (auto& F : fresh) {
+                F->t0 = Clock::now();
+                done.clear();
+                const Request* r0 = nullptr;
+                for (Request* r : F->grp)
+                    if (r) {
+                        r0 = r;
+                        break;
+                    }
+                const amg_status st = amg::guarded([&] {
+                    if (r0) F->run = amg::pcg_run_start(F->bt, r0->rtol, r0->maxit, done);
+                });
+                if (st != AMG_OK || !r0) {
+                    for (size_t i = 0; i < F->grp.size(); ++i) deliver(*F, (int)i, st != AMG_OK ? st : AMG_EHIP);
+                    retire(*F);
+                    continue;
+                }
+                for (int i : done) deliver(*F, i);
+                if (amg::pcg_run_live(F->run) == 0) {
+                    retire(*F);
+                    continue;
+                }
+                live.push_back(std::move(F));
+            }
+            for (auto& F : live) {
+                const amg_status st = amg::guarded([&] { amg::pcg_run_enqueue(F->run); });
+                if (st != AMG_OK)
+                    for (size_t i = 0; i < F->grp.size(); ++i) deliver(*F, (int)i, st);
+            }
+            for (auto& F : live) {
+                done.clear();
+                const amg_status st = amg::guarded([&] { amg::pcg_run_collect(F->run, done); });
+                for (int i : done) deliver(*F, i);
+                if (st != AMG_OK)
+                    for (size_t i = 0; i < F->grp.size(); ++i) deliver(*F, (int)i, st);
+            }
+            for (auto& F : live) {
+                bool any = false;
+                for (Request* r : F->grp) any |= r != nullptr;
+                if (!any) {
+                    retire(*F);
+                    F.reset();
+                }
+            }
+            live.erase(std::remove(live.begin(), live.end(), nullptr), live.end());
+        }
+    }
 };
 
 extern "C" {
@@ -321,14 +542,10 @@ amg_status amg_server_create(const amg_server_config* c, amg_server** out) {
                 delete s;
                 return AMG_EHIP;
             }
+        if (s->batched()) s->scheduler = std::thread([s] { s->solve_loop(); });
         for (int i = 0; i < cfg.workers; ++i) s->threads.emplace_back([s, i] { s->worker(i); });
     } catch (...) {
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->stopping = true;
-        }
-        s->cv_work.notify_all();
-        for (auto& t : s->threads) t.join();
+        s->stop_threads();
         s->release_streams();
         delete s;
         return AMG_ENOMEM;
@@ -402,12 +619,7 @@ amg_status amg_server_wait(amg_server* s, int64_t ticket, amg_info* info, double
 
 amg_status amg_server_destroy(amg_server* s) {
     if (!s) return AMG_OK;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->stopping = true;
-    }
-    s->cv_work.notify_all();
-    for (auto& t : s->threads) t.join();
+    s->stop_threads();
     s->release_streams();
     for (auto& kv : s->reqs) {
         if (kv.second->ready) amg::event_put(kv.second->ready, false);

@@ -246,6 +246,13 @@ void launch_spmv_dot(const LevelView& A, const double* p, double* q, const doubl
     finish(g, 1, R, slot, slot, s);
 }
 
+int launch_spmv_dot_parts(const LevelView& A, const double* p, double* q, const double* d, double* part,
+                          hipStream_t s) {
+    const int g = amg::stream_blocks(A.n, kFusedParts);
+    hipLaunchKernelGGL(k_stream_spmv_dot, dim3(g), dim3(BS), 0, s, A.n, A.rp, EntAxD{A.v, A.ci, p}, q, d, part);
+    return g;
+}
+
 // t = A p, partials (t, t) and (t, sv)
 __global__ __launch_bounds__(BS) void k_stream_spmv_dot2(int n, const int* __restrict__ rp, EntAxD ent,
                                                          double* __restrict__ t, const double* __restrict__ sv,
@@ -285,13 +292,22 @@ void launch_dot(int n, const double* a, const double* b, const Reducer& R, int s
 }
 
 // Algorithm 4: alpha = (r,z)/(Ap,p); x += alpha p; r -= alpha Ap; partial (r,r).
+// pq_part: (Ap, p) is added here from the SpMV's partials (every block the
+// same sum), and block 0 stores it in slot_pq for the host.
 template <class TG>
 __global__ __launch_bounds__(BS) void k_cg_update(int n, double* __restrict__ x, double* __restrict__ r,
                                                   const double* __restrict__ p, const double* __restrict__ q,
                                                   const double* __restrict__ dinv, TG* __restrict__ g,
-                                                  double* part, const double* __restrict__ S, int slot_rho,
-                                                  int slot_pq) {
-    const double rho = S[slot_rho], pq = S[slot_pq];
+                                                  double* part, double* __restrict__ S, int slot_rho,
+                                                  int slot_pq, const double* __restrict__ pq_part, int pq_np) {
+    double pq;
+    if (pq_part) {
+        pq = block_sum_partials<BS>(pq_part, pq_np);
+        if (blockIdx.x == 0 && threadIdx.x == 0) S[slot_pq] = pq;
+    } else {
+        pq = S[slot_pq];
+    }
+    const double rho = S[slot_rho];
     const bool ok = usable(pq) && isfinite(rho);
     const double alpha = ok ? rho / pq : 0.0;
     double acc[1] = {0.0};
@@ -309,28 +325,52 @@ __global__ __launch_bounds__(BS) void k_cg_update(int n, double* __restrict__ x,
 }
 
 void launch_cg_update(int n, double* x, double* r, const double* p, const double* q, const double* dinv, void* gout,
-                      bool g32, const Reducer& R, int slot_rho, int slot_pq, int slot_rr, hipStream_t s) {
-    const int g = vec_blocks(n);
+                      bool g32, const Reducer& R, int slot_rho, int slot_pq, int slot_rr, hipStream_t s,
+                      const double* pq_part, int pq_np, double* rr_part, int* rr_np) {
+    const bool fused = pq_part != nullptr;
+    int g = vec_blocks(n);
+    if (fused && g > kFusedParts) g = kFusedParts;
+    double* out = fused ? rr_part : R.part;
     if (g32)
         hipLaunchKernelGGL(k_cg_update<float>, dim3(g), dim3(BS), 0, s, n, x, r, p, q, dinv,
-                           static_cast<float*>(gout), R.part, R.S, slot_rho, slot_pq);
+                           static_cast<float*>(gout), out, R.S, slot_rho, slot_pq, pq_part, pq_np);
     else
         hipLaunchKernelGGL(k_cg_update<double>, dim3(g), dim3(BS), 0, s, n, x, r, p, q, dinv,
-                           static_cast<double*>(gout), R.part, R.S, slot_rho, slot_pq);
-    finish(g, 1, R, slot_rr, slot_rr, s);
+                           static_cast<double*>(gout), out, R.S, slot_rho, slot_pq, pq_part, pq_np);
+    if (fused) *rr_np = g;
+    else finish(g, 1, R, slot_rr, slot_rr, s);
 }
 
-// p_new = z + beta p, beta = rho_new / rho
+// p_new = z + beta p, beta = rho_new / rho.  new_part: rho_new = (r, z) is
+// added here from the level-0 postsmoothing's partials (every block the same
+// sum; block 0 stores it in slot_new).  rr_part: block 0 adds the update's
+// (r, r) partials into slot_rr.  With Sh (host memory mapped into the device),
+// block 0 then copies the first nsh scalar slots there: the iteration's last
+// kernel hands its scalars to the host without a copy.
 __global__ __launch_bounds__(BS) void k_cg_dir(int n, const double* __restrict__ z, const double* __restrict__ p,
-                                               double* __restrict__ pn, const double* __restrict__ S, int slot_new,
-                                               int slot_old) {
-    const double beta = S[slot_new] / S[slot_old];
+                                               double* __restrict__ pn, double* __restrict__ S, int slot_new,
+                                               int slot_old, double* Sh, int nsh, const double* __restrict__ new_part,
+                                               int new_np, const double* __restrict__ rr_part, int rr_np,
+                                               int slot_rr) {
+    const double rho_new = new_part ? block_sum_partials<BS>(new_part, new_np) : S[slot_new];
+    if (blockIdx.x == 0 && (new_part || rr_part)) {
+        const double rr = rr_part ? block_sum_partials<BS>(rr_part, rr_np) : 0.0;
+        if (threadIdx.x == 0) {
+            if (new_part) S[slot_new] = rho_new;
+            if (rr_part) S[slot_rr] = rr;
+        }
+        __syncthreads();  // the slots just stored, for the copy below
+    }
+    const double beta = rho_new / S[slot_old];
     for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) pn[i] = z[i] + beta * p[i];
+    if (Sh && blockIdx.x == 0 && (int)threadIdx.x < nsh) Sh[threadIdx.x] = S[threadIdx.x];
 }
 
-void launch_cg_dir(int n, const double* z, const double* p, double* pn, const double* S, int slot_new, int slot_old,
-                   hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_dir, dim3(vec_blocks(n)), dim3(BS), 0, s, n, z, p, pn, S, slot_new, slot_old);
+void launch_cg_dir(int n, const double* z, const double* p, double* pn, double* S, int slot_new, int slot_old,
+                   hipStream_t s, double* Sh, int nsh, const double* new_part, int new_np, const double* rr_part,
+                   int rr_np, int slot_rr) {
+    hipLaunchKernelGGL(k_cg_dir, dim3(vec_blocks(n)), dim3(BS), 0, s, n, z, p, pn, S, slot_new, slot_old, Sh, nsh,
+                       new_part, new_np, rr_part, rr_np, slot_rr);
 }
 
 // Algorithm 5: s = r - alpha v, alpha = rho / (rbar, v)

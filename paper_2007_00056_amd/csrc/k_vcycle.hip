@@ -157,17 +157,19 @@ void post_launch(int gsz, hipStream_t s, hipEvent_t t0, hipEvent_t t1, int n, co
 }
 
 template <class T, class TOUT, int MODE, bool GF>
-void post_rb(int rb, int n, hipStream_t s, hipEvent_t t0, hipEvent_t t1, const int* rp, const EntAx<T>& ent,
-             const T* g, const T* dinv, T w, TOUT* z, const double* f, double* part, const ScatterT<T>& sc) {
-    const int gsz = rb_blocks(n, rb);
+int post_rb(int rb, int n, hipStream_t s, hipEvent_t t0, hipEvent_t t1, const int* rp, const EntAx<T>& ent,
+            const T* g, const T* dinv, T w, TOUT* z, const double* f, double* part, const ScatterT<T>& sc,
+            int cap = kRedBlocks) {
+    const int gsz = rb_blocks(n, rb) < cap ? rb_blocks(n, rb) : cap;
     if (rb == 128) post_launch<T, TOUT, MODE, 128, GF>(gsz, s, t0, t1, n, rp, ent, g, dinv, w, z, f, part, sc);
     else if (rb == 512) post_launch<T, TOUT, MODE, 512, GF>(gsz, s, t0, t1, n, rp, ent, g, dinv, w, z, f, part, sc);
     else post_launch<T, TOUT, MODE, 256, GF>(gsz, s, t0, t1, n, rp, ent, g, dinv, w, z, f, part, sc);
+    return gsz;
 }
 
 template <class T, class TOUT>
-void vc_stream_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, const double* f, const Reducer* R,
-                    int slot, const ScatterT<T>* sc, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+int vc_stream_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, const double* f, const Reducer* R,
+                   int slot, const ScatterT<T>* sc, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     const int rb = L.rb == 128 || L.rb == 512 ? L.rb : 256;
     const EntAx<T> ent{L.v, L.ci, xp};
     const ScatterT<T> none{nullptr, nullptr, nullptr, T(0)};
@@ -175,9 +177,12 @@ void vc_stream_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, c
     constexpr bool kCanGF = std::is_same<T, double>::value && std::is_same<TOUT, double>::value;
     const bool gf = kCanGF && f != nullptr;
     if (R) {
-        if (gf) post_rb<T, TOUT, 1, kCanGF>(rb, L.n, s, t0, t1, L.rp, ent, g, L.dinv, w, z, f, R->part, none);
-        else post_rb<T, TOUT, 1, false>(rb, L.n, s, t0, t1, L.rp, ent, g, L.dinv, w, z, f, R->part, none);
-        launch_finish(rb_blocks(L.n, rb), 1, *R, slot, slot, s);
+        const int cap = slot == kPartialsOnly ? kFusedParts : kRedBlocks;
+        const int np =
+            gf ? post_rb<T, TOUT, 1, kCanGF>(rb, L.n, s, t0, t1, L.rp, ent, g, L.dinv, w, z, f, R->part, none, cap)
+               : post_rb<T, TOUT, 1, false>(rb, L.n, s, t0, t1, L.rp, ent, g, L.dinv, w, z, f, R->part, none, cap);
+        if (slot == kPartialsOnly) return np;
+        launch_finish(np, 1, *R, slot, slot, s);
     } else if (sc) {
         post_rb<T, TOUT, 2, false>(rb, L.n, s, t0, t1, L.rp, ent, g, L.dinv, w, z, nullptr, nullptr, *sc);
     } else if (gf) {
@@ -185,6 +190,7 @@ void vc_stream_post(const VLevel<T>& L, const T* xp, const T* g, T w, TOUT* z, c
     } else {
         post_rb<T, TOUT, 0, false>(rb, L.n, s, t0, t1, L.rp, ent, g, L.dinv, w, z, nullptr, nullptr, none);
     }
+    return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -358,8 +364,8 @@ void launch_cast_f32(int64_t n, const double* a, float* b, hipStream_t s) {
 #define AMG_INST(T)                                                                                                 \
     template void vc_stream_resid<T, T>(const VLevel<T>&, const T*, const T*, T, T*, hipStream_t);                   \
     template void vc_restrict<T>(int, const int4*, const T*, const T*, T*, T*, hipStream_t);                         \
-    template void vc_stream_post<T, T>(const VLevel<T>&, const T*, const T*, T, T*, const double*, const Reducer*,  \
-                                       int, const ScatterT<T>*, hipStream_t, hipEvent_t, hipEvent_t);                \
+    template int vc_stream_post<T, T>(const VLevel<T>&, const T*, const T*, T, T*, const double*, const Reducer*,   \
+                                      int, const ScatterT<T>*, hipStream_t, hipEvent_t, hipEvent_t);                 \
     template void vc_resid_restrict<T, T>(const VLevel<T>&, int, const T*, const T*, T, const T*, T*, T*,            \
                                           hipStream_t);                                                               \
     template void vc_prolong_post<T, T>(const VLevel<T>&, const T*, const T*, T, T*, const ScatterT<T>*,            \
@@ -371,7 +377,7 @@ AMG_INST(float)
 #undef AMG_INST
 template void vc_stream_resid<float, double>(const VLevel<float>&, const double*, const float*, float, float*,
                                              hipStream_t);
-template void vc_stream_post<float, double>(const VLevel<float>&, const float*, const float*, float, double*,
+template int vc_stream_post<float, double>(const VLevel<float>&, const float*, const float*, float, double*,
                                             const double*, const Reducer*, int, const ScatterT<float>*, hipStream_t,
                                             hipEvent_t, hipEvent_t);
 template void vc_resid_restrict<float, double>(const VLevel<float>&, int, const double*, const float*, float,

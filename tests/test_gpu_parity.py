@@ -282,9 +282,16 @@ def test_alternating_direction_at_128(torch):
 
 def test_edge_based_matching_stall_reported_like_oracle(torch):
     """On a strongly heterogeneous field the edge-ordered matching leaves many
-    vertices whose neighbours are all taken, coarsening stalls above the dense
-    limit, and setup reports the stall on both sides."""
+    vertices whose neighbours are all taken and coarsening stalls.  At 64^3 it
+    stalls at 2367 rows, which both sides take as a dense coarsest level; at
+    80^3 above the 4096-row dense limit, and setup reports the stall on both
+    sides."""
     a = P.lognormal_diffusion3d(64, 7, 2.0)
+    g, o = both(a, hem=1)
+    assert_same_hierarchy(g, o)
+    assert g.level(g.nlevels - 1)[0].size - 1 == 2367
+    g.close()
+    a = P.lognormal_diffusion3d(80, 7, 2.0)
     with pytest.raises(oracle.OracleError) as eo:
         oracle.Hierarchy(a, hem=1)
     assert eo.value.status == oracle.ESTALL
