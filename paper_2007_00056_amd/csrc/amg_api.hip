@@ -229,6 +229,8 @@ struct SetupWork {
         if (const char* e = getenv("HEMAMG_TILE_STRICT")) tile_strict = atoi(e) != 0;
         if (const char* e = getenv("HEMAMG_HEM_TILE"))  // rows per tile; 0: no tiled passes
             hw.tile_rows = atoi(e) <= 0 ? 0 : (atoi(e) < kHemTileRows ? atoi(e) : kHemTileRows);
+        if (const char* e = getenv("HEMAMG_HEM_TILE_C"))  // rows per LDS-record tile; 0: not used
+            hw.tile_c_rows = atoi(e) <= 0 ? 0 : (atoi(e) < kHemTileCRows ? atoi(e) : kHemTileCRows);
     }
     ~SetupWork() {
         event_put(ev[0], false);
@@ -766,11 +768,14 @@ void pcg_iteration(amg_hier* h, const double* b, double* x, int pc, bool graphs,
         HIPCHK(hipGraphLaunch(h->g_full[pc], s));
         return;
     }
-    // timed: the level-0 postsmoothing runs between two graphs, bracketed by events
+    // timed: the level-0 postsmoothing runs between two graphs, bracketed by
+    // events.  The second graph is captured after the postsmoothing has been
+    // enqueued once: the direction kernel takes the number of (r, z) partials
+    // the postsmoothing leaves (h->rz_np), which that enqueue sets.
     if (!h->g_a[pc]) h->g_a[pc] = capture(s, [&] { pcg_iter_a(h, x, pc, s); });
-    if (!h->g_b[pc]) h->g_b[pc] = capture(s, [&] { pcg_iter_b(h, pc, s); });
     HIPCHK(hipGraphLaunch(h->g_a[pc], s));
     pcg_iter_p(h, pc, s);
+    if (!h->g_b[pc]) h->g_b[pc] = capture(s, [&] { pcg_iter_b(h, pc, s); });
     HIPCHK(hipGraphLaunch(h->g_b[pc], s));
 }
 
@@ -1662,6 +1667,7 @@ amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x,
                         void* stream, amg_info* info) {
     return amg::krylov_run(h, method, b, x, rtol, maxit, stream, info, nullptr);
 }
+
 
 amg_status amg_num_levels(const amg_hier* h, int32_t* levels) {
     return guarded([&] {

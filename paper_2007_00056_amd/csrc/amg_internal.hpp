@@ -40,6 +40,7 @@ constexpr int kRecLoTrunc = 1 << 18;
 constexpr int kHemLdsRows = 32768;  // passes up to this size keep their matching state in LDS
 constexpr int kHemTileRows = 32768;  // largest tile of a tiled pass (its state in LDS)
 constexpr int kHemMaxTiles = 4096;   // tiled passes up to this many tiles
+constexpr int kHemTileCRows = 4096;  // largest tile whose records are kept in LDS
 template <int SIDE>
 struct alignas(4 * (SIDE + 1) * 2) HemRecT {
     int hdr;  // #higher | #lower << 8 | kRecOverflow | kRecHiTrunc | kRecLoTrunc
@@ -62,6 +63,7 @@ struct HemWork {
     int* err;
     int round_grid = 96;  // blocks of a one-launch-per-round pass
     int tile_rows = kHemTileRows;  // rows per tile of a tiled pass (0: no tiled passes)
+    int tile_c_rows = kHemTileCRows;  // rows per tile when the records have side 7 and sit in LDS (0: not used)
     int lds_rows = kHemLdsRows;  // one-workgroup passes up to this size keep their state in LDS
     double* wsym = nullptr;  // edge-based matching: [nnz] heavier of |a_uv|, |a_vu| (0 on the diagonal)
     int* ptr = nullptr;      // edge-based matching: [n] best undecided neighbour

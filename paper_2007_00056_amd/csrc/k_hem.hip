@@ -673,8 +673,11 @@ __device__ __forceinline__ int hem_lds_body(int off, int n, const HemState& S, c
         const uint16_t* c = cur;
         const int* g = gin;
         const int klc = kl;
+        // the round's first items go to wave r mod (waves), as in the tiled passes
+        constexpr int NW = hem_nt<SIDE>() / kWave;
+        const int first = (int)((threadIdx.x + (unsigned)(NW - r % NW) * kWave) % hem_nt<SIDE>());
         hem_round_body<LdsSt, SIDE, hem_nt<SIDE>()>(
-            S, st, r, m, threadIdx.x, hem_nt<SIDE>(), [&](int i) { return i < klc ? (int)c[i] + off : g[i - klc]; }, A,
+            S, st, r, m, first, hem_nt<SIDE>(), [&](int i) { return i < klc ? (int)c[i] + off : g[i - klc]; }, A,
             s_wave, &s_nw, HL_WCAP);
         kl = min(s_cnt, HL_LCAP);
         kg = s_gnext;
@@ -998,6 +1001,323 @@ __device__ __forceinline__ void tile_visit(const HemState& S, const TileSt& st, 
     atomicAdd(s_ndec, 1);
     tile_release<SIDE>(S, st, R, u, A);
 }
+
+// ---------------------------------------------------------------------------
+// Small tiles with their adjacency records in LDS.  A tile of up to
+// kTileCRows rows keeps, besides its stamps and counters, a compact copy of
+// each of its vertices' records: up to kCSide higher and kCSide lower
+// neighbours as 16-bit offsets from the vertex.  A vertex whose record does
+// not fit (longer lists, truncated lists, offsets beyond 16 bits) is marked
+// and read from the global record instead.  A visit then reads global memory
+// only for what lies outside the tile: the published words of out-of-tile
+// neighbours, and only those the decision needs.
+//  * The choice of u scans its preference list; an out-of-tile entry's word
+//    is read only when it precedes the first undecided in-tile entry.
+//  * The target's lower edge-neighbours in lower tiles are read only while
+//    the target is pending: a target of this tile that is no longer pending
+//    was settled free, so those neighbours are decided and none took it.
+// The rules between tiles are those of the tiled pass above.
+// ---------------------------------------------------------------------------
+constexpr int kTileCRows = kHemTileCRows;  // largest tile of the compact-record driver
+constexpr int kCSide = 4;         // entries a side of a compact record
+constexpr int kCGlobal = 0x80;    // compact header flag: use the global record
+constexpr int kCompactMaxTiles = 512;  // compact tiles only for passes of at most this many
+
+struct CRecs {
+    const uint8_t* hdr;  // per tile vertex: #higher | #lower << 3 | kCGlobal
+    const int16_t* h;    // h[t * kTileCRows + i]: offset of the t-th higher neighbour of vertex off+i
+    const int16_t* l;    // lower edge-neighbours, the same layout
+    const HemRecT<7>* g;
+    int off, m;
+    // record of v: from LDS when v is a tile vertex with a compact record
+    __device__ __forceinline__ void load(int v, HemRecT<7>& R) const {
+        const int i = v - off;
+        const int hd = (unsigned)i < (unsigned)m ? hdr[i] : kCGlobal;
+        if (hd & kCGlobal) {
+            R = g[v];
+            return;
+        }
+        const int nh = hd & 7, nl = (hd >> 3) & 7;
+        R.hdr = nh | (nl << 8);
+#pragma unroll
+        for (int t = 0; t < 7; ++t) {
+            R.h[t] = t < kCSide && t < nh ? v + h[t * kTileCRows + i] : -1;
+            R.l[t] = t < kCSide && t < nl ? v + l[t * kTileCRows + i] : -1;
+        }
+        R.pad = 0;
+    }
+};
+
+// Smallest undecided lower edge-neighbour of w (stamp view of round r), or -1,
+// as tile_back; settled: w is a tile vertex that is not pending, so its
+// lower-tile edge-neighbours are decided and none named it (not read).
+__device__ __forceinline__ int tile_back_c(const HemState& S, const TileSt& st, const HemRecT<7>& B, int w, int r,
+                                           bool settled, bool& named) {
+    if (!settled) return tile_back<7>(S, st, B, w, r, named);
+    named = false;
+    const int nl = (B.hdr >> 8) & 255;
+    int back = -1;
+#pragma unroll
+    for (int t = 6; t >= 0; --t) {
+        if (t < nl) {
+            const int x = B.l[t];
+            if (st.mine(x) && st.sdec[x - st.off] >= r) back = x;
+        }
+    }
+    if (back >= 0 || !(B.hdr & kRecLoTrunc)) return back;
+    for (int e = S.rp[w]; e < S.rp[w + 1]; ++e) {  // every listed one decided
+        const int x = S.ci[e];
+        if (x >= w) break;
+        if (x < st.off || !S.lowok[e]) continue;
+        if (st.sdec[x - st.off] >= r) return x;
+    }
+    return -1;
+}
+
+// Round r for a ready vertex u of a compact tile: the visit of tile_visit
+// with records from LDS and the out-of-tile reads cut to what decides.
+template <class Ap>
+__device__ __forceinline__ void tile_visit_c(const HemState& S, const TileSt& st, const CRecs& C, int r, int u,
+                                             const Ap& A, int* s_ndec) {
+    HemRecT<7> R;
+    C.load(u, R);
+    const int su = st.sdec[u - st.off];
+    if (su < r) return;  // decided earlier (as a match target): stale entry
+    const int nh = R.hdr & 255;
+    const int b0 = nh > 0 ? R.h[0] : -1;
+    HemRecT<7> B;
+    if (b0 >= 0) C.load(b0, B);  // the first preference, loaded with the states it is chosen by
+    if (su == kTilePend) {
+        bool open, taken;
+        cross_lower<7>(S, st, R, u, open, taken);
+        if (open) {
+            A.push(u);
+            return;
+        }
+        if (tile_settle<7>(S, st, R, u, r, taken, A, s_ndec) != kFree) return;
+    }
+    int best = -1;
+    {
+        int fin = 7;  // first undecided tile entry in preference order
+#pragma unroll
+        for (int t = 6; t >= 0; --t)
+            if (t < nh && st.mine(R.h[t]) && st.sdec[R.h[t] - st.off] >= r) fin = t;
+        bool und[7];
+#pragma unroll
+        for (int t = 0; t < 7; ++t) {
+            und[t] = false;
+            if (t < nh && t < fin && !st.mine(R.h[t])) und[t] = st.word(R.h[t]) == kUndecided;
+        }
+#pragma unroll
+        for (int t = 6; t >= 0; --t)
+            if (t < nh && (t == fin || und[t])) best = R.h[t];
+    }
+    if (best < 0 && (R.hdr & kRecHiTrunc))  // every listed choice decided: the row decides
+        best = hem_best(S, st, r, u, S.rp[u], S.rp[u + 1]);
+    if (best < 0) {  // no undecided neighbour: unaggregated singleton
+        st.sdec[u - st.off] = (uint16_t)r;
+        S.mate[u] = -1;
+        st.publish(u, -1);
+        atomicAdd(s_ndec, 1);
+        tile_release<7>(S, st, R, u, A);
+        return;
+    }
+    if (best != b0) C.load(best, B);
+    const bool settled = st.mine(best) && st.sdec[best - st.off] != kTilePend;
+    bool named;
+    const int back = tile_back_c(S, st, B, best, r, settled, named);
+    if (back != u) {
+        A.push(u);  // still ready, retry next round
+        return;
+    }
+    if (st.mine(best)) {
+        if (!settled && tile_settle<7>(S, st, B, best, r, named, A, s_ndec) != kFree) {
+            A.push(u);
+            return;
+        }
+        st.sdec[u - st.off] = (uint16_t)r;
+        st.sdec[best - st.off] = (uint16_t)r;
+        S.mate[u] = best;
+        S.mate[best] = u;
+        st.publish(best, u);
+        st.publish(u, best);
+        atomicAdd(s_ndec, 2);
+        tile_release<7>(S, st, R, u, A);
+        tile_release<7>(S, st, B, best, A);
+        return;
+    }
+    if (named) {  // taken from a lower tile
+        A.push(u);
+        return;
+    }
+    st.sdec[u - st.off] = (uint16_t)r;
+    S.mate[u] = best;
+    S.mate[best] = u;
+    st.publish(best, u);
+    st.publish(u, best);
+    __builtin_amdgcn_s_waitcnt(0);  // stores complete before the round ends
+    atomicAdd(s_ndec, 1);
+    tile_release<7>(S, st, R, u, A);
+}
+
+// Releases of a compact vertex: its in-tile higher neighbours h[0..nh) lose
+// an undecided lower neighbour; those that reach zero are ready.
+template <class Ap>
+__device__ __forceinline__ void lean_release(const TileSt& st, const int* h, int nh, const Ap& A) {
+    int old[kCSide];
+#pragma unroll
+    for (int t = 0; t < kCSide; ++t) old[t] = t < nh && st.mine(h[t]) ? st.drop(h[t]) : 0;
+#pragma unroll
+    for (int t = 0; t < kCSide; ++t)
+        if (t < nh && old[t] == 1) A.push(h[t]);
+}
+
+// The visit of tile_visit_c for a vertex u with a compact record, written on
+// the compact lists themselves (at most kCSide entries a side, no 7-entry
+// record built); a target without a compact record (outside the tile, or
+// with longer lists) hands the visit to tile_visit_c, before any change.
+template <class Ap>
+__device__ __forceinline__ void tile_visit_lean(const HemState& S, const TileSt& st, const CRecs& C, int r, int u,
+                                                const Ap& A, int* s_ndec) {
+    const int off = st.off;
+    const int i = u - off;
+    const int hd = C.hdr[i];
+    const int su = st.sdec[i];
+    if (hd & kCGlobal) {
+        tile_visit_c(S, st, C, r, u, A, s_ndec);
+        return;
+    }
+    if (su < r) return;  // decided earlier (as a match target): stale entry
+    const int nh = hd & 7, nl = (hd >> 3) & 7;
+    int h[kCSide], l[kCSide];
+#pragma unroll
+    for (int t = 0; t < kCSide; ++t) {
+        h[t] = u + C.h[t * kTileCRows + i];
+        l[t] = u + C.l[t * kTileCRows + i];
+    }
+    if (su == kTilePend) {  // lower-tile edge-neighbours: all decided, and did one take u?
+        int wx[kCSide];
+#pragma unroll
+        for (int t = 0; t < kCSide; ++t) wx[t] = t < nl && l[t] < off ? st.word(l[t]) : 0;
+        bool open = false, taken = false;
+#pragma unroll
+        for (int t = 0; t < kCSide; ++t) {
+            open |= wx[t] == kUndecided;
+            taken |= wx[t] == u + 2;
+        }
+        if (open) {
+            A.push(u);
+            return;
+        }
+        const int old = cas_stamp(st.sdec, i, kTilePend, taken ? r - 1 : kTileUnd);
+        if (old == kTilePend) {
+            if (taken) {
+                atomicAdd(s_ndec, 1);
+                lean_release(st, h, nh, A);
+                return;
+            }
+        } else if (old != kTileUnd) {
+            return;
+        }
+    }
+    // the choice: first undecided entry in preference order; out-of-tile
+    // words only for entries before the first undecided tile entry
+    int fin = kCSide;
+    bool inb[kCSide];
+#pragma unroll
+    for (int t = kCSide - 1; t >= 0; --t) {
+        inb[t] = st.mine(h[t]);
+        if (t < nh && inb[t] && st.sdec[h[t] - off] >= r) fin = t;
+    }
+    int best = -1;
+    {
+        bool und[kCSide];
+#pragma unroll
+        for (int t = 0; t < kCSide; ++t) und[t] = t < nh && t < fin && !inb[t] && st.word(h[t]) == kUndecided;
+#pragma unroll
+        for (int t = kCSide - 1; t >= 0; --t)
+            if (t < nh && (t == fin || und[t])) best = h[t];
+    }
+    if (best < 0) {  // no undecided neighbour: unaggregated singleton
+        st.sdec[i] = (uint16_t)r;
+        S.mate[u] = -1;
+        st.publish(u, -1);
+        atomicAdd(s_ndec, 1);
+        lean_release(st, h, nh, A);
+        return;
+    }
+    const int j = best - off;
+    const int hdb = st.mine(best) ? C.hdr[j] : kCGlobal;
+    if (hdb & kCGlobal) {  // a target outside the tile or without a compact record
+        tile_visit_c(S, st, C, r, u, A, s_ndec);
+        return;
+    }
+    const bool settled = st.sdec[j] != kTilePend;
+    const int nhb = hdb & 7, nlb = (hdb >> 3) & 7;
+    int hb[kCSide], lb[kCSide];
+#pragma unroll
+    for (int t = 0; t < kCSide; ++t) {
+        hb[t] = best + C.h[t * kTileCRows + j];
+        lb[t] = best + C.l[t * kTileCRows + j];
+    }
+    // back: the target's smallest undecided lower edge-neighbour; named: one
+    // of its lower-tile neighbours below back took it (read only while the
+    // target is pending)
+    int back = -1;
+    bool named = false;
+    {
+        int d[kCSide];
+        bool nm[kCSide];
+#pragma unroll
+        for (int t = 0; t < kCSide; ++t) {
+            d[t] = -1;
+            nm[t] = false;
+            if (t < nlb) {
+                const int x = lb[t];
+                if (x >= off) {
+                    d[t] = st.sdec[x - off];
+                } else if (!settled) {
+                    const int wx = st.word(x);
+                    d[t] = wx == kUndecided ? INT_MAX : -1;
+                    nm[t] = wx == best + 2;
+                }
+            }
+        }
+#pragma unroll
+        for (int t = kCSide - 1; t >= 0; --t)
+            if (t < nlb && d[t] >= r) back = lb[t];
+#pragma unroll
+        for (int t = 0; t < kCSide; ++t)
+            if (t < nlb && nm[t] && (back < 0 || lb[t] < back)) named = true;
+    }
+    if (back != u) {
+        A.push(u);  // still ready, retry next round
+        return;
+    }
+    if (!settled) {  // a pending target: settle it (free, or taken from a lower tile)
+        const int old = cas_stamp(st.sdec, j, kTilePend, named ? r - 1 : kTileUnd);
+        if (old == kTilePend) {
+            if (named) {
+                atomicAdd(s_ndec, 1);
+                lean_release(st, hb, nhb, A);
+                A.push(u);
+                return;
+            }
+        } else if (old != kTileUnd) {
+            A.push(u);
+            return;
+        }
+    }
+    st.sdec[i] = (uint16_t)r;
+    st.sdec[j] = (uint16_t)r;
+    S.mate[u] = best;
+    S.mate[best] = u;
+    st.publish(best, u);
+    st.publish(u, best);
+    atomicAdd(s_ndec, 2);
+    lean_release(st, h, nh, A);
+    lean_release(st, hb, nhb, A);
+}
 }  // namespace
 
 // Per vertex: the LDS ready counter (lcnt: undecided lower edge-neighbours in
@@ -1021,14 +1341,20 @@ __global__ __launch_bounds__(BS) void k_hem_tile_prep(int n, int T, const int* _
 }
 
 // One workgroup per tile.  gl0/gl1: global list space (the tile's rows of
-// each); tmo: time limit in wall-clock ticks.
-template <int SIDE>
+// each); tmo: time limit in wall-clock ticks.  COMPACT: tiles of at most
+// kTileCRows rows with their records in LDS (SIDE 7).
+template <int SIDE, bool COMPACT>
 __global__ __launch_bounds__(hem_nt<SIDE>()) void k_hem_tile(int n, int T, HemState S, int* dec_g,
                                                       const int* __restrict__ lcnt_g, int* gl0, int* gl1, int* cnt,
                                                       long long tmo) {
-    __shared__ uint16_t s_dec[kHemTileRows];
-    __shared__ unsigned s_lcnt2[kHemTileRows / 2];
+    static_assert(!COMPACT || SIDE == 7, "compact records hold 7-entry records");
+    constexpr int TR = COMPACT ? kTileCRows : kHemTileRows;
+    constexpr int CR = COMPACT ? kTileCRows : 1;
+    __shared__ uint16_t s_dec[TR];
+    __shared__ unsigned s_lcnt2[TR / 2];
     __shared__ uint16_t s_la[TL_LCAP], s_lb[TL_LCAP];
+    __shared__ uint8_t c_hdr[CR];
+    __shared__ int16_t c_h[kCSide * CR], c_l[kCSide * CR];
     __shared__ int s_cnt, s_gnext, s_ndec, s_stop;
     const long long t_start = wall_clock64();
     if (cnt[7] & 2) return;  // a counter beyond 16 bits: the host repeats the pass with rounds
@@ -1055,8 +1381,32 @@ __global__ __launch_bounds__(hem_nt<SIDE>()) void k_hem_tile(int n, int T, HemSt
         s_lcnt2[i] = lo | (hi << 16);
     }
     if (pre) atomicAdd(&s_ndec, pre);
+    if (COMPACT) {  // compact copies of the tile's records
+        const HemRecT<7>* __restrict__ g = static_cast<const HemRecT<7>*>(S.rec);
+        for (int i = threadIdx.x; i < m; i += hem_nt<SIDE>()) {
+            const int v = off + i;
+            const HemRecT<7> R = g[v];
+            const int nh = R.hdr & 255, nl = (R.hdr >> 8) & 255;
+            bool fit = !(R.hdr & kRecOverflow) && nh <= kCSide && nl <= kCSide;
+            int16_t dh[kCSide], dl[kCSide];
+#pragma unroll
+            for (int t = 0; t < kCSide; ++t) {
+                const int a = t < nh ? R.h[t] - v : 0, b = t < nl ? R.l[t] - v : 0;
+                fit = fit && a >= -32768 && a <= 32767 && b >= -32768 && b <= 32767;
+                dh[t] = (int16_t)a;
+                dl[t] = (int16_t)b;
+            }
+#pragma unroll
+            for (int t = 0; t < kCSide; ++t) {
+                c_h[t * CR + i] = dh[t];
+                c_l[t * CR + i] = dl[t];
+            }
+            c_hdr[i] = (uint8_t)(fit ? nh | (nl << 3) : kCGlobal);
+        }
+    }
     __syncthreads();
     const TileSt st{s_dec, s_lcnt2, off, m, dec_g};
+    const CRecs C{c_hdr, c_h, c_l, static_cast<const HemRecT<7>*>(S.rec), off, COMPACT ? m : 0};
     int* gin = gl0 + off;
     int* gout = gl1 + off;
     uint16_t* cur = s_la;
@@ -1081,9 +1431,16 @@ __global__ __launch_bounds__(hem_nt<SIDE>()) void k_hem_tile(int n, int T, HemSt
         __syncthreads();
         const Appender<uint16_t> A{nxt, &s_cnt, TL_LCAP, gout, &s_gnext, off};
         const int klc = kl;
-        for (int idx = threadIdx.x; idx < kl + kg; idx += hem_nt<SIDE>()) {
+        // compact tiles: the round's first items go to wave r mod (waves), so
+        // the wave that visited in the previous round, whose stores may still
+        // be in flight, does not wait for them at its first memory access
+        constexpr int NW = hem_nt<SIDE>() / kWave;
+        const int first = COMPACT ? (int)((threadIdx.x + (unsigned)(NW - r % NW) * kWave) % hem_nt<SIDE>())
+                                  : (int)threadIdx.x;
+        for (int idx = first; idx < kl + kg; idx += hem_nt<SIDE>()) {
             const int u = idx < klc ? (int)cur[idx] + off : gin[idx - klc];
-            tile_visit<SIDE>(S, st, r, u, A, &s_ndec);
+            if (COMPACT) tile_visit_lean(S, st, C, r, u, A, &s_ndec);
+            else tile_visit<SIDE>(S, st, r, u, A, &s_ndec);
         }
         if (threadIdx.x == 0 && (r & 31) == 0 && (wall_clock64() - t_start > tmo || r >= kTileMaxRound))
             s_stop = 1;
@@ -1325,15 +1682,22 @@ void launch_seg_table(int m, const int* off, const int* agg, int n, bool mirror,
 
 void launch_hem_tile(int n, const int* rp, const int* ci, const double* v, HemWork& w, long long tmo,
                      hipStream_t s) {
-    const int T = w.tile_rows;
+    // records of side 7 go to small tiles with LDS copies of the records when
+    // those tiles can all be resident at once (one workgroup per compute unit):
+    // a tile that is not resident waits for a lower one to finish, and on long
+    // dependency chains the larger tiles are faster
+    const int Tc = w.tile_c_rows < kTileCRows ? w.tile_c_rows : kTileCRows;
+    const bool compact = w.side == 7 && Tc > 0 && ((int64_t)n + Tc - 1) / Tc <= kCompactMaxTiles;
+    const int T = compact ? Tc : w.tile_rows;
     const int nt = (n + T - 1) / T;
     hipLaunchKernelGGL(k_hem_tile_prep, dim3(blocks_for(n)), dim3(BS), 0, s, n, T, rp, ci, w.lowok, w.lcnt, w.cnt);
     const HemState S{rp, ci, v, w.lowok, w.rec, w.mate};
-#define CALL(SD)                                                                                               \
-    hipLaunchKernelGGL(k_hem_tile<SD>, dim3(nt), dim3(hem_nt<SD>()), 0, s, n, T, S, w.dec, w.lcnt, w.wl[0], w.wl[1], \
-                       w.cnt, tmo)
-    if (w.side == 7) CALL(7);
-    else CALL(15);  // records of tiled passes hold at most 15 entries a side
+#define CALL(SD, CP)                                                                                              \
+    hipLaunchKernelGGL((k_hem_tile<SD, CP>), dim3(nt), dim3(hem_nt<SD>()), 0, s, n, T, S, w.dec, w.lcnt, w.wl[0], \
+                       w.wl[1], w.cnt, tmo)
+    if (compact) CALL(7, true);
+    else if (w.side == 7) CALL(7, false);
+    else CALL(15, false);  // records of tiled passes hold at most 15 entries a side
 #undef CALL
 }
 

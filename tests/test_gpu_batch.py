@@ -408,16 +408,18 @@ def test_batched_setup_at_served_sizes(torch):
         bt.close()
 
 
+@pytest.mark.parametrize("compact", [0, 1])
 @pytest.mark.parametrize("alternate", [0, 1])
-def test_batched_setup_tiles_across_systems(torch, alternate, monkeypatch):
+def test_batched_setup_tiles_across_systems(torch, alternate, compact, monkeypatch):
     """Tiled matching inside a batched setup: with the per-system LDS limit at
     200 rows and tiles of 37 rows, the small systems are matched one
     workgroup each and marked decided, and the others by tiles that straddle
     system boundaries and those decided rows.  The batch must equal the
     hierarchies set up one by one (which use the same drivers alone)."""
-    say("alternate", alternate)
+    say("alternate", alternate, "compact", compact)
     monkeypatch.setenv("HEMAMG_HEM_LDS", "200")
     monkeypatch.setenv("HEMAMG_HEM_TILE", "37")
+    monkeypatch.setenv("HEMAMG_HEM_TILE_C", "37" if compact else "0")
     monkeypatch.setenv("HEMAMG_TILE_STRICT", "1")
     systems = mix()
     seeds = list(range(len(systems)))

@@ -95,9 +95,15 @@ DRIVERS = {
     "launch_per_round_small_grid": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_GRID": "3", "HEMAMG_HEM_TILE": "0"},
     # tiled passes with tiles far smaller than the systems: many cross-tile
     # edges, messages and takes; 37 rows leave a ragged last tile
-    "tiles_64": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_TILE": "64", "HEMAMG_TILE_STRICT": "1"},
-    "tiles_37": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_TILE": "37", "HEMAMG_TILE_STRICT": "1"},
-    "tiles_1": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_TILE": "1", "HEMAMG_TILE_STRICT": "1"},
+    "tiles_64": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_TILE": "64", "HEMAMG_HEM_TILE_C": "0", "HEMAMG_TILE_STRICT": "1"},
+    "tiles_37": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_TILE": "37", "HEMAMG_HEM_TILE_C": "0", "HEMAMG_TILE_STRICT": "1"},
+    "tiles_1": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_TILE": "1", "HEMAMG_HEM_TILE_C": "0", "HEMAMG_TILE_STRICT": "1"},
+    # tiles with LDS copies of the records (passes whose records have 7
+    # entries a side; longer rows still take the tiles above)
+    "ctiles_64": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_TILE_C": "64", "HEMAMG_TILE_STRICT": "1"},
+    "ctiles_37": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_TILE_C": "37", "HEMAMG_TILE_STRICT": "1"},
+    "ctiles_1": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_HEM_TILE_C": "1", "HEMAMG_TILE_STRICT": "1"},
+    "ctiles_4096": {"HEMAMG_HEM_SMALL": "0", "HEMAMG_TILE_STRICT": "1"},
 }
 
 

@@ -30,7 +30,11 @@ UND = 1 << 30      # published word before a decision; LDS stamp "undecided"
 PEND = UND - 1     # LDS stamp: pending
 
 
-def tiled_model(a, T, rng, delay=3, speed=0.7, defer=0.2):
+def tiled_model(a, T, rng, delay=3, speed=0.7, defer=0.2, lazy=False):
+    """lazy: the reads of the LDS-record tiles: a choice reads out-of-tile
+    words only for entries before its first undecided in-tile entry, and a
+    target of the tile that is no longer pending has its lower-tile
+    neighbours taken as decided without reading their words."""
     n, rp, ci, v = a.n, a.row_ptr, a.col, a.val
 
     def has_edge(u, w):  # u < w: entry (u, w) stored in row u and non-zero
@@ -120,7 +124,13 @@ def tiled_model(a, T, rng, delay=3, speed=0.7, defer=0.2):
                         continue
                     if settle(u, u + 2 in ws) != "free":
                         continue
-                best = next((j for j in higher[u] if get(j) >= r), -1)
+                if lazy:
+                    fin = next((k for k, j in enumerate(higher[u]) if lo <= j < hi and stamp[j] >= r),
+                               len(higher[u]))
+                    best = next((j for k, j in enumerate(higher[u])
+                                 if (k == fin) or (k < fin and not lo <= j < hi and get(j) >= r)), -1)
+                else:
+                    best = next((j for j in higher[u] if get(j) >= r), -1)
                 if best < 0:
                     stamp[u] = r
                     mate[u] = -1
@@ -129,7 +139,10 @@ def tiled_model(a, T, rng, delay=3, speed=0.7, defer=0.2):
                     release(u)
                     continue
                 back, named = -1, False
+                settled = lazy and lo <= best < hi and stamp[best] != PEND
                 for x in lower[best]:
+                    if settled and x < lo:
+                        continue
                     if lo <= x < hi:
                         if stamp[x] >= r:
                             back = x
@@ -179,8 +192,9 @@ def test_tiles_equal_sequential_random(seed):
                                    nonsym_values=seed % 2 == 1, explicit_zeros=0.15 * (seed % 4 == 0))
     want = oracle.hem_pass(a)
     for T in (1, 3, int(rng.integers(2, n + 1)), n):
-        got = tiled_model(a, T, rng, delay=int(rng.integers(0, 6)))
-        np.testing.assert_array_equal(got, want, err_msg=f"n={n} T={T}")
+        for lazy in (False, True):
+            got = tiled_model(a, T, rng, delay=int(rng.integers(0, 6)), lazy=lazy)
+            np.testing.assert_array_equal(got, want, err_msg=f"n={n} T={T} lazy={lazy}")
 
 
 @pytest.mark.parametrize("make", [lambda: P.poisson3d(6, 5, 4), lambda: P.convdiff3d(5),
@@ -191,7 +205,9 @@ def test_tiles_equal_sequential_grids_all_levels(make):
     for _ in range(4):  # follow the passes down the hierarchy
         want = oracle.hem_pass(a)
         for T in (7, 30, max(1, a.n // 3)):
-            np.testing.assert_array_equal(tiled_model(a, T, rng), want, err_msg=f"n={a.n} T={T}")
+            for lazy in (False, True):
+                np.testing.assert_array_equal(tiled_model(a, T, rng, lazy=lazy), want,
+                                              err_msg=f"n={a.n} T={T} lazy={lazy}")
         agg, nc = oracle.number(want)
         if nc == a.n or nc < 2:
             break
