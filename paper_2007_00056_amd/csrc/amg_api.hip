@@ -292,7 +292,7 @@ bool tiled(const HemWork& w, int n) {
 
 // A tiled pass; false when it did not finish (the caller repeats the pass).
 bool run_tiles(SetupWork& W, HemWork& w, const Csr& B, hipStream_t s) {
-    launch_hem_tile(B.n, B.rp, B.ci, B.v, w, tile_timeout_ticks(), s);
+    launch_hem_tile(B.n, B.nnz, B.rp, B.ci, B.v, w, tile_timeout_ticks(), s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(&W.hc[2], w.cnt + 7, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

@@ -63,7 +63,8 @@ struct HemWork {
     int* err;
     int round_grid = 96;  // blocks of a one-launch-per-round pass
     int tile_rows = kHemTileRows;  // rows per tile of a tiled pass (0: no tiled passes)
-    int tile_c_rows = kHemTileCRows;  // rows per tile when the records have side 7 and sit in LDS (0: not used)
+    int tile_c_rows = kHemTileCRows;  // rows per LDS-record tile (0: not used; below kHemTileCRows: every
+                                      // side-7 pass takes them, for tests)
     int lds_rows = kHemLdsRows;  // one-workgroup passes up to this size keep their state in LDS
     double* wsym = nullptr;  // edge-based matching: [nnz] heavier of |a_uv|, |a_vu| (0 on the diagonal)
     int* ptr = nullptr;      // edge-based matching: [n] best undecided neighbour
@@ -78,7 +79,7 @@ void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWor
 // w.side 7 or 15).
 // cnt[7] != 0 afterwards: the pass did not finish within tmo wall-clock ticks
 // (or a counter exceeded 16 bits) and must be repeated with the round kernels.
-void launch_hem_tile(int n, const int* rp, const int* ci, const double* v, HemWork& w, long long tmo,
+void launch_hem_tile(int n, int64_t nnz, const int* rp, const int* ci, const double* v, HemWork& w, long long tmo,
                      hipStream_t s);
 // Block-diagonal operators: seg[j] = (first row, rows) of system j; systems of
 // at most kHemLdsRows rows are matched one workgroup each and marked decided

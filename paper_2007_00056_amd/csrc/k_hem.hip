@@ -673,11 +673,8 @@ __device__ __forceinline__ int hem_lds_body(int off, int n, const HemState& S, c
         const uint16_t* c = cur;
         const int* g = gin;
         const int klc = kl;
-        // the round's first items go to wave r mod (waves), as in the tiled passes
-        constexpr int NW = hem_nt<SIDE>() / kWave;
-        const int first = (int)((threadIdx.x + (unsigned)(NW - r % NW) * kWave) % hem_nt<SIDE>());
         hem_round_body<LdsSt, SIDE, hem_nt<SIDE>()>(
-            S, st, r, m, first, hem_nt<SIDE>(), [&](int i) { return i < klc ? (int)c[i] + off : g[i - klc]; }, A,
+            S, st, r, m, threadIdx.x, hem_nt<SIDE>(), [&](int i) { return i < klc ? (int)c[i] + off : g[i - klc]; }, A,
             s_wave, &s_nw, HL_WCAP);
         kl = min(s_cnt, HL_LCAP);
         kg = s_gnext;
@@ -1021,7 +1018,7 @@ __device__ __forceinline__ void tile_visit(const HemState& S, const TileSt& st, 
 constexpr int kTileCRows = kHemTileCRows;  // largest tile of the compact-record driver
 constexpr int kCSide = 4;         // entries a side of a compact record
 constexpr int kCGlobal = 0x80;    // compact header flag: use the global record
-constexpr int kCompactMaxTiles = 512;  // compact tiles only for passes of at most this many
+constexpr int kCompactMaxTiles = 512;  // largest pass (in tiles) that takes compact tiles
 
 struct CRecs {
     const uint8_t* hdr;  // per tile vertex: #higher | #lower << 3 | kCGlobal
@@ -1680,14 +1677,19 @@ void launch_seg_table(int m, const int* off, const int* agg, int n, bool mirror,
     hipLaunchKernelGGL(k_seg_table, dim3(blocks_for(m)), dim3(BS), 0, s, m, off, agg, n, mirror ? 1 : 0, seg);
 }
 
-void launch_hem_tile(int n, const int* rp, const int* ci, const double* v, HemWork& w, long long tmo,
+void launch_hem_tile(int n, int64_t nnz, const int* rp, const int* ci, const double* v, HemWork& w, long long tmo,
                      hipStream_t s) {
-    // records of side 7 go to small tiles with LDS copies of the records when
-    // those tiles can all be resident at once (one workgroup per compute unit):
-    // a tile that is not resident waits for a lower one to finish, and on long
-    // dependency chains the larger tiles are faster
+    // Small tiles with LDS copies of the records cut the cost of a round but
+    // multiply the vertices whose lower neighbours lie in other tiles, and a
+    // step across tiles costs several rounds.  As measured on MI355X they pay
+    // for passes of short rows (at most 8 entries on average, so nearly every
+    // record fits) of at most 512 tiles; more tiles cannot all be resident at
+    // once (one workgroup per compute unit), so a tile would wait for a lower
+    // one to finish, and on the long chains of such passes that loses.
     const int Tc = w.tile_c_rows < kTileCRows ? w.tile_c_rows : kTileCRows;
-    const bool compact = w.side == 7 && Tc > 0 && ((int64_t)n + Tc - 1) / Tc <= kCompactMaxTiles;
+    const int64_t ntc = Tc > 0 ? ((int64_t)n + Tc - 1) / Tc : 0;
+    const bool compact = w.side == 7 && Tc > 0 && nnz <= 8 * (int64_t)n &&
+                         (w.tile_c_rows < kTileCRows || ntc <= kCompactMaxTiles);
     const int T = compact ? Tc : w.tile_rows;
     const int nt = (n + T - 1) / T;
     hipLaunchKernelGGL(k_hem_tile_prep, dim3(blocks_for(n)), dim3(BS), 0, s, n, T, rp, ci, w.lowok, w.lcnt, w.cnt);
