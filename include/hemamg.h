@@ -169,6 +169,21 @@ amg_status amg_vcycle(amg_hier* h, const double* r, double* z, void* stream);
 amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x, double rtol, int32_t maxit,
                         void* stream, amg_info* info);
 
+/* krylov_solve for callers that cannot allocate memory during the call (a
+ * serving loop that must not call hipMalloc, a harness that forbids it): the
+ * same arguments, kernels and results, but the Krylov work vectors come from
+ * a scratch array compiled into the library (80 MiB on every device the
+ * library runs on, held until the process ends), so the call allocates
+ * nothing and never draws the handle's workspace.  Iterations are not
+ * replayed from graphs.  Limit: the handle's level 0 has at most 1048576
+ * rows (else AMG_EINVAL).  Calls on one device share that scratch: calls that
+ * overlap in time on one device (other threads, or work still running on
+ * other streams) race and give wrong results; the call blocks the host until
+ * its work is done, so calls made one after another are safe.
+ * Errors: as krylov_solve (AMG_ENOMEM cannot occur). */
+amg_status krylov_solve_noalloc(amg_hier* h, int32_t method, const double* b, double* x, double rtol,
+                                int32_t maxit, void* stream, amg_info* info);
+
 /* Number of levels (coarsest included) and the size of level k.  [host] */
 amg_status amg_num_levels(const amg_hier* h, int32_t* levels);
 amg_status amg_level_size(const amg_hier* h, int32_t k, int32_t* n, int64_t* nnz);

@@ -1668,6 +1668,60 @@ amg_status krylov_solve(amg_hier* h, int32_t method, const double* b, double* x,
     return amg::krylov_run(h, method, b, x, rtol, maxit, stream, info, nullptr);
 }
 
+}  // extern "C"
+
+// Work vectors of krylov_solve_noalloc: kKrylovVecs vectors of up to
+// kNoAllocRows doubles each (80 MiB), one copy on every device the library
+// runs on, held until the process ends.  Host code never uses the array's
+// name as an address: each device's copy is reached through the pointer that
+// hipGetSymbolAddress returns for it.
+namespace {
+constexpr int kNoAllocRows = 1 << 20;
+static __device__ __align__(256) double scratch[(size_t)amg::kKrylovVecs * kNoAllocRows];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices];  // device address of scratch, per device (nullptr: not resolved yet)
+
+// The current device's copy of scratch, resolved once per device.
+double* scratch_of_current_device() {
+    const int d = amg::current_device();
+    if (d < 0 || d >= kMaxDevices) raise(AMG_EHIP, "krylov_solve_noalloc: device %d out of range", d);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_dev[d]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            raise(AMG_EHIP, "krylov_solve_noalloc: hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_dev[d] = static_cast<double*>(p);
+    }
+    return g_scratch_dev[d];
+}
+}  // namespace
+
+extern "C" {
+
+amg_status krylov_solve_noalloc(amg_hier* h, int32_t method, const double* b, double* x, double rtol, int32_t maxit,
+                                void* stream, amg_info* info) {
+    double* ext[amg::kKrylovVecs];
+    const amg_status st = guarded([&] {
+        if (!h) raise(AMG_EINVAL, "krylov_solve_noalloc: NULL argument");
+        const int n = h->lev[0].n;
+        if (n > kNoAllocRows)
+            raise(AMG_EINVAL, "krylov_solve_noalloc: %d rows exceed the scratch limit of %d rows", n, kNoAllocRows);
+        double* base = scratch_of_current_device();
+        const size_t stride = ((size_t)n + 31) / 32 * 32;  // 256-byte aligned vectors
+        for (int k = 0; k < amg::kKrylovVecs; ++k) ext[k] = base + (size_t)k * stride;
+    });
+    if (st != AMG_OK) {
+        if (info) {
+            *info = amg_info{};
+            info->status = st;
+        }
+        return st;
+    }
+    return amg::krylov_run(h, method, b, x, rtol, maxit, stream, info, ext);
+}
 
 amg_status amg_num_levels(const amg_hier* h, int32_t* levels) {
     return guarded([&] {

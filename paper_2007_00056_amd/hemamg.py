@@ -27,7 +27,7 @@ EXPORTED = ["amg_params_default", "amg_setup", "amg_destroy", "amg_vcycle", "kry
             "amg_last_error", "amg_footprint_bytes", "amg_server_config_default", "amg_server_create",
             "amg_server_submit", "amg_server_wait", "amg_server_destroy", "amg_batch_create", "amg_batch_rows",
             "amg_batch_solve", "amg_batch_destroy", "amg_batch_levels", "amg_batch_autotune", "amg_autotune",
-            "amg_batch_setup", "amg_batch_set_graphs"]
+            "amg_batch_setup", "amg_batch_set_graphs", "krylov_solve_noalloc"]
 
 
 class amg_csr(C.Structure):
@@ -84,6 +84,7 @@ def lib():
             "amg_destroy": [vp],
             "amg_vcycle": [vp, vp, vp, vp],
             "krylov_solve": [vp, i32, vp, vp, f64, i32, vp, C.POINTER(amg_info)],
+            "krylov_solve_noalloc": [vp, i32, vp, vp, f64, i32, vp, C.POINTER(amg_info)],
             "amg_num_levels": [vp, C.POINTER(i32)],
             "amg_level_size": [vp, i32, C.POINTER(i32), C.POINTER(i64)],
             "amg_export_level": [vp, i32, vp, vp, vp, vp, vp],
@@ -221,6 +222,18 @@ def amg_vcycle(h: int, r, z, stream=None) -> None:
 def krylov_solve(h: int, method: int, b, x, rtol: float, maxit: int, stream=None, check: bool = True) -> dict:
     info = amg_info()
     st = lib().krylov_solve(h, method, _ptr(b), _ptr(x), rtol, maxit, _stream_ptr(stream), C.byref(info))
+    out = _info_dict(st, info)
+    if check and st not in (AMG_OK,):
+        raise AmgError(st, lib().amg_last_error().decode())
+    return out
+
+
+def krylov_solve_noalloc(h: int, method: int, b, x, rtol: float, maxit: int, stream=None,
+                         check: bool = True) -> dict:
+    """krylov_solve with the work vectors in the library's static scratch
+    (no allocation during the call; level 0 of at most 2^20 rows)."""
+    info = amg_info()
+    st = lib().krylov_solve_noalloc(h, method, _ptr(b), _ptr(x), rtol, maxit, _stream_ptr(stream), C.byref(info))
     out = _info_dict(st, info)
     if check and st not in (AMG_OK,):
         raise AmgError(st, lib().amg_last_error().decode())
