@@ -8,14 +8,14 @@
 // (setup, Krylov solve, teardown) through the public entry points; kernels
 // of different requests overlap on the device.
 //
-// Batched mode (batch >= 2), continuous: worker threads take the queued
-// requests of one class (method, stop settings, small or large systems; up
-// to `batch`, within the budget) and build their hierarchies together
-// (amg_batch_setup).  A PCG group then joins the solve scheduler, one
-// thread that advances every batch in flight by one iteration per tick
-// (each batch on its own stream, so their kernels overlap), while the
-// workers already set up the next groups from whatever has arrived since.
-// A request is complete as soon as its own system leaves the iteration; the
+// Batched mode (batch >= 2): worker threads take the queued requests of one
+// class (method, stop settings, small or large systems; up to `batch`,
+// within the budget) and build their hierarchies together
+// (amg_batch_setup).  The worker then advances its PCG group one iteration
+// at a time on its own stream, so the groups of different workers overlap
+// on the device and their launches come from several host threads, while
+// idle workers form the next groups from whatever has arrived since.  A
+// request is complete as soon as its own system leaves the iteration; the
 // batch's memory, and the budget of its requests, is released when its last
 // system is done.  BiCGStab groups are solved by their worker in one call.
 #include <hip/hip_runtime.h>
@@ -98,19 +98,17 @@ struct amg_server {
     amg_server_config cfg{};
     int device = 0;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done, cv_solve;
+    std::condition_variable cv_work, cv_done;
     std::deque<int64_t> pending;
     std::unordered_map<int64_t, Request*> reqs;
     int64_t next_id = 1;
     uint64_t in_use = 0;
     int active = 0;
     bool stopping = false;
-    bool workers_done = false;
     std::vector<std::thread> threads;
-    std::thread scheduler;
     std::vector<hipStream_t> wstreams;  // one per worker, destroyed with the server
 
-    // A set-up PCG group waiting for, or in, the solve scheduler.
+    // A set-up PCG group being solved by its worker.
     struct Flight {
         amg_batch* bt = nullptr;
         std::vector<Request*> grp;     // nullptr once the request is complete
@@ -119,7 +117,6 @@ struct amg_server {
         amg::PcgRun* run = nullptr;
         Clock::time_point t0;
     };
-    std::deque<std::unique_ptr<Flight>> ready;  // set up, not yet started
 
     void release_streams() {
         for (hipStream_t& st : wstreams)
@@ -133,8 +130,7 @@ struct amg_server {
     bool batched() const { return cfg.batch >= 2; }
     const amg_allocator* alloc() const { return cfg.alloc.alloc ? &cfg.alloc : nullptr; }
 
-    // Workers drain the queue and exit, then the scheduler finishes the
-    // batches in flight and exits.
+    // Workers drain the queue, finish their groups and exit.
     void stop_threads() {
         {
             std::lock_guard<std::mutex> lk(mu);
@@ -143,12 +139,6 @@ struct amg_server {
         cv_work.notify_all();
         for (auto& t : threads) t.join();
         threads.clear();
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            workers_done = true;
-        }
-        cv_solve.notify_all();
-        if (scheduler.joinable()) scheduler.join();
     }
 
     // The request's result is final: its waiter may proceed (and free it).
@@ -230,7 +220,7 @@ struct amg_server {
                 run_one(grp[0], s);
                 finish(grp[0]);
             } else if (grp[0]->method == 0) {
-                setup_group(grp, s);  // on to the solve scheduler
+                pcg_group(grp, s);
             } else {
                 run_group(grp, s);
                 for (Request* r : grp) finish(r);
@@ -262,11 +252,11 @@ struct amg_server {
     }
 
     // A PCG group: batched setup on the worker's stream, the systems' right-
-    // hand sides and initial guesses loaded into the batch, then the group
-    // joins the solve scheduler.  When the batched setup fails as a whole, or a
+    // hand sides and initial guesses loaded into the batch, then the solve,
+    // one iteration at a time.  When the batched setup fails as a whole, or a
     // system cannot be batched (a single level), the requests concerned are
     // run one by one here.
-    void setup_group(std::vector<Request*>& grp, hipStream_t s) {
+    void pcg_group(std::vector<Request*>& grp, hipStream_t s) {
         const int n = (int)grp.size();
         std::vector<amg_csr> A(n);
         for (int i = 0; i < n; ++i) A[i] = grp[i]->A;
@@ -314,15 +304,11 @@ struct amg_server {
                 F->feet.push_back(grp[i]->foot);
             }
         }
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            ready.push_back(std::move(F));
-        }
-        cv_solve.notify_one();
         for (Request* r : alone) {
             run_one(r, s);
             finish(r);
         }
+        solve_flight(*F);
     }
 
     // BiCGStab groups: one batched setup and one batched solve.  When the
@@ -431,70 +417,35 @@ struct amg_server {
         for (uint64_t f : F.feet) release(f);
     }
 
-    // The solve scheduler: every tick, each batch in flight gets one PCG
-    // iteration enqueued on its own stream, then each is collected; groups
-    // set up meanwhile join at the next tick.
-    void solve_loop() {
-        if (hipSetDevice(device) != hipSuccess) return;
-        std::vector<std::unique_ptr<Flight>> live;
+    // The batched PCG of flight F, one iteration at a time: each system is
+    // delivered as soon as it leaves the iteration; the batch goes with the
+    // last one.
+    void solve_flight(Flight& F) {
+        F.t0 = Clock::now();
         std::vector<int> done;
-        for (;;) {
-            std::vector<std::unique_ptr<Flight>> fresh;
-            {
-                std::unique_lock<std::mutex> lk(mu);
-                cv_solve.wait(lk, [&] { return !ready.empty() || !live.empty() || workers_done; });
-                if (ready.empty() && live.empty() && workers_done) break;
-                while (!ready.empty()) {
-                    fresh.push_back(std::move(ready.front()));
-                    ready.pop_front();
-                }
+        const Request* r0 = nullptr;
+        for (Request* r : F.grp)
+            if (r) {
+                r0 = r;
+                break;
             }
-            for (auto& F : fresh) {
-                F->t0 = Clock::now();
-                done.clear();
-                const Request* r0 = nullptr;
-                for (Request* r : F->grp)
-                    if (r) {
-                        r0 = r;
-                        break;
-                    }
-                const amg_status st = amg::guarded([&] {
-                    if (r0) F->run = amg::pcg_run_start(F->bt, r0->rtol, r0->maxit, done);
-                });
-                if (st != AMG_OK || !r0) {
-                    for (size_t i = 0; i < F->grp.size(); ++i) deliver(*F, (int)i, st != AMG_OK ? st : AMG_EHIP);
-                    retire(*F);
-                    continue;
-                }
-                for (int i : done) deliver(*F, i);
-                if (amg::pcg_run_live(F->run) == 0) {
-                    retire(*F);
-                    continue;
-                }
-                live.push_back(std::move(F));
-            }
-            for (auto& F : live) {
-                const amg_status st = amg::guarded([&] { amg::pcg_run_enqueue(F->run); });
-                if (st != AMG_OK)
-                    for (size_t i = 0; i < F->grp.size(); ++i) deliver(*F, (int)i, st);
-            }
-            for (auto& F : live) {
-                done.clear();
-                const amg_status st = amg::guarded([&] { amg::pcg_run_collect(F->run, done); });
-                for (int i : done) deliver(*F, i);
-                if (st != AMG_OK)
-                    for (size_t i = 0; i < F->grp.size(); ++i) deliver(*F, (int)i, st);
-            }
-            for (auto& F : live) {
-                bool any = false;
-                for (Request* r : F->grp) any |= r != nullptr;
-                if (!any) {
-                    retire(*F);
-                    F.reset();
-                }
-            }
-            live.erase(std::remove(live.begin(), live.end(), nullptr), live.end());
+        if (!r0) {
+            retire(F);
+            return;
         }
+        amg_status st = amg::guarded([&] { F.run = amg::pcg_run_start(F.bt, r0->rtol, r0->maxit, done); });
+        for (int i : done) deliver(F, i);
+        while (st == AMG_OK && F.run && amg::pcg_run_live(F.run) > 0) {
+            done.clear();
+            st = amg::guarded([&] {
+                amg::pcg_run_enqueue(F.run);
+                amg::pcg_run_collect(F.run, done);
+            });
+            for (int i : done) deliver(F, i);
+        }
+        if (st != AMG_OK)
+            for (size_t i = 0; i < F.grp.size(); ++i) deliver(F, (int)i, st);
+        retire(F);
     }
 };
 
@@ -542,7 +493,6 @@ amg_status amg_server_create(const amg_server_config* c, amg_server** out) {
                 delete s;
                 return AMG_EHIP;
             }
-        if (s->batched()) s->scheduler = std::thread([s] { s->solve_loop(); });
         for (int i = 0; i < cfg.workers; ++i) s->threads.emplace_back([s, i] { s->worker(i); });
     } catch (...) {
         s->stop_threads();

@@ -369,8 +369,12 @@ __global__ __launch_bounds__(BS) void k_cg_dir(int n, const double* __restrict__
 void launch_cg_dir(int n, const double* z, const double* p, double* pn, double* S, int slot_new, int slot_old,
                    hipStream_t s, double* Sh, int nsh, const double* new_part, int new_np, const double* rr_part,
                    int rr_np, int slot_rr) {
-    hipLaunchKernelGGL(k_cg_dir, dim3(vec_blocks(n)), dim3(BS), 0, s, n, z, p, pn, S, slot_new, slot_old, Sh, nsh,
-                       new_part, new_np, rr_part, rr_np, slot_rr);
+    // every block adds the (r, z) partials itself, so with partials the grid
+    // stays at kFusedParts blocks (grid-stride) to bound those reads
+    int g = vec_blocks(n);
+    if (new_part && g > kFusedParts) g = kFusedParts;
+    hipLaunchKernelGGL(k_cg_dir, dim3(g), dim3(BS), 0, s, n, z, p, pn, S, slot_new, slot_old, Sh, nsh, new_part,
+                       new_np, rr_part, rr_np, slot_rr);
 }
 
 // Algorithm 5: s = r - alpha v, alpha = rho / (rbar, v)
