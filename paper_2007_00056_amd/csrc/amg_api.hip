@@ -87,6 +87,83 @@ void stream_put(hipStream_t s) {
     g_res[current_device()].streams.push_back(s);
 }
 
+namespace {
+struct KeptChunk {
+    void* p;
+    size_t bytes;
+    hipEvent_t ev;  // recorded on the stream that last used the chunk
+};
+std::mutex g_chunk_mu;
+std::map<int, std::vector<KeptChunk>> g_chunks;  // per device, oldest first
+std::map<int, size_t> g_chunk_bytes;
+}  // namespace
+
+bool chunk_keep(void* p, size_t bytes, hipStream_t s) {
+    const int d = current_device();
+    if (bytes > kChunkCacheBytes) return false;
+    hipEvent_t ev = event_get(false);
+    if (hipEventRecord(ev, s) != hipSuccess) {
+        (void)hipGetLastError();
+        event_put(ev, false);
+        return false;
+    }
+    std::vector<KeptChunk> evict;
+    {
+        std::lock_guard<std::mutex> g(g_chunk_mu);
+        auto& v = g_chunks[d];
+        size_t& tot = g_chunk_bytes[d];
+        v.push_back(KeptChunk{p, bytes, ev});
+        tot += bytes;
+        while (tot > kChunkCacheBytes) {  // the oldest go back to the pool
+            evict.push_back(v.front());
+            tot -= v.front().bytes;
+            v.erase(v.begin());
+        }
+    }
+    for (KeptChunk& k : evict) {
+        (void)hipStreamWaitEvent(s, k.ev, 0);
+        (void)hipFreeAsync(k.p, s);
+        event_put(k.ev, false);
+    }
+    return true;
+}
+
+void* chunk_take(size_t bytes, hipStream_t s) {
+    const int d = current_device();
+    KeptChunk k{nullptr, 0, nullptr};
+    {
+        std::lock_guard<std::mutex> g(g_chunk_mu);
+        auto& v = g_chunks[d];
+        for (size_t i = v.size(); i-- > 0;)
+            if (v[i].bytes == bytes) {
+                k = v[i];
+                v.erase(v.begin() + (std::ptrdiff_t)i);
+                g_chunk_bytes[d] -= bytes;
+                break;
+            }
+    }
+    if (!k.p) return nullptr;
+    HIPCHK(hipStreamWaitEvent(s, k.ev, 0));
+    event_put(k.ev, false);
+    return k.p;
+}
+
+void chunk_flush() {
+    const int d = current_device();
+    std::vector<KeptChunk> all;
+    {
+        std::lock_guard<std::mutex> g(g_chunk_mu);
+        all.swap(g_chunks[d]);
+        g_chunk_bytes[d] = 0;
+    }
+    for (KeptChunk& k : all) {
+        (void)hipEventSynchronize(k.ev);
+        (void)hipFreeAsync(k.p, nullptr);
+        event_put(k.ev, false);
+    }
+    if (!all.empty()) (void)hipStreamSynchronize(nullptr);
+}
+
 hipEvent_t event_get(bool timing) {
     {
         std::lock_guard<std::mutex> g(g_res_mu);

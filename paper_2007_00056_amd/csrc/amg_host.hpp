@@ -95,16 +95,34 @@ inline amg_allocator checked_allocator(const amg_allocator* a) {
     return *a;
 }
 
+// Library-pool chunks that an arena releases are kept per device instead of
+// being freed: returning a block of a few hundred MB to the stream-ordered
+// pool costs about 0.3 ms of host time on MI355X, and setups of one shape
+// ask for the same chunk sizes again.  chunk_keep stores a chunk with an
+// event recorded on the stream that last used it (false: the cache is full,
+// the caller frees it); chunk_take hands out a kept chunk of exactly `bytes`
+// on the current device after `s` waits for that event (nullptr: none);
+// chunk_flush frees every kept chunk of the current device.
+bool chunk_keep(void* p, size_t bytes, hipStream_t s);
+void* chunk_take(size_t bytes, hipStream_t s);
+void chunk_flush();
+constexpr size_t kChunkCacheBytes = size_t(8) << 30;  // kept per device at most
+
 // An arena over the pool (or the caller's allocator): pieces (256-byte
 // aligned) are carved from a few chunks (sized from a hint, or by a larger
 // request), so a handle makes a handful of allocation calls instead of one
 // per array.  Chunks are released stream-ordered on the stream they were
-// drawn on.
+// drawn on (library chunks into the chunk cache above).
 struct DevPool {
+    struct Chunk {
+        void* p;
+        hipStream_t s;
+        size_t bytes;
+    };
     hipStream_t s = nullptr;
     hipMemPool_t mp = nullptr;
     amg_allocator al{};                // al.alloc set: chunks come from the caller
-    std::vector<std::pair<void*, hipStream_t>> chunks;
+    std::vector<Chunk> chunks;
     char* cur = nullptr;
     size_t left = 0;
     size_t bytes = 0;                 // device memory held (sum of chunks)
@@ -123,11 +141,18 @@ struct DevPool {
             if (al.alloc) {
                 p = al.alloc(c, al.ctx, s);
                 if (!p) raise(AMG_ENOMEM, "the caller's allocator returned NULL for %zu bytes", c);
-            } else {
+            } else if (!(p = chunk_take(c, s))) {
                 if (!mp) mp = lib_pool();
-                HIPCHK(hipMallocFromPoolAsync(&p, c, mp, s));
+                hipError_t e = hipMallocFromPoolAsync(&p, c, mp, s);
+                if (e == hipErrorOutOfMemory) {  // give the kept chunks back and try once more
+                    (void)hipGetLastError();
+                    chunk_flush();
+                    e = hipMallocFromPoolAsync(&p, c, mp, s);
+                }
+                if (e == hipErrorOutOfMemory) raise(AMG_ENOMEM, "hipMallocFromPoolAsync: out of GPU memory");
+                if (e != hipSuccess) raise(AMG_EHIP, "hipMallocFromPoolAsync: %s", hipGetErrorString(e));
             }
-            chunks.emplace_back(p, s);
+            chunks.push_back(Chunk{p, s, c});
             cur = static_cast<char*>(p);
             left = c;
             bytes += c;
@@ -140,8 +165,8 @@ struct DevPool {
     }
     void release() {
         for (auto& c : chunks) {
-            if (al.alloc) al.free(c.first, al.ctx, c.second);
-            else (void)hipFreeAsync(c.first, c.second);
+            if (al.alloc) al.free(c.p, al.ctx, c.s);
+            else if (!chunk_keep(c.p, c.bytes, c.s)) (void)hipFreeAsync(c.p, c.s);
         }
         chunks.clear();
         cur = nullptr;
