@@ -3,6 +3,7 @@
 // (Algorithm 1) and the Krylov drivers (Algorithms 4 and 5).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -772,35 +773,75 @@ void spmv_dot_timed(amg_hier* h, const LevelView& A, const double* p, double* q,
 // the iteration are added by their consumer kernels from the producers' block
 // partials (the update adds (p, q), the direction kernel (r, z) and (r, r)),
 // so no separate finish kernel runs.
-void pcg_iter_a(amg_hier* h, double* x, int pc, hipStream_t s) {
+// [A] is enqueued in two parts: the SpMV (q = A p and the (p, q) partials,
+// both scratch that nothing else reads, so it may run ahead of the decision
+// whether the iteration is needed), then the update and the V-cycle to level 1.
+void pcg_iter_q(amg_hier* h, int pc, hipStream_t s) {
+    const Level& A0 = h->lev[0];
+    const Reducer R = h->reducer();
+    double* p = h->pv[pc];
+    if (h->fuse_dots) {
+        timed_begin(h, 2, s);
+        h->pq_np = launch_spmv_dot_parts(A0.view(), p, h->q, p, R.part + kPartPQ, s);
+        timed_end(h, 2, s);
+    } else {
+        spmv_dot_timed(h, A0.view(), p, h->q, p, S_PQ, s);
+        h->pq_np = 0;
+    }
+}
+
+void pcg_iter_u(amg_hier* h, double* x, int pc, hipStream_t s) {
     const Level& A0 = h->lev[0];
     const Reducer R = h->reducer();
     const int cur = pc ? S_RHO1 : S_RHO0, nxt = pc ? S_RHO0 : S_RHO1;
     double* p = h->pv[pc];
     if (h->fuse_dots) {
-        timed_begin(h, 2, s);
-        const int np = launch_spmv_dot_parts(A0.view(), p, h->q, p, R.part + kPartPQ, s);
-        timed_end(h, 2, s);
         launch_cg_update(A0.n, x, h->r, p, h->q, A0.dinv, h->g0, h->prec32, R, cur, S_PQ, S_RR, s, R.part + kPartPQ,
-                         np, R.part + kPartRR, &h->rr_np);
+                         h->pq_np, R.part + kPartRR, &h->rr_np);
     } else {
-        spmv_dot_timed(h, A0.view(), p, h->q, p, S_PQ, s);
         launch_cg_update(A0.n, x, h->r, p, h->q, A0.dinv, h->g0, h->prec32, R, cur, S_PQ, S_RR, s);
         h->rr_np = 0;
     }
     run_vcycle(h, h->r, h->z, s, h->g0, nxt, 1);
 }
 
+void pcg_iter_a(amg_hier* h, double* x, int pc, hipStream_t s) {
+    pcg_iter_q(h, pc, s);
+    pcg_iter_u(h, x, pc, s);
+}
+
 void pcg_iter_p(amg_hier* h, int pc, hipStream_t s) {
     run_vcycle(h, h->r, h->z, s, h->g0, pc ? S_RHO0 : S_RHO1, 2);
 }
 
-void pcg_iter_b(amg_hier* h, int pc, hipStream_t s) {
+// seq != 0: the direction kernel also publishes seq after the slots (eager
+// launches only: a captured graph would replay one value).
+void pcg_iter_b(amg_hier* h, int pc, hipStream_t s, unsigned long long seq = 0) {
     const int cur = pc ? S_RHO1 : S_RHO0, nxt = pc ? S_RHO0 : S_RHO1;
     double* part = h->part;
     // the direction kernel also writes the slots into the mapped host block
+    unsigned long long* hseq = seq ? reinterpret_cast<unsigned long long*>(h->S_dev + kSeqSlot) : nullptr;
     launch_cg_dir(h->lev[0].n, h->z, h->pv[pc], h->pv[1 - pc], h->S, nxt, cur, s, h->S_dev, S_COUNT,
-                  h->rz_np ? part + kPartRZ : nullptr, h->rz_np, h->rr_np ? part + kPartRR : nullptr, h->rr_np, S_RR);
+                  h->rz_np ? part + kPartRZ : nullptr, h->rz_np, h->rr_np ? part + kPartRR : nullptr, h->rr_np, S_RR,
+                  hseq, seq);
+}
+
+// Waits for the eager iteration that publishes sequence number h->seq: the
+// host watches that word of the mapped slot block instead of blocking on the
+// stream (the next iteration is launched sooner).  After one second it falls
+// back to a blocking synchronisation, which also reports a failed kernel.
+void wait_slots(amg_hier* h, hipStream_t s) {
+    volatile unsigned long long* w = reinterpret_cast<volatile unsigned long long*>(h->S_host + kSeqSlot);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned k = 1; *w != h->seq; ++k) {
+        if ((k & 4095) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) {
+            HIPCHK(hipStreamSynchronize(s));
+            if (*w != h->seq) raise(AMG_EHIP, "krylov_solve: the iteration's scalars did not arrive");
+            break;
+        }
+        __builtin_ia32_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
 }
 
 template <class F>
@@ -822,13 +863,19 @@ hipGraphExec_t capture(hipStream_t s, F&& body) {
 }
 
 // Enqueue PCG iteration `pc` and its slot read-back on s (graph replay when
-// possible); the caller synchronises s and reads the slots.
-void pcg_iteration(amg_hier* h, const double* b, double* x, int pc, bool graphs, hipStream_t s) {
+// possible); the caller waits for the slots (wait_slots for eager launches,
+// a stream synchronisation for graphs) and reads them.  Eager launches:
+// q_done says the iteration's SpMV is already enqueued, and ahead (for the
+// iteration after this one, parity 1 - pc) enqueues the next SpMV behind it.
+void pcg_iteration(amg_hier* h, const double* b, double* x, int pc, bool graphs, hipStream_t s, bool q_done = false,
+                   bool ahead = false) {
     const bool timed = h->tim[0].on && vcycle_splits(h);
     if (!graphs) {
-        pcg_iter_a(h, x, pc, s);
+        if (!q_done) pcg_iter_q(h, pc, s);
+        pcg_iter_u(h, x, pc, s);
         pcg_iter_p(h, pc, s);
-        pcg_iter_b(h, pc, s);
+        pcg_iter_b(h, pc, s, ++h->seq);
+        if (ahead) pcg_iter_q(h, 1 - pc, s);
         HIPCHK(hipGetLastError());
         return;
     }
@@ -882,12 +929,18 @@ amg_status pcg(amg_hier* h, const double* b, double* x, double rtol, int maxit, 
     int pc = 0;
     run_vcycle(h, h->r, h->z, s, h->g0, S_RHO0);
     HIPCHK(hipMemcpyAsync(h->pv[0], h->z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    bool q_done = false;  // eager launches: this iteration's SpMV was enqueued ahead
     for (int it = 1; it <= maxit; ++it) {
         const int cur = pc ? S_RHO1 : S_RHO0, nxt = pc ? S_RHO0 : S_RHO1;
         // the preconditioning, (r, z) and the next direction are speculative:
-        // unused when this iteration stops
-        pcg_iteration(h, b, x, pc, graphs, s);
-        HIPCHK(hipStreamSynchronize(s));
+        // unused when this iteration stops; so is the next iteration's SpMV,
+        // enqueued before the host reads this iteration's scalars (it writes
+        // only q and its partials)
+        const bool ahead = !graphs && it < maxit;
+        pcg_iteration(h, b, x, pc, graphs, s, q_done, ahead);
+        q_done = ahead;
+        if (graphs) HIPCHK(hipStreamSynchronize(s));
+        else wait_slots(h, s);
         if (!usable(S[S_PQ]) || !std::isfinite(S[cur])) return AMG_EBREAKDOWN;
         info.iters = it;
         rel = std::sqrt(S[S_RR]) / nb;
@@ -902,6 +955,7 @@ amg_status pcg(amg_hier* h, const double* b, double* x, double rtol, int maxit, 
             run_vcycle(h, h->r, h->z, s, h->g0, nxt);
             launch_cg_dir(n, h->z, h->pv[pc], h->pv[1 - pc], h->S, nxt, cur, s);
             read_slots(h, s);
+            q_done = false;  // the direction changed: the SpMV enqueued ahead is stale
         }
         if (!usable(S[nxt])) return AMG_EBREAKDOWN;
         pc = 1 - pc;
@@ -1196,9 +1250,13 @@ void setup_impl(const amg_csr* Ain, const amg_params* pin, const amg_allocator* 
     h->S = P.get<double>(S_COUNT);
     h->part = P.get<double>(2 * (size_t)kRedBlocks);
     HIPCHK(hipMemsetAsync(h->S, 0, S_COUNT * sizeof(double), s));
-    static_assert((S_COUNT + 1) * sizeof(double) <= kPinnedBlock, "slots and a read-back word");
+    static_assert((kSeqSlot + 1) * sizeof(double) <= kPinnedBlock, "slots, a read-back word and the sequence word");
     h->S_host = static_cast<double*>(pinned_get());
     HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&h->S_dev), h->S_host, 0));
+    // the block may come from an earlier handle (whose work has finished):
+    // its sequence word restarts with this handle's counter
+    *reinterpret_cast<volatile unsigned long long*>(h->S_host + kSeqSlot) = 0;
+    h->seq = 0;
     HIPCHK(hipStreamSynchronize(s));
     for (size_t k = 0; k + 1 < pev.size(); k += 2) {
         float ms = 0.f;

@@ -218,6 +218,10 @@ struct Level {
 
 // Scalar slots of the Krylov recurrences.
 enum Slot { S_BB = 0, S_RR, S_TRR, S_PQ, S_RHO0, S_RHO1, S_RV, S_TT, S_TS, S_COUNT = 16 };
+// In a handle's mapped slot block: S_COUNT slots, an int read-back word at
+// S_COUNT, and at kSeqSlot the sequence number of the last eager PCG
+// iteration whose slots have arrived.
+constexpr int kSeqSlot = S_COUNT + 1;
 
 struct Timer {
     bool on = false;
@@ -337,9 +341,10 @@ struct amg_hier {
     // the PCG iteration's reductions are added by their consumer kernels
     // (HEMAMG_FUSE_DOTS=0: separate finish kernels); partial counts pending
     bool fuse_dots = true;
-    int rz_np = 0, rr_np = 0;
+    int rz_np = 0, rr_np = 0, pq_np = 0;
     double* S_host = nullptr;  // pinned, mapped and coherent host block of the slots
     double* S_dev = nullptr;   // the same block's device address
+    unsigned long long seq = 0;  // sequence number of the last eager PCG iteration enqueued
     Timer tim[3];
     // PCG iteration graphs (one per ping-pong parity), replayed on gstream
     bool use_graphs = false;  // HEMAMG_GRAPHS=1: replay PCG iterations from HIP graphs

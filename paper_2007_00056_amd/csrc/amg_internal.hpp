@@ -250,10 +250,13 @@ void launch_cg_update(int n, double* x, double* r, const double* p, const double
 // first nsh scalar slots (nsh <= 256).  new_part (non-null): the kernel adds
 // the new_np partials of the new (r, z) itself (block 0 stores the sum in
 // slot_new).  rr_part (non-null): block 0 adds the rr_np partials of (r, r)
-// into slot_rr.
+// into slot_rr.  hseq (non-null, with Sh): after the slots, the word hseq
+// (mapped host memory too) receives seq, so the host can wait for the slots
+// by watching that word.
 void launch_cg_dir(int n, const double* z, const double* p, double* pn, double* S, int slot_new, int slot_old,
                    hipStream_t s, double* Sh = nullptr, int nsh = 0, const double* new_part = nullptr, int new_np = 0,
-                   const double* rr_part = nullptr, int rr_np = 0, int slot_rr = 0);
+                   const double* rr_part = nullptr, int rr_np = 0, int slot_rr = 0, unsigned long long* hseq = nullptr,
+                   unsigned long long seq = 0);
 void launch_bicg_s(int n, const double* r, const double* v, double* sv, const double* S, int slot_rho, int slot_rv,
                    hipStream_t s);
 void launch_bicg_update(int n, double* x, double* r, const double* pt, const double* st, const double* sv,

@@ -347,11 +347,13 @@ void launch_cg_update(int n, double* x, double* r, const double* p, const double
 // (r, r) partials into slot_rr.  With Sh (host memory mapped into the device),
 // block 0 then copies the first nsh scalar slots there: the iteration's last
 // kernel hands its scalars to the host without a copy.
+// hseq (non-null): after the slots, block 0 stores seq there (system scope),
+// so a host waiting on that word knows the slots are complete.
 __global__ __launch_bounds__(BS) void k_cg_dir(int n, const double* __restrict__ z, const double* __restrict__ p,
                                                double* __restrict__ pn, double* __restrict__ S, int slot_new,
                                                int slot_old, double* Sh, int nsh, const double* __restrict__ new_part,
                                                int new_np, const double* __restrict__ rr_part, int rr_np,
-                                               int slot_rr) {
+                                               int slot_rr, unsigned long long* hseq, unsigned long long seq) {
     const double rho_new = new_part ? block_sum_partials<BS>(new_part, new_np) : S[slot_new];
     if (blockIdx.x == 0 && (new_part || rr_part)) {
         const double rr = rr_part ? block_sum_partials<BS>(rr_part, rr_np) : 0.0;
@@ -363,18 +365,24 @@ __global__ __launch_bounds__(BS) void k_cg_dir(int n, const double* __restrict__
     }
     const double beta = rho_new / S[slot_old];
     for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) pn[i] = z[i] + beta * p[i];
-    if (Sh && blockIdx.x == 0 && (int)threadIdx.x < nsh) Sh[threadIdx.x] = S[threadIdx.x];
+    if (Sh && blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < nsh; ++k) Sh[k] = S[k];
+        if (hseq) {
+            __threadfence_system();  // the slots before the sequence word
+            __hip_atomic_store(hseq, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
 }
 
 void launch_cg_dir(int n, const double* z, const double* p, double* pn, double* S, int slot_new, int slot_old,
                    hipStream_t s, double* Sh, int nsh, const double* new_part, int new_np, const double* rr_part,
-                   int rr_np, int slot_rr) {
+                   int rr_np, int slot_rr, unsigned long long* hseq, unsigned long long seq) {
     // every block adds the (r, z) partials itself, so with partials the grid
     // stays at kFusedParts blocks (grid-stride) to bound those reads
     int g = vec_blocks(n);
     if (new_part && g > kFusedParts) g = kFusedParts;
     hipLaunchKernelGGL(k_cg_dir, dim3(g), dim3(BS), 0, s, n, z, p, pn, S, slot_new, slot_old, Sh, nsh, new_part,
-                       new_np, rr_part, rr_np, slot_rr);
+                       new_np, rr_part, rr_np, slot_rr, hseq, seq);
 }
 
 // Algorithm 5: s = r - alpha v, alpha = rho / (rbar, v)
