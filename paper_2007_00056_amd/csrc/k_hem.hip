@@ -532,7 +532,6 @@ __device__ __forceinline__ void hem_round_body(const HemState& S, const St& st, 
 
 constexpr int HEM_BS = 512;
 constexpr int HEM_LCAP = 4096;
-constexpr int HEM_BS1 = 1024;
 // Threads of the workgroup-wide drivers with LDS state (one workgroup, systems
 // of a batch, tiles): records of 31 entries a side need the registers of 512.
 template <int SIDE>
@@ -580,13 +579,15 @@ __global__ __launch_bounds__(HEM_BS) void k_hem_round(int r, int n, HemState S, 
 // Mid-size passes: one workgroup runs every round, separated by barriers,
 // with the state in global memory.  Each round decides at least the smallest
 // undecided vertex, so n + 1 rounds always suffice; the bound only guards
-// against invalid input.
+// against invalid input.  Records of 31 entries a side take the registers of
+// 512 threads, as in the LDS-state drivers; with 1024 they would spill.
 template <int SIDE>
-__global__ __launch_bounds__(HEM_BS1) void k_hem_all(int n, HemState S, int* dec, int* lcnt, int* wl0, int* wl1,
+__global__ __launch_bounds__(hem_nt<SIDE>()) void k_hem_all(int n, HemState S, int* dec, int* lcnt, int* wl0, int* wl1,
                                                      int* cnt) {
     __shared__ int s_list[HEM_LCAP1];
     __shared__ int s_wave[HEM_WCAP];
     __shared__ int s_cnt, s_next, s_m, s_nw;
+    constexpr int NT = hem_nt<SIDE>();
     if (threadIdx.x == 0) s_m = cnt[0];
     __syncthreads();
     const GlobalSt<__HIP_MEMORY_SCOPE_WORKGROUP> st{dec, lcnt};
@@ -603,11 +604,11 @@ __global__ __launch_bounds__(HEM_BS1) void k_hem_all(int n, HemState S, int* dec
         }
         __syncthreads();
         const Appender<int> A{s_list, &s_cnt, HEM_LCAP1, wout, &s_next};
-        hem_round_body<GlobalSt<__HIP_MEMORY_SCOPE_WORKGROUP>, SIDE, HEM_BS1>(
-            S, st, r, m, threadIdx.x, HEM_BS1, [&](int i) { return win[i]; }, A, s_wave, &s_nw, HEM_WCAP);
+        hem_round_body<GlobalSt<__HIP_MEMORY_SCOPE_WORKGROUP>, SIDE, NT>(
+            S, st, r, m, threadIdx.x, NT, [&](int i) { return win[i]; }, A, s_wave, &s_nw, HEM_WCAP);
         const int k = min(s_cnt, HEM_LCAP1);
         const int base = s_next;
-        for (int i = threadIdx.x; i < k; i += HEM_BS1) wout[base + i] = s_list[i];
+        for (int i = threadIdx.x; i < k; i += NT) wout[base + i] = s_list[i];
         __syncthreads();
         if (threadIdx.x == 0) s_m = base + k;
         int* t = win;
@@ -1712,7 +1713,7 @@ void launch_hem_all(int n, const int* rp, const int* ci, const double* v, HemWor
 #undef CALL
     } else {
 #define CALL(SD) \
-    hipLaunchKernelGGL(k_hem_all<SD>, dim3(1), dim3(HEM_BS1), 0, s, n, S, w.dec, w.lcnt, w.wl[0], w.wl[1], w.cnt)
+    hipLaunchKernelGGL(k_hem_all<SD>, dim3(1), dim3(hem_nt<SD>()), 0, s, n, S, w.dec, w.lcnt, w.wl[0], w.wl[1], w.cnt)
         AMG_HEM_SIDE(w.side, CALL)
 #undef CALL
     }
