@@ -230,9 +230,13 @@ const char* amg_last_error(void);
  * A server owns `workers` host threads, each with its own HIP stream; a
  * request runs setup, the Krylov solve and teardown on one worker while other
  * requests proceed on the others, so their kernels overlap on the device.
- * Requests are admitted in arrival order while the sum of the footprints of
- * the requests in flight stays within `hbm_budget_bytes` (the device-memory
- * concern of Section 3.1, here as admission control).
+ * Requests are admitted in arrival order while the sum of the shares of the
+ * requests in flight stays within `hbm_budget_bytes` (the device-memory
+ * concern of Section 3.1, here as admission control).  A request's share is
+ * its footprint (amg_footprint_bytes) until its setup is done, then the
+ * device memory it holds (never more than the footprint).  With batch >= 2 a
+ * worker starts a group only once the whole group it would take fits the
+ * budget, or nothing else is in flight.
  * ------------------------------------------------------------------------ */
 typedef struct amg_server amg_server;
 
@@ -240,10 +244,11 @@ typedef struct {
     int32_t workers;          /* concurrent requests, 1..64 (4)                 */
     int32_t batch;            /* >= 2: a worker takes up to this many queued
                                * requests with equal method (PCG or BiCGStab),
-                               * rtol and maxit that fit the
-                               * budget, builds their hierarchies together
-                               * (amg_batch_setup) and solves them together
-                               * (amg_batch_solve); 0 or 1: one request per
+                               * rtol, maxit and size class (at most 32768
+                               * rows, or more), builds their hierarchies
+                               * together (amg_batch_setup) and solves them
+                               * together, each request completing when its
+                               * own system stops; 0 or 1: one request per
                                * worker (0)                                      */
     uint64_t hbm_budget_bytes; /* admission budget (64 GiB)                     */
     amg_params params;        /* hierarchy and cycle parameters of every request */

@@ -3,6 +3,7 @@
 // (Algorithm 1) and the Krylov drivers (Algorithms 4 and 5).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -99,9 +100,27 @@ std::map<int, std::vector<KeptChunk>> g_chunks;  // per device, oldest first
 std::map<int, size_t> g_chunk_bytes;
 }  // namespace
 
+size_t chunk_cache_cap() {
+    static std::mutex mu;
+    static std::map<int, size_t> caps;
+    const int d = current_device();
+    std::lock_guard<std::mutex> g(mu);
+    auto it = caps.find(d);
+    if (it != caps.end()) return it->second;
+    size_t total = 0;
+    if (hipDeviceTotalMem(&total, d) != hipSuccess) {
+        (void)hipGetLastError();
+        total = 0;
+    }
+    const size_t cap = std::min(total / 4, size_t(64) << 30);
+    caps[d] = cap;
+    return cap;
+}
+
 bool chunk_keep(void* p, size_t bytes, hipStream_t s) {
     const int d = current_device();
-    if (bytes > kChunkCacheBytes) return false;
+    const size_t cap = chunk_cache_cap();
+    if (bytes > cap) return false;
     hipEvent_t ev = event_get(false);
     if (hipEventRecord(ev, s) != hipSuccess) {
         (void)hipGetLastError();
@@ -115,7 +134,7 @@ bool chunk_keep(void* p, size_t bytes, hipStream_t s) {
         size_t& tot = g_chunk_bytes[d];
         v.push_back(KeptChunk{p, bytes, ev});
         tot += bytes;
-        while (tot > kChunkCacheBytes) {  // the oldest go back to the pool
+        while (tot > cap) {  // the oldest go back to the pool
             evict.push_back(v.front());
             tot -= v.front().bytes;
             v.erase(v.begin());

@@ -977,6 +977,7 @@ const double* batch_x(const amg_batch* B, int i, int* n) {
 }
 
 hipStream_t batch_stream(const amg_batch* B) { return B->stream; }
+size_t batch_bytes(const amg_batch* B) { return B->pool.bytes; }
 
 void batch_fill_info(const amg_batch* B, int i, amg_info& I) {
     I.setup_ms = B->setup_ms;

@@ -96,17 +96,35 @@ inline amg_allocator checked_allocator(const amg_allocator* a) {
 }
 
 // Library-pool chunks that an arena releases are kept per device instead of
-// being freed: returning a block of a few hundred MB to the stream-ordered
-// pool costs about 0.3 ms of host time on MI355X, and setups of one shape
-// ask for the same chunk sizes again.  chunk_keep stores a chunk with an
-// event recorded on the stream that last used it (false: the cache is full,
-// the caller frees it); chunk_take hands out a kept chunk of exactly `bytes`
-// on the current device after `s` waits for that event (nullptr: none);
-// chunk_flush frees every kept chunk of the current device.
+// being handed back to the stream-ordered pool.  Returning a block costs about
+// 0.3 ms of host time on MI355X, and once blocks have gone back, a later
+// allocation that reuses them has been measured to block the host for 0.3 to
+// 1.8 s while the device sits idle (concurrent setups of a served stream).
+// Chunk sizes are rounded up to classes (below) so that released chunks fit
+// later requests.  chunk_keep stores a chunk with an event recorded on the
+// stream that last used it (false: larger than the cache, the caller frees
+// it); the oldest kept chunks go back to the pool once the device's cache
+// holds more than chunk_cache_cap().  chunk_take hands out a kept chunk of
+// exactly `bytes` on the current device after `s` waits for that event
+// (nullptr: none); chunk_flush frees every kept chunk of the current device
+// (an allocation that finds the device out of memory calls it).
 bool chunk_keep(void* p, size_t bytes, hipStream_t s);
 void* chunk_take(size_t bytes, hipStream_t s);
 void chunk_flush();
-constexpr size_t kChunkCacheBytes = size_t(8) << 30;  // kept per device at most
+// Kept bytes per device at most: a quarter of the device's memory, and no
+// more than 64 GiB.
+size_t chunk_cache_cap();
+
+// Size class of a library-pool chunk of at least c bytes: c rounded up to a
+// multiple of a quarter of the largest power of two not above it (classes
+// 4, 5, 6, 7 and 8 times 2^(k-2) between 2^k and 2^(k+1): at most 25% over),
+// and at least 1 MiB.
+inline size_t chunk_class(size_t c) {
+    if (c <= (size_t(1) << 20)) return size_t(1) << 20;
+    const int k = 63 - __builtin_clzll((unsigned long long)c);
+    const size_t q = size_t(1) << (k - 2);
+    return (c + q - 1) / q * q;
+}
 
 // An arena over the pool (or the caller's allocator): pieces (256-byte
 // aligned) are carved from a few chunks (sized from a hint, or by a larger
@@ -136,8 +154,9 @@ struct DevPool {
     T* get(size_t count) {
         const size_t b = (((count > 0 ? count : 1) * sizeof(T)) + 255) & ~size_t(255);
         if (b > left) {
-            const size_t c = b > next_chunk ? b : next_chunk;
+            size_t c = b > next_chunk ? b : next_chunk;
             void* p = nullptr;
+            if (!al.alloc) c = chunk_class(c);
             if (al.alloc) {
                 p = al.alloc(c, al.ctx, s);
                 if (!p) raise(AMG_ENOMEM, "the caller's allocator returned NULL for %zu bytes", c);
@@ -301,6 +320,8 @@ void batch_load(amg_batch* B, int i, const double* b, const double* x0, hipStrea
 // Device address and rows of system i's iterate inside the batch, and the
 // batch's stream.
 const double* batch_x(const amg_batch* B, int i, int* n);
+// Device memory the batch holds (levels, coarsest blocks, Krylov vectors).
+size_t batch_bytes(const amg_batch* B);
 hipStream_t batch_stream(const amg_batch* B);
 // setup_ms and levels of system i (what amg_batch_solve reports).
 void batch_fill_info(const amg_batch* B, int i, amg_info& I);

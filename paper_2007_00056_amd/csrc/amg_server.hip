@@ -167,10 +167,65 @@ struct amg_server {
         release(f);
     }
 
+    // Once a setup is done, the memory its requests hold is known.  Their
+    // admission estimates assume the worst (the largest coarsest block the
+    // parameters allow, every setup buffer at its peak), while the coarsest
+    // level normally has at most max_coarse_rows rows and the setup's scratch
+    // is gone: the shares are cut to the `held` bytes, split in proportion to
+    // the estimates, and admission may take further requests.  A share never
+    // grows.
+    void settle(const std::vector<uint64_t*>& feet, uint64_t held) {
+        uint64_t sum = 0;
+        for (const uint64_t* f : feet) sum += *f;
+        if (feet.empty() || held >= sum) return;
+        uint64_t cut = 0;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            uint64_t left = held;
+            for (size_t i = 0; i < feet.size(); ++i) {
+                uint64_t f = i + 1 < feet.size() ? (uint64_t)((long double)*feet[i] * held / sum) : left;
+                if (f > *feet[i]) f = *feet[i];
+                cut += *feet[i] - f;
+                left -= f;
+                *feet[i] = f;
+            }
+            in_use -= cut;
+        }
+        if (cut) cv_work.notify_all();
+    }
+
+    // Requests that a group headed by h may hold: the same Krylov method (PCG
+    // or BiCGStab) and stop settings, and the same size class (systems that
+    // fit one workgroup's matching state are grouped apart from larger ones:
+    // a group of small systems then needs no round kernels at all).
+    static bool groups_with(const Request* h, const Request* r) {
+        return (r->A.n <= kSmallRows) == (h->A.n <= kSmallRows) && r->method == h->method && r->rtol == h->rtol &&
+               r->maxit == h->maxit;
+    }
+
+    // Budget the group a worker would take now needs: the head's footprint
+    // and, in batched mode, those of the queued requests it groups with, up
+    // to `batch` of them.  Called with mu held.
+    uint64_t group_need() {
+        const Request* h = reqs[pending.front()];
+        uint64_t need = h->foot;
+        if (!(batched() && h->method <= 1)) return need;
+        int k = 1;
+        for (auto it = pending.begin() + 1; it != pending.end() && k < cfg.batch; ++it) {
+            const Request* r = reqs[*it];
+            if (groups_with(h, r)) {
+                need += r->foot;
+                ++k;
+            }
+        }
+        return need;
+    }
+
     // Worker i runs on wstreams[i].  It takes the request at the head of the
-    // queue once its footprint fits; in batched mode it also takes the queued
-    // requests with the same Krylov method (PCG or BiCGStab) and stop settings
-    // that still fit, up to `batch`.
+    // queue, and in batched mode the queued requests that group with it, up to
+    // `batch`, once that whole group fits the budget (or nothing else is in
+    // flight): budget freed a little at a time would otherwise be taken by
+    // ever smaller groups, whose iterations cost nearly as much as full ones.
     void worker(int i) {
         if (hipSetDevice(device) != hipSuccess) return;
         hipStream_t s = wstreams[i];
@@ -180,8 +235,7 @@ struct amg_server {
                 std::unique_lock<std::mutex> lk(mu);
                 cv_work.wait(lk, [&] {
                     if (pending.empty()) return stopping;
-                    const Request* f = reqs[pending.front()];
-                    return active == 0 || in_use + f->foot <= cfg.hbm_budget_bytes;
+                    return active == 0 || in_use + group_need() <= cfg.hbm_budget_bytes;
                 });
                 if (pending.empty()) break;  // stopping and drained
                 Request* head = reqs[pending.front()];
@@ -190,15 +244,9 @@ struct amg_server {
                 in_use += head->foot;
                 ++active;
                 if (batched() && head->method <= 1) {
-                    // systems that fit one workgroup's matching state are grouped
-                    // apart from larger ones: a group of small systems then needs
-                    // no round kernels at all
-                    const bool small = head->A.n <= kSmallRows;
                     for (auto it = pending.begin(); it != pending.end() && (int)grp.size() < cfg.batch;) {
                         Request* r = reqs[*it];
-                        if ((r->A.n <= kSmallRows) == small && r->method == head->method && r->rtol == head->rtol &&
-                            r->maxit == head->maxit &&
-                            in_use + r->foot <= cfg.hbm_budget_bytes) {
+                        if (groups_with(head, r) && in_use + r->foot <= cfg.hbm_budget_bytes) {
                             grp.push_back(r);
                             in_use += r->foot;
                             ++active;
@@ -240,6 +288,12 @@ struct amg_server {
         // no graph capture on a worker: it would make device-wide calls of the
         // other workers and of the caller's threads fail while it lasts
         if (h) h->use_graphs = false;
+        if (st == AMG_OK) {
+            // held: the hierarchy, the Krylov vectors still to come and the
+            // reduction partials
+            const uint64_t n0 = (uint64_t)h->lev[0].n;
+            settle({&r->foot}, (uint64_t)h->pool.bytes + (h->r ? 0 : 10 * 8 * n0) + (1u << 20));
+        }
         if (st == AMG_OK) st = krylov_solve(h, r->method, r->b, r->x, r->rtol, r->maxit, s, &r->info);
         else r->info.status = st;
         if (h) (void)amg_destroy(h);
@@ -304,6 +358,11 @@ struct amg_server {
                 F->feet.push_back(grp[i]->foot);
             }
         }
+        {
+            std::vector<uint64_t*> fp;
+            for (uint64_t& f : F->feet) fp.push_back(&f);
+            settle(fp, (uint64_t)amg::batch_bytes(bt) + (1u << 20));
+        }
         for (Request* r : alone) {
             run_one(r, s);
             finish(r);
@@ -333,6 +392,14 @@ struct amg_server {
         (void)amg_batch_set_graphs(bt, 0);
         std::vector<int32_t> off(n + 1);
         (void)amg_batch_rows(bt, off.data());
+        {
+            // held: the batch, BiCGStab's vectors still to come and the
+            // group's right-hand sides and solutions below
+            std::vector<uint64_t*> fp;
+            for (int i = 0; i < n; ++i)
+                if (!(st[i] == AMG_EINVAL && off[i + 1] == off[i])) fp.push_back(&grp[i]->foot);
+            settle(fp, (uint64_t)amg::batch_bytes(bt) + 7 * 8 * (uint64_t)off[n] + (1u << 20));
+        }
         // right-hand sides and solutions of the group, drawn like every other
         // buffer of a request (so the allocator accounts for them) and released
         // with the group
