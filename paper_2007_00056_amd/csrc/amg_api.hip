@@ -1045,18 +1045,27 @@ amg_status bicgstab(amg_hier* h, const double* b, double* x, double rtol, int ma
     int cur = S_RHO0, nxt = S_RHO1, pc = 0;
     launch_dot(n, h->r, h->rb, R, cur, s);
     double* v = h->q;
+    unsigned long long* hseq = reinterpret_cast<unsigned long long*>(h->S_dev + kSeqSlot);
+    // The direction kernel hands the slots over through the mapped block and
+    // the host waits on its sequence word.  Before that wait, the next
+    // iteration's first V-cycle (pt = M^{-1} p_next, scratch until the next
+    // iteration reads it) is enqueued, so the device works while the host
+    // decides; v_done says it was.
+    bool v_done = false;
     for (int it = 1; it <= maxit; ++it) {
         double* p = h->pv[pc];
         double* pn = h->pv[1 - pc];
-        run_vcycle(h, p, h->pt, s);
+        if (!v_done) run_vcycle(h, p, h->pt, s);
         spmv_dot_timed(h, A, h->pt, v, h->rb, S_RV, s);
         launch_bicg_s(n, h->r, v, h->sv, h->S, cur, S_RV, s);
         run_vcycle(h, h->sv, h->st, s);
         launch_spmv_dot2(A, h->st, h->t, h->sv, R, S_TT, S_TS, s);
         launch_bicg_update(n, x, h->r, h->pt, h->st, h->sv, h->t, h->rb, R, cur, S_RV, S_TT, S_TS, S_RR, nxt, s);
-        launch_bicg_dir(n, h->r, p, v, pn, h->S, cur, S_RV, S_TT, S_TS, nxt, s);
+        launch_bicg_dir(n, h->r, p, v, pn, h->S, cur, S_RV, S_TT, S_TS, nxt, s, h->S_dev, S_COUNT, hseq, ++h->seq);
+        v_done = it < maxit;
+        if (v_done) run_vcycle(h, pn, h->pt, s);
         HIPCHK(hipGetLastError());
-        read_slots(h, s);
+        wait_slots(h, s);
         if (!usable(S[S_RV]) || !usable(S[cur])) return AMG_EBREAKDOWN;
         if (!std::isfinite(S[S_TT]) || !std::isfinite(S[S_TS]) || S[S_TT] == 0.0) return AMG_EBREAKDOWN;
         const double omega = S[S_TS] / S[S_TT];
@@ -1073,6 +1082,7 @@ amg_status bicgstab(amg_hier* h, const double* b, double* x, double rtol, int ma
             launch_dot(n, h->r, h->rb, R, nxt, s);
             launch_bicg_dir(n, h->r, p, v, pn, h->S, cur, S_RV, S_TT, S_TS, nxt, s);
             read_slots(h, s);
+            v_done = false;  // the direction changed: the V-cycle enqueued ahead is stale
         }
         if (omega == 0.0 || !usable(S[nxt])) return AMG_EBREAKDOWN;
         std::swap(cur, nxt);

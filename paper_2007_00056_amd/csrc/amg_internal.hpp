@@ -262,8 +262,12 @@ void launch_bicg_s(int n, const double* r, const double* v, double* sv, const do
 void launch_bicg_update(int n, double* x, double* r, const double* pt, const double* st, const double* sv,
                         const double* t, const double* rb, const Reducer& R, int slot_rho, int slot_rv, int slot_tt,
                         int slot_ts, int slot_rr, int slot_rhonew, hipStream_t s);
+// Sh/nsh/hseq/seq: the slot hand-over into mapped host memory (see the PCG
+// direction kernel); null leaves it out.
 void launch_bicg_dir(int n, const double* r, const double* p, const double* v, double* pn, const double* S,
-                     int slot_rho, int slot_rv, int slot_tt, int slot_ts, int slot_rhonew, hipStream_t s);
+                     int slot_rho, int slot_rv, int slot_tt, int slot_ts, int slot_rhonew, hipStream_t s,
+                     double* Sh = nullptr, int nsh = 0, unsigned long long* hseq = nullptr,
+                     unsigned long long seq = 0);
 void launch_scale_zero(int n, double* x, hipStream_t s);
 void launch_add(int n, double* x, const double* z, hipStream_t s);
 // err |= ERR_NONFINITE if any entry of a or b is NaN or Inf.

@@ -432,19 +432,32 @@ void launch_bicg_update(int n, double* x, double* r, const double* pt, const dou
 }
 
 // p_new = r + beta (p - omega v), beta = (rho_new / rho) (alpha / omega)
+// With Sh (host memory mapped into the device), block 0 also copies the first
+// nsh scalar slots there and then, with hseq, stores seq (system scope), as
+// the PCG direction kernel does: the iteration's scalars reach the host
+// without a copy, and the host learns they are complete from that word.
 __global__ __launch_bounds__(BS) void k_bicg_dir(int n, const double* __restrict__ r, const double* __restrict__ p,
                                                  const double* __restrict__ v, double* __restrict__ pn,
                                                  const double* __restrict__ S, int slot_rho, int slot_rv, int slot_tt,
-                                                 int slot_ts, int slot_rhonew) {
+                                                 int slot_ts, int slot_rhonew, double* Sh, int nsh,
+                                                 unsigned long long* hseq, unsigned long long seq) {
     const double alpha = S[slot_rho] / S[slot_rv], omega = S[slot_ts] / S[slot_tt];
     const double beta = (S[slot_rhonew] / S[slot_rho]) * (alpha / omega);
     for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) pn[i] = r[i] + beta * (p[i] - omega * v[i]);
+    if (Sh && blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < nsh; ++k) Sh[k] = S[k];
+        if (hseq) {
+            __threadfence_system();  // the slots before the sequence word
+            __hip_atomic_store(hseq, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
 }
 
 void launch_bicg_dir(int n, const double* r, const double* p, const double* v, double* pn, const double* S,
-                     int slot_rho, int slot_rv, int slot_tt, int slot_ts, int slot_rhonew, hipStream_t s) {
+                     int slot_rho, int slot_rv, int slot_tt, int slot_ts, int slot_rhonew, hipStream_t s, double* Sh,
+                     int nsh, unsigned long long* hseq, unsigned long long seq) {
     hipLaunchKernelGGL(k_bicg_dir, dim3(vec_blocks(n)), dim3(BS), 0, s, n, r, p, v, pn, S, slot_rho, slot_rv,
-                       slot_tt, slot_ts, slot_rhonew);
+                       slot_tt, slot_ts, slot_rhonew, Sh, nsh, hseq, seq);
 }
 
 // x += z (one step of the stationary iteration)
