@@ -198,6 +198,14 @@ struct GlobalSt {
     __device__ __forceinline__ int drop(int y) const {
         return __hip_atomic_fetch_add(&lcnt[y], -1, __ATOMIC_RELAXED, SCOPE);
     }
+    // drop(y) when take, else an atomic add of zero on the counter of self (a
+    // decided vertex): the updates of a list are then issued back to back with
+    // one wait, where a branch around each would wait for every one in turn
+    // (returns 0 when not take)
+    __device__ __forceinline__ int drop_if(int y, bool take, int self) const {
+        const int old = __hip_atomic_fetch_add(&lcnt[take ? y : self], take ? -1 : 0, __ATOMIC_RELAXED, SCOPE);
+        return take ? old : 0;
+    }
 };
 
 // The same in LDS: 16-bit stamps (0xffff = undecided) and 16-bit counters
@@ -215,6 +223,13 @@ struct LdsSt {
         const unsigned sh = 16u * (unsigned)(y & 1);
         const unsigned old = atomicSub(&lcnt2[y >> 1], 1u << sh);
         return (int)((old >> sh) & 0xffffu);
+    }
+    // as GlobalSt::drop_if (self: a vertex of the range)
+    __device__ __forceinline__ int drop_if(int y, bool take, int self) const {
+        const int i = (take ? y : self) - off;
+        const unsigned sh = 16u * (unsigned)(i & 1);
+        const unsigned old = atomicSub(&lcnt2[i >> 1], take ? 1u << sh : 0u);
+        return take ? (int)((old >> sh) & 0xffffu) : 0;
     }
 };
 
@@ -255,7 +270,7 @@ __device__ __forceinline__ void hem_release(const HemState& S, const St& st, int
             }
         }
 #pragma unroll
-        for (int t = 0; t < HEM_WIN; ++t) old[t] = ys[t] >= 0 ? st.drop(ys[t]) : 0;
+        for (int t = 0; t < HEM_WIN; ++t) old[t] = st.drop_if(ys[t], ys[t] >= 0, x);
 #pragma unroll
         for (int t = 0; t < HEM_WIN; ++t)
             if (ys[t] >= 0 && old[t] == 1) A.push(ys[t]);
@@ -338,7 +353,7 @@ __device__ __forceinline__ void rec_release(const HemState& S, const St& st, con
     const int nh = R.hdr & 255;
     int old[SIDE];
 #pragma unroll
-    for (int t = 0; t < SIDE; ++t) old[t] = t < nh ? st.drop(R.h[t]) : 0;
+    for (int t = 0; t < SIDE; ++t) old[t] = st.drop_if(R.h[t], t < nh, x);
 #pragma unroll
     for (int t = 0; t < SIDE; ++t)
         if (t < nh && old[t] == 1) A.push(R.h[t]);
@@ -778,6 +793,14 @@ struct TileSt {
         const unsigned old = atomicSub(&lcnt2[y >> 1], 1u << sh);
         return (int)((old >> sh) & 0xffffu);
     }
+    // as GlobalSt::drop_if; take implies mine(y), and a self outside the
+    // tile gives the tile's first counter
+    __device__ __forceinline__ int drop_if(int y, bool take, int self) const {
+        const int i = take ? y - off : (mine(self) ? self - off : 0);
+        const unsigned sh = 16u * (unsigned)(i & 1);
+        const unsigned old = atomicSub(&lcnt2[i >> 1], take ? 1u << sh : 0u);
+        return take ? (int)((old >> sh) & 0xffffu) : 0;
+    }
     __device__ __forceinline__ void publish(int v, int partner) const {
         __hip_atomic_store(&dec_g[v], partner + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -798,7 +821,10 @@ __device__ __forceinline__ void tile_release(const HemState& S, const TileSt& st
     const int nh = R.hdr & 255;
     int old[SIDE];
 #pragma unroll
-    for (int t = 0; t < SIDE; ++t) old[t] = t < nh && st.mine(R.h[t]) ? st.drop(R.h[t]) : 0;
+    for (int t = 0; t < SIDE; ++t) {
+        const int y = t < nh ? R.h[t] : x;
+        old[t] = st.drop_if(y, t < nh && st.mine(y), x);
+    }
 #pragma unroll
     for (int t = 0; t < SIDE; ++t)
         if (t < nh && old[t] == 1) A.push(R.h[t]);
@@ -1158,13 +1184,16 @@ __device__ __forceinline__ void tile_visit_c(const HemState& S, const TileSt& st
     tile_release<7>(S, st, R, u, A);
 }
 
-// Releases of a compact vertex: its in-tile higher neighbours h[0..nh) lose
-// an undecided lower neighbour; those that reach zero are ready.
+// Releases of a compact vertex self: its in-tile higher neighbours h[0..nh)
+// lose an undecided lower neighbour; those that reach zero are ready.
 template <class Ap>
-__device__ __forceinline__ void lean_release(const TileSt& st, const int* h, int nh, const Ap& A) {
+__device__ __forceinline__ void lean_release(const TileSt& st, const int* h, int nh, int self, const Ap& A) {
     int old[kCSide];
 #pragma unroll
-    for (int t = 0; t < kCSide; ++t) old[t] = t < nh && st.mine(h[t]) ? st.drop(h[t]) : 0;
+    for (int t = 0; t < kCSide; ++t) {
+        const int y = t < nh ? h[t] : self;
+        old[t] = st.drop_if(y, t < nh && st.mine(y), self);
+    }
 #pragma unroll
     for (int t = 0; t < kCSide; ++t)
         if (t < nh && old[t] == 1) A.push(h[t]);
@@ -1211,7 +1240,7 @@ __device__ __forceinline__ void tile_visit_lean(const HemState& S, const TileSt&
         if (old == kTilePend) {
             if (taken) {
                 atomicAdd(s_ndec, 1);
-                lean_release(st, h, nh, A);
+                lean_release(st, h, nh, u, A);
                 return;
             }
         } else if (old != kTileUnd) {
@@ -1241,7 +1270,7 @@ __device__ __forceinline__ void tile_visit_lean(const HemState& S, const TileSt&
         S.mate[u] = -1;
         st.publish(u, -1);
         atomicAdd(s_ndec, 1);
-        lean_release(st, h, nh, A);
+        lean_release(st, h, nh, u, A);
         return;
     }
     const int j = best - off;
@@ -1297,7 +1326,7 @@ __device__ __forceinline__ void tile_visit_lean(const HemState& S, const TileSt&
         if (old == kTilePend) {
             if (named) {
                 atomicAdd(s_ndec, 1);
-                lean_release(st, hb, nhb, A);
+                lean_release(st, hb, nhb, best, A);
                 A.push(u);
                 return;
             }
@@ -1313,8 +1342,8 @@ __device__ __forceinline__ void tile_visit_lean(const HemState& S, const TileSt&
     st.publish(best, u);
     st.publish(u, best);
     atomicAdd(s_ndec, 2);
-    lean_release(st, h, nh, A);
-    lean_release(st, hb, nhb, A);
+    lean_release(st, h, nh, u, A);
+    lean_release(st, hb, nhb, best, A);
 }
 }  // namespace
 
