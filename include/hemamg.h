@@ -128,6 +128,19 @@ typedef struct {
     void* ctx;
 } amg_allocator;
 
+/* Device memory the library's own pool keeps for reuse on the current device
+ * (the chunks of destroyed handles, batches and servers, held so that later
+ * setups do not go back to the driver; at most a quarter of the device's
+ * memory and 64 GiB).  amg_cached_bytes stores the kept bytes in *bytes
+ * (AMG_EINVAL for NULL).  amg_release_cached waits for the work that last
+ * used each kept chunk, frees the chunks and returns the pool's unused
+ * memory to the driver, as a caller sharing the device with another
+ * allocator may want to do; live handles, batches and servers are not
+ * touched.  Memory drawn through a caller's amg_allocator is never kept.
+ * Errors: AMG_EHIP.  [host] */
+amg_status amg_cached_bytes(uint64_t* bytes);
+amg_status amg_release_cached(void);
+
 /* Fills *p with the defaults shown above.  [host] */
 amg_status amg_params_default(amg_params* p);
 

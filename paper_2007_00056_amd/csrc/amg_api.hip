@@ -168,6 +168,13 @@ void* chunk_take(size_t bytes, hipStream_t s) {
     return k.p;
 }
 
+size_t chunk_kept_bytes() {
+    const int d = current_device();
+    std::lock_guard<std::mutex> g(g_chunk_mu);
+    auto it = g_chunk_bytes.find(d);
+    return it == g_chunk_bytes.end() ? 0 : it->second;
+}
+
 void chunk_flush() {
     const int d = current_device();
     std::vector<KeptChunk> all;
@@ -1971,5 +1978,19 @@ amg_status amg_timing_read(amg_hier* h, int32_t kernel, int64_t* launches, doubl
 }
 
 const char* amg_last_error(void) { return g_err.c_str(); }
+
+amg_status amg_cached_bytes(uint64_t* bytes) {
+    return guarded([&] {
+        if (!bytes) raise(AMG_EINVAL, "amg_cached_bytes: NULL argument");
+        *bytes = (uint64_t)chunk_kept_bytes();
+    });
+}
+
+amg_status amg_release_cached(void) {
+    return guarded([&] {
+        chunk_flush();  // waits for each chunk's last use, frees it and waits for the frees
+        HIPCHK(hipMemPoolTrimTo(lib_pool(), 0));
+    });
+}
 
 }  // extern "C"

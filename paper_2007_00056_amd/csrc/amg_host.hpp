@@ -111,6 +111,7 @@ inline amg_allocator checked_allocator(const amg_allocator* a) {
 bool chunk_keep(void* p, size_t bytes, hipStream_t s);
 void* chunk_take(size_t bytes, hipStream_t s);
 void chunk_flush();
+size_t chunk_kept_bytes();  // kept on the current device
 // Kept bytes per device at most: a quarter of the device's memory, and no
 // more than 64 GiB.
 size_t chunk_cache_cap();

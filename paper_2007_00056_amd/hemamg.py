@@ -27,7 +27,8 @@ EXPORTED = ["amg_params_default", "amg_setup", "amg_destroy", "amg_vcycle", "kry
             "amg_last_error", "amg_footprint_bytes", "amg_server_config_default", "amg_server_create",
             "amg_server_submit", "amg_server_wait", "amg_server_destroy", "amg_batch_create", "amg_batch_rows",
             "amg_batch_solve", "amg_batch_destroy", "amg_batch_levels", "amg_batch_autotune", "amg_autotune",
-            "amg_batch_setup", "amg_batch_set_graphs", "krylov_solve_noalloc"]
+            "amg_batch_setup", "amg_batch_set_graphs", "krylov_solve_noalloc", "amg_cached_bytes",
+            "amg_release_cached"]
 
 
 class amg_csr(C.Structure):
@@ -92,6 +93,8 @@ def lib():
             "amg_timing_enable": [vp, i32, i32],
             "amg_timing_read": [vp, i32, C.POINTER(i64), C.POINTER(f64)],
             "amg_footprint_bytes": [i32, i64, C.POINTER(amg_params), C.POINTER(C.c_uint64)],
+            "amg_cached_bytes": [C.POINTER(C.c_uint64)],
+            "amg_release_cached": [],
             "amg_server_config_default": [C.POINTER(amg_server_config)],
             "amg_server_create": [C.POINTER(amg_server_config), C.POINTER(vp)],
             "amg_server_submit": [vp, C.POINTER(amg_csr), vp, vp, i32, f64, i32, vp, C.POINTER(i64)],
@@ -300,6 +303,18 @@ def amg_footprint_bytes(n: int, nnz: int, params: amg_params | None = None) -> i
     b = C.c_uint64()
     _check(lib().amg_footprint_bytes(n, nnz, C.byref(params) if params is not None else None, C.byref(b)))
     return b.value
+
+
+def amg_cached_bytes() -> int:
+    """Device memory the library keeps for reuse on the current device."""
+    b = C.c_uint64()
+    _check(lib().amg_cached_bytes(C.byref(b)))
+    return b.value
+
+
+def amg_release_cached() -> None:
+    """Frees the kept chunks and trims the library pool (current device)."""
+    _check(lib().amg_release_cached())
 
 
 def amg_server_config_default(**overrides) -> amg_server_config:

@@ -131,3 +131,35 @@ def test_batched_setup_allocation_failures(torch, fp32):
         assert st == hemamg.AMG_ENOMEM and ca.live == 0, (k, st, ca.live)
     st, x = run(CountingAllocator(torch))
     np.testing.assert_array_equal(bits(x), bits(xref))
+
+
+def test_kept_chunks_are_reused_and_released(torch):
+    """The library pool keeps the chunks of a destroyed handle: a second setup
+    of the same system draws exactly those chunks again (the kept bytes do not
+    grow), amg_release_cached frees them and gives the pool's memory back to
+    the driver, and setups afterwards give the same bits."""
+    a = P.poisson3d(64)
+    A = hemamg.DeviceCSR.from_host(a)
+    b = torch.from_numpy(P.rhs_uniform(a.n, 2)).cuda()
+    hemamg.amg_release_cached()
+    assert hemamg.amg_cached_bytes() == 0
+    st, x1 = setup_and_solve(torch, A, b, None)
+    assert st == hemamg.AMG_OK
+    torch.cuda.synchronize()
+    kept = hemamg.amg_cached_bytes()
+    say("kept after one setup + solve:", kept / 1e6, "MB")
+    assert kept >= 1 << 20
+    st, x2 = setup_and_solve(torch, A, b, None)
+    assert st == hemamg.AMG_OK
+    assert hemamg.amg_cached_bytes() == kept
+    np.testing.assert_array_equal(bits(x2), bits(x1))
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    hemamg.amg_release_cached()
+    assert hemamg.amg_cached_bytes() == 0
+    free1 = torch.cuda.mem_get_info()[0]
+    say("device memory freed by the release:", (free1 - free0) / 1e6, "MB")
+    assert free1 - free0 >= kept // 2
+    st, x3 = setup_and_solve(torch, A, b, None)
+    assert st == hemamg.AMG_OK
+    np.testing.assert_array_equal(bits(x3), bits(x1))
