@@ -966,11 +966,7 @@ __device__ __forceinline__ void tile_visit(const HemState& S, const TileSt& st, 
     const HemRecT<SIDE> R = recs[u];
     const int su = st.sdec[u - st.off];
     if (su < r) return;  // decided earlier (as a match target): stale entry
-    // the first preference's record, loaded with the states it is chosen by
-    const bool spec = (R.hdr & 255) > 0;
-    HemRecT<SIDE> B;
-    if (spec) B = recs[R.h[0]];
-    if (su == kTilePend) {
+    if (su == kTilePend) {  // most visits of a pending vertex find it still open
         bool open, taken;
         cross_lower<SIDE>(S, st, R, u, open, taken);
         if (open) {
@@ -979,6 +975,10 @@ __device__ __forceinline__ void tile_visit(const HemState& S, const TileSt& st, 
         }
         if (tile_settle<SIDE>(S, st, R, u, r, taken, A, s_ndec) != kFree) return;
     }
+    // the first preference's record, loaded with the states it is chosen by
+    const bool spec = (R.hdr & 255) > 0;
+    HemRecT<SIDE> B;
+    if (spec) B = recs[R.h[0]];
     int best = -1;
     {
         const int nh = R.hdr & 255;
@@ -1119,11 +1119,7 @@ __device__ __forceinline__ void tile_visit_c(const HemState& S, const TileSt& st
     C.load(u, R);
     const int su = st.sdec[u - st.off];
     if (su < r) return;  // decided earlier (as a match target): stale entry
-    const int nh = R.hdr & 255;
-    const int b0 = nh > 0 ? R.h[0] : -1;
-    HemRecT<7> B;
-    if (b0 >= 0) C.load(b0, B);  // the first preference, loaded with the states it is chosen by
-    if (su == kTilePend) {
+    if (su == kTilePend) {  // most visits of a pending vertex find it still open
         bool open, taken;
         cross_lower<7>(S, st, R, u, open, taken);
         if (open) {
@@ -1132,6 +1128,10 @@ __device__ __forceinline__ void tile_visit_c(const HemState& S, const TileSt& st
         }
         if (tile_settle<7>(S, st, R, u, r, taken, A, s_ndec) != kFree) return;
     }
+    const int nh = R.hdr & 255;
+    const int b0 = nh > 0 ? R.h[0] : -1;
+    HemRecT<7> B;
+    if (b0 >= 0) C.load(b0, B);  // the first preference, loaded with the states it is chosen by
     int best = -1;
     {
         int fin = 7;  // first undecided tile entry in preference order
