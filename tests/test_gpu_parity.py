@@ -361,6 +361,32 @@ def test_graph_replay_matches_eager(torch, name, monkeypatch):
     assert torch.equal(out["graph_timed"][0], out["eager"][0])
 
 
+@pytest.mark.parametrize("name", ["convdiff3d_13", "lognormal3d_11"])
+def test_residual_replacement_every_few_iterations(torch, name):
+    """A true-residual replacement every 3 iterations re-forms the search
+    direction.  The GPU solvers enqueue part of the next iteration before the
+    host decides (the SpMV of PCG, the first V-cycle of BiCGStab) and must redo
+    it after each replacement; they stay in parity with the oracle run with the
+    same period (Algorithms 4 and 5)."""
+    a = CASES[name]()
+    method = "bicgstab" if name in NONSYM else "pcg"
+    say("case", name, method)
+    A = hemamg.DeviceCSR.from_host(a)
+    g = hemamg.Hierarchy(A, hemamg.amg_params_default(true_res_period=3))
+    o = oracle.Hierarchy(a)
+    b = P.rhs_uniform(a.n, 5)
+    xo, io = o.solve(b, method=method, rtol=1e-8, maxit=500, true_res_period=3)
+    assert io["status"] == oracle.OK and io["iters"] > 6
+    xg, ig = g.solve(dev(torch, b), method=method, rtol=1e-8, maxit=500)
+    assert ig["status"] == hemamg.AMG_OK
+    assert abs(ig["iters"] - io["iters"]) <= 1, (ig, io)
+    assert ig["true_rel_res"] <= 1e-8
+    xg2, ig2 = g.solve(dev(torch, b), method=method, rtol=0.0, maxit=io["iters"], check=False)
+    assert ig2["iters"] == io["iters"]
+    assert_close(xg2.cpu().numpy(), xo, SOL_TOL, "equal iterations")
+    g.close()
+
+
 # ---------------------------------------------------------------- edge cases
 
 def test_one_by_one(torch):
