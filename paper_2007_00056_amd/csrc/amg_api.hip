@@ -956,19 +956,25 @@ amg_status pcg(amg_hier* h, const double* b, double* x, double rtol, int maxit, 
     run_vcycle(h, h->r, h->z, s, h->g0, S_RHO0);
     HIPCHK(hipMemcpyAsync(h->pv[0], h->z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     bool q_done = false;  // eager launches: this iteration's SpMV was enqueued ahead
+    double rel_prev = 0.0;  // relative residual one iteration earlier (0: none yet)
     for (int it = 1; it <= maxit; ++it) {
         const int cur = pc ? S_RHO1 : S_RHO0, nxt = pc ? S_RHO0 : S_RHO1;
         // the preconditioning, (r, z) and the next direction are speculative:
         // unused when this iteration stops; so is the next iteration's SpMV,
         // enqueued before the host reads this iteration's scalars (it writes
-        // only q and its partials)
-        const bool ahead = !graphs && it < maxit;
+        // only q and its partials).  It is not enqueued when the iteration
+        // ends in a residual replacement, or when the last two residuals
+        // extrapolate to convergence in this iteration (a wrong guess only
+        // delays the next SpMV).
+        const bool ahead = !graphs && it < maxit && !(period > 0 && it % period == 0) &&
+                           !(rel_prev > 0.0 && rel * (rel / rel_prev) <= rtol);
         pcg_iteration(h, b, x, pc, graphs, s, q_done, ahead);
         q_done = ahead;
         if (graphs) HIPCHK(hipStreamSynchronize(s));
         else wait_slots(h, s);
         if (!usable(S[S_PQ]) || !std::isfinite(S[cur])) return AMG_EBREAKDOWN;
         info.iters = it;
+        rel_prev = rel;
         rel = std::sqrt(S[S_RR]) / nb;
         info.rel_res = rel;
         if (!std::isfinite(rel)) return AMG_EBREAKDOWN;
@@ -1059,6 +1065,7 @@ amg_status bicgstab(amg_hier* h, const double* b, double* x, double rtol, int ma
     // iteration reads it) is enqueued, so the device works while the host
     // decides; v_done says it was.
     bool v_done = false;
+    double rel_prev = 0.0;  // relative residual one iteration earlier (0: none yet)
     for (int it = 1; it <= maxit; ++it) {
         double* p = h->pv[pc];
         double* pn = h->pv[1 - pc];
@@ -1069,7 +1076,10 @@ amg_status bicgstab(amg_hier* h, const double* b, double* x, double rtol, int ma
         launch_spmv_dot2(A, h->st, h->t, h->sv, R, S_TT, S_TS, s);
         launch_bicg_update(n, x, h->r, h->pt, h->st, h->sv, h->t, h->rb, R, cur, S_RV, S_TT, S_TS, S_RR, nxt, s);
         launch_bicg_dir(n, h->r, p, v, pn, h->S, cur, S_RV, S_TT, S_TS, nxt, s, h->S_dev, S_COUNT, hseq, ++h->seq);
-        v_done = it < maxit;
+        // not ahead when this iteration ends in a residual replacement, or is
+        // extrapolated to converge (as in PCG)
+        v_done = it < maxit && !(period > 0 && it % period == 0) &&
+                 !(rel_prev > 0.0 && rel * (rel / rel_prev) <= rtol);
         if (v_done) run_vcycle(h, pn, h->pt, s);
         HIPCHK(hipGetLastError());
         wait_slots(h, s);
@@ -1077,6 +1087,7 @@ amg_status bicgstab(amg_hier* h, const double* b, double* x, double rtol, int ma
         if (!std::isfinite(S[S_TT]) || !std::isfinite(S[S_TS]) || S[S_TT] == 0.0) return AMG_EBREAKDOWN;
         const double omega = S[S_TS] / S[S_TT];
         info.iters = it;
+        rel_prev = rel;
         rel = std::sqrt(S[S_RR]) / nb;
         info.rel_res = rel;
         if (!std::isfinite(rel)) return AMG_EBREAKDOWN;
