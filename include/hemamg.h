@@ -274,7 +274,10 @@ typedef struct {
 /* Upper estimate of the device memory one request of n rows and nnz entries
  * needs at its peak (hierarchy, Krylov workspace and setup scratch; level 0
  * is the caller's).  It assumes the coarse levels together hold at most n
- * rows and nnz entries (operator complexity <= 2).  [host] */
+ * rows and nnz entries (operator complexity <= 2).  It counts the bytes the
+ * request asks for: the library's own pool rounds each chunk up to a size
+ * class (at most 25% more), a caller's amg_allocator gets the exact sizes.
+ * [host] */
 amg_status amg_footprint_bytes(int32_t n, int64_t nnz, const amg_params* params, uint64_t* bytes);
 
 /* Fills *c with the defaults shown above (params from amg_params_default). */
