@@ -219,12 +219,14 @@ __global__ __launch_bounds__(BS) void k_bzero(BatchTab T, double* __restrict__ x
 }
 
 // Coarsest solves x = A_L^{-1} f of every segment (explicit inverse, column
-// major), 64 rows per block with the columns split over 8 waves and their
-// sums added in wave order; each result is scattered to the segment's finer
-// level.  Block b handles rows 64*tab[b].y.. of segment tab[b].x.
+// major), 64 rows per block with the columns split over 8 waves; each wave
+// keeps ACC sums over its columns in turn (loads in flight), added in a fixed
+// order, then the waves' in wave order; each result is scattered to the
+// segment's finer level.  Block b handles rows 64*tab[b].y.. of segment
+// tab[b].x.
 template <class T>
 __global__ __launch_bounds__(512) void k_bdense(const BDense<T>* __restrict__ dd, const int2* __restrict__ tab) {
-    constexpr int ROWS = 64, WAVES = 8;
+    constexpr int ROWS = 64, WAVES = 8, ACC = 8;
     __shared__ double fs[kDenseMaxRows];
     __shared__ double psum[WAVES][ROWS];
     const int2 bk = tab[blockIdx.x];
@@ -234,16 +236,27 @@ __global__ __launch_bounds__(512) void k_bdense(const BDense<T>* __restrict__ dd
     __syncthreads();
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int i = bk.y * ROWS + lane;
-    double s0 = 0.0, s1 = 0.0;
+    double acc[ACC];
+#pragma unroll
+    for (int k = 0; k < ACC; ++k) acc[k] = 0.0;
     if (i < n) {
-        int j = w;
-        for (; j + WAVES < n; j += 2 * WAVES) {
-            s0 += d.ainv_t[(size_t)j * n + i] * fs[j];
-            s1 += d.ainv_t[(size_t)(j + WAVES) * n + i] * fs[j + WAVES];
+        // whole groups without a bound check per load, then the last columns
+        int j0 = w;
+        for (; j0 + (ACC - 1) * WAVES < n; j0 += ACC * WAVES) {
+            double a[ACC];
+#pragma unroll
+            for (int k = 0; k < ACC; ++k) a[k] = d.ainv_t[(size_t)(j0 + k * WAVES) * n + i];
+#pragma unroll
+            for (int k = 0; k < ACC; ++k) acc[k] += a[k] * fs[j0 + k * WAVES];
         }
-        if (j < n) s0 += d.ainv_t[(size_t)j * n + i] * fs[j];
+        for (int k = 0; j0 + k * WAVES < n; ++k)
+            acc[k] += d.ainv_t[(size_t)(j0 + k * WAVES) * n + i] * fs[j0 + k * WAVES];
     }
-    psum[w][lane] = s0 + s1;
+#pragma unroll
+    for (int k = ACC / 2; k > 0; k /= 2)
+#pragma unroll
+        for (int q = 0; q < k; ++q) acc[q] += acc[q + k];
+    psum[w][lane] = acc[0];
     __syncthreads();
     if (w == 0 && i < n) {
         double xi = psum[0][lane];

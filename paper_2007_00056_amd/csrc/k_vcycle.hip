@@ -305,8 +305,12 @@ constexpr int DENSE_ROWS = kWave;  // rows per block, one per lane
 constexpr int DENSE_WAVES = DENSE_BS / kWave;
 
 // x = A_L^{-1} f: a block owns 64 rows (one per lane, coalesced reads of the
-// column-major inverse); its 8 waves split the columns round-robin and their
-// partial sums are added in wave order, so the result is reproducible.
+// column-major inverse); its 8 waves split the columns round-robin, each wave
+// keeps DENSE_ACC sums over its columns in turn (so that many loads are in
+// flight: the product is latency-bound at a few hundred rows), and the sums
+// are added in a fixed order, then the waves' in wave order, so the result is
+// reproducible.
+constexpr int DENSE_ACC = 8;
 template <class T, class TIN, class TOUT>
 __global__ __launch_bounds__(DENSE_BS) void k_vc_dense(int n, const double* __restrict__ ainv_t,
                                                        const TIN* __restrict__ f, TOUT* __restrict__ x,
@@ -319,16 +323,28 @@ __global__ __launch_bounds__(DENSE_BS) void k_vc_dense(int n, const double* __re
     __syncthreads();
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int i = blk * DENSE_ROWS + lane;
-    double s0 = 0.0, s1 = 0.0;
+    double acc[DENSE_ACC];
+#pragma unroll
+    for (int k = 0; k < DENSE_ACC; ++k) acc[k] = 0.0;
     if (i < n) {
-        int j = w;
-        for (; j + DENSE_WAVES < n; j += 2 * DENSE_WAVES) {
-            s0 += ainv_t[(size_t)j * n + i] * fs[j];
-            s1 += ainv_t[(size_t)(j + DENSE_WAVES) * n + i] * fs[j + DENSE_WAVES];
+        // whole groups without a bound check per load (a branch around each
+        // load would wait for it before the next), then the last columns
+        int j0 = w;
+        for (; j0 + (DENSE_ACC - 1) * DENSE_WAVES < n; j0 += DENSE_ACC * DENSE_WAVES) {
+            double a[DENSE_ACC];
+#pragma unroll
+            for (int k = 0; k < DENSE_ACC; ++k) a[k] = ainv_t[(size_t)(j0 + k * DENSE_WAVES) * n + i];
+#pragma unroll
+            for (int k = 0; k < DENSE_ACC; ++k) acc[k] += a[k] * fs[j0 + k * DENSE_WAVES];
         }
-        if (j < n) s0 += ainv_t[(size_t)j * n + i] * fs[j];
+        for (int k = 0; j0 + k * DENSE_WAVES < n; ++k)
+            acc[k] += ainv_t[(size_t)(j0 + k * DENSE_WAVES) * n + i] * fs[j0 + k * DENSE_WAVES];
     }
-    part[w][lane] = s0 + s1;
+#pragma unroll
+    for (int k = DENSE_ACC / 2; k > 0; k /= 2)
+#pragma unroll
+        for (int q = 0; q < k; ++q) acc[q] += acc[q + k];
+    part[w][lane] = acc[0];
     __syncthreads();
     if (w == 0 && i < n) {
         double xi = part[0][lane];
