@@ -240,17 +240,22 @@ __global__ __launch_bounds__(512) void k_bdense(const BDense<T>* __restrict__ dd
 #pragma unroll
     for (int k = 0; k < ACC; ++k) acc[k] = 0.0;
     if (i < n) {
-        // whole groups without a bound check per load, then the last columns
-        int j0 = w;
-        for (; j0 + (ACC - 1) * WAVES < n; j0 += ACC * WAVES) {
+        // a group of ACC columns a step, loaded together: a column past the
+        // end loads column j0 again (in bounds) and is not added, so no load
+        // waits behind a branch
+        for (int j0 = w; j0 < n; j0 += ACC * WAVES) {
             double a[ACC];
 #pragma unroll
-            for (int k = 0; k < ACC; ++k) a[k] = d.ainv_t[(size_t)(j0 + k * WAVES) * n + i];
+            for (int k = 0; k < ACC; ++k) {
+                const int j = j0 + k * WAVES;
+                a[k] = d.ainv_t[(size_t)(j < n ? j : j0) * n + i];
+            }
 #pragma unroll
-            for (int k = 0; k < ACC; ++k) acc[k] += a[k] * fs[j0 + k * WAVES];
+            for (int k = 0; k < ACC; ++k) {
+                const int j = j0 + k * WAVES;
+                if (j < n) acc[k] += a[k] * fs[j];
+            }
         }
-        for (int k = 0; j0 + k * WAVES < n; ++k)
-            acc[k] += d.ainv_t[(size_t)(j0 + k * WAVES) * n + i] * fs[j0 + k * WAVES];
     }
 #pragma unroll
     for (int k = ACC / 2; k > 0; k /= 2)

@@ -327,18 +327,22 @@ __global__ __launch_bounds__(DENSE_BS) void k_vc_dense(int n, const double* __re
 #pragma unroll
     for (int k = 0; k < DENSE_ACC; ++k) acc[k] = 0.0;
     if (i < n) {
-        // whole groups without a bound check per load (a branch around each
-        // load would wait for it before the next), then the last columns
-        int j0 = w;
-        for (; j0 + (DENSE_ACC - 1) * DENSE_WAVES < n; j0 += DENSE_ACC * DENSE_WAVES) {
+        // a group of DENSE_ACC columns a step, loaded together: a column past the
+        // end loads column j0 again (in bounds) and is not added, so no load
+        // waits behind a branch
+        for (int j0 = w; j0 < n; j0 += DENSE_ACC * DENSE_WAVES) {
             double a[DENSE_ACC];
 #pragma unroll
-            for (int k = 0; k < DENSE_ACC; ++k) a[k] = ainv_t[(size_t)(j0 + k * DENSE_WAVES) * n + i];
+            for (int k = 0; k < DENSE_ACC; ++k) {
+                const int j = j0 + k * DENSE_WAVES;
+                a[k] = ainv_t[(size_t)(j < n ? j : j0) * n + i];
+            }
 #pragma unroll
-            for (int k = 0; k < DENSE_ACC; ++k) acc[k] += a[k] * fs[j0 + k * DENSE_WAVES];
+            for (int k = 0; k < DENSE_ACC; ++k) {
+                const int j = j0 + k * DENSE_WAVES;
+                if (j < n) acc[k] += a[k] * fs[j];
+            }
         }
-        for (int k = 0; j0 + k * DENSE_WAVES < n; ++k)
-            acc[k] += ainv_t[(size_t)(j0 + k * DENSE_WAVES) * n + i] * fs[j0 + k * DENSE_WAVES];
     }
 #pragma unroll
     for (int k = DENSE_ACC / 2; k > 0; k /= 2)
