@@ -213,9 +213,14 @@ void event_put(hipEvent_t e, bool timing) {
 }
 
 // Pinned host words for small read-backs (per thread, kept for the process).
-int* pinned_words() {
+int* pinned_words(int** dev) {
     thread_local int* p = nullptr;
-    if (!p) HIPCHK(hipHostMalloc((void**)&p, 64 * sizeof(int), hipHostMallocDefault));
+    thread_local int* d = nullptr;
+    if (!p) {
+        HIPCHK(hipHostMalloc((void**)&p, 64 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+        HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&d), p, 0));
+    }
+    if (dev) *dev = d;
     return p;
 }
 
@@ -496,11 +501,10 @@ Csr galerkin(const Csr& B, Pass& P, SetupWork& W, DevPool& out, hipStream_t s, c
     C.rp = out.get<int>((size_t)nmax + 1);
     launch_scan(W.rowcnt, nmax, C.rp, W.stmp, s);
     HIPCHK(hipGetLastError());
-    int* hw = pinned_words();
-    HIPCHK(hipMemcpyAsync(hw, P.cnt, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hw + 8, ncp, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hw + 9, C.rp + nmax, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hw + 10, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    int* dw = nullptr;
+    int* hw = pinned_words(&dw);
+    launch_pass_words(dw, P.cnt, ncp, C.rp + nmax, err, s);  // one launch in place of four copies
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     raise_err_word(hw[10], "amg_setup");
     if (hw[5] != 0) raise(AMG_EINVAL, "matching: sparsity pattern is not structurally symmetric");

@@ -58,7 +58,9 @@ constexpr size_t kPinnedBlock = 4096;
 void* pinned_get();
 void pinned_put(void* p);
 // Pinned host words for small read-backs (per thread, kept for the process).
-int* pinned_words();
+// (mapped into the device and coherent: a kernel may write them, through the
+// device address *dev, for the host to read once the stream has finished)
+int* pinned_words(int** dev = nullptr);
 int read_int(const int* d, hipStream_t s);
 void raise_err_word(int e, const char* where);
 void check_err_word(const int* err, hipStream_t s, const char* where);

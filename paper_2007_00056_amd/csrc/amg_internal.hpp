@@ -98,6 +98,9 @@ int hem_next_count_slot(int round);  // counter slot that holds |worklist| befor
 
 // Exclusive prefix sum: out[i] = sum in[0..i), out[n] = total.  tmp: scan_tmp_ints(n).
 size_t scan_tmp_ints(int n);
+// out[0..7] = cnt[0..7], out[8] = *ncp, out[9] = *nnzc, out[10] = *err (out: a
+// device address of mapped host memory).
+void launch_pass_words(int* out, const int* cnt, const int* ncp, const int* nnzc, const int* err, hipStream_t s);
 void launch_scan(const int* in, int n, int* out, int* tmp, hipStream_t s);
 void launch_leader_flags(int n, const int* mate, int* flag, hipStream_t s);
 // agg[v] = id of v's aggregate; lead[id] = smaller vertex of the aggregate.

@@ -149,6 +149,22 @@ __global__ __launch_bounds__(BS) void k_scan_apply(const int* __restrict__ in, i
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tsum[nt];
 }
 
+// The words a pass hands to the host, gathered by one small launch: the
+// matching's 8 counters, the coarse row count, the coarse entry count and the
+// error word.
+__global__ void k_pass_words(int* __restrict__ out, const int* __restrict__ cnt, const int* __restrict__ ncp,
+                             const int* __restrict__ nnzc, const int* __restrict__ err) {
+    const int t = threadIdx.x;
+    if (t < 8) out[t] = cnt[t];
+    else if (t == 8) out[8] = *ncp;
+    else if (t == 9) out[9] = *nnzc;
+    else if (t == 10) out[10] = *err;
+}
+
+void launch_pass_words(int* out, const int* cnt, const int* ncp, const int* nnzc, const int* err, hipStream_t s) {
+    hipLaunchKernelGGL(k_pass_words, dim3(1), dim3(kWave), 0, s, out, cnt, ncp, nnzc, err);
+}
+
 size_t scan_tmp_ints(int n) { return (size_t)(n + SCAN_TILE - 1) / SCAN_TILE + 1; }
 
 void launch_scan(const int* in, int n, int* out, int* tmp, hipStream_t s) {
